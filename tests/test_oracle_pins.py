@@ -1,0 +1,386 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test checks the oracle against a closed form, an independent integrator,
+group theory, a published table or a mathematical identity, chosen so that a
+plausible slip (a dropped term, a flipped sign, a transposed product, a wrong
+index) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg
+import scipy.special
+
+import oracle as orc
+from workloads import dimer_dense, dimer_tridiag, drive_cos, gue, haar_unitary
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TWO_PI = 2.0 * math.pi
+
+
+def _rm(n, seed):
+    rng = np.random.default_rng(seed)
+    return gue(n, rng), gue(n, rng)
+
+
+def _nodes_cos(T, M, eps0=0.0, eps1=1.0, omega=1.0):
+    return drive_cos(orc.node_times(T, M), eps0, eps1, omega)
+
+
+def _brute_force(H_of_t, n, T, rtol=1e-13, atol=1e-13):
+    """U(T) from i dU/dt = H(t) U, U(0) = 1, by an adaptive 8th-order
+    Runge-Kutta (DOP853) on the real and imaginary parts."""
+    def rhs(t, y):
+        U = (y[: n * n] + 1j * y[n * n:]).reshape(n, n)
+        dU = -1j * (H_of_t(t) @ U)
+        return np.concatenate([dU.real.ravel(), dU.imag.ravel()])
+
+    y0 = np.concatenate([np.eye(n).ravel(), np.zeros(n * n)])
+    sol = scipy.integrate.solve_ivp(rhs, (0.0, T), y0, method="DOP853", rtol=rtol, atol=atol)
+    y = sol.y[:, -1]
+    return (y[: n * n] + 1j * y[n * n:]).reshape(n, n)
+
+
+def _spin_matrices(S2):
+    """Spin-S matrices (S = S2/2) in the basis m = -S, ..., S (ascending)."""
+    S = S2 / 2.0
+    m = np.arange(S2 + 1) - S
+    Sz = np.diag(m).astype(np.complex128)
+    Sp = np.zeros((S2 + 1, S2 + 1), dtype=np.complex128)
+    for i in range(S2):
+        Sp[i + 1, i] = math.sqrt(S * (S + 1) - m[i] * (m[i] + 1))
+    Sx = (Sp + Sp.conj().T) / 2
+    Sy = (Sp - Sp.conj().T) / 2j
+    return Sx, Sy, Sz
+
+
+# --- Bessel weights and the scalar expansion -------------------------------------------------
+
+def test_bessel_against_published_table():
+    rows = np.loadtxt(os.path.join(GOLDEN, "bessel_table.txt"))
+    for n, x, ref in rows:
+        a = orc.bessel_coefficients(x, int(n))
+        val = a[int(n)] / (1.0 if n == 0 else 2.0)
+        assert abs(val - ref) <= 5e-10 * max(1.0, abs(ref)) + 1e-19, (n, x, val, ref)
+
+
+@pytest.mark.parametrize("R", [0.126, 0.251, 3.0, 37.03, 250.0])
+def test_jacobi_anger(R):
+    """sum_l a_l (-i)^l T_l(x) = exp(-i R x) on [-1, 1] to the chosen tolerance,
+    and J_0 + 2 sum_k J_2k = 1."""
+    tol = 1e-13
+    L = orc.choose_L(R, tol)
+    a = orc.bessel_coefficients(R, L)
+    x = np.linspace(-1.0, 1.0, 2001)
+    p, _ = orc.chebyshev_polynomial_values(x, a, 0.0, 1.0)
+    assert np.max(np.abs(p - np.exp(-1j * R * x))) < 50 * tol
+    big = orc.bessel_coefficients(R, L + 40)
+    assert abs(big[0] + np.sum(big[2::2]) - 1.0) < 1e-12
+
+
+def test_choose_L_is_minimal():
+    for R in [0.05, 0.126, 1.0, 10.0, 37.03, 300.0]:
+        tol = 1e-12
+        L = orc.choose_L(R, tol)
+        j = np.abs(scipy.special.jv(np.arange(L + 400), R))
+        assert 2 * j[L + 1:].sum() <= tol
+        if L > 1:
+            assert 2 * j[L:].sum() > tol
+
+
+def test_chebyshev_polynomial_derivative():
+    a = orc.bessel_coefficients(2.0, 30)
+    x = np.linspace(-0.9, 0.9, 7)
+    _, dp = orc.chebyshev_polynomial_values(x, a, 0.3, 0.1)
+    e = 1e-6
+    pp, _ = orc.chebyshev_polynomial_values(x + e, a, 0.3, 0.1)
+    pm, _ = orc.chebyshev_polynomial_values(x - e, a, 0.3, 0.1)
+    assert np.max(np.abs((pp - pm) / (2 * e) - dp)) < 1e-7
+
+
+def test_chebyshev_step_on_known_spectrum():
+    """Matrix recurrence on H = Q diag(lam) Q^dagger with Q and lam chosen, not
+    computed: must equal Q diag(exp(-i h lam)) Q^dagger X."""
+    rng = np.random.default_rng(7)
+    n = 12
+    Q = haar_unitary(n, rng)
+    lam = rng.uniform(-3.0, 5.0, n)
+    H = (Q * lam) @ Q.conj().T
+    X = haar_unitary(n, rng)[:, :5]
+    h = 0.37
+    beta, dE, R = orc.rescale(-3.0, 5.0, h)
+    a = orc.bessel_coefficients(R, orc.choose_L(R, 1e-14))
+    got = orc.chebyshev_step(H, beta, dE, h, a, X)
+    ref = (Q * np.exp(-1j * h * lam)) @ (Q.conj().T @ X)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+# --- Gauss-Legendre nodes and the Magnus-4 step -----------------------------------------------
+
+def test_node_times_integrate_cubics_exactly():
+    T, M = 2.0, 7
+    t = orc.node_times(T, M)
+    h = T / M
+    for deg in range(4):
+        quad = h / 2 * np.sum(t[:, 0] ** deg + t[:, 1] ** deg)
+        assert abs(quad - T ** (deg + 1) / (deg + 1)) < 1e-12
+    quad4 = h / 2 * np.sum(t[:, 0] ** 4 + t[:, 1] ** 4)
+    assert abs(quad4 - T ** 5 / 5) > 1e-6        # degree 4 is not exact
+
+
+def test_static_hamiltonian_closed_form():
+    """f = const: no commutator term, U_T = exp(-i T (H0 + c V)) exactly."""
+    H0, V = _rm(8, 11)
+    T, M, c = 1.7, 20, 0.6
+    f = np.full((M, 2), c)
+    ref = scipy.linalg.expm(-1j * T * (H0 + c * V))
+    Ue = orc.build_ut(H0, V, f, T, M, route="exact")
+    Uc = orc.build_ut(H0, V, f, T, M, route="cheb", tol=1e-14)
+    assert orc.column_error(Ue, ref) < 1e-12
+    assert orc.column_error(Uc, ref) < 1e-11
+
+
+def test_zero_h0_closed_form():
+    """H0 = 0: all steps commute and the Gauss-Legendre sum of cos over a
+    period vanishes, so U_T = exp(-i eps0 T V)."""
+    _, V = _rm(6, 12)
+    T, M = TWO_PI, 30
+    f = _nodes_cos(T, M, eps0=0.4, eps1=1.3)
+    U = orc.build_ut(np.zeros_like(V), V, f, T, M, route="cheb", tol=1e-14)
+    ref = scipy.linalg.expm(-1j * 0.4 * T * V)
+    assert orc.column_error(U, ref) < 1e-11
+
+
+def _gue_drive(n, seed):
+    H0, V = _rm(n, seed)
+    return H0, V, (lambda t: H0 + math.cos(t) * V)
+
+
+def test_brute_force_tiny():
+    H0, V, Ht = _gue_drive(4, 21)
+    T, M = TWO_PI, 200
+    ref = _brute_force(Ht, 4, T)
+    U = orc.build_ut(H0, V, _nodes_cos(T, M), T, M, route="cheb")
+    assert orc.column_error(U, ref) < 2e-7
+
+
+def test_fourth_order_convergence_and_commutator_sign():
+    """e(M) / e(2M) -> 16 for the scheme; swapping the two nodes flips the sign
+    of the commutator term and must drop the order to 2 (ratio 4)."""
+    H0, V, Ht = _gue_drive(6, 3)
+    T = TWO_PI
+    ref = _brute_force(Ht, 6, T)
+    errs, errs_flip = [], []
+    for M in (25, 50, 100):
+        f = _nodes_cos(T, M)
+        errs.append(orc.column_error(orc.build_ut(H0, V, f, T, M, route="exact"), ref))
+        errs_flip.append(orc.column_error(orc.build_ut(H0, V, f[:, ::-1], T, M, route="exact"), ref))
+    r = [errs[i] / errs[i + 1] for i in range(2)]
+    rf = [errs_flip[i] / errs_flip[i + 1] for i in range(2)]
+    assert all(14.0 < x < 18.0 for x in r), r
+    assert all(3.5 < x < 4.6 for x in rf), rf
+
+
+def test_ordering_later_steps_on_the_left():
+    """A non-commuting two-valued piecewise drive: the chain must equal
+    E_2 E_1 (later on the left), not E_1 E_2."""
+    H0, V = _rm(5, 4)
+    T, M = 1.0, 2
+    f = np.array([[0.3, 0.3], [-1.1, -1.1]])
+    h = T / M
+    E1 = scipy.linalg.expm(-1j * h * (H0 + 0.3 * V))
+    E2 = scipy.linalg.expm(-1j * h * (H0 - 1.1 * V))
+    U = orc.build_ut(H0, V, f, T, M, route="cheb", tol=1e-14)
+    assert orc.column_error(U, E2 @ E1) < 1e-12
+    assert orc.column_error(U, E1 @ E2) > 1e-3
+
+
+def test_unitarity_of_chebyshev_route():
+    H0, V = _rm(16, 5)
+    T, M = TWO_PI, 50
+    U = orc.build_ut(H0, V, _nodes_cos(T, M), T, M, route="cheb", tol=1e-13)
+    mx, fro = orc.unitarity_error(U)
+    assert mx < 1e-12 and fro < 1e-11
+
+
+def test_route_c_matches_route_e_to_truncation():
+    H0, V = _rm(10, 6)
+    T, M = TWO_PI, 40
+    f = _nodes_cos(T, M)
+    Ue = orc.build_ut(H0, V, f, T, M, route="exact")
+    for tol in (1e-8, 1e-12):
+        Uc = orc.build_ut(H0, V, f, T, M, route="cheb", tol=tol)
+        assert orc.column_error(Uc, Ue) <= M * tol + 1e-12
+
+
+def test_cover_independence():
+    """Widening the spectral interval changes the Chebyshev route only at
+    truncation level."""
+    H0, V = _rm(8, 8)
+    T, M = TWO_PI, 30
+    f = _nodes_cos(T, M)
+    U1, info = orc.build_ut(H0, V, f, T, M, route="cheb", tol=1e-13, return_info=True)
+    U2 = orc.build_ut(H0, V, f, T, M, route="cheb", tol=1e-13,
+                      e_min=info["e_min"] - 3.0, e_max=info["e_max"] + 5.0)
+    assert orc.column_error(U1, U2) < 1e-10
+
+
+def test_weyl_cover_contains_every_step():
+    H0, V = _rm(20, 9)
+    T, M = TWO_PI, 25
+    h = T / M
+    a, b = orc.magnus4_weights(_nodes_cos(T, M), h)
+    K = orc.commutator(H0, V)
+    lo, hi = orc.weyl_cover(H0, V, K, a, b)
+    for k in range(M):
+        ev = np.linalg.eigvalsh(H0 + a[k] * V + b[k] * K)
+        assert lo <= ev[0] and ev[-1] <= hi
+
+
+# --- Bose-Hubbard dimer -----------------------------------------------------------------------
+
+def test_dimer_noninteracting_is_spin_representation():
+    """U = 0: H0 = -2 J S_x and V = 2 S_z of spin S = Nb/2 (Schwinger map). The
+    Lie-algebra map preserves commutators, so the discrete scheme on Nb bosons
+    equals the spin-S image of the same scheme on one boson (2 x 2)."""
+    nb, J = 9, 1.0
+    T, M = TWO_PI, 40
+    f = _nodes_cos(T, M, eps0=0.5, eps1=1.5)
+    d1, e1, v1 = dimer_tridiag(1, J, 0.0)
+    u = orc.build_ut_tridiag(d1, e1, v1, f, T, M, route="exact")
+    Sx1, Sy1, Sz1 = _spin_matrices(1)
+    sig = [2 * Sx1, 2 * Sy1, 2 * Sz1]
+    # u = cos|a| 1 - i sin|a| (a/|a|).sigma  (det u = 1 since H is traceless)
+    c = np.real(np.trace(u)) / 2
+    s_vec = np.array([np.real(1j * np.trace(u @ s) / 2) for s in sig])   # = sin|a| a/|a|
+    ang = math.atan2(np.linalg.norm(s_vec), c)
+    avec = s_vec / np.linalg.norm(s_vec) * ang
+    SxN, SyN, SzN = _spin_matrices(nb)
+    ref = scipy.linalg.expm(-1j * 2 * (avec[0] * SxN + avec[1] * SyN + avec[2] * SzN))
+    dN, eN, vN = dimer_tridiag(nb, J, 0.0)
+    for route in ("exact", "cheb"):
+        U = orc.build_ut_tridiag(dN, eN, vN, f, T, M, route=route, tol=1e-14)
+        assert orc.column_error(U, ref) < 1e-11, route
+    # eigenphase ladder: eig(u) = exp(-/+ i phi) -> eig(U) = exp(-i 2 m phi)
+    th_u = orc.eigenphases(u)
+    phi = abs(th_u[0])
+    ladder = -2 * (np.arange(nb + 1) - nb / 2) * phi
+    ladder = np.angle(np.exp(-1j * ladder)) * -1.0
+    assert orc.quasienergy_distance(orc.eigenphases(ref), ladder, T) < 1e-10
+
+
+def test_two_level_dimer_brute_force():
+    d1, e1, v1 = dimer_tridiag(1, 1.0, 0.0)
+    H0, V = dimer_dense(1, 1.0, 0.0)
+    T, M = TWO_PI, 200
+    ref = _brute_force(lambda t: H0 + (0.5 + 1.5 * math.cos(t)) * V, 2, T)
+    u = orc.build_ut_tridiag(d1, e1, v1, _nodes_cos(T, M, 0.5, 1.5), T, M, route="cheb")
+    assert orc.column_error(u, ref) < 1e-7
+
+
+def test_dimer_time_reversal_symmetry():
+    """Real symmetric H0, V and f(T - t) = f(t): U_T equals its transpose."""
+    d, e, v = dimer_tridiag(12, 1.0, 0.3)
+    T, M = TWO_PI, 60
+    U = orc.build_ut_tridiag(d, e, v, _nodes_cos(T, M, 0.5, 1.5), T, M, route="cheb")
+    assert np.max(np.abs(U - U.T)) < 1e-12
+    assert np.max(np.abs(U - np.eye(len(d)))) > 0.1
+
+
+def test_tridiag_route_matches_dense_route():
+    nb = 7
+    d, e, v = dimer_tridiag(nb, 1.0, 0.2)
+    H0, V = dimer_dense(nb, 1.0, 0.2)
+    T, M = TWO_PI, 20
+    f = _nodes_cos(T, M, 0.5, 1.5)
+    lo, hi = orc.tridiag_cover(d, e, v, *orc.magnus4_weights(f, T / M))
+    Ut = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi)
+    Ud = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi)
+    assert orc.column_error(Ut, Ud) < 1e-12
+
+
+def test_tridiag_cover_is_exact_extremes():
+    d, e, v = dimer_tridiag(30, 1.0, 0.01)
+    e = e * np.exp(1j * np.linspace(0, 2, len(e)))     # complex off-diagonal
+    H0 = np.diag(d) + np.diag(e, 1) + np.diag(np.conj(e), -1)
+    T, M = TWO_PI, 9
+    a, b = orc.magnus4_weights(_nodes_cos(T, M, 0.5, 1.5), T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    K = orc.commutator(H0, np.diag(v).astype(complex))
+    evs = [np.linalg.eigvalsh(H0 + a[k] * np.diag(v) + b[k] * K) for k in range(M)]
+    assert abs(lo - min(x[0] for x in evs)) < 1e-9
+    assert abs(hi - max(x[-1] for x in evs)) < 1e-9
+
+
+# --- Metrics ----------------------------------------------------------------------------------
+
+def test_quasienergy_distance_properties():
+    rng = np.random.default_rng(1)
+    th = np.sort(rng.uniform(-math.pi, math.pi, 50))
+    T = 2.0
+    assert orc.quasienergy_distance(th, th, T) == 0.0
+    assert abs(orc.quasienergy_distance(th, th + 1e-7, T) - 1e-7 / T) < 1e-12
+    a = np.array([math.pi - 1e-6])
+    b = np.array([-math.pi + 1e-6])
+    assert abs(orc.quasienergy_distance(a, b, 1.0) - 2e-6) < 1e-12
+
+
+def test_eigenphases_of_known_unitary():
+    rng = np.random.default_rng(2)
+    Q = haar_unitary(9, rng)
+    th = np.sort(rng.uniform(-3.0, 3.0, 9))
+    U = (Q * np.exp(-1j * th)) @ Q.conj().T
+    assert np.max(np.abs(orc.eigenphases(U) - th)) < 1e-12
+
+
+# --- Gradient ---------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("route", ["exact", "cheb"])
+def test_gradient_against_central_differences(route):
+    rng = np.random.default_rng(33)
+    n, M, T = 6, 10, 2.0
+    H0, V = gue(n, rng), gue(n, rng)
+    f = rng.uniform(-1, 1, M)
+    W = haar_unitary(n, rng)
+    lo, hi = -6.0, 6.0
+
+    def loss(ff):
+        U = orc.build_ut(H0, V, np.stack([ff, ff], 1), T, M, route=route,
+                         e_min=lo, e_max=hi, L=20)
+        return orc.trace_fidelity_loss(U, W)
+
+    g = orc.grad_piecewise(H0, V, f, T, W, route=route, e_min=lo, e_max=hi, L=20)
+    eps = 1e-5
+    for k in range(M):
+        fp, fm = f.copy(), f.copy()
+        fp[k] += eps
+        fm[k] -= eps
+        fd = (loss(fp) - loss(fm)) / (2 * eps)
+        assert abs(fd - g[k]) < 1e-8 + 1e-6 * abs(g[k]), (k, fd, g[k])
+
+
+def test_gradient_routes_agree_to_truncation():
+    rng = np.random.default_rng(34)
+    n, M, T = 5, 8, 2.0
+    H0, V = gue(n, rng), gue(n, rng)
+    f = rng.uniform(-1, 1, M)
+    W = haar_unitary(n, rng)
+    ge = orc.grad_piecewise(H0, V, f, T, W, route="exact")
+    gc = orc.grad_piecewise(H0, V, f, T, W, route="cheb", e_min=-6, e_max=6, tol=1e-14)
+    assert np.max(np.abs(ge - gc)) < 1e-11
+
+
+# --- Work model (Sec. 6, Table 2) -------------------------------------------------------------
+
+def test_work_model_matches_paper_operation_counts():
+    """The paper's profiler count, times 4 double-precision operations per
+    packed instruction, equals M L complex N^3 products (8 N^3 real
+    operations each) to within a few per cent: the hot path is M L zgemm's."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "paper_table2_opcounts.txt"))
+    M, L = 100, 50
+    for N, oc in rows:
+        ratio = 4.0 * oc * 1e6 / (M * L * 8.0 * N ** 3)
+        assert 1.0 <= ratio < 1.04, (N, ratio)
