@@ -1,0 +1,192 @@
+/*
+ * floquet.h -- C ABI of the MI355X Floquet-operator library (libfloquet.so).
+ *
+ * The library builds the one-period propagator ("Floquet operator") U_T of
+ *     i dX/dt = H(t) X,   H(t) = H0 + f(t) Hmod,   f(t + T) = f(t)
+ * (Laptyeva et al., arXiv:1508.07621, Sec. 3, Eq. (13); propagator Sec. 2,
+ * Eqs. (1) and (3); hbar = 1) as a chain of M single-step exponentials
+ * (Sec. 2, Eq. (9)), each applied to all N columns at once (Sec. 3 and Sec. 5:
+ * the identity is propagated as a block, so the work is matrix-matrix products).
+ *
+ * One step k (time t_{k-1} = (k-1) h to t_k, h = T / M):
+ *   - Magnus-4 effective Hamiltonian from the drive at the two Gauss-Legendre
+ *     nodes t_{k-1} + (1/2 -/+ sqrt(3)/6) h (values f1, f2; Sec. 2, Eq. (8)
+ *     truncated after its commutator term):
+ *         H_eff,k = H0 + a_k Hmod + b_k K,   K = -i [H0, Hmod],
+ *         a_k = (f1 + f2) / 2,   b_k = sqrt(3) h (f1 - f2) / 12;
+ *   - rescaling into [-1, 1] (Sec. 2, Eq. (11)):
+ *         Ht = (H_eff,k - beta) / dE,  beta = (e_max + e_min) / 2,
+ *         dE = (e_max - e_min) / 2,    R = h dE;
+ *   - Chebyshev expansion with Bessel weights (Sec. 2, Eqs. (10)-(12)), in the
+ *     equivalent real-multiplier form
+ *         P_0 = X, P_1 = Ht X, P_{l+1} = 2 Ht P_l - P_{l-1},
+ *         X <- exp(-i beta h) sum_{l=0..L} c_l P_l,
+ *         c_0 = J_0(R), c_l = 2 (-i)^l J_l(R).
+ *
+ * Conventions for every entry point:
+ *   - complex numbers are complex128 (two float64, real part first);
+ *   - dense matrices are row-major, element [i][j] = <i|A|j>; the columns of
+ *     X, U_T and X0 are the propagated states;
+ *   - "device" pointers are HIP device memory owned by the caller; the library
+ *     never allocates or frees device memory (the caller hands in one
+ *     workspace, sized by fq_workspace_bytes); "host" pointers are ordinary
+ *     host memory owned by the caller;
+ *   - all device work is enqueued on the stream given to fq_create; entry
+ *     points that return host values synchronise that stream first;
+ *   - every entry point returns fq_status; FQ_OK == 0. Arguments are checked
+ *     before any device work; on a non-OK status the outputs are unspecified
+ *     and fq_last_error() describes the failure (thread-local string). The
+ *     context stays usable after every error except FQ_ERR_HIP.
+ */
+#ifndef FLOQUET_H
+#define FLOQUET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FQ_OK = 0,
+  FQ_ERR_ARG = 1,          /* invalid argument: size, null pointer, range, layout */
+  FQ_ERR_NONFINITE = 2,    /* NaN / Inf in a host scalar or array argument */
+  FQ_ERR_SPECTRUM = 3,     /* given interval does not contain the library's bounds */
+  FQ_ERR_HIP = 4,          /* a HIP runtime call failed; the context is unusable */
+  FQ_ERR_UNSUPPORTED = 5,  /* valid request this build does not implement */
+  FQ_ERR_STATE = 6         /* call out of order (e.g. floquet_grad without a tape) */
+} fq_status;
+
+typedef enum { FQ_DENSE = 0, FQ_TRIDIAG = 1 } fq_layout;
+
+/* Arithmetic of the Chebyshev products. FQ_FP64: everything in float64.
+ * FQ_FP32: products on FP32 matrix cores with FP32 accumulation; P_l stored
+ * FP32; X, the Chebyshev sum and the step phase stay float64.
+ * FQ_BF16X3: products on BF16 matrix cores, each operand split into three
+ * BF16 pieces (six cross products kept), FP32 accumulation; X and the
+ * Chebyshev sum float64. Setup, coefficients and checks are always float64. */
+typedef enum { FQ_FP64 = 0, FQ_FP32 = 1, FQ_BF16X3 = 2 } fq_precision;
+
+/* The time-independent operators of H(t) = H0 + f(t) Hmod (Sec. 3, Eq. (13)). */
+typedef struct fq_system {
+  int64_t n;                 /* dimension N >= 1 */
+  int32_t layout;            /* fq_layout */
+  int32_t reserved0;         /* must be 0 */
+  /* FQ_DENSE: device, n*n complex128, row-major, Hermitian (not checked). */
+  const void* h0;
+  const void* hmod;
+  /* FQ_TRIDIAG: H0 Hermitian tridiagonal, Hmod real diagonal (the dimer of
+   * Sec. 4 has exactly this structure in its Fock basis). Device pointers:
+   * h0_diag n float64, h0_off n-1 complex128 with h0_off[i] = H0[i][i+1]
+   * (H0[i+1][i] is its conjugate), hmod_diag n float64. */
+  const double* h0_diag;
+  const void* h0_off;
+  const double* hmod_diag;
+} fq_system;
+
+/* Time grid, drive samples and method parameters. */
+typedef struct fq_params {
+  double T;                  /* period > 0 */
+  int32_t M;                 /* steps per period >= 1; h = T / M */
+  int32_t L;                 /* Chebyshev order; 0 = smallest L with
+                                2 sum_{l>L} |J_l(R)| <= tol */
+  const double* f_nodes;     /* host, 2*M float64: f at the two Gauss-Legendre
+                                nodes of each step, earlier node first
+                                (fq_node_times gives the times) */
+  double e_min, e_max;       /* spectral interval containing the spectrum of
+                                every H_eff,k; both NaN = the library computes
+                                it (tridiagonal: exact per-step extremes by
+                                Sturm bisection; dense: Weyl cover from Lanczos
+                                extremes of H0 and Hmod plus a 1 % margin).
+                                A given interval is rejected with
+                                FQ_ERR_SPECTRUM when it misses a point known to
+                                lie in some step's spectral hull (tridiagonal:
+                                the exact extremes; dense: Ritz values of H_eff
+                                at the steps with the smallest and largest a_k) */
+  double tol;                /* truncation tolerance used when L == 0 (> 0) */
+  int32_t precision;         /* fq_precision (FQ_TRIDIAG supports FQ_FP64 only) */
+  int32_t checkpoint_every;  /* > 0: floquet_build_UT keeps X_0, X_s, X_2s, ...
+                                (s = checkpoint_every) for floquet_grad;
+                                0 = no tape */
+} fq_params;
+
+/* Setup values and per-build measurements. */
+typedef struct fq_report {
+  int32_t L;                 /* Chebyshev order in use */
+  int32_t M;
+  double R, dE, beta;        /* R = h dE; beta = interval midpoint */
+  double e_min, e_max;       /* interval in use */
+  double unitarity_max;      /* max |(U^dagger U - 1)_ij| of the last build (FP64) */
+  double unitarity_fro;      /* Frobenius norm of U^dagger U - 1 */
+  double ms_build;           /* device time of the last build, milliseconds */
+} fq_report;
+
+typedef struct fq_ctx fq_ctx;  /* opaque; host memory owned by the library */
+
+/* Gauss-Legendre sampling times of the drive: t_out[2k] and t_out[2k+1] are
+ * the earlier and later node of step k+1, i.e. (k + 1/2 -/+ sqrt(3)/6) h.
+ * t_out: host, 2*M float64. */
+fq_status fq_node_times(double T, int32_t M, double* t_out);
+
+/* Expansion weights a_0 = J_0(R), a_l = 2 J_l(R), l = 1..L (Sec. 2, Eq. (12)),
+ * by Miller's backward recurrence normalised with J_0 + 2 sum_k J_2k = 1.
+ * R >= 0, L >= 0; out: host, L+1 float64. */
+fq_status fq_bessel_weights(double R, int32_t L, double* out);
+
+/* Smallest L >= 1 with 2 sum_{l > L} |J_l(R)| <= tol (R >= 0, tol > 0). */
+fq_status fq_choose_order(double R, double tol, int32_t* L_out);
+
+/* Extreme eigenvalues of the Hermitian tridiagonal matrix with diagonal d[n]
+ * and off-diagonal moduli |e[i]| = e_abs[i] (n-1 values), by Sturm-sequence
+ * bisection to full FP64 accuracy. Host pointers. */
+fq_status fq_tridiag_extremes(int64_t n, const double* d, const double* e_abs,
+                              double* lam_min, double* lam_max);
+
+/* Bytes of device workspace a context for (sys, par) needs (256-byte aligned
+ * pointer expected). Checks the arguments like fq_create. */
+fq_status fq_workspace_bytes(const fq_system* sys, const fq_params* par, size_t* bytes);
+
+/* Create a context: validates, computes K, the spectral interval, R, L, the
+ * Bessel weights and the node scalars (host FP64 except K, which is formed on
+ * the device). The operator arrays of sys must stay valid and unchanged for
+ * the life of the context. workspace: device, ws_bytes >= fq_workspace_bytes.
+ * stream: a hipStream_t (NULL = default stream). */
+fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+fq_status fq_destroy(fq_ctx* ctx);
+
+/* Setup values (L, R, dE, beta, interval) and the last build's measurements. */
+fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep);
+
+/* Build U_T = X_M from X_0 = identity (Sec. 3: the identity propagated over
+ * one period). U_out: device, n*n complex128 row-major, [i][j] = <i|U_T|j>.
+ * rep (host, nullable) receives fq_get_report after the build, including the
+ * FP64 unitarity measures of U_T. If checkpoint_every > 0 the tape for
+ * floquet_grad is recorded. */
+fq_status floquet_build_UT(fq_ctx* ctx, void* U_out, fq_report* rep);
+
+/* Propagate ncols given states over steps k0+1 .. k1 (0 <= k0 <= k1 <= M):
+ * X_out = E_k1 ... E_{k0+1} X0 (the second propagation round of Sec. 3 and
+ * its resumption from any step). X0, X_out: device, n*ncols complex128,
+ * row-major (column c is state c); they may alias. 1 <= ncols <= n. */
+fq_status floquet_propagate(fq_ctx* ctx, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
+                            void* X_out);
+
+/* Gradient of a real loss of U_T with respect to the 2*M drive samples, by
+ * the reverse sweep through the Chebyshev recurrence of every step (beta, dE
+ * and L held fixed), recomputing each segment from the tape of the last
+ * floquet_build_UT. U_bar: device, n*n complex128 row-major with
+ * U_bar[i][j] = dLoss/dRe U[i][j] + i dLoss/dIm U[i][j]. grad_f_nodes: host,
+ * 2*M float64, same order as f_nodes. Needs checkpoint_every > 0. */
+fq_status floquet_grad(fq_ctx* ctx, const void* U_bar, double* grad_f_nodes);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* fq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOQUET_H */

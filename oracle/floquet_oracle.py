@@ -238,7 +238,7 @@ def tridiag_cover(h0_diag, h0_off, v_diag, a, b) -> Tuple[float, float]:
 # The chain (Sec. 2, Eq. (9); Sec. 3, the algorithm)
 # ---------------------------------------------------------------------------
 
-def _chain(Hk_of, M: int, T: float, route: str, X0, e_min, e_max, L, tol):
+def _chain(Hk_of, M: int, T: float, route: str, X0, e_min, e_max, L, tol, k_range=None):
     h = T / M
     info: Dict[str, float] = {}
     if route == "cheb":
@@ -248,7 +248,8 @@ def _chain(Hk_of, M: int, T: float, route: str, X0, e_min, e_max, L, tol):
         a = bessel_coefficients(R, L)
         info.update(beta=beta, dE=dE, R=R, L=L)
     X = X0
-    for k in range(M):
+    k0, k1 = (0, M) if k_range is None else k_range
+    for k in range(k0, k1):
         Hk = Hk_of(k)
         if route == "exact":
             Hd = Hk.toarray() if scipy.sparse.issparse(Hk) else Hk
@@ -263,13 +264,15 @@ def _chain(Hk_of, M: int, T: float, route: str, X0, e_min, e_max, L, tol):
 def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: int,
              route: str = "cheb", e_min: Optional[float] = None, e_max: Optional[float] = None,
              L: Optional[int] = None, tol: float = 1e-12, X0: Optional[np.ndarray] = None,
-             return_info: bool = False):
+             return_info: bool = False, k_range: Optional[Tuple[int, int]] = None):
     """U_T (or U_T X0) of the dense model H0 + f(t) V.
 
     f_nodes has shape (M, 2): the drive at the two Gauss-Legendre nodes of each
     step (node_times). route "exact" exponentiates each H_eff exactly; route
     "cheb" uses the Chebyshev recurrence with the interval [e_min, e_max]
     (default: the Weyl cover) and order L (default: choose_L(R, tol)).
+    k_range = (k0, k1) applies only steps k0+1 .. k1 to X0: the propagator
+    from t_k0 to t_k1, since single-step propagators compose (Sec. 2).
     """
     H0 = np.asarray(H0, np.complex128)
     V = np.asarray(V, np.complex128)
@@ -281,7 +284,7 @@ def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: in
         e_min, e_max = weyl_cover(H0, V, K, a, b)
     X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
     U, info = _chain(lambda k: magnus4_heff(H0, V, K, a[k], b[k]), M, T, route, X0,
-                     e_min, e_max, L, tol)
+                     e_min, e_max, L, tol, k_range)
     info.update(e_min=e_min, e_max=e_max)
     return (U, info) if return_info else U
 
@@ -289,7 +292,7 @@ def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: in
 def build_ut_tridiag(h0_diag, h0_off, v_diag, f_nodes, T: float, M: int, route: str = "cheb",
                      e_min: Optional[float] = None, e_max: Optional[float] = None,
                      L: Optional[int] = None, tol: float = 1e-12, X0: Optional[np.ndarray] = None,
-                     return_info: bool = False):
+                     return_info: bool = False, k_range: Optional[Tuple[int, int]] = None):
     """Same as build_ut for a Hermitian tridiagonal H0 and a diagonal V, with
     sparse products (default interval: tridiag_cover)."""
     n = len(h0_diag)
@@ -300,7 +303,7 @@ def build_ut_tridiag(h0_diag, h0_off, v_diag, f_nodes, T: float, M: int, route: 
         e_min, e_max = tridiag_cover(h0_diag, h0_off, v_diag, a, b)
     X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
     U, info = _chain(lambda k: (H0 + a[k] * V + b[k] * K).tocsr(), M, T, route, X0,
-                     e_min, e_max, L, tol)
+                     e_min, e_max, L, tol, k_range)
     info.update(e_min=e_min, e_max=e_max)
     return (U, info) if return_info else U
 

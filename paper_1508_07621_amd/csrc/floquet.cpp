@@ -1,0 +1,707 @@
+// C-ABI driver of libfloquet: argument checks, host FP64 setup, workspace
+// layout and the step loops that enqueue the HIP kernels on one stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using fq::ChebTerm;
+
+namespace {
+
+thread_local std::string g_err;
+
+fq_status fail(fq_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define FQ_HIP(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      if (ctx) (ctx)->broken = true;                                                       \
+      return fail(FQ_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+    }                                                                                      \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxOrder = 65535;       // capacity of the device coefficient table
+constexpr int kLanczosSteps = 160;
+constexpr double kDenseMargin = 0.01;  // relative widening of the Lanczos-based cover
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+long dense_tile(long n) { return n >= 1024 ? 128 : 64; }
+long pad_to(long x, long t) { return (x + t - 1) / t * t; }
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+struct Layout {
+  size_t total = 0;
+  size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
+         off_pb = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0;
+  long np = 0;
+  int n_tape = 0;
+};
+
+Layout plan(const fq_system* sys, const fq_params* par) {
+  Layout lay;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = cur;
+    cur = align_up(cur + bytes);
+    return o;
+  };
+  const long n = sys->n;
+  if (sys->layout == FQ_DENSE) {
+    lay.np = pad_to(n, dense_tile(n));
+    const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
+    lay.off_h0 = take(plane2);
+    lay.off_v = take(plane2);
+    lay.off_k = take(plane2);
+    lay.off_ht = take(plane2);
+    lay.off_x = take(plane2);
+    lay.off_y = take(plane2);
+    lay.off_pa = take(plane2);
+    lay.off_pb = take(plane2);
+    if (par->checkpoint_every > 0) {
+      lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
+      lay.off_tape = take(plane2 * (size_t)lay.n_tape);
+    }
+  } else {
+    lay.np = pad_to(n, dense_tile(n));
+    const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
+    lay.off_x = take(plane2);  // planar copy of U_T for the unitarity check
+  }
+  lay.off_small = take(64 * sizeof(double));
+  lay.off_ab = take(2 * sizeof(double) * (size_t)par->M);
+  lay.off_coef = take(2 * sizeof(double) * (size_t)(kMaxOrder + 1));
+  lay.total = cur;
+  return lay;
+}
+
+fq_status validate(const fq_system* sys, const fq_params* par) {
+  if (!sys || !par) return fail(FQ_ERR_ARG, "null system or params");
+  if (sys->n < 1) return fail(FQ_ERR_ARG, "n must be >= 1 (got %lld)", (long long)sys->n);
+  if (sys->reserved0 != 0) return fail(FQ_ERR_ARG, "reserved0 must be 0");
+  if (sys->layout == FQ_DENSE) {
+    if (!sys->h0 || !sys->hmod) return fail(FQ_ERR_ARG, "dense layout needs h0 and hmod");
+    if (sys->n > 46336) return fail(FQ_ERR_ARG, "n too large for 32-bit tile indexing");
+  } else if (sys->layout == FQ_TRIDIAG) {
+    if (!sys->h0_diag || !sys->hmod_diag || (sys->n > 1 && !sys->h0_off))
+      return fail(FQ_ERR_ARG, "tridiagonal layout needs h0_diag, h0_off and hmod_diag");
+  } else {
+    return fail(FQ_ERR_ARG, "unknown layout %d", sys->layout);
+  }
+  if (!is_finite(par->T) || par->T <= 0) return fail(FQ_ERR_ARG, "T must be finite and > 0");
+  if (par->M < 1) return fail(FQ_ERR_ARG, "M must be >= 1");
+  if (!par->f_nodes) return fail(FQ_ERR_ARG, "f_nodes is null");
+  for (int i = 0; i < 2 * par->M; ++i)
+    if (!is_finite(par->f_nodes[i])) return fail(FQ_ERR_NONFINITE, "f_nodes[%d] is not finite", i);
+  if (par->L < 0 || par->L > kMaxOrder) return fail(FQ_ERR_ARG, "L out of range [0, %d]", kMaxOrder);
+  if (par->L == 0 && (!is_finite(par->tol) || par->tol <= 0))
+    return fail(FQ_ERR_ARG, "tol must be finite and > 0 when L == 0");
+  const bool nmin = std::isnan(par->e_min), nmax = std::isnan(par->e_max);
+  if (nmin != nmax) return fail(FQ_ERR_ARG, "give both e_min and e_max, or neither (NaN)");
+  if (!nmin) {
+    if (!is_finite(par->e_min) || !is_finite(par->e_max))
+      return fail(FQ_ERR_NONFINITE, "spectral interval is not finite");
+    if (!(par->e_max > par->e_min)) return fail(FQ_ERR_SPECTRUM, "need e_max > e_min");
+  }
+  if (par->precision < FQ_FP64 || par->precision > FQ_BF16X3)
+    return fail(FQ_ERR_ARG, "unknown precision %d", par->precision);
+  if (par->checkpoint_every < 0) return fail(FQ_ERR_ARG, "checkpoint_every must be >= 0");
+  if (sys->layout == FQ_TRIDIAG) {
+    if (par->precision != FQ_FP64)
+      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal layout runs in FP64 only");
+    if (sys->n > fq::tridiag_resident_max_n())
+      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal n > %ld not supported", fq::tridiag_resident_max_n());
+    if (par->checkpoint_every > 0)
+      return fail(FQ_ERR_UNSUPPORTED, "gradient tape not available for the tridiagonal layout");
+  }
+  if (sys->layout == FQ_DENSE && par->precision != FQ_FP64)
+    return fail(FQ_ERR_UNSUPPORTED, "mixed precision not available in this build");
+  return FQ_OK;
+}
+
+// ---- spectral interval ------------------------------------------------------------------------
+
+using cd = std::complex<double>;
+using Matvec = std::function<fq_status(const std::vector<cd>&, std::vector<cd>&)>;
+
+// y = A x for a dense complex128 device matrix, through the device scratch
+// (the Y planes are free during setup).
+fq_status device_matvec(fq_ctx* ctx, const void* A, const std::vector<cd>& x, std::vector<cd>& y) {
+  const long n = ctx->n;
+  void* dx = ctx->yr;
+  void* dy = ctx->yr + 2 * n;
+  y.resize(n);
+  FQ_HIP(ctx, hipMemcpyAsync(dx, x.data(), n * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+  FQ_HIP(ctx, fq::launch_zgemv(A, n, dx, dy, ctx->stream));
+  FQ_HIP(ctx, hipMemcpyAsync(y.data(), dy, n * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+  FQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return FQ_OK;
+}
+
+// Extreme Ritz values of a Hermitian operator after k Lanczos steps from a
+// fixed pseudo-random start vector. Ritz values lie inside
+// [lambda_min, lambda_max] and converge to its ends fastest.
+fq_status lanczos_ritz(fq_ctx* ctx, const Matvec& mv, double* lo, double* hi) {
+  const long n = ctx->n;
+  std::vector<cd> q(n), qp(n, 0.0), w(n);
+  uint64_t s = 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    s ^= s << 13;
+    s ^= s >> 7;
+    s ^= s << 17;
+    return (double)(s >> 11) / 9007199254740992.0 - 0.5;
+  };
+  double nrm = 0.0;
+  for (long i = 0; i < n; ++i) {
+    const double re = next();
+    q[i] = cd(re, next());
+    nrm += std::norm(q[i]);
+  }
+  nrm = std::sqrt(nrm);
+  for (auto& v : q) v /= nrm;
+  const int ksteps = (int)std::min<long>(n, kLanczosSteps);
+  std::vector<double> alpha, beta;
+  double bprev = 0.0;
+  for (int j = 0; j < ksteps; ++j) {
+    fq_status st = mv(q, w);
+    if (st != FQ_OK) return st;
+    double a = 0.0;
+    for (long i = 0; i < n; ++i) a += std::real(std::conj(q[i]) * w[i]);
+    double b2 = 0.0;
+    for (long i = 0; i < n; ++i) {
+      w[i] -= a * q[i] + bprev * qp[i];
+      b2 += std::norm(w[i]);
+    }
+    alpha.push_back(a);
+    const double b = std::sqrt(b2);
+    if (j + 1 == ksteps || b <= 1e-13 * (std::fabs(a) + bprev + 1e-300)) break;
+    beta.push_back(b);
+    for (long i = 0; i < n; ++i) {
+      qp[i] = q[i];
+      q[i] = w[i] / b;
+    }
+    bprev = b;
+  }
+  fq::tridiag_extremes((long)alpha.size(), alpha.data(), beta.data(), lo, hi);
+  return FQ_OK;
+}
+
+// Outer estimate of the union of spec(H_eff,k): Weyl's inequalities on the
+// Lanczos extremes of H0 and Hmod (each widened by `margin` of its spread, as
+// Ritz values approach the ends from inside) and ||K||_2 <= 2 ||H0|| ||Hmod||.
+fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin) {
+  double l0, h0, lv, hv;
+  Matvec mh0 = [&](const std::vector<cd>& x, std::vector<cd>& y) { return device_matvec(ctx, ctx->sys.h0, x, y); };
+  Matvec mv = [&](const std::vector<cd>& x, std::vector<cd>& y) { return device_matvec(ctx, ctx->sys.hmod, x, y); };
+  fq_status st = lanczos_ritz(ctx, mh0, &l0, &h0);
+  if (st != FQ_OK) return st;
+  st = lanczos_ritz(ctx, mv, &lv, &hv);
+  if (st != FQ_OK) return st;
+  const double w0 = h0 - l0, wv = hv - lv;
+  l0 -= margin * w0;
+  h0 += margin * w0;
+  lv -= margin * wv;
+  hv += margin * wv;
+  const double kap = 2.0 * std::max(std::fabs(l0), std::fabs(h0)) * std::max(std::fabs(lv), std::fabs(hv));
+  double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+  for (int k = 0; k < ctx->M; ++k) {
+    const double a = ctx->a[k], b = std::fabs(ctx->b[k]);
+    lo = std::min(lo, l0 + std::min(a * lv, a * hv) - b * kap);
+    hi = std::max(hi, h0 + std::max(a * lv, a * hv) + b * kap);
+  }
+  *lo_out = lo;
+  *hi_out = hi;
+  return FQ_OK;
+}
+
+// Inner bounds for checking a caller's interval: Ritz values of H_eff,k at the
+// steps with the smallest and the largest a_k. Each Ritz value lies in the
+// spectrum's hull of its step, so an interval that misses one cannot contain
+// that step's spectrum.
+fq_status dense_inner_bounds(fq_ctx* ctx, double* lo_out, double* hi_out) {
+  int kmin = 0, kmax = 0;
+  for (int k = 1; k < ctx->M; ++k) {
+    if (ctx->a[k] < ctx->a[kmin]) kmin = k;
+    if (ctx->a[k] > ctx->a[kmax]) kmax = k;
+  }
+  double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+  for (int k : {kmin, kmax}) {
+    const double a = ctx->a[k], b = ctx->b[k];
+    Matvec mv = [&](const std::vector<cd>& x, std::vector<cd>& y) {
+      // H0 x + a Hmod x + b K x with K x = -i (H0 (Hmod x) - Hmod (H0 x))
+      std::vector<cd> u1, u2, u3, u4;
+      fq_status st = device_matvec(ctx, ctx->sys.h0, x, u1);
+      if (st == FQ_OK) st = device_matvec(ctx, ctx->sys.hmod, x, u2);
+      if (st == FQ_OK && b != 0.0) st = device_matvec(ctx, ctx->sys.h0, u2, u3);
+      if (st == FQ_OK && b != 0.0) st = device_matvec(ctx, ctx->sys.hmod, u1, u4);
+      if (st != FQ_OK) return st;
+      y.resize(x.size());
+      for (size_t i = 0; i < x.size(); ++i) {
+        y[i] = u1[i] + a * u2[i];
+        if (b != 0.0) y[i] += b * cd(0.0, -1.0) * (u3[i] - u4[i]);
+      }
+      return FQ_OK;
+    };
+    double l, h;
+    fq_status st = lanczos_ritz(ctx, mv, &l, &h);
+    if (st != FQ_OK) return st;
+    lo = std::min(lo, l);
+    hi = std::max(hi, h);
+    if (kmin == kmax) break;
+  }
+  *lo_out = lo;
+  *hi_out = hi;
+  return FQ_OK;
+}
+
+fq_status tridiag_cover(fq_ctx* ctx, double* lo_out, double* hi_out) {
+  const long n = ctx->n;
+  std::vector<double> d0(n), v(n), off(2 * std::max<long>(n - 1, 0));
+  FQ_HIP(ctx, hipMemcpy(d0.data(), ctx->sys.h0_diag, n * sizeof(double), hipMemcpyDeviceToHost));
+  FQ_HIP(ctx, hipMemcpy(v.data(), ctx->sys.hmod_diag, n * sizeof(double), hipMemcpyDeviceToHost));
+  if (n > 1)
+    FQ_HIP(ctx, hipMemcpy(off.data(), ctx->sys.h0_off, 2 * (n - 1) * sizeof(double),
+                          hipMemcpyDeviceToHost));
+  std::vector<double> d(n), e(std::max<long>(n - 1, 1));
+  double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+  for (int k = 0; k < ctx->M; ++k) {
+    const double a = ctx->a[k], b = ctx->b[k];
+    for (long i = 0; i < n; ++i) d[i] = d0[i] + a * v[i];
+    for (long i = 0; i + 1 < n; ++i) {
+      // |h (1 - i b dv)| = |h| sqrt(1 + (b dv)^2)
+      const double hm = std::hypot(off[2 * i], off[2 * i + 1]);
+      e[i] = hm * std::hypot(1.0, b * (v[i + 1] - v[i]));
+    }
+    double l, h;
+    fq::tridiag_extremes(n, d.data(), e.data(), &l, &h);
+    lo = std::min(lo, l);
+    hi = std::max(hi, h);
+  }
+  *lo_out = lo;
+  *hi_out = hi;
+  return FQ_OK;
+}
+
+// ---- dense step loop ----------------------------------------------------------------------------
+
+fq_status dense_heff(fq_ctx* c, int k) {
+  FQ_HIP(c, fq::launch_heff_f64(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
+                                c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->stream));
+  return FQ_OK;
+}
+
+// One step on the state-major block held in (X planes): X <- E_k X.
+fq_status dense_cheb_step(fq_ctx* c, int mrows) {
+  const int L = c->L;
+  const int np = (int)c->np;
+  ChebTerm t{};
+  t.b_re = c->htr;
+  t.b_im = c->hti;
+  t.phr = c->phr;
+  t.phi = c->phi;
+  auto C = [&](int l) { return std::complex<double>(c->coef[2 * l], c->coef[2 * l + 1]); };
+  if (L == 1) {
+    t.kind = fq::CHEB_FIRST_LAST;
+    t.a_re = c->xr; t.a_im = c->xi;
+    t.p_re = c->xr; t.p_im = c->xi;
+    t.o_re = c->yr; t.o_im = c->yi;
+    t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(1).real(); t.ci = C(1).imag();
+    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+    std::swap(c->xr, c->yr);
+    std::swap(c->xi, c->yi);
+    return FQ_OK;
+  }
+  // l = 0: P1 -> Pa, Y = c0 X + c1 P1
+  t.kind = fq::CHEB_FIRST;
+  t.a_re = c->xr; t.a_im = c->xi;
+  t.p_re = c->xr; t.p_im = c->xi;
+  t.o_re = c->par; t.o_im = c->pai;
+  t.y_re = c->yr; t.y_im = c->yi;
+  t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(1).real(); t.ci = C(1).imag();
+  FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+  // buffers holding P_{l-1} and P_l
+  double *prv_r = c->xr, *prv_i = c->xi, *cur_r = c->par, *cur_i = c->pai;
+  for (int l = 1; l <= L - 1; ++l) {
+    const bool last = (l == L - 1);
+    t.kind = last ? fq::CHEB_LAST : fq::CHEB_MID;
+    t.a_re = cur_r; t.a_im = cur_i;
+    t.p_re = prv_r; t.p_im = prv_i;
+    t.cr = C(l + 1).real(); t.ci = C(l + 1).imag();
+    double *out_r, *out_i;
+    if (last) {
+      out_r = c->xr; out_i = c->xi;          // X is free once P_2 exists (or is P_0 itself, in place)
+    } else if (l == 1) {
+      out_r = c->pbr; out_i = c->pbi;        // keep X intact until P_2 is formed
+    } else {
+      out_r = prv_r; out_i = prv_i;          // in place over P_{l-1}
+    }
+    t.o_re = out_r; t.o_im = out_i;
+    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+    if (!last) {
+      prv_r = cur_r; prv_i = cur_i;
+      cur_r = out_r; cur_i = out_i;
+    }
+  }
+  return FQ_OK;
+}
+
+fq_status dense_steps(fq_ctx* c, int k0, int k1, int mrows, bool record_tape) {
+  const size_t plane2 = 2 * (size_t)c->np * (size_t)c->np;
+  if (record_tape && k0 == 0)
+    FQ_HIP(c, hipMemcpyAsync(c->tape, c->xr, plane2 / 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (record_tape && k0 == 0)
+    FQ_HIP(c, hipMemcpyAsync(c->tape + plane2 / 2, c->xi, plane2 / 2 * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  for (int k = k0; k < k1; ++k) {
+    fq_status st = dense_heff(c, k);
+    if (st != FQ_OK) return st;
+    st = dense_cheb_step(c, mrows);
+    if (st != FQ_OK) return st;
+    if (record_tape && ((k + 1) % c->ckpt == 0 || k + 1 == c->M)) {
+      const int slot = (k + 1 + c->ckpt - 1) / c->ckpt;
+      double* dst = c->tape + (size_t)slot * plane2;
+      FQ_HIP(c, hipMemcpyAsync(dst, c->xr, plane2 / 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      FQ_HIP(c, hipMemcpyAsync(dst + plane2 / 2, c->xi, plane2 / 2 * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
+  }
+  return FQ_OK;
+}
+
+fq_status unitarity(fq_ctx* c, const double* xr, const double* xi) {
+  FQ_HIP(c, hipMemsetAsync(c->small, 0, 2 * sizeof(double), c->stream));
+  FQ_HIP(c, fq::launch_unitarity_f64(xr, xi, (int)c->n, (int)c->np, c->small, c->stream));
+  double h[2];
+  FQ_HIP(c, hipMemcpyAsync(h, c->small, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  FQ_HIP(c, hipStreamSynchronize(c->stream));
+  c->last.unitarity_max = h[0];
+  c->last.unitarity_fro = std::sqrt(h[1]);
+  return FQ_OK;
+}
+
+void fill_report(fq_ctx* c) {
+  c->last.L = c->L;
+  c->last.M = c->M;
+  c->last.R = c->R;
+  c->last.dE = c->dE;
+  c->last.beta = c->beta;
+  c->last.e_min = c->e_min;
+  c->last.e_max = c->e_max;
+}
+
+fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, void* x_out) {
+  fq::TridiagJob job{};
+  job.n = c->n;
+  job.ncols = ncols;
+  job.h0_diag = c->sys.h0_diag;
+  job.h0_off = reinterpret_cast<const double*>(c->sys.h0_off);
+  job.v_diag = c->sys.hmod_diag;
+  job.ab = c->d_ab;
+  job.coef = c->d_coef;
+  job.L = c->L;
+  job.k0 = k0;
+  job.k1 = k1;
+  job.beta = c->beta;
+  job.inv_dE = 1.0 / c->dE;
+  job.phr = c->phr;
+  job.phi = c->phi;
+  job.x0 = x0;
+  job.ld_x0 = ncols;
+  job.x_out = x_out;
+  job.ld_out = ncols;
+  FQ_HIP(c, fq::launch_tridiag_resident(job, c->stream));
+  return FQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fq_last_error(void) { return g_err.c_str(); }
+
+fq_status fq_node_times(double T, int32_t M, double* t_out) {
+  if (!is_finite(T) || T <= 0) return fail(FQ_ERR_ARG, "T must be finite and > 0");
+  if (M < 1) return fail(FQ_ERR_ARG, "M must be >= 1");
+  if (!t_out) return fail(FQ_ERR_ARG, "t_out is null");
+  fq::gl2_node_times(T, M, t_out);
+  return FQ_OK;
+}
+
+fq_status fq_bessel_weights(double R, int32_t L, double* out) {
+  if (!is_finite(R) || R < 0) return fail(FQ_ERR_ARG, "R must be finite and >= 0");
+  if (L < 0 || L > kMaxOrder) return fail(FQ_ERR_ARG, "L out of range");
+  if (!out) return fail(FQ_ERR_ARG, "out is null");
+  std::vector<double> j;
+  fq::bessel_j_table(R, L, j);
+  for (int l = 0; l <= L; ++l) out[l] = (l == 0 ? 1.0 : 2.0) * j[l];
+  return FQ_OK;
+}
+
+fq_status fq_choose_order(double R, double tol, int32_t* L_out) {
+  if (!is_finite(R) || R < 0) return fail(FQ_ERR_ARG, "R must be finite and >= 0");
+  if (!is_finite(tol) || tol <= 0) return fail(FQ_ERR_ARG, "tol must be finite and > 0");
+  if (!L_out) return fail(FQ_ERR_ARG, "L_out is null");
+  const int L = fq::choose_order(R, tol);
+  if (L < 1 || L > kMaxOrder) return fail(FQ_ERR_UNSUPPORTED, "required order exceeds %d", kMaxOrder);
+  *L_out = L;
+  return FQ_OK;
+}
+
+fq_status fq_tridiag_extremes(int64_t n, const double* d, const double* e_abs, double* lam_min,
+                              double* lam_max) {
+  if (n < 1 || !d || (n > 1 && !e_abs) || !lam_min || !lam_max)
+    return fail(FQ_ERR_ARG, "bad arguments");
+  for (int64_t i = 0; i < n; ++i)
+    if (!is_finite(d[i]) || (i + 1 < n && !is_finite(e_abs[i])))
+      return fail(FQ_ERR_NONFINITE, "non-finite entry");
+  fq::tridiag_extremes((long)n, d, e_abs, lam_min, lam_max);
+  return FQ_OK;
+}
+
+fq_status fq_workspace_bytes(const fq_system* sys, const fq_params* par, size_t* bytes) {
+  fq_status st = validate(sys, par);
+  if (st != FQ_OK) return st;
+  if (!bytes) return fail(FQ_ERR_ARG, "bytes is null");
+  *bytes = plan(sys, par).total;
+  return FQ_OK;
+}
+
+fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  if (!out) return fail(FQ_ERR_ARG, "out is null");
+  *out = nullptr;
+  fq_status st = validate(sys, par);
+  if (st != FQ_OK) return st;
+  const Layout lay = plan(sys, par);
+  if (!workspace) return fail(FQ_ERR_ARG, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(FQ_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (ws_bytes < lay.total)
+    return fail(FQ_ERR_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
+
+  fq_ctx* c = new (std::nothrow) fq_ctx();
+  if (!c) return fail(FQ_ERR_ARG, "out of host memory");
+  c->n = sys->n;
+  c->layout = sys->layout;
+  c->sys = *sys;
+  c->T = par->T;
+  c->M = par->M;
+  c->h = par->T / par->M;
+  c->tol = par->tol;
+  c->precision = par->precision;
+  c->ckpt = par->checkpoint_every;
+  c->f_nodes.assign(par->f_nodes, par->f_nodes + 2 * par->M);
+  c->a.resize(c->M);
+  c->b.resize(c->M);
+  for (int k = 0; k < c->M; ++k) {
+    const double f1 = c->f_nodes[2 * k], f2 = c->f_nodes[2 * k + 1];
+    c->a[k] = 0.5 * (f1 + f2);
+    c->b[k] = std::sqrt(3.0) * c->h * (f1 - f2) / 12.0;
+  }
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->ws_bytes = ws_bytes;
+  c->np = lay.np;
+  auto P = [&](size_t off) { return reinterpret_cast<double*>(c->ws + off); };
+  const size_t plane = (size_t)lay.np * (size_t)lay.np;
+  c->small = P(lay.off_small);
+  c->d_ab = P(lay.off_ab);
+  c->d_coef = P(lay.off_coef);
+  c->xr = P(lay.off_x);
+  c->xi = c->xr + plane;
+  if (sys->layout == FQ_DENSE) {
+    c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;
+    c->vr = P(lay.off_v);   c->vi = c->vr + plane;
+    c->kr = P(lay.off_k);   c->ki = c->kr + plane;
+    c->htr = P(lay.off_ht); c->hti = c->htr + plane;
+    c->yr = P(lay.off_y);   c->yi = c->yr + plane;
+    c->par = P(lay.off_pa); c->pai = c->par + plane;
+    c->pbr = P(lay.off_pb); c->pbi = c->pbr + plane;
+    if (lay.n_tape > 0) {
+      c->tape = P(lay.off_tape);
+      c->n_tape = lay.n_tape;
+    }
+  }
+
+  auto bail = [&](fq_status s) {
+    delete c;
+    return s;
+  };
+  if (hipMemsetAsync(c->ws, 0, lay.total, c->stream) != hipSuccess)
+    return bail(fail(FQ_ERR_HIP, "hipMemsetAsync of the workspace failed"));
+
+  const long n = c->n;
+  if (sys->layout == FQ_DENSE) {
+    // planar copies of H0 and Hmod, and K = -i (H0 Hmod - Hmod H0) on FP64 matrix cores:
+    // (H0 Hmod)(i,j) = sum_k H0(i,k) conj(Hmod(j,k)) for Hermitian Hmod, and likewise.
+    const int np = (int)c->np;
+    if (fq::launch_pack_planar(sys->h0, n, n, n, c->h0r, c->h0i, np, c->stream) != hipSuccess ||
+        fq::launch_pack_planar(sys->hmod, n, n, n, c->vr, c->vi, np, c->stream) != hipSuccess ||
+        fq::launch_zgemm_nt_f64(c->h0r, c->h0i, false, c->vr, c->vi, true, c->kr, c->ki, np, np,
+                                np, np, 0.0, -1.0, 0.0, 0.0, c->stream) != hipSuccess ||
+        fq::launch_zgemm_nt_f64(c->vr, c->vi, false, c->h0r, c->h0i, true, c->kr, c->ki, np, np,
+                                np, np, 0.0, 1.0, 1.0, 0.0, c->stream) != hipSuccess)
+      return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(hipGetLastError())));
+  }
+
+  // spectral interval
+  double lo, hi;
+  const bool given = !std::isnan(par->e_min);
+  if (sys->layout == FQ_DENSE) {
+    st = given ? dense_inner_bounds(c, &lo, &hi) : dense_cover(c, &lo, &hi, kDenseMargin);
+  } else {
+    st = tridiag_cover(c, &lo, &hi);
+  }
+  if (st != FQ_OK) return bail(st);
+  if (given) {
+    const double slack = 1e-9 * std::max({1.0, std::fabs(lo), std::fabs(hi)});
+    if (par->e_min > lo + slack || par->e_max < hi - slack)
+      return bail(fail(FQ_ERR_SPECTRUM,
+                       "interval [%.17g, %.17g] does not contain the bounds [%.17g, %.17g]",
+                       par->e_min, par->e_max, lo, hi));
+    lo = par->e_min;
+    hi = par->e_max;
+  }
+  if (!(hi > lo)) {  // a constant H: any positive half-width gives the exact phase
+    const double s = std::max(1.0, std::fabs(lo)) * 1e-8;
+    lo -= s;
+    hi += s;
+  }
+  c->e_min = lo;
+  c->e_max = hi;
+  c->beta = 0.5 * (hi + lo);
+  c->dE = 0.5 * (hi - lo);
+  c->R = c->h * c->dE;
+  if (par->L > 0) {
+    c->L = par->L;
+  } else {
+    c->L = fq::choose_order(c->R, par->tol);
+    if (c->L < 1 || c->L > kMaxOrder)
+      return bail(fail(FQ_ERR_UNSUPPORTED, "required Chebyshev order exceeds %d (R = %g)", kMaxOrder, c->R));
+  }
+  std::vector<double> j;
+  fq::bessel_j_table(c->R, c->L, j);
+  c->weights.resize(c->L + 1);
+  c->coef.resize(2 * (c->L + 1));
+  for (int l = 0; l <= c->L; ++l) {
+    const double w = (l == 0 ? 1.0 : 2.0) * j[l];
+    c->weights[l] = w;
+    // (-i)^l w
+    const int q = l & 3;
+    c->coef[2 * l] = (q == 0) ? w : (q == 2 ? -w : 0.0);
+    c->coef[2 * l + 1] = (q == 1) ? -w : (q == 3 ? w : 0.0);
+  }
+  c->phr = std::cos(c->beta * c->h);
+  c->phi = -std::sin(c->beta * c->h);
+  std::vector<double> ab(2 * c->M);
+  for (int k = 0; k < c->M; ++k) {
+    ab[2 * k] = c->a[k];
+    ab[2 * k + 1] = c->b[k];
+  }
+  if (hipMemcpyAsync(c->d_ab, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(FQ_ERR_HIP, "upload of the step tables failed"));
+  fill_report(c);
+  *out = c;
+  return FQ_OK;
+}
+
+fq_status fq_destroy(fq_ctx* ctx) {
+  delete ctx;
+  return FQ_OK;
+}
+
+fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep) {
+  if (!ctx || !rep) return fail(FQ_ERR_ARG, "null argument");
+  *rep = ctx->last;
+  return FQ_OK;
+}
+
+fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
+  if (!c || !U_out) return fail(FQ_ERR_ARG, "null argument");
+  if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  hipEvent_t e0, e1;
+  FQ_HIP(c, hipEventCreate(&e0));
+  FQ_HIP(c, hipEventCreate(&e1));
+  fq_status st = FQ_OK;
+  if (c->layout == FQ_DENSE) {
+    FQ_HIP(c, fq::launch_identity_rows(c->xr, c->xi, c->n, c->np, c->np, c->stream));
+    FQ_HIP(c, hipEventRecord(e0, c->stream));
+    st = dense_steps(c, 0, c->M, (int)c->np, c->ckpt > 0);
+    if (st != FQ_OK) return st;
+    FQ_HIP(c, hipEventRecord(e1, c->stream));
+    FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->stream));
+    c->tape_valid = c->ckpt > 0;
+    st = unitarity(c, c->xr, c->xi);
+  } else {
+    FQ_HIP(c, hipEventRecord(e0, c->stream));
+    st = tridiag_run(c, nullptr, c->n, 0, c->M, U_out);
+    if (st != FQ_OK) return st;
+    FQ_HIP(c, hipEventRecord(e1, c->stream));
+    FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->stream));
+    st = unitarity(c, c->xr, c->xi);
+  }
+  if (st != FQ_OK) return st;
+  FQ_HIP(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  FQ_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->last.ms_build = ms;
+  fill_report(c);
+  if (rep) *rep = c->last;
+  return FQ_OK;
+}
+
+fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
+                            void* X_out) {
+  if (!c || !X0 || !X_out) return fail(FQ_ERR_ARG, "null argument");
+  if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
+  if (k0 < 0 || k1 < k0 || k1 > c->M) return fail(FQ_ERR_ARG, "need 0 <= k0 <= k1 <= M");
+  if (c->layout == FQ_DENSE) {
+    const long mrows = pad_to(ncols, dense_tile(c->n));
+    FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->stream));
+    fq_status st = dense_steps(c, k0, k1, (int)mrows, false);
+    if (st != FQ_OK) return st;
+    FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, ncols, X_out, ncols, c->stream));
+    c->tape_valid = false;  // the planes the tape was taken from were reused
+  } else {
+    fq_status st = tridiag_run(c, X0, ncols, k0, k1, X_out);
+    if (st != FQ_OK) return st;
+  }
+  FQ_HIP(c, hipStreamSynchronize(c->stream));
+  return FQ_OK;
+}
+
+fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
+  if (!c || !U_bar || !grad_f_nodes) return fail(FQ_ERR_ARG, "null argument");
+  if (c->ckpt <= 0) return fail(FQ_ERR_STATE, "context was created without a gradient tape");
+  if (!c->tape_valid) return fail(FQ_ERR_STATE, "no tape: call floquet_build_UT first");
+  return fail(FQ_ERR_UNSUPPORTED, "gradient not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Internal declarations shared by the C-ABI driver and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/floquet.h"
+
+namespace fq {
+
+// ---- host numerics (host_numerics.cpp) ---------------------------------------------------
+void gl2_node_times(double T, int M, double* t_out);
+void bessel_j_table(double x, int lmax, std::vector<double>& out);
+int choose_order(double R, double tol);
+void tridiag_extremes(long n, const double* d, const double* e_abs, double* lo, double* hi);
+
+// ---- dense kernels (kernels_dense.hip) ---------------------------------------------------
+// All dense working matrices are planar (separate real and imaginary float64
+// planes), padded to np x np with zeros, row stride np. Column states are
+// stored "state-major": row j of a plane holds state j (the transpose of the
+// user's column layout), so every product is C(j, i) = sum_k A(j, k) B(i, k)
+// with both operands contiguous along k.
+
+// Epilogue kinds of the Chebyshev products (one launch = one term).
+enum ChebKind : int {
+  CHEB_FIRST = 0,       // P1 = acc; Y = c0 X + c1 P1
+  CHEB_FIRST_LAST = 1,  // (L == 1) out = ph (c0 X + c1 acc)
+  CHEB_MID = 2,         // P_{l+1} = 2 acc - P_{l-1}; Y += c P_{l+1}
+  CHEB_LAST = 3         // P_L = 2 acc - P_{L-1}; out = ph (Y + c P_L)
+};
+
+struct ChebTerm {
+  int kind;
+  const double* a_re;  // A operand planes: P_l (state-major)
+  const double* a_im;
+  const double* b_re;  // B operand planes: rescaled H (row-major)
+  const double* b_im;
+  const double* p_re;  // previous term P_{l-1} (X for the first product)
+  const double* p_im;
+  double* y_re;        // Chebyshev sum
+  double* y_im;
+  double* o_re;        // output term or new X
+  double* o_im;
+  double c0r, c0i, cr, ci;  // coefficients (c0 only for the first product)
+  double phr, phi;          // exp(-i beta h)
+};
+
+// Launch one Chebyshev product over rows [0, mrows) of the state-major
+// operands (mrows, np multiples of the tile size chosen by the launcher).
+hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s);
+
+// C = alpha * (A op(B)^T) + beta * C with conjugation flags; planar fp64.
+hipError_t launch_zgemm_nt_f64(const double* ar, const double* ai, bool conj_a, const double* br,
+                               const double* bi, bool conj_b, double* cr, double* ci, int mrows,
+                               int ncols, int kdim, int ld, double alr, double ali, double ber,
+                               double bei, hipStream_t s);
+
+// max |(A^H A - 1)_ij| (bit pattern, atomic max) and sum |.|^2 over an
+// n x n Gram matrix of the first n state rows. out[0] = max (as double bits),
+// out[1] = sum of squares; caller zeroes out first.
+hipError_t launch_unitarity_f64(const double* xr, const double* xi, int n, int np,
+                                double* out, hipStream_t s);
+
+// Complex128 interleaved (rows x cols, row stride ld_src) -> planar planes (row stride ld).
+hipError_t launch_pack_planar(const void* src, long rows, long cols, long ld_src, double* re,
+                              double* im, long ld, hipStream_t s);
+// Transposing pack: planes(j, i) = src(i, j) for i < rows, j < cols (src row stride ld_src);
+// planes(j, i) = 0 elsewhere in [0, mrows) x [0, ld).
+hipError_t launch_pack_planar_t(const void* src, long rows, long cols, long ld_src, double* re,
+                                double* im, long ld, long mrows, hipStream_t s);
+// Transposing unpack: dst(i, j) = planes(j, i) for i < rows, j < cols (dst row stride ld_dst).
+hipError_t launch_unpack_planar_t(const double* re, const double* im, long ld, long rows,
+                                  long cols, void* dst, long ld_dst, hipStream_t s);
+// Rows [0, m) x [0, ld) of the state-major planes set to the n x n identity (zero padding).
+hipError_t launch_identity_rows(double* re, double* im, long n, long m, long ld, hipStream_t s);
+// Rescaled Hamiltonian Ht = (H0 + a V + b K - beta 1) / dE on the n x n block.
+hipError_t launch_heff_f64(const double* h0r, const double* h0i, const double* vr,
+                           const double* vi, const double* kr, const double* ki, double a,
+                           double b, double beta, double dE, long n, long ld, double* hr,
+                           double* hi, hipStream_t s);
+// y = A x for a dense complex128 row-major matrix (n x n) and vectors x, y (complex128).
+hipError_t launch_zgemv(const void* A, long n, const void* x, void* y, hipStream_t s);
+
+// ---- tridiagonal kernels (kernels_tridiag.hip) --------------------------------------------
+struct TridiagJob {
+  long n;                // dimension
+  long ncols;            // states propagated (one workgroup per state)
+  const double* h0_diag; // device
+  const double* h0_off;  // device, complex128 interleaved (n-1)
+  const double* v_diag;  // device
+  const double* ab;      // device, 2*M: a_k, b_k interleaved, for the steps in use
+  const double* coef;    // device, 2*(L+1): c_l complex interleaved
+  int L;
+  int k0, k1;            // steps k0+1 .. k1
+  double beta, inv_dE, phr, phi;
+  const void* x0;        // device complex128 n x ncols row-major, or nullptr = identity
+  long ld_x0;
+  void* x_out;           // device complex128 n x ncols row-major
+  long ld_out;
+};
+// Returns hipErrorInvalidValue when n exceeds what one workgroup can hold.
+hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
+long tridiag_resident_max_n();
+
+}  // namespace fq
+
+// ---- the context ---------------------------------------------------------------------------
+struct fq_ctx {
+  // system
+  int64_t n = 0;
+  int layout = 0;
+  fq_system sys{};
+  // params
+  double T = 0, h = 0, tol = 0;
+  int M = 0, L = 0, precision = 0, ckpt = 0;
+  std::vector<double> f_nodes, a, b;  // host
+  double e_min = 0, e_max = 0, beta = 0, dE = 0, R = 0;
+  std::vector<double> weights;        // a_l = (2 - delta_l0) J_l(R), l = 0..L
+  std::vector<double> coef;           // c_l = (2 - delta_l0) (-i)^l J_l(R), interleaved
+  double phr = 1, phi = 0;            // exp(-i beta h)
+  // device
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  long np = 0;                        // padded dimension (dense)
+  // dense planes
+  double *h0r = nullptr, *h0i = nullptr, *vr = nullptr, *vi = nullptr, *kr = nullptr, *ki = nullptr;
+  double *htr = nullptr, *hti = nullptr;
+  double *xr = nullptr, *xi = nullptr, *yr = nullptr, *yi = nullptr;
+  double *par = nullptr, *pai = nullptr, *pbr = nullptr, *pbi = nullptr;
+  double* tape = nullptr;             // checkpoints, each 2 planes
+  int n_tape = 0;
+  double* small = nullptr;            // 64 doubles of reduction scratch
+  double* d_ab = nullptr;             // 2*M
+  double* d_coef = nullptr;           // 2*(L+1)
+  // state
+  bool tape_valid = false;
+  bool broken = false;
+  fq_report last{};
+};

@@ -1,0 +1,473 @@
+// Dense-operator kernels for gfx950: the Chebyshev products on FP64 matrix
+// cores with the recurrence, the Bessel-weighted accumulation and the step
+// phase fused into the epilogue, plus the O(N^2) helpers around them.
+//
+// Complex products use four real MFMA products per operand pair on planar
+// (real / imaginary) operands. Every product has the form
+//     C(m, n) = sum_k A(m, k) B(n, k)
+// with both operands contiguous along k ("NT"), which is what the state-major
+// storage of the propagated block gives: A = P_l^T (row j = state j) and
+// B = the rescaled Hamiltonian (row i = basis index i).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace fq {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  // D(16x16) += A(16x4) B(4x16); lane l supplies A(l%16, kq(l)) and
+  // B(kq(l), l%16) with kq(l) = l/16, and holds D(4*r + l/16, l%16), r = 0..3
+  // (layout measured with one-hot operands on gfx950).
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct Operands {
+  const double* ar;
+  const double* ai;
+  const double* br;
+  const double* bi;
+  int ld;      // row stride of A and B (elements)
+  int kdim;    // reduction length, multiple of BK
+  int tiles_n; // tiles along n
+  int tiles_m;
+};
+
+// ---------------------------------------------------------------------------------------
+// Main loop: one workgroup computes a BM x BN complex tile with WGM x WGN waves.
+// K is consumed in BK-wide stages staged through LDS; the next stage's global
+// loads are issued before the current stage's MFMAs (register prefetch).
+// Within a stage, lane l reads the k pair (8p + 2(l/16), +1) of its row with one
+// 16-byte LDS read and feeds two MFMA k-steps; A and B use the same k order, so
+// the sum over k is unchanged.
+// ---------------------------------------------------------------------------------------
+template <int BM, int BN, int BK, int WGM, int WGN, bool CONJ_A, bool CONJ_B, class Epi>
+__global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op, Epi epi) {
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int S = BK + 2;  // LDS row stride (doubles): conflict-free 16-byte reads
+  constexpr int CPR = BK / 2;  // 16-byte chunks per row
+  constexpr int RA = BM * CPR / NT, RB = BN * CPR / NT;
+  static_assert(BM * CPR % NT == 0 && BN * CPR % NT == 0, "load split");
+  static_assert(BK % 8 == 0, "BK");
+
+  __shared__ __attribute__((aligned(16))) double As[2][BM * S];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BN * S];
+
+  // Tile order: consecutive workgroup ids land on different XCDs (round-robin
+  // dispatch), so spread the id space so that each XCD sweeps a compact band
+  // of output tiles that share A rows.
+  const int nblk = op.tiles_m * op.tiles_n;
+  int bid = blockIdx.x;
+  if (nblk % 8 == 0) bid = (bid % 8) * (nblk / 8) + bid / 8;
+  const int tm = bid / op.tiles_n, tn = bid % op.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / WGN, wn = wid % WGN;
+  const long ld = op.ld;
+
+  d4 accR[FM][FN], accI[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      accR[i][j] = d4{0, 0, 0, 0};
+      accI[i][j] = d4{0, 0, 0, 0};
+    }
+
+  d2 ga[2][RA], gb[2][RB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int c = tid + r * NT, row = c / CPR, col = 2 * (c % CPR);
+      const long off = (long)(m0 + row) * ld + k0 + col;
+      ga[0][r] = *reinterpret_cast<const d2*>(op.ar + off);
+      ga[1][r] = *reinterpret_cast<const d2*>(op.ai + off);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int c = tid + r * NT, row = c / CPR, col = 2 * (c % CPR);
+      const long off = (long)(n0 + row) * ld + k0 + col;
+      gb[0][r] = *reinterpret_cast<const d2*>(op.br + off);
+      gb[1][r] = *reinterpret_cast<const d2*>(op.bi + off);
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int c = tid + r * NT, row = c / CPR, col = 2 * (c % CPR);
+      *reinterpret_cast<d2*>(&As[0][row * S + col]) = ga[0][r];
+      *reinterpret_cast<d2*>(&As[1][row * S + col]) = CONJ_A ? -ga[1][r] : ga[1][r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int c = tid + r * NT, row = c / CPR, col = 2 * (c % CPR);
+      *reinterpret_cast<d2*>(&Bs[0][row * S + col]) = gb[0][r];
+      *reinterpret_cast<d2*>(&Bs[1][row * S + col]) = CONJ_B ? -gb[1][r] : gb[1][r];
+    }
+  };
+
+  gload(0);
+  for (int k0 = 0; k0 < op.kdim; k0 += BK) {
+    __syncthreads();
+    lstore();
+    __syncthreads();
+    if (k0 + BK < op.kdim) gload(k0 + BK);
+    const int rr = lane & 15;
+#pragma unroll
+    for (int p = 0; p < BK / 8; ++p) {
+      const int kk = 8 * p + 2 * (lane >> 4);
+      d2 far_[FM], fai[FM], fbr[FN], fbi[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int row = wm * WTM + i * 16 + rr;
+        far_[i] = *reinterpret_cast<const d2*>(&As[0][row * S + kk]);
+        fai[i] = *reinterpret_cast<const d2*>(&As[1][row * S + kk]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int row = wn * WTN + j * 16 + rr;
+        fbr[j] = *reinterpret_cast<const d2*>(&Bs[0][row * S + kk]);
+        fbi[j] = *reinterpret_cast<const d2*>(&Bs[1][row * S + kk]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accR[i][j] = mfma_f64(far_[i][t], fbr[j][t], accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accI[i][j] = mfma_f64(far_[i][t], fbi[j][t], accI[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accR[i][j] = mfma_f64(-fai[i][t], fbi[j][t], accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accI[i][j] = mfma_f64(fai[i][t], fbr[j][t], accI[i][j]);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * WTM + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+        epi(m, n, accR[i][j][r], accI[i][j][r]);
+      }
+  epi.finish();
+}
+
+// ---- epilogues ------------------------------------------------------------------------------
+
+template <int KIND>
+struct EpiCheb {
+  ChebTerm t;
+  long ld;
+  __device__ __forceinline__ void operator()(int m, int n, double ar, double ai) const {
+    const long idx = (long)m * ld + n;
+    if (KIND == CHEB_FIRST) {
+      const double xr = t.p_re[idx], xi = t.p_im[idx];
+      t.o_re[idx] = ar;
+      t.o_im[idx] = ai;
+      t.y_re[idx] = t.c0r * xr - t.c0i * xi + t.cr * ar - t.ci * ai;
+      t.y_im[idx] = t.c0r * xi + t.c0i * xr + t.cr * ai + t.ci * ar;
+    } else if (KIND == CHEB_FIRST_LAST) {
+      const double xr = t.p_re[idx], xi = t.p_im[idx];
+      const double sr = t.c0r * xr - t.c0i * xi + t.cr * ar - t.ci * ai;
+      const double si = t.c0r * xi + t.c0i * xr + t.cr * ai + t.ci * ar;
+      t.o_re[idx] = t.phr * sr - t.phi * si;
+      t.o_im[idx] = t.phr * si + t.phi * sr;
+    } else if (KIND == CHEB_MID) {
+      const double pr = 2.0 * ar - t.p_re[idx], pi = 2.0 * ai - t.p_im[idx];
+      t.o_re[idx] = pr;
+      t.o_im[idx] = pi;
+      t.y_re[idx] += t.cr * pr - t.ci * pi;
+      t.y_im[idx] += t.cr * pi + t.ci * pr;
+    } else {  // CHEB_LAST
+      const double pr = 2.0 * ar - t.p_re[idx], pi = 2.0 * ai - t.p_im[idx];
+      const double sr = t.y_re[idx] + t.cr * pr - t.ci * pi;
+      const double si = t.y_im[idx] + t.cr * pi + t.ci * pr;
+      t.o_re[idx] = t.phr * sr - t.phi * si;
+      t.o_im[idx] = t.phr * si + t.phi * sr;
+    }
+  }
+  __device__ __forceinline__ void finish() const {}
+};
+
+struct EpiStore {
+  double* cr;
+  double* ci;
+  long ld;
+  double alr, ali, ber, bei;
+  __device__ __forceinline__ void operator()(int m, int n, double ar, double ai) const {
+    const long idx = (long)m * ld + n;
+    double r = alr * ar - ali * ai, i = alr * ai + ali * ar;
+    if (ber != 0.0 || bei != 0.0) {
+      const double xr = cr[idx], xi = ci[idx];
+      r += ber * xr - bei * xi;
+      i += ber * xi + bei * xr;
+    }
+    cr[idx] = r;
+    ci[idx] = i;
+  }
+  __device__ __forceinline__ void finish() const {}
+};
+
+struct EpiUnitarity {
+  int n;
+  double* out;
+  double mx = 0.0, ss = 0.0;
+  __device__ __forceinline__ void operator()(int m, int c, double ar, double ai) {
+    if (m < n && c < n) {
+      const double dr = ar - (m == c ? 1.0 : 0.0);
+      const double a2 = dr * dr + ai * ai;
+      mx = fmax(mx, a2);
+      ss += a2;
+    }
+  }
+  __device__ void finish() {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, o));
+      ss += __shfl_xor(ss, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(sqrt(mx)));
+      atomicAdd(out + 1, ss);
+    }
+  }
+};
+
+template <bool CONJ_A, bool CONJ_B, class Epi>
+hipError_t launch_gemm(const Operands& op0, int mrows, int ncols, Epi epi, hipStream_t s) {
+  Operands op = op0;
+  if (mrows % 128 == 0 && ncols % 128 == 0 && (long)mrows * ncols >= 512L * 1024) {
+    op.tiles_m = mrows / 128;
+    op.tiles_n = ncols / 128;
+    hipLaunchKernelGGL((zgemm_nt_f64_kernel<128, 128, 16, 2, 4, CONJ_A, CONJ_B, Epi>),
+                       dim3(op.tiles_m * op.tiles_n), dim3(512), 0, s, op, epi);
+  } else if (mrows % 64 == 0 && ncols % 64 == 0) {
+    op.tiles_m = mrows / 64;
+    op.tiles_n = ncols / 64;
+    hipLaunchKernelGGL((zgemm_nt_f64_kernel<64, 64, 16, 2, 2, CONJ_A, CONJ_B, Epi>),
+                       dim3(op.tiles_m * op.tiles_n), dim3(256), 0, s, op, epi);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---- O(N^2) helpers ----------------------------------------------------------------------------
+
+__global__ void heff_kernel(const double* __restrict__ h0r, const double* __restrict__ h0i,
+                            const double* __restrict__ vr, const double* __restrict__ vi,
+                            const double* __restrict__ kr, const double* __restrict__ ki,
+                            double a, double b, double beta, double inv_dE, long n, long ld,
+                            double* __restrict__ hr, double* __restrict__ hi) {
+  const long total = n * ld;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long i = e / ld, k = e % ld;
+    if (k >= n) continue;
+    double re = h0r[e] + a * vr[e] + b * kr[e];
+    const double im = h0i[e] + a * vi[e] + b * ki[e];
+    if (i == k) re -= beta;
+    hr[e] = re * inv_dE;
+    hi[e] = im * inv_dE;
+  }
+}
+
+__global__ void pack_planar_kernel(const double2* __restrict__ src, long rows, long cols,
+                                   long ld_src, double* __restrict__ re, double* __restrict__ im,
+                                   long ld) {
+  const long total = rows * cols;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long i = e / cols, j = e % cols;
+    const double2 v = src[i * ld_src + j];
+    re[i * ld + j] = v.x;
+    im[i * ld + j] = v.y;
+  }
+}
+
+// 32 x 32 tiles through LDS: planes(j, i) = src(i, j), zero outside the source.
+__global__ void pack_planar_t_kernel(const double2* __restrict__ src, long rows, long cols,
+                                     long ld_src, double* __restrict__ re,
+                                     double* __restrict__ im, long ld) {
+  __shared__ double tr[32][33], ti[32][33];
+  const long i0 = blockIdx.x * 32L, j0 = blockIdx.y * 32L;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: ty 0..7
+  for (int r = ty; r < 32; r += 8) {
+    const long i = i0 + r, j = j0 + tx;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < rows && j < cols) v = src[i * ld_src + j];
+    tr[r][tx] = v.x;
+    ti[r][tx] = v.y;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const long j = j0 + r, i = i0 + tx;
+    if (i < ld) {
+      re[j * ld + i] = tr[tx][r];
+      im[j * ld + i] = ti[tx][r];
+    }
+  }
+}
+
+// dst(i, j) = planes(j, i).
+__global__ void unpack_planar_t_kernel(const double* __restrict__ re,
+                                       const double* __restrict__ im, long ld, long rows,
+                                       long cols, double2* __restrict__ dst, long ld_dst) {
+  __shared__ double tr[32][33], ti[32][33];
+  const long j0 = blockIdx.y * 32L, i0 = blockIdx.x * 32L;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const long j = j0 + r, i = i0 + tx;
+    if (j < cols && i < rows) {
+      tr[r][tx] = re[j * ld + i];
+      ti[r][tx] = im[j * ld + i];
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const long i = i0 + r, j = j0 + tx;
+    if (i < rows && j < cols) dst[i * ld_dst + j] = make_double2(tr[tx][r], ti[tx][r]);
+  }
+}
+
+__global__ void identity_rows_kernel(double* __restrict__ re, double* __restrict__ im, long n,
+                                     long m, long ld) {
+  const long total = m * ld;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long j = e / ld, i = e % ld;
+    re[e] = (i == j && j < n) ? 1.0 : 0.0;
+    im[e] = 0.0;
+  }
+}
+
+__global__ void zgemv_kernel(const double2* __restrict__ A, long n, const double2* __restrict__ x,
+                             double2* __restrict__ y) {
+  __shared__ double sr[256], si[256];
+  const long i = blockIdx.x;
+  double accr = 0.0, acci = 0.0;
+  for (long k = threadIdx.x; k < n; k += blockDim.x) {
+    const double2 a = A[i * n + k], v = x[k];
+    accr += a.x * v.x - a.y * v.y;
+    acci += a.x * v.y + a.y * v.x;
+  }
+  sr[threadIdx.x] = accr;
+  si[threadIdx.x] = acci;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      si[threadIdx.x] += si[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[i] = make_double2(sr[0], si[0]);
+}
+
+inline unsigned grid_for(long total, int block) {
+  long g = (total + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s) {
+  Operands op{t.a_re, t.a_im, t.b_re, t.b_im, np, np, 0, 0};
+  switch (t.kind) {
+    case CHEB_FIRST:
+      return launch_gemm<false, false>(op, mrows, np, EpiCheb<CHEB_FIRST>{t, np}, s);
+    case CHEB_FIRST_LAST:
+      return launch_gemm<false, false>(op, mrows, np, EpiCheb<CHEB_FIRST_LAST>{t, np}, s);
+    case CHEB_MID:
+      return launch_gemm<false, false>(op, mrows, np, EpiCheb<CHEB_MID>{t, np}, s);
+    case CHEB_LAST:
+      return launch_gemm<false, false>(op, mrows, np, EpiCheb<CHEB_LAST>{t, np}, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_zgemm_nt_f64(const double* ar, const double* ai, bool conj_a, const double* br,
+                               const double* bi, bool conj_b, double* cr, double* ci, int mrows,
+                               int ncols, int kdim, int ld, double alr, double ali, double ber,
+                               double bei, hipStream_t s) {
+  Operands op{ar, ai, br, bi, ld, kdim, 0, 0};
+  EpiStore e{cr, ci, ld, alr, ali, ber, bei};
+  if (conj_a && conj_b) return launch_gemm<true, true>(op, mrows, ncols, e, s);
+  if (conj_a) return launch_gemm<true, false>(op, mrows, ncols, e, s);
+  if (conj_b) return launch_gemm<false, true>(op, mrows, ncols, e, s);
+  return launch_gemm<false, false>(op, mrows, ncols, e, s);
+}
+
+hipError_t launch_unitarity_f64(const double* xr, const double* xi, int n, int np, double* out,
+                                hipStream_t s) {
+  Operands op{xr, xi, xr, xi, np, np, 0, 0};
+  EpiUnitarity e{n, out};
+  return launch_gemm<true, false>(op, np, np, e, s);
+}
+
+hipError_t launch_pack_planar(const void* src, long rows, long cols, long ld_src, double* re,
+                              double* im, long ld, hipStream_t s) {
+  hipLaunchKernelGGL(pack_planar_kernel, dim3(grid_for(rows * cols, 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(src), rows, cols, ld_src, re, im, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_planar_t(const void* src, long rows, long cols, long ld_src, double* re,
+                                double* im, long ld, long mrows, hipStream_t s) {
+  if (mrows % 32 != 0 || ld % 32 != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(ld / 32), (unsigned)(mrows / 32));
+  hipLaunchKernelGGL(pack_planar_t_kernel, grid, dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(src), rows, cols, ld_src, re, im, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_planar_t(const double* re, const double* im, long ld, long rows,
+                                  long cols, void* dst, long ld_dst, hipStream_t s) {
+  dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32));
+  hipLaunchKernelGGL(unpack_planar_t_kernel, grid, dim3(256), 0, s, re, im, ld, rows, cols,
+                     reinterpret_cast<double2*>(dst), ld_dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_rows(double* re, double* im, long n, long m, long ld, hipStream_t s) {
+  hipLaunchKernelGGL(identity_rows_kernel, dim3(grid_for(m * ld, 256)), dim3(256), 0, s, re, im,
+                     n, m, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_heff_f64(const double* h0r, const double* h0i, const double* vr,
+                           const double* vi, const double* kr, const double* ki, double a,
+                           double b, double beta, double dE, long n, long ld, double* hr,
+                           double* hi, hipStream_t s) {
+  hipLaunchKernelGGL(heff_kernel, dim3(grid_for(n * ld, 256)), dim3(256), 0, s, h0r, h0i, vr, vi,
+                     kr, ki, a, b, beta, 1.0 / dE, n, ld, hr, hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemv(const void* A, long n, const void* x, void* y, hipStream_t s) {
+  hipLaunchKernelGGL(zgemv_kernel, dim3((unsigned)n), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(A), n, reinterpret_cast<const double2*>(x),
+                     reinterpret_cast<double2*>(y));
+  return hipGetLastError();
+}
+
+}  // namespace fq

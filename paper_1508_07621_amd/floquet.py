@@ -1,0 +1,237 @@
+"""Python binding of libfloquet: argument marshalling around the C ABI.
+
+PyTorch provides device memory (operators, outputs, the workspace) and the
+stream; every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import FqParams, FqReport, FqSystem, check, dptr, lib
+
+__all__ = ["node_times", "bessel_weights", "choose_order", "tridiag_extremes",
+           "FloquetContext", "floquet_build_UT", "floquet_propagate", "floquet_grad", "FloquetUT"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ---- host numerics exported by the library ---------------------------------------------------
+
+def node_times(T: float, M: int) -> np.ndarray:
+    """(M, 2) Gauss-Legendre sampling times of the drive (earlier node first)."""
+    out = np.empty(2 * M, dtype=np.float64)
+    check(lib().fq_node_times(float(T), int(M), dptr(out)))
+    return out.reshape(M, 2)
+
+
+def bessel_weights(R: float, L: int) -> np.ndarray:
+    """a_0 = J_0(R), a_l = 2 J_l(R) for l = 1..L."""
+    out = np.empty(L + 1, dtype=np.float64)
+    check(lib().fq_bessel_weights(float(R), int(L), dptr(out)))
+    return out
+
+
+def choose_order(R: float, tol: float) -> int:
+    import ctypes
+    L = ctypes.c_int32(0)
+    check(lib().fq_choose_order(float(R), float(tol), ctypes.byref(L)))
+    return int(L.value)
+
+
+def tridiag_extremes(d, e_abs):
+    import ctypes
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    e = np.ascontiguousarray(e_abs, dtype=np.float64)
+    if e.size == 0:
+        e = np.zeros(1)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    check(lib().fq_tridiag_extremes(len(d), dptr(d), dptr(e), ctypes.byref(lo), ctypes.byref(hi)))
+    return lo.value, hi.value
+
+
+# ---- context ---------------------------------------------------------------------------------
+
+def _device_tensor(x, dtype, device):
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a torch tensor or NumPy array")
+    return x.to(device=device, dtype=dtype).contiguous()
+
+
+class FloquetContext:
+    """One problem H(t) = H0 + f(t) Hmod on one GPU, set up once, built many times.
+
+    Dense operators: h0, hmod (n x n complex). Tridiagonal: h0_diag (n real),
+    h0_off (n-1 complex, H0[i][i+1]), hmod_diag (n real).
+    f_nodes: (M, 2) drive samples at node_times(T, M).
+    precision: "fp64", "fp32" or "bf16x3" (arithmetic of the Chebyshev products).
+    """
+
+    def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_diag=None,
+                 h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
+                 e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
+                 precision: str = "fp64", checkpoint_every: int = 0, device=None):
+        torch = _torch()
+        L_ = lib()
+        self.device = torch.device(device if device is not None else "cuda")
+        self._keep = []
+        sysd = FqSystem()
+        if h0 is not None:
+            h0t = _device_tensor(h0, torch.complex128, self.device)
+            vt = _device_tensor(hmod, torch.complex128, self.device)
+            self.n = int(h0t.shape[0])
+            if h0t.shape != (self.n, self.n) or vt.shape != (self.n, self.n):
+                raise ValueError("h0 and hmod must be square and of equal size")
+            sysd.n, sysd.layout = self.n, _abi.FQ_DENSE
+            sysd.h0, sysd.hmod = h0t.data_ptr(), vt.data_ptr()
+            self._keep += [h0t, vt]
+        else:
+            d = _device_tensor(h0_diag, torch.float64, self.device)
+            v = _device_tensor(hmod_diag, torch.float64, self.device)
+            self.n = int(d.shape[0])
+            off = _device_tensor(h0_off if h0_off is not None else np.zeros(max(self.n - 1, 0)),
+                                 torch.complex128, self.device)
+            if v.shape[0] != self.n or off.shape[0] != max(self.n - 1, 0):
+                raise ValueError("tridiagonal arrays have inconsistent sizes")
+            sysd.n, sysd.layout = self.n, _abi.FQ_TRIDIAG
+            sysd.h0_diag, sysd.hmod_diag = d.data_ptr(), v.data_ptr()
+            sysd.h0_off = off.data_ptr() if self.n > 1 else None
+            self._keep += [d, v, off]
+        self.layout = sysd.layout
+        self.M = int(M)
+        self.T = float(T)
+        self._f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))
+        if self._f.size != 2 * self.M:
+            raise ValueError("f_nodes must hold 2*M values")
+        par = FqParams()
+        par.T, par.M, par.L = self.T, self.M, int(L)
+        par.f_nodes = dptr(self._f)
+        par.e_min = math.nan if e_min is None else float(e_min)
+        par.e_max = math.nan if e_max is None else float(e_max)
+        par.tol = float(tol)
+        par.precision = _abi.PRECISIONS[precision]
+        par.checkpoint_every = int(checkpoint_every)
+        self.precision = precision
+        import ctypes
+        nbytes = ctypes.c_size_t(0)
+        check(L_.fq_workspace_bytes(ctypes.byref(sysd), ctypes.byref(par), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._stream = torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L_.fq_create(ctypes.byref(handle), ctypes.byref(sysd), ctypes.byref(par),
+                               self.workspace.data_ptr(), nbytes.value, self._stream.cuda_stream))
+        self._ctx = handle
+        self._sys, self._par = sysd, par
+
+    @property
+    def report(self) -> dict:
+        import ctypes
+        r = FqReport()
+        check(lib().fq_get_report(self._ctx, ctypes.byref(r)))
+        return r.as_dict()
+
+    def build_ut(self, out=None):
+        """U_T as an n x n complex128 tensor ([i, j] = <i|U_T|j>)."""
+        import ctypes
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.complex128, device=self.device)
+        r = FqReport()
+        with torch.cuda.device(self.device):
+            check(lib().floquet_build_UT(self._ctx, out.data_ptr(), ctypes.byref(r)))
+        self.last_report = r.as_dict()
+        return out
+
+    def propagate(self, X0, k0: int = 0, k1: Optional[int] = None, out=None):
+        """E_k1 ... E_{k0+1} X0 for an n x ncols complex block X0 (columns = states)."""
+        torch = _torch()
+        k1 = self.M if k1 is None else int(k1)
+        X0 = _device_tensor(X0, torch.complex128, self.device)
+        if X0.dim() != 2 or X0.shape[0] != self.n:
+            raise ValueError("X0 must be n x ncols")
+        if out is None:
+            out = torch.empty_like(X0)
+        with torch.cuda.device(self.device):
+            check(lib().floquet_propagate(self._ctx, X0.data_ptr(), int(X0.shape[1]), int(k0), k1,
+                                          out.data_ptr()))
+        return out
+
+    def grad(self, U_bar) -> np.ndarray:
+        """d loss / d f_nodes, shape (M, 2), for U_bar = dL/dRe U + i dL/dIm U."""
+        torch = _torch()
+        ub = _device_tensor(U_bar, torch.complex128, self.device)
+        g = np.empty(2 * self.M, dtype=np.float64)
+        with torch.cuda.device(self.device):
+            check(lib().floquet_grad(self._ctx, ub.data_ptr(), dptr(g)))
+        return g.reshape(self.M, 2)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().fq_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- one-shot wrappers with the entry points' names -----------------------------------------
+
+def floquet_build_UT(**kw):
+    """Build U_T in one call; returns (U_T tensor, report dict)."""
+    ctx = FloquetContext(**kw)
+    U = ctx.build_ut()
+    rep = ctx.last_report
+    ctx.close()
+    return U, rep
+
+
+def floquet_propagate(X0, k0=0, k1=None, **kw):
+    ctx = FloquetContext(**kw)
+    X = ctx.propagate(X0, k0, k1)
+    ctx.close()
+    return X
+
+
+def floquet_grad(U_bar, **kw):
+    ctx = FloquetContext(**kw)
+    ctx.build_ut()
+    g = ctx.grad(U_bar)
+    ctx.close()
+    return g
+
+
+class FloquetUT:
+    """torch.autograd.Function wrapper: forward builds U_T with a tape,
+    backward returns d loss / d f_nodes through floquet_grad."""
+
+    @staticmethod
+    def apply(f_nodes, **kw):
+        torch = _torch()
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx_, f):
+                c = FloquetContext(f_nodes=f.detach().cpu().numpy(), **kw)
+                ctx_.fq = c
+                return c.build_ut()
+
+            @staticmethod
+            def backward(ctx_, gU):
+                g = ctx_.fq.grad(gU)
+                ctx_.fq.close()
+                return torch.from_numpy(g).to(f_nodes.dtype).reshape(f_nodes.shape)
+
+        return _Fn.apply(f_nodes)

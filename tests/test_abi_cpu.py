@@ -1,0 +1,217 @@
+"""The C ABI on the CPU: the library loads, exports every declared entry point,
+its host FP64 numerics match independent references, and invalid arguments are
+rejected before any device work (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special
+
+import oracle as orc
+from paper_1508_07621_amd import _abi
+from paper_1508_07621_amd import floquet as fl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "floquet.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:fq|floquet)_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    declared = _declared_functions()
+    assert set(declared) == set(_abi.EXPORTS), (declared, _abi.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 5 * 8
+    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4
+    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 8 * 8
+
+
+def test_node_times_match_oracle():
+    for T, M in [(2 * math.pi, 100), (1.0, 1), (3.3, 17)]:
+        np.testing.assert_allclose(fl.node_times(T, M), orc.node_times(T, M), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("R", [0.0, 1e-8, 0.126, 0.251, 1.0, 10.0, 37.03, 500.0, 1762.0, 3441.0])
+def test_bessel_weights_match_scipy(R):
+    L = max(4, int(R * 1.1) + 40)
+    w = fl.bessel_weights(R, L)
+    ref = 2.0 * scipy.special.jv(np.arange(L + 1), R)
+    ref[0] *= 0.5
+    scale = np.max(np.abs(ref))
+    # SciPy's AMOS values carry ~1e-14 relative error at arguments in the thousands
+    assert np.max(np.abs(w - ref)) <= 2e-14 * max(1.0, R / 50.0) * scale
+
+
+@pytest.mark.parametrize("R", [0.126, 37.03, 500.0, 1762.0])
+def test_bessel_weights_match_mpmath(R):
+    mpmath = pytest.importorskip("mpmath")
+    w = fl.bessel_weights(R, int(R) + 40)
+    for l in sorted({0, 1, 2, int(R / 2), int(R), int(R) + 20}):
+        ref = float((1 if l == 0 else 2) * mpmath.besselj(l, R))
+        assert abs(w[l] - ref) <= 2e-16 * max(abs(ref), 1e-3), (l, w[l], ref)
+
+
+def test_bessel_weights_against_published_table():
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "bessel_table.txt"))
+    for n, x, ref in rows:
+        w = fl.bessel_weights(x, int(n))[int(n)] / (1.0 if n == 0 else 2.0)
+        assert abs(w - ref) <= 5e-10 * max(1.0, abs(ref)) + 1e-19
+
+
+@pytest.mark.parametrize("R", [0.05, 0.098, 0.126, 0.251, 1.0, 37.03, 1762.0])
+def test_choose_order_matches_oracle(R):
+    for tol in (1e-8, 1e-12, 1e-14):
+        assert fl.choose_order(R, tol) == orc.choose_L(R, tol)
+
+
+def test_tridiag_extremes_match_lapack():
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 3, 50, 1000):
+        d = rng.standard_normal(n) * 10
+        e = np.abs(rng.standard_normal(max(n - 1, 0)))
+        lo, hi = fl.tridiag_extremes(d, e)
+        if n == 1:
+            ref = np.array([d[0]])
+        else:
+            ref = scipy.linalg.eigvalsh_tridiagonal(d, e)
+        assert abs(lo - ref[0]) <= 1e-13 * max(1, abs(ref[0]))
+        assert abs(hi - ref[-1]) <= 1e-13 * max(1, abs(ref[-1]))
+
+
+def test_tridiag_extremes_dimer_spectrum():
+    """Spin-S matrix -2 J S_x has the exact spectrum {-2 J m}: extremes -/+ J Nb."""
+    from workloads import dimer_tridiag
+    nb = 999
+    d, e, _ = dimer_tridiag(nb, 1.0, 0.0)
+    lo, hi = fl.tridiag_extremes(d, np.abs(e))
+    assert abs(lo + nb) < 1e-10 and abs(hi - nb) < 1e-10
+
+
+# ---- argument validation: every path below returns before any HIP call --------------------
+
+FAKE = 0x1000  # non-null placeholder; validation never dereferences device pointers
+
+
+def _dense(n=8):
+    s = _abi.FqSystem()
+    s.n, s.layout, s.h0, s.hmod = n, _abi.FQ_DENSE, FAKE, FAKE
+    return s
+
+
+def _tridiag(n=8):
+    s = _abi.FqSystem()
+    s.n, s.layout, s.h0_diag, s.h0_off, s.hmod_diag = n, _abi.FQ_TRIDIAG, FAKE, FAKE, FAKE
+    return s
+
+
+def _params(M=4, f=None, **kw):
+    p = _abi.FqParams()
+    f = np.zeros(2 * M) if f is None else f
+    p.T, p.M, p.L, p.tol = 1.0, M, 0, 1e-12
+    p.f_nodes = _abi.dptr(f)
+    p.e_min = p.e_max = math.nan
+    p.precision, p.checkpoint_every = 0, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    p._keep = f
+    return p
+
+
+def _ws(sysd, par):
+    n = ctypes.c_size_t(0)
+    st = _abi.lib().fq_workspace_bytes(ctypes.byref(sysd), ctypes.byref(par), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_bytes_ok_and_grows_with_n():
+    st1, b1 = _ws(_dense(100), _params())
+    st2, b2 = _ws(_dense(1000), _params())
+    st3, b3 = _ws(_dense(1000), _params(checkpoint_every=2))
+    assert st1 == st2 == st3 == _abi.FQ_OK
+    assert 0 < b1 < b2 < b3
+    st, b = _ws(_tridiag(1000), _params())
+    assert st == _abi.FQ_OK and b > 0
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda s, p: setattr(s, "n", 0), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(s, "layout", 7), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(s, "reserved0", 1), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(s, "h0", None), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "T", -1.0), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "T", math.inf), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "M", 0), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "L", -1), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "L", 10 ** 6), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "tol", 0.0), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "e_min", 0.0), _abi.FQ_ERR_ARG),
+    (lambda s, p: (setattr(p, "e_min", 1.0), setattr(p, "e_max", 1.0)), _abi.FQ_ERR_SPECTRUM),
+    (lambda s, p: (setattr(p, "e_min", -math.inf), setattr(p, "e_max", 1.0)), _abi.FQ_ERR_NONFINITE),
+    (lambda s, p: setattr(p, "precision", 9), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "checkpoint_every", -2), _abi.FQ_ERR_ARG),
+])
+def test_invalid_arguments_rejected(mutate, status):
+    s, p = _dense(), _params()
+    mutate(s, p)
+    st, _ = _ws(s, p)
+    assert st == status
+    assert _abi.lib().fq_last_error().decode() != ""
+
+
+def test_nonfinite_drive_rejected():
+    f = np.zeros(8)
+    f[5] = math.nan
+    st, _ = _ws(_dense(), _params(M=4, f=f))
+    assert st == _abi.FQ_ERR_NONFINITE
+    assert "f_nodes[5]" in _abi.lib().fq_last_error().decode()
+
+
+def test_tridiag_restrictions():
+    st, _ = _ws(_tridiag(), _params(precision=1))
+    assert st == _abi.FQ_ERR_UNSUPPORTED
+
+
+def test_create_rejects_before_device_work():
+    L = _abi.lib()
+    s, p = _dense(), _params()
+    h = ctypes.c_void_p()
+    assert L.fq_create(ctypes.byref(h), ctypes.byref(s), ctypes.byref(p), None, 0, None) == _abi.FQ_ERR_ARG
+    assert L.fq_create(ctypes.byref(h), ctypes.byref(s), ctypes.byref(p), 0x1001, 1 << 40, None) == _abi.FQ_ERR_ARG
+    assert L.fq_create(ctypes.byref(h), ctypes.byref(s), ctypes.byref(p), 0x1000, 16, None) == _abi.FQ_ERR_ARG
+    assert "too small" in L.fq_last_error().decode()
+    assert L.fq_create(None, ctypes.byref(s), ctypes.byref(p), 0x1000, 16, None) == _abi.FQ_ERR_ARG
+
+
+def test_null_context_calls_rejected():
+    L = _abi.lib()
+    g = np.zeros(8)
+    assert L.floquet_build_UT(None, FAKE, None) == _abi.FQ_ERR_ARG
+    assert L.floquet_propagate(None, FAKE, 1, 0, 1, FAKE) == _abi.FQ_ERR_ARG
+    assert L.floquet_grad(None, FAKE, _abi.dptr(g)) == _abi.FQ_ERR_ARG
+    assert L.fq_node_times(1.0, 0, _abi.dptr(g)) == _abi.FQ_ERR_ARG
+    assert L.fq_bessel_weights(-1.0, 3, _abi.dptr(g)) == _abi.FQ_ERR_ARG
+    with pytest.raises(_abi.FloquetError):
+        fl.choose_order(1.0, -1.0)
+
+
+def test_torch_complex_gradient_convention():
+    """The backward hands floquet_grad dL/dRe U + i dL/dIm U: check that this is
+    what torch supplies as the gradient of a complex tensor for a real loss."""
+    torch = pytest.importorskip("torch")
+    z = torch.tensor([1.0 + 2.0j, -0.5 + 0.25j], dtype=torch.complex128, requires_grad=True)
+    loss = (z.real ** 3 + 2 * z.imag).sum()
+    loss.backward()
+    expect = 3 * z.detach().real ** 2 + 2j
+    assert torch.allclose(z.grad, expect)

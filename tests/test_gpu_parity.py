@@ -1,0 +1,268 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every comparison runs the library and the oracle on the same seeded inputs with
+the same spectral interval and Chebyshev order, so their difference is pure
+rounding; the bar for the FP64 path is 1e-10 in the worst column 2-norm.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as orc
+from workloads import dimer_tridiag, drive_cos, gue, haar_unitary, workload
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2.0 * math.pi
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def fl(require_gpu):
+    from paper_1508_07621_amd import floquet
+    floquet.node_times(1.0, 1)          # loads the library or raises
+    return floquet
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _cos_nodes(fl, T, M, eps0=0.0, eps1=1.0):
+    return drive_cos(fl.node_times(T, M), eps0, eps1, 1.0)
+
+
+def _dense_case(n, seed):
+    rng = np.random.default_rng(seed)
+    return gue(n, rng), gue(n, rng)
+
+
+def _oracle_interval(H0, V, f, T, M, tol=1e-12):
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.weyl_cover(H0, V, orc.commutator(H0, V), a, b)
+    _, _, R = orc.rescale(lo, hi, T / M)
+    return lo, hi, orc.choose_L(R, tol)
+
+
+# ---- dense FP64 ----------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,M,seed", [(64, 100, 1508), (100, 12, 2), (200, 6, 3), (1030, 2, 4)])
+def test_dense_fp64_matches_oracle(fl, n, M, seed):
+    _say("dense fp64", n, M, seed)
+    H0, V = _dense_case(n, seed)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L)
+    U = ctx.build_ut().cpu().numpy()
+    rep = ctx.last_report
+    Uref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+    err = orc.column_error(U, Uref)
+    _say("e_col", err, "L", rep["L"], "unitarity", rep["unitarity_max"])
+    assert rep["L"] == L
+    assert err < FP64_TOL
+    mx, fro = orc.unitarity_error(U)
+    assert abs(rep["unitarity_max"] - mx) < 1e-13 + 1e-6 * mx
+    assert abs(rep["unitarity_fro"] - fro) < 1e-13 + 1e-6 * fro
+
+
+def test_dense_library_cover_contains_every_step(fl):
+    n, M = 96, 40
+    _say("dense cover", n, M)
+    H0, V = _dense_case(n, 11)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M, 0.3, 1.2)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, tol=1e-12)
+    rep = ctx.report
+    a, b = orc.magnus4_weights(f, T / M)
+    K = orc.commutator(H0, V)
+    for k in range(M):
+        ev = np.linalg.eigvalsh(H0 + a[k] * V + b[k] * K)
+        assert rep["e_min"] <= ev[0] and ev[-1] <= rep["e_max"]
+    U = ctx.build_ut().cpu().numpy()
+    Ue = orc.build_ut(H0, V, f, T, M, route="exact")
+    assert orc.column_error(U, Ue) < M * 1e-12 + 1e-10
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_dense_low_orders(fl, L):
+    """L = 1 and L = 2 take the special buffer paths of the step."""
+    n, M = 64, 5
+    _say("dense low order", L)
+    H0, V = _dense_case(n, 21)
+    T = 0.05
+    f = _cos_nodes(fl, T, M)
+    lo, hi, _ = _oracle_interval(H0, V, f, T, M)
+    U = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L).build_ut()
+    Uref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+    assert orc.column_error(U.cpu().numpy(), Uref) < 1e-12
+
+
+def test_dense_static_closed_form(fl):
+    n, M, c = 256, 16, 0.7
+    _say("dense static", n)
+    H0, V = _dense_case(n, 5)
+    T = 1.3
+    f = np.full((M, 2), c)
+    U = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, tol=1e-13).build_ut().cpu().numpy()
+    ref = scipy.linalg.expm(-1j * T * (H0 + c * V))
+    assert orc.column_error(U, ref) < 1e-10
+
+
+def test_dense_propagate_ranges_and_columns(fl):
+    n, M = 150, 10
+    _say("dense propagate", n, M)
+    H0, V = _dense_case(n, 6)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L)
+    X0 = haar_unitary(n, np.random.default_rng(9))[:, :7]
+    X = ctx.propagate(X0, 3, 8).cpu().numpy()
+    Xref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0, k_range=(3, 8))
+    assert orc.column_error(X, Xref) < FP64_TOL
+    # empty step range is the identity map
+    X = ctx.propagate(X0, 4, 4).cpu().numpy()
+    assert np.max(np.abs(X - X0)) == 0.0
+    # column subset of the full build equals propagating those columns
+    U = ctx.build_ut().cpu().numpy()
+    E = np.eye(n, dtype=complex)[:, [0, 77, 149]]
+    Xc = ctx.propagate(E).cpu().numpy()
+    assert np.max(np.abs(Xc - U[:, [0, 77, 149]])) < 1e-13
+
+
+def test_dense_rejects_too_narrow_interval(fl):
+    from paper_1508_07621_amd._abi import FQ_ERR_SPECTRUM, FloquetError
+    H0, V = _dense_case(64, 7)
+    f = _cos_nodes(fl, TWO_PI, 10)
+    with pytest.raises(FloquetError) as ei:
+        fl.FloquetContext(h0=H0, hmod=V, T=TWO_PI, M=10, f_nodes=f, e_min=-1.0, e_max=1.0)
+    assert ei.value.status == FQ_ERR_SPECTRUM
+
+
+def test_dense_full_size_sampled_columns(fl):
+    """The 4096-state random-matrix model in the benchmark's launch shape
+    (few steps so that the oracle can follow three columns)."""
+    wl = workload("gue4096")
+    H0, V = wl.arrays["h0"], wl.arrays["v"]
+    M = 4
+    T = wl.T
+    _say("dense full size", wl.n, M)
+    f = _cos_nodes(fl, T, M)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = -4.2, 4.2
+    _, _, R = orc.rescale(lo, hi, T / M)
+    L = orc.choose_L(R, 1e-12)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L)
+    U = ctx.build_ut()
+    rep = ctx.last_report
+    cols = [0, 1234, 4095]
+    Uc = U[:, cols].cpu().numpy()
+    X0 = np.eye(wl.n, dtype=complex)[:, cols]
+    Xref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0)
+    err = orc.column_error(Uc, Xref)
+    _say("e_col", err, "unitarity", rep["unitarity_max"], "ms", rep["ms_build"])
+    assert err < FP64_TOL
+    assert rep["unitarity_max"] < 1e-11
+
+
+# ---- tridiagonal (dimer) FP64 ---------------------------------------------------------------------
+
+def _dimer_ctx(fl, nb, U_int, M, eps0=0.5, eps1=1.5, L=None, tol=1e-12):
+    d, e, v = dimer_tridiag(nb, 1.0, U_int)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M, eps0, eps1)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    if hi - lo < 1e-12 * max(1.0, abs(lo)):      # constant H (one level): any width is exact
+        lo, hi = lo - 1e-8, hi + 1e-8
+    _, _, R = orc.rescale(lo, hi, T / M)
+    L = orc.choose_L(R, tol) if L is None else L
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f,
+                            e_min=lo, e_max=hi, L=L)
+    return ctx, (d, e, v, f, T, lo, hi, L)
+
+
+@pytest.mark.parametrize("nb,U_int,M", [(0, 0.01, 10), (1, 0.0, 40), (9, 0.01, 50),
+                                         (128, 0.01, 20), (200, 0.3, 20), (520, 0.01, 10),
+                                         (1499, 0.01, 4)])
+def test_tridiag_matches_oracle(fl, nb, U_int, M):
+    _say("tridiag", nb, U_int, M)
+    ctx, (d, e, v, f, T, lo, hi, L) = _dimer_ctx(fl, nb, U_int, M)
+    U = ctx.build_ut().cpu().numpy()
+    n = nb + 1
+    cols = sorted({0, n // 3, n - 1})
+    X0 = np.eye(n, dtype=complex)[:, cols]
+    Xref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0)
+    err = orc.column_error(U[:, cols], Xref)
+    _say("e_col", err, "L", L)
+    assert err < FP64_TOL
+    assert ctx.last_report["unitarity_max"] < 1e-11
+
+
+def test_tridiag_library_cover_is_exact(fl):
+    d, e, v = dimer_tridiag(300, 1.0, 0.01)
+    M = 25
+    f = _cos_nodes(fl, TWO_PI, M, 0.5, 1.5)
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=TWO_PI, M=M, f_nodes=f)
+    rep = ctx.report
+    lo, hi = orc.tridiag_cover(d, e, v, *orc.magnus4_weights(f, TWO_PI / M))
+    assert abs(rep["e_min"] - lo) < 1e-9 * abs(lo) + 1e-9
+    assert abs(rep["e_max"] - hi) < 1e-9 * abs(hi) + 1e-9
+
+
+def test_tridiag_dimer1000_full_config(fl):
+    """Dimer with 999 bosons, M = 500: sampled columns against the oracle and
+    the time-reversal symmetry U = U^T of the whole matrix."""
+    wl = workload("dimer1000")
+    d, e, v = wl.arrays["h0_diag"], wl.arrays["h0_off"], wl.arrays["v_diag"]
+    M, T = wl.M, wl.T
+    _say("tridiag dimer1000", wl.n, M)
+    f = drive_cos(fl.node_times(T, M), 0.5, 1.5, 1.0)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    _, _, R = orc.rescale(lo, hi, T / M)
+    L = orc.choose_L(R, 1e-12)
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f,
+                            e_min=lo, e_max=hi, L=L)
+    U = ctx.build_ut().cpu().numpy()
+    rep = ctx.last_report
+    cols = [0, 499, 999]
+    X0 = np.eye(wl.n, dtype=complex)[:, cols]
+    Xref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0)
+    err = orc.column_error(U[:, cols], Xref)
+    _say("e_col", err, "L", L, "R", R, "unitarity", rep["unitarity_max"], "ms", rep["ms_build"])
+    assert L == rep["L"]
+    assert err < FP64_TOL
+    assert np.max(np.abs(U - U.T)) < 1e-10
+    assert rep["unitarity_max"] < 1e-10
+
+
+def test_tridiag_propagate(fl):
+    ctx, (d, e, v, f, T, lo, hi, L) = _dimer_ctx(fl, 150, 0.05, 12)
+    n = 151
+    X0 = haar_unitary(n, np.random.default_rng(4))[:, :5]
+    X = ctx.propagate(X0, 2, 9).cpu().numpy()
+    Xref = orc.build_ut_tridiag(d, e, v, f, T, 12, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0,
+                                k_range=(2, 9))
+    assert orc.column_error(X, Xref) < FP64_TOL
+
+
+def test_tridiag_complex_offdiagonal(fl):
+    """A general Hermitian tridiagonal H0 (complex couplings) with a diagonal Hmod."""
+    rng = np.random.default_rng(12)
+    n, M = 300, 8
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(n - 1) + 1j * rng.standard_normal(n - 1)
+    v = rng.standard_normal(n)
+    T = 2.0
+    f = _cos_nodes(fl, T, M, 0.2, 0.9)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    _, _, R = orc.rescale(lo, hi, T / M)
+    L = orc.choose_L(R, 1e-12)
+    U = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f,
+                          e_min=lo, e_max=hi, L=L).build_ut().cpu().numpy()
+    Uref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+    assert orc.column_error(U, Uref) < FP64_TOL

@@ -198,6 +198,18 @@ def test_ordering_later_steps_on_the_left():
     assert orc.column_error(U, E1 @ E2) > 1e-3
 
 
+def test_step_ranges_compose():
+    """E_M..E_{k+1} (E_k..E_1 X) = E_M..E_1 X: resuming from any step."""
+    H0, V = _rm(7, 14)
+    T, M = TWO_PI, 12
+    f = _nodes_cos(T, M)
+    X0 = haar_unitary(7, np.random.default_rng(3))[:, :3]
+    full = orc.build_ut(H0, V, f, T, M, route="exact", X0=X0)
+    mid = orc.build_ut(H0, V, f, T, M, route="exact", X0=X0, k_range=(0, 5))
+    rest = orc.build_ut(H0, V, f, T, M, route="exact", X0=mid, k_range=(5, 12))
+    assert orc.column_error(rest, full) < 1e-13
+
+
 def test_unitarity_of_chebyshev_route():
     H0, V = _rm(16, 5)
     T, M = TWO_PI, 50
