@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Seconds per Floquet-operator build on one MI355X, with the dominant kernel's
+roofline fraction and the FP64 CPU oracle timed beside it.
+
+A "step" is one complete build of U_T from the identity over one period: every
+per-step Hamiltonian, every Chebyshev product, the phase hand-off, the chain of
+M steps, and the FP64 unitarity check of the result. Inputs (operators, drive
+samples) are resident in HBM before the timed region; setup (commutator,
+spectral interval, coefficients) is done once before it.
+
+    python bench.py [--steps K] [--warmup W] [--workload gue4096|dimer1000|gue64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X datasheet peaks used for the roofline fractions.
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+#: algorithmic real flops per element and Chebyshev term of the tridiagonal
+#: pass: two complex-by-complex couplings (6 each), a real diagonal (2), two
+#: complex adds (4), 2 t - P_{l-1} (4) and the Bessel-weighted accumulation (4).
+TRIDIAG_FLOPS_PER_ELEMENT_TERM = 26
+
+WORKLOAD_TEXT = {
+    "gue4096": "random-matrix model N=4096 (GUE H0, V), f=cos t, T=2pi, M=200 Magnus-4 steps, "
+               "Chebyshev order for 1e-12 per step",
+    "dimer1000": "Bose-Hubbard dimer, 999 bosons (N=1000, tridiagonal), J=1, U=0.01, "
+                 "eps=0.5+1.5cos t, T=2pi, M=500",
+    "gue64": "random-matrix model N=64 (GUE H0, V), f=cos t, T=2pi, M=100",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gue4096", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, f_nodes, target_s: float):
+    """The FP64 oracle on a bounded sample of the same workload, scaled to one
+    full build: columns are independent and every step costs the same, so the
+    cost is linear in both (the paper extrapolates in M the same way)."""
+    import numpy as np
+
+    import oracle as orc
+    t_cpu0 = time.time()
+    h = wl.T / wl.M
+    a, b = orc.magnus4_weights(f_nodes, h)
+    # Untimed setup, as on the GPU side: the fixed operators and the coefficients.
+    if wl.layout == "dense":
+        ncols = 64
+        H0, V = wl.arrays["h0"], wl.arrays["v"]
+        K = orc.commutator(H0, V)
+        lo, hi = -4.5, 4.5       # any cover of the spectrum; the cost does not depend on it
+        heff = lambda k: orc.magnus4_heff(H0, V, K, a[k], b[k])  # noqa: E731
+    else:
+        ncols = 8
+        d, e, v = wl.arrays["h0_diag"], wl.arrays["h0_off"], wl.arrays["v_diag"]
+        H0, V, K = orc.tridiag_matrices(d, e, v)
+        lo, hi = orc.tridiag_cover(d, e, v, a, b)
+        heff = lambda k: (H0 + a[k] * V + b[k] * K).tocsr()  # noqa: E731
+    beta, dE, R = orc.rescale(lo, hi, h)
+    coef = orc.bessel_coefficients(R, orc.choose_L(R, 1e-12))
+    X = np.eye(wl.n, dtype=np.complex128)[:, :ncols]
+    # Timed: per step, the operator build (independent of the number of columns)
+    # and the Chebyshev step on ncols columns (linear in the number of columns).
+    t_op = t_step = 0.0
+    steps = 0
+    while steps < wl.M and (steps < 1 or t_op + t_step < target_s):
+        t0 = time.perf_counter()
+        Hk = heff(steps)
+        t1 = time.perf_counter()
+        X = orc.chebyshev_step(Hk, beta, dE, h, coef, X)
+        t2 = time.perf_counter()
+        t_op += t1 - t0
+        t_step += t2 - t1
+        steps += 1
+    scaled = wl.M * (t_op / steps + (t_step / steps) * (wl.n / ncols))
+    dt = t_op + t_step
+    sample = (f"{steps} of {wl.M} steps on {ncols} of {wl.n} columns; per-step operator time "
+              f"x M plus per-step Chebyshev time x M x N/{ncols}")
+    cores = _blas_threads()
+    return {"value": scaled, "unit": "s/build", "cores": cores, "kind": "oracle",
+            "sample": sample, "sample_seconds": round(dt, 3),
+            "wall_seconds": round(time.time() - t_cpu0, 1)}
+
+
+def _log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _blas_threads() -> int:
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        n = [i.get("num_threads") for i in info if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); the column-sharded multi-GPU layout is a design note, "
+              "not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1508_07621_amd import floquet as fl
+    from workloads import drive_cos, workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    wl = workload(args.workload)
+    if args.workload == "dimer1000":
+        f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.5, 1.5, 1.0)
+    else:
+        f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.0, 1.0, 1.0)
+
+    t_setup = time.perf_counter()
+    if wl.layout == "dense":
+        kw = dict(h0=wl.arrays["h0"], hmod=wl.arrays["v"])
+    else:
+        kw = dict(h0_diag=wl.arrays["h0_diag"], h0_off=wl.arrays["h0_off"],
+                  hmod_diag=wl.arrays["v_diag"])
+    ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12,
+                            precision=args.precision, profile=True, device=dev, **kw)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    info = ctx.report
+    _log(f"setup {setup_s:.2f} s: L={info['L']} R={info['R']:.4f} "
+         f"interval=[{info['e_min']:.6g}, {info['e_max']:.6g}]")
+    U = torch.empty((wl.n, wl.n), dtype=torch.complex128, device=dev)
+
+    for i in range(args.warmup):
+        ctx.build_ut(out=U)
+        _log(f"warmup build {i + 1}/{args.warmup}: {ctx.last_report['ms_build']:.1f} ms")
+    torch.cuda.synchronize()
+    reports = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.build_ut(out=U)
+        reports.append(ctx.last_report)
+        _log(f"timed build {i + 1}/{args.steps}: {reports[-1]['ms_build']:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s_per_build = elapsed / args.steps
+
+    from paper_1508_07621_amd._abi import K_MID, K_TRIDIAG
+    n = wl.n
+    if wl.layout == "dense":
+        kind = K_MID
+        n_launch = sum(r["n_kernel"][kind] for r in reports)
+        ms_launch = sum(r["ms_kernel"][kind] for r in reports) / max(n_launch, 1)
+        flops = 8.0 * n ** 3                       # one complex N x N x N product
+        peak = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
+                "bf16x3": PEAK_BF16_MFMA_TFLOPS}[args.precision]
+        achieved = flops / (ms_launch * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "Chebyshev product (middle terms), zgemm_nt_f64_kernel<128,128,16,2,4>",
+                "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
+                "algorithmic_flops_per_launch": flops}
+        build_tflops = info["L"] * wl.M * flops / s_per_build / 1e12
+    else:
+        kind = K_TRIDIAG
+        n_launch = sum(r["n_kernel"][kind] for r in reports)
+        ms_launch = sum(r["ms_kernel"][kind] for r in reports) / max(n_launch, 1)
+        flops = float(TRIDIAG_FLOPS_PER_ELEMENT_TERM) * n * n * wl.M * info["L"]
+        achieved = flops / (ms_launch * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4),
+                "traffic": None, "kernel": "tridiag_resident_kernel<8> (whole chain per column)",
+                "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
+                "algorithmic_flops_per_launch": flops}
+        build_tflops = flops / s_per_build / 1e12
+
+    last = reports[-1]
+    out = {
+        "metric": "s per U_T build + TFLOP/s (% MFMA/HBM peak), mixed vs FP64 at stated error",
+        "value": round(s_per_build, 6),
+        "unit": "s/build",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * s_per_build, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "n": n,
+                   "M": wl.M, "L": info["L"], "R": round(info["R"], 6),
+                   "interval": [info["e_min"], info["e_max"]], "precision": args.precision,
+                   "parallelism": "1 GPU"},
+        "build_tflops_algorithmic": round(build_tflops, 3),
+        "errors": {"unitarity_max": last["unitarity_max"], "unitarity_fro": last["unitarity_fro"]},
+        "setup_s": round(setup_s, 3),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, f_nodes, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,7 +109,22 @@ typedef struct fq_params {
   int32_t checkpoint_every;  /* > 0: floquet_build_UT keeps X_0, X_s, X_2s, ...
                                 (s = checkpoint_every) for floquet_grad;
                                 0 = no tape */
+  int32_t profile;           /* 1: time every kernel launch of a build with HIP
+                                events on the library's stream and report the
+                                per-kind sums in fq_report; 0: off */
+  int32_t reserved1;         /* must be 0 */
 } fq_params;
+
+/* Kernel kinds timed in profile mode (indices of fq_report.ms_kernel). */
+enum {
+  FQ_K_FIRST = 0,       /* first Chebyshev product of a step (P_1 = Ht X) */
+  FQ_K_FIRST_LAST = 1,  /* the only product of a step when L == 1 */
+  FQ_K_MID = 2,         /* products P_{l+1} = 2 Ht P_l - P_{l-1}, 1 <= l < L-1 */
+  FQ_K_LAST = 3,        /* last product of a step, with the phase and hand-off */
+  FQ_K_HEFF = 4,        /* per-step rescaled Hamiltonian */
+  FQ_K_TRIDIAG = 5,     /* tridiagonal whole-chain kernel */
+  FQ_K_SLOTS = 8
+};
 
 /* Setup values and per-build measurements. */
 typedef struct fq_report {
@@ -120,6 +135,8 @@ typedef struct fq_report {
   double unitarity_max;      /* max |(U^dagger U - 1)_ij| of the last build (FP64) */
   double unitarity_fro;      /* Frobenius norm of U^dagger U - 1 */
   double ms_build;           /* device time of the last build, milliseconds */
+  double ms_kernel[FQ_K_SLOTS];   /* profile mode: summed event time per kind */
+  int32_t n_kernel[FQ_K_SLOTS];   /* profile mode: launches per kind */
 } fq_report;
 
 typedef struct fq_ctx fq_ctx;  /* opaque; host memory owned by the library */

@@ -17,6 +17,8 @@ STATUS_NAMES = {0: "FQ_OK", 1: "FQ_ERR_ARG", 2: "FQ_ERR_NONFINITE", 3: "FQ_ERR_S
                 4: "FQ_ERR_HIP", 5: "FQ_ERR_UNSUPPORTED", 6: "FQ_ERR_STATE"}
 FQ_DENSE, FQ_TRIDIAG = 0, 1
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+#: kernel kinds timed in profile mode (fq_report.ms_kernel indices)
+K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 8
 
 #: every entry point include/floquet.h declares
 EXPORTS = (
@@ -36,17 +38,23 @@ class FqParams(ctypes.Structure):
     _fields_ = [("T", c_double), ("M", c_int32), ("L", c_int32),
                 ("f_nodes", POINTER(c_double)),
                 ("e_min", c_double), ("e_max", c_double), ("tol", c_double),
-                ("precision", c_int32), ("checkpoint_every", c_int32)]
+                ("precision", c_int32), ("checkpoint_every", c_int32),
+                ("profile", c_int32), ("reserved1", c_int32)]
 
 
 class FqReport(ctypes.Structure):
     _fields_ = [("L", c_int32), ("M", c_int32), ("R", c_double), ("dE", c_double),
                 ("beta", c_double), ("e_min", c_double), ("e_max", c_double),
                 ("unitarity_max", c_double), ("unitarity_fro", c_double),
-                ("ms_build", c_double)]
+                ("ms_build", c_double), ("ms_kernel", c_double * K_SLOTS),
+                ("n_kernel", c_int32 * K_SLOTS)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name in ("ms_kernel", "n_kernel") else v
+        return out
 
 
 class FloquetError(RuntimeError):

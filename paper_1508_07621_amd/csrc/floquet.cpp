@@ -128,6 +128,8 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (par->precision < FQ_FP64 || par->precision > FQ_BF16X3)
     return fail(FQ_ERR_ARG, "unknown precision %d", par->precision);
   if (par->checkpoint_every < 0) return fail(FQ_ERR_ARG, "checkpoint_every must be >= 0");
+  if (par->profile != 0 && par->profile != 1) return fail(FQ_ERR_ARG, "profile must be 0 or 1");
+  if (par->reserved1 != 0) return fail(FQ_ERR_ARG, "reserved1 must be 0");
   if (sys->layout == FQ_TRIDIAG) {
     if (par->precision != FQ_FP64)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal layout runs in FP64 only");
@@ -304,9 +306,52 @@ fq_status tridiag_cover(fq_ctx* ctx, double* lo_out, double* hi_out) {
   return FQ_OK;
 }
 
+// ---- profile-mode event marks ----------------------------------------------------------------
+
+// Record the event that opens the next launch (kind >= 0) or closes the last (kind < 0).
+fq_status mark(fq_ctx* c, int kind) {
+  if (!c->profile) return FQ_OK;
+  if (c->n_events == c->events.size()) {
+    hipEvent_t e;
+    FQ_HIP(c, hipEventCreate(&e));
+    c->events.push_back(e);
+    c->event_kind.push_back(-1);
+  }
+  FQ_HIP(c, hipEventRecord(c->events[c->n_events], c->stream));
+  c->event_kind[c->n_events] = kind;
+  ++c->n_events;
+  return FQ_OK;
+}
+
+#define FQ_MARK(c, kind)               \
+  do {                                 \
+    fq_status s_ = mark((c), (kind));  \
+    if (s_ != FQ_OK) return s_;        \
+  } while (0)
+
+// Sum the per-launch intervals into the report (after the stream has drained).
+fq_status collect_profile(fq_ctx* c) {
+  for (int i = 0; i < FQ_K_SLOTS; ++i) {
+    c->last.ms_kernel[i] = 0.0;
+    c->last.n_kernel[i] = 0;
+  }
+  if (!c->profile || c->n_events < 2) return FQ_OK;
+  FQ_HIP(c, hipEventSynchronize(c->events[c->n_events - 1]));
+  for (size_t i = 0; i + 1 < c->n_events; ++i) {
+    const int k = c->event_kind[i];
+    if (k < 0 || k >= FQ_K_SLOTS) continue;
+    float ms = 0.f;
+    FQ_HIP(c, hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]));
+    c->last.ms_kernel[k] += ms;
+    c->last.n_kernel[k] += 1;
+  }
+  return FQ_OK;
+}
+
 // ---- dense step loop ----------------------------------------------------------------------------
 
 fq_status dense_heff(fq_ctx* c, int k) {
+  FQ_MARK(c, FQ_K_HEFF);
   FQ_HIP(c, fq::launch_heff_f64(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
                                 c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->stream));
   return FQ_OK;
@@ -328,6 +373,7 @@ fq_status dense_cheb_step(fq_ctx* c, int mrows) {
     t.p_re = c->xr; t.p_im = c->xi;
     t.o_re = c->yr; t.o_im = c->yi;
     t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(1).real(); t.ci = C(1).imag();
+    FQ_MARK(c, FQ_K_FIRST_LAST);
     FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
     std::swap(c->xr, c->yr);
     std::swap(c->xi, c->yi);
@@ -340,6 +386,7 @@ fq_status dense_cheb_step(fq_ctx* c, int mrows) {
   t.o_re = c->par; t.o_im = c->pai;
   t.y_re = c->yr; t.y_im = c->yi;
   t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(1).real(); t.ci = C(1).imag();
+  FQ_MARK(c, FQ_K_FIRST);
   FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
   // buffers holding P_{l-1} and P_l
   double *prv_r = c->xr, *prv_i = c->xi, *cur_r = c->par, *cur_i = c->pai;
@@ -358,6 +405,7 @@ fq_status dense_cheb_step(fq_ctx* c, int mrows) {
       out_r = prv_r; out_i = prv_i;          // in place over P_{l-1}
     }
     t.o_re = out_r; t.o_im = out_i;
+    FQ_MARK(c, last ? FQ_K_LAST : FQ_K_MID);
     FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
     if (!last) {
       prv_r = cur_r; prv_i = cur_i;
@@ -431,6 +479,7 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.ld_x0 = ncols;
   job.x_out = x_out;
   job.ld_out = ncols;
+  FQ_MARK(c, FQ_K_TRIDIAG);
   FQ_HIP(c, fq::launch_tridiag_resident(job, c->stream));
   return FQ_OK;
 }
@@ -512,6 +561,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->tol = par->tol;
   c->precision = par->precision;
   c->ckpt = par->checkpoint_every;
+  c->profile = par->profile != 0;
   c->f_nodes.assign(par->f_nodes, par->f_nodes + 2 * par->M);
   c->a.resize(c->M);
   c->b.resize(c->M);
@@ -647,11 +697,13 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
   FQ_HIP(c, hipEventCreate(&e0));
   FQ_HIP(c, hipEventCreate(&e1));
   fq_status st = FQ_OK;
+  c->n_events = 0;
   if (c->layout == FQ_DENSE) {
     FQ_HIP(c, fq::launch_identity_rows(c->xr, c->xi, c->n, c->np, c->np, c->stream));
     FQ_HIP(c, hipEventRecord(e0, c->stream));
     st = dense_steps(c, 0, c->M, (int)c->np, c->ckpt > 0);
     if (st != FQ_OK) return st;
+    FQ_MARK(c, -1);
     FQ_HIP(c, hipEventRecord(e1, c->stream));
     FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->stream));
     c->tape_valid = c->ckpt > 0;
@@ -660,6 +712,7 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     FQ_HIP(c, hipEventRecord(e0, c->stream));
     st = tridiag_run(c, nullptr, c->n, 0, c->M, U_out);
     if (st != FQ_OK) return st;
+    FQ_MARK(c, -1);
     FQ_HIP(c, hipEventRecord(e1, c->stream));
     FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->stream));
     st = unitarity(c, c->xr, c->xi);
@@ -671,6 +724,8 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->last.ms_build = ms;
+  st = collect_profile(c);
+  if (st != FQ_OK) return st;
   fill_report(c);
   if (rep) *rep = c->last;
   return FQ_OK;
@@ -682,19 +737,21 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
   if (k0 < 0 || k1 < k0 || k1 > c->M) return fail(FQ_ERR_ARG, "need 0 <= k0 <= k1 <= M");
+  c->n_events = 0;
   if (c->layout == FQ_DENSE) {
     const long mrows = pad_to(ncols, dense_tile(c->n));
     FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->stream));
     fq_status st = dense_steps(c, k0, k1, (int)mrows, false);
     if (st != FQ_OK) return st;
+    FQ_MARK(c, -1);
     FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, ncols, X_out, ncols, c->stream));
-    c->tape_valid = false;  // the planes the tape was taken from were reused
   } else {
     fq_status st = tridiag_run(c, X0, ncols, k0, k1, X_out);
     if (st != FQ_OK) return st;
+    FQ_MARK(c, -1);
   }
   FQ_HIP(c, hipStreamSynchronize(c->stream));
-  return FQ_OK;
+  return collect_profile(c);
 }
 
 fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {

@@ -141,4 +141,13 @@ struct fq_ctx {
   bool tape_valid = false;
   bool broken = false;
   fq_report last{};
+  // profile mode: one event before every launch of a build (and one after the
+  // last); launch i took the time between events i and i+1.
+  bool profile = false;
+  std::vector<hipEvent_t> events;
+  std::vector<int> event_kind;
+  size_t n_events = 0;
+  ~fq_ctx() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
 };

@@ -79,7 +79,8 @@ class FloquetContext:
     def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_diag=None,
                  h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
                  e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
-                 precision: str = "fp64", checkpoint_every: int = 0, device=None):
+                 precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
+                 device=None):
         torch = _torch()
         L_ = lib()
         self.device = torch.device(device if device is not None else "cuda")
@@ -120,6 +121,7 @@ class FloquetContext:
         par.tol = float(tol)
         par.precision = _abi.PRECISIONS[precision]
         par.checkpoint_every = int(checkpoint_every)
+        par.profile = 1 if profile else 0
         self.precision = precision
         import ctypes
         nbytes = ctypes.c_size_t(0)

@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 5 * 8
-    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4
-    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 8 * 8
+    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 4 * 4
+    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 8 * 8 + 8 * 8 + 4 * 8
 
 
 def test_node_times_match_oracle():
@@ -161,6 +161,8 @@ def test_workspace_bytes_ok_and_grows_with_n():
     (lambda s, p: (setattr(p, "e_min", -math.inf), setattr(p, "e_max", 1.0)), _abi.FQ_ERR_NONFINITE),
     (lambda s, p: setattr(p, "precision", 9), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "checkpoint_every", -2), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "profile", 2), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "reserved1", 1), _abi.FQ_ERR_ARG),
 ])
 def test_invalid_arguments_rejected(mutate, status):
     s, p = _dense(), _params()
