@@ -21,6 +21,7 @@ SOURCES = [
     "floquet.cpp",
     "kernels_dense.hip",
     "kernels_tridiag.hip",
+    "kernels_mixed.hip",
 ]
 
 HIPCC_FLAGS = [

@@ -56,7 +56,7 @@ bool is_finite(double x) { return std::isfinite(x); }
 struct Layout {
   size_t total = 0;
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
-         off_pb = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0;
+         off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -81,6 +81,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.off_y = take(plane2);
     lay.off_pa = take(plane2);
     lay.off_pb = take(plane2);
+    if (par->precision != FQ_FP64) lay.off_htx = take(plane2);
     if (par->checkpoint_every > 0) {
       lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
       lay.off_tape = take(plane2 * (size_t)lay.n_tape);
@@ -138,8 +139,6 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
     if (par->checkpoint_every > 0)
       return fail(FQ_ERR_UNSUPPORTED, "gradient tape not available for the tridiagonal layout");
   }
-  if (sys->layout == FQ_DENSE && par->precision != FQ_FP64)
-    return fail(FQ_ERR_UNSUPPORTED, "mixed precision not available in this build");
   return FQ_OK;
 }
 
@@ -352,64 +351,100 @@ fq_status collect_profile(fq_ctx* c) {
 
 fq_status dense_heff(fq_ctx* c, int k) {
   FQ_MARK(c, FQ_K_HEFF);
-  FQ_HIP(c, fq::launch_heff_f64(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
-                                c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->stream));
+  if (c->precision == FQ_FP64) {
+    FQ_HIP(c, fq::launch_heff_f64(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
+                                  c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->stream));
+  } else {
+    FQ_HIP(c, fq::launch_heff_mixed(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k],
+                                    c->b[k], c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->htx,
+                                    c->precision, c->stream));
+  }
   return FQ_OK;
 }
 
-// One step on the state-major block held in (X planes): X <- E_k X.
+// One Chebyshev product. a, p, o are the first planes of their buffers
+// (real part first; the imaginary planes follow); `*_f64` says whether that
+// buffer holds FP64 planes (X, Y) or the product format of the context.
+fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, double* p, bool p_f64,
+                      double* o, bool o_f64, std::complex<double> c0, std::complex<double> cl) {
+  const int np = (int)c->np;
+  const long plane = c->np * c->np;
+  static const int slot[4] = {FQ_K_FIRST, FQ_K_FIRST_LAST, FQ_K_MID, FQ_K_LAST};
+  FQ_MARK(c, slot[kind]);
+  if (c->precision == FQ_FP64) {
+    ChebTerm t{};
+    t.kind = kind;
+    t.a_re = a; t.a_im = a + plane;
+    t.b_re = c->htr; t.b_im = c->hti;
+    t.p_re = p; t.p_im = p + plane;
+    t.y_re = c->yr; t.y_im = c->yi;
+    t.o_re = o; t.o_im = o + plane;
+    t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
+    t.phr = c->phr; t.phi = c->phi;
+    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+  } else {
+    const int pf = c->precision == FQ_FP32 ? fq::FMT_F32 : fq::FMT_BF16X3;
+    fq::ChebTermX t{};
+    t.kind = kind;
+    t.a_fmt = a_f64 ? fq::FMT_F64 : pf;
+    t.p_fmt = p_f64 ? fq::FMT_F64 : pf;
+    t.o_fmt = o_f64 ? fq::FMT_F64 : pf;
+    t.plane = plane;
+    t.a = a; t.b = c->htx; t.p = p; t.o = o;
+    t.y_re = c->yr; t.y_im = c->yi;
+    t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
+    t.phr = c->phr; t.phi = c->phi;
+    if (kind == fq::CHEB_FIRST || kind == fq::CHEB_FIRST_LAST) {
+      // P_1 = Ht X carries the largest Chebyshev weight (|c_1| ~ R) and feeds
+      // every later term, so it is formed on FP64 matrix cores.
+      FQ_HIP(c, fq::launch_cheb_first_mixed(t, c->htr, c->hti, mrows, np, c->stream));
+    } else {
+      FQ_HIP(c, fq::launch_cheb_mixed(t, c->precision, mrows, np, c->stream));
+    }
+  }
+  return FQ_OK;
+}
+
+#define FQ_TRY(expr)                 \
+  do {                               \
+    fq_status s_ = (expr);           \
+    if (s_ != FQ_OK) return s_;      \
+  } while (0)
+
+// One step on the state-major block held in the X planes: X <- E_k X.
+// Buffers: X and Y FP64; Pa, Pb hold P_1 .. P_L in the product format.
 fq_status dense_cheb_step(fq_ctx* c, int mrows) {
   const int L = c->L;
-  const int np = (int)c->np;
-  ChebTerm t{};
-  t.b_re = c->htr;
-  t.b_im = c->hti;
-  t.phr = c->phr;
-  t.phi = c->phi;
   auto C = [&](int l) { return std::complex<double>(c->coef[2 * l], c->coef[2 * l + 1]); };
-  if (L == 1) {
-    t.kind = fq::CHEB_FIRST_LAST;
-    t.a_re = c->xr; t.a_im = c->xi;
-    t.p_re = c->xr; t.p_im = c->xi;
-    t.o_re = c->yr; t.o_im = c->yi;
-    t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(1).real(); t.ci = C(1).imag();
-    FQ_MARK(c, FQ_K_FIRST_LAST);
-    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+  if (L == 1) {  // X_new = ph (c0 X + c1 Ht X), written to Y, then the roles swap
+    FQ_TRY(cheb_launch(c, fq::CHEB_FIRST_LAST, mrows, c->xr, true, c->xr, true, c->yr, true, C(0), C(1)));
     std::swap(c->xr, c->yr);
     std::swap(c->xi, c->yi);
     return FQ_OK;
   }
   // l = 0: P1 -> Pa, Y = c0 X + c1 P1
-  t.kind = fq::CHEB_FIRST;
-  t.a_re = c->xr; t.a_im = c->xi;
-  t.p_re = c->xr; t.p_im = c->xi;
-  t.o_re = c->par; t.o_im = c->pai;
-  t.y_re = c->yr; t.y_im = c->yi;
-  t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(1).real(); t.ci = C(1).imag();
-  FQ_MARK(c, FQ_K_FIRST);
-  FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
-  // buffers holding P_{l-1} and P_l
-  double *prv_r = c->xr, *prv_i = c->xi, *cur_r = c->par, *cur_i = c->pai;
+  FQ_TRY(cheb_launch(c, fq::CHEB_FIRST, mrows, c->xr, true, c->xr, true, c->par, false, C(0), C(1)));
+  double* prv = c->xr;  // P_{l-1}
+  bool prv_f64 = true;
+  double* cur = c->par;  // P_l
   for (int l = 1; l <= L - 1; ++l) {
     const bool last = (l == L - 1);
-    t.kind = last ? fq::CHEB_LAST : fq::CHEB_MID;
-    t.a_re = cur_r; t.a_im = cur_i;
-    t.p_re = prv_r; t.p_im = prv_i;
-    t.cr = C(l + 1).real(); t.ci = C(l + 1).imag();
-    double *out_r, *out_i;
+    double* out;
+    bool out_f64 = false;
     if (last) {
-      out_r = c->xr; out_i = c->xi;          // X is free once P_2 exists (or is P_0 itself, in place)
+      out = c->xr;  // X is free once P_2 exists (or is P_0 itself, updated in place)
+      out_f64 = true;
     } else if (l == 1) {
-      out_r = c->pbr; out_i = c->pbi;        // keep X intact until P_2 is formed
+      out = c->pbr;  // keep X intact until P_2 is formed
     } else {
-      out_r = prv_r; out_i = prv_i;          // in place over P_{l-1}
+      out = prv;  // in place over P_{l-1}
     }
-    t.o_re = out_r; t.o_im = out_i;
-    FQ_MARK(c, last ? FQ_K_LAST : FQ_K_MID);
-    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+    FQ_TRY(cheb_launch(c, last ? fq::CHEB_LAST : fq::CHEB_MID, mrows, cur, false, prv, prv_f64, out,
+                       out_f64, C(0), C(l + 1)));
     if (!last) {
-      prv_r = cur_r; prv_i = cur_i;
-      cur_r = out_r; cur_i = out_i;
+      prv = cur;
+      prv_f64 = false;
+      cur = out;
     }
   }
   return FQ_OK;
@@ -589,6 +624,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     c->yr = P(lay.off_y);   c->yi = c->yr + plane;
     c->par = P(lay.off_pa); c->pai = c->par + plane;
     c->pbr = P(lay.off_pb); c->pbi = c->pbr + plane;
+    if (par->precision != FQ_FP64) c->htx = P(lay.off_htx);
     if (lay.n_tape > 0) {
       c->tape = P(lay.off_tape);
       c->n_tape = lay.n_tape;

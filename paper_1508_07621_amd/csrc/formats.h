@@ -1,0 +1,79 @@
+// Device-side storage formats of complex planes (see Fmt in internal.h):
+// BF16 three-piece splitting and element load / store in any format.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace fq {
+
+typedef uint16_t u16;
+
+__device__ __forceinline__ u16 bf16_bits(__bf16 v) { return __builtin_bit_cast(u16, v); }
+__device__ __forceinline__ float bf16_val(u16 b) { return (float)__builtin_bit_cast(__bf16, b); }
+
+// x ~ hi + mid + lo, each piece the BF16 rounding (to nearest even) of what the
+// previous ones left; the three pieces carry about 24 significant bits.
+__device__ __forceinline__ void split3(float x, u16& h, u16& m, u16& l) {
+  const __bf16 bh = (__bf16)x;
+  const float r1 = x - (float)bh;
+  const __bf16 bm = (__bf16)r1;
+  const float r2 = r1 - (float)bm;
+  h = bf16_bits(bh);
+  m = bf16_bits(bm);
+  l = bf16_bits((__bf16)r2);
+}
+
+__device__ __forceinline__ void load_c(const void* base, int fmt, long plane, long idx, double& re,
+                                       double& im) {
+  if (fmt == FMT_F64) {
+    const double* p = static_cast<const double*>(base);
+    re = p[idx];
+    im = p[plane + idx];
+  } else if (fmt == FMT_F32) {
+    const float* p = static_cast<const float*>(base);
+    re = p[idx];
+    im = p[plane + idx];
+  } else {
+    const u16* p = static_cast<const u16*>(base);
+    re = (double)(bf16_val(p[idx]) + bf16_val(p[plane + idx]) + bf16_val(p[2 * plane + idx]));
+    im = (double)(bf16_val(p[3 * plane + idx]) + bf16_val(p[4 * plane + idx]) +
+                  bf16_val(p[5 * plane + idx]));
+  }
+}
+
+// Store (re, im) in the given format and return in (re, im) the value the
+// storage now holds.
+__device__ __forceinline__ void store_c(void* base, int fmt, long plane, long idx, double& re,
+                                        double& im) {
+  if (fmt == FMT_F64) {
+    double* p = static_cast<double*>(base);
+    p[idx] = re;
+    p[plane + idx] = im;
+  } else if (fmt == FMT_F32) {
+    float* p = static_cast<float*>(base);
+    const float r = (float)re, i = (float)im;
+    p[idx] = r;
+    p[plane + idx] = i;
+    re = r;
+    im = i;
+  } else {
+    u16* p = static_cast<u16*>(base);
+    u16 h, m, l;
+    split3((float)re, h, m, l);
+    p[idx] = h;
+    p[plane + idx] = m;
+    p[2 * plane + idx] = l;
+    re = (double)(bf16_val(h) + bf16_val(m) + bf16_val(l));
+    split3((float)im, h, m, l);
+    p[3 * plane + idx] = h;
+    p[4 * plane + idx] = m;
+    p[5 * plane + idx] = l;
+    im = (double)(bf16_val(h) + bf16_val(m) + bf16_val(l));
+  }
+}
+
+}  // namespace fq

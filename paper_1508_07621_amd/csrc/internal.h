@@ -53,6 +53,41 @@ struct ChebTerm {
 // operands (mrows, np multiples of the tile size chosen by the launcher).
 hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s);
 
+// ---- mixed-precision products (kernels_mixed.hip) ------------------------------------------
+// Storage formats of a complex plane pair. F64 and F32: two planes (re, im).
+// BF16X3: six planes of 16-bit words, re_hi re_mid re_lo im_hi im_mid im_lo,
+// whose sum hi + mid + lo carries about 24 significant bits.
+enum Fmt : int { FMT_F64 = 0, FMT_F32 = 1, FMT_BF16X3 = 2 };
+
+struct ChebTermX {
+  int kind;
+  int a_fmt, p_fmt, o_fmt;  // formats of A (P_l or X), P_{l-1} (or X), and the output
+  long plane;               // elements per plane (np * np)
+  const void* a;            // A planes (state-major)
+  const void* b;            // B planes: rescaled H in the product format (F32 or BF16X3)
+  const void* p;            // P_{l-1} (X for the first product)
+  double* y_re;             // Chebyshev sum, F64
+  double* y_im;
+  void* o;                  // output planes
+  double c0r, c0i, cr, ci, phr, phi;
+};
+
+// Products P_{l+1} = 2 Ht P_l - P_{l-1} (l >= 1) with A = P_l in the product
+// format; precision: FQ_FP32 or FQ_BF16X3 (FP32 or BF16 matrix cores).
+hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s);
+// The first product of a step in a mixed-precision build (kind CHEB_FIRST or
+// CHEB_FIRST_LAST): A = X and B = the FP64 rescaled Hamiltonian (b64_re,
+// b64_im) on FP64 matrix cores; P_1 is stored in the product format t.o_fmt
+// and the FP64 product goes into Y (or into the FP64 output for L == 1).
+hipError_t launch_cheb_first_mixed(const ChebTermX& t, const double* b64_re, const double* b64_im,
+                                   int mrows, int np, hipStream_t s);
+// Rescaled Hamiltonian, written both as FP64 planes (hr, hi) and in the
+// product format of `precision` (out).
+hipError_t launch_heff_mixed(const double* h0r, const double* h0i, const double* vr,
+                             const double* vi, const double* kr, const double* ki, double a,
+                             double b, double beta, double dE, long n, long ld, double* hr,
+                             double* hi, void* out, int precision, hipStream_t s);
+
 // C = alpha * (A op(B)^T) + beta * C with conjugation flags; planar fp64.
 hipError_t launch_zgemm_nt_f64(const double* ar, const double* ai, bool conj_a, const double* br,
                                const double* bi, bool conj_b, double* cr, double* ci, int mrows,
@@ -132,6 +167,7 @@ struct fq_ctx {
   double *htr = nullptr, *hti = nullptr;
   double *xr = nullptr, *xi = nullptr, *yr = nullptr, *yi = nullptr;
   double *par = nullptr, *pai = nullptr, *pbr = nullptr, *pbi = nullptr;
+  void* htx = nullptr;                // mixed builds: rescaled H in the product format
   double* tape = nullptr;             // checkpoints, each 2 planes
   int n_tape = 0;
   double* small = nullptr;            // 64 doubles of reduction scratch

@@ -167,6 +167,58 @@ def test_dense_full_size_sampled_columns(fl):
     assert rep["unitarity_max"] < 1e-11
 
 
+# ---- dense mixed precision --------------------------------------------------------------------------
+
+MIXED_TOL = 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,M,seed,tol", [(64, 100, 1508, MIXED_TOL), (200, 20, 3, MIXED_TOL),
+                                          (1030, 20, 4, MIXED_TOL), (300, 3, 8, 3e-6)])
+def test_dense_mixed_matches_oracle(fl, precision, n, M, seed, tol):
+    """Bar 1e-6 in the worst column at step sizes like the workloads' (R <= 1.3).
+    The last case takes three steps of R ~ 8 (27 products per step): there the
+    products after the first, which run in the product format, carry weights
+    up to ~|J_l(R)| and the error grows with R, so its bar is 3e-6."""
+    _say("dense", precision, n, M, seed)
+    H0, V = _dense_case(n, seed)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
+                            precision=precision)
+    U = ctx.build_ut().cpu().numpy()
+    rep = ctx.last_report
+    cols = list(range(n)) if n <= 300 else [0, 511, n - 1]
+    X0 = np.eye(n, dtype=complex)[:, cols]
+    Xref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0)
+    err = orc.column_error(U[:, cols], Xref)
+    _say("e_col", err, "L", L, "unitarity", rep["unitarity_max"])
+    assert err < tol
+    assert rep["unitarity_max"] < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_dense_mixed_low_orders_and_propagate(fl, precision):
+    n, M = 96, 6
+    H0, V = _dense_case(n, 31)
+    T = 0.3
+    f = _cos_nodes(fl, T, M)
+    lo, hi, _ = _oracle_interval(H0, V, f, T, M)
+    for L in (1, 2, 3):
+        _say("dense", precision, "L", L)
+        U = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
+                              precision=precision).build_ut().cpu().numpy()
+        Uref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+        assert orc.column_error(U, Uref) < MIXED_TOL
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=5,
+                            precision=precision)
+    X0 = haar_unitary(n, np.random.default_rng(2))[:, :9]
+    X = ctx.propagate(X0, 1, 5).cpu().numpy()
+    Xref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=5, X0=X0, k_range=(1, 5))
+    assert orc.column_error(X, Xref) < MIXED_TOL
+
+
 # ---- tridiagonal (dimer) FP64 ---------------------------------------------------------------------
 
 def _dimer_ctx(fl, nb, U_int, M, eps0=0.5, eps1=1.5, L=None, tol=1e-12):
