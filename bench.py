@@ -50,8 +50,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gue4096", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the dense Chebyshev products (the tridiagonal path is FP64)")
+    ap.add_argument("--no-fp64-ref", action="store_true",
+                    help="skip the FP64 reference build of a mixed-precision run")
+    ap.add_argument("--no-eig", action="store_true", help="skip the host eigenphase comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run one device-to-device copy of BYTES bytes (the reference "
+                         "kernel for scaling HBM traffic counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -122,6 +129,69 @@ def _blas_threads() -> int:
     return len(os.sched_getaffinity(0))
 
 
+#: MFMA operations issued per algorithmic real flop of a complex product:
+#: FP64 and FP32 run the four real products once; BF16x3 runs six piece
+#: products for each of the four real products.
+MFMA_FLOPS_PER_FLOP = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 6.0}
+PEAKS = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
+         "bf16x3": PEAK_BF16_MFMA_TFLOPS}
+KERNEL_NAMES = {"fp64": "zgemm_nt_f64_kernel<128,128,16,2,4,EpiCheb<MID>> (FP64 MFMA 16x16x4)",
+                "fp32": "cheb_f32_kernel<128,128,32,2,4,EpiMix<MID>> (FP32 MFMA 16x16x4)",
+                "bf16x3": "cheb_bf16x3_kernel<128,128,2,4,EpiMix<MID>> (BF16 MFMA 16x16x32)"}
+
+
+def time_builds(ctx, U, warmup: int, steps: int, tag: str):
+    """W untimed builds, then K builds timed between device synchronisations."""
+    import torch
+    for i in range(warmup):
+        ctx.build_ut(out=U)
+        _log(f"{tag} warmup build {i + 1}/{warmup}: {ctx.last_report['ms_build']:.1f} ms")
+    torch.cuda.synchronize()
+    reports = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ctx.build_ut(out=U)
+        reports.append(ctx.last_report)
+        _log(f"{tag} timed build {i + 1}/{steps}: {reports[-1]['ms_build']:.1f} ms")
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, reports
+
+
+def dense_roofline(reports, n: int, precision: str):
+    from paper_1508_07621_amd._abi import K_MID
+    n_launch = sum(r["n_kernel"][K_MID] for r in reports)
+    ms_launch = sum(r["ms_kernel"][K_MID] for r in reports) / max(n_launch, 1)
+    flops = 8.0 * n ** 3                                   # one complex N x N x N product
+    mfma_flops = flops * MFMA_FLOPS_PER_FLOP[precision]
+    achieved = mfma_flops / (ms_launch * 1e-3) / 1e12
+    peak = PEAKS[precision]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None, "kernel": KERNEL_NAMES[precision],
+            "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
+            "mfma_flops_per_launch": mfma_flops, "algorithmic_flops_per_launch": flops,
+            "algorithmic_tflops": round(flops / (ms_launch * 1e-3) / 1e12, 3)}
+
+
+def eigen_errors(U, Uref, T: float):
+    """Host FP64 eigenphases (LAPACK zgeev through NumPy) of both results and
+    the largest quasienergy difference (symmetric circular matching)."""
+    import numpy as np
+    from paper_1508_07621_amd.analysis import eigenphases
+    t0 = time.perf_counter()
+    th = eigenphases(U)
+    th_ref = eigenphases(Uref)
+
+    def one_way(x, y):
+        ext = np.concatenate([y - 2 * math.pi, y, y + 2 * math.pi])
+        idx = np.searchsorted(ext, x)
+        lo = np.clip(idx - 1, 0, len(ext) - 1)
+        hi = np.clip(idx, 0, len(ext) - 1)
+        return float(np.max(np.minimum(np.abs(x - ext[lo]), np.abs(x - ext[hi]))))
+
+    d = max(one_way(th, th_ref), one_way(th_ref, th)) / T
+    return d, time.perf_counter() - t0
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -131,69 +201,81 @@ def main():
               "not an implemented path", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1508_07621_amd import floquet as fl
+    from paper_1508_07621_amd._abi import K_TRIDIAG
     from workloads import drive_cos, workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}), flush=True)
+        return
     wl = workload(args.workload)
+    precision = args.precision if wl.layout == "dense" else "fp64"
     if args.workload == "dimer1000":
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.5, 1.5, 1.0)
     else:
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.0, 1.0, 1.0)
-
-    t_setup = time.perf_counter()
     if wl.layout == "dense":
         kw = dict(h0=wl.arrays["h0"], hmod=wl.arrays["v"])
     else:
         kw = dict(h0_diag=wl.arrays["h0_diag"], h0_off=wl.arrays["h0_off"],
                   hmod_diag=wl.arrays["v_diag"])
-    ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12,
-                            precision=args.precision, profile=True, device=dev, **kw)
+
+    t_setup = time.perf_counter()
+    ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision=precision,
+                            profile=True, device=dev, **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     info = ctx.report
     _log(f"setup {setup_s:.2f} s: L={info['L']} R={info['R']:.4f} "
          f"interval=[{info['e_min']:.6g}, {info['e_max']:.6g}]")
-    U = torch.empty((wl.n, wl.n), dtype=torch.complex128, device=dev)
-
-    for i in range(args.warmup):
-        ctx.build_ut(out=U)
-        _log(f"warmup build {i + 1}/{args.warmup}: {ctx.last_report['ms_build']:.1f} ms")
-    torch.cuda.synchronize()
-    reports = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ctx.build_ut(out=U)
-        reports.append(ctx.last_report)
-        _log(f"timed build {i + 1}/{args.steps}: {reports[-1]['ms_build']:.1f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    s_per_build = elapsed / args.steps
-
-    from paper_1508_07621_amd._abi import K_MID, K_TRIDIAG
     n = wl.n
+    U = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    s_per_build, reports = time_builds(ctx, U, args.warmup, args.steps, precision)
+    last = reports[-1]
+    errors = {"unitarity_max": last["unitarity_max"], "unitarity_fro": last["unitarity_fro"]}
+
+    extra = {}
     if wl.layout == "dense":
-        kind = K_MID
-        n_launch = sum(r["n_kernel"][kind] for r in reports)
-        ms_launch = sum(r["ms_kernel"][kind] for r in reports) / max(n_launch, 1)
-        flops = 8.0 * n ** 3                       # one complex N x N x N product
-        peak = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
-                "bf16x3": PEAK_BF16_MFMA_TFLOPS}[args.precision]
-        achieved = flops / (ms_launch * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "Chebyshev product (middle terms), zgemm_nt_f64_kernel<128,128,16,2,4>",
-                "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
-                "algorithmic_flops_per_launch": flops}
-        build_tflops = info["L"] * wl.M * flops / s_per_build / 1e12
+        roof = dense_roofline(reports, n, precision)
+        build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
+        if precision != "fp64" and not args.no_fp64_ref:
+            # The FP64 build of the same workload: reference result and timing.
+            ref = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision="fp64",
+                                    e_min=info["e_min"], e_max=info["e_max"], L=info["L"],
+                                    profile=True, device=dev, **kw)
+            Uref = torch.empty_like(U)
+            s_ref, rep_ref = time_builds(ref, Uref, 0, 1, "fp64")
+            D = U - Uref
+            errors.update({
+                "reference": "FP64 build of the same workload on the GPU (same interval and L)",
+                "e_col": torch.linalg.vector_norm(D, dim=0).max().item(),
+                "fro_over_sqrtN": torch.linalg.vector_norm(D).item() / math.sqrt(n),
+                "max_abs": D.abs().max().item(),
+                "ref_unitarity_max": rep_ref[-1]["unitarity_max"],
+            })
+            if not args.no_eig:
+                _log("host FP64 eigenphases of both results")
+                dq, eig_s = eigen_errors(U.cpu().numpy(), Uref.cpu().numpy(), wl.T)
+                errors["max_quasienergy_error"] = dq
+                extra["eig_seconds_host"] = round(eig_s, 1)
+            extra["fp64"] = {"s_per_build": round(s_ref, 4),
+                             "build_tflops_algorithmic": round(
+                                 info["L"] * wl.M * 8.0 * n ** 3 / s_ref / 1e12, 3),
+                             "roofline": dense_roofline(rep_ref, n, "fp64")}
+            extra["speedup_vs_fp64"] = round(s_ref / s_per_build, 3)
+            del ref, Uref
     else:
-        kind = K_TRIDIAG
-        n_launch = sum(r["n_kernel"][kind] for r in reports)
-        ms_launch = sum(r["ms_kernel"][kind] for r in reports) / max(n_launch, 1)
+        n_launch = sum(r["n_kernel"][K_TRIDIAG] for r in reports)
+        ms_launch = sum(r["ms_kernel"][K_TRIDIAG] for r in reports) / max(n_launch, 1)
         flops = float(TRIDIAG_FLOPS_PER_ELEMENT_TERM) * n * n * wl.M * info["L"]
         achieved = flops / (ms_launch * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
@@ -203,7 +285,6 @@ def main():
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops / s_per_build / 1e12
 
-    last = reports[-1]
     out = {
         "metric": "s per U_T build + TFLOP/s (% MFMA/HBM peak), mixed vs FP64 at stated error",
         "value": round(s_per_build, 6),
@@ -215,18 +296,20 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[precision],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "n": n,
                    "M": wl.M, "L": info["L"], "R": round(info["R"], 6),
-                   "interval": [info["e_min"], info["e_max"]], "precision": args.precision,
+                   "interval": [info["e_min"], info["e_max"]], "precision": precision,
                    "parallelism": "1 GPU"},
         "build_tflops_algorithmic": round(build_tflops, 3),
-        "errors": {"unitarity_max": last["unitarity_max"], "unitarity_fro": last["unitarity_fro"]},
+        "errors": errors,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
     }
+    out.update(extra)
     if not args.no_cpu_baseline:
+        _log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(wl, f_nodes, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -10,6 +10,24 @@
 
 namespace fq {
 
+// Output tile of workgroup `bid` in a tiles_m x tiles_n grid. Workgroups are
+// dispatched round-robin over the 8 XCDs (XCD = bid % 8), and each XCD has its
+// own L2. When tiles_m divides by 8, XCD x owns the tile rows
+// [x r, (x+1) r), r = tiles_m / 8, and walks them column by column with all r
+// rows interleaved: the ~32 workgroups resident on one XCD then cover r rows
+// and a few columns, so they stream r A panels and a few B panels, which its
+// L2 can hold, instead of one distinct panel pair each.
+__device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  if (tiles_m % 8 == 0) {
+    const int x = bid % 8, local = bid / 8, r = tiles_m / 8;
+    tm = x * r + local % r;
+    tn = local / r;
+  } else {
+    tm = bid / tiles_n;
+    tn = bid % tiles_n;
+  }
+}
+
 typedef uint16_t u16;
 
 __device__ __forceinline__ u16 bf16_bits(__bf16 v) { return __builtin_bit_cast(u16, v); }

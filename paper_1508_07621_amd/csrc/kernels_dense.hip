@@ -59,13 +59,8 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
   __shared__ __attribute__((aligned(16))) double As[2][BM * S];
   __shared__ __attribute__((aligned(16))) double Bs[2][BN * S];
 
-  // Tile order: consecutive workgroup ids land on different XCDs (round-robin
-  // dispatch), so spread the id space so that each XCD sweeps a compact band
-  // of output tiles that share A rows.
-  const int nblk = op.tiles_m * op.tiles_n;
-  int bid = blockIdx.x;
-  if (nblk % 8 == 0) bid = (bid % 8) * (nblk / 8) + bid / 8;
-  const int tm = bid / op.tiles_n, tn = bid % op.tiles_n;
+  int tm, tn;
+  tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;

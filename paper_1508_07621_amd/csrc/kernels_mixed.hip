@@ -83,11 +83,6 @@ struct MixOperands {
   int tiles_m, tiles_n;
 };
 
-__device__ __forceinline__ int remap_tile(int bid, int nblk) {
-  // consecutive workgroup ids go to different XCDs; give each XCD a compact band
-  return (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
-}
-
 // ---------------------------------------------------------------------------------------------
 // FP32 products. A = F32 planes, or F64 planes (X) rounded while staging.
 // LDS row stride BK + 4 floats: the 16 rows read by one 16-lane group start on
@@ -108,8 +103,8 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
   __shared__ __attribute__((aligned(16))) float As[2][BM * S];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN * S];
 
-  const int bid = remap_tile(blockIdx.x, op.tiles_m * op.tiles_n);
-  const int tm = bid / op.tiles_n, tn = bid % op.tiles_n;
+  int tm, tn;
+  tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
@@ -250,8 +245,8 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf16x3_kernel(MixOperands 
   __shared__ __attribute__((aligned(16))) u16 As[6][BM * S];
   __shared__ __attribute__((aligned(16))) u16 Bs[6][BN * S];
 
-  const int bid = remap_tile(blockIdx.x, op.tiles_m * op.tiles_n);
-  const int tm = bid / op.tiles_n, tn = bid % op.tiles_n;
+  int tm, tn;
+  tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
