@@ -56,7 +56,8 @@ bool is_finite(double x) { return std::isfinite(x); }
 struct Layout {
   size_t total = 0;
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
-         off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0;
+         off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
+         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -74,8 +75,10 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.np = pad_to(n, dense_tile(n));
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
     lay.off_h0 = take(plane2);
-    lay.off_v = take(plane2);
-    lay.off_k = take(plane2);
+    // Hmod and K share one block laid out re(Hmod), re(K), im(Hmod), im(K), so
+    // that [Hmod; K] is one 2np-row operand for the gradient contraction.
+    lay.off_v = take(2 * plane2);
+    lay.off_k = lay.off_v;
     lay.off_ht = take(plane2);
     lay.off_x = take(plane2);
     lay.off_y = take(plane2);
@@ -85,6 +88,10 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     if (par->checkpoint_every > 0) {
       lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
       lay.off_tape = take(plane2 * (size_t)lay.n_tape);
+      lay.off_seg = take(3 * plane2 * (size_t)par->checkpoint_every);
+      lay.off_stack = take(4 * plane2);
+      lay.off_lam = take(plane2);
+      lay.off_grad = take(2 * sizeof(double) * (size_t)par->M);
     }
   } else {
     lay.np = pad_to(n, dense_tile(n));
@@ -381,6 +388,10 @@ fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, dou
     t.o_re = o; t.o_im = o + plane;
     t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
     t.phr = c->phr; t.phi = c->phi;
+    if (c->save_pl && (kind == fq::CHEB_LAST || kind == fq::CHEB_FIRST_LAST)) {
+      t.save_re = c->save_pl;
+      t.save_im = c->save_pl + plane;
+    }
     FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
   } else {
     const int pf = c->precision == FQ_FP32 ? fq::FMT_F32 : fq::FMT_BF16X3;
@@ -415,7 +426,10 @@ fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, dou
 // Buffers: X and Y FP64; Pa, Pb hold P_1 .. P_L in the product format.
 fq_status dense_cheb_step(fq_ctx* c, int mrows) {
   const int L = c->L;
+  const size_t p2bytes = 2 * sizeof(double) * (size_t)c->np * (size_t)c->np;
   auto C = [&](int l) { return std::complex<double>(c->coef[2 * l], c->coef[2 * l + 1]); };
+  if (c->save_plm1 && L == 1)  // P_{L-1} = P_0 = X
+    FQ_HIP(c, hipMemcpyAsync(c->save_plm1, c->xr, p2bytes, hipMemcpyDeviceToDevice, c->stream));
   if (L == 1) {  // X_new = ph (c0 X + c1 Ht X), written to Y, then the roles swap
     FQ_TRY(cheb_launch(c, fq::CHEB_FIRST_LAST, mrows, c->xr, true, c->xr, true, c->yr, true, C(0), C(1)));
     std::swap(c->xr, c->yr);
@@ -439,6 +453,8 @@ fq_status dense_cheb_step(fq_ctx* c, int mrows) {
     } else {
       out = prv;  // in place over P_{l-1}
     }
+    if (last && c->save_plm1)  // FP64 only: the buffers hold planar FP64 P_{L-1}
+      FQ_HIP(c, hipMemcpyAsync(c->save_plm1, cur, p2bytes, hipMemcpyDeviceToDevice, c->stream));
     FQ_TRY(cheb_launch(c, last ? fq::CHEB_LAST : fq::CHEB_MID, mrows, cur, false, prv, prv_f64, out,
                        out_f64, C(0), C(l + 1)));
     if (!last) {
@@ -516,6 +532,132 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.ld_out = ncols;
   FQ_MARK(c, FQ_K_TRIDIAG);
   FQ_HIP(c, fq::launch_tridiag_resident(job, c->stream));
+  return FQ_OK;
+}
+
+// ---- adjoint ---------------------------------------------------------------------------------
+//
+// One step maps X to X' = phi sum_l c_l P_l with P_0 = X, P_1 = Ht X,
+// P_{l+1} = 2 Ht P_l - P_{l-1}, phi = exp(-i beta h). For a real loss with
+// Lambda = dL/dRe X' + i dL/dIm X', the chain rule gives (Ht Hermitian):
+//   Pbar_L = d_L Lambda,  Pbar_{L-1} = 2 Ht Pbar_L + d_{L-1} Lambda,
+//   Pbar_l = 2 Ht Pbar_{l+1} - Pbar_{l+2} + d_l Lambda   (1 <= l <= L-2),
+//   Pbar_0 = Ht Pbar_1 - Pbar_2 + d_0 Lambda = dL/dRe X + i dL/dIm X,
+// with d_l = conj(phi c_l), and
+//   dL/da_k = Re sum_l w_l <Pbar_{l+1}, Hmod P_l> / dE,  w_0 = 1, w_l = 2,
+// likewise dL/db_k with K. The P_l are regenerated backwards from P_{L-1},
+// P_L by P_{l-1} = 2 Ht P_l - P_{l+1}, in the same product as the Pbar_l
+// (stacked operand [P_l; Pbar_{l+1}]). X_{k-1}, P_{L-1}, P_L of each step come
+// from recomputing its segment forward from the tape.
+
+fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
+  const int L = c->L;
+  const int np = (int)c->np;
+  const long plane = c->np * c->np;
+  const size_t pbytes = sizeof(double) * (size_t)plane;
+  hipStream_t s = c->stream;
+  double* seg_x = c->seg + (size_t)slot * 6 * plane;
+  double* seg_lm1 = seg_x + 2 * plane;
+  double* seg_l = seg_x + 4 * plane;
+  auto D = [&](int l) {  // conj(phi c_l)
+    const std::complex<double> ph(c->phr, c->phi), cl(c->coef[2 * l], c->coef[2 * l + 1]);
+    return std::conj(ph * cl);
+  };
+  // stack views: re plane (2np x np) then im plane; top = P, bottom = Pbar
+  auto top_re = [&](int i) { return c->stack[i]; };
+  auto top_im = [&](int i) { return c->stack[i] + 2 * plane; };
+  auto bot_re = [&](int i) { return c->stack[i] + plane; };
+  auto bot_im = [&](int i) { return c->stack[i] + 3 * plane; };
+  double* lr = c->lam;
+  double* li = c->lam + plane;
+  double* gk = c->d_grad + 2 * (size_t)k;
+  const int dot_cols = any_b ? 2 * np : np;
+  auto copy2 = [&](double* dre, double* dim, const double* src) -> fq_status {
+    FQ_HIP(c, hipMemcpyAsync(dre, src, pbytes, hipMemcpyDeviceToDevice, s));
+    FQ_HIP(c, hipMemcpyAsync(dim, src + plane, pbytes, hipMemcpyDeviceToDevice, s));
+    return FQ_OK;
+  };
+  auto dot = [&](int i, double w) -> fq_status {
+    FQ_HIP(c, fq::launch_adj_dot(top_re(i), top_im(i), c->vr, c->vi, dot_cols, bot_re(i),
+                                 bot_im(i), w, gk, np, s));
+    return FQ_OK;
+  };
+  // Pbar_L = d_L Lambda over P_{L-1} in stack 0; P_L over zero in stack 1
+  std::complex<double> d = D(L);
+  FQ_TRY(copy2(top_re(0), top_im(0), seg_lm1));
+  FQ_HIP(c, fq::launch_scale_planar(lr, li, d.real(), d.imag(), bot_re(0), bot_im(0), plane, s));
+  FQ_TRY(copy2(top_re(1), top_im(1), seg_l));
+  FQ_HIP(c, hipMemsetAsync(bot_re(1), 0, pbytes, s));
+  FQ_HIP(c, hipMemsetAsync(bot_im(1), 0, pbytes, s));
+  int cur = 0;
+  for (int l = L - 1; l >= 1; --l) {
+    const int o = 1 - cur;
+    FQ_TRY(dot(cur, 2.0));  // <Pbar_{l+1}, D P_l>
+    d = D(l);
+    if (l >= 2) {
+      FQ_HIP(c, fq::launch_adj_step(top_re(cur), top_im(cur), 2 * np, c->htr, c->hti, top_re(o),
+                                    top_im(o), lr, li, d.real(), d.imag(), 2.0, 0, np, s));
+    } else {  // l = 1: Pbar_1 only; P_0 = X_{k-1} from the segment store
+      FQ_HIP(c, fq::launch_adj_step(bot_re(cur), bot_im(cur), np, c->htr, c->hti, top_re(o),
+                                    top_im(o), lr, li, d.real(), d.imag(), 2.0, np, np, s));
+      FQ_TRY(copy2(top_re(o), top_im(o), seg_x));
+    }
+    cur = o;
+  }
+  if (L == 1) {  // stack 0 = [P_0; Pbar_1]
+    FQ_TRY(copy2(top_re(0), top_im(0), seg_x));
+    cur = 0;
+  }
+  // l = 0: <Pbar_1, D P_0>, then Pbar_0 = Ht Pbar_1 - Pbar_2 + d_0 Lambda
+  const int o = 1 - cur;
+  FQ_TRY(dot(cur, 1.0));
+  d = D(0);
+  FQ_HIP(c, fq::launch_adj_step(bot_re(cur), bot_im(cur), np, c->htr, c->hti, top_re(o), top_im(o),
+                                lr, li, d.real(), d.imag(), 1.0, np, np, s));
+  FQ_HIP(c, hipMemcpyAsync(lr, bot_re(o), pbytes, hipMemcpyDeviceToDevice, s));
+  FQ_HIP(c, hipMemcpyAsync(li, bot_im(o), pbytes, hipMemcpyDeviceToDevice, s));
+  return FQ_OK;
+}
+
+fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
+  const int M = c->M, s = c->ckpt;
+  const long plane = c->np * c->np;
+  const size_t p2bytes = 2 * sizeof(double) * (size_t)plane;
+  FQ_HIP(c, fq::launch_pack_planar_t(U_bar, c->n, c->n, c->n, c->lam, c->lam + plane, c->np,
+                                     c->np, c->stream));
+  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
+  bool any_b = false;
+  for (int k = 0; k < M; ++k) any_b = any_b || (c->b[k] != 0.0);
+  const int nseg = (M + s - 1) / s;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int k0 = sg * s, k1 = std::min(M, k0 + s);
+    // regenerate the segment forward in FP64 from its checkpoint
+    FQ_HIP(c, hipMemcpyAsync(c->xr, c->tape + (size_t)sg * 2 * plane, p2bytes,
+                             hipMemcpyDeviceToDevice, c->stream));
+    for (int k = k0; k < k1; ++k) {
+      double* slot = c->seg + (size_t)(k - k0) * 6 * plane;
+      FQ_HIP(c, hipMemcpyAsync(slot, c->xr, p2bytes, hipMemcpyDeviceToDevice, c->stream));
+      c->save_plm1 = slot + 2 * plane;
+      c->save_pl = slot + 4 * plane;
+      FQ_TRY(dense_heff(c, k));
+      FQ_TRY(dense_cheb_step(c, (int)c->np));
+      c->save_pl = c->save_plm1 = nullptr;
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      FQ_TRY(dense_heff(c, k));
+      FQ_TRY(adjoint_step(c, k, k - k0, any_b));
+    }
+  }
+  std::vector<double> g(2 * (size_t)M);
+  FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  FQ_HIP(c, hipStreamSynchronize(c->stream));
+  const double w = std::sqrt(3.0) * c->h / 12.0;
+  for (int k = 0; k < M; ++k) {
+    const double ga = g[2 * k] / c->dE, gb = g[2 * k + 1] / c->dE;
+    grad_f_nodes[2 * k] = 0.5 * ga + w * gb;
+    grad_f_nodes[2 * k + 1] = 0.5 * ga - w * gb;
+  }
   return FQ_OK;
 }
 
@@ -618,8 +760,8 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->xi = c->xr + plane;
   if (sys->layout == FQ_DENSE) {
     c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;
-    c->vr = P(lay.off_v);   c->vi = c->vr + plane;
-    c->kr = P(lay.off_k);   c->ki = c->kr + plane;
+    c->vr = P(lay.off_v);   c->kr = c->vr + plane;   // re(Hmod), re(K),
+    c->vi = c->vr + 2 * plane; c->ki = c->vr + 3 * plane;  // im(Hmod), im(K)
     c->htr = P(lay.off_ht); c->hti = c->htr + plane;
     c->yr = P(lay.off_y);   c->yi = c->yr + plane;
     c->par = P(lay.off_pa); c->pai = c->par + plane;
@@ -628,6 +770,11 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     if (lay.n_tape > 0) {
       c->tape = P(lay.off_tape);
       c->n_tape = lay.n_tape;
+      c->seg = P(lay.off_seg);
+      c->stack[0] = P(lay.off_stack);
+      c->stack[1] = c->stack[0] + 4 * plane;
+      c->lam = P(lay.off_lam);
+      c->d_grad = P(lay.off_grad);
     }
   }
 
@@ -792,9 +939,26 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
 
 fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   if (!c || !U_bar || !grad_f_nodes) return fail(FQ_ERR_ARG, "null argument");
+  if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (c->ckpt <= 0) return fail(FQ_ERR_STATE, "context was created without a gradient tape");
   if (!c->tape_valid) return fail(FQ_ERR_STATE, "no tape: call floquet_build_UT first");
-  return fail(FQ_ERR_UNSUPPORTED, "gradient not available in this build");
+  if (c->layout != FQ_DENSE) return fail(FQ_ERR_UNSUPPORTED, "gradient needs the dense layout");
+  // The reverse sweep and the segment recomputation run in FP64 whatever the
+  // build precision: they differentiate the FP64 Chebyshev map.
+  struct Restore {
+    fq_ctx* c;
+    int prec;
+    bool prof;
+    ~Restore() {
+      c->precision = prec;
+      c->profile = prof;
+      c->save_pl = c->save_plm1 = nullptr;
+    }
+  } restore{c, c->precision, c->profile};
+  c->precision = FQ_FP64;
+  c->profile = false;
+  fq_status st = adjoint(c, U_bar, grad_f_nodes);
+  return st;
 }
 
 }  // extern "C"

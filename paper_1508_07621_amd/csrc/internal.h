@@ -47,7 +47,24 @@ struct ChebTerm {
   double* o_im;
   double c0r, c0i, cr, ci;  // coefficients (c0 only for the first product)
   double phr, phi;          // exp(-i beta h)
+  double* save_re;          // optional: the last product also stores P_L here
+  double* save_im;
 };
+
+// ---- adjoint products (kernels_dense.hip) ---------------------------------------------------
+// Reverse term on a stack (rows [0, np) = P_l, [np, 2np) = Pbar_{l+1}) of mrows
+// rows starting at A: P_{l-1} = 2 Ht P_l - P_{l+1} and
+// Pbar_l = fac Ht Pbar_{l+1} - Pbar_{l+2} + d Lambda, in place over the output
+// stack (P_{l+1} over Pbar_{l+2}); row_off = np when A holds only the adjoint half.
+hipError_t launch_adj_step(const double* ar, const double* ai, int mrows, const double* htr,
+                           const double* hti, double* sr, double* si, const double* lr,
+                           const double* li, double dr, double di, double fac, int row_off, int np,
+                           hipStream_t s);
+// out[0] += w Re <Pbar, Hmod P>, out[1] += w Re <Pbar, K P> (ncols = 2np; np: Hmod only),
+// with B = the planes [Hmod; K] stacked as 2np rows.
+hipError_t launch_adj_dot(const double* pr, const double* pi, const double* dr, const double* di,
+                          int ncols, const double* pbr, const double* pbi, double w, double* out,
+                          int np, hipStream_t s);
 
 // Launch one Chebyshev product over rows [0, mrows) of the state-major
 // operands (mrows, np multiples of the tile size chosen by the launcher).
@@ -117,6 +134,9 @@ hipError_t launch_heff_f64(const double* h0r, const double* h0i, const double* v
                            const double* vi, const double* kr, const double* ki, double a,
                            double b, double beta, double dE, long n, long ld, double* hr,
                            double* hi, hipStream_t s);
+// t = d * s elementwise on count planar complex elements.
+hipError_t launch_scale_planar(const double* sr, const double* si, double dr, double di,
+                               double* tr, double* ti, long count, hipStream_t s);
 // y = A x for a dense complex128 row-major matrix (n x n) and vectors x, y (complex128).
 hipError_t launch_zgemv(const void* A, long n, const void* x, void* y, hipStream_t s);
 
@@ -170,6 +190,13 @@ struct fq_ctx {
   void* htx = nullptr;                // mixed builds: rescaled H in the product format
   double* tape = nullptr;             // checkpoints, each 2 planes
   int n_tape = 0;
+  // gradient: per segment step X_{k-1}, P_{L-1}, P_L; two stacks; Lambda; d/da, d/db per step
+  double* seg = nullptr;
+  double* stack[2] = {nullptr, nullptr};
+  double* lam = nullptr;
+  double* d_grad = nullptr;
+  double* save_pl = nullptr;          // when set, a step also stores P_L and P_{L-1} here
+  double* save_plm1 = nullptr;
   double* small = nullptr;            // 64 doubles of reduction scratch
   double* d_ab = nullptr;             // 2*M
   double* d_coef = nullptr;           // 2*(L+1)

@@ -181,6 +181,10 @@ struct EpiCheb {
       t.y_im[idx] = t.c0r * xi + t.c0i * xr + t.cr * ai + t.ci * ar;
     } else if (KIND == CHEB_FIRST_LAST) {
       const double xr = t.p_re[idx], xi = t.p_im[idx];
+      if (t.save_re) {
+        t.save_re[idx] = ar;
+        t.save_im[idx] = ai;
+      }
       const double sr = t.c0r * xr - t.c0i * xi + t.cr * ar - t.ci * ai;
       const double si = t.c0r * xi + t.c0i * xr + t.cr * ai + t.ci * ar;
       t.o_re[idx] = t.phr * sr - t.phi * si;
@@ -193,6 +197,10 @@ struct EpiCheb {
       t.y_im[idx] += t.cr * pi + t.ci * pr;
     } else {  // CHEB_LAST
       const double pr = 2.0 * ar - t.p_re[idx], pi = 2.0 * ai - t.p_im[idx];
+      if (t.save_re) {
+        t.save_re[idx] = pr;
+        t.save_im[idx] = pi;
+      }
       const double sr = t.y_re[idx] + t.cr * pr - t.ci * pi;
       const double si = t.y_im[idx] + t.cr * pi + t.ci * pr;
       t.o_re[idx] = t.phr * sr - t.phi * si;
@@ -242,6 +250,71 @@ struct EpiUnitarity {
     if ((threadIdx.x & 63) == 0) {
       atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(sqrt(mx)));
       atomicAdd(out + 1, ss);
+    }
+  }
+};
+
+// ---- adjoint epilogues -----------------------------------------------------------------------
+// A "stack" holds two state-major blocks as one 2np-row operand: rows [0, np)
+// the forward term P_l, rows [np, 2np) the adjoint term Pbar_{l+1}.
+
+// One reverse term: with acc = Ht * (A rows), in place over the output stack
+// (which holds P_{l+1} over Pbar_{l+2}):
+//   rows < np:   P_{l-1} = 2 acc - P_{l+1}                    (backward recurrence)
+//   rows >= np:  Pbar_l  = fac acc - Pbar_{l+2} + d * Lambda  (adjoint recurrence)
+struct EpiAdjStep {
+  double* sr;  // output stack planes (2np x np each)
+  double* si;
+  const double* lr;  // Lambda (np x np)
+  const double* li;
+  double dr, di;  // d = conj(phase c_l)
+  double fac;     // 2, or 1 for l = 0
+  long ld;        // np
+  int row_off;    // 0, or np when only the adjoint half is launched
+  __device__ __forceinline__ void operator()(int m, int n, double ar, double ai) const {
+    const long mg = (long)m + row_off;
+    const long idx = mg * ld + n;
+    if (mg < ld) {
+      sr[idx] = 2.0 * ar - sr[idx];
+      si[idx] = 2.0 * ai - si[idx];
+    } else {
+      const long li_ = (mg - ld) * ld + n;
+      const double xr = lr[li_], xi = li[li_];
+      sr[idx] = fac * ar - sr[idx] + dr * xr - di * xi;
+      si[idx] = fac * ai - si[idx] + dr * xi + di * xr;
+    }
+  }
+  __device__ __forceinline__ void finish() const {}
+};
+
+// Gradient contraction of one term: acc(j, i) = (D P_l)(i', j) with D = Hmod
+// for i < np and D = K for i >= np (i' = i mod np); accumulates
+// w Re <Pbar_{l+1}, D P_l> into out[0] (Hmod) and out[1] (K).
+struct EpiAdjDot {
+  const double* pbr;  // Pbar_{l+1} (np x np)
+  const double* pbi;
+  double* out;
+  long ld;
+  double w;
+  double sa = 0.0, sb = 0.0;
+  __device__ __forceinline__ void operator()(int m, int n, double ar, double ai) {
+    const bool k_part = n >= ld;
+    const long idx = (long)m * ld + (k_part ? n - ld : n);
+    const double v = pbr[idx] * ar + pbi[idx] * ai;  // Re(conj(pbar) * acc)
+    if (k_part)
+      sb += v;
+    else
+      sa += v;
+  }
+  __device__ void finish() {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      sa += __shfl_xor(sa, o);
+      sb += __shfl_xor(sb, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(out, w * sa);
+      atomicAdd(out + 1, w * sb);
     }
   }
 };
@@ -380,6 +453,18 @@ __global__ void identity_rows_kernel(double* __restrict__ re, double* __restrict
   }
 }
 
+// dst = d * src on count elements of planar complex arrays.
+__global__ void scale_planar_kernel(const double* __restrict__ sr, const double* __restrict__ si,
+                                    double dr, double di, double* __restrict__ tr,
+                                    double* __restrict__ ti, long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x) {
+    const double xr = sr[e], xi = si[e];
+    tr[e] = dr * xr - di * xi;
+    ti[e] = dr * xi + di * xr;
+  }
+}
+
 __global__ void zgemv_kernel(const double2* __restrict__ A, long n, const double2* __restrict__ x,
                              double2* __restrict__ y) {
   __shared__ double sr[256], si[256];
@@ -425,6 +510,23 @@ hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s) 
       return launch_gemm<false, false>(op, mrows, np, EpiCheb<CHEB_LAST>{t, np}, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_step(const double* ar, const double* ai, int mrows, const double* htr,
+                           const double* hti, double* sr, double* si, const double* lr,
+                           const double* li, double dr, double di, double fac, int row_off, int np,
+                           hipStream_t s) {
+  Operands op{ar, ai, htr, hti, np, np, 0, 0};
+  EpiAdjStep e{sr, si, lr, li, dr, di, fac, np, row_off};
+  return launch_gemm<false, false>(op, mrows, np, e, s);
+}
+
+hipError_t launch_adj_dot(const double* pr, const double* pi, const double* dr_, const double* di_,
+                          int ncols, const double* pbr, const double* pbi, double w, double* out,
+                          int np, hipStream_t s) {
+  Operands op{pr, pi, dr_, di_, np, np, 0, 0};
+  EpiAdjDot e{pbr, pbi, out, np, w};
+  return launch_gemm<false, false>(op, np, ncols, e, s);
 }
 
 hipError_t launch_cheb_first_mixed(const ChebTermX& t, const double* b64_re, const double* b64_im,
@@ -494,6 +596,13 @@ hipError_t launch_heff_f64(const double* h0r, const double* h0i, const double* v
                            double* hi, hipStream_t s) {
   hipLaunchKernelGGL(heff_kernel, dim3(grid_for(n * ld, 256)), dim3(256), 0, s, h0r, h0i, vr, vi,
                      kr, ki, a, b, beta, 1.0 / dE, n, ld, hr, hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_planar(const double* sr, const double* si, double dr, double di,
+                               double* tr, double* ti, long count, hipStream_t s) {
+  hipLaunchKernelGGL(scale_planar_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, sr, si, dr,
+                     di, tr, ti, count);
   return hipGetLastError();
 }
 

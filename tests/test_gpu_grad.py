@@ -1,0 +1,160 @@
+"""Adjoint gradient (floquet_grad) against the oracle and finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from workloads import drive_cos, gue, haar_unitary, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fl(require_gpu):
+    from paper_1508_07621_amd import floquet
+    floquet.node_times(1.0, 1)
+    return floquet
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _trace_loss_and_bar(U, W):
+    """loss = 1 - |Tr(W^dagger U)|^2 / N^2 and Ubar = dL/dRe U + i dL/dIm U."""
+    n = U.shape[0]
+    tau = np.vdot(W, U)
+    return 1.0 - abs(tau) ** 2 / n ** 2, -(2.0 / n ** 2) * tau * W
+
+
+def _problem(n, M, seed):
+    rng = np.random.default_rng(seed)
+    H0, V = gue(n, rng), gue(n, rng)
+    f = rng.uniform(-1, 1, M)
+    W = haar_unitary(n, rng)
+    return H0, V, f, W
+
+
+@pytest.mark.parametrize("n,M,ckpt,precision,tol", [(48, 24, 5, "fp64", 1e-9), (64, 20, 16, "fp64", 1e-9),
+                                                    (130, 12, 4, "fp64", 1e-9), (64, 20, 8, "fp32", 1e-5),
+                                                    (64, 20, 8, "bf16x3", 1e-5)])
+def test_piecewise_gradient_matches_oracle(fl, n, M, ckpt, precision, tol):
+    """Piecewise-constant drive: the oracle's exact (Daleckii-Krein) derivative
+    of the Chebyshev chain with the same interval and order."""
+    _say("grad piecewise", n, M, ckpt, precision)
+    H0, V, f, W = _problem(n, M, 40 + n)
+    T = 2.0
+    lo, hi = orc.weyl_cover(H0, V, np.zeros_like(H0), f, np.zeros(M))
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-13)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=np.stack([f, f], 1), e_min=lo,
+                            e_max=hi, L=L, precision=precision, checkpoint_every=ckpt)
+    U = ctx.build_ut().cpu().numpy()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar)
+    g_f = g.sum(axis=1)
+    ref = orc.grad_piecewise(H0, V, f, T, W, route="cheb", e_min=lo, e_max=hi, L=L)
+    err = np.max(np.abs(g_f - ref)) / np.max(np.abs(ref))
+    _say("rel err", err, "max|g|", np.max(np.abs(ref)))
+    assert err < tol
+
+
+def test_smooth_drive_gradient_matches_oracle_differences(fl):
+    """Smooth drive (b_k != 0 exercises the commutator contraction): every
+    node derivative against central differences of the oracle."""
+    n, M = 24, 8
+    rng = np.random.default_rng(77)
+    H0, V = gue(n, rng), gue(n, rng)
+    W = haar_unitary(n, rng)
+    T = 2 * math.pi
+    f = drive_cos(fl.node_times(T, M), 0.2, 1.1, 1.0)
+    lo, hi = -5.0, 5.0
+    L = 30
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
+                            checkpoint_every=3)
+    U = ctx.build_ut().cpu().numpy()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar)
+
+    def loss(ff):
+        Uo = orc.build_ut(H0, V, ff, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+        return _trace_loss_and_bar(Uo, W)[0]
+
+    eps = 1e-5
+    fd = np.zeros_like(f)
+    for k in range(M):
+        for i in range(2):
+            fp, fm = f.copy(), f.copy()
+            fp[k, i] += eps
+            fm[k, i] -= eps
+            fd[k, i] = (loss(fp) - loss(fm)) / (2 * eps)
+    err = np.max(np.abs(g - fd)) / np.max(np.abs(fd))
+    _say("smooth rel err", err)
+    assert err < 1e-6
+    assert np.max(np.abs(g[:, 0] - g[:, 1])) > 1e-6 * np.max(np.abs(g))  # nodes differ
+
+
+def test_autograd_function(fl):
+    import torch
+    n, M = 40, 10
+    H0, V, f, W = _problem(n, M, 5)
+    T = 1.5
+    lo, hi = -5.0, 5.0
+    fn = torch.tensor(np.stack([f, f], 1), dtype=torch.float64, requires_grad=True)
+    U = fl.FloquetUT.apply(fn, h0=H0, hmod=V, T=T, M=M, e_min=lo, e_max=hi, tol=1e-13,
+                           checkpoint_every=4)
+    Wt = torch.from_numpy(W).to(U.device)
+    loss = 1.0 - torch.abs(torch.sum(torch.conj(Wt) * U)) ** 2 / n ** 2
+    loss.backward()
+    g = fn.grad.numpy().sum(axis=1)
+    ref = orc.grad_piecewise(H0, V, f, T, W, route="cheb", e_min=lo, e_max=hi, tol=1e-13)
+    assert np.max(np.abs(g - ref)) / np.max(np.abs(ref)) < 1e-8
+
+
+def test_grad_error_paths(fl):
+    from paper_1508_07621_amd._abi import FQ_ERR_STATE, FloquetError
+    n, M = 32, 4
+    H0, V, f, W = _problem(n, M, 6)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=1.0, M=M, f_nodes=np.stack([f, f], 1), e_min=-5,
+                            e_max=5)
+    with pytest.raises(FloquetError) as e:
+        ctx.grad(np.zeros((n, n), complex))
+    assert e.value.status == FQ_ERR_STATE
+    ctx2 = fl.FloquetContext(h0=H0, hmod=V, T=1.0, M=M, f_nodes=np.stack([f, f], 1), e_min=-5,
+                             e_max=5, checkpoint_every=2)
+    with pytest.raises(FloquetError) as e:
+        ctx2.grad(np.zeros((n, n), complex))   # no build yet
+    assert e.value.status == FQ_ERR_STATE
+
+
+def test_adjoint_config_full_size_against_fd(fl):
+    """The 1024-state adjoint workload: complex64 forward (FP32 products),
+    checkpoint every 16 steps, against central differences (h = 1e-4) of the
+    FP64 forward on 8 seeded amplitudes."""
+    wl = workload("adjoint1024")
+    H0, V, W, f = wl.arrays["h0"], wl.arrays["v"], wl.arrays["w"], wl.amplitudes
+    T, M, n = wl.T, wl.M, wl.n
+    lo, hi = orc.weyl_cover(np.diag(np.linalg.eigvalsh(H0)), np.diag(np.linalg.eigvalsh(V)),
+                            np.zeros((1, 1)), f, np.zeros(M))
+    _say("adjoint1024", n, M, lo, hi)
+    nodes = np.stack([f, f], 1)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=nodes, e_min=lo, e_max=hi, tol=1e-12,
+                            precision="fp32", checkpoint_every=16)
+    U = ctx.build_ut().cpu().numpy()
+    L = ctx.report["L"]
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar).sum(axis=1)
+    ref_ctx_kw = dict(h0=H0, hmod=V, T=T, M=M, e_min=lo, e_max=hi, L=L)
+    rng = np.random.default_rng(1508 + 30)
+    ks = rng.choice(M, size=8, replace=False)
+    eps = 1e-4
+    for k in ks:
+        vals = []
+        for sgn in (+1, -1):
+            ff = f.copy()
+            ff[k] += sgn * eps
+            Uf = fl.FloquetContext(f_nodes=np.stack([ff, ff], 1), **ref_ctx_kw).build_ut().cpu().numpy()
+            vals.append(_trace_loss_and_bar(Uf, W)[0])
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        _say("k", k, "adjoint", g[k], "fd", fd)
+        assert abs(g[k] - fd) <= 1e-3 * abs(fd) + 1e-9
