@@ -57,7 +57,7 @@ struct Layout {
   size_t total = 0;
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
          off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
-         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0;
+         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -97,6 +97,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.np = pad_to(n, dense_tile(n));
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
     lay.off_x = take(plane2);  // planar copy of U_T for the unitarity check
+    lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)par->M);
   }
   lay.off_small = take(64 * sizeof(double));
   lay.off_ab = take(2 * sizeof(double) * (size_t)par->M);
@@ -309,6 +310,12 @@ fq_status tridiag_cover(fq_ctx* ctx, double* lo_out, double* hi_out) {
   }
   *lo_out = lo;
   *hi_out = hi;
+  // gauge factors of every step, for the kernel's real-symmetric form of Ht_s
+  std::vector<double> wtab(2 * (size_t)n * ctx->M);
+  for (int k = 0; k < ctx->M; ++k)
+    fq::tridiag_gauge(n, off.data(), v.data(), ctx->b[k], wtab.data() + 2 * (size_t)n * k);
+  FQ_HIP(ctx, hipMemcpy(ctx->d_gauge, wtab.data(), wtab.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
   return FQ_OK;
 }
 
@@ -519,6 +526,7 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.v_diag = c->sys.hmod_diag;
   job.ab = c->d_ab;
   job.coef = c->d_coef;
+  job.gauge = c->d_gauge;
   job.L = c->L;
   job.k0 = k0;
   job.k1 = k1;
@@ -757,6 +765,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->d_ab = P(lay.off_ab);
   c->d_coef = P(lay.off_coef);
   c->xr = P(lay.off_x);
+  if (sys->layout == FQ_TRIDIAG) c->d_gauge = P(lay.off_gauge);
   c->xi = c->xr + plane;
   if (sys->layout == FQ_DENSE) {
     c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;

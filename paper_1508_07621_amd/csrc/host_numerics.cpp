@@ -133,4 +133,34 @@ void tridiag_extremes(long n, const double* d, const double* e_abs, double* lo_o
   *hi_out = hi.second;  // count(a) < n <= count(b): lambda_max in [a, b)
 }
 
+// A Hermitian tridiagonal matrix with couplings e_i = H[i][i+1] is unitarily
+// similar, through D = diag(w), to the real one with couplings |e_i|:
+// (D^+ H D)[i][i+1] = conj(w_i) e_i w_{i+1} = |e_i| when w_{i+1} = w_i conj(e_i) / |e_i|.
+// The prefix product runs sequentially in 80-bit arithmetic and every factor
+// is renormalised, so each ratio w_{i+1} / w_i matches conj(e_i / |e_i|) to
+// one rounding however long the chain. For the Magnus-4 step operator
+// e_i = h_i (1 - i b (v_{i+1} - v_i)) (the 1/dE scale does not change phases).
+void tridiag_gauge(long n, const double* h0_off, const double* v_diag, double b, double* w_out) {
+  long double wr = 1.0L, wi = 0.0L;
+  w_out[0] = 1.0;
+  w_out[1] = 0.0;
+  for (long i = 0; i + 1 < n; ++i) {
+    const long double hr = h0_off[2 * i], hi = h0_off[2 * i + 1];
+    const long double q = (long double)b * ((long double)v_diag[i + 1] - v_diag[i]);
+    const long double er = hr + hi * q, ei = hi - hr * q;  // h (1 - i q)
+    const long double m = sqrtl(er * er + ei * ei);
+    long double ur = 1.0L, ui = 0.0L;
+    if (m > 0.0L) {
+      ur = er / m;
+      ui = ei / m;
+    }
+    const long double nr = wr * ur + wi * ui, ni = wi * ur - wr * ui;  // w conj(u)
+    const long double nm = sqrtl(nr * nr + ni * ni);
+    wr = nr / nm;
+    wi = ni / nm;
+    w_out[2 * (i + 1)] = (double)wr;
+    w_out[2 * (i + 1) + 1] = (double)wi;
+  }
+}
+
 }  // namespace fq

@@ -149,6 +149,7 @@ struct TridiagJob {
   const double* v_diag;  // device
   const double* ab;      // device, 2*M: a_k, b_k interleaved, for the steps in use
   const double* coef;    // device, 2*(L+1): c_l complex interleaved
+  const double* gauge;   // device, M x n complex: w[s][i], D_s = diag(w[s]) makes D_s^+ Ht_s D_s real
   int L;
   int k0, k1;            // steps k0+1 .. k1
   double beta, inv_dE, phr, phi;
@@ -160,6 +161,10 @@ struct TridiagJob {
 // Returns hipErrorInvalidValue when n exceeds what one workgroup can hold.
 hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
 long tridiag_resident_max_n();
+
+// Unit gauge factors of step s (host FP64): w_0 = 1, w_{i+1} = w_i conj(u_i) with
+// u_i = e_i / |e_i| the phase of Ht[i][i+1] (u_i = 1 where e_i = 0).
+void tridiag_gauge(long n, const double* h0_off, const double* v_diag, double b, double* w_out);
 
 }  // namespace fq
 
@@ -200,6 +205,7 @@ struct fq_ctx {
   double* small = nullptr;            // 64 doubles of reduction scratch
   double* d_ab = nullptr;             // 2*M
   double* d_coef = nullptr;           // 2*(L+1)
+  double* d_gauge = nullptr;          // tridiagonal: M x n complex gauge factors
   // state
   bool tape_valid = false;
   bool broken = false;

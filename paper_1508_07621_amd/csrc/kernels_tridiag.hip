@@ -1,13 +1,18 @@
 // Tridiagonal operators (the Bose-Hubbard dimer of Sec. 4 in its Fock basis):
 // the whole chain of single-step propagators for one state column runs inside
-// one workgroup, with the column's rows spread over lanes (R consecutive rows
-// per lane, G waves). The previous and current Chebyshev terms and the running
-// sum live in registers for all M steps and all L terms; each term exchanges
-// one boundary row with each neighbouring lane (cross-lane shuffle) and, at
-// wave boundaries, through LDS. The per-step rescaled Hamiltonian is formed in
-// registers from H0, Hmod and the step scalars (a_k, b_k), so device memory is
-// touched only to read the operator diagonals once per step and to write the
-// final column.
+// one workgroup, with every term of every step held in registers.
+//
+// Step s uses Ht_s = D_s G_s D_s^+ with D_s = diag(w_s) unit gauge factors and
+// G_s real symmetric tridiagonal (diagonal d_i, couplings g_i = |Ht_s[i][i+1]|),
+// so the Chebyshev polynomial of Ht_s is D_s p(G_s) D_s^+. A real G_s acts on
+// the real and imaginary parts of a state independently: one group of waves
+// runs the recurrence P_{l+1} = 2 G P_l - P_{l-1} on the real part, another on
+// the imaginary part, each lane holding R consecutive rows of P_{l-1}, P_l and
+// of its share of the Chebyshev sum. Neighbour rows come from adjacent lanes by
+// shuffles (and across waves through LDS when a part spans several waves).
+// The two halves of the sum meet in LDS once per step, where the step phase
+// and the change of gauge D_{s+1}^+ D_s are applied. The rows of G_s are
+// formed in registers from H0, Hmod and the step scalars (a_s, b_s).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -15,198 +20,219 @@
 namespace fq {
 namespace {
 
-constexpr int kMaxWaves = 16;
+constexpr int kMaxWaves = 8;  // waves per part
 
-template <int R>
-__global__ __launch_bounds__(512) void tridiag_resident_kernel(TridiagJob job) {
-  const int G = blockDim.x >> 6;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// Whole-wave DPP shifts by one lane; the lane without a source gets +0.0.
+__device__ __forceinline__ double from_prev_lane(double v) {  // lane l <- lane l-1
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_next_lane(double v) {  // lane l <- lane l+1
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int R, int MAXT, bool MULTI>
+__global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int G) {
+  extern __shared__ double ysh[];  // [part][lane in part][r][2]
+  __shared__ double halo[2][2][2][kMaxWaves];  // [parity][part][0 first row, 1 last row][wave]
+
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int part = wid / G, w = wid % G;
+  const int pl = w * 64 + lane;  // lane index within its part
   const long col = blockIdx.x;
   const long n = job.n;
-  const long base = ((long)w * 64 + lane) * R;
-
-  __shared__ double2 halo[2][2][kMaxWaves];  // [parity][0: first row of wave, 1: last row][wave]
-
-  double xr[R], xi[R];      // X (state at the step boundary)
-  double pr[R], pi_[R];     // P_{l-1}
-  double cr[R], ci[R];      // P_l
-  double yr[R], yi[R];      // running Chebyshev sum
-  double d[R], er[R], ei[R];  // rows of the rescaled Hamiltonian: diag, H[i][i+1]
-  double emr = 0.0, emi = 0.0;  // H[base-1][base]
-
-  const double2* x0 = reinterpret_cast<const double2*>(job.x0);
+  const long base = (long)pl * R;
+  const double sgn = part == 0 ? 1.0 : -1.0;
+  const double2* gauge = reinterpret_cast<const double2*>(job.gauge);
+  const double2* coef = reinterpret_cast<const double2*>(job.coef);
   const double2* h0o = reinterpret_cast<const double2*>(job.h0_off);
+
+  double pa[R], pb[R];  // the two most recent terms (roles alternate)
+  double ys[R], yo[R];  // share of the sum: ys -> this part's component, yo -> the other one
+  double d2[R], g2[R];  // 2 G: diagonal, coupling to the next row
+  double gm2 = 0.0;     // 2 G coupling of row base-1 to row base
+
+  // X~ = D_{k0}^+ X, this part's component
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const long i = base + r;
-    double vr = 0.0, vi = 0.0;
+    double v = 0.0;
     if (i < n) {
-      if (x0) {
-        const double2 v = x0[i * job.ld_x0 + col];
-        vr = v.x;
-        vi = v.y;
+      double xr, xi;
+      if (job.x0) {
+        const double2 x = reinterpret_cast<const double2*>(job.x0)[i * job.ld_x0 + col];
+        xr = x.x;
+        xi = x.y;
       } else {
-        vr = (i == col) ? 1.0 : 0.0;
+        xr = (i == col) ? 1.0 : 0.0;
+        xi = 0.0;
       }
+      const double2 g = gauge[(long)job.k0 * n + i];
+      v = part == 0 ? g.x * xr + g.y * xi : g.x * xi - g.y * xr;  // conj(w) x
     }
-    xr[r] = vr;
-    xi[r] = vi;
+    pa[r] = v;
   }
 
-  // (Ht v) for the rows of this lane, given the neighbour values v[base-1], v[base+R].
-  auto apply = [&](const double* vr, const double* vi, double upr, double upi, double dnr,
-                   double dni, double* tr, double* ti) {
+  int parity = 0;
+  auto neighbours = [&](const double* v, double& up, double& dn) {
+    up = from_prev_lane(v[R - 1]);
+    dn = from_next_lane(v[0]);
+    if constexpr (MULTI) {  // wave ends exchange through LDS
+      if (lane == 0) halo[parity][part][0][w] = v[0];
+      if (lane == 63) halo[parity][part][1][w] = v[R - 1];
+      __syncthreads();
+      const double hu = (w > 0) ? halo[parity][part][1][w - 1] : 0.0;
+      const double hd = (w + 1 < G) ? halo[parity][part][0][w + 1] : 0.0;
+      up = (lane == 0) ? hu : up;
+      dn = (lane == 63) ? hd : dn;
+      parity ^= 1;
+    }
+  };
+  // nw = 2 G v - nw (in place over the older term)
+  auto advance = [&](const double* v, double* nw) {
+    double up, dn;
+    neighbours(v, up, dn);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const double lr = (r == 0) ? upr : vr[r - 1], li = (r == 0) ? upi : vi[r - 1];
-      const double hr = (r == R - 1) ? dnr : vr[r + 1], hi = (r == R - 1) ? dni : vi[r + 1];
-      const double cer = (r == 0) ? emr : er[r - 1], cei = (r == 0) ? emi : ei[r - 1];
-      // conj(e_{i-1}) v_{i-1} + d_i v_i + e_i v_{i+1}
-      double sr = d[r] * vr[r], si = d[r] * vi[r];
-      sr = fma(cer, lr, sr);
-      sr = fma(cei, li, sr);
-      si = fma(cer, li, si);
-      si = fma(-cei, lr, si);
-      sr = fma(er[r], hr, sr);
-      sr = fma(-ei[r], hi, sr);
-      si = fma(er[r], hi, si);
-      si = fma(ei[r], hr, si);
-      tr[r] = sr;
-      ti[r] = si;
+      const double lo = (r == 0) ? up : v[r - 1];
+      const double hi = (r == R - 1) ? dn : v[r + 1];
+      double t = fma(d2[r], v[r], -nw[r]);
+      t = fma((r == 0) ? gm2 : g2[r - 1], lo, t);
+      nw[r] = fma(g2[r], hi, t);
     }
   };
-
-  // Neighbour rows of v: from the adjacent lanes, or across waves through LDS.
-  int parity = 0;
-  auto exchange = [&](const double* vr, const double* vi, double& upr, double& upi, double& dnr,
-                      double& dni) {
-    if (G > 1) {
-      if (lane == 0) halo[parity][0][w] = make_double2(vr[0], vi[0]);
-      if (lane == 63) halo[parity][1][w] = make_double2(vr[R - 1], vi[R - 1]);
-      __syncthreads();
-    }
-    upr = __shfl_up(vr[R - 1], 1);
-    upi = __shfl_up(vi[R - 1], 1);
-    dnr = __shfl_down(vr[0], 1);
-    dni = __shfl_down(vi[0], 1);
-    if (lane == 0) {
-      if (w > 0) {
-        const double2 t = halo[parity][1][w - 1];
-        upr = t.x;
-        upi = t.y;
-      } else {
-        upr = upi = 0.0;
-      }
-    }
-    if (lane == 63) {
-      if (w + 1 < G) {
-        const double2 t = halo[parity][0][w + 1];
-        dnr = t.x;
-        dni = t.y;
-      } else {
-        dnr = dni = 0.0;
-      }
-    }
-    parity ^= 1;
+  // c_l P_l into the sum: even l has real c_l (this component), odd l imaginary
+  auto acc_even = [&](const double* p, double c) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) ys[r] = fma(c, p[r], ys[r]);
+  };
+  auto acc_odd = [&](const double* p, double c) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) yo[r] = fma(c, p[r], yo[r]);
   };
 
-  const double2* coef = reinterpret_cast<const double2*>(job.coef);
   const int L = job.L;
-
-  for (int k = job.k0; k < job.k1; ++k) {
-    const double a = job.ab[2 * k], b = job.ab[2 * k + 1];
-    // Rows of Ht = (H0 + a Hmod + b K - beta) / dE, K = -i [H0, Hmod]:
-    // Ht[i][i] = (h0_ii + a v_i - beta) / dE,
-    // Ht[i][i+1] = h0_{i,i+1} (1 - i b (v_{i+1} - v_i)) / dE.
+  for (int s = job.k0; s < job.k1; ++s) {
+    const double a = job.ab[2 * s], b = job.ab[2 * s + 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const long i = base + r;
-      d[r] = 0.0;
-      er[r] = 0.0;
-      ei[r] = 0.0;
+      d2[r] = 0.0;
+      g2[r] = 0.0;
       if (i < n) {
-        const double vi_ = job.v_diag[i];
-        d[r] = (job.h0_diag[i] + a * vi_ - job.beta) * job.inv_dE;
+        const double vi = job.v_diag[i];
+        d2[r] = 2.0 * (job.h0_diag[i] + a * vi - job.beta) * job.inv_dE;
         if (i + 1 < n) {
           const double2 h = h0o[i];
-          const double bd = b * (job.v_diag[i + 1] - vi_);
-          er[r] = (h.x + h.y * bd) * job.inv_dE;
-          ei[r] = (h.y - h.x * bd) * job.inv_dE;
+          const double q = b * (job.v_diag[i + 1] - vi);
+          g2[r] = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
         }
       }
     }
-    emr = emi = 0.0;
-    if (base >= 1 && base - 1 + 1 < n) {
-      const long i = base - 1;
-      const double2 h = h0o[i];
-      const double bd = b * (job.v_diag[i + 1] - job.v_diag[i]);
-      emr = (h.x + h.y * bd) * job.inv_dE;
-      emi = (h.y - h.x * bd) * job.inv_dE;
+    gm2 = 0.0;
+    if (base >= 1 && base < n) {
+      const double2 h = h0o[base - 1];
+      const double q = b * (job.v_diag[base] - job.v_diag[base - 1]);
+      gm2 = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
     }
 
-    // l = 0, 1: P_0 = X, P_1 = Ht X, Y = c_0 P_0 + c_1 P_1
-    double upr, upi, dnr, dni;
-    exchange(xr, xi, upr, upi, dnr, dni);
-    apply(xr, xi, upr, upi, dnr, dni, cr, ci);
+    // l = 0, 1: P_0 = X~ (in pa), P_1 = G X~ (into pb)
     {
-      const double2 c0 = coef[0], c1 = coef[1];
+      const double c0 = coef[0].x, c1 = sgn * coef[1].y;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        pr[r] = xr[r];
-        pi_[r] = xi[r];
-        yr[r] = c0.x * xr[r] - c0.y * xi[r] + c1.x * cr[r] - c1.y * ci[r];
-        yi[r] = c0.x * xi[r] + c0.y * xr[r] + c1.x * ci[r] + c1.y * cr[r];
+        pb[r] = 0.0;
+        ys[r] = c0 * pa[r];
+        yo[r] = 0.0;
       }
-    }
-    // l = 1 .. L-1: P_{l+1} = 2 Ht P_l - P_{l-1}, Y += c_{l+1} P_{l+1}
-    for (int l = 1; l < L; ++l) {
-      double tr[R], ti[R];
-      exchange(cr, ci, upr, upi, dnr, dni);
-      apply(cr, ci, upr, upi, dnr, dni, tr, ti);
-      const double2 c = coef[l + 1];
+      advance(pa, pb);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double nr = 2.0 * tr[r] - pr[r], ni = 2.0 * ti[r] - pi_[r];
-        pr[r] = cr[r];
-        pi_[r] = ci[r];
-        cr[r] = nr;
-        ci[r] = ni;
-        yr[r] = fma(c.x, nr, fma(-c.y, ni, yr[r]));
-        yi[r] = fma(c.x, ni, fma(c.y, nr, yi[r]));
-      }
+      for (int r = 0; r < R; ++r) pb[r] *= 0.5;
+      acc_odd(pb, c1);
     }
-    // X = exp(-i beta h) Y
+    // l = 2 .. L in pairs: P_{l} over P_{l-2}
+    int l = 2;
+    for (; l + 1 <= L; l += 2) {
+      advance(pb, pa);  // P_l (even) into pa
+      acc_even(pa, coef[l].x);
+      advance(pa, pb);  // P_{l+1} (odd) into pb
+      acc_odd(pb, sgn * coef[l + 1].y);
+    }
+    const bool last_in_a = (l <= L);
+    if (last_in_a) {
+      advance(pb, pa);
+      acc_even(pa, coef[l].x);
+    }
+
+    // both halves of Y meet: X~_next = phase * w_s * conj(w_{s+1}) * Y (or
+    // phase * w_s * Y after the last step); this part keeps its component.
+    const bool final_step = (s + 1 == job.k1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      xr[r] = job.phr * yr[r] - job.phi * yi[r];
-      xi[r] = job.phr * yi[r] + job.phi * yr[r];
+      double* slot = ysh + (((long)part * G * 64 + pl) * R + r) * 2;
+      slot[0] = ys[r];
+      slot[1] = yo[r];
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      const double* other = ysh + (((long)(1 - part) * G * 64 + pl) * R + r) * 2;
+      // component sums: this part's own component and the other component
+      const double own = ys[r] + other[1];
+      const double oth = yo[r] + other[0];
+      const double yr = part == 0 ? own : oth, yi = part == 0 ? oth : own;
+      double v = 0.0;
+      if (i < n) {
+        const double2 ws = gauge[(long)s * n + i];
+        // rot = phase * w_s [* conj(w_{s+1})]
+        double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
+        if (!final_step) {
+          const double2 wn = gauge[(long)(s + 1) * n + i];
+          const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
+          rr = tr;
+          ri = ti;
+        }
+        v = part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
+      }
+      pa[r] = v;
+    }
+    __syncthreads();
   }
 
-  double2* out = reinterpret_cast<double2*>(job.x_out);
+  double* out = reinterpret_cast<double*>(job.x_out);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const long i = base + r;
-    if (i < n) out[i * job.ld_out + col] = make_double2(xr[r], xi[r]);
+    if (i < n) out[2 * (i * job.ld_out + col) + part] = pa[r];
   }
+}
+
+template <int R, int MAXT, bool MULTI>
+hipError_t launch_r(const TridiagJob& job, int G, hipStream_t s) {
+  const size_t shmem = sizeof(double) * 2 * (size_t)G * 64 * R * 2;
+  hipLaunchKernelGGL((tridiag_gauge_kernel<R, MAXT, MULTI>), dim3((unsigned)job.ncols),
+                     dim3(2 * G * 64), shmem, s, job, G);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-long tridiag_resident_max_n() { return 8L * 64 * 8; }
+// 16 rows per lane and up to 4 waves per part (512 threads, <= 256 VGPRs).
+long tridiag_resident_max_n() { return 4L * 64 * 16; }
 
 hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s) {
   if (job.n < 1 || job.ncols < 1) return hipErrorInvalidValue;
-  if (job.n <= 128) {
-    hipLaunchKernelGGL(tridiag_resident_kernel<2>, dim3((unsigned)job.ncols), dim3(64), 0, s, job);
-  } else if (job.n <= tridiag_resident_max_n()) {
-    const int G = (int)((job.n + 511) / 512);
-    hipLaunchKernelGGL(tridiag_resident_kernel<8>, dim3((unsigned)job.ncols), dim3(64 * G), 0, s,
-                       job);
-  } else {
-    return hipErrorInvalidValue;
+  if (job.n <= 256) return launch_r<4, 128, false>(job, 1, s);
+  if (job.n <= 1024) return launch_r<16, 512, false>(job, 1, s);
+  if (job.n <= tridiag_resident_max_n()) {
+    const int G = (int)((job.n + 1023) / 1024);
+    return launch_r<16, 512, true>(job, G, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fq
