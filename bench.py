@@ -280,7 +280,7 @@ def main():
         achieved = flops / (ms_launch * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4),
-                "traffic": None, "kernel": "tridiag_resident_kernel<8> (whole chain per column)",
+                "traffic": None, "kernel": "tridiag_gauge_kernel<16,512> (whole chain per state column, real gauge form)",
                 "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops / s_per_build / 1e12

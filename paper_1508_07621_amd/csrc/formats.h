@@ -45,52 +45,66 @@ __device__ __forceinline__ void split3(float x, u16& h, u16& m, u16& l) {
   l = bf16_bits((__bf16)r2);
 }
 
-__device__ __forceinline__ void load_c(const void* base, int fmt, long plane, long idx, double& re,
-                                       double& im) {
+// BF16X3 matrices are stored k-blocked for the split-BF16 products: plane q
+// (re_hi, re_mid, re_lo, im_hi, im_mid, im_lo) of an np x np matrix holds
+// np/16 slices, one per block of 16 columns k; slice kb holds the np rows in
+// order, 32 bytes per row (columns 16 kb .. 16 kb + 15), so the rows a
+// workgroup stages for one k-block are one contiguous run. Within a row the
+// two 8-column halves are swapped when bit 3 of the row index is set, which
+// makes the 16-byte fragment reads of the 32x32 matrix-core tiles free of LDS
+// bank conflicts. Offset of element (m, k) within plane 0, in 16-bit words:
+__host__ __device__ __forceinline__ long bf3_offset(long m, long k, long np) {
+  const long half = ((k >> 3) & 1) ^ ((m >> 3) & 1);
+  return ((k >> 4) * np + m) * 16 + half * 8 + (k & 7);
+}
+
+// Element (m, n) of planar matrices with row stride ld (plane = ld * ld
+// elements per plane) in the given format.
+__device__ __forceinline__ void load_c(const void* base, int fmt, long plane, long m, long n,
+                                       long ld, double& re, double& im) {
   if (fmt == FMT_F64) {
     const double* p = static_cast<const double*>(base);
-    re = p[idx];
-    im = p[plane + idx];
+    re = p[m * ld + n];
+    im = p[plane + m * ld + n];
   } else if (fmt == FMT_F32) {
     const float* p = static_cast<const float*>(base);
-    re = p[idx];
-    im = p[plane + idx];
+    re = p[m * ld + n];
+    im = p[plane + m * ld + n];
   } else {
-    const u16* p = static_cast<const u16*>(base);
-    re = (double)(bf16_val(p[idx]) + bf16_val(p[plane + idx]) + bf16_val(p[2 * plane + idx]));
-    im = (double)(bf16_val(p[3 * plane + idx]) + bf16_val(p[4 * plane + idx]) +
-                  bf16_val(p[5 * plane + idx]));
+    const u16* p = static_cast<const u16*>(base) + bf3_offset(m, n, ld);
+    re = (double)(bf16_val(p[0]) + bf16_val(p[plane]) + bf16_val(p[2 * plane]));
+    im = (double)(bf16_val(p[3 * plane]) + bf16_val(p[4 * plane]) + bf16_val(p[5 * plane]));
   }
 }
 
 // Store (re, im) in the given format and return in (re, im) the value the
 // storage now holds.
-__device__ __forceinline__ void store_c(void* base, int fmt, long plane, long idx, double& re,
-                                        double& im) {
+__device__ __forceinline__ void store_c(void* base, int fmt, long plane, long m, long n, long ld,
+                                        double& re, double& im) {
   if (fmt == FMT_F64) {
     double* p = static_cast<double*>(base);
-    p[idx] = re;
-    p[plane + idx] = im;
+    p[m * ld + n] = re;
+    p[plane + m * ld + n] = im;
   } else if (fmt == FMT_F32) {
     float* p = static_cast<float*>(base);
     const float r = (float)re, i = (float)im;
-    p[idx] = r;
-    p[plane + idx] = i;
+    p[m * ld + n] = r;
+    p[plane + m * ld + n] = i;
     re = r;
     im = i;
   } else {
-    u16* p = static_cast<u16*>(base);
-    u16 h, m, l;
-    split3((float)re, h, m, l);
-    p[idx] = h;
-    p[plane + idx] = m;
-    p[2 * plane + idx] = l;
-    re = (double)(bf16_val(h) + bf16_val(m) + bf16_val(l));
-    split3((float)im, h, m, l);
-    p[3 * plane + idx] = h;
-    p[4 * plane + idx] = m;
-    p[5 * plane + idx] = l;
-    im = (double)(bf16_val(h) + bf16_val(m) + bf16_val(l));
+    u16* p = static_cast<u16*>(base) + bf3_offset(m, n, ld);
+    u16 h, md, l;
+    split3((float)re, h, md, l);
+    p[0] = h;
+    p[plane] = md;
+    p[2 * plane] = l;
+    re = (double)(bf16_val(h) + bf16_val(md) + bf16_val(l));
+    split3((float)im, h, md, l);
+    p[3 * plane] = h;
+    p[4 * plane] = md;
+    p[5 * plane] = l;
+    im = (double)(bf16_val(h) + bf16_val(md) + bf16_val(l));
   }
 }
 

@@ -333,7 +333,7 @@ struct EpiFirstMixed {
     const double si = t.c0r * xi + t.c0i * xr + t.cr * ai + t.ci * ar;
     if (KIND == CHEB_FIRST) {
       double o_r = ar, o_i = ai;
-      store_c(t.o, t.o_fmt, t.plane, idx, o_r, o_i);
+      store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
       t.y_re[idx] = sr;
       t.y_im[idx] = si;
     } else {  // CHEB_FIRST_LAST

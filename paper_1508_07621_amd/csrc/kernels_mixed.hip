@@ -1,19 +1,19 @@
 // Mixed-precision Chebyshev products for gfx950.
 //
-// FQ_FP32: operands rounded to FP32, products on FP32 matrix cores
-// (v_mfma_f32_16x16x4f32), FP32 accumulation.
+// FQ_FP32: operands rounded to FP32 (planar, row-major), products on FP32
+// matrix cores (v_mfma_f32_16x16x4f32), FP32 accumulation.
 // FQ_BF16X3: every operand element x is split into three BF16 pieces
 // x ~ hi + mid + lo (each piece the rounded remainder of the previous ones,
-// about 24 significant bits in total); a real product keeps the six piece
-// products whose weight is at least 2^-16 of the leading one
-// (hh, hm, mh, hl, mm, lh) on BF16 matrix cores (v_mfma_f32_16x16x32_bf16)
-// with FP32 accumulation.
+// about 24 significant bits in total), stored k-blocked (bf3_offset); a real
+// product keeps the six piece products whose weight is at least 2^-16 of the
+// leading one (hh, hm, mh, hl, mm, lh) on BF16 matrix cores
+// (v_mfma_f32_32x32x16_bf16) with FP32 accumulation.
 //
 // In both, the propagated block X and the Chebyshev sum Y stay FP64: the first
-// product of a step reads X and rounds / splits it while staging it into LDS,
-// the epilogue adds the Bessel-weighted term to Y in FP64, and the last
-// product applies the step phase in FP64. Only the chain P_1 .. P_L is held in
-// the product format.
+// product of a step, P_1 = Ht X, runs on FP64 matrix cores (its term carries
+// the largest weight |c_1| ~ R) and stores P_1 in the product format; the
+// kernels here form P_2 .. P_L, add each Bessel-weighted term to Y in FP64,
+// and the last one applies the step phase in FP64.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -48,20 +48,20 @@ struct EpiMix {
     const long idx = (long)m * ld + n;
     const double ar = ar_, ai = ai_;
     double pr, pi;
-    load_c(t.p, t.p_fmt, t.plane, idx, pr, pi);
+    load_c(t.p, t.p_fmt, t.plane, m, n, ld, pr, pi);
     if (KIND == CHEB_FIRST) {
       double o_r = ar, o_i = ai;
-      store_c(t.o, t.o_fmt, t.plane, idx, o_r, o_i);
+      store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
       t.y_re[idx] = t.c0r * pr - t.c0i * pi + t.cr * o_r - t.ci * o_i;
       t.y_im[idx] = t.c0r * pi + t.c0i * pr + t.cr * o_i + t.ci * o_r;
     } else if (KIND == CHEB_FIRST_LAST) {
       const double sr = t.c0r * pr - t.c0i * pi + t.cr * ar - t.ci * ai;
       const double si = t.c0r * pi + t.c0i * pr + t.cr * ai + t.ci * ar;
       double o_r = t.phr * sr - t.phi * si, o_i = t.phr * si + t.phi * sr;
-      store_c(t.o, t.o_fmt, t.plane, idx, o_r, o_i);
+      store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
     } else if (KIND == CHEB_MID) {
       double o_r = 2.0 * ar - pr, o_i = 2.0 * ai - pi;
-      store_c(t.o, t.o_fmt, t.plane, idx, o_r, o_i);
+      store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
       t.y_re[idx] += t.cr * o_r - t.ci * o_i;
       t.y_im[idx] += t.cr * o_i + t.ci * o_r;
     } else {
@@ -69,7 +69,7 @@ struct EpiMix {
       const double sr = t.y_re[idx] + t.cr * qr - t.ci * qi;
       const double si = t.y_im[idx] + t.cr * qi + t.ci * qr;
       double o_r = t.phr * sr - t.phi * si, o_i = t.phr * si + t.phi * sr;
-      store_c(t.o, t.o_fmt, t.plane, idx, o_r, o_i);
+      store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
     }
   }
 };
@@ -225,161 +225,294 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
 }
 
 // ---------------------------------------------------------------------------------------------
-// Split-BF16 products. A = BF16X3 planes, or F64 planes (X) split while staging.
-// B = BF16X3 planes. One MFMA k-chunk (32) per LDS stage; LDS row stride 40
-// halves (80 bytes) keeps the 16-byte fragment reads conflict-free.
+// Split-BF16 products P_{l+1} = 2 Ht P_l - P_{l-1} on 32x32x16 BF16 matrix cores.
+//
+// A = P_l and B = Ht are BF16X3 matrices in the k-blocked layout (bf3_offset):
+// one k-block (16 columns) of a BM-row tile is 6 contiguous runs of BM x 32
+// bytes, copied to LDS unchanged (16 bytes per thread and load, coalesced), so
+// LDS holds the same row-swizzled layout and the fragment reads
+// (lane l: row l % 32, columns 8 (l / 32) .. + 7) are conflict-free. Two LDS
+// stages: while the waves multiply out of one, the next k-block is written to
+// the other from registers loaded one stage earlier; one barrier per k-block.
+//
+// Each wave owns a WTM x WTN block of 32x32 MFMA tiles. Per k-block and tile,
+// the complex product takes 4 real products for each of the 6 kept piece
+// pairs (hh, hm, mh, hl, mm, lh); the imaginary pieces of B are negated once
+// per k-block for the Ar Br - Ai Bi part.
+//
+// Epilogue: the FP32 accumulators are written to LDS in the k-blocked order,
+// then each thread takes 8 consecutive columns of one row (one 16-byte chunk
+// of every BF16 plane): it reads P_{l-1}, forms P_{l+1} = 2 acc - P_{l-1} in
+// FP64, stores its split pieces, and adds c_l P_{l+1} (the stored value) to
+// the FP64 sum Y; the last product of a step instead writes
+// X_k = exp(-i beta h) (Y + c_L P_L) as FP64 planes.
 // ---------------------------------------------------------------------------------------------
-template <int BM, int BN, int WGM, int WGN, bool A_F64, class Epi>
-__global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf16x3_kernel(MixOperands op, Epi epi) {
-  constexpr int BK = 32;
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c) {
+  // lane l: A(l%32, 8*(l/32)+e), B(8*(l/32)+e, l%32); holds D(8*(r/4)+4*(l/32)+r%4, l%32)
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+struct Bf3Args {
+  const u16* a;        // A, k-blocked BF16X3 (row capacity np)
+  const u16* b;        // B = Ht, k-blocked BF16X3
+  const void* p;       // P_{l-1}: k-blocked BF16X3, or FP64 planes (P_0 = X)
+  void* o;             // P_{l+1} (k-blocked BF16X3) or X_k (FP64 planes, last product)
+  double* y_re;        // Chebyshev sum, FP64 planes
+  double* y_im;
+  long plane;          // np * np
+  int np;
+  int tiles_m, tiles_n;
+  double cr, ci, phr, phi;
+};
+
+template <int BM, int BN, int WGM, int WGN, int KIND, bool P_F64>
+__global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
-  constexpr int FM = WTM / 16, FN = WTN / 16;
-  constexpr int S = BK + 8;
-  constexpr int CPR16 = BK / 8;                  // 16-byte chunks per row of a BF16 plane
-  constexpr int CPR64 = BK / 2;                  // 16-byte chunks per row of an F64 plane
-  constexpr int RA = A_F64 ? BM * CPR64 / NT : BM * CPR16 / NT;
-  constexpr int RB = BN * CPR16 / NT;
-  static_assert((A_F64 ? BM * CPR64 : BM * CPR16) % NT == 0 && BN * CPR16 % NT == 0, "split");
+  constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int SA = BM * 32, SB = BN * 32;  // bytes per plane and k-block
+  constexpr int STAGE = 6 * (SA + SB);
+  constexpr int NCH = 12 * (BM + BN) / NT;   // 16-byte chunks per thread and k-block
+  constexpr int NCA = 12 * BM / NT;          // of which from A
+  constexpr int EPI = 2 * BM * BN * 4;       // FP32 accumulators, k-blocked order
+  constexpr int SMEM = (2 * STAGE > EPI) ? 2 * STAGE : EPI;
+  static_assert(12 * BM % NT == 0 && 12 * BN % NT == 0, "chunk split");
+  static_assert(FM >= 1 && FN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile");
+  static_assert(KIND == CHEB_MID || KIND == CHEB_LAST, "kind");
 
-  __shared__ __attribute__((aligned(16))) u16 As[6][BM * S];
-  __shared__ __attribute__((aligned(16))) u16 Bs[6][BN * S];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
 
   int tm, tn;
-  tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
+  tile_coords(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
-  const long ld = op.ld, plane = op.plane;
+  const long np = g.np, plane = g.plane;
+  const int nk = g.np / 16;
+  const long kstride = np * 16;  // words between consecutive k-blocks of a plane
 
-  f4 accR[FM][FN], accI[FM][FN];
+  // This thread's chunks: global source (k-block 0) and LDS destination.
+  const u16* src[NCH];
+  int ldst[NCH];
+#pragma unroll
+  for (int j = 0; j < NCH; ++j) {
+    const int q = tid + j * NT;
+    if (j < NCA) {
+      const int p = q / (2 * BM), c = q % (2 * BM);
+      src[j] = g.a + p * plane + (long)m0 * 16 + c * 8;
+      ldst[j] = p * SA + c * 16;
+    } else {
+      const int qb = q - NCA * NT;
+      const int p = qb / (2 * BN), c = qb % (2 * BN);
+      src[j] = g.b + p * plane + (long)n0 * 16 + c * 8;
+      ldst[j] = 6 * SA + p * SB + c * 16;
+    }
+  }
+  u32x4 st[NCH];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) st[j] = *reinterpret_cast<const u32x4*>(src[j] + kb * kstride);
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+      *reinterpret_cast<u32x4*>(smem + buf * STAGE + ldst[j]) = st[j];
+  };
+
+  // Fragment offsets (bytes within a plane of a stage).
+  int aoff[FM], boff[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int row = wm * WTM + i * 32 + (lane & 31);
+    aoff[i] = row * 32 + 16 * ((lane >> 5) ^ ((row >> 3) & 1));
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int row = wn * WTN + j * 32 + (lane & 31);
+    boff[j] = 6 * SA + row * 32 + 16 * ((lane >> 5) ^ ((row >> 3) & 1));
+  }
+
+  f16v accR[FM][FN], accI[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      accR[i][j] = f4{0, 0, 0, 0};
-      accI[i][j] = f4{0, 0, 0, 0};
-    }
-
-  using AChunk = typename std::conditional<A_F64, d2, u32x4>::type;
-  constexpr int APL = A_F64 ? 2 : 6;
-  AChunk ga[APL][RA];
-  u32x4 gb[6][RB];
-  auto gload = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      if constexpr (A_F64) {
-        const int c = tid + r * NT, row = c / CPR64, col = 2 * (c % CPR64);
-        const long off = (long)(m0 + row) * ld + k0 + col;
-        const double* a = static_cast<const double*>(op.a);
-        ga[0][r] = *reinterpret_cast<const d2*>(a + off);
-        ga[1][r] = *reinterpret_cast<const d2*>(a + plane + off);
-      } else {
-        const int c = tid + r * NT, row = c / CPR16, col = 8 * (c % CPR16);
-        const long off = (long)(m0 + row) * ld + k0 + col;
-        const u16* a = static_cast<const u16*>(op.a);
-#pragma unroll
-        for (int p = 0; p < 6; ++p) ga[p][r] = *reinterpret_cast<const u32x4*>(a + p * plane + off);
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
       }
     }
-    const u16* b = static_cast<const u16*>(op.b);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int c = tid + r * NT, row = c / CPR16, col = 8 * (c % CPR16);
-      const long off = (long)(n0 + row) * ld + k0 + col;
-#pragma unroll
-      for (int p = 0; p < 6; ++p) gb[p][r] = *reinterpret_cast<const u32x4*>(b + p * plane + off);
-    }
-  };
-  auto lstore = [&]() {
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      if constexpr (A_F64) {
-        const int c = tid + r * NT, row = c / CPR64, col = 2 * (c % CPR64);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {  // re, im
-          u16 h0, m0_, l0, h1, m1, l1;
-          split3((float)ga[q][r][0], h0, m0_, l0);
-          split3((float)ga[q][r][1], h1, m1, l1);
-          *reinterpret_cast<uint32_t*>(&As[3 * q + 0][row * S + col]) = h0 | ((uint32_t)h1 << 16);
-          *reinterpret_cast<uint32_t*>(&As[3 * q + 1][row * S + col]) = m0_ | ((uint32_t)m1 << 16);
-          *reinterpret_cast<uint32_t*>(&As[3 * q + 2][row * S + col]) = l0 | ((uint32_t)l1 << 16);
-        }
-      } else {
-        const int c = tid + r * NT, row = c / CPR16, col = 8 * (c % CPR16);
-#pragma unroll
-        for (int p = 0; p < 6; ++p) *reinterpret_cast<u32x4*>(&As[p][row * S + col]) = ga[p][r];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int c = tid + r * NT, row = c / CPR16, col = 8 * (c % CPR16);
-#pragma unroll
-      for (int p = 0; p < 6; ++p) *reinterpret_cast<u32x4*>(&Bs[p][row * S + col]) = gb[p][r];
-    }
-  };
 
-  // (piece of A, piece of B) pairs kept below: weights 1, 2^-8 (x2), 2^-16 (x3)
   gload(0);
-  for (int k0 = 0; k0 < op.kdim; k0 += BK) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (k0 + BK < op.kdim) gload(k0 + BK);
-    const int rr = lane & 15, kk = 8 * (lane >> 4);
-    bf8 fb[6][FN];
+  lstore(0);
+  if (nk > 1) gload(1);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int cur = kb & 1;
+    if (kb + 1 < nk) lstore(cur ^ 1);  // that buffer was last read before the previous barrier
+    if (kb + 2 < nk) gload(kb + 2);
+    const unsigned char* sb = smem + cur * STAGE;
+    bf8 fb[6][FN], fbn[3][FN];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int row = wn * WTN + j * 16 + rr;
 #pragma unroll
-      for (int p = 0; p < 6; ++p) fb[p][j] = *reinterpret_cast<const bf8*>(&Bs[p][row * S + kk]);
+      for (int p = 0; p < 6; ++p) fb[p][j] = *reinterpret_cast<const bf8*>(sb + p * SB + boff[j]);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {  // -Bi pieces (sign flip of each half word)
+        u32x4 u = __builtin_bit_cast(u32x4, fb[3 + p][j]);
+        u ^= 0x80008000u;
+        fbn[p][j] = __builtin_bit_cast(bf8, u);
+      }
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
-      const int row = wm * WTM + i * 16 + rr;
-      bf8 fa[6], fan[3];
+      bf8 fa[6];
 #pragma unroll
-      for (int p = 0; p < 6; ++p) fa[p] = *reinterpret_cast<const bf8*>(&As[p][row * S + kk]);
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {  // -Ai pieces (sign flip of each half word)
-        u32x4 u = __builtin_bit_cast(u32x4, fa[3 + p]);
-        u.x ^= 0x80008000u;
-        u.y ^= 0x80008000u;
-        u.z ^= 0x80008000u;
-        u.w ^= 0x80008000u;
-        fan[p] = __builtin_bit_cast(bf8, u);
-      }
-#define FQ_PIECES(pa, pb)                                                                        \
-  {                                                                                              \
-    _Pragma("unroll") for (int j = 0; j < FN; ++j) accR[i][j] =                                  \
-        mfma_bf16(fa[pa], fb[pb][j], accR[i][j]);                                                \
-    _Pragma("unroll") for (int j = 0; j < FN; ++j) accI[i][j] =                                  \
-        mfma_bf16(fa[pa], fb[3 + pb][j], accI[i][j]);                                            \
-    _Pragma("unroll") for (int j = 0; j < FN; ++j) accR[i][j] =                                  \
-        mfma_bf16(fan[pa], fb[3 + pb][j], accR[i][j]);                                           \
-    _Pragma("unroll") for (int j = 0; j < FN; ++j) accI[i][j] =                                  \
-        mfma_bf16(fa[3 + pa], fb[pb][j], accI[i][j]);                                            \
+      for (int p = 0; p < 6; ++p) fa[p] = *reinterpret_cast<const bf8*>(sb + p * SA + aoff[i]);
+#define FQ_PAIR(pa, pb)                                                            \
+  {                                                                                \
+    _Pragma("unroll") for (int j = 0; j < FN; ++j) {                               \
+      accR[i][j] = mfma32_bf16(fa[pa], fb[pb][j], accR[i][j]);                     \
+      accI[i][j] = mfma32_bf16(fa[pa], fb[3 + pb][j], accI[i][j]);                 \
+    }                                                                              \
+    _Pragma("unroll") for (int j = 0; j < FN; ++j) {                               \
+      accR[i][j] = mfma32_bf16(fa[3 + pa], fbn[pb][j], accR[i][j]);                \
+      accI[i][j] = mfma32_bf16(fa[3 + pa], fb[pb][j], accI[i][j]);                 \
+    }                                                                              \
   }
-      FQ_PIECES(0, 0)
-      FQ_PIECES(0, 1)
-      FQ_PIECES(1, 0)
-      FQ_PIECES(0, 2)
-      FQ_PIECES(1, 1)
-      FQ_PIECES(2, 0)
-#undef FQ_PIECES
+      FQ_PAIR(0, 0)
+      FQ_PAIR(0, 1)
+      FQ_PAIR(1, 0)
+      FQ_PAIR(0, 2)
+      FQ_PAIR(1, 1)
+      FQ_PAIR(2, 0)
+#undef FQ_PAIR
     }
+    __syncthreads();
   }
 
+  // ---- epilogue ----
+  // Accumulators to LDS, k-blocked order: element (row, col) of the tile at
+  // float index ((col / 16) * BM + row) * 16 + 8 * slot + col % 8 with
+  // slot = ((col / 8) & 1) ^ ((row / 8) & 1); real parts first, then imaginary.
+  float* cr = reinterpret_cast<float*>(smem);
+  float* ci = cr + BM * BN;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
-        const int n = n0 + wn * WTN + j * 16 + (lane & 15);
-        epi(m, n, accR[i][j][r], accI[i][j][r]);
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wn * WTN + j * 32 + (lane & 31);
+        const int slot = ((col >> 3) & 1) ^ ((row >> 3) & 1);
+        const int f = ((col >> 4) * BM + row) * 16 + 8 * slot + (col & 7);
+        cr[f] = accR[i][j][r];
+        ci[f] = accI[i][j][r];
       }
+  __syncthreads();
+
+  const double cr_ = g.cr, ci_ = g.ci;
+  for (int q = tid; q < BM * BN / 8; q += NT) {
+    const int kbl = q / (2 * BM), rem = q % (2 * BM);
+    const int row = rem >> 1, slot = rem & 1;
+    const long m = m0 + row;
+    const long n = n0 + kbl * 16 + 8 * (slot ^ ((row >> 3) & 1));  // first of 8 columns
+    const long chunk = ((long)(n0 / 16 + kbl) * np + m) * 16 + 8 * slot;  // in a BF16X3 plane
+    float ar[8], ai[8];
+    *reinterpret_cast<f4*>(ar) = *reinterpret_cast<const f4*>(cr + q * 8);
+    *reinterpret_cast<f4*>(ar + 4) = *reinterpret_cast<const f4*>(cr + q * 8 + 4);
+    *reinterpret_cast<f4*>(ai) = *reinterpret_cast<const f4*>(ci + q * 8);
+    *reinterpret_cast<f4*>(ai + 4) = *reinterpret_cast<const f4*>(ci + q * 8 + 4);
+    // P_{l-1}
+    double pr[8], pi[8];
+    if constexpr (P_F64) {
+      const double* p = static_cast<const double*>(g.p) + m * np + n;
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const d2 vr = *reinterpret_cast<const d2*>(p + e);
+        const d2 vi = *reinterpret_cast<const d2*>(p + plane + e);
+        pr[e] = vr[0]; pr[e + 1] = vr[1];
+        pi[e] = vi[0]; pi[e + 1] = vi[1];
+      }
+    } else {
+      const u16* p = static_cast<const u16*>(g.p) + chunk;
+      u32x4 w[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = *reinterpret_cast<const u32x4*>(p + k * plane);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float s3[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const uint32_t word = w[k][e >> 1];
+          s3[k] = bf16_val((u16)((e & 1) ? (word >> 16) : (word & 0xffffu)));
+        }
+        pr[e] = (double)(s3[0] + s3[1] + s3[2]);
+        pi[e] = (double)(s3[3] + s3[4] + s3[5]);
+      }
+    }
+    double* yr = g.y_re + m * np + n;
+    double* yi = g.y_im + m * np + n;
+    if constexpr (KIND == CHEB_MID) {
+      u32x4 w[6];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double orr = 2.0 * (double)ar[e] - pr[e], oii = 2.0 * (double)ai[e] - pi[e];
+        u16 h0, h1, h2, h3, h4, h5;
+        split3((float)orr, h0, h1, h2);
+        split3((float)oii, h3, h4, h5);
+        const u16 hs[6] = {h0, h1, h2, h3, h4, h5};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          if (e & 1)
+            w[k][e >> 1] |= (uint32_t)hs[k] << 16;
+          else
+            w[k][e >> 1] = hs[k];
+        }
+        // the value the pieces hold
+        pr[e] = (double)(bf16_val(h0) + bf16_val(h1) + bf16_val(h2));
+        pi[e] = (double)(bf16_val(h3) + bf16_val(h4) + bf16_val(h5));
+      }
+      u16* o = static_cast<u16*>(g.o) + chunk;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        d2 vr = *reinterpret_cast<const d2*>(yr + e);
+        d2 vi = *reinterpret_cast<const d2*>(yi + e);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          vr[u] += cr_ * pr[e + u] - ci_ * pi[e + u];
+          vi[u] += cr_ * pi[e + u] + ci_ * pr[e + u];
+        }
+        *reinterpret_cast<d2*>(yr + e) = vr;
+        *reinterpret_cast<d2*>(yi + e) = vi;
+      }
+    } else {  // CHEB_LAST: X_k = ph (Y + c_L (2 acc - P_{L-1}))
+      double* o = static_cast<double*>(g.o) + m * np + n;
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const d2 vr = *reinterpret_cast<const d2*>(yr + e);
+        const d2 vi = *reinterpret_cast<const d2*>(yi + e);
+        d2 xr, xi;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double qr = 2.0 * (double)ar[e + u] - pr[e + u];
+          const double qi = 2.0 * (double)ai[e + u] - pi[e + u];
+          const double sr = vr[u] + cr_ * qr - ci_ * qi;
+          const double si = vi[u] + cr_ * qi + ci_ * qr;
+          xr[u] = g.phr * sr - g.phi * si;
+          xi[u] = g.phr * si + g.phi * sr;
+        }
+        *reinterpret_cast<d2*>(o + e) = xr;
+        *reinterpret_cast<d2*>(o + plane + e) = xi;
+      }
+    }
+  }
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
@@ -402,22 +535,54 @@ hipError_t launch_f32(MixOperands op, int mrows, int np, Epi epi, hipStream_t s)
   return hipGetLastError();
 }
 
-template <bool A_F64, class Epi>
-hipError_t launch_bf16x3(MixOperands op, int mrows, int np, Epi epi, hipStream_t s) {
+template <int KIND, bool P_F64>
+hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
+  Bf3Args g = g0;
+  const int np = g.np;
   if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= 512L * 1024) {
-    op.tiles_m = mrows / 128;
-    op.tiles_n = np / 128;
-    hipLaunchKernelGGL((cheb_bf16x3_kernel<128, 128, 2, 4, A_F64, Epi>),
-                       dim3(op.tiles_m * op.tiles_n), dim3(512), 0, s, op, epi);
+    g.tiles_m = mrows / 128;
+    g.tiles_n = np / 128;
+    hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64>),
+                       dim3(g.tiles_m * g.tiles_n), dim3(512), 0, s, g);
   } else if (mrows % 64 == 0 && np % 64 == 0) {
-    op.tiles_m = mrows / 64;
-    op.tiles_n = np / 64;
-    hipLaunchKernelGGL((cheb_bf16x3_kernel<64, 64, 2, 2, A_F64, Epi>),
-                       dim3(op.tiles_m * op.tiles_n), dim3(256), 0, s, op, epi);
+    g.tiles_m = mrows / 64;
+    g.tiles_n = np / 64;
+    hipLaunchKernelGGL((cheb_bf3_kernel<64, 64, 2, 2, KIND, P_F64>),
+                       dim3(g.tiles_m * g.tiles_n), dim3(256), 0, s, g);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Split-BF16 product of kind CHEB_MID (P_{l+1} in BF16X3) or CHEB_LAST (X_k in
+// FP64); A = P_l in BF16X3, P_{l-1} in BF16X3 or FP64 (P_0 = X).
+hipError_t dispatch_bf3(const ChebTermX& t, int mrows, int np, hipStream_t s) {
+  if (t.a_fmt != FMT_BF16X3 || (t.p_fmt != FMT_BF16X3 && t.p_fmt != FMT_F64))
+    return hipErrorInvalidValue;
+  Bf3Args g{};
+  g.a = static_cast<const u16*>(t.a);
+  g.b = static_cast<const u16*>(t.b);
+  g.p = t.p;
+  g.o = t.o;
+  g.y_re = t.y_re;
+  g.y_im = t.y_im;
+  g.plane = t.plane;
+  g.np = np;
+  g.cr = t.cr;
+  g.ci = t.ci;
+  g.phr = t.phr;
+  g.phi = t.phi;
+  const bool pf = t.p_fmt == FMT_F64;
+  if (t.kind == CHEB_MID) {
+    if (t.o_fmt != FMT_BF16X3) return hipErrorInvalidValue;
+    return pf ? launch_bf3<CHEB_MID, true>(g, mrows, s) : launch_bf3<CHEB_MID, false>(g, mrows, s);
+  }
+  if (t.kind == CHEB_LAST) {
+    if (t.o_fmt != FMT_F64) return hipErrorInvalidValue;
+    return pf ? launch_bf3<CHEB_LAST, true>(g, mrows, s) : launch_bf3<CHEB_LAST, false>(g, mrows, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <class Epi>
@@ -427,7 +592,6 @@ hipError_t dispatch(const ChebTermX& t, int precision, int mrows, int np, Epi ep
   // (launch_cheb_first_mixed); these kernels take the P_l in the product format.
   if (t.a_fmt == FMT_F64) return hipErrorInvalidValue;
   if (precision == FQ_FP32) return launch_f32<false>(op, mrows, np, epi, s);
-  if (precision == FQ_BF16X3) return launch_bf16x3<false>(op, mrows, np, epi, s);
   return hipErrorInvalidValue;
 }
 
@@ -451,13 +615,14 @@ __global__ void heff_mixed_kernel(const double* __restrict__ h0r, const double* 
     im *= inv_dE;
     hr[e] = re;
     hi[e] = im;
-    store_c(out, fmt, plane, e, re, im);
+    store_c(out, fmt, plane, i, k, ld, re, im);
   }
 }
 
 }  // namespace
 
 hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s) {
+  if (precision == FQ_BF16X3) return dispatch_bf3(t, mrows, np, s);
   switch (t.kind) {
     case CHEB_FIRST:
       return dispatch(t, precision, mrows, np, EpiMix<CHEB_FIRST>{t, np}, s);
