@@ -82,9 +82,14 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.off_ht = take(plane2);
     lay.off_x = take(plane2);
     lay.off_y = take(plane2);
-    lay.off_pa = take(plane2);
-    lay.off_pb = take(plane2);
-    if (par->precision != FQ_FP64) lay.off_htx = take(plane2);
+    // P buffers hold FP64 planes, or the product format (BF16X3: nine 16-bit planes)
+    const size_t pbytes = par->precision == FQ_BF16X3
+                              ? std::max(plane2, sizeof(uint16_t) * fq::BF3_PLANES *
+                                                     (size_t)lay.np * (size_t)lay.np)
+                              : plane2;
+    lay.off_pa = take(pbytes);
+    lay.off_pb = take(pbytes);
+    if (par->precision != FQ_FP64) lay.off_htx = take(pbytes);
     if (par->checkpoint_every > 0) {
       lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
       lay.off_tape = take(plane2 * (size_t)lay.n_tape);

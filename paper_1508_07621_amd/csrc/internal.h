@@ -72,9 +72,11 @@ hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s);
 
 // ---- mixed-precision products (kernels_mixed.hip) ------------------------------------------
 // Storage formats of a complex plane pair. F64 and F32: two planes (re, im).
-// BF16X3: six planes of 16-bit words, re_hi re_mid re_lo im_hi im_mid im_lo,
-// whose sum hi + mid + lo carries about 24 significant bits.
+// BF16X3: nine k-blocked planes of 16-bit words (formats.h), the hi, mid and lo
+// pieces of re, of im and of re + im; hi + mid + lo carries about 24
+// significant bits.
 enum Fmt : int { FMT_F64 = 0, FMT_F32 = 1, FMT_BF16X3 = 2 };
+constexpr int BF3_PLANES = 9;
 
 struct ChebTermX {
   int kind;

@@ -227,24 +227,25 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
 // ---------------------------------------------------------------------------------------------
 // Split-BF16 products P_{l+1} = 2 Ht P_l - P_{l-1} on 32x32x16 BF16 matrix cores.
 //
-// A = P_l and B = Ht are BF16X3 matrices in the k-blocked layout (bf3_offset):
-// one k-block (16 columns) of a BM-row tile is 6 contiguous runs of BM x 32
+// A = P_l and B = Ht are BF16X3 matrices in the k-blocked layout (bf3_offset)
+// with nine planes: the three pieces of the real part, of the imaginary part
+// and of their sum. A complex product takes three real ones (Gauss):
+// T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2,
+// Im = T3 - T1 - T2, each over the 6 kept piece pairs (hh, hm, mh, hl, mm, lh):
+// 18 products of 32x32x16 per tile and k-block instead of 24.
+//
+// One k-block (16 columns) of a BM-row tile is 9 contiguous runs of BM x 32
 // bytes, copied to LDS unchanged (16 bytes per thread and load, coalesced), so
 // LDS holds the same row-swizzled layout and the fragment reads
 // (lane l: row l % 32, columns 8 (l / 32) .. + 7) are conflict-free. Two LDS
 // stages: while the waves multiply out of one, the next k-block is written to
 // the other from registers loaded one stage earlier; one barrier per k-block.
 //
-// Each wave owns a WTM x WTN block of 32x32 MFMA tiles. Per k-block and tile,
-// the complex product takes 4 real products for each of the 6 kept piece
-// pairs (hh, hm, mh, hl, mm, lh); the imaginary pieces of B are negated once
-// per k-block for the Ar Br - Ai Bi part.
-//
-// Epilogue: the FP32 accumulators are written to LDS in the k-blocked order,
-// then each thread takes 8 consecutive columns of one row (one 16-byte chunk
-// of every BF16 plane): it reads P_{l-1}, forms P_{l+1} = 2 acc - P_{l-1} in
-// FP64, stores its split pieces, and adds c_l P_{l+1} (the stored value) to
-// the FP64 sum Y; the last product of a step instead writes
+// Epilogue: Re and Im are written to LDS in the k-blocked order, then each
+// thread takes 8 consecutive columns of one row (one 16-byte chunk of every
+// BF16 plane): it reads P_{l-1}, forms P_{l+1} = 2 acc - P_{l-1} in FP64,
+// stores its split pieces, and adds c_l P_{l+1} (the stored value) to the
+// FP64 sum Y; the last product of a step instead writes
 // X_k = exp(-i beta h) (Y + c_L P_L) as FP64 planes.
 // ---------------------------------------------------------------------------------------------
 typedef float f16v __attribute__((ext_vector_type(16)));
@@ -272,13 +273,14 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int NP = BF3_PLANES;
   constexpr int SA = BM * 32, SB = BN * 32;  // bytes per plane and k-block
-  constexpr int STAGE = 6 * (SA + SB);
-  constexpr int NCH = 12 * (BM + BN) / NT;   // 16-byte chunks per thread and k-block
-  constexpr int NCA = 12 * BM / NT;          // of which from A
-  constexpr int EPI = 2 * BM * BN * 4;       // FP32 accumulators, k-blocked order
+  constexpr int STAGE = NP * (SA + SB);
+  constexpr int NCHA = 2 * NP * BM;          // 16-byte chunks of A per k-block
+  constexpr int NCH = 2 * NP * (BM + BN) / NT;  // per thread
+  constexpr int EPI = 2 * BM * BN * 4;       // FP32 Re, Im in k-blocked order
   constexpr int SMEM = (2 * STAGE > EPI) ? 2 * STAGE : EPI;
-  static_assert(12 * BM % NT == 0 && 12 * BN % NT == 0, "chunk split");
+  static_assert(2 * NP * (BM + BN) % NT == 0, "chunk split");
   static_assert(FM >= 1 && FN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile");
   static_assert(KIND == CHEB_MID || KIND == CHEB_LAST, "kind");
 
@@ -299,15 +301,15 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
 #pragma unroll
   for (int j = 0; j < NCH; ++j) {
     const int q = tid + j * NT;
-    if (j < NCA) {
+    if (q < NCHA) {
       const int p = q / (2 * BM), c = q % (2 * BM);
       src[j] = g.a + p * plane + (long)m0 * 16 + c * 8;
       ldst[j] = p * SA + c * 16;
     } else {
-      const int qb = q - NCA * NT;
+      const int qb = q - NCHA;
       const int p = qb / (2 * BN), c = qb % (2 * BN);
       src[j] = g.b + p * plane + (long)n0 * 16 + c * 8;
-      ldst[j] = 6 * SA + p * SB + c * 16;
+      ldst[j] = NP * SA + p * SB + c * 16;
     }
   }
   u32x4 st[NCH];
@@ -331,20 +333,20 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
     const int row = wn * WTN + j * 32 + (lane & 31);
-    boff[j] = 6 * SA + row * 32 + 16 * ((lane >> 5) ^ ((row >> 3) & 1));
+    boff[j] = NP * SA + row * 32 + 16 * ((lane >> 5) ^ ((row >> 3) & 1));
   }
 
-  f16v accR[FM][FN], accI[FM][FN];
+  f16v t1[FM][FN], t2[FM][FN], t3[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        accR[i][j][r] = 0.f;
-        accI[i][j][r] = 0.f;
+        t1[i][j][r] = 0.f;
+        t2[i][j][r] = 0.f;
+        t3[i][j][r] = 0.f;
       }
-    }
 
   gload(0);
   lstore(0);
@@ -355,33 +357,21 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
     if (kb + 1 < nk) lstore(cur ^ 1);  // that buffer was last read before the previous barrier
     if (kb + 2 < nk) gload(kb + 2);
     const unsigned char* sb = smem + cur * STAGE;
-    bf8 fb[6][FN], fbn[3][FN];
+    bf8 fb[NP][FN];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int p = 0; p < 6; ++p) fb[p][j] = *reinterpret_cast<const bf8*>(sb + p * SB + boff[j]);
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {  // -Bi pieces (sign flip of each half word)
-        u32x4 u = __builtin_bit_cast(u32x4, fb[3 + p][j]);
-        u ^= 0x80008000u;
-        fbn[p][j] = __builtin_bit_cast(bf8, u);
-      }
-    }
+      for (int p = 0; p < NP; ++p) fb[p][j] = *reinterpret_cast<const bf8*>(sb + p * SB + boff[j]);
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
-      bf8 fa[6];
+      bf8 fa[NP];
 #pragma unroll
-      for (int p = 0; p < 6; ++p) fa[p] = *reinterpret_cast<const bf8*>(sb + p * SA + aoff[i]);
-#define FQ_PAIR(pa, pb)                                                            \
-  {                                                                                \
-    _Pragma("unroll") for (int j = 0; j < FN; ++j) {                               \
-      accR[i][j] = mfma32_bf16(fa[pa], fb[pb][j], accR[i][j]);                     \
-      accI[i][j] = mfma32_bf16(fa[pa], fb[3 + pb][j], accI[i][j]);                 \
-    }                                                                              \
-    _Pragma("unroll") for (int j = 0; j < FN; ++j) {                               \
-      accR[i][j] = mfma32_bf16(fa[3 + pa], fbn[pb][j], accR[i][j]);                \
-      accI[i][j] = mfma32_bf16(fa[3 + pa], fb[pb][j], accI[i][j]);                 \
-    }                                                                              \
+      for (int p = 0; p < NP; ++p) fa[p] = *reinterpret_cast<const bf8*>(sb + p * SA + aoff[i]);
+#define FQ_PAIR(pa, pb)                                                     \
+  _Pragma("unroll") for (int j = 0; j < FN; ++j) {                          \
+    t1[i][j] = mfma32_bf16(fa[pa], fb[pb][j], t1[i][j]);                    \
+    t2[i][j] = mfma32_bf16(fa[3 + pa], fb[3 + pb][j], t2[i][j]);            \
+    t3[i][j] = mfma32_bf16(fa[6 + pa], fb[6 + pb][j], t3[i][j]);            \
   }
       FQ_PAIR(0, 0)
       FQ_PAIR(0, 1)
@@ -395,11 +385,11 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   }
 
   // ---- epilogue ----
-  // Accumulators to LDS, k-blocked order: element (row, col) of the tile at
-  // float index ((col / 16) * BM + row) * 16 + 8 * slot + col % 8 with
+  // Re and Im to LDS, k-blocked order: element (row, col) of the tile at float
+  // index ((col / 16) * BM + row) * 16 + 8 * slot + col % 8 with
   // slot = ((col / 8) & 1) ^ ((row / 8) & 1); real parts first, then imaginary.
-  float* cr = reinterpret_cast<float*>(smem);
-  float* ci = cr + BM * BN;
+  float* cre = reinterpret_cast<float*>(smem);
+  float* cim = cre + BM * BN;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -410,8 +400,8 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
         const int col = wn * WTN + j * 32 + (lane & 31);
         const int slot = ((col >> 3) & 1) ^ ((row >> 3) & 1);
         const int f = ((col >> 4) * BM + row) * 16 + 8 * slot + (col & 7);
-        cr[f] = accR[i][j][r];
-        ci[f] = accI[i][j][r];
+        cre[f] = t1[i][j][r] - t2[i][j][r];
+        cim[f] = t3[i][j][r] - t1[i][j][r] - t2[i][j][r];
       }
   __syncthreads();
 
@@ -423,10 +413,10 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
     const long n = n0 + kbl * 16 + 8 * (slot ^ ((row >> 3) & 1));  // first of 8 columns
     const long chunk = ((long)(n0 / 16 + kbl) * np + m) * 16 + 8 * slot;  // in a BF16X3 plane
     float ar[8], ai[8];
-    *reinterpret_cast<f4*>(ar) = *reinterpret_cast<const f4*>(cr + q * 8);
-    *reinterpret_cast<f4*>(ar + 4) = *reinterpret_cast<const f4*>(cr + q * 8 + 4);
-    *reinterpret_cast<f4*>(ai) = *reinterpret_cast<const f4*>(ci + q * 8);
-    *reinterpret_cast<f4*>(ai + 4) = *reinterpret_cast<const f4*>(ci + q * 8 + 4);
+    *reinterpret_cast<f4*>(ar) = *reinterpret_cast<const f4*>(cre + q * 8);
+    *reinterpret_cast<f4*>(ar + 4) = *reinterpret_cast<const f4*>(cre + q * 8 + 4);
+    *reinterpret_cast<f4*>(ai) = *reinterpret_cast<const f4*>(cim + q * 8);
+    *reinterpret_cast<f4*>(ai + 4) = *reinterpret_cast<const f4*>(cim + q * 8 + 4);
     // P_{l-1}
     double pr[8], pi[8];
     if constexpr (P_F64) {
@@ -458,28 +448,28 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
     double* yr = g.y_re + m * np + n;
     double* yi = g.y_im + m * np + n;
     if constexpr (KIND == CHEB_MID) {
-      u32x4 w[6];
+      u32x4 w[NP];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const double orr = 2.0 * (double)ar[e] - pr[e], oii = 2.0 * (double)ai[e] - pi[e];
-        u16 h0, h1, h2, h3, h4, h5;
-        split3((float)orr, h0, h1, h2);
-        split3((float)oii, h3, h4, h5);
-        const u16 hs[6] = {h0, h1, h2, h3, h4, h5};
+        u16 hs[NP];
+        split3((float)orr, hs[0], hs[1], hs[2]);
+        split3((float)oii, hs[3], hs[4], hs[5]);
+        split3((float)(orr + oii), hs[6], hs[7], hs[8]);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < NP; ++k) {
           if (e & 1)
             w[k][e >> 1] |= (uint32_t)hs[k] << 16;
           else
             w[k][e >> 1] = hs[k];
         }
         // the value the pieces hold
-        pr[e] = (double)(bf16_val(h0) + bf16_val(h1) + bf16_val(h2));
-        pi[e] = (double)(bf16_val(h3) + bf16_val(h4) + bf16_val(h5));
+        pr[e] = (double)(bf16_val(hs[0]) + bf16_val(hs[1]) + bf16_val(hs[2]));
+        pi[e] = (double)(bf16_val(hs[3]) + bf16_val(hs[4]) + bf16_val(hs[5]));
       }
       u16* o = static_cast<u16*>(g.o) + chunk;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
+      for (int k = 0; k < NP; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
         d2 vr = *reinterpret_cast<const d2*>(yr + e);
@@ -619,6 +609,57 @@ __global__ void heff_mixed_kernel(const double* __restrict__ h0r, const double* 
   }
 }
 
+// BF16X3 variant: one thread per pair of columns (k, k + 1) of a row, in
+// row-major order: a wave reads 1 KB contiguous from every FP64 plane and
+// writes 4 bytes per lane into every BF16 plane (32-byte runs per k-block).
+// Padding rows and columns stay zero.
+__global__ void heff_bf3_kernel(const double* __restrict__ h0r, const double* __restrict__ h0i,
+                                const double* __restrict__ vr, const double* __restrict__ vi,
+                                const double* __restrict__ kr, const double* __restrict__ ki,
+                                double a, double b, double beta, double inv_dE, long n, long np,
+                                double* __restrict__ hr, double* __restrict__ hi,
+                                u16* __restrict__ out) {
+  const long pairs = np * np / 2, plane = np * np;
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < pairs;
+       q += (long)gridDim.x * blockDim.x) {
+    const long i = q / (np / 2), k = 2 * (q % (np / 2)), idx = i * np + k;
+    uint32_t wd[BF3_PLANES] = {};
+    if (i < n && k < n) {
+      const d2 h0r2 = *reinterpret_cast<const d2*>(h0r + idx);
+      const d2 h0i2 = *reinterpret_cast<const d2*>(h0i + idx);
+      const d2 vr2 = *reinterpret_cast<const d2*>(vr + idx);
+      const d2 vi2 = *reinterpret_cast<const d2*>(vi + idx);
+      const d2 kr2 = *reinterpret_cast<const d2*>(kr + idx);
+      const d2 ki2 = *reinterpret_cast<const d2*>(ki + idx);
+      d2 re2, im2;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        double re = 0.0, im = 0.0;
+        if (k + e < n) {
+          re = h0r2[e] + a * vr2[e] + b * kr2[e];
+          im = h0i2[e] + a * vi2[e] + b * ki2[e];
+          if (i == k + e) re -= beta;
+          re *= inv_dE;
+          im *= inv_dE;
+        }
+        re2[e] = re;
+        im2[e] = im;
+        u16 hs[BF3_PLANES];
+        split3((float)re, hs[0], hs[1], hs[2]);
+        split3((float)im, hs[3], hs[4], hs[5]);
+        split3((float)(re + im), hs[6], hs[7], hs[8]);
+#pragma unroll
+        for (int p = 0; p < BF3_PLANES; ++p) wd[p] |= (uint32_t)hs[p] << (16 * e);
+      }
+      *reinterpret_cast<d2*>(hr + idx) = re2;
+      *reinterpret_cast<d2*>(hi + idx) = im2;
+    }
+    u16* o = out + bf3_offset(i, k, np);  // columns k, k + 1: adjacent words
+#pragma unroll
+    for (int p = 0; p < BF3_PLANES; ++p) *reinterpret_cast<uint32_t*>(o + p * plane) = wd[p];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s) {
@@ -640,7 +681,14 @@ hipError_t launch_heff_mixed(const double* h0r, const double* h0i, const double*
                              const double* vi, const double* kr, const double* ki, double a,
                              double b, double beta, double dE, long n, long ld, double* hr,
                              double* hi, void* out, int precision, hipStream_t s) {
-  const int fmt = precision == FQ_FP32 ? FMT_F32 : FMT_BF16X3;
+  if (precision == FQ_BF16X3) {
+    long g = (ld * ld / 2 + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(heff_bf3_kernel, dim3((unsigned)g), dim3(256), 0, s, h0r, h0i, vr, vi, kr,
+                       ki, a, b, beta, 1.0 / dE, n, ld, hr, hi, static_cast<u16*>(out));
+    return hipGetLastError();
+  }
+  const int fmt = FMT_F32;
   long g = (n * ld + 255) / 256;
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL(heff_mixed_kernel, dim3((unsigned)g), dim3(256), 0, s, h0r, h0i, vr, vi, kr,
