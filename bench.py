@@ -129,15 +129,54 @@ def _blas_threads() -> int:
     return len(os.sched_getaffinity(0))
 
 
-#: MFMA operations issued per algorithmic real flop of a complex product:
-#: FP64 and FP32 run the four real products once; BF16x3 runs six piece
-#: products for each of the four real products.
-MFMA_FLOPS_PER_FLOP = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 6.0}
+#: MFMA operations issued per algorithmic real flop of a complex product
+#: (algorithmic: four real products, 8 N^3 flop): FP64 and FP32 run the four
+#: real products once; BF16x3 runs three real products (Gauss) for each of six
+#: piece pairs, 18 / 4 = 4.5.
+MFMA_FLOPS_PER_FLOP = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 4.5}
 PEAKS = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
          "bf16x3": PEAK_BF16_MFMA_TFLOPS}
 KERNEL_NAMES = {"fp64": "zgemm_nt_f64_kernel<128,128,16,2,4,EpiCheb<MID>> (FP64 MFMA 16x16x4)",
                 "fp32": "cheb_f32_kernel<128,128,32,2,4,EpiMix<MID>> (FP32 MFMA 16x16x4)",
-                "bf16x3": "cheb_bf16x3_kernel<128,128,2,4,EpiMix<MID>> (BF16 MFMA 16x16x32)"}
+                "bf16x3": "cheb_bf3_kernel<128,128,2,4,MID> (BF16 MFMA 32x32x16, 3 real products "
+                          "x 6 piece pairs)"}
+
+#: Kernel sources behind each roofline entry; HBM traffic recorded under
+#: profiles/ is reported only while these files are unchanged.
+TRAFFIC_SOURCES = {
+    "fp64": ["kernels_dense.hip", "formats.h", "internal.h"],
+    "fp32": ["kernels_mixed.hip", "formats.h", "internal.h"],
+    "bf16x3": ["kernels_mixed.hip", "formats.h", "internal.h"],
+    "tridiag": ["kernels_tridiag.hip", "internal.h"],
+}
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+
+
+def source_digest(key: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES[key]:
+        with open(os.path.join(ROOT, "paper_1508_07621_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(key: str, workload: str):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 counter
+    table (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or None
+    when there is no row for this kernel and workload or its sources changed."""
+    try:
+        lines = open(TRAFFIC_TABLE).read().splitlines()
+    except OSError:
+        return None
+    digest = source_digest(key)
+    for line in lines:
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == key and cells[1] == workload and cells[2] == digest:
+            fetch, write = float(cells[3]), float(cells[4])
+            return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+                    "source_digest": digest}
+    return None
 
 
 def time_builds(ctx, U, warmup: int, steps: int, tag: str):
@@ -157,7 +196,7 @@ def time_builds(ctx, U, warmup: int, steps: int, tag: str):
     return (time.perf_counter() - t0) / steps, reports
 
 
-def dense_roofline(reports, n: int, precision: str):
+def dense_roofline(reports, n: int, precision: str, workload: str):
     from paper_1508_07621_amd._abi import K_MID
     n_launch = sum(r["n_kernel"][K_MID] for r in reports)
     ms_launch = sum(r["ms_kernel"][K_MID] for r in reports) / max(n_launch, 1)
@@ -165,8 +204,10 @@ def dense_roofline(reports, n: int, precision: str):
     mfma_flops = flops * MFMA_FLOPS_PER_FLOP[precision]
     achieved = mfma_flops / (ms_launch * 1e-3) / 1e12
     peak = PEAKS[precision]
+    tr = recorded_traffic(precision, workload)
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None, "kernel": KERNEL_NAMES[precision],
+            "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
+            "traffic_detail": tr, "kernel": KERNEL_NAMES[precision],
             "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
             "mfma_flops_per_launch": mfma_flops, "algorithmic_flops_per_launch": flops,
             "algorithmic_tflops": round(flops / (ms_launch * 1e-3) / 1e12, 3)}
@@ -245,7 +286,7 @@ def main():
 
     extra = {}
     if wl.layout == "dense":
-        roof = dense_roofline(reports, n, precision)
+        roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
         if precision != "fp64" and not args.no_fp64_ref:
             # The FP64 build of the same workload: reference result and timing.
@@ -270,7 +311,7 @@ def main():
             extra["fp64"] = {"s_per_build": round(s_ref, 4),
                              "build_tflops_algorithmic": round(
                                  info["L"] * wl.M * 8.0 * n ** 3 / s_ref / 1e12, 3),
-                             "roofline": dense_roofline(rep_ref, n, "fp64")}
+                             "roofline": dense_roofline(rep_ref, n, "fp64", args.workload)}
             extra["speedup_vs_fp64"] = round(s_ref / s_per_build, 3)
             del ref, Uref
     else:
@@ -278,9 +319,10 @@ def main():
         ms_launch = sum(r["ms_kernel"][K_TRIDIAG] for r in reports) / max(n_launch, 1)
         flops = float(TRIDIAG_FLOPS_PER_ELEMENT_TERM) * n * n * wl.M * info["L"]
         achieved = flops / (ms_launch * 1e-3) / 1e12
+        tr = recorded_traffic("tridiag", args.workload)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4),
-                "traffic": None, "kernel": "tridiag_gauge_kernel<16,512> (whole chain per state column, real gauge form)",
+                "traffic": tr["bytes"] if tr else None, "traffic_detail": tr, "kernel": "tridiag_gauge_kernel<16,512> (whole chain per state column, real gauge form)",
                 "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops / s_per_build / 1e12

@@ -390,21 +390,38 @@ fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, dou
   const long plane = c->np * c->np;
   static const int slot[4] = {FQ_K_FIRST, FQ_K_FIRST_LAST, FQ_K_MID, FQ_K_LAST};
   FQ_MARK(c, slot[kind]);
-  if (c->precision == FQ_FP64) {
+  auto f64_term = [&](double* out) {
     ChebTerm t{};
     t.kind = kind;
     t.a_re = a; t.a_im = a + plane;
     t.b_re = c->htr; t.b_im = c->hti;
     t.p_re = p; t.p_im = p + plane;
     t.y_re = c->yr; t.y_im = c->yi;
-    t.o_re = o; t.o_im = o + plane;
+    t.o_re = out; t.o_im = out + plane;
     t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
     t.phr = c->phr; t.phi = c->phi;
+    return t;
+  };
+  const bool first = kind == fq::CHEB_FIRST || kind == fq::CHEB_FIRST_LAST;
+  if (c->precision == FQ_FP64) {
+    ChebTerm t = f64_term(o);
     if (c->save_pl && (kind == fq::CHEB_LAST || kind == fq::CHEB_FIRST_LAST)) {
       t.save_re = c->save_pl;
       t.save_im = c->save_pl + plane;
     }
     FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+  } else if (first) {
+    // P_1 = Ht X carries the largest Chebyshev weight (|c_1| ~ R) and feeds
+    // every later term, so it is formed on FP64 matrix cores from the FP64
+    // Ht; Y takes its FP64 value. For L > 1 the product goes to the P buffer
+    // that is free until P_2 (pb) and is rounded from there into o.
+    const bool to_fmt = kind == fq::CHEB_FIRST;
+    ChebTerm t = f64_term(to_fmt ? c->pbr : o);
+    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+    if (to_fmt) {
+      const int pf = c->precision == FQ_FP32 ? fq::FMT_F32 : fq::FMT_BF16X3;
+      FQ_HIP(c, fq::launch_to_product(c->pbr, c->pbr + plane, o, pf, mrows, np, c->stream));
+    }
   } else {
     const int pf = c->precision == FQ_FP32 ? fq::FMT_F32 : fq::FMT_BF16X3;
     fq::ChebTermX t{};
@@ -417,13 +434,7 @@ fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, dou
     t.y_re = c->yr; t.y_im = c->yi;
     t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
     t.phr = c->phr; t.phi = c->phi;
-    if (kind == fq::CHEB_FIRST || kind == fq::CHEB_FIRST_LAST) {
-      // P_1 = Ht X carries the largest Chebyshev weight (|c_1| ~ R) and feeds
-      // every later term, so it is formed on FP64 matrix cores.
-      FQ_HIP(c, fq::launch_cheb_first_mixed(t, c->htr, c->hti, mrows, np, c->stream));
-    } else {
-      FQ_HIP(c, fq::launch_cheb_mixed(t, c->precision, mrows, np, c->stream));
-    }
+    FQ_HIP(c, fq::launch_cheb_mixed(t, c->precision, mrows, np, c->stream));
   }
   return FQ_OK;
 }

@@ -94,12 +94,12 @@ struct ChebTermX {
 // Products P_{l+1} = 2 Ht P_l - P_{l-1} (l >= 1) with A = P_l in the product
 // format; precision: FQ_FP32 or FQ_BF16X3 (FP32 or BF16 matrix cores).
 hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s);
-// The first product of a step in a mixed-precision build (kind CHEB_FIRST or
-// CHEB_FIRST_LAST): A = X and B = the FP64 rescaled Hamiltonian (b64_re,
-// b64_im) on FP64 matrix cores; P_1 is stored in the product format t.o_fmt
-// and the FP64 product goes into Y (or into the FP64 output for L == 1).
-hipError_t launch_cheb_first_mixed(const ChebTermX& t, const double* b64_re, const double* b64_im,
-                                   int mrows, int np, hipStream_t s);
+// FP64 planes (rows [0, mrows) of an np x np pair, row stride np) rounded into
+// the product format `fmt` (FMT_F32 planar or FMT_BF16X3 k-blocked) at `out`.
+// The first product of a mixed-precision step runs on FP64 matrix cores and
+// its P_1 reaches the product format through this conversion.
+hipError_t launch_to_product(const double* re, const double* im, void* out, int fmt, long mrows,
+                             long np, hipStream_t s);
 // Rescaled Hamiltonian, written both as FP64 planes (hr, hi) and in the
 // product format of `precision` (out).
 hipError_t launch_heff_mixed(const double* h0r, const double* h0i, const double* vr,

@@ -319,32 +319,6 @@ struct EpiAdjDot {
   }
 };
 
-// First product of a step of a mixed-precision build: FP64 product Ht X,
-// P_1 stored in the product format, the FP64 product added to Y.
-template <int KIND>
-struct EpiFirstMixed {
-  ChebTermX t;
-  long ld;
-  __device__ __forceinline__ void operator()(int m, int n, double ar, double ai) const {
-    const long idx = (long)m * ld + n;
-    const double* x = static_cast<const double*>(t.p);
-    const double xr = x[idx], xi = x[t.plane + idx];
-    const double sr = t.c0r * xr - t.c0i * xi + t.cr * ar - t.ci * ai;
-    const double si = t.c0r * xi + t.c0i * xr + t.cr * ai + t.ci * ar;
-    if (KIND == CHEB_FIRST) {
-      double o_r = ar, o_i = ai;
-      store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
-      t.y_re[idx] = sr;
-      t.y_im[idx] = si;
-    } else {  // CHEB_FIRST_LAST
-      double* o = static_cast<double*>(t.o);
-      o[idx] = t.phr * sr - t.phi * si;
-      o[t.plane + idx] = t.phr * si + t.phi * sr;
-    }
-  }
-  __device__ __forceinline__ void finish() const {}
-};
-
 template <bool CONJ_A, bool CONJ_B, class Epi>
 hipError_t launch_gemm(const Operands& op0, int mrows, int ncols, Epi epi, hipStream_t s) {
   Operands op = op0;
@@ -527,18 +501,6 @@ hipError_t launch_adj_dot(const double* pr, const double* pi, const double* dr_,
   Operands op{pr, pi, dr_, di_, np, np, 0, 0};
   EpiAdjDot e{pbr, pbi, out, np, w};
   return launch_gemm<false, false>(op, np, ncols, e, s);
-}
-
-hipError_t launch_cheb_first_mixed(const ChebTermX& t, const double* b64_re, const double* b64_im,
-                                   int mrows, int np, hipStream_t s) {
-  const double* a = static_cast<const double*>(t.a);
-  Operands op{a, a + t.plane, b64_re, b64_im, np, np, 0, 0};
-  if (t.a_fmt != FMT_F64 || t.p_fmt != FMT_F64) return hipErrorInvalidValue;
-  if (t.kind == CHEB_FIRST)
-    return launch_gemm<false, false>(op, mrows, np, EpiFirstMixed<CHEB_FIRST>{t, np}, s);
-  if (t.kind == CHEB_FIRST_LAST && t.o_fmt == FMT_F64)
-    return launch_gemm<false, false>(op, mrows, np, EpiFirstMixed<CHEB_FIRST_LAST>{t, np}, s);
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_zgemm_nt_f64(const double* ar, const double* ai, bool conj_a, const double* br,

@@ -578,8 +578,9 @@ hipError_t dispatch_bf3(const ChebTermX& t, int mrows, int np, hipStream_t s) {
 template <class Epi>
 hipError_t dispatch(const ChebTermX& t, int precision, int mrows, int np, Epi epi, hipStream_t s) {
   MixOperands op{t.a, t.b, t.plane, np, np, 0, 0};
-  // The first product of a step (A = X in FP64) runs on FP64 matrix cores
-  // (launch_cheb_first_mixed); these kernels take the P_l in the product format.
+  // The first product of a step (A = X in FP64) runs on FP64 matrix cores and
+  // reaches the product format through launch_to_product; these kernels take
+  // the P_l in the product format.
   if (t.a_fmt == FMT_F64) return hipErrorInvalidValue;
   if (precision == FQ_FP32) return launch_f32<false>(op, mrows, np, epi, s);
   return hipErrorInvalidValue;
@@ -660,6 +661,38 @@ __global__ void heff_bf3_kernel(const double* __restrict__ h0r, const double* __
   }
 }
 
+// FP64 planes -> product format, one thread per pair of columns (k, k + 1) of a
+// row in row-major order (16-byte reads per plane, 4-byte BF16 writes).
+__global__ void to_product_kernel(const double* __restrict__ re, const double* __restrict__ im,
+                                  void* __restrict__ out, int fmt, long mrows, long np) {
+  const long pairs = mrows * np / 2, plane = np * np;
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < pairs;
+       q += (long)gridDim.x * blockDim.x) {
+    const long i = q / (np / 2), k = 2 * (q % (np / 2)), idx = i * np + k;
+    const d2 r2 = *reinterpret_cast<const d2*>(re + idx);
+    const d2 i2 = *reinterpret_cast<const d2*>(im + idx);
+    if (fmt == FMT_F32) {
+      float* o = static_cast<float*>(out);
+      *reinterpret_cast<f2*>(o + idx) = f2{(float)r2[0], (float)r2[1]};
+      *reinterpret_cast<f2*>(o + plane + idx) = f2{(float)i2[0], (float)i2[1]};
+    } else {
+      uint32_t wd[BF3_PLANES] = {};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        u16 hs[BF3_PLANES];
+        split3((float)r2[e], hs[0], hs[1], hs[2]);
+        split3((float)i2[e], hs[3], hs[4], hs[5]);
+        split3((float)(r2[e] + i2[e]), hs[6], hs[7], hs[8]);
+#pragma unroll
+        for (int p = 0; p < BF3_PLANES; ++p) wd[p] |= (uint32_t)hs[p] << (16 * e);
+      }
+      u16* o = static_cast<u16*>(out) + bf3_offset(i, k, np);
+#pragma unroll
+      for (int p = 0; p < BF3_PLANES; ++p) *reinterpret_cast<uint32_t*>(o + p * plane) = wd[p];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s) {
@@ -693,6 +726,17 @@ hipError_t launch_heff_mixed(const double* h0r, const double* h0i, const double*
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL(heff_mixed_kernel, dim3((unsigned)g), dim3(256), 0, s, h0r, h0i, vr, vi, kr,
                      ki, a, b, beta, 1.0 / dE, n, ld, hr, hi, out, fmt);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_product(const double* re, const double* im, void* out, int fmt, long mrows,
+                             long np, hipStream_t s) {
+  if (mrows < 1 || mrows > np || np % 2 || (fmt != FMT_F32 && fmt != FMT_BF16X3))
+    return hipErrorInvalidValue;
+  long g = (mrows * np / 2 + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(to_product_kernel, dim3((unsigned)g), dim3(256), 0, s, re, im, out, fmt,
+                     mrows, np);
   return hipGetLastError();
 }
 
