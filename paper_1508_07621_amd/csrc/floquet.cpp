@@ -57,7 +57,7 @@ struct Layout {
   size_t total = 0;
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
          off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
-         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0;
+         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -103,6 +103,8 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
     lay.off_x = take(plane2);  // planar copy of U_T for the unitarity check
     lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)par->M);
+    if (n > fq::tridiag_resident_max_n())  // two 8-plane states of up to n x n doubles
+      lay.off_stream = take(2 * 8 * sizeof(double) * (size_t)n * (size_t)n);
   }
   lay.off_small = take(64 * sizeof(double));
   lay.off_ab = take(2 * sizeof(double) * (size_t)par->M);
@@ -147,8 +149,10 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (sys->layout == FQ_TRIDIAG) {
     if (par->precision != FQ_FP64)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal layout runs in FP64 only");
-    if (sys->n > fq::tridiag_resident_max_n())
-      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal n > %ld not supported", fq::tridiag_resident_max_n());
+    // beyond one workgroup's column (4096 rows) the streamed passes keep two
+    // 8-plane n x n FP64 states in the workspace (128 n^2 bytes)
+    if (sys->n > 40000)
+      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal n > 40000 not supported");
     if (par->checkpoint_every > 0)
       return fail(FQ_ERR_UNSUPPORTED, "gradient tape not available for the tridiagonal layout");
   }
@@ -554,8 +558,34 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.ld_x0 = ncols;
   job.x_out = x_out;
   job.ld_out = ncols;
-  FQ_MARK(c, FQ_K_TRIDIAG);
-  FQ_HIP(c, fq::launch_tridiag_resident(job, c->stream));
+  if (c->n <= fq::tridiag_resident_max_n()) {
+    FQ_MARK(c, FQ_K_TRIDIAG);
+    FQ_HIP(c, fq::launch_tridiag_resident(job, c->stream));
+    return FQ_OK;
+  }
+  // Longer columns: k-term passes with ghost rows, state ping-ponged through HBM.
+  const int K = 128;
+  fq::TridiagStream st{};
+  st.plane = c->n * ncols;
+  st.K = K;
+  st.B = fq::tridiag_stream_rows() - 2L * K;
+  st.nblk = (c->n + st.B - 1) / st.B;
+  double* buf[2] = {c->d_stream, c->d_stream + 8 * (size_t)c->n * (size_t)c->n};
+  int cur = 0;
+  for (int s = k0; s < k1; ++s) {
+    for (int l0 = 0; l0 <= c->L; l0 += K) {
+      st.s = s;
+      st.l0 = l0;
+      st.l1 = std::min(l0 + K, c->L + 1);
+      st.first_step = (s == k0 && l0 == 0);
+      st.last_step = (s + 1 == k1);
+      st.in = buf[cur];
+      st.out = buf[cur ^ 1];
+      FQ_MARK(c, FQ_K_TRIDIAG);
+      FQ_HIP(c, fq::launch_tridiag_stream(job, st, c->stream));
+      cur ^= 1;
+    }
+  }
   return FQ_OK;
 }
 
@@ -782,6 +812,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->d_coef = P(lay.off_coef);
   c->xr = P(lay.off_x);
   if (sys->layout == FQ_TRIDIAG) c->d_gauge = P(lay.off_gauge);
+  if (lay.off_stream) c->d_stream = P(lay.off_stream);
   c->xi = c->xr + plane;
   if (sys->layout == FQ_DENSE) {
     c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;

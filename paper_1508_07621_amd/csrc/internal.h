@@ -164,6 +164,26 @@ struct TridiagJob {
 hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
 long tridiag_resident_max_n();
 
+// Longer columns: one launch runs terms [l0, l1) of step s on blocks of B owned
+// rows with K ghost rows per side (B + 2K = tridiag_stream_rows()), reading the
+// state from `in` and writing it to `out` (8 planes of ncols x n doubles each),
+// or, at the end of the last step (last_step and l1 == L + 1), X to job.x_out.
+// first_step with l0 == 0 takes X from job.x0 (identity when null) instead of in.
+struct TridiagStream {
+  const double* in;
+  double* out;
+  long plane;       // n * ncols
+  int s;            // step index (0-based)
+  int l0, l1;       // terms of this launch, l1 - l0 <= K, l0 != 1
+  int first_step;
+  int last_step;
+  int K;            // ghost rows per side
+  long B;           // owned rows per block
+  long nblk;        // blocks per column = ceil(n / B)
+};
+long tridiag_stream_rows();
+hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s);
+
 // Unit gauge factors of step s (host FP64): w_0 = 1, w_{i+1} = w_i conj(u_i) with
 // u_i = e_i / |e_i| the phase of Ht[i][i+1] (u_i = 1 where e_i = 0).
 void tridiag_gauge(long n, const double* h0_off, const double* v_diag, double b, double* w_out);
@@ -208,6 +228,7 @@ struct fq_ctx {
   double* d_ab = nullptr;             // 2*M
   double* d_coef = nullptr;           // 2*(L+1)
   double* d_gauge = nullptr;          // tridiagonal: M x n complex gauge factors
+  double* d_stream = nullptr;         // tridiagonal n > resident size: two 8-plane states
   // state
   bool tape_valid = false;
   bool broken = false;

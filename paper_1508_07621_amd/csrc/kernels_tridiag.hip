@@ -219,6 +219,236 @@ hipError_t launch_r(const TridiagJob& job, int G, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- columns longer than one workgroup holds: k-term passes over HBM ----------------------------
+//
+// A column is cut into blocks of B owned rows; a workgroup loads its block with
+// K ghost rows on each side (4096 rows: 16 per lane, 4 waves per part), runs at
+// most K terms of one step in registers exactly as above, and writes back only
+// its owned rows: after t terms the rows within t of a cut are stale, the owned
+// ones are not. Between launches the state lives in HBM in the gauge frame of
+// the current step, as 8 planes of ncols x n doubles (column-major per state):
+// role 0 = latest even term, role 1 = latest odd term, role 2 = the part's own
+// share of the sum, role 3 = its share of the other component; plane index
+// (role * 2 + part). At a step start role 0 holds X~ = D_s^+ X.
+template <int R, int MAXT>
+__global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, TridiagStream st,
+                                                              int G) {
+  extern __shared__ double ysh[];  // [part][lane in part][r][2]
+  __shared__ double halo[2][2][2][kMaxWaves];
+
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int part = wid / G, w = wid % G;
+  const int pl = w * 64 + lane;
+  const long col = blockIdx.x / st.nblk, blk = blockIdx.x % st.nblk;
+  const long n = job.n;
+  const long a0 = blk * st.B;                       // first owned row
+  const long own_end = (a0 + st.B < n) ? a0 + st.B : n;
+  const long base = a0 - st.K + (long)pl * R;       // global row of this lane's first row
+  const double sgn = part == 0 ? 1.0 : -1.0;
+  const double2* gauge = reinterpret_cast<const double2*>(job.gauge);
+  const double2* coef = reinterpret_cast<const double2*>(job.coef);
+  const double2* h0o = reinterpret_cast<const double2*>(job.h0_off);
+  const long cn = col * n;                          // column offset in a state plane
+  auto plane_in = [&](int role, int pt) { return st.in + (role * 2 + pt) * st.plane + cn; };
+  auto plane_out = [&](int role, int pt) { return st.out + (role * 2 + pt) * st.plane + cn; };
+
+  double pe[R], po[R];  // latest even and odd terms
+  double ys[R], yo[R];
+  double d2[R], g2[R];
+  double gm2 = 0.0;
+  const int s = st.s;
+
+  // rows of 2 G for step s
+  {
+    const double a = job.ab[2 * s], b = job.ab[2 * s + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      d2[r] = 0.0;
+      g2[r] = 0.0;
+      if (i >= 0 && i < n) {
+        const double vi = job.v_diag[i];
+        d2[r] = 2.0 * (job.h0_diag[i] + a * vi - job.beta) * job.inv_dE;
+        if (i + 1 < n) {
+          const double2 h = h0o[i];
+          const double q = b * (job.v_diag[i + 1] - vi);
+          g2[r] = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
+        }
+      }
+    }
+    if (base >= 1 && base < n) {
+      const double2 h = h0o[base - 1];
+      const double q = b * (job.v_diag[base] - job.v_diag[base - 1]);
+      gm2 = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
+    }
+  }
+
+  // load
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const long i = base + r;
+    const bool in_col = i >= 0 && i < n;
+    const bool owned = i >= a0 && i < own_end;
+    double e = 0.0, o = 0.0, y1 = 0.0, y2 = 0.0;
+    if (in_col) {
+      if (st.l0 == 0 && st.first_step) {
+        double xr, xi;
+        if (job.x0) {
+          const double2 x = reinterpret_cast<const double2*>(job.x0)[i * job.ld_x0 + col];
+          xr = x.x;
+          xi = x.y;
+        } else {
+          xr = (i == col) ? 1.0 : 0.0;
+          xi = 0.0;
+        }
+        const double2 g = gauge[(long)s * n + i];
+        e = part == 0 ? g.x * xr + g.y * xi : g.x * xi - g.y * xr;  // conj(w) x
+      } else {
+        e = plane_in(0, part)[i];
+        if (st.l0 > 0) {
+          o = plane_in(1, part)[i];
+          if (owned) {
+            y1 = plane_in(2, part)[i];
+            y2 = plane_in(3, part)[i];
+          }
+        }
+      }
+    }
+    pe[r] = e;
+    po[r] = o;
+    ys[r] = y1;
+    yo[r] = y2;
+  }
+
+  int parity = 0;
+  auto neighbours = [&](const double* v, double& up, double& dn) {
+    up = from_prev_lane(v[R - 1]);
+    dn = from_next_lane(v[0]);
+    if (lane == 0) halo[parity][part][0][w] = v[0];
+    if (lane == 63) halo[parity][part][1][w] = v[R - 1];
+    __syncthreads();
+    const double hu = (w > 0) ? halo[parity][part][1][w - 1] : 0.0;
+    const double hd = (w + 1 < G) ? halo[parity][part][0][w + 1] : 0.0;
+    up = (lane == 0) ? hu : up;
+    dn = (lane == 63) ? hd : dn;
+    parity ^= 1;
+  };
+  auto advance = [&](const double* v, double* nw) {
+    double up, dn;
+    neighbours(v, up, dn);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double lo = (r == 0) ? up : v[r - 1];
+      const double hi = (r == R - 1) ? dn : v[r + 1];
+      double t = fma(d2[r], v[r], -nw[r]);
+      t = fma((r == 0) ? gm2 : g2[r - 1], lo, t);
+      nw[r] = fma(g2[r], hi, t);
+    }
+  };
+
+  int l = st.l0;
+  if (l == 0) {  // P_0 = X~ (in pe), P_1 = G X~ (into po)
+    const double c0 = coef[0].x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ys[r] = c0 * pe[r];
+      yo[r] = 0.0;
+      po[r] = 0.0;
+    }
+    l = 1;
+    if (l < st.l1) {
+      advance(pe, po);
+      const double c1 = sgn * coef[1].y;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        po[r] *= 0.5;
+        yo[r] = fma(c1, po[r], yo[r]);
+      }
+      l = 2;
+    }
+  }
+  if (l < st.l1 && (l & 1)) {  // odd start: P_l over P_{l-2} in po
+    advance(pe, po);
+    const double c = sgn * coef[l].y;
+#pragma unroll
+    for (int r = 0; r < R; ++r) yo[r] = fma(c, po[r], yo[r]);
+    ++l;
+  }
+  for (; l + 1 < st.l1; l += 2) {  // even l into pe, odd l + 1 into po
+    advance(po, pe);
+    const double ce = coef[l].x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) ys[r] = fma(ce, pe[r], ys[r]);
+    advance(pe, po);
+    const double co = sgn * coef[l + 1].y;
+#pragma unroll
+    for (int r = 0; r < R; ++r) yo[r] = fma(co, po[r], yo[r]);
+  }
+  if (l < st.l1) {
+    advance(po, pe);
+    const double ce = coef[l].x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) ys[r] = fma(ce, pe[r], ys[r]);
+  }
+
+  if (st.l1 <= job.L) {  // mid-step: keep the two latest terms and the sum
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      if (i >= a0 && i < own_end) {
+        plane_out(0, part)[i] = pe[r];
+        plane_out(1, part)[i] = po[r];
+        plane_out(2, part)[i] = ys[r];
+        plane_out(3, part)[i] = yo[r];
+      }
+    }
+    return;
+  }
+
+  // step end: both halves of Y meet; X~_{s+1} = phase w_s conj(w_{s+1}) Y, or
+  // X = phase w_s Y after the last step (to x_out, complex128 row-major).
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double* slot = ysh + (((long)part * G * 64 + pl) * R + r) * 2;
+    slot[0] = ys[r];
+    slot[1] = yo[r];
+  }
+  __syncthreads();
+  double* out = reinterpret_cast<double*>(job.x_out);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const long i = base + r;
+    if (i < a0 || i >= own_end) continue;
+    const double* other = ysh + (((long)(1 - part) * G * 64 + pl) * R + r) * 2;
+    const double own = ys[r] + other[1];
+    const double oth = yo[r] + other[0];
+    const double yr = part == 0 ? own : oth, yi = part == 0 ? oth : own;
+    const double2 ws = gauge[(long)s * n + i];
+    double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
+    if (!st.last_step) {
+      const double2 wn = gauge[(long)(s + 1) * n + i];
+      const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
+      rr = tr;
+      ri = ti;
+    }
+    const double v = part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
+    if (st.last_step)
+      out[2 * (i * job.ld_out + col) + part] = v;
+    else
+      plane_out(0, part)[i] = v;
+  }
+}
+
+template <int R, int MAXT>
+hipError_t launch_stream_r(const TridiagJob& job, const TridiagStream& st, int G, hipStream_t s) {
+  const size_t shmem = sizeof(double) * 2 * (size_t)G * 64 * R * 2;
+  const long grid = job.ncols * st.nblk;
+  if (grid < 1 || grid > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((tridiag_stream_kernel<R, MAXT>), dim3((unsigned)grid), dim3(2 * G * 64),
+                     shmem, s, job, st, G);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // 16 rows per lane and up to 4 waves per part (512 threads, <= 256 VGPRs).
@@ -233,6 +463,17 @@ hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s) {
     return launch_r<16, 512, true>(job, G, s);
   }
   return hipErrorInvalidValue;
+}
+
+long tridiag_stream_rows() { return 4L * 64 * 16; }
+
+hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s) {
+  if (job.n < 1 || job.ncols < 1 || st.K < 2 || st.l0 < 0 || st.l1 <= st.l0 ||
+      st.l1 - st.l0 > st.K || st.l1 > job.L + 1 || st.B < 1 ||
+      st.B + 2L * st.K != tridiag_stream_rows() || st.nblk != (job.n + st.B - 1) / st.B ||
+      (st.l0 == 1))
+    return hipErrorInvalidValue;
+  return launch_stream_r<16, 512>(job, st, 4, s);
 }
 
 }  // namespace fq

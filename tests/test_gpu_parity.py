@@ -167,6 +167,33 @@ def test_dense_full_size_sampled_columns(fl):
     assert rep["unitarity_max"] < 1e-11
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("bf16x3", 1e-6)])
+def test_dense_n10000_full_launch_sampled_columns(fl, precision, tol):
+    """The 10^4-state random-matrix model at its real shape: the whole identity
+    block (79 x 79 tiles of 128) through the first two of its 200 steps (same
+    step size, interval and order as the full build), four columns checked
+    against the oracle."""
+    wl = workload("gue10000")
+    H0, V = wl.arrays["h0"], wl.arrays["v"]
+    T, M, n = wl.T, wl.M, wl.n
+    f = _cos_nodes(fl, T, M)
+    lo, hi = -4.5, 4.5
+    _, _, R = orc.rescale(lo, hi, T / M)
+    L = orc.choose_L(R, 1e-12)
+    _say("dense n=10^4", precision, "L", L)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
+                            precision=precision)
+    X = ctx.propagate(np.eye(n, dtype=complex), 0, 2)
+    cols = [0, 4321, 8191, n - 1]
+    Xc = X[:, cols].cpu().numpy()
+    del X
+    Xref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L,
+                        X0=np.eye(n, dtype=complex)[:, cols], k_range=(0, 2))
+    err = orc.column_error(Xc, Xref)
+    _say("e_col", err)
+    assert err < tol
+
+
 # ---- dense mixed precision --------------------------------------------------------------------------
 
 MIXED_TOL = 1e-6
@@ -289,6 +316,54 @@ def test_tridiag_dimer1000_full_config(fl):
     assert err < FP64_TOL
     assert np.max(np.abs(U - U.T)) < 1e-10
     assert rep["unitarity_max"] < 1e-10
+
+
+@pytest.mark.parametrize("nb,M,steps,cols", [(4499, 300, (0, 3), [0, 1, 3839, 3840, 4499]),
+                                           (5000, 2000, (7, 9), [17, 2500, 5000])])
+def test_tridiag_streamed_long_columns(fl, nb, M, steps, cols):
+    """Columns longer than one workgroup holds (n > 4096) run in passes of at
+    most 128 terms over blocks with ghost rows. M = 300 gives L ~ 400 (four
+    passes per step); the second case has L small enough for one pass per
+    step. Columns straddle the block cut at row 3840."""
+    ctx, (d, e, v, f, T, lo, hi, L) = _dimer_ctx(fl, nb, 0.01, M)
+    n = nb + 1
+    _say("tridiag streamed", n, "M", M, "L", L, "steps", steps)
+    X0 = np.eye(n, dtype=complex)[:, cols]
+    X = ctx.propagate(X0, *steps).cpu().numpy()
+    Xref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0,
+                                k_range=steps)
+    err = orc.column_error(X, Xref)
+    _say("e_col", err)
+    assert err < FP64_TOL
+
+
+def test_tridiag_dimer10000_sampled_columns(fl):
+    """The 9999-boson dimer (n = 10^4, M = 500, L = 1870: 15 passes per step) in
+    its full launch shape for the first two steps: every column of the identity,
+    four of them checked against the oracle, and unitarity of the block."""
+    wl = workload("dimer10000")
+    d, e, v = wl.arrays["h0_diag"], wl.arrays["h0_off"], wl.arrays["v_diag"]
+    M, T, n = wl.M, wl.T, wl.n
+    f = drive_cos(fl.node_times(T, M), 0.5, 1.5, 1.0)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    _, _, R = orc.rescale(lo, hi, T / M)
+    L = orc.choose_L(R, 1e-12)
+    _say("tridiag dimer10000", n, "M", M, "L", L)
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f,
+                            e_min=lo, e_max=hi, L=L)
+    X = ctx.propagate(np.eye(n, dtype=complex), 0, 2)
+    cols = [0, 3840, 7679, n - 1]
+    Xc = X[:, cols].cpu().numpy()
+    G = (X.conj().T @ X).cpu()
+    del X
+    uerr = float((G - np.eye(n)).abs().max())
+    Xref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L,
+                                X0=np.eye(n, dtype=complex)[:, cols], k_range=(0, 2))
+    err = orc.column_error(Xc, Xref)
+    _say("e_col", err, "unitarity", uerr)
+    assert err < FP64_TOL
+    assert uerr < 1e-10
 
 
 def test_tridiag_propagate(fl):
