@@ -105,6 +105,13 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)par->M);
     if (n > fq::tridiag_resident_max_n())  // two 8-plane states of up to n x n doubles
       lay.off_stream = take(2 * 8 * sizeof(double) * (size_t)n * (size_t)n);
+    if (par->checkpoint_every > 0) {  // X_{j ckpt} per column; per-column segment buffers
+      const size_t vec = 2 * sizeof(double) * (size_t)n;
+      lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
+      lay.off_tape = take(vec * (size_t)n * (size_t)lay.n_tape);
+      lay.off_seg = take(vec * (size_t)n * 3 * (size_t)par->checkpoint_every);
+      lay.off_grad = take(2 * sizeof(double) * (size_t)par->M);
+    }
   }
   lay.off_small = take(64 * sizeof(double));
   lay.off_ab = take(2 * sizeof(double) * (size_t)par->M);
@@ -153,8 +160,9 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
     // 8-plane n x n FP64 states in the workspace (128 n^2 bytes)
     if (sys->n > 40000)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal n > 40000 not supported");
-    if (par->checkpoint_every > 0)
-      return fail(FQ_ERR_UNSUPPORTED, "gradient tape not available for the tridiagonal layout");
+    if (par->checkpoint_every > 0 && sys->n > fq::tridiag_adjoint_max_n())
+      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal gradient needs n <= %ld",
+                  fq::tridiag_adjoint_max_n());
   }
   return FQ_OK;
 }
@@ -558,6 +566,11 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.ld_x0 = ncols;
   job.x_out = x_out;
   job.ld_out = ncols;
+  // a build (identity, all steps) with a gradient tape records X_{j ckpt}
+  if (c->tape && x0 == nullptr && k0 == 0 && k1 == c->M && ncols == c->n) {
+    job.tape = c->tape;
+    job.ckpt = c->ckpt;
+  }
   if (c->n <= fq::tridiag_resident_max_n()) {
     FQ_MARK(c, FQ_K_TRIDIAG);
     FQ_HIP(c, fq::launch_tridiag_resident(job, c->stream));
@@ -715,6 +728,47 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   return FQ_OK;
 }
 
+// Gradient of the tridiagonal chain: one reverse-sweep launch over all columns
+// (each workgroup recomputes its column's segments from the tape), then the
+// chain rule to the node samples as in the dense case.
+fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
+  const int M = c->M;
+  fq::TridiagAdjJob job{};
+  job.n = c->n;
+  job.ncols = c->n;
+  job.h0_diag = c->sys.h0_diag;
+  job.h0_off = reinterpret_cast<const double*>(c->sys.h0_off);
+  job.v_diag = c->sys.hmod_diag;
+  job.ab = c->d_ab;
+  job.coef = c->d_coef;
+  job.L = c->L;
+  job.M = M;
+  job.ckpt = c->ckpt;
+  job.any_b = 0;
+  for (int k = 0; k < M; ++k) job.any_b |= (c->b[k] != 0.0);
+  job.beta = c->beta;
+  job.inv_dE = 1.0 / c->dE;
+  job.phr = c->phr;
+  job.phi = c->phi;
+  job.tape = c->tape;
+  job.u_bar = U_bar;
+  job.seg = c->seg;
+  job.grad = c->d_grad;
+  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
+  FQ_HIP(c, fq::launch_tridiag_adjoint(job, c->stream));
+  std::vector<double> g(2 * (size_t)M);
+  FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  FQ_HIP(c, hipStreamSynchronize(c->stream));
+  const double w = std::sqrt(3.0) * c->h / 12.0;
+  for (int k = 0; k < M; ++k) {
+    const double ga = g[2 * k] / c->dE, gb = g[2 * k + 1] / c->dE;
+    grad_f_nodes[2 * k] = 0.5 * ga + w * gb;
+    grad_f_nodes[2 * k + 1] = 0.5 * ga - w * gb;
+  }
+  return FQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -811,8 +865,16 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->d_ab = P(lay.off_ab);
   c->d_coef = P(lay.off_coef);
   c->xr = P(lay.off_x);
-  if (sys->layout == FQ_TRIDIAG) c->d_gauge = P(lay.off_gauge);
-  if (lay.off_stream) c->d_stream = P(lay.off_stream);
+  if (sys->layout == FQ_TRIDIAG) {
+    c->d_gauge = P(lay.off_gauge);
+    if (lay.off_stream) c->d_stream = P(lay.off_stream);
+    if (lay.n_tape > 0) {
+      c->tape = P(lay.off_tape);
+      c->n_tape = lay.n_tape;
+      c->seg = P(lay.off_seg);
+      c->d_grad = P(lay.off_grad);
+    }
+  }
   c->xi = c->xr + plane;
   if (sys->layout == FQ_DENSE) {
     c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;
@@ -953,6 +1015,7 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
     FQ_HIP(c, hipEventRecord(e1, c->stream));
+    c->tape_valid = c->ckpt > 0;
     FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->stream));
     st = unitarity(c, c->xr, c->xi);
   }
@@ -998,7 +1061,7 @@ fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (c->ckpt <= 0) return fail(FQ_ERR_STATE, "context was created without a gradient tape");
   if (!c->tape_valid) return fail(FQ_ERR_STATE, "no tape: call floquet_build_UT first");
-  if (c->layout != FQ_DENSE) return fail(FQ_ERR_UNSUPPORTED, "gradient needs the dense layout");
+  if (c->layout == FQ_TRIDIAG) return tridiag_adjoint(c, U_bar, grad_f_nodes);
   // The reverse sweep and the segment recomputation run in FP64 whatever the
   // build precision: they differentiate the FP64 Chebyshev map.
   struct Restore {

@@ -159,6 +159,8 @@ struct TridiagJob {
   long ld_x0;
   void* x_out;           // device complex128 n x ncols row-major
   long ld_out;
+  double* tape;          // optional (resident kernel): X_{j ckpt} as complex, slot j at
+  int ckpt;              //   ((j * ncols + col) * n + i), written during the build
 };
 // Returns hipErrorInvalidValue when n exceeds what one workgroup can hold.
 hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
@@ -182,6 +184,25 @@ struct TridiagStream {
   long nblk;        // blocks per column = ceil(n / B)
 };
 long tridiag_stream_rows();
+
+// Gradient of the tridiagonal chain, one workgroup per column (n <= 2048).
+struct TridiagAdjJob {
+  long n, ncols;
+  const double* h0_diag;
+  const double* h0_off;   // complex128 interleaved (n-1)
+  const double* v_diag;
+  const double* ab;       // a_k, b_k
+  const double* coef;     // c_l complex interleaved
+  int L, M, ckpt;
+  int any_b;              // accumulate the K contraction
+  double beta, inv_dE, phr, phi;
+  const double* tape;     // X_{j ckpt} (forward build), complex, ((j * ncols + col) * n + i)
+  const void* u_bar;      // Lambda_M, complex128 n x ncols row-major
+  double* seg;            // per column: ckpt x 3 complex vectors of n
+  double* grad;           // 2 M accumulators: Re sum w_l <Pbar_{l+1}, D P_l>, D = Hmod, K
+};
+long tridiag_adjoint_max_n();
+hipError_t launch_tridiag_adjoint(const TridiagAdjJob& job, hipStream_t s);
 hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s);
 
 // Unit gauge factors of step s (host FP64): w_0 = 1, w_{i+1} = w_i conj(u_i) with

@@ -72,6 +72,9 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
       }
       const double2 g = gauge[(long)job.k0 * n + i];
       v = part == 0 ? g.x * xr + g.y * xi : g.x * xi - g.y * xr;  // conj(w) x
+      if (job.tape && job.k0 % job.ckpt == 0)  // checkpoint of X_{k0} (plain frame)
+        job.tape[2 * (((long)(job.k0 / job.ckpt) * job.ncols + col) * n + i) + part] =
+            part == 0 ? xr : xi;
     }
     pa[r] = v;
   }
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
     // both halves of Y meet: X~_next = phase * w_s * conj(w_{s+1}) * Y (or
     // phase * w_s * Y after the last step); this part keeps its component.
     const bool final_step = (s + 1 == job.k1);
+    const bool ckpt_step = job.tape && !final_step && (s + 1) % job.ckpt == 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       double* slot = ysh + (((long)part * G * 64 + pl) * R + r) * 2;
@@ -190,6 +194,9 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
         const double2 ws = gauge[(long)s * n + i];
         // rot = phase * w_s [* conj(w_{s+1})]
         double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
+        if (ckpt_step)  // X_{s+1} = phase w_s Y (plain frame)
+          job.tape[2 * (((long)((s + 1) / job.ckpt) * job.ncols + col) * n + i) + part] =
+              part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
         if (!final_step) {
           const double2 wn = gauge[(long)(s + 1) * n + i];
           const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
@@ -449,6 +456,321 @@ hipError_t launch_stream_r(const TridiagJob& job, const TridiagStream& st, int G
   return hipGetLastError();
 }
 
+// ---- reverse sweep (gradient) ----------------------------------------------------------------
+//
+// One workgroup per state column, W waves, R consecutive rows per lane, complex
+// values (real and imaginary parts side by side; no gauge: the operator is
+// applied in its complex tridiagonal form). For every checkpoint segment, last
+// first: the segment is recomputed forward from its tape entry, storing each
+// step's input X_k and its last two terms P_{L-1}, P_L in the column's segment
+// buffer; then the steps are reversed with the adjoint recurrence
+//   Pbar_l = (2 - delta_l0) Ht Pbar_{l+1} - Pbar_{l+2} + conj(phase c_l) Lambda,
+// the terms regenerated downwards by P_{l-1} = 2 Ht P_l - P_{l+1} (P_0 read
+// back), and the contractions (2 - delta_l0) Re <Pbar_{l+1}, D P_l> for
+// D = Hmod and D = K summed per wave and added to the step's accumulators.
+// Lambda = Pbar_0 then enters the step before.
+struct Cx {  // complex scalar helpers on (re, im) pairs
+  __device__ static __forceinline__ void mul(double ar, double ai, double br, double bi,
+                                             double& cr, double& ci) {
+    cr = ar * br - ai * bi;
+    ci = ar * bi + ai * br;
+  }
+};
+
+template <int R, int W>
+__global__ __launch_bounds__(W * 64) void tridiag_adjoint_kernel(TridiagAdjJob job) {
+  __shared__ double halo[2][4][2][W];  // [parity][value][first row / last row][wave]
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long col = blockIdx.x;
+  const long n = job.n;
+  const long base = ((long)wid * 64 + lane) * R;
+  const double2* h0o = reinterpret_cast<const double2*>(job.h0_off);
+  const double2* coef = reinterpret_cast<const double2*>(job.coef);
+  const double2* tape = reinterpret_cast<const double2*>(job.tape);
+  double2* seg = reinterpret_cast<double2*>(job.seg);
+  const long segcol = col * (long)job.ckpt * 3 * n;  // this column's segment buffer
+  const int L = job.L;
+
+  double lr[R], li[R];                 // Lambda
+  double ar[R], ai[R], br[R], bi[R];   // two P terms
+  double qr[R], qi[R], sr[R], si[R];   // two Pbar terms (Y in the forward recompute)
+  double dd[R], er[R], ei[R], kr[R], ki[R], vv[R];
+  double emr = 0.0, emi = 0.0, kmr = 0.0, kmi = 0.0;  // couplings from row base - 1
+
+  // Lambda_M = Ubar column
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const long i = base + r;
+    lr[r] = li[r] = 0.0;
+    vv[r] = 0.0;
+    if (i < n) {
+      const double2 u = reinterpret_cast<const double2*>(job.u_bar)[i * job.ncols + col];
+      lr[r] = u.x;
+      li[r] = u.y;
+      vv[r] = job.v_diag[i];
+    }
+  }
+
+  auto set_step = [&](int k) {
+    const double a = job.ab[2 * k], b = job.ab[2 * k + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      dd[r] = er[r] = ei[r] = kr[r] = ki[r] = 0.0;
+      if (i < n) {
+        dd[r] = (job.h0_diag[i] + a * vv[r] - job.beta) * job.inv_dE;
+        if (i + 1 < n) {
+          const double2 h = h0o[i];
+          const double dv = job.v_diag[i + 1] - vv[r], q = b * dv;
+          er[r] = (h.x + h.y * q) * job.inv_dE;  // h (1 - i q) / dE
+          ei[r] = (h.y - h.x * q) * job.inv_dE;
+          kr[r] = h.y * dv;                      // K = -i h dv
+          ki[r] = -h.x * dv;
+        }
+      }
+    }
+    emr = emi = kmr = kmi = 0.0;
+    if (base >= 1 && base < n) {
+      const double2 h = h0o[base - 1];
+      const double dv = job.v_diag[base] - job.v_diag[base - 1], q = b * dv;
+      emr = (h.x + h.y * q) * job.inv_dE;
+      emi = (h.y - h.x * q) * job.inv_dE;
+      kmr = h.y * dv;
+      kmi = -h.x * dv;
+    }
+  };
+
+  int parity = 0;
+  // Neighbour values of up to two complex vectors: row base - 1 (u*) and base + R (d*).
+  auto exchange = [&](const double* xr, const double* xi, const double* yr, const double* yi,
+                      double nb[8]) {
+    nb[0] = from_prev_lane(xr[R - 1]);
+    nb[1] = from_prev_lane(xi[R - 1]);
+    nb[2] = from_prev_lane(yr[R - 1]);
+    nb[3] = from_prev_lane(yi[R - 1]);
+    nb[4] = from_next_lane(xr[0]);
+    nb[5] = from_next_lane(xi[0]);
+    nb[6] = from_next_lane(yr[0]);
+    nb[7] = from_next_lane(yi[0]);
+    if constexpr (W > 1) {
+      if (lane == 0) {
+        halo[parity][0][0][wid] = xr[0];
+        halo[parity][1][0][wid] = xi[0];
+        halo[parity][2][0][wid] = yr[0];
+        halo[parity][3][0][wid] = yi[0];
+      }
+      if (lane == 63) {
+        halo[parity][0][1][wid] = xr[R - 1];
+        halo[parity][1][1][wid] = xi[R - 1];
+        halo[parity][2][1][wid] = yr[R - 1];
+        halo[parity][3][1][wid] = yi[R - 1];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double hu = (wid > 0) ? halo[parity][q][1][wid - 1] : 0.0;
+        const double hd = (wid + 1 < W) ? halo[parity][q][0][wid + 1] : 0.0;
+        nb[q] = (lane == 0) ? hu : nb[q];
+        nb[4 + q] = (lane == 63) ? hd : nb[4 + q];
+      }
+      parity ^= 1;
+    }
+  };
+  // out = f Ht x - out + (cr + i ci) lam   (f = 1 or 2; cr = ci = 0 for no source)
+  auto apply = [&](const double* xr, const double* xi, double ur, double ui, double dr_, double di_,
+                   double f, double* or_, double* oi, double cr, double ci) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double lor = (r == 0) ? ur : xr[r - 1], loi = (r == 0) ? ui : xi[r - 1];
+      const double hir = (r == R - 1) ? dr_ : xr[r + 1], hii = (r == R - 1) ? di_ : xi[r + 1];
+      const double cer = (r == 0) ? emr : er[r - 1], cei = (r == 0) ? emi : ei[r - 1];
+      // conj(e_{i-1}) x_{i-1} + e_i x_{i+1} + d_i x_i
+      double hr = dd[r] * xr[r] + cer * lor + cei * loi + er[r] * hir - ei[r] * hii;
+      double hi = dd[r] * xi[r] + cer * loi - cei * lor + er[r] * hii + ei[r] * hir;
+      or_[r] = f * hr - or_[r] + (cr * lr[r] - ci * li[r]);
+      oi[r] = f * hi - oi[r] + (cr * li[r] + ci * lr[r]);
+    }
+  };
+
+  const int nseg = (job.M + job.ckpt - 1) / job.ckpt;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int k0 = sg * job.ckpt, k1 = (k0 + job.ckpt < job.M) ? k0 + job.ckpt : job.M;
+    // ---- forward recompute of the segment from its checkpoint ----
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      ar[r] = ai[r] = 0.0;
+      if (i < n) {
+        const double2 x = tape[((long)sg * job.ncols + col) * n + i];
+        ar[r] = x.x;
+        ai[r] = x.y;
+      }
+    }
+    for (int k = k0; k < k1; ++k) {
+      set_step(k);
+      double2* sx = seg + segcol + ((long)(k - k0) * 3) * n;  // X_k, P_{L-1}, P_L
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long i = base + r;
+        if (i < n) sx[i] = make_double2(ar[r], ai[r]);
+      }
+      // P_0 in a, P_1 = Ht P_0 in b, Y (in q) = c0 P_0 + c1 P_1
+      double nb[8];
+      exchange(ar, ai, ar, ai, nb);
+#pragma unroll
+      for (int r = 0; r < R; ++r) br[r] = bi[r] = 0.0;
+      apply(ar, ai, nb[0], nb[1], nb[4], nb[5], 1.0, br, bi, 0.0, 0.0);
+      {
+        const double2 c0 = coef[0], c1 = coef[1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double t1r, t1i, t2r, t2i;
+          Cx::mul(c0.x, c0.y, ar[r], ai[r], t1r, t1i);
+          Cx::mul(c1.x, c1.y, br[r], bi[r], t2r, t2i);
+          qr[r] = t1r + t2r;
+          qi[r] = t1i + t2i;
+        }
+      }
+      // P_{l+1} = 2 Ht P_l - P_{l-1}, alternating between a (even) and b (odd)
+      for (int l = 1; l < L; ++l) {
+        // P_l is in b for odd l (P_{l-1} in a is overwritten by P_{l+1}), in a for even l
+        if (l & 1) {
+          exchange(br, bi, br, bi, nb);
+          apply(br, bi, nb[0], nb[1], nb[4], nb[5], 2.0, ar, ai, 0.0, 0.0);
+        } else {
+          exchange(ar, ai, ar, ai, nb);
+          apply(ar, ai, nb[0], nb[1], nb[4], nb[5], 2.0, br, bi, 0.0, 0.0);
+        }
+        const double2 c = coef[l + 1];
+        const bool in_a = (l & 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double pr = in_a ? ar[r] : br[r], pi = in_a ? ai[r] : bi[r];
+          double tr, ti;
+          Cx::mul(c.x, c.y, pr, pi, tr, ti);
+          qr[r] += tr;
+          qi[r] += ti;
+        }
+      }
+      // P_L is in a if L even, else in b; P_{L-1} in the other
+      const bool last_in_a = !(L & 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long i = base + r;
+        if (i < n) {
+          sx[n + i] = last_in_a ? make_double2(br[r], bi[r]) : make_double2(ar[r], ai[r]);
+          sx[2 * n + i] = last_in_a ? make_double2(ar[r], ai[r]) : make_double2(br[r], bi[r]);
+        }
+      }
+      // X_{k+1} = phase Y into a
+#pragma unroll
+      for (int r = 0; r < R; ++r) Cx::mul(job.phr, job.phi, qr[r], qi[r], ar[r], ai[r]);
+    }
+    // ---- reverse through the segment ----
+    for (int k = k1 - 1; k >= k0; --k) {
+      set_step(k);
+      const double2* sx = seg + segcol + ((long)(k - k0) * 3) * n;
+      // a = P_{L-1}, b = P_L; q = Pbar_L = d_L Lambda, s = Pbar_{L+1} = 0
+      const double2 cL = coef[L];
+      const double dLr = job.phr * cL.x - job.phi * cL.y, dLi = -(job.phr * cL.y + job.phi * cL.x);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long i = base + r;
+        ar[r] = ai[r] = br[r] = bi[r] = 0.0;
+        if (i < n) {
+          const double2 pm = sx[n + i], pl = sx[2 * n + i];
+          ar[r] = pm.x;
+          ai[r] = pm.y;
+          br[r] = pl.x;
+          bi[r] = pl.y;
+        }
+        qr[r] = dLr * lr[r] - dLi * li[r];
+        qi[r] = dLr * li[r] + dLi * lr[r];
+        sr[r] = si[r] = 0.0;
+      }
+      double gv = 0.0, gk = 0.0;
+      // one downward term: x = P_l, z = P_{l+1} (-> P_{l-1}); p = Pbar_{l+1}, o = Pbar_{l+2} (-> Pbar_l)
+      auto down = [&](double* xr_, double* xi_, double* zr, double* zi, double* pr_, double* pi_,
+                      double* or_, double* oi_, int l) {
+        double nb[8];
+        exchange(xr_, xi_, pr_, pi_, nb);
+        const double w = (l >= 1) ? 2.0 : 1.0;
+        // contractions with Hmod (diagonal) and K (tridiagonal, K_{i,i+1} = k_i)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          gv += w * vv[r] * (pr_[r] * xr_[r] + pi_[r] * xi_[r]);
+          if (job.any_b) {
+            const double lor = (r == 0) ? nb[0] : xr_[r - 1], loi = (r == 0) ? nb[1] : xi_[r - 1];
+            const double hir = (r == R - 1) ? nb[4] : xr_[r + 1],
+                         hii = (r == R - 1) ? nb[5] : xi_[r + 1];
+            const double ckr = (r == 0) ? kmr : kr[r - 1], cki = (r == 0) ? kmi : ki[r - 1];
+            // (K x)_i = conj(k_{i-1}) x_{i-1} + k_i x_{i+1}
+            const double tr = ckr * lor + cki * loi + kr[r] * hir - ki[r] * hii;
+            const double ti = ckr * loi - cki * lor + kr[r] * hii + ki[r] * hir;
+            gk += w * (pr_[r] * tr + pi_[r] * ti);
+          }
+        }
+        // Pbar_l = w Ht Pbar_{l+1} - Pbar_{l+2} + conj(phase c_l) Lambda
+        const double2 cl = coef[l];
+        const double dr = job.phr * cl.x - job.phi * cl.y, di = -(job.phr * cl.y + job.phi * cl.x);
+        apply(pr_, pi_, nb[2], nb[3], nb[6], nb[7], w, or_, oi_, dr, di);
+        // P_{l-1} = 2 Ht P_l - P_{l+1}; P_0 is read back
+        if (l == 1) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const long i = base + r;
+            zr[r] = zi[r] = 0.0;
+            if (i < n) {
+              const double2 x0 = sx[i];
+              zr[r] = x0.x;
+              zi[r] = x0.y;
+            }
+          }
+        } else if (l >= 2) {
+          apply(xr_, xi_, nb[0], nb[1], nb[4], nb[5], 2.0, zr, zi, 0.0, 0.0);
+        }
+      };
+      int l = L - 1;
+      for (; l >= 1; l -= 2) {
+        down(ar, ai, br, bi, qr, qi, sr, si, l);      // P_l in a, P_{l-1} -> b; Pbar_l -> s
+        down(br, bi, ar, ai, sr, si, qr, qi, l - 1);  // P_{l-1} in b; Pbar_{l-1} -> q
+      }
+      if (l == 0) {
+        down(ar, ai, br, bi, qr, qi, sr, si, 0);      // Pbar_0 -> s
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          lr[r] = sr[r];
+          li[r] = si[r];
+        }
+      } else {  // l == -1: Pbar_0 is in q
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          lr[r] = qr[r];
+          li[r] = qi[r];
+        }
+      }
+      // per-wave sums to the step's accumulators
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        gv += __shfl_xor(gv, o);
+        gk += __shfl_xor(gk, o);
+      }
+      if (lane == 0) {
+        atomicAdd(job.grad + 2 * k, gv);
+        if (job.any_b) atomicAdd(job.grad + 2 * k + 1, gk);
+      }
+    }
+  }
+}
+
+template <int R, int W>
+hipError_t launch_adj_r(const TridiagAdjJob& job, hipStream_t s) {
+  hipLaunchKernelGGL((tridiag_adjoint_kernel<R, W>), dim3((unsigned)job.ncols), dim3(W * 64), 0, s,
+                     job);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // 16 rows per lane and up to 4 waves per part (512 threads, <= 256 VGPRs).
@@ -474,6 +796,18 @@ hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st,
       (st.l0 == 1))
     return hipErrorInvalidValue;
   return launch_stream_r<16, 512>(job, st, 4, s);
+}
+
+long tridiag_adjoint_max_n() { return 8L * 64 * 4; }
+
+hipError_t launch_tridiag_adjoint(const TridiagAdjJob& job, hipStream_t s) {
+  if (job.n < 1 || job.ncols < 1 || job.L < 1 || job.M < 1 || job.ckpt < 1 ||
+      job.ncols > 0x7fffffffL)
+    return hipErrorInvalidValue;
+  if (job.n <= 256) return launch_adj_r<4, 1>(job, s);
+  if (job.n <= 1024) return launch_adj_r<4, 4>(job, s);
+  if (job.n <= tridiag_adjoint_max_n()) return launch_adj_r<4, 8>(job, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fq

@@ -183,6 +183,18 @@ def test_nonfinite_drive_rejected():
 def test_tridiag_restrictions():
     st, _ = _ws(_tridiag(), _params(precision=1))
     assert st == _abi.FQ_ERR_UNSUPPORTED
+    # gradient tape: per-column reverse sweep up to 2048 rows
+    st, b0 = _ws(_tridiag(2048), _params())
+    st1, b1 = _ws(_tridiag(2048), _params(checkpoint_every=4))
+    assert st == st1 == _abi.FQ_OK and b1 > b0
+    st, _ = _ws(_tridiag(2049), _params(checkpoint_every=4))
+    assert st == _abi.FQ_ERR_UNSUPPORTED
+    assert "2048" in _abi.lib().fq_last_error().decode()
+    # columns longer than one workgroup: two streamed states of n x n doubles
+    st, b = _ws(_tridiag(5000), _params())
+    assert st == _abi.FQ_OK and b >= 2 * 8 * 8 * 5000 * 5000
+    st, _ = _ws(_tridiag(40001), _params())
+    assert st == _abi.FQ_ERR_UNSUPPORTED
 
 
 def test_create_rejects_before_device_work():

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from workloads import drive_cos, gue, haar_unitary, workload
+from workloads import dimer_tridiag, drive_cos, gue, haar_unitary, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -158,3 +158,107 @@ def test_adjoint_config_full_size_against_fd(fl):
         fd = (vals[0] - vals[1]) / (2 * eps)
         _say("k", k, "adjoint", g[k], "fd", fd)
         assert abs(g[k] - fd) <= 1e-3 * abs(fd) + 1e-9
+
+
+# ---- tridiagonal (dimer) gradient ---------------------------------------------------------------
+
+def _dimer_problem(nb, M, seed, U_int=0.01):
+    d, e, v = dimer_tridiag(nb, 1.0, U_int)
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-1, 1, M)
+    W = haar_unitary(nb + 1, rng)
+    return d, e, v, f, W
+
+
+@pytest.mark.parametrize("nb,M,ckpt", [(39, 24, 5), (199, 16, 16), (700, 12, 4), (1499, 6, 2)])
+def test_tridiag_piecewise_gradient_matches_oracle(fl, nb, M, ckpt):
+    """Piecewise-constant drive on the dimer: the per-column reverse sweep
+    against the oracle's exact derivative of the same Chebyshev chain (dense
+    copies of the tridiagonal operators)."""
+    _say("tridiag grad piecewise", nb + 1, M, ckpt)
+    d, e, v, f, W = _dimer_problem(nb, M, 90 + nb)
+    T = 2.0
+    nodes = np.stack([f, f], 1)
+    a, b = orc.magnus4_weights(nodes, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-13)
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=nodes, e_min=lo,
+                            e_max=hi, L=L, checkpoint_every=ckpt)
+    U = ctx.build_ut().cpu().numpy()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar)
+    H0s, Vs, _ = orc.tridiag_matrices(d, e, v)
+    ref = orc.grad_piecewise(H0s.toarray(), Vs.toarray(), f, T, W, route="cheb", e_min=lo, e_max=hi,
+                             L=L)
+    err = np.max(np.abs(g.sum(axis=1) - ref)) / np.max(np.abs(ref))
+    _say("rel err", err, "L", L, "max|g|", np.max(np.abs(ref)))
+    assert err < 1e-9
+    assert np.max(np.abs(g[:, 0] - g[:, 1])) < 1e-12 * np.max(np.abs(g))  # b_k = 0: nodes agree
+
+
+def test_tridiag_smooth_drive_gradient_matches_oracle_differences(fl):
+    """Smooth drive on an interacting dimer (b_k != 0: the K contraction):
+    every node derivative against central differences of the oracle."""
+    nb, M = 23, 8
+    d, e, v = dimer_tridiag(nb, 1.0, 0.3)
+    W = haar_unitary(nb + 1, np.random.default_rng(78))
+    T = 2 * math.pi
+    f = drive_cos(fl.node_times(T, M), 0.5, 1.5, 1.0)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    lo, hi = lo - 1.0, hi + 1.0   # room for the perturbed drives
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-14)
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f, e_min=lo,
+                            e_max=hi, L=L, checkpoint_every=3)
+    U = ctx.build_ut().cpu().numpy()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar)
+
+    def loss(ff):
+        Uo = orc.build_ut_tridiag(d, e, v, ff, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+        return _trace_loss_and_bar(Uo, W)[0]
+
+    eps = 1e-5
+    fd = np.zeros_like(f)
+    for k in range(M):
+        for i in range(2):
+            fp, fm = f.copy(), f.copy()
+            fp[k, i] += eps
+            fm[k, i] -= eps
+            fd[k, i] = (loss(fp) - loss(fm)) / (2 * eps)
+    err = np.max(np.abs(g - fd)) / np.max(np.abs(fd))
+    _say("tridiag smooth rel err", err)
+    assert err < 1e-6
+    assert np.max(np.abs(g[:, 0] - g[:, 1])) > 1e-6 * np.max(np.abs(g))
+
+
+def test_tridiag_dimer1000_256_amplitudes_against_fd(fl):
+    """The 999-boson dimer with 256 piecewise-constant amplitudes (checkpoint
+    every 16 steps): the adjoint against central differences (h = 1e-4) of the
+    library's own FP64 build on 8 seeded amplitudes."""
+    nb, M = 999, 256
+    d, e, v, f, W = _dimer_problem(nb, M, 1508 + 50)
+    T = 2 * math.pi
+    nodes = np.stack([f, f], 1)
+    a, b = orc.magnus4_weights(nodes, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    lo, hi = lo - 10.0, hi + 10.0
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-13)
+    kw = dict(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, e_min=lo, e_max=hi, L=L)
+    ctx = fl.FloquetContext(f_nodes=nodes, checkpoint_every=16, **kw)
+    U = ctx.build_ut().cpu().numpy()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar).sum(axis=1)
+    _say("dimer1000 grad L", L, "max|g|", np.max(np.abs(g)))
+    ks = np.random.default_rng(1508 + 51).choice(M, size=8, replace=False)
+    eps = 1e-4
+    for k in ks:
+        vals = []
+        for sgn in (+1, -1):
+            ff = f.copy()
+            ff[k] += sgn * eps
+            Uf = fl.FloquetContext(f_nodes=np.stack([ff, ff], 1), **kw).build_ut().cpu().numpy()
+            vals.append(_trace_loss_and_bar(Uf, W)[0])
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        _say("k", k, "adjoint", g[k], "fd", fd)
+        assert abs(g[k] - fd) <= 1e-5 * abs(fd) + 1e-9
