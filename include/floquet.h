@@ -112,7 +112,14 @@ typedef struct fq_params {
   int32_t profile;           /* 1: time every kernel launch of a build with HIP
                                 events on the library's stream and report the
                                 per-kind sums in fq_report; 0: off */
-  int32_t reserved1;         /* must be 0 */
+  int32_t reorthonormalize;  /* 1: after the build replace U_T by its polar
+                                factor U (U^dagger U)^(-1/2), the nearest
+                                unitary matrix in the Frobenius norm, by two
+                                FP64 Newton-Schulz steps
+                                X <- X (3 - X^dagger X) / 2 on the device; the
+                                report gives the unitarity before and after
+                                (a correction of the result, not part of the
+                                paper's method). 0: off */
 } fq_params;
 
 /* Kernel kinds timed in profile mode (indices of fq_report.ms_kernel). */
@@ -134,6 +141,8 @@ typedef struct fq_report {
   double e_min, e_max;       /* interval in use */
   double unitarity_max;      /* max |(U^dagger U - 1)_ij| of the last build (FP64) */
   double unitarity_fro;      /* Frobenius norm of U^dagger U - 1 */
+  double unitarity_max_after;  /* the same after re-orthonormalisation (0 if off) */
+  double unitarity_fro_after;
   double ms_build;           /* device time of the last build, milliseconds */
   double ms_kernel[FQ_K_SLOTS];   /* profile mode: summed event time per kind */
   int32_t n_kernel[FQ_K_SLOTS];   /* profile mode: launches per kind */
@@ -185,11 +194,16 @@ fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep);
 fq_status floquet_build_UT(fq_ctx* ctx, void* U_out, fq_report* rep);
 
 /* Propagate ncols given states over steps k0+1 .. k1 (0 <= k0 <= k1 <= M):
- * X_out = E_k1 ... E_{k0+1} X0 (the second propagation round of Sec. 3 and
- * its resumption from any step). X0, X_out: device, n*ncols complex128,
- * row-major (column c is state c); they may alias. 1 <= ncols <= n. */
+ * X_out = E_k1 ... E_{k0+1} X0 (the second propagation round of Sec. 3, e.g.
+ * Floquet states over one period, and its resumption from any step). X0,
+ * X_out: device, n*ncols complex128, row-major (column c is state c); they
+ * may alias. 1 <= ncols <= n. snapshots (device, nullable): with
+ * snap_every >= 1, the states after steps k0 + j*snap_every, j = 1 ..
+ * (k1 - k0) / snap_every, are written as n*ncols complex128 blocks, block j-1
+ * at snapshots + (j-1)*n*ncols elements; snap_every must be 0 when
+ * snapshots is NULL. */
 fq_status floquet_propagate(fq_ctx* ctx, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
-                            void* X_out);
+                            void* X_out, void* snapshots, int32_t snap_every);
 
 /* Gradient of a real loss of U_T with respect to the 2*M drive samples, by
  * the reverse sweep through the Chebyshev recurrence of every step (beta, dE

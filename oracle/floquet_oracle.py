@@ -46,7 +46,8 @@ __all__ = [
     "GL2_C1", "GL2_C2", "node_times", "commutator", "magnus4_weights", "magnus4_heff",
     "bessel_coefficients", "choose_L", "rescale", "weyl_cover", "tridiag_cover",
     "exact_step", "chebyshev_step", "build_ut", "build_ut_tridiag", "tridiag_matrices",
-    "column_error", "fro_error", "unitarity_error", "eigenphases", "quasienergy_distance",
+    "column_error", "fro_error", "unitarity_error", "nearest_unitary", "eigenphases",
+    "quasienergy_distance",
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
 ]
 
@@ -326,6 +327,14 @@ def unitarity_error(U: np.ndarray) -> Tuple[float, float]:
     """(max-abs, Frobenius) norms of U^dagger U - 1."""
     G = U.conj().T @ U - np.eye(U.shape[0])
     return float(np.max(np.abs(G))), float(np.linalg.norm(G))
+
+
+def nearest_unitary(U: np.ndarray) -> np.ndarray:
+    """Polar factor U (U^dagger U)^(-1/2): the unitary matrix nearest to U in
+    the Frobenius norm (the optional re-orthonormalisation of U_T; the paper
+    only notes that the truncated expansion is unitary up to the truncation,
+    Sec. 2). SciPy's polar decomposition."""
+    return scipy.linalg.polar(np.asarray(U, np.complex128), side="right")[0]
 
 
 def eigenphases(U: np.ndarray) -> np.ndarray:

@@ -39,13 +39,14 @@ class FqParams(ctypes.Structure):
                 ("f_nodes", POINTER(c_double)),
                 ("e_min", c_double), ("e_max", c_double), ("tol", c_double),
                 ("precision", c_int32), ("checkpoint_every", c_int32),
-                ("profile", c_int32), ("reserved1", c_int32)]
+                ("profile", c_int32), ("reorthonormalize", c_int32)]
 
 
 class FqReport(ctypes.Structure):
     _fields_ = [("L", c_int32), ("M", c_int32), ("R", c_double), ("dE", c_double),
                 ("beta", c_double), ("e_min", c_double), ("e_max", c_double),
                 ("unitarity_max", c_double), ("unitarity_fro", c_double),
+                ("unitarity_max_after", c_double), ("unitarity_fro_after", c_double),
                 ("ms_build", c_double), ("ms_kernel", c_double * K_SLOTS),
                 ("n_kernel", c_int32 * K_SLOTS)]
 
@@ -88,7 +89,8 @@ def lib() -> ctypes.CDLL:
     L.fq_destroy.argtypes = [c_void_p]
     L.fq_get_report.argtypes = [c_void_p, POINTER(FqReport)]
     L.floquet_build_UT.argtypes = [c_void_p, c_void_p, POINTER(FqReport)]
-    L.floquet_propagate.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p]
+    L.floquet_propagate.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
+                                    c_void_p, c_int32]
     L.floquet_grad.argtypes = [c_void_p, c_void_p, POINTER(c_double)]
     for name in EXPORTS:
         if name != "fq_last_error":

@@ -41,6 +41,12 @@ fq_status fail(fq_status st, const char* fmt, ...) {
     }                                                                                      \
   } while (0)
 
+#define FQ_TRY(expr)                 \
+  do {                               \
+    fq_status s_ = (expr);           \
+    if (s_ != FQ_OK) return s_;      \
+  } while (0)
+
 constexpr size_t kAlign = 256;
 constexpr int kMaxOrder = 65535;       // capacity of the device coefficient table
 constexpr int kLanczosSteps = 160;
@@ -102,6 +108,11 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.np = pad_to(n, dense_tile(n));
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
     lay.off_x = take(plane2);  // planar copy of U_T for the unitarity check
+    if (par->reorthonormalize) {  // Newton-Schulz scratch: X X^dagger, X^T, next X
+      lay.off_pa = take(plane2);
+      lay.off_pb = take(plane2);
+      lay.off_y = take(plane2);
+    }
     lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)par->M);
     if (n > fq::tridiag_resident_max_n())  // two 8-plane states of up to n x n doubles
       lay.off_stream = take(2 * 8 * sizeof(double) * (size_t)n * (size_t)n);
@@ -152,7 +163,8 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
     return fail(FQ_ERR_ARG, "unknown precision %d", par->precision);
   if (par->checkpoint_every < 0) return fail(FQ_ERR_ARG, "checkpoint_every must be >= 0");
   if (par->profile != 0 && par->profile != 1) return fail(FQ_ERR_ARG, "profile must be 0 or 1");
-  if (par->reserved1 != 0) return fail(FQ_ERR_ARG, "reserved1 must be 0");
+  if (par->reorthonormalize != 0 && par->reorthonormalize != 1)
+    return fail(FQ_ERR_ARG, "reorthonormalize must be 0 or 1");
   if (sys->layout == FQ_TRIDIAG) {
     if (par->precision != FQ_FP64)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal layout runs in FP64 only");
@@ -451,12 +463,6 @@ fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, dou
   return FQ_OK;
 }
 
-#define FQ_TRY(expr)                 \
-  do {                               \
-    fq_status s_ = (expr);           \
-    if (s_ != FQ_OK) return s_;      \
-  } while (0)
-
 // One step on the state-major block held in the X planes: X <- E_k X.
 // Buffers: X and Y FP64; Pa, Pb hold P_1 .. P_L in the product format.
 fq_status dense_cheb_step(fq_ctx* c, int mrows) {
@@ -513,6 +519,12 @@ fq_status dense_steps(fq_ctx* c, int k0, int k1, int mrows, bool record_tape) {
     if (st != FQ_OK) return st;
     st = dense_cheb_step(c, mrows);
     if (st != FQ_OK) return st;
+    if (c->snap && (k + 1 - c->snap_k0) % c->snap_every == 0) {  // X_{k+1} to the user's buffer
+      const long j = (k + 1 - c->snap_k0) / c->snap_every - 1;
+      char* dst = static_cast<char*>(c->snap) + (size_t)j * 16 * (size_t)c->n * (size_t)c->snap_ncols;
+      FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->snap_ncols, dst,
+                                           c->snap_ncols, c->stream));
+    }
     if (record_tape && ((k + 1) % c->ckpt == 0 || k + 1 == c->M)) {
       const int slot = (k + 1 + c->ckpt - 1) / c->ckpt;
       double* dst = c->tape + (size_t)slot * plane2;
@@ -532,6 +544,41 @@ fq_status unitarity(fq_ctx* c, const double* xr, const double* xi) {
   FQ_HIP(c, hipStreamSynchronize(c->stream));
   c->last.unitarity_max = h[0];
   c->last.unitarity_fro = std::sqrt(h[1]);
+  return FQ_OK;
+}
+
+// Polar factor of U_T by Newton-Schulz steps X <- X (3 - X^dagger X) / 2, in
+// the state-major planes A = U^T: A <- 1.5 A - 0.5 (A A^dagger) A, where
+// (A A^dagger) A is the NT product of A A^dagger with the transpose of A.
+// Quadratic convergence from ||U^dagger U - 1|| < 1; two steps take the
+// build's residual (1e-8 for BF16x3, 1e-12 for FP64) to round-off.
+fq_status reorthonormalize(fq_ctx* c) {
+  const int np = (int)c->np;
+  const size_t p2bytes = 2 * sizeof(double) * (size_t)c->np * (size_t)c->np;
+  for (int it = 0; it < 2; ++it) {
+    FQ_HIP(c, fq::launch_zgemm_nt_f64(c->xr, c->xi, false, c->xr, c->xi, true, c->par, c->pai, np,
+                                      np, np, np, 1.0, 0.0, 0.0, 0.0, c->stream));
+    FQ_HIP(c, fq::launch_transpose_planar(c->xr, c->xi, c->pbr, c->pbi, c->np, c->stream));
+    FQ_HIP(c, hipMemcpyAsync(c->yr, c->xr, p2bytes, hipMemcpyDeviceToDevice, c->stream));
+    FQ_HIP(c, fq::launch_zgemm_nt_f64(c->par, c->pai, false, c->pbr, c->pbi, false, c->yr, c->yi,
+                                      np, np, np, np, -0.5, 0.0, 1.5, 0.0, c->stream));
+    std::swap(c->xr, c->yr);
+    std::swap(c->xi, c->yi);
+  }
+  return FQ_OK;
+}
+
+// Re-orthonormalise the planar U_T, write it to U_out and measure it again;
+// the build's own unitarity stays in unitarity_max / unitarity_fro.
+fq_status finish_reortho(fq_ctx* c, void* U_out) {
+  const double umax = c->last.unitarity_max, ufro = c->last.unitarity_fro;
+  FQ_TRY(reorthonormalize(c));
+  FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->stream));
+  FQ_TRY(unitarity(c, c->xr, c->xi));
+  c->last.unitarity_max_after = c->last.unitarity_max;
+  c->last.unitarity_fro_after = c->last.unitarity_fro;
+  c->last.unitarity_max = umax;
+  c->last.unitarity_fro = ufro;
   return FQ_OK;
 }
 
@@ -566,6 +613,10 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.ld_x0 = ncols;
   job.x_out = x_out;
   job.ld_out = ncols;
+  if (c->snap) {
+    job.snap = static_cast<double*>(c->snap);
+    job.snap_every = c->snap_every;
+  }
   // a build (identity, all steps) with a gradient tape records X_{j ckpt}
   if (c->tape && x0 == nullptr && k0 == 0 && k1 == c->M && ncols == c->n) {
     job.tape = c->tape;
@@ -847,6 +898,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->precision = par->precision;
   c->ckpt = par->checkpoint_every;
   c->profile = par->profile != 0;
+  c->reortho = par->reorthonormalize != 0;
   c->f_nodes.assign(par->f_nodes, par->f_nodes + 2 * par->M);
   c->a.resize(c->M);
   c->b.resize(c->M);
@@ -866,6 +918,11 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->d_coef = P(lay.off_coef);
   c->xr = P(lay.off_x);
   if (sys->layout == FQ_TRIDIAG) {
+    if (par->reorthonormalize) {
+      c->par = P(lay.off_pa); c->pai = c->par + plane;
+      c->pbr = P(lay.off_pb); c->pbi = c->pbr + plane;
+      c->yr = P(lay.off_y);   c->yi = c->yr + plane;
+    }
     c->d_gauge = P(lay.off_gauge);
     if (lay.off_stream) c->d_stream = P(lay.off_stream);
     if (lay.n_tape > 0) {
@@ -1009,6 +1066,7 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->stream));
     c->tape_valid = c->ckpt > 0;
     st = unitarity(c, c->xr, c->xi);
+    if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
   } else {
     FQ_HIP(c, hipEventRecord(e0, c->stream));
     st = tridiag_run(c, nullptr, c->n, 0, c->M, U_out);
@@ -1018,6 +1076,7 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     c->tape_valid = c->ckpt > 0;
     FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->stream));
     st = unitarity(c, c->xr, c->xi);
+    if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
   }
   if (st != FQ_OK) return st;
   FQ_HIP(c, hipEventSynchronize(e1));
@@ -1034,11 +1093,21 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
 }
 
 fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
-                            void* X_out) {
+                            void* X_out, void* snapshots, int32_t snap_every) {
   if (!c || !X0 || !X_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
   if (k0 < 0 || k1 < k0 || k1 > c->M) return fail(FQ_ERR_ARG, "need 0 <= k0 <= k1 <= M");
+  if (snapshots && snap_every < 1) return fail(FQ_ERR_ARG, "snap_every must be >= 1 with snapshots");
+  if (!snapshots && snap_every != 0) return fail(FQ_ERR_ARG, "snap_every without a snapshot buffer");
+  struct SnapReset {
+    fq_ctx* c;
+    ~SnapReset() { c->snap = nullptr; }
+  } snap_reset{c};
+  c->snap = snapshots;
+  c->snap_every = snap_every;
+  c->snap_k0 = k0;
+  c->snap_ncols = ncols;
   c->n_events = 0;
   if (c->layout == FQ_DENSE) {
     const long mrows = pad_to(ncols, dense_tile(c->n));

@@ -136,6 +136,9 @@ hipError_t launch_heff_f64(const double* h0r, const double* h0i, const double* v
                            const double* vi, const double* kr, const double* ki, double a,
                            double b, double beta, double dE, long n, long ld, double* hr,
                            double* hi, hipStream_t s);
+// dst = src^T for np x np planar pairs (dst must not alias src).
+hipError_t launch_transpose_planar(const double* sr, const double* si, double* dr, double* di,
+                                   long np, hipStream_t s);
 // t = d * s elementwise on count planar complex elements.
 hipError_t launch_scale_planar(const double* sr, const double* si, double dr, double di,
                                double* tr, double* ti, long count, hipStream_t s);
@@ -161,6 +164,8 @@ struct TridiagJob {
   long ld_out;
   double* tape;          // optional (resident kernel): X_{j ckpt} as complex, slot j at
   int ckpt;              //   ((j * ncols + col) * n + i), written during the build
+  double* snap;          // optional: X_{k0 + (j+1) snap_every}, complex128 n x ncols row-major
+  int snap_every;        //   at snap + 2 j n ncols
 };
 // Returns hipErrorInvalidValue when n exceeds what one workgroup can hold.
 hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
@@ -257,6 +262,10 @@ struct fq_ctx {
   // profile mode: one event before every launch of a build (and one after the
   // last); launch i took the time between events i and i+1.
   bool profile = false;
+  bool reortho = false;               // polar factor of U_T after the build
+  void* snap = nullptr;               // propagate: snapshot buffer, every snap_every steps
+  int snap_every = 0, snap_k0 = 0;
+  long snap_ncols = 0;
   std::vector<hipEvent_t> events;
   std::vector<int> event_kind;
   size_t n_events = 0;

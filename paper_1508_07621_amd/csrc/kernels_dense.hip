@@ -469,6 +469,25 @@ inline unsigned grid_for(long total, int block) {
   return (unsigned)g;
 }
 
+// dst(j, i) = src(i, j) through 32 x 32 LDS tiles (one padding column).
+__global__ __launch_bounds__(256) void transpose_planar_kernel(const double* __restrict__ sr,
+                                                               const double* __restrict__ si,
+                                                               double* __restrict__ dr,
+                                                               double* __restrict__ di, long np) {
+  __shared__ double tr[32][33], ti[32][33];
+  const long bi = blockIdx.y * 32L, bj = blockIdx.x * 32L;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int r = ty; r < 32; r += 8) {
+    tr[r][tx] = sr[(bi + r) * np + bj + tx];
+    ti[r][tx] = si[(bi + r) * np + bj + tx];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    dr[(bj + r) * np + bi + tx] = tr[tx][r];
+    di[(bj + r) * np + bi + tx] = ti[tx][r];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s) {
@@ -572,6 +591,14 @@ hipError_t launch_zgemv(const void* A, long n, const void* x, void* y, hipStream
   hipLaunchKernelGGL(zgemv_kernel, dim3((unsigned)n), dim3(256), 0, s,
                      reinterpret_cast<const double2*>(A), n, reinterpret_cast<const double2*>(x),
                      reinterpret_cast<double2*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_planar(const double* sr, const double* si, double* dr, double* di,
+                                   long np, hipStream_t s) {
+  if (np < 32 || np % 32 != 0 || np / 32 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_planar_kernel, dim3((unsigned)(np / 32), (unsigned)(np / 32)),
+                     dim3(256), 0, s, sr, si, dr, di, np);
   return hipGetLastError();
 }
 

@@ -174,6 +174,8 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
     // phase * w_s * Y after the last step); this part keeps its component.
     const bool final_step = (s + 1 == job.k1);
     const bool ckpt_step = job.tape && !final_step && (s + 1) % job.ckpt == 0;
+    const bool snap_step = job.snap && (s + 1 - job.k0) % job.snap_every == 0;
+    const long snap_j = snap_step ? (s + 1 - job.k0) / job.snap_every - 1 : 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       double* slot = ysh + (((long)part * G * 64 + pl) * R + r) * 2;
@@ -194,9 +196,10 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
         const double2 ws = gauge[(long)s * n + i];
         // rot = phase * w_s [* conj(w_{s+1})]
         double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
-        if (ckpt_step)  // X_{s+1} = phase w_s Y (plain frame)
-          job.tape[2 * (((long)((s + 1) / job.ckpt) * job.ncols + col) * n + i) + part] =
-              part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
+        const double plain = part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;  // X_{s+1}
+        if (ckpt_step)
+          job.tape[2 * (((long)((s + 1) / job.ckpt) * job.ncols + col) * n + i) + part] = plain;
+        if (snap_step) job.snap[2 * ((snap_j * n + i) * job.ncols + col) + part] = plain;
         if (!final_step) {
           const double2 wn = gauge[(long)(s + 1) * n + i];
           const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
@@ -432,6 +435,11 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     const double yr = part == 0 ? own : oth, yi = part == 0 ? oth : own;
     const double2 ws = gauge[(long)s * n + i];
     double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
+    if (job.snap && (s + 1 - job.k0) % job.snap_every == 0) {  // X_{s+1}, plain frame
+      const long j = (s + 1 - job.k0) / job.snap_every - 1;
+      job.snap[2 * ((j * n + i) * job.ncols + col) + part] =
+          part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
+    }
     if (!st.last_step) {
       const double2 wn = gauge[(long)(s + 1) * n + i];
       const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;

@@ -74,13 +74,15 @@ class FloquetContext:
     h0_off (n-1 complex, H0[i][i+1]), hmod_diag (n real).
     f_nodes: (M, 2) drive samples at node_times(T, M).
     precision: "fp64", "fp32" or "bf16x3" (arithmetic of the Chebyshev products).
+    reorthonormalize: replace U_T by its polar factor after each build (FP64
+    Newton-Schulz); the report keeps the unitarity before and after.
     """
 
     def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_diag=None,
                  h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
                  e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
                  precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
-                 device=None):
+                 reorthonormalize: bool = False, device=None):
         torch = _torch()
         L_ = lib()
         self.device = torch.device(device if device is not None else "cuda")
@@ -122,6 +124,7 @@ class FloquetContext:
         par.precision = _abi.PRECISIONS[precision]
         par.checkpoint_every = int(checkpoint_every)
         par.profile = 1 if profile else 0
+        par.reorthonormalize = 1 if reorthonormalize else 0
         self.precision = precision
         import ctypes
         nbytes = ctypes.c_size_t(0)
@@ -154,8 +157,10 @@ class FloquetContext:
         self.last_report = r.as_dict()
         return out
 
-    def propagate(self, X0, k0: int = 0, k1: Optional[int] = None, out=None):
-        """E_k1 ... E_{k0+1} X0 for an n x ncols complex block X0 (columns = states)."""
+    def propagate(self, X0, k0: int = 0, k1: Optional[int] = None, out=None, snap_every: int = 0):
+        """E_k1 ... E_{k0+1} X0 for an n x ncols complex block X0 (columns = states).
+        With snap_every > 0 also returns the states after steps k0 + j snap_every
+        as a ((k1 - k0) // snap_every, n, ncols) tensor."""
         torch = _torch()
         k1 = self.M if k1 is None else int(k1)
         X0 = _device_tensor(X0, torch.complex128, self.device)
@@ -163,10 +168,17 @@ class FloquetContext:
             raise ValueError("X0 must be n x ncols")
         if out is None:
             out = torch.empty_like(X0)
+        snaps = None
+        if snap_every > 0:
+            count = (k1 - int(k0)) // int(snap_every)
+            snaps = torch.empty((max(count, 1),) + tuple(X0.shape), dtype=torch.complex128,
+                                device=self.device)[:count]
         with torch.cuda.device(self.device):
             check(lib().floquet_propagate(self._ctx, X0.data_ptr(), int(X0.shape[1]), int(k0), k1,
-                                          out.data_ptr()))
-        return out
+                                          out.data_ptr(),
+                                          snaps.data_ptr() if snaps is not None else None,
+                                          int(snap_every)))
+        return (out, snaps) if snaps is not None else out
 
     def grad(self, U_bar) -> np.ndarray:
         """d loss / d f_nodes, shape (M, 2), for U_bar = dL/dRe U + i dL/dIm U."""

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 5 * 8
     assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 4 * 4
-    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 8 * 8 + 8 * 8 + 4 * 8
+    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 8 * 8 + 4 * 8
 
 
 def test_node_times_match_oracle():
@@ -162,7 +162,7 @@ def test_workspace_bytes_ok_and_grows_with_n():
     (lambda s, p: setattr(p, "precision", 9), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "checkpoint_every", -2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "profile", 2), _abi.FQ_ERR_ARG),
-    (lambda s, p: setattr(p, "reserved1", 1), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "reorthonormalize", 2), _abi.FQ_ERR_ARG),
 ])
 def test_invalid_arguments_rejected(mutate, status):
     s, p = _dense(), _params()
@@ -212,7 +212,7 @@ def test_null_context_calls_rejected():
     L = _abi.lib()
     g = np.zeros(8)
     assert L.floquet_build_UT(None, FAKE, None) == _abi.FQ_ERR_ARG
-    assert L.floquet_propagate(None, FAKE, 1, 0, 1, FAKE) == _abi.FQ_ERR_ARG
+    assert L.floquet_propagate(None, FAKE, 1, 0, 1, FAKE, None, 0) == _abi.FQ_ERR_ARG
     assert L.floquet_grad(None, FAKE, _abi.dptr(g)) == _abi.FQ_ERR_ARG
     assert L.fq_node_times(1.0, 0, _abi.dptr(g)) == _abi.FQ_ERR_ARG
     assert L.fq_bessel_weights(-1.0, 3, _abi.dptr(g)) == _abi.FQ_ERR_ARG

@@ -246,6 +246,84 @@ def test_dense_mixed_low_orders_and_propagate(fl, precision):
     assert orc.column_error(X, Xref) < MIXED_TOL
 
 
+# ---- optional re-orthonormalisation ------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("bf16x3", 1e-6)])
+def test_dense_reorthonormalized_matches_oracle_polar_factor(fl, precision, tol):
+    """Two FP64 Newton-Schulz steps after the build: against the polar factor
+    of the oracle's U_T; the report keeps the build's own unitarity."""
+    n, M = 200, 20
+    H0, V = _dense_case(n, 13)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    kw = dict(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L, precision=precision)
+    plain = fl.FloquetContext(**kw)
+    U0 = plain.build_ut().cpu().numpy()
+    ctx = fl.FloquetContext(reorthonormalize=True, **kw)
+    U = ctx.build_ut().cpu().numpy()
+    rep = ctx.last_report
+    Uref = orc.nearest_unitary(orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L))
+    err = orc.column_error(U, Uref)
+    _say("reortho", precision, "e_col", err, "before", rep["unitarity_max"], "after",
+         rep["unitarity_max_after"])
+    assert err < tol
+    assert rep["unitarity_max_after"] < 1e-14
+    assert rep["unitarity_max"] == plain.last_report["unitarity_max"]
+    assert orc.unitarity_error(U)[0] < 1e-14
+    assert orc.column_error(U, U0) < 10 * max(rep["unitarity_max"], 1e-15) + 1e-13
+
+
+def test_tridiag_reorthonormalized_matches_oracle_polar_factor(fl):
+    ctx, (d, e, v, f, T, lo, hi, L) = _dimer_ctx(fl, 128, 0.01, 20)
+    ctx2 = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=20, f_nodes=f, e_min=lo,
+                             e_max=hi, L=L, reorthonormalize=True)
+    U = ctx2.build_ut().cpu().numpy()
+    Uref = orc.nearest_unitary(orc.build_ut_tridiag(d, e, v, f, T, 20, route="cheb", e_min=lo,
+                                                    e_max=hi, L=L))
+    err = orc.column_error(U, Uref)
+    _say("tridiag reortho e_col", err, "after", ctx2.last_report["unitarity_max_after"])
+    assert err < FP64_TOL
+    assert ctx2.last_report["unitarity_max_after"] < 1e-14
+
+
+# ---- propagation with snapshots ----------------------------------------------------------------------
+
+def test_dense_propagate_snapshots(fl):
+    """States after steps k0 + j s (the second round over a period): every
+    snapshot against the oracle's propagation over the same steps."""
+    n, M = 100, 12
+    H0, V = _dense_case(n, 21)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L)
+    X0 = haar_unitary(n, np.random.default_rng(5))[:, :7]
+    X, snaps = ctx.propagate(X0, 2, 11, snap_every=3)
+    assert snaps.shape == (3, n, 7)
+    for j, k in enumerate((5, 8, 11)):
+        ref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0,
+                           k_range=(2, k))
+        assert orc.column_error(snaps[j].cpu().numpy(), ref) < FP64_TOL
+    assert np.array_equal(snaps[2].cpu().numpy(), X.cpu().numpy())
+
+
+@pytest.mark.parametrize("nb,M,steps,every", [(150, 12, (1, 9), 2), (4499, 300, (0, 3), 1)])
+def test_tridiag_propagate_snapshots(fl, nb, M, steps, every):
+    ctx, (d, e, v, f, T, lo, hi, L) = _dimer_ctx(fl, nb, 0.05, M)
+    n = nb + 1
+    X0 = np.eye(n, dtype=complex)[:, [0, n // 2, n - 1]]
+    X, snaps = ctx.propagate(X0, *steps, snap_every=every)
+    ks = list(range(steps[0] + every, steps[1] + 1, every))
+    assert snaps.shape[0] == len(ks)
+    for j, k in enumerate(ks):
+        ref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, X0=X0,
+                                   k_range=(steps[0], k))
+        err = orc.column_error(snaps[j].cpu().numpy(), ref)
+        _say("snapshot", n, k, err)
+        assert err < FP64_TOL
+
+
 # ---- tridiagonal (dimer) FP64 ---------------------------------------------------------------------
 
 def _dimer_ctx(fl, nb, U_int, M, eps0=0.5, eps1=1.5, L=None, tol=1e-12):

@@ -396,3 +396,18 @@ def test_work_model_matches_paper_operation_counts():
     for N, oc in rows:
         ratio = 4.0 * oc * 1e6 / (M * L * 8.0 * N ** 3)
         assert 1.0 <= ratio < 1.04, (N, ratio)
+
+
+def test_nearest_unitary_is_the_polar_factor():
+    """A = Q P with Q unitary and P Hermitian positive definite has the unique
+    polar factor Q; a unitary input is its own polar factor."""
+    rng = np.random.default_rng(11)
+    n = 12
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Q, _ = np.linalg.qr(Z)
+    S = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    P = scipy.linalg.expm(0.05 * (S + S.conj().T))          # Hermitian positive definite
+    assert np.max(np.abs(orc.nearest_unitary(Q @ P) - Q)) < 1e-13
+    assert np.max(np.abs(orc.nearest_unitary(Q) - Q)) < 1e-14
+    W = orc.nearest_unitary(Q @ P)
+    assert orc.unitarity_error(W)[0] < 1e-14
