@@ -34,8 +34,14 @@ __device__ __forceinline__ double from_next_lane(double v) {  // lane l <- lane 
   return __hiloint2double(hi, lo);
 }
 
+// coef, tape and snap come as separate restrict-qualified arguments so that the
+// checkpoint and snapshot stores inside the step loop cannot be taken to alias
+// the coefficient table, which then stays on scalar loads.
 template <int R, int MAXT, bool MULTI>
-__global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int G) {
+__global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int G,
+                                                             const double2* __restrict__ coef,
+                                                             double* __restrict__ tape,
+                                                             double* __restrict__ snap) {
   extern __shared__ double ysh[];  // [part][lane in part][r][2]
   __shared__ double halo[2][2][2][kMaxWaves];  // [parity][part][0 first row, 1 last row][wave]
 
@@ -47,7 +53,6 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
   const long base = (long)pl * R;
   const double sgn = part == 0 ? 1.0 : -1.0;
   const double2* gauge = reinterpret_cast<const double2*>(job.gauge);
-  const double2* coef = reinterpret_cast<const double2*>(job.coef);
   const double2* h0o = reinterpret_cast<const double2*>(job.h0_off);
 
   double pa[R], pb[R];  // the two most recent terms (roles alternate)
@@ -72,8 +77,8 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
       }
       const double2 g = gauge[(long)job.k0 * n + i];
       v = part == 0 ? g.x * xr + g.y * xi : g.x * xi - g.y * xr;  // conj(w) x
-      if (job.tape && job.k0 % job.ckpt == 0)  // checkpoint of X_{k0} (plain frame)
-        job.tape[2 * (((long)(job.k0 / job.ckpt) * job.ncols + col) * n + i) + part] =
+      if (tape && job.k0 % job.ckpt == 0)  // checkpoint of X_{k0} (plain frame)
+        tape[2 * (((long)(job.k0 / job.ckpt) * job.ncols + col) * n + i) + part] =
             part == 0 ? xr : xi;
     }
     pa[r] = v;
@@ -94,17 +99,28 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
       parity ^= 1;
     }
   };
-  // nw = 2 G v - nw (in place over the older term)
+  // nw = 2 G v - nw (in place over the older term). The two edge rows, which
+  // take the neighbour lanes' values, go first: their inputs (the previous
+  // term's edge rows) are then the oldest results in flight, and the shifted
+  // values of this term's edges are ready long before the next term needs them.
   auto advance = [&](const double* v, double* nw) {
     double up, dn;
     neighbours(v, up, dn);
+    {
+      double t = fma(d2[0], v[0], -nw[0]);
+      t = fma(gm2, up, t);
+      nw[0] = fma(g2[0], (R > 1) ? v[1] : dn, t);
+    }
+    if constexpr (R > 1) {
+      double t = fma(d2[R - 1], v[R - 1], -nw[R - 1]);
+      t = fma(g2[R - 2], v[R - 2], t);
+      nw[R - 1] = fma(g2[R - 1], dn, t);
+    }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double lo = (r == 0) ? up : v[r - 1];
-      const double hi = (r == R - 1) ? dn : v[r + 1];
+    for (int r = 1; r < R - 1; ++r) {
       double t = fma(d2[r], v[r], -nw[r]);
-      t = fma((r == 0) ? gm2 : g2[r - 1], lo, t);
-      nw[r] = fma(g2[r], hi, t);
+      t = fma(g2[r - 1], v[r - 1], t);
+      nw[r] = fma(g2[r], v[r + 1], t);
     }
   };
   // c_l P_l into the sum: even l has real c_l (this component), odd l imaginary
@@ -173,8 +189,8 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
     // both halves of Y meet: X~_next = phase * w_s * conj(w_{s+1}) * Y (or
     // phase * w_s * Y after the last step); this part keeps its component.
     const bool final_step = (s + 1 == job.k1);
-    const bool ckpt_step = job.tape && !final_step && (s + 1) % job.ckpt == 0;
-    const bool snap_step = job.snap && (s + 1 - job.k0) % job.snap_every == 0;
+    const bool ckpt_step = tape && !final_step && (s + 1) % job.ckpt == 0;
+    const bool snap_step = snap && (s + 1 - job.k0) % job.snap_every == 0;
     const long snap_j = snap_step ? (s + 1 - job.k0) / job.snap_every - 1 : 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -198,8 +214,8 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
         double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
         const double plain = part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;  // X_{s+1}
         if (ckpt_step)
-          job.tape[2 * (((long)((s + 1) / job.ckpt) * job.ncols + col) * n + i) + part] = plain;
-        if (snap_step) job.snap[2 * ((snap_j * n + i) * job.ncols + col) + part] = plain;
+          tape[2 * (((long)((s + 1) / job.ckpt) * job.ncols + col) * n + i) + part] = plain;
+        if (snap_step) snap[2 * ((snap_j * n + i) * job.ncols + col) + part] = plain;
         if (!final_step) {
           const double2 wn = gauge[(long)(s + 1) * n + i];
           const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
@@ -225,7 +241,8 @@ template <int R, int MAXT, bool MULTI>
 hipError_t launch_r(const TridiagJob& job, int G, hipStream_t s) {
   const size_t shmem = sizeof(double) * 2 * (size_t)G * 64 * R * 2;
   hipLaunchKernelGGL((tridiag_gauge_kernel<R, MAXT, MULTI>), dim3((unsigned)job.ncols),
-                     dim3(2 * G * 64), shmem, s, job, G);
+                     dim3(2 * G * 64), shmem, s, job, G,
+                     reinterpret_cast<const double2*>(job.coef), job.tape, job.snap);
   return hipGetLastError();
 }
 
