@@ -41,6 +41,11 @@ WORKLOAD_TEXT = {
     "dimer1000": "Bose-Hubbard dimer, 999 bosons (N=1000, tridiagonal), J=1, U=0.01, "
                  "eps=0.5+1.5cos t, T=2pi, M=500",
     "gue64": "random-matrix model N=64 (GUE H0, V), f=cos t, T=2pi, M=100",
+    "adjoint1024": "adjoint: random-matrix model N=1024, piecewise-constant f_j ~ U(-1,1), M=256, "
+                   "loss 1-|Tr(W^dagger U)|^2/N^2 with Haar W, checkpoint every 16 steps; "
+                   "step = forward build + gradient",
+    "dimer10000": "Bose-Hubbard dimer, 9999 bosons (N=10^4, tridiagonal), params as dimer1000, M=500",
+    "gue10000": "random-matrix model N=10^4 (GUE H0, V), f=cos t, T=2pi, M=200",
 }
 
 
@@ -49,7 +54,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gue4096", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="gue4096", choices=sorted(WORKLOAD_TEXT),
+                    help="gue4096 (default), dimer1000, gue64, adjoint1024 (build + gradient), "
+                         "dimer10000, gue10000 (minutes per build)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the dense Chebyshev products (the tridiagonal path is FP64)")
     ap.add_argument("--no-fp64-ref", action="store_true",
@@ -196,6 +203,33 @@ def time_builds(ctx, U, warmup: int, steps: int, tag: str):
     return (time.perf_counter() - t0) / steps, reports
 
 
+def time_build_grad(ctx, U, W, warmup: int, steps: int):
+    """Forward build with the gradient tape, then the reverse sweep for the loss
+    1 - |Tr(W^dagger U)|^2 / N^2 (U_bar formed on the device); K timed pairs."""
+    import torch
+    n = U.shape[0]
+
+    def one():
+        ctx.build_ut(out=U)
+        tau = torch.sum(torch.conj(W) * U)
+        ubar = (-2.0 / n ** 2) * tau * W
+        t0 = time.perf_counter()
+        ctx.grad(ubar)
+        return time.perf_counter() - t0
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    reports, gsum = [], 0.0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        gsum += one()
+        reports.append(ctx.last_report)
+        _log(f"build+grad {i + 1}/{steps}: build {reports[-1]['ms_build']:.1f} ms")
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, reports, 1e3 * gsum / steps
+
+
 def dense_roofline(reports, n: int, precision: str, workload: str):
     from paper_1508_07621_amd._abi import K_MID
     n_launch = sum(r["n_kernel"][K_MID] for r in reports)
@@ -242,6 +276,7 @@ def main():
               "not an implemented path", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_1508_07621_amd import floquet as fl
@@ -260,7 +295,12 @@ def main():
         return
     wl = workload(args.workload)
     precision = args.precision if wl.layout == "dense" else "fp64"
-    if args.workload == "dimer1000":
+    grad_mode = args.workload == "adjoint1024"
+    if grad_mode:
+        f_nodes = np.stack([wl.amplitudes, wl.amplitudes], 1)
+        if args.precision == "bf16x3" and "--precision" not in sys.argv:
+            precision = "fp32"  # the configuration's complex64 forward
+    elif wl.layout == "tridiag":
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.5, 1.5, 1.0)
     else:
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.0, 1.0, 1.0)
@@ -272,7 +312,8 @@ def main():
 
     t_setup = time.perf_counter()
     ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision=precision,
-                            profile=True, device=dev, **kw)
+                            profile=True, device=dev, checkpoint_every=16 if grad_mode else 0,
+                            **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     info = ctx.report
@@ -280,15 +321,24 @@ def main():
          f"interval=[{info['e_min']:.6g}, {info['e_max']:.6g}]")
     n = wl.n
     U = torch.empty((n, n), dtype=torch.complex128, device=dev)
-    s_per_build, reports = time_builds(ctx, U, args.warmup, args.steps, precision)
+    if grad_mode:
+        W = torch.from_numpy(wl.arrays["w"]).to(dev)
+        s_per_build, reports, grad_ms = time_build_grad(ctx, U, W, args.warmup, args.steps)
+    else:
+        s_per_build, reports = time_builds(ctx, U, args.warmup, args.steps, precision)
     last = reports[-1]
     errors = {"unitarity_max": last["unitarity_max"], "unitarity_fro": last["unitarity_fro"]}
 
     extra = {}
+    if grad_mode:
+        extra["gradient"] = {"ms_per_grad": round(grad_ms, 3),
+                             "ms_per_build": round(1e3 * s_per_build - grad_ms, 3),
+                             "note": "value = forward build (FP32 products, tape every 16 steps) "
+                                     "+ FP64 reverse sweep for the 256 amplitudes"}
     if wl.layout == "dense":
         roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
-        if precision != "fp64" and not args.no_fp64_ref:
+        if precision != "fp64" and not args.no_fp64_ref and not grad_mode:
             # The FP64 build of the same workload: reference result and timing.
             ref = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision="fp64",
                                     e_min=info["e_min"], e_max=info["e_max"], L=info["L"],
@@ -317,7 +367,9 @@ def main():
     else:
         n_launch = sum(r["n_kernel"][K_TRIDIAG] for r in reports)
         ms_launch = sum(r["ms_kernel"][K_TRIDIAG] for r in reports) / max(n_launch, 1)
-        flops = float(TRIDIAG_FLOPS_PER_ELEMENT_TERM) * n * n * wl.M * info["L"]
+        per_build = max(n_launch // max(len(reports), 1), 1)  # launches per build
+        # algorithmic work of one launch: the build's total over its launches
+        flops = float(TRIDIAG_FLOPS_PER_ELEMENT_TERM) * n * n * wl.M * info["L"] / per_build
         achieved = flops / (ms_launch * 1e-3) / 1e12
         tr = recorded_traffic("tridiag", args.workload)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
@@ -325,7 +377,7 @@ def main():
                 "traffic": tr["bytes"] if tr else None, "traffic_detail": tr, "kernel": "tridiag_gauge_kernel<16,512> (whole chain per state column, real gauge form)",
                 "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
                 "algorithmic_flops_per_launch": flops}
-        build_tflops = flops / s_per_build / 1e12
+        build_tflops = flops * per_build / s_per_build / 1e12
 
     out = {
         "metric": "s per U_T build + TFLOP/s (% MFMA/HBM peak), mixed vs FP64 at stated error",
@@ -350,7 +402,7 @@ def main():
         "roofline": roof,
     }
     out.update(extra)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not grad_mode and wl.n <= 4096:
         _log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(wl, f_nodes, args.cpu_seconds)
     print(json.dumps(out), flush=True)

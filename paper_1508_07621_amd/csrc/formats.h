@@ -28,6 +28,10 @@ __device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, i
   }
 }
 
+// 128 x 128 output tiles only when they make at least 256 workgroups (one per
+// CU); smaller products take 64 x 64 tiles so that every CU has work.
+constexpr long kBigTileElems = 256L * 128 * 128;
+
 typedef uint16_t u16;
 
 __device__ __forceinline__ u16 bf16_bits(__bf16 v) { return __builtin_bit_cast(u16, v); }

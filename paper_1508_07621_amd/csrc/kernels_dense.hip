@@ -322,7 +322,7 @@ struct EpiAdjDot {
 template <bool CONJ_A, bool CONJ_B, class Epi>
 hipError_t launch_gemm(const Operands& op0, int mrows, int ncols, Epi epi, hipStream_t s) {
   Operands op = op0;
-  if (mrows % 128 == 0 && ncols % 128 == 0 && (long)mrows * ncols >= 512L * 1024) {
+  if (mrows % 128 == 0 && ncols % 128 == 0 && (long)mrows * ncols >= kBigTileElems) {
     op.tiles_m = mrows / 128;
     op.tiles_n = ncols / 128;
     hipLaunchKernelGGL((zgemm_nt_f64_kernel<128, 128, 16, 2, 4, CONJ_A, CONJ_B, Epi>),

@@ -509,7 +509,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
 
 template <bool A_F64, class Epi>
 hipError_t launch_f32(MixOperands op, int mrows, int np, Epi epi, hipStream_t s) {
-  if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= 512L * 1024) {
+  if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= kBigTileElems) {
     op.tiles_m = mrows / 128;
     op.tiles_n = np / 128;
     hipLaunchKernelGGL((cheb_f32_kernel<128, 128, 32, 2, 4, A_F64, Epi>),
@@ -529,7 +529,7 @@ template <int KIND, bool P_F64>
 hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
   Bf3Args g = g0;
   const int np = g.np;
-  if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= 512L * 1024) {
+  if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= kBigTileElems) {
     g.tiles_m = mrows / 128;
     g.tiles_n = np / 128;
     hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64>),
