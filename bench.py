@@ -271,7 +271,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}, "
+        print(f"bench.py: measures one GPU only (got --gpus {args.gpus}, "
               f"WORLD_SIZE {world}); the column-sharded multi-GPU layout is a design note, "
               "not an implemented path", file=sys.stderr)
         sys.exit(2)

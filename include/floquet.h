@@ -54,7 +54,7 @@ typedef enum {
   FQ_ERR_NONFINITE = 2,    /* NaN / Inf in a host scalar or array argument */
   FQ_ERR_SPECTRUM = 3,     /* given interval does not contain the library's bounds */
   FQ_ERR_HIP = 4,          /* a HIP runtime call failed; the context is unusable */
-  FQ_ERR_UNSUPPORTED = 5,  /* valid request this build does not implement */
+  FQ_ERR_UNSUPPORTED = 5,  /* valid request the library does not implement */
   FQ_ERR_STATE = 6         /* call out of order (e.g. floquet_grad without a tape) */
 } fq_status;
 

@@ -12,14 +12,21 @@ namespace fq {
 
 // Output tile of workgroup `bid` in a tiles_m x tiles_n grid. Workgroups are
 // dispatched round-robin over the 8 XCDs (XCD = bid % 8), and each XCD has its
-// own L2. When tiles_m divides by 8, XCD x owns the tile rows
-// [x r, (x+1) r), r = tiles_m / 8, and walks them column by column with all r
-// rows interleaved: the ~32 workgroups resident on one XCD then cover r rows
-// and a few columns, so they stream r A panels and a few B panels, which its
-// L2 can hold, instead of one distinct panel pair each.
+// own L2. XCD x owns the tile rows [x r, (x+1) r), r = grid_rows / 8, and walks
+// them column by column with all r rows interleaved: the ~32 workgroups resident
+// on one XCD then cover r rows and a few columns, so they stream r A panels and
+// a few B panels, which its L2 can hold, instead of one distinct panel pair
+// each. When tiles_m is not a multiple of 8 but large, the grid is padded to
+// the next multiple (grid_rows) and the padding workgroups (tm >= tiles_m)
+// return at once; small odd grids keep row-major order.
+__host__ __device__ __forceinline__ int grid_rows(int tiles_m) {
+  if (tiles_m % 8 == 0 || tiles_m < 64) return tiles_m;
+  return (tiles_m + 7) / 8 * 8;
+}
 __device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
-  if (tiles_m % 8 == 0) {
-    const int x = bid % 8, local = bid / 8, r = tiles_m / 8;
+  const int tp = grid_rows(tiles_m);
+  if (tp % 8 == 0) {
+    const int x = bid % 8, local = bid / 8, r = tp / 8;
     tm = x * r + local % r;
     tn = local / r;
   } else {

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
 
   int tm, tn;
   tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
+  if (tm >= op.tiles_m) return;  // grid padding
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
@@ -326,12 +327,12 @@ hipError_t launch_gemm(const Operands& op0, int mrows, int ncols, Epi epi, hipSt
     op.tiles_m = mrows / 128;
     op.tiles_n = ncols / 128;
     hipLaunchKernelGGL((zgemm_nt_f64_kernel<128, 128, 16, 2, 4, CONJ_A, CONJ_B, Epi>),
-                       dim3(op.tiles_m * op.tiles_n), dim3(512), 0, s, op, epi);
+                       dim3(grid_rows(op.tiles_m) * op.tiles_n), dim3(512), 0, s, op, epi);
   } else if (mrows % 64 == 0 && ncols % 64 == 0) {
     op.tiles_m = mrows / 64;
     op.tiles_n = ncols / 64;
     hipLaunchKernelGGL((zgemm_nt_f64_kernel<64, 64, 16, 2, 2, CONJ_A, CONJ_B, Epi>),
-                       dim3(op.tiles_m * op.tiles_n), dim3(256), 0, s, op, epi);
+                       dim3(grid_rows(op.tiles_m) * op.tiles_n), dim3(256), 0, s, op, epi);
   } else {
     return hipErrorInvalidValue;
   }

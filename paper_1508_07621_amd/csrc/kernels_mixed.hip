@@ -105,6 +105,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
 
   int tm, tn;
   tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
+  if (tm >= op.tiles_m) return;  // grid padding
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
 
   int tm, tn;
   tile_coords(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
+  if (tm >= g.tiles_m) return;  // grid padding
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
@@ -513,12 +515,12 @@ hipError_t launch_f32(MixOperands op, int mrows, int np, Epi epi, hipStream_t s)
     op.tiles_m = mrows / 128;
     op.tiles_n = np / 128;
     hipLaunchKernelGGL((cheb_f32_kernel<128, 128, 32, 2, 4, A_F64, Epi>),
-                       dim3(op.tiles_m * op.tiles_n), dim3(512), 0, s, op, epi);
+                       dim3(grid_rows(op.tiles_m) * op.tiles_n), dim3(512), 0, s, op, epi);
   } else if (mrows % 64 == 0 && np % 64 == 0) {
     op.tiles_m = mrows / 64;
     op.tiles_n = np / 64;
     hipLaunchKernelGGL((cheb_f32_kernel<64, 64, 32, 2, 2, A_F64, Epi>),
-                       dim3(op.tiles_m * op.tiles_n), dim3(256), 0, s, op, epi);
+                       dim3(grid_rows(op.tiles_m) * op.tiles_n), dim3(256), 0, s, op, epi);
   } else {
     return hipErrorInvalidValue;
   }
@@ -533,12 +535,12 @@ hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
     g.tiles_m = mrows / 128;
     g.tiles_n = np / 128;
     hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64>),
-                       dim3(g.tiles_m * g.tiles_n), dim3(512), 0, s, g);
+                       dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(512), 0, s, g);
   } else if (mrows % 64 == 0 && np % 64 == 0) {
     g.tiles_m = mrows / 64;
     g.tiles_n = np / 64;
     hipLaunchKernelGGL((cheb_bf3_kernel<64, 64, 2, 2, KIND, P_F64>),
-                       dim3(g.tiles_m * g.tiles_n), dim3(256), 0, s, g);
+                       dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(256), 0, s, g);
   } else {
     return hipErrorInvalidValue;
   }

@@ -1,6 +1,6 @@
 """Seeded generators for the synthetic workloads.
 
-Models (Sec. 4 of the paper, re-specified for this build):
+Models (Sec. 4 of the paper, with the parameters of the benchmark workloads):
 
 * random-matrix model: H(t) = H0 + f(t) V with H0, V drawn from the Gaussian
   unitary ensemble, H = (A + A^dagger) / (2 sqrt(N)), Re A_ij, Im A_ij iid N(0, 1).
