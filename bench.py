@@ -313,16 +313,16 @@ def main():
     t_setup = time.perf_counter()
     ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision=precision,
                             profile=True, device=dev, checkpoint_every=16 if grad_mode else 0,
-                            **kw)
+                            dtype="complex64" if grad_mode else "complex128", **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     info = ctx.report
     _log(f"setup {setup_s:.2f} s: L={info['L']} R={info['R']:.4f} "
          f"interval=[{info['e_min']:.6g}, {info['e_max']:.6g}]")
     n = wl.n
-    U = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    U = torch.empty((n, n), dtype=ctx.state_dtype, device=dev)
     if grad_mode:
-        W = torch.from_numpy(wl.arrays["w"]).to(dev)
+        W = torch.from_numpy(wl.arrays["w"]).to(device=dev, dtype=ctx.state_dtype)
         s_per_build, reports, grad_ms = time_build_grad(ctx, U, W, args.warmup, args.steps)
     else:
         s_per_build, reports = time_builds(ctx, U, args.warmup, args.steps, precision)
@@ -334,7 +334,8 @@ def main():
         extra["gradient"] = {"ms_per_grad": round(grad_ms, 3),
                              "ms_per_build": round(1e3 * s_per_build - grad_ms, 3),
                              "note": "value = forward build (FP32 products, tape every 16 steps) "
-                                     "+ FP64 reverse sweep for the 256 amplitudes"}
+                                     "+ FP64 reverse sweep for the 256 amplitudes; U_T and "
+                                     "U_bar stored in complex64"}
     if wl.layout == "dense":
         roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12

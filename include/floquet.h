@@ -24,7 +24,8 @@
  *         c_0 = J_0(R), c_l = 2 (-i)^l J_l(R).
  *
  * Conventions for every entry point:
- *   - complex numbers are complex128 (two float64, real part first);
+ *   - complex numbers are complex128 (two float64, real part first), except
+ *     the state blocks when fq_params.dtype = FQ_C64 (complex64);
  *   - dense matrices are row-major, element [i][j] = <i|A|j>; the columns of
  *     X, U_T and X0 are the propagated states;
  *   - "device" pointers are HIP device memory owned by the caller; the library
@@ -85,6 +86,14 @@ typedef struct fq_system {
   const double* hmod_diag;
 } fq_system;
 
+/* Storage of the state blocks that cross the boundary: U_T, X0, X_out, the
+ * snapshots and U_bar. Operators stay complex128 / float64. */
+typedef enum fq_dtype {
+  FQ_C128 = 0,  /* complex128 (interleaved float64 pairs) */
+  FQ_C64 = 1    /* complex64 (interleaved float32 pairs); the library still
+                   propagates in its own working precision and rounds on output */
+} fq_dtype;
+
 /* Time grid, drive samples and method parameters. */
 typedef struct fq_params {
   double T;                  /* period > 0 */
@@ -120,6 +129,8 @@ typedef struct fq_params {
                                 report gives the unitarity before and after
                                 (a correction of the result, not part of the
                                 paper's method). 0: off */
+  int32_t dtype;             /* fq_dtype of the state blocks */
+  int32_t reserved2;         /* must be 0 */
 } fq_params;
 
 /* Kernel kinds timed in profile mode (indices of fq_report.ms_kernel). */
@@ -187,7 +198,8 @@ fq_status fq_destroy(fq_ctx* ctx);
 fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep);
 
 /* Build U_T = X_M from X_0 = identity (Sec. 3: the identity propagated over
- * one period). U_out: device, n*n complex128 row-major, [i][j] = <i|U_T|j>.
+ * one period). U_out: device, n*n complex (fq_params.dtype) row-major,
+ * [i][j] = <i|U_T|j>.
  * rep (host, nullable) receives fq_get_report after the build, including the
  * FP64 unitarity measures of U_T. If checkpoint_every > 0 the tape for
  * floquet_grad is recorded. */
@@ -195,20 +207,20 @@ fq_status floquet_build_UT(fq_ctx* ctx, void* U_out, fq_report* rep);
 
 /* Propagate ncols given states over steps k0+1 .. k1 (0 <= k0 <= k1 <= M):
  * X_out = E_k1 ... E_{k0+1} X0 (the second propagation round of Sec. 3, e.g.
- * Floquet states over one period, and its resumption from any step). X0,
- * X_out: device, n*ncols complex128, row-major (column c is state c); they
- * may alias. 1 <= ncols <= n. snapshots (device, nullable): with
- * snap_every >= 1, the states after steps k0 + j*snap_every, j = 1 ..
- * (k1 - k0) / snap_every, are written as n*ncols complex128 blocks, block j-1
- * at snapshots + (j-1)*n*ncols elements; snap_every must be 0 when
- * snapshots is NULL. */
+ * Floquet states over one period, and its resumption from any step).
+ * X0, X_out: device, n*ncols complex (fq_params.dtype), row-major (column c
+ * is state c); they may alias. 1 <= ncols <= n. snapshots (device,
+ * nullable): with snap_every >= 1, the states after steps k0 + j*snap_every,
+ * j = 1 .. (k1 - k0) / snap_every, are written as n*ncols blocks of the same
+ * dtype, block j-1 at snapshots + (j-1)*n*ncols elements; snap_every must be
+ * 0 when snapshots is NULL. */
 fq_status floquet_propagate(fq_ctx* ctx, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
                             void* X_out, void* snapshots, int32_t snap_every);
 
 /* Gradient of a real loss of U_T with respect to the 2*M drive samples, by
  * the reverse sweep through the Chebyshev recurrence of every step (beta, dE
  * and L held fixed), recomputing each segment from the tape of the last
- * floquet_build_UT. U_bar: device, n*n complex128 row-major with
+ * floquet_build_UT. U_bar: device, n*n complex (fq_params.dtype) row-major with
  * U_bar[i][j] = dLoss/dRe U[i][j] + i dLoss/dIm U[i][j]. grad_f_nodes: host,
  * 2*M float64, same order as f_nodes. Needs checkpoint_every > 0. */
 fq_status floquet_grad(fq_ctx* ctx, const void* U_bar, double* grad_f_nodes);

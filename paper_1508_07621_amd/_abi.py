@@ -16,6 +16,7 @@ FQ_OK, FQ_ERR_ARG, FQ_ERR_NONFINITE, FQ_ERR_SPECTRUM, FQ_ERR_HIP, FQ_ERR_UNSUPPO
 STATUS_NAMES = {0: "FQ_OK", 1: "FQ_ERR_ARG", 2: "FQ_ERR_NONFINITE", 3: "FQ_ERR_SPECTRUM",
                 4: "FQ_ERR_HIP", 5: "FQ_ERR_UNSUPPORTED", 6: "FQ_ERR_STATE"}
 FQ_DENSE, FQ_TRIDIAG = 0, 1
+FQ_C128, FQ_C64 = 0, 1
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 #: kernel kinds timed in profile mode (fq_report.ms_kernel indices)
 K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 8
@@ -39,7 +40,8 @@ class FqParams(ctypes.Structure):
                 ("f_nodes", POINTER(c_double)),
                 ("e_min", c_double), ("e_max", c_double), ("tol", c_double),
                 ("precision", c_int32), ("checkpoint_every", c_int32),
-                ("profile", c_int32), ("reorthonormalize", c_int32)]
+                ("profile", c_int32), ("reorthonormalize", c_int32),
+                ("dtype", c_int32), ("reserved2", c_int32)]
 
 
 class FqReport(ctypes.Structure):

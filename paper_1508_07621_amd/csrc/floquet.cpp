@@ -165,6 +165,9 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (par->profile != 0 && par->profile != 1) return fail(FQ_ERR_ARG, "profile must be 0 or 1");
   if (par->reorthonormalize != 0 && par->reorthonormalize != 1)
     return fail(FQ_ERR_ARG, "reorthonormalize must be 0 or 1");
+  if (par->dtype != FQ_C128 && par->dtype != FQ_C64)
+    return fail(FQ_ERR_ARG, "dtype must be FQ_C128 or FQ_C64");
+  if (par->reserved2 != 0) return fail(FQ_ERR_ARG, "reserved2 must be 0");
   if (sys->layout == FQ_TRIDIAG) {
     if (par->precision != FQ_FP64)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal layout runs in FP64 only");
@@ -521,9 +524,10 @@ fq_status dense_steps(fq_ctx* c, int k0, int k1, int mrows, bool record_tape) {
     if (st != FQ_OK) return st;
     if (c->snap && (k + 1 - c->snap_k0) % c->snap_every == 0) {  // X_{k+1} to the user's buffer
       const long j = (k + 1 - c->snap_k0) / c->snap_every - 1;
-      char* dst = static_cast<char*>(c->snap) + (size_t)j * 16 * (size_t)c->n * (size_t)c->snap_ncols;
+      char* dst = static_cast<char*>(c->snap) +
+                  (size_t)j * (c->c64 ? 8 : 16) * (size_t)c->n * (size_t)c->snap_ncols;
       FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->snap_ncols, dst,
-                                           c->snap_ncols, c->stream));
+                                           c->snap_ncols, c->c64, c->stream));
     }
     if (record_tape && ((k + 1) % c->ckpt == 0 || k + 1 == c->M)) {
       const int slot = (k + 1 + c->ckpt - 1) / c->ckpt;
@@ -573,7 +577,8 @@ fq_status reorthonormalize(fq_ctx* c) {
 fq_status finish_reortho(fq_ctx* c, void* U_out) {
   const double umax = c->last.unitarity_max, ufro = c->last.unitarity_fro;
   FQ_TRY(reorthonormalize(c));
-  FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->stream));
+  FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->c64,
+                                       c->stream));
   FQ_TRY(unitarity(c, c->xr, c->xi));
   c->last.unitarity_max_after = c->last.unitarity_max;
   c->last.unitarity_fro_after = c->last.unitarity_fro;
@@ -613,6 +618,7 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   job.ld_x0 = ncols;
   job.x_out = x_out;
   job.ld_out = ncols;
+  job.c64 = c->c64 ? 1 : 0;
   if (c->snap) {
     job.snap = static_cast<double*>(c->snap);
     job.snap_every = c->snap_every;
@@ -742,7 +748,7 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const long plane = c->np * c->np;
   const size_t p2bytes = 2 * sizeof(double) * (size_t)plane;
   FQ_HIP(c, fq::launch_pack_planar_t(U_bar, c->n, c->n, c->n, c->lam, c->lam + plane, c->np,
-                                     c->np, c->stream));
+                                     c->np, c->c64, c->stream));
   FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
   bool any_b = false;
   for (int k = 0; k < M; ++k) any_b = any_b || (c->b[k] != 0.0);
@@ -803,6 +809,7 @@ fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   job.phi = c->phi;
   job.tape = c->tape;
   job.u_bar = U_bar;
+  job.c64 = c->c64 ? 1 : 0;
   job.seg = c->seg;
   job.grad = c->d_grad;
   FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
@@ -899,6 +906,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->ckpt = par->checkpoint_every;
   c->profile = par->profile != 0;
   c->reortho = par->reorthonormalize != 0;
+  c->c64 = par->dtype == FQ_C64;
   c->f_nodes.assign(par->f_nodes, par->f_nodes + 2 * par->M);
   c->a.resize(c->M);
   c->b.resize(c->M);
@@ -1063,7 +1071,8 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
     FQ_HIP(c, hipEventRecord(e1, c->stream));
-    FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->stream));
+    FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->c64,
+                                       c->stream));
     c->tape_valid = c->ckpt > 0;
     st = unitarity(c, c->xr, c->xi);
     if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
@@ -1074,7 +1083,8 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     FQ_MARK(c, -1);
     FQ_HIP(c, hipEventRecord(e1, c->stream));
     c->tape_valid = c->ckpt > 0;
-    FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->stream));
+    FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->c64,
+                                       c->stream));
     st = unitarity(c, c->xr, c->xi);
     if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
   }
@@ -1111,11 +1121,13 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
   c->n_events = 0;
   if (c->layout == FQ_DENSE) {
     const long mrows = pad_to(ncols, dense_tile(c->n));
-    FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->stream));
+    FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->c64,
+                                       c->stream));
     fq_status st = dense_steps(c, k0, k1, (int)mrows, false);
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
-    FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, ncols, X_out, ncols, c->stream));
+    FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, ncols, X_out, ncols, c->c64,
+                                         c->stream));
   } else {
     fq_status st = tridiag_run(c, X0, ncols, k0, k1, X_out);
     if (st != FQ_OK) return st;

@@ -123,12 +123,13 @@ hipError_t launch_unitarity_f64(const double* xr, const double* xi, int n, int n
 hipError_t launch_pack_planar(const void* src, long rows, long cols, long ld_src, double* re,
                               double* im, long ld, hipStream_t s);
 // Transposing pack: planes(j, i) = src(i, j) for i < rows, j < cols (src row stride ld_src);
-// planes(j, i) = 0 elsewhere in [0, mrows) x [0, ld).
+// planes(j, i) = 0 elsewhere in [0, mrows) x [0, ld). src is complex64 when c64, else complex128.
 hipError_t launch_pack_planar_t(const void* src, long rows, long cols, long ld_src, double* re,
-                                double* im, long ld, long mrows, hipStream_t s);
-// Transposing unpack: dst(i, j) = planes(j, i) for i < rows, j < cols (dst row stride ld_dst).
+                                double* im, long ld, long mrows, bool c64, hipStream_t s);
+// Transposing unpack: dst(i, j) = planes(j, i) for i < rows, j < cols (dst row stride ld_dst),
+// rounded to complex64 when c64.
 hipError_t launch_unpack_planar_t(const double* re, const double* im, long ld, long rows,
-                                  long cols, void* dst, long ld_dst, hipStream_t s);
+                                  long cols, void* dst, long ld_dst, bool c64, hipStream_t s);
 // Rows [0, m) x [0, ld) of the state-major planes set to the n x n identity (zero padding).
 hipError_t launch_identity_rows(double* re, double* im, long n, long m, long ld, hipStream_t s);
 // Rescaled Hamiltonian Ht = (H0 + a V + b K - beta 1) / dE on the n x n block.
@@ -164,8 +165,9 @@ struct TridiagJob {
   long ld_out;
   double* tape;          // optional (resident kernel): X_{j ckpt} as complex, slot j at
   int ckpt;              //   ((j * ncols + col) * n + i), written during the build
-  double* snap;          // optional: X_{k0 + (j+1) snap_every}, complex128 n x ncols row-major
-  int snap_every;        //   at snap + 2 j n ncols
+  double* snap;          // optional: X_{k0 + (j+1) snap_every}, complex n x ncols row-major
+  int snap_every;        //   (block j at element j n ncols)
+  int c64;               // x0, x_out and snap hold complex64 (else complex128)
 };
 // Returns hipErrorInvalidValue when n exceeds what one workgroup can hold.
 hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
@@ -202,7 +204,8 @@ struct TridiagAdjJob {
   int any_b;              // accumulate the K contraction
   double beta, inv_dE, phr, phi;
   const double* tape;     // X_{j ckpt} (forward build), complex, ((j * ncols + col) * n + i)
-  const void* u_bar;      // Lambda_M, complex128 n x ncols row-major
+  const void* u_bar;      // Lambda_M, complex n x ncols row-major
+  int c64;                // u_bar is complex64 (else complex128)
   double* seg;            // per column: ckpt x 3 complex vectors of n
   double* grad;           // 2 M accumulators: Re sum w_l <Pbar_{l+1}, D P_l>, D = Hmod, K
 };
@@ -263,6 +266,7 @@ struct fq_ctx {
   // last); launch i took the time between events i and i+1.
   bool profile = false;
   bool reortho = false;               // polar factor of U_T after the build
+  bool c64 = false;                   // user state blocks (U, X, W, snapshots) in complex64
   void* snap = nullptr;               // propagate: snapshot buffer, every snap_every steps
   int snap_every = 0, snap_k0 = 0;
   long snap_ncols = 0;

@@ -373,7 +373,8 @@ __global__ void pack_planar_kernel(const double2* __restrict__ src, long rows, l
 }
 
 // 32 x 32 tiles through LDS: planes(j, i) = src(i, j), zero outside the source.
-__global__ void pack_planar_t_kernel(const double2* __restrict__ src, long rows, long cols,
+template <class C>  // double2 (complex128) or float2 (complex64) source elements
+__global__ void pack_planar_t_kernel(const C* __restrict__ src, long rows, long cols,
                                      long ld_src, double* __restrict__ re,
                                      double* __restrict__ im, long ld) {
   __shared__ double tr[32][33], ti[32][33];
@@ -381,10 +382,14 @@ __global__ void pack_planar_t_kernel(const double2* __restrict__ src, long rows,
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: ty 0..7
   for (int r = ty; r < 32; r += 8) {
     const long i = i0 + r, j = j0 + tx;
-    double2 v = make_double2(0.0, 0.0);
-    if (i < rows && j < cols) v = src[i * ld_src + j];
-    tr[r][tx] = v.x;
-    ti[r][tx] = v.y;
+    double vr = 0.0, vi = 0.0;
+    if (i < rows && j < cols) {
+      const C v = src[i * ld_src + j];
+      vr = v.x;
+      vi = v.y;
+    }
+    tr[r][tx] = vr;
+    ti[r][tx] = vi;
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
@@ -397,9 +402,10 @@ __global__ void pack_planar_t_kernel(const double2* __restrict__ src, long rows,
 }
 
 // dst(i, j) = planes(j, i).
+template <class C>  // double2 (complex128) or float2 (complex64) destination elements
 __global__ void unpack_planar_t_kernel(const double* __restrict__ re,
                                        const double* __restrict__ im, long ld, long rows,
-                                       long cols, double2* __restrict__ dst, long ld_dst) {
+                                       long cols, C* __restrict__ dst, long ld_dst) {
   __shared__ double tr[32][33], ti[32][33];
   const long j0 = blockIdx.y * 32L, i0 = blockIdx.x * 32L;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -413,7 +419,12 @@ __global__ void unpack_planar_t_kernel(const double* __restrict__ re,
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const long i = i0 + r, j = j0 + tx;
-    if (i < rows && j < cols) dst[i * ld_dst + j] = make_double2(tr[tx][r], ti[tx][r]);
+    if (i < rows && j < cols) {
+      C v;
+      v.x = tr[tx][r];
+      v.y = ti[tx][r];
+      dst[i * ld_dst + j] = v;
+    }
   }
 }
 
@@ -550,19 +561,27 @@ hipError_t launch_pack_planar(const void* src, long rows, long cols, long ld_src
 }
 
 hipError_t launch_pack_planar_t(const void* src, long rows, long cols, long ld_src, double* re,
-                                double* im, long ld, long mrows, hipStream_t s) {
+                                double* im, long ld, long mrows, bool c64, hipStream_t s) {
   if (mrows % 32 != 0 || ld % 32 != 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)(ld / 32), (unsigned)(mrows / 32));
-  hipLaunchKernelGGL(pack_planar_t_kernel, grid, dim3(256), 0, s,
-                     reinterpret_cast<const double2*>(src), rows, cols, ld_src, re, im, ld);
+  if (c64)
+    hipLaunchKernelGGL(pack_planar_t_kernel<float2>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(src), rows, cols, ld_src, re, im, ld);
+  else
+    hipLaunchKernelGGL(pack_planar_t_kernel<double2>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(src), rows, cols, ld_src, re, im, ld);
   return hipGetLastError();
 }
 
 hipError_t launch_unpack_planar_t(const double* re, const double* im, long ld, long rows,
-                                  long cols, void* dst, long ld_dst, hipStream_t s) {
+                                  long cols, void* dst, long ld_dst, bool c64, hipStream_t s) {
   dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32));
-  hipLaunchKernelGGL(unpack_planar_t_kernel, grid, dim3(256), 0, s, re, im, ld, rows, cols,
-                     reinterpret_cast<double2*>(dst), ld_dst);
+  if (c64)
+    hipLaunchKernelGGL(unpack_planar_t_kernel<float2>, grid, dim3(256), 0, s, re, im, ld, rows,
+                       cols, reinterpret_cast<float2*>(dst), ld_dst);
+  else
+    hipLaunchKernelGGL(unpack_planar_t_kernel<double2>, grid, dim3(256), 0, s, re, im, ld, rows,
+                       cols, reinterpret_cast<double2*>(dst), ld_dst);
   return hipGetLastError();
 }
 

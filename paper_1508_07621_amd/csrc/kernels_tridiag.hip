@@ -37,6 +37,27 @@ __device__ __forceinline__ double from_next_lane(double v) {  // lane l <- lane 
 // coef, tape and snap come as separate restrict-qualified arguments so that the
 // checkpoint and snapshot stores inside the step loop cannot be taken to alias
 // the coefficient table, which then stays on scalar loads.
+// Complex state elements of the user blocks: complex128, or complex64 when c64.
+__device__ __forceinline__ void load_state(const void* base, long idx, int c64, double& re,
+                                           double& im) {
+  if (c64) {
+    const float2 v = reinterpret_cast<const float2*>(base)[idx];
+    re = v.x;
+    im = v.y;
+  } else {
+    const double2 v = reinterpret_cast<const double2*>(base)[idx];
+    re = v.x;
+    im = v.y;
+  }
+}
+// One part (0 = real, 1 = imaginary) of element idx.
+__device__ __forceinline__ void store_part(void* base, long idx, int part, int c64, double v) {
+  if (c64)
+    reinterpret_cast<float*>(base)[2 * idx + part] = (float)v;
+  else
+    reinterpret_cast<double*>(base)[2 * idx + part] = v;
+}
+
 template <int R, int MAXT, bool MULTI>
 __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int G,
                                                              const double2* __restrict__ coef,
@@ -68,9 +89,7 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
     if (i < n) {
       double xr, xi;
       if (job.x0) {
-        const double2 x = reinterpret_cast<const double2*>(job.x0)[i * job.ld_x0 + col];
-        xr = x.x;
-        xi = x.y;
+        load_state(job.x0, i * job.ld_x0 + col, job.c64, xr, xi);
       } else {
         xr = (i == col) ? 1.0 : 0.0;
         xi = 0.0;
@@ -215,7 +234,7 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
         const double plain = part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;  // X_{s+1}
         if (ckpt_step)
           tape[2 * (((long)((s + 1) / job.ckpt) * job.ncols + col) * n + i) + part] = plain;
-        if (snap_step) snap[2 * ((snap_j * n + i) * job.ncols + col) + part] = plain;
+        if (snap_step) store_part(snap, (snap_j * n + i) * job.ncols + col, part, job.c64, plain);
         if (!final_step) {
           const double2 wn = gauge[(long)(s + 1) * n + i];
           const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
@@ -229,11 +248,10 @@ __global__ __launch_bounds__(MAXT) void tridiag_gauge_kernel(TridiagJob job, int
     __syncthreads();
   }
 
-  double* out = reinterpret_cast<double*>(job.x_out);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const long i = base + r;
-    if (i < n) out[2 * (i * job.ld_out + col) + part] = pa[r];
+    if (i < n) store_part(job.x_out, i * job.ld_out + col, part, job.c64, pa[r]);
   }
 }
 
@@ -321,9 +339,7 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
       if (st.l0 == 0 && st.first_step) {
         double xr, xi;
         if (job.x0) {
-          const double2 x = reinterpret_cast<const double2*>(job.x0)[i * job.ld_x0 + col];
-          xr = x.x;
-          xi = x.y;
+          load_state(job.x0, i * job.ld_x0 + col, job.c64, xr, xi);
         } else {
           xr = (i == col) ? 1.0 : 0.0;
           xi = 0.0;
@@ -441,7 +457,6 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     slot[1] = yo[r];
   }
   __syncthreads();
-  double* out = reinterpret_cast<double*>(job.x_out);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const long i = base + r;
@@ -454,8 +469,8 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
     if (job.snap && (s + 1 - job.k0) % job.snap_every == 0) {  // X_{s+1}, plain frame
       const long j = (s + 1 - job.k0) / job.snap_every - 1;
-      job.snap[2 * ((j * n + i) * job.ncols + col) + part] =
-          part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
+      store_part(job.snap, (j * n + i) * job.ncols + col, part, job.c64,
+                 part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr);
     }
     if (!st.last_step) {
       const double2 wn = gauge[(long)(s + 1) * n + i];
@@ -465,7 +480,7 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     }
     const double v = part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr;
     if (st.last_step)
-      out[2 * (i * job.ld_out + col) + part] = v;
+      store_part(job.x_out, i * job.ld_out + col, part, job.c64, v);
     else
       plane_out(0, part)[i] = v;
   }
@@ -530,9 +545,7 @@ __global__ __launch_bounds__(W * 64) void tridiag_adjoint_kernel(TridiagAdjJob j
     lr[r] = li[r] = 0.0;
     vv[r] = 0.0;
     if (i < n) {
-      const double2 u = reinterpret_cast<const double2*>(job.u_bar)[i * job.ncols + col];
-      lr[r] = u.x;
-      li[r] = u.y;
+      load_state(job.u_bar, i * job.ncols + col, job.c64, lr[r], li[r]);
       vv[r] = job.v_diag[i];
     }
   }

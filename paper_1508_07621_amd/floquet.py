@@ -76,13 +76,15 @@ class FloquetContext:
     precision: "fp64", "fp32" or "bf16x3" (arithmetic of the Chebyshev products).
     reorthonormalize: replace U_T by its polar factor after each build (FP64
     Newton-Schulz); the report keeps the unitarity before and after.
+    dtype: "complex128" or "complex64", storage of U_T, X and U_bar (the
+    operators stay complex128 / float64).
     """
 
     def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_diag=None,
                  h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
                  e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
                  precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
-                 reorthonormalize: bool = False, device=None):
+                 reorthonormalize: bool = False, dtype: str = "complex128", device=None):
         torch = _torch()
         L_ = lib()
         self.device = torch.device(device if device is not None else "cuda")
@@ -125,6 +127,10 @@ class FloquetContext:
         par.checkpoint_every = int(checkpoint_every)
         par.profile = 1 if profile else 0
         par.reorthonormalize = 1 if reorthonormalize else 0
+        if dtype not in ("complex128", "complex64"):
+            raise ValueError("dtype must be complex128 or complex64")
+        par.dtype = _abi.FQ_C64 if dtype == "complex64" else _abi.FQ_C128
+        self.state_dtype = torch.complex64 if dtype == "complex64" else torch.complex128
         self.precision = precision
         import ctypes
         nbytes = ctypes.c_size_t(0)
@@ -146,11 +152,13 @@ class FloquetContext:
         return r.as_dict()
 
     def build_ut(self, out=None):
-        """U_T as an n x n complex128 tensor ([i, j] = <i|U_T|j>)."""
+        """U_T as an n x n tensor of the context's dtype ([i, j] = <i|U_T|j>)."""
         import ctypes
         torch = _torch()
         if out is None:
-            out = torch.empty((self.n, self.n), dtype=torch.complex128, device=self.device)
+            out = torch.empty((self.n, self.n), dtype=self.state_dtype, device=self.device)
+        if out.dtype != self.state_dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of the context's dtype")
         r = FqReport()
         with torch.cuda.device(self.device):
             check(lib().floquet_build_UT(self._ctx, out.data_ptr(), ctypes.byref(r)))
@@ -163,7 +171,7 @@ class FloquetContext:
         as a ((k1 - k0) // snap_every, n, ncols) tensor."""
         torch = _torch()
         k1 = self.M if k1 is None else int(k1)
-        X0 = _device_tensor(X0, torch.complex128, self.device)
+        X0 = _device_tensor(X0, self.state_dtype, self.device)
         if X0.dim() != 2 or X0.shape[0] != self.n:
             raise ValueError("X0 must be n x ncols")
         if out is None:
@@ -171,7 +179,7 @@ class FloquetContext:
         snaps = None
         if snap_every > 0:
             count = (k1 - int(k0)) // int(snap_every)
-            snaps = torch.empty((max(count, 1),) + tuple(X0.shape), dtype=torch.complex128,
+            snaps = torch.empty((max(count, 1),) + tuple(X0.shape), dtype=self.state_dtype,
                                 device=self.device)[:count]
         with torch.cuda.device(self.device):
             check(lib().floquet_propagate(self._ctx, X0.data_ptr(), int(X0.shape[1]), int(k0), k1,
@@ -183,7 +191,7 @@ class FloquetContext:
     def grad(self, U_bar) -> np.ndarray:
         """d loss / d f_nodes, shape (M, 2), for U_bar = dL/dRe U + i dL/dIm U."""
         torch = _torch()
-        ub = _device_tensor(U_bar, torch.complex128, self.device)
+        ub = _device_tensor(U_bar, self.state_dtype, self.device)
         g = np.empty(2 * self.M, dtype=np.float64)
         with torch.cuda.device(self.device):
             check(lib().floquet_grad(self._ctx, ub.data_ptr(), dptr(g)))

@@ -34,8 +34,36 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 5 * 8
-    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 4 * 4
+    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 6 * 4
     assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 8 * 8 + 4 * 8
+
+
+def test_struct_offsets_match_compiled_header(tmp_path):
+    """sizeof / offsetof of the ABI structs from a C compilation of
+    include/floquet.h against the ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    fields = {"fq_system": _abi.FqSystem, "fq_params": _abi.FqParams, "fq_report": _abi.FqReport}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "floquet.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in fields.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_node_times_match_oracle():
@@ -163,6 +191,8 @@ def test_workspace_bytes_ok_and_grows_with_n():
     (lambda s, p: setattr(p, "checkpoint_every", -2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "profile", 2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "reorthonormalize", 2), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "dtype", 2), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "reserved2", 1), _abi.FQ_ERR_ARG),
 ])
 def test_invalid_arguments_rejected(mutate, status):
     s, p = _dense(), _params()

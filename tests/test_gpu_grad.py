@@ -128,9 +128,9 @@ def test_grad_error_paths(fl):
 
 
 def test_adjoint_config_full_size_against_fd(fl):
-    """The 1024-state adjoint workload: complex64 forward (FP32 products),
-    checkpoint every 16 steps, against central differences (h = 1e-4) of the
-    FP64 forward on 8 seeded amplitudes."""
+    """The 1024-state adjoint workload: complex64 forward (FP32 products,
+    complex64 U_T and U_bar), checkpoint every 16 steps, against central
+    differences (h = 1e-4) of the FP64 forward on 8 seeded amplitudes."""
     wl = workload("adjoint1024")
     H0, V, W, f = wl.arrays["h0"], wl.arrays["v"], wl.arrays["w"], wl.amplitudes
     T, M, n = wl.T, wl.M, wl.n
@@ -139,8 +139,8 @@ def test_adjoint_config_full_size_against_fd(fl):
     _say("adjoint1024", n, M, lo, hi)
     nodes = np.stack([f, f], 1)
     ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=nodes, e_min=lo, e_max=hi, tol=1e-12,
-                            precision="fp32", checkpoint_every=16)
-    U = ctx.build_ut().cpu().numpy()
+                            precision="fp32", checkpoint_every=16, dtype="complex64")
+    U = ctx.build_ut().cpu().numpy().astype(complex)
     L = ctx.report["L"]
     _, Ubar = _trace_loss_and_bar(U, W)
     g = ctx.grad(Ubar).sum(axis=1)
@@ -262,3 +262,26 @@ def test_tridiag_dimer1000_256_amplitudes_against_fd(fl):
         fd = (vals[0] - vals[1]) / (2 * eps)
         _say("k", k, "adjoint", g[k], "fd", fd)
         assert abs(g[k] - fd) <= 1e-5 * abs(fd) + 1e-9
+
+
+def test_tridiag_gradient_complex64_ubar(fl):
+    """The tridiagonal reverse sweep reads a complex64 U_bar when the context
+    stores its state blocks in complex64."""
+    d, e, v, f, W = _dimer_problem(60, 10, 321)
+    T = 2.0
+    nodes = np.stack([f, f], 1)
+    a, b = orc.magnus4_weights(nodes, T / 10)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    L = orc.choose_L(orc.rescale(lo, hi, T / 10)[2], 1e-13)
+    kw = dict(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=10, f_nodes=nodes, e_min=lo, e_max=hi, L=L,
+              checkpoint_every=3)
+    c128 = fl.FloquetContext(**kw)
+    c64 = fl.FloquetContext(dtype="complex64", **kw)
+    U = c128.build_ut().cpu().numpy()
+    c64.build_ut()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g1 = c128.grad(Ubar)
+    g2 = c64.grad(Ubar.astype(np.complex64))
+    err = np.max(np.abs(g1 - g2)) / np.max(np.abs(g1))
+    _say("c64 ubar rel", err)
+    assert err < 1e-5

@@ -324,6 +324,45 @@ def test_tridiag_propagate_snapshots(fl, nb, M, steps, every):
         assert err < FP64_TOL
 
 
+# ---- complex64 storage of the state blocks ----------------------------------------------------------
+
+def test_complex64_storage_dense_and_tridiag(fl):
+    """dtype complex64: U_T, X and snapshots are stored in complex64 (the
+    propagation itself keeps its working precision): errors at the complex64
+    rounding level against the oracle, unitarity still measured in FP64."""
+    import torch
+    n, M = 96, 8
+    H0, V = _dense_case(n, 41)
+    T = TWO_PI
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
+                            dtype="complex64")
+    U = ctx.build_ut()
+    assert U.dtype == torch.complex64
+    Uref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+    err = orc.column_error(U.cpu().numpy().astype(complex), Uref)
+    _say("c64 dense e_col", err, "unitarity", ctx.last_report["unitarity_max"])
+    assert err < 2e-6
+    assert ctx.last_report["unitarity_max"] < 2e-6
+    X0 = haar_unitary(n, np.random.default_rng(3))[:, :5].astype(np.complex64)
+    X, snaps = ctx.propagate(X0, 1, 7, snap_every=3)
+    assert X.dtype == torch.complex64 and snaps.dtype == torch.complex64
+    ref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L,
+                       X0=X0.astype(complex), k_range=(1, 4))
+    assert orc.column_error(snaps[0].cpu().numpy().astype(complex), ref) < 2e-6
+
+    ctx2, (d, e, v, f2, T2, lo2, hi2, L2) = _dimer_ctx(fl, 128, 0.01, 20)
+    ctx3 = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T2, M=20, f_nodes=f2, e_min=lo2,
+                             e_max=hi2, L=L2, dtype="complex64")
+    U3 = ctx3.build_ut()
+    assert U3.dtype == torch.complex64
+    Uref3 = orc.build_ut_tridiag(d, e, v, f2, T2, 20, route="cheb", e_min=lo2, e_max=hi2, L=L2)
+    err3 = orc.column_error(U3.cpu().numpy().astype(complex), Uref3)
+    _say("c64 tridiag e_col", err3)
+    assert err3 < 2e-6
+
+
 # ---- tridiagonal (dimer) FP64 ---------------------------------------------------------------------
 
 def _dimer_ctx(fl, nb, U_int, M, eps0=0.5, eps1=1.5, L=None, tol=1e-12):
