@@ -56,8 +56,8 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
   static_assert(BM * CPR % NT == 0 && BN * CPR % NT == 0, "load split");
   static_assert(BK % 8 == 0, "BK");
 
-  __shared__ __attribute__((aligned(16))) double As[2][BM * S];
-  __shared__ __attribute__((aligned(16))) double Bs[2][BN * S];
+  __shared__ __attribute__((aligned(16))) double As[2][2][BM * S];  // [stage][re, im]
+  __shared__ __attribute__((aligned(16))) double Bs[2][2][BN * S];
 
   int tm, tn;
   tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
@@ -93,27 +93,33 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
       gb[1][r] = *reinterpret_cast<const d2*>(op.bi + off);
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int st) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const int c = tid + r * NT, row = c / CPR, col = 2 * (c % CPR);
-      *reinterpret_cast<d2*>(&As[0][row * S + col]) = ga[0][r];
-      *reinterpret_cast<d2*>(&As[1][row * S + col]) = CONJ_A ? -ga[1][r] : ga[1][r];
+      *reinterpret_cast<d2*>(&As[st][0][row * S + col]) = ga[0][r];
+      *reinterpret_cast<d2*>(&As[st][1][row * S + col]) = CONJ_A ? -ga[1][r] : ga[1][r];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int c = tid + r * NT, row = c / CPR, col = 2 * (c % CPR);
-      *reinterpret_cast<d2*>(&Bs[0][row * S + col]) = gb[0][r];
-      *reinterpret_cast<d2*>(&Bs[1][row * S + col]) = CONJ_B ? -gb[1][r] : gb[1][r];
+      *reinterpret_cast<d2*>(&Bs[st][0][row * S + col]) = gb[0][r];
+      *reinterpret_cast<d2*>(&Bs[st][1][row * S + col]) = CONJ_B ? -gb[1][r] : gb[1][r];
     }
   };
 
+  // Two LDS stages, one barrier per K-stage: the next stage is written from
+  // registers (loaded one stage earlier) while the waves multiply out of the
+  // current one.
+  const int nk = op.kdim / BK;
   gload(0);
-  for (int k0 = 0; k0 < op.kdim; k0 += BK) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (k0 + BK < op.kdim) gload(k0 + BK);
+  lstore(0);
+  if (nk > 1) gload(BK);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int cur = kb & 1;
+    if (kb + 1 < nk) lstore(cur ^ 1);  // that stage was last read before the previous barrier
+    if (kb + 2 < nk) gload((kb + 2) * BK);
     const int rr = lane & 15;
 #pragma unroll
     for (int p = 0; p < BK / 8; ++p) {
@@ -122,14 +128,14 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int row = wm * WTM + i * 16 + rr;
-        far_[i] = *reinterpret_cast<const d2*>(&As[0][row * S + kk]);
-        fai[i] = *reinterpret_cast<const d2*>(&As[1][row * S + kk]);
+        far_[i] = *reinterpret_cast<const d2*>(&As[cur][0][row * S + kk]);
+        fai[i] = *reinterpret_cast<const d2*>(&As[cur][1][row * S + kk]);
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int row = wn * WTN + j * 16 + rr;
-        fbr[j] = *reinterpret_cast<const d2*>(&Bs[0][row * S + kk]);
-        fbi[j] = *reinterpret_cast<const d2*>(&Bs[1][row * S + kk]);
+        fbr[j] = *reinterpret_cast<const d2*>(&Bs[cur][0][row * S + kk]);
+        fbi[j] = *reinterpret_cast<const d2*>(&Bs[cur][1][row * S + kk]);
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -151,6 +157,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
           for (int j = 0; j < FN; ++j) accI[i][j] = mfma_f64(fai[i][t], fbr[j][t], accI[i][j]);
       }
     }
+    __syncthreads();
   }
 
 #pragma unroll
