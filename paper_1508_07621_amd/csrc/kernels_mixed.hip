@@ -100,8 +100,8 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
   static_assert(BM * CPRA % NT == 0 && BN * CPRB % NT == 0, "load split");
   static_assert(BK % 16 == 0, "BK");
 
-  __shared__ __attribute__((aligned(16))) float As[2][BM * S];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BN * S];
+  __shared__ __attribute__((aligned(16))) float As[2][2][BM * S];  // [stage][re, im]
+  __shared__ __attribute__((aligned(16))) float Bs[2][2][BN * S];
 
   int tm, tn;
   tile_coords(blockIdx.x, op.tiles_m, op.tiles_n, tm, tn);
@@ -147,33 +147,38 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
       gb[1][r] = *reinterpret_cast<const f4*>(b + plane + off);
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int st) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const int c = tid + r * NT, row = c / CPRA, col = AEL * (c % CPRA);
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         if constexpr (A_F64) {
-          *reinterpret_cast<f2*>(&As[p][row * S + col]) = f2{(float)ga[p][r][0], (float)ga[p][r][1]};
+          *reinterpret_cast<f2*>(&As[st][p][row * S + col]) =
+              f2{(float)ga[p][r][0], (float)ga[p][r][1]};
         } else {
-          *reinterpret_cast<f4*>(&As[p][row * S + col]) = ga[p][r];
+          *reinterpret_cast<f4*>(&As[st][p][row * S + col]) = ga[p][r];
         }
       }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int c = tid + r * NT, row = c / CPRB, col = 4 * (c % CPRB);
-      *reinterpret_cast<f4*>(&Bs[0][row * S + col]) = gb[0][r];
-      *reinterpret_cast<f4*>(&Bs[1][row * S + col]) = gb[1][r];
+      *reinterpret_cast<f4*>(&Bs[st][0][row * S + col]) = gb[0][r];
+      *reinterpret_cast<f4*>(&Bs[st][1][row * S + col]) = gb[1][r];
     }
   };
 
+  // Two LDS stages, one barrier per K-stage (as in the FP64 kernel).
+  const int nk = op.kdim / BK;
   gload(0);
-  for (int k0 = 0; k0 < op.kdim; k0 += BK) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (k0 + BK < op.kdim) gload(k0 + BK);
+  lstore(0);
+  if (nk > 1) gload(BK);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int cur = kb & 1;
+    if (kb + 1 < nk) lstore(cur ^ 1);  // that stage was last read before the previous barrier
+    if (kb + 2 < nk) gload((kb + 2) * BK);
     const int rr = lane & 15;
 #pragma unroll
     for (int p = 0; p < BK / 16; ++p) {
@@ -182,14 +187,14 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int row = wm * WTM + i * 16 + rr;
-        far_[i] = *reinterpret_cast<const f4*>(&As[0][row * S + kk]);
-        fai[i] = *reinterpret_cast<const f4*>(&As[1][row * S + kk]);
+        far_[i] = *reinterpret_cast<const f4*>(&As[cur][0][row * S + kk]);
+        fai[i] = *reinterpret_cast<const f4*>(&As[cur][1][row * S + kk]);
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int row = wn * WTN + j * 16 + rr;
-        fbr[j] = *reinterpret_cast<const f4*>(&Bs[0][row * S + kk]);
-        fbi[j] = *reinterpret_cast<const f4*>(&Bs[1][row * S + kk]);
+        fbr[j] = *reinterpret_cast<const f4*>(&Bs[cur][0][row * S + kk]);
+        fbi[j] = *reinterpret_cast<const f4*>(&Bs[cur][1][row * S + kk]);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -211,6 +216,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
           for (int j = 0; j < FN; ++j) accI[i][j] = mfma_f32(fai[i][t], fbr[j][t], accI[i][j]);
       }
     }
+    __syncthreads();
   }
 
 #pragma unroll
