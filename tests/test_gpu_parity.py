@@ -47,8 +47,13 @@ def _oracle_interval(H0, V, f, T, M, tol=1e-12):
 
 # ---- dense FP64 ----------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,M,seed", [(64, 100, 1508), (100, 12, 2), (200, 6, 3), (1030, 2, 4)])
+@pytest.mark.parametrize("n,M,seed", [(64, 100, 1508), (100, 12, 2), (200, 6, 3), (1030, 2, 4),
+                                      (1, 5, 7), (2, 1, 8), (3, 3, 9), (65, 1, 10), (2049, 1, 11)])
 def test_dense_fp64_matches_oracle(fl, n, M, seed):
+    """Sizes span one partial tile (n = 1, 2, 3), a tile plus one row (65), several
+    tiles with ragged tails (100, 200, 1030) and a size that takes 128-row tiles in
+    row-major order (2049 -> 17 x 17 tiles; the padded XCD order of larger grids
+    is covered by the 10^4-state test); M = 1 is a single step."""
     _say("dense fp64", n, M, seed)
     H0, V = _dense_case(n, seed)
     T = TWO_PI
