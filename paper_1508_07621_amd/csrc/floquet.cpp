@@ -114,8 +114,10 @@ Layout plan(const fq_system* sys, const fq_params* par) {
       lay.off_y = take(plane2);
     }
     lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)par->M);
-    if (n > fq::tridiag_resident_max_n())  // two 8-plane states of up to n x n doubles
-      lay.off_stream = take(2 * 8 * sizeof(double) * (size_t)n * (size_t)n);
+    if (n > fq::tridiag_resident_max_n()) {  // two 8-plane states of n16 x n, per-step rows
+      const size_t n16 = (size_t)(n + 15) / 16 * 16;
+      lay.off_stream = take(sizeof(double) * (2 * 8 * n16 * (size_t)n + 6 * n16));
+    }
     if (par->checkpoint_every > 0) {  // X_{j ckpt} per column; per-column segment buffers
       const size_t vec = 2 * sizeof(double) * (size_t)n;
       lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
@@ -636,19 +638,25 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   // Longer columns: k-term passes with ghost rows, state ping-ponged through HBM.
   const int K = 128;
   fq::TridiagStream st{};
-  st.plane = c->n * ncols;
+  st.n16 = (c->n + 15) / 16 * 16;
+  st.plane = st.n16 * ncols;
   st.K = K;
   st.B = fq::tridiag_stream_rows() - 2L * K;
   st.nblk = (c->n + st.B - 1) / st.B;
-  double* buf[2] = {c->d_stream, c->d_stream + 8 * (size_t)c->n * (size_t)c->n};
+  const size_t state = 8 * (size_t)st.n16 * (size_t)c->n;
+  double* buf[2] = {c->d_stream, c->d_stream + state};
+  double* stepc = c->d_stream + 2 * state;
+  st.stepc = stepc;
   int cur = 0;
   for (int s = k0; s < k1; ++s) {
+    st.s = s;
+    st.last_step = (s + 1 == k1);
+    FQ_MARK(c, FQ_K_HEFF);  // rows of 2 Ht_s and the gauge factors of the step
+    FQ_HIP(c, fq::launch_tridiag_stream_step(job, st, stepc, c->stream));
     for (int l0 = 0; l0 <= c->L; l0 += K) {
-      st.s = s;
       st.l0 = l0;
       st.l1 = std::min(l0 + K, c->L + 1);
       st.first_step = (s == k0 && l0 == 0);
-      st.last_step = (s + 1 == k1);
       st.in = buf[cur];
       st.out = buf[cur ^ 1];
       FQ_MARK(c, FQ_K_TRIDIAG);

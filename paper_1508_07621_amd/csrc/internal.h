@@ -178,10 +178,16 @@ long tridiag_resident_max_n();
 // state from `in` and writing it to `out` (8 planes of ncols x n doubles each),
 // or, at the end of the last step (last_step and l1 == L + 1), X to job.x_out.
 // first_step with l0 == 0 takes X from job.x0 (identity when null) instead of in.
+// State planes between passes hold row i of a column at (i mod 16) nq + i / 16
+// (nq = n16 / 16, n16 = n rounded up to 16), so that the 16 consecutive rows a
+// lane owns are read and written with unit stride across the wave.
 struct TridiagStream {
   const double* in;
   double* out;
-  long plane;       // n * ncols
+  long plane;       // n16 * ncols
+  long n16;         // rows per column in a state plane
+  const double* stepc;  // per-step rows (same interleaved layout): 2 diag, 2 coupling,
+                        // phase w_s (re, im), w_{s+1} (re, im); 6 n16 doubles
   int s;            // step index (0-based)
   int l0, l1;       // terms of this launch, l1 - l0 <= K, l0 != 1
   int first_step;
@@ -191,6 +197,8 @@ struct TridiagStream {
   long nblk;        // blocks per column = ceil(n / B)
 };
 long tridiag_stream_rows();
+hipError_t launch_tridiag_stream_step(const TridiagJob& job, const TridiagStream& st,
+                                      double* stepc, hipStream_t s);
 
 // Gradient of the tridiagonal chain, one workgroup per column (n <= 2048).
 struct TridiagAdjJob {

@@ -271,31 +271,72 @@ hipError_t launch_r(const TridiagJob& job, int G, hipStream_t s) {
 // most K terms of one step in registers exactly as above, and writes back only
 // its owned rows: after t terms the rows within t of a cut are stale, the owned
 // ones are not. Between launches the state lives in HBM in the gauge frame of
-// the current step, as 8 planes of ncols x n doubles (column-major per state):
-// role 0 = latest even term, role 1 = latest odd term, role 2 = the part's own
-// share of the sum, role 3 = its share of the other component; plane index
-// (role * 2 + part). At a step start role 0 holds X~ = D_s^+ X.
+// the current step, as 8 planes of ncols x n16 doubles: role 0 = latest even
+// term, role 1 = latest odd term, role 2 = the part's own share of the sum,
+// role 3 = its share of the other component; plane index (role * 2 + part).
+// Within a column, row i sits at (i mod 16) nq + i / 16, so a lane's 16 rows
+// are one element of 16 unit-stride wave-wide accesses (B and K are multiples
+// of 16, so a row keeps its lane slot r = i mod 16 in every block that reads
+// it). At a step start role 0 holds X~ = D_s^+ X.
+
+// Per-step rows of 2 Ht, the phase-weighted gauge phi w_s and w_{s+1}, in the
+// interleaved layout; rows n .. n16-1 are zero.
+__global__ __launch_bounds__(256) void tridiag_stream_step_kernel(TridiagJob job, int s, int last,
+                                                                  long n16, double* out) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n16) return;
+  const long n = job.n, nq = n16 >> 4;
+  const long at = (i & 15) * nq + (i >> 4);
+  double d2 = 0.0, g2 = 0.0, wr = 0.0, wi = 0.0, nr = 1.0, ni = 0.0;
+  if (i < n) {
+    const double a = job.ab[2 * s], b = job.ab[2 * s + 1];
+    const double vi = job.v_diag[i];
+    d2 = 2.0 * (job.h0_diag[i] + a * vi - job.beta) * job.inv_dE;
+    if (i + 1 < n) {
+      const double2 h = reinterpret_cast<const double2*>(job.h0_off)[i];
+      const double q = b * (job.v_diag[i + 1] - vi);
+      g2 = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
+    }
+    const double2 g = reinterpret_cast<const double2*>(job.gauge)[(long)s * n + i];
+    wr = job.phr * g.x - job.phi * g.y;
+    wi = job.phr * g.y + job.phi * g.x;
+    if (!last) {
+      const double2 gn = reinterpret_cast<const double2*>(job.gauge)[(long)(s + 1) * n + i];
+      nr = gn.x;
+      ni = gn.y;
+    }
+  }
+  out[at] = d2;
+  out[n16 + at] = g2;
+  out[2 * n16 + at] = wr;
+  out[3 * n16 + at] = wi;
+  out[4 * n16 + at] = nr;
+  out[5 * n16 + at] = ni;
+}
+
 template <int R, int MAXT>
 __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, TridiagStream st,
                                                               int G) {
-  extern __shared__ double ysh[];  // [part][lane in part][r][2]
+  static_assert(R == 16, "the interleaved state layout assumes 16 rows per lane");
+  extern __shared__ double ysh[];  // [part][r][lane in part][2]
   __shared__ double halo[2][2][2][kMaxWaves];
 
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int part = wid / G, w = wid % G;
   const int pl = w * 64 + lane;
   const long col = blockIdx.x / st.nblk, blk = blockIdx.x % st.nblk;
-  const long n = job.n;
+  const long n = job.n, n16 = st.n16, nq = n16 >> 4;
   const long a0 = blk * st.B;                       // first owned row
   const long own_end = (a0 + st.B < n) ? a0 + st.B : n;
-  const long base = a0 - st.K + (long)pl * R;       // global row of this lane's first row
+  const long q = (a0 - st.K) / 16 + pl;             // row group of this lane (may be < 0)
+  const long base = q * 16;                         // global row of this lane's first row
   const double sgn = part == 0 ? 1.0 : -1.0;
-  const double2* gauge = reinterpret_cast<const double2*>(job.gauge);
   const double2* coef = reinterpret_cast<const double2*>(job.coef);
-  const double2* h0o = reinterpret_cast<const double2*>(job.h0_off);
-  const long cn = col * n;                          // column offset in a state plane
+  const double* stc = st.stepc;
+  const long cn = col * n16;                        // column offset in a state plane
   auto plane_in = [&](int role, int pt) { return st.in + (role * 2 + pt) * st.plane + cn; };
   auto plane_out = [&](int role, int pt) { return st.out + (role * 2 + pt) * st.plane + cn; };
+  auto at = [&](int r) { return (long)r * nq + q; };
 
   double pe[R], po[R];  // latest even and odd terms
   double ys[R], yo[R];
@@ -303,30 +344,15 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
   double gm2 = 0.0;
   const int s = st.s;
 
-  // rows of 2 G for step s
-  {
-    const double a = job.ab[2 * s], b = job.ab[2 * s + 1];
+  // rows of 2 Ht for step s; the coupling above the first row is row base - 1's
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const long i = base + r;
-      d2[r] = 0.0;
-      g2[r] = 0.0;
-      if (i >= 0 && i < n) {
-        const double vi = job.v_diag[i];
-        d2[r] = 2.0 * (job.h0_diag[i] + a * vi - job.beta) * job.inv_dE;
-        if (i + 1 < n) {
-          const double2 h = h0o[i];
-          const double q = b * (job.v_diag[i + 1] - vi);
-          g2[r] = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
-        }
-      }
-    }
-    if (base >= 1 && base < n) {
-      const double2 h = h0o[base - 1];
-      const double q = b * (job.v_diag[base] - job.v_diag[base - 1]);
-      gm2 = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * job.inv_dE;
-    }
+  for (int r = 0; r < R; ++r) {
+    const long i = base + r;
+    const bool in_col = i >= 0 && i < n;
+    d2[r] = in_col ? stc[at(r)] : 0.0;
+    g2[r] = in_col ? stc[n16 + at(r)] : 0.0;
   }
+  if (base >= 1 && base < n) gm2 = stc[n16 + (long)(R - 1) * nq + q - 1];
 
   // load
 #pragma unroll
@@ -344,15 +370,15 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
           xr = (i == col) ? 1.0 : 0.0;
           xi = 0.0;
         }
-        const double2 g = gauge[(long)s * n + i];
+        const double2 g = reinterpret_cast<const double2*>(job.gauge)[(long)s * n + i];
         e = part == 0 ? g.x * xr + g.y * xi : g.x * xi - g.y * xr;  // conj(w) x
       } else {
-        e = plane_in(0, part)[i];
+        e = plane_in(0, part)[at(r)];
         if (st.l0 > 0) {
-          o = plane_in(1, part)[i];
+          o = plane_in(1, part)[at(r)];
           if (owned) {
-            y1 = plane_in(2, part)[i];
-            y2 = plane_in(3, part)[i];
+            y1 = plane_in(2, part)[at(r)];
+            y2 = plane_in(3, part)[at(r)];
           }
         }
       }
@@ -439,42 +465,41 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     for (int r = 0; r < R; ++r) {
       const long i = base + r;
       if (i >= a0 && i < own_end) {
-        plane_out(0, part)[i] = pe[r];
-        plane_out(1, part)[i] = po[r];
-        plane_out(2, part)[i] = ys[r];
-        plane_out(3, part)[i] = yo[r];
+        plane_out(0, part)[at(r)] = pe[r];
+        plane_out(1, part)[at(r)] = po[r];
+        plane_out(2, part)[at(r)] = ys[r];
+        plane_out(3, part)[at(r)] = yo[r];
       }
     }
     return;
   }
 
   // step end: both halves of Y meet; X~_{s+1} = phase w_s conj(w_{s+1}) Y, or
-  // X = phase w_s Y after the last step (to x_out, complex128 row-major).
+  // X = phase w_s Y after the last step (to x_out, row-major).
+  const int np = G * 64;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    double* slot = ysh + (((long)part * G * 64 + pl) * R + r) * 2;
-    slot[0] = ys[r];
-    slot[1] = yo[r];
+    double2* slot = reinterpret_cast<double2*>(ysh) + ((long)part * R + r) * np + pl;
+    *slot = make_double2(ys[r], yo[r]);
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const long i = base + r;
     if (i < a0 || i >= own_end) continue;
-    const double* other = ysh + (((long)(1 - part) * G * 64 + pl) * R + r) * 2;
-    const double own = ys[r] + other[1];
-    const double oth = yo[r] + other[0];
+    const double2 other = reinterpret_cast<const double2*>(ysh)[((long)(1 - part) * R + r) * np + pl];
+    const double own = ys[r] + other.y;
+    const double oth = yo[r] + other.x;
     const double yr = part == 0 ? own : oth, yi = part == 0 ? oth : own;
-    const double2 ws = gauge[(long)s * n + i];
-    double rr = job.phr * ws.x - job.phi * ws.y, ri = job.phr * ws.y + job.phi * ws.x;
+    double rr = stc[2 * n16 + at(r)], ri = stc[3 * n16 + at(r)];  // phase w_s
     if (job.snap && (s + 1 - job.k0) % job.snap_every == 0) {  // X_{s+1}, plain frame
       const long j = (s + 1 - job.k0) / job.snap_every - 1;
       store_part(job.snap, (j * n + i) * job.ncols + col, part, job.c64,
                  part == 0 ? rr * yr - ri * yi : rr * yi + ri * yr);
     }
     if (!st.last_step) {
-      const double2 wn = gauge[(long)(s + 1) * n + i];
-      const double tr = rr * wn.x + ri * wn.y, ti = ri * wn.x - rr * wn.y;
+      const double wr = stc[4 * n16 + at(r)], wi = stc[5 * n16 + at(r)];
+      const double tr = rr * wr + ri * wi, ti = ri * wr - rr * wi;
       rr = tr;
       ri = ti;
     }
@@ -482,13 +507,14 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     if (st.last_step)
       store_part(job.x_out, i * job.ld_out + col, part, job.c64, v);
     else
-      plane_out(0, part)[i] = v;
+      plane_out(0, part)[at(r)] = v;
   }
 }
 
 template <int R, int MAXT>
 hipError_t launch_stream_r(const TridiagJob& job, const TridiagStream& st, int G, hipStream_t s) {
-  const size_t shmem = sizeof(double) * 2 * (size_t)G * 64 * R * 2;
+  // only a pass that ends its step exchanges the two halves of Y through LDS
+  const size_t shmem = st.l1 > job.L ? sizeof(double) * 2 * (size_t)G * 64 * R * 2 : 0;
   const long grid = job.ncols * st.nblk;
   if (grid < 1 || grid > 0x7fffffffL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((tridiag_stream_kernel<R, MAXT>), dim3((unsigned)grid), dim3(2 * G * 64),
@@ -831,9 +857,19 @@ hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st,
   if (job.n < 1 || job.ncols < 1 || st.K < 2 || st.l0 < 0 || st.l1 <= st.l0 ||
       st.l1 - st.l0 > st.K || st.l1 > job.L + 1 || st.B < 1 ||
       st.B + 2L * st.K != tridiag_stream_rows() || st.nblk != (job.n + st.B - 1) / st.B ||
-      (st.l0 == 1))
+      (st.l0 == 1) || st.K % 16 || st.B % 16 || st.n16 != (job.n + 15) / 16 * 16 ||
+      st.plane < st.n16 * job.ncols || st.stepc == nullptr)
     return hipErrorInvalidValue;
   return launch_stream_r<16, 512>(job, st, 4, s);
+}
+
+hipError_t launch_tridiag_stream_step(const TridiagJob& job, const TridiagStream& st,
+                                      double* stepc, hipStream_t s) {
+  if (job.n < 1 || st.n16 != (job.n + 15) / 16 * 16 || st.s < 0 || stepc == nullptr)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_stream_step_kernel, dim3((unsigned)((st.n16 + 255) / 256)), dim3(256),
+                     0, s, job, st.s, st.last_step, st.n16, stepc);
+  return hipGetLastError();
 }
 
 long tridiag_adjoint_max_n() { return 8L * 64 * 4; }
