@@ -35,6 +35,10 @@ PEAK_HBM_GBS = 8000.0
 #: complex adds (4), 2 t - P_{l-1} (4) and the Bessel-weighted accumulation (4).
 TRIDIAG_FLOPS_PER_ELEMENT_TERM = 26
 
+#: longest column the library keeps resident in one workgroup; longer ones run
+#: as streamed passes with ghost rows
+TRIDIAG_RESIDENT_MAX_N = 4096
+
 WORKLOAD_TEXT = {
     "gue4096": "random-matrix model N=4096 (GUE H0, V), f=cos t, T=2pi, M=200 Magnus-4 steps, "
                "Chebyshev order for 1e-12 per step",
@@ -375,7 +379,11 @@ def main():
         tr = recorded_traffic("tridiag", args.workload)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4),
-                "traffic": tr["bytes"] if tr else None, "traffic_detail": tr, "kernel": "tridiag_gauge_kernel<16,512> (whole chain per state column, real gauge form)",
+                "traffic": tr["bytes"] if tr else None, "traffic_detail": tr,
+                "kernel": ("tridiag_gauge_kernel<16,512> (whole chain per state column, real gauge form)"
+                           if n <= TRIDIAG_RESIDENT_MAX_N else
+                           "tridiag_stream_kernel<16,1> (128-term passes; 768 owned + 2 x 128 ghost "
+                           "rows per workgroup, real gauge form)"),
                 "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops * per_build / s_per_build / 1e12

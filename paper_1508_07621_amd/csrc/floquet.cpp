@@ -636,12 +636,13 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
     return FQ_OK;
   }
   // Longer columns: k-term passes with ghost rows, state ping-ponged through HBM.
-  const int K = 128;
+  const int K = 128, G = 1;  // 768 owned rows per workgroup
   fq::TridiagStream st{};
+  st.G = G;
   st.n16 = (c->n + 15) / 16 * 16;
   st.plane = st.n16 * ncols;
   st.K = K;
-  st.B = fq::tridiag_stream_rows() - 2L * K;
+  st.B = fq::tridiag_stream_rows(G) - 2L * K;
   st.nblk = (c->n + st.B - 1) / st.B;
   const size_t state = 8 * (size_t)st.n16 * (size_t)c->n;
   double* buf[2] = {c->d_stream, c->d_stream + state};

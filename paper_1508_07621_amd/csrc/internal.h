@@ -174,8 +174,8 @@ hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s);
 long tridiag_resident_max_n();
 
 // Longer columns: one launch runs terms [l0, l1) of step s on blocks of B owned
-// rows with K ghost rows per side (B + 2K = tridiag_stream_rows()), reading the
-// state from `in` and writing it to `out` (8 planes of ncols x n doubles each),
+// rows with K ghost rows per side (B + 2K = tridiag_stream_rows(G)), reading the
+// state from `in` and writing it to `out` (8 planes of ncols x n16 doubles each),
 // or, at the end of the last step (last_step and l1 == L + 1), X to job.x_out.
 // first_step with l0 == 0 takes X from job.x0 (identity when null) instead of in.
 // State planes between passes hold row i of a column at (i mod 16) nq + i / 16
@@ -193,10 +193,11 @@ struct TridiagStream {
   int first_step;
   int last_step;
   int K;            // ghost rows per side
+  int G;            // waves per part: 1024 G rows per workgroup (the launcher takes G = 1)
   long B;           // owned rows per block
   long nblk;        // blocks per column = ceil(n / B)
 };
-long tridiag_stream_rows();
+long tridiag_stream_rows(int G);
 hipError_t launch_tridiag_stream_step(const TridiagJob& job, const TridiagStream& st,
                                       double* stepc, hipStream_t s);
 

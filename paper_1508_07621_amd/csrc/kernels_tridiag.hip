@@ -267,10 +267,12 @@ hipError_t launch_r(const TridiagJob& job, int G, hipStream_t s) {
 // ---- columns longer than one workgroup holds: k-term passes over HBM ----------------------------
 //
 // A column is cut into blocks of B owned rows; a workgroup loads its block with
-// K ghost rows on each side (4096 rows: 16 per lane, 4 waves per part), runs at
-// most K terms of one step in registers exactly as above, and writes back only
-// its owned rows: after t terms the rows within t of a cut are stale, the owned
-// ones are not. Between launches the state lives in HBM in the gauge frame of
+// K ghost rows on each side (1024 G rows: 16 per lane, G waves per part), runs
+// at most K terms of one step in registers exactly as above, and writes back
+// only its owned rows: after t terms the rows within t of a cut are stale, the
+// owned ones are not. One wave per part (G = 1) is what the library launches:
+// its waves never wait for each other inside a pass, and the third of the rows
+// that are ghosts costs less than a barrier per term does with G = 2 or 4. Between launches the state lives in HBM in the gauge frame of
 // the current step, as 8 planes of ncols x n16 doubles: role 0 = latest even
 // term, role 1 = latest odd term, role 2 = the part's own share of the sum,
 // role 3 = its share of the other component; plane index (role * 2 + part).
@@ -314,10 +316,12 @@ __global__ __launch_bounds__(256) void tridiag_stream_step_kernel(TridiagJob job
   out[5 * n16 + at] = ni;
 }
 
-template <int R, int MAXT>
-__global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, TridiagStream st,
-                                                              int G) {
+template <int R, int G>
+__global__ __launch_bounds__(512) void tridiag_stream_kernel(TridiagJob job, TridiagStream st,
+                                                             const double2* __restrict__ coef,
+                                                             const double* __restrict__ stc) {
   static_assert(R == 16, "the interleaved state layout assumes 16 rows per lane");
+  static_assert(G >= 1 && G <= 4 && G <= kMaxWaves, "waves per part (512 threads at most)");
   extern __shared__ double ysh[];  // [part][r][lane in part][2]
   __shared__ double halo[2][2][2][kMaxWaves];
 
@@ -331,8 +335,6 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
   const long q = (a0 - st.K) / 16 + pl;             // row group of this lane (may be < 0)
   const long base = q * 16;                         // global row of this lane's first row
   const double sgn = part == 0 ? 1.0 : -1.0;
-  const double2* coef = reinterpret_cast<const double2*>(job.coef);
-  const double* stc = st.stepc;
   const long cn = col * n16;                        // column offset in a state plane
   auto plane_in = [&](int role, int pt) { return st.in + (role * 2 + pt) * st.plane + cn; };
   auto plane_out = [&](int role, int pt) { return st.out + (role * 2 + pt) * st.plane + cn; };
@@ -389,33 +391,62 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     yo[r] = y2;
   }
 
+  // Neighbour values of the latest term: row base - 1 (up) and row base + R (dn).
+  // post() starts their exchange as soon as the term's two edge rows are final
+  // (lane shifts, and the wave ends through LDS); complete() waits for the other
+  // waves and picks up the wave ends. advance() computes the edge rows first and
+  // the interior rows between the two, so the exchange overlaps the interior.
   int parity = 0;
-  auto neighbours = [&](const double* v, double& up, double& dn) {
+  double up = 0.0, dn = 0.0;
+  auto post = [&](const double* v) {
     up = from_prev_lane(v[R - 1]);
     dn = from_next_lane(v[0]);
-    if (lane == 0) halo[parity][part][0][w] = v[0];
-    if (lane == 63) halo[parity][part][1][w] = v[R - 1];
-    __syncthreads();
-    const double hu = (w > 0) ? halo[parity][part][1][w - 1] : 0.0;
-    const double hd = (w + 1 < G) ? halo[parity][part][0][w + 1] : 0.0;
-    up = (lane == 0) ? hu : up;
-    dn = (lane == 63) ? hd : dn;
+    if constexpr (G > 1) {
+      if (lane == 0) halo[parity][part][0][w] = v[0];
+      if (lane == 63) halo[parity][part][1][w] = v[R - 1];
+    }
+  };
+  auto complete = [&]() {
+    if constexpr (G > 1) {
+      __syncthreads();
+      const double hu = (w > 0) ? halo[parity][part][1][w - 1] : 0.0;
+      const double hd = (w + 1 < G) ? halo[parity][part][0][w + 1] : 0.0;
+      up = (lane == 0) ? hu : up;
+      dn = (lane == 63) ? hd : dn;
+    } else {
+      up = (lane == 0) ? 0.0 : up;
+      dn = (lane == 63) ? 0.0 : dn;
+    }
     parity ^= 1;
   };
-  auto advance = [&](const double* v, double* nw) {
-    double up, dn;
-    neighbours(v, up, dn);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double lo = (r == 0) ? up : v[r - 1];
-      const double hi = (r == R - 1) ? dn : v[r + 1];
-      double t = fma(d2[r], v[r], -nw[r]);
-      t = fma((r == 0) ? gm2 : g2[r - 1], lo, t);
-      nw[r] = fma(g2[r], hi, t);
+  auto advance = [&](const double* v, double* nw) {  // nw = 2 Ht v - nw
+    {
+      double t = fma(d2[0], v[0], -nw[0]);
+      t = fma(gm2, up, t);
+      nw[0] = fma(g2[0], v[1], t);
     }
+    {
+      double t = fma(d2[R - 1], v[R - 1], -nw[R - 1]);
+      t = fma(g2[R - 2], v[R - 2], t);
+      nw[R - 1] = fma(g2[R - 1], dn, t);
+    }
+    post(nw);
+#pragma unroll
+    for (int r = 1; r < R - 1; ++r) {
+      double t = fma(d2[r], v[r], -nw[r]);
+      t = fma(g2[r - 1], v[r - 1], t);
+      nw[r] = fma(g2[r], v[r + 1], t);
+    }
+    complete();
   };
 
   int l = st.l0;
+  // the latest term on entry: P_0 (l0 = 0) or P_{l0 - 1}, even in pe, odd in po
+  if (l == 0 || (l & 1))
+    post(pe);
+  else
+    post(po);
+  complete();
   if (l == 0) {  // P_0 = X~ (in pe), P_1 = G X~ (into po)
     const double c0 = coef[0].x;
 #pragma unroll
@@ -427,6 +458,8 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
     l = 1;
     if (l < st.l1) {
       advance(pe, po);
+      up *= 0.5;
+      dn *= 0.5;
       const double c1 = sgn * coef[1].y;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -511,14 +544,15 @@ __global__ __launch_bounds__(MAXT) void tridiag_stream_kernel(TridiagJob job, Tr
   }
 }
 
-template <int R, int MAXT>
-hipError_t launch_stream_r(const TridiagJob& job, const TridiagStream& st, int G, hipStream_t s) {
+template <int G>
+hipError_t launch_stream_g(const TridiagJob& job, const TridiagStream& st, hipStream_t s) {
+  constexpr int R = 16;
   // only a pass that ends its step exchanges the two halves of Y through LDS
   const size_t shmem = st.l1 > job.L ? sizeof(double) * 2 * (size_t)G * 64 * R * 2 : 0;
   const long grid = job.ncols * st.nblk;
   if (grid < 1 || grid > 0x7fffffffL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((tridiag_stream_kernel<R, MAXT>), dim3((unsigned)grid), dim3(2 * G * 64),
-                     shmem, s, job, st, G);
+  hipLaunchKernelGGL((tridiag_stream_kernel<R, G>), dim3((unsigned)grid), dim3(2 * G * 64), shmem,
+                     s, job, st, reinterpret_cast<const double2*>(job.coef), st.stepc);
   return hipGetLastError();
 }
 
@@ -851,16 +885,17 @@ hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-long tridiag_stream_rows() { return 4L * 64 * 16; }
+long tridiag_stream_rows(int G) { return (long)G * 64 * 16; }
 
 hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s) {
   if (job.n < 1 || job.ncols < 1 || st.K < 2 || st.l0 < 0 || st.l1 <= st.l0 ||
       st.l1 - st.l0 > st.K || st.l1 > job.L + 1 || st.B < 1 ||
-      st.B + 2L * st.K != tridiag_stream_rows() || st.nblk != (job.n + st.B - 1) / st.B ||
+      st.G != 1 || st.B + 2L * st.K != tridiag_stream_rows(st.G) ||
+      st.nblk != (job.n + st.B - 1) / st.B ||
       (st.l0 == 1) || st.K % 16 || st.B % 16 || st.n16 != (job.n + 15) / 16 * 16 ||
       st.plane < st.n16 * job.ncols || st.stepc == nullptr)
     return hipErrorInvalidValue;
-  return launch_stream_r<16, 512>(job, st, 4, s);
+  return launch_stream_g<1>(job, st, s);
 }
 
 hipError_t launch_tridiag_stream_step(const TridiagJob& job, const TridiagStream& st,
