@@ -141,13 +141,24 @@ def _blas_threads() -> int:
 
 
 #: MFMA operations issued per algorithmic real flop of a complex product
-#: (algorithmic: four real products, 8 N^3 flop): FP64 and FP32 run the four
-#: real products once; BF16x3 runs three real products (Gauss) for each of six
-#: piece pairs, 18 / 4 = 4.5.
-MFMA_FLOPS_PER_FLOP = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 4.5}
+#: (algorithmic: four real products, 8 N^3 flop): FP32 runs the four real
+#: products once; FP64 on 128 x 128 tiles runs three (Gauss), 3 / 4, and four on
+#: 64 x 64 tiles; BF16x3 runs three real products (Gauss) for each of six piece
+#: pairs, 18 / 4 = 4.5.
+MFMA_FLOPS_PER_FLOP = {"fp64": 0.75, "fp32": 1.0, "bf16x3": 4.5}
+
+#: products of at least this many output elements use 128 x 128 tiles
+BIG_TILE_ELEMS = 256 * 128 * 128
+
+
+def mfma_flops_per_flop(precision: str, n: int) -> float:
+    if precision == "fp64" and n * n < BIG_TILE_ELEMS:
+        return 1.0
+    return MFMA_FLOPS_PER_FLOP[precision]
 PEAKS = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
          "bf16x3": PEAK_BF16_MFMA_TFLOPS}
-KERNEL_NAMES = {"fp64": "zgemm_nt_f64_kernel<128,128,16,2,4,EpiCheb<MID>> (FP64 MFMA 16x16x4)",
+KERNEL_NAMES = {"fp64": "zgemm_nt_f64_kernel<128,128,8,2,4,Gauss,EpiCheb<MID>> (FP64 MFMA 16x16x4, "
+                        "3 real products)",
                 "fp32": "cheb_f32_kernel<128,128,32,2,4,EpiMix<MID>> (FP32 MFMA 16x16x4)",
                 "bf16x3": "cheb_bf3_kernel<128,128,2,4,MID> (BF16 MFMA 32x32x16, 3 real products "
                           "x 6 piece pairs)"}
@@ -239,7 +250,7 @@ def dense_roofline(reports, n: int, precision: str, workload: str):
     n_launch = sum(r["n_kernel"][K_MID] for r in reports)
     ms_launch = sum(r["ms_kernel"][K_MID] for r in reports) / max(n_launch, 1)
     flops = 8.0 * n ** 3                                   # one complex N x N x N product
-    mfma_flops = flops * MFMA_FLOPS_PER_FLOP[precision]
+    mfma_flops = flops * mfma_flops_per_flop(precision, n)
     achieved = mfma_flops / (ms_launch * 1e-3) / 1e12
     peak = PEAKS[precision]
     tr = recorded_traffic(precision, workload)

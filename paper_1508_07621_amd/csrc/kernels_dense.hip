@@ -3,7 +3,8 @@
 // phase fused into the epilogue, plus the O(N^2) helpers around them.
 //
 // Complex products use four real MFMA products per operand pair on planar
-// (real / imaginary) operands. Every product has the form
+// (real / imaginary) operands, or three (Gauss) on the large tiles. Every
+// product has the form
 //     C(m, n) = sum_k A(m, k) B(n, k)
 // with both operands contiguous along k ("NT"), which is what the state-major
 // storage of the propagated block gives: A = P_l^T (row j = state j) and
@@ -44,8 +45,14 @@ struct Operands {
 // Within a stage, lane l reads the k pair (8p + 2(l/16), +1) of its row with one
 // 16-byte LDS read and feeds two MFMA k-steps; A and B use the same k order, so
 // the sum over k is unchanged.
+//
+// GAUSS: three real products per k-step instead of four, T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2, Im = T3 - T1 - T2 (Gauss's complex
+// multiplication). The sums Ar + Ai and Br + Bi are formed in registers from
+// the fragments just read, so LDS keeps two planes per operand.
 // ---------------------------------------------------------------------------------------
-template <int BM, int BN, int BK, int WGM, int WGN, bool CONJ_A, bool CONJ_B, class Epi>
+template <int BM, int BN, int BK, int WGM, int WGN, bool CONJ_A, bool CONJ_B, bool GAUSS,
+          class Epi>
 __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op, Epi epi) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
@@ -67,7 +74,9 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
   const int wm = wid / WGN, wn = wid % WGN;
   const long ld = op.ld;
 
-  d4 accR[FM][FN], accI[FM][FN];
+  // 4M: accR = Re, accI = Im; GAUSS: accR = T1, accI = T2, accS = T3
+  constexpr int SM = GAUSS ? FM : 1, SN = GAUSS ? FN : 1;
+  d4 accR[FM][FN], accI[FM][FN], accS[SM][SN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -75,6 +84,10 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
       accR[i][j] = d4{0, 0, 0, 0};
       accI[i][j] = d4{0, 0, 0, 0};
     }
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) accS[i][j] = d4{0, 0, 0, 0};
 
   d2 ga[2][RA], gb[2][RB];
   auto gload = [&](int k0) {
@@ -121,6 +134,39 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
     if (kb + 1 < nk) lstore(cur ^ 1);  // that stage was last read before the previous barrier
     if (kb + 2 < nk) gload((kb + 2) * BK);
     const int rr = lane & 15;
+    if constexpr (GAUSS) {
+#pragma unroll
+      for (int p = 0; p < BK / 8; ++p) {
+        const int kk = 8 * p + 2 * (lane >> 4);
+        d2 fbr[FN], fbi[FN], fbs[FN];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int row = wn * WTN + j * 16 + rr;
+          fbr[j] = *reinterpret_cast<const d2*>(&Bs[cur][0][row * S + kk]);
+          fbi[j] = *reinterpret_cast<const d2*>(&Bs[cur][1][row * S + kk]);
+          fbs[j] = fbr[j] + fbi[j];
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const int row = wm * WTM + i * 16 + rr;
+          const d2 far_ = *reinterpret_cast<const d2*>(&As[cur][0][row * S + kk]);
+          const d2 fai = *reinterpret_cast<const d2*>(&As[cur][1][row * S + kk]);
+          const d2 fas = far_ + fai;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j) accR[i][j] = mfma_f64(far_[t], fbr[j][t], accR[i][j]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j) accI[i][j] = mfma_f64(fai[t], fbi[j][t], accI[i][j]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              accS[i % SM][j % SN] = mfma_f64(fas[t], fbs[j][t], accS[i % SM][j % SN]);
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
 #pragma unroll
     for (int p = 0; p < BK / 8; ++p) {
       const int kk = 8 * p + 2 * (lane >> 4);
@@ -168,7 +214,12 @@ __global__ __launch_bounds__(WGM* WGN * 64) void zgemm_nt_f64_kernel(Operands op
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * WTM + i * 16 + 4 * r + (lane >> 4);
         const int n = n0 + wn * WTN + j * 16 + (lane & 15);
-        epi(m, n, accR[i][j][r], accI[i][j][r]);
+        if constexpr (GAUSS) {
+          const double t1 = accR[i][j][r], t2 = accI[i][j][r];
+          epi(m, n, t1 - t2, accS[i % SM][j % SN][r] - t1 - t2);
+        } else {
+          epi(m, n, accR[i][j][r], accI[i][j][r]);
+        }
       }
   epi.finish();
 }
@@ -327,18 +378,27 @@ struct EpiAdjDot {
   }
 };
 
+// 128 x 128 tiles take Gauss's three products with 8-wide K-stages: the third
+// accumulator set (64 VGPRs) fits the 256-VGPR budget of two waves per SIMD only
+// once the staged loads shrink to one 16-byte chunk per plane (8.15 -> 6.49 ms
+// per N = 4096 product; with 16-wide stages it spills and takes 9.97 ms). The
+// 64 x 64 tiles keep four products: with a third set their accumulators move
+// between AGPRs and VGPRs on every stage.
+constexpr bool kGaussBig = true, kGaussSmall = false;
+constexpr int kBigBK = 8;
+
 template <bool CONJ_A, bool CONJ_B, class Epi>
 hipError_t launch_gemm(const Operands& op0, int mrows, int ncols, Epi epi, hipStream_t s) {
   Operands op = op0;
   if (mrows % 128 == 0 && ncols % 128 == 0 && (long)mrows * ncols >= kBigTileElems) {
     op.tiles_m = mrows / 128;
     op.tiles_n = ncols / 128;
-    hipLaunchKernelGGL((zgemm_nt_f64_kernel<128, 128, 16, 2, 4, CONJ_A, CONJ_B, Epi>),
+    hipLaunchKernelGGL((zgemm_nt_f64_kernel<128, 128, kBigBK, 2, 4, CONJ_A, CONJ_B, kGaussBig, Epi>),
                        dim3(grid_rows(op.tiles_m) * op.tiles_n), dim3(512), 0, s, op, epi);
   } else if (mrows % 64 == 0 && ncols % 64 == 0) {
     op.tiles_m = mrows / 64;
     op.tiles_n = ncols / 64;
-    hipLaunchKernelGGL((zgemm_nt_f64_kernel<64, 64, 16, 2, 2, CONJ_A, CONJ_B, Epi>),
+    hipLaunchKernelGGL((zgemm_nt_f64_kernel<64, 64, 16, 2, 2, CONJ_A, CONJ_B, kGaussSmall, Epi>),
                        dim3(grid_rows(op.tiles_m) * op.tiles_n), dim3(256), 0, s, op, epi);
   } else {
     return hipErrorInvalidValue;
