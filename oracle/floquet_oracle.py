@@ -12,7 +12,9 @@ systems", arXiv:1508.07621):
   states (Sec. 2, Eq. (9); time grid t_k = k T / M);
 * each step's Hamiltonian from the Magnus series (Sec. 2, Eq. (8)) truncated
   after its commutator term with two-point Gauss-Legendre quadrature (4th
-  order; the paper's own choice is a higher-order midpoint variant, Eq. (14));
+  order), or by the paper's own sixth-order midpoint scheme (Sec. 3, Eq. (14)
+  with its alpha_j and C_1, C_2), the alpha_j taken from three-point
+  Gauss-Legendre quadrature;
 * each exponential either exactly (Hermitian eigendecomposition, "route E") or
   by the paper's Chebyshev recurrence (Sec. 2, Eqs. (10)-(12), "route C"), on
   the spectrum rescaled into [-1, 1] (Eq. (11));
@@ -26,7 +28,13 @@ Readings of the paper that this file takes (each pinned by a test):
 * the rescaled operator of Eqs. (10)-(12) is (H_eff - beta) / dE with
   beta = (E_max + E_min)/2, dE = (E_max - E_min)/2, R = h dE, global phase
   exp(-i beta h);
-* the spectral interval must contain the spectrum of every step's H_eff.
+* the spectral interval must contain the spectrum of every step's H_eff;
+* in the sixth-order scheme the alpha_j are the three-point Gauss-Legendre
+  combinations of A(t) = -i H(t) at the nodes 1/2 -/+ sqrt(15)/10 and 1/2:
+  alpha_1 = h A_2, alpha_2 = (sqrt(15) h / 3)(A_3 - A_1),
+  alpha_3 = (10 h / 3)(A_3 - 2 A_2 + A_1); these agree with the printed
+  scaled midpoint derivatives to leading order, and with them the scheme has
+  order six (with the exact derivatives it has order four).
 
 Parity pins: every function here is pinned by a test in tests/test_oracle_pins.py
 against closed forms, a brute-force ODE integration, group theory (spin
@@ -49,6 +57,7 @@ __all__ = [
     "column_error", "fro_error", "unitarity_error", "nearest_unitary", "eigenphases",
     "quasienergy_distance",
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
+    "GL3_C", "node_times6", "magnus6_omega", "magnus6_heff", "exact_cover",
 ]
 
 # ---------------------------------------------------------------------------
@@ -98,6 +107,65 @@ def magnus4_weights(f_nodes: np.ndarray, h: float) -> Tuple[np.ndarray, np.ndarr
 def magnus4_heff(H0, V, K, a: float, b: float):
     """H_eff = H0 + a V + b K (dense or scipy.sparse operands)."""
     return H0 + a * V + b * K
+
+
+# ---------------------------------------------------------------------------
+# The paper's sixth-order Magnus scheme (Sec. 3, Eq. (14)), three-point
+# Gauss-Legendre alpha_j
+# ---------------------------------------------------------------------------
+
+#: Nodes of the three-point Gauss-Legendre rule on [0, 1], in time order.
+GL3_C = (0.5 - math.sqrt(15.0) / 10.0, 0.5, 0.5 + math.sqrt(15.0) / 10.0)
+
+
+def node_times6(T: float, M: int) -> np.ndarray:
+    """Sampling times of the drive for the sixth-order scheme, shape (M, 3):
+    t_{k-1} + c_j h for the three Gauss-Legendre nodes, h = T / M."""
+    h = T / M
+    k = np.arange(M, dtype=np.float64)[:, None]
+    return (k + np.asarray(GL3_C)[None, :]) * h
+
+
+def magnus6_omega(H0: np.ndarray, V: np.ndarray, f3, h: float) -> np.ndarray:
+    """Omega of one step of length h for the generator A(t) = -i (H0 + f(t) V),
+    by the paper's scheme (Sec. 3, Eq. (14)):
+        Omega = alpha_1 + alpha_3 / 12 + [-20 alpha_1 - alpha_3 + C_1, alpha_2 + C_2] / 240,
+        C_1 = [alpha_1, alpha_2],  C_2 = -[alpha_1, 2 alpha_3 + C_1] / 60,
+    with the alpha_j from the drive f3 = (f_1, f_2, f_3) at the three nodes
+    (reading in the module header). Dense matrix arithmetic, as written."""
+    f1, f2, f3_ = (float(x) for x in f3)
+    A1 = -1j * (H0 + f1 * V)
+    A2 = -1j * (H0 + f2 * V)
+    A3 = -1j * (H0 + f3_ * V)
+    al1 = h * A2
+    al2 = (math.sqrt(15.0) * h / 3.0) * (A3 - A1)
+    al3 = (10.0 * h / 3.0) * (A3 - 2.0 * A2 + A1)
+
+    def comm(X, Y):
+        return X @ Y - Y @ X
+
+    C1 = comm(al1, al2)
+    C2 = -comm(al1, 2.0 * al3 + C1) / 60.0
+    return al1 + al3 / 12.0 + comm(-20.0 * al1 - al3 + C1, al2 + C2) / 240.0
+
+
+def magnus6_heff(H0: np.ndarray, V: np.ndarray, f3, h: float) -> np.ndarray:
+    """H_eff with exp(Omega) = exp(-i h H_eff): H_eff = i Omega / h, made exactly
+    Hermitian by averaging with its adjoint (Omega is anti-Hermitian up to
+    rounding)."""
+    H = 1j * magnus6_omega(H0, V, f3, h) / h
+    return 0.5 * (H + H.conj().T)
+
+
+def exact_cover(Heffs) -> Tuple[float, float]:
+    """min / max over the given Hermitian matrices of their exact extreme
+    eigenvalues (LAPACK): the tightest interval containing every spectrum."""
+    lo, hi = np.inf, -np.inf
+    for H in Heffs:
+        ev = np.linalg.eigvalsh(H)
+        lo = min(lo, float(ev[0]))
+        hi = max(hi, float(ev[-1]))
+    return lo, hi
 
 
 # ---------------------------------------------------------------------------
@@ -265,27 +333,42 @@ def _chain(Hk_of, M: int, T: float, route: str, X0, e_min, e_max, L, tol, k_rang
 def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: int,
              route: str = "cheb", e_min: Optional[float] = None, e_max: Optional[float] = None,
              L: Optional[int] = None, tol: float = 1e-12, X0: Optional[np.ndarray] = None,
-             return_info: bool = False, k_range: Optional[Tuple[int, int]] = None):
+             return_info: bool = False, k_range: Optional[Tuple[int, int]] = None,
+             scheme: str = "magnus4"):
     """U_T (or U_T X0) of the dense model H0 + f(t) V.
 
-    f_nodes has shape (M, 2): the drive at the two Gauss-Legendre nodes of each
-    step (node_times). route "exact" exponentiates each H_eff exactly; route
-    "cheb" uses the Chebyshev recurrence with the interval [e_min, e_max]
-    (default: the Weyl cover) and order L (default: choose_L(R, tol)).
-    k_range = (k0, k1) applies only steps k0+1 .. k1 to X0: the propagator
-    from t_k0 to t_k1, since single-step propagators compose (Sec. 2).
+    scheme "magnus4": f_nodes has shape (M, 2), the drive at the two
+    Gauss-Legendre nodes of each step (node_times); scheme "magnus6" (the
+    paper's Eq. (14)): shape (M, 3) at the three nodes of node_times6.
+    route "exact" exponentiates each H_eff exactly; route "cheb" uses the
+    Chebyshev recurrence with the interval [e_min, e_max] (default: the Weyl
+    cover for magnus4, the exact cover for magnus6) and order L (default:
+    choose_L(R, tol)). k_range = (k0, k1) applies only steps k0+1 .. k1 to X0:
+    the propagator from t_k0 to t_k1, since single-step propagators compose
+    (Sec. 2).
     """
     H0 = np.asarray(H0, np.complex128)
     V = np.asarray(V, np.complex128)
     n = H0.shape[0]
     h = T / M
-    K = commutator(H0, V)
-    a, b = magnus4_weights(f_nodes, h)
-    if route == "cheb" and (e_min is None or e_max is None):
-        e_min, e_max = weyl_cover(H0, V, K, a, b)
+    if scheme == "magnus6":
+        f3 = np.asarray(f_nodes, np.float64).reshape(M, 3)
+        Hs = [magnus6_heff(H0, V, f3[k], h) for k in range(M)]
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = exact_cover(Hs)
+        Hk_of = Hs.__getitem__
+    elif scheme == "magnus4":
+        K = commutator(H0, V)
+        a, b = magnus4_weights(f_nodes, h)
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = weyl_cover(H0, V, K, a, b)
+
+        def Hk_of(k):
+            return magnus4_heff(H0, V, K, a[k], b[k])
+    else:
+        raise ValueError(scheme)
     X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
-    U, info = _chain(lambda k: magnus4_heff(H0, V, K, a[k], b[k]), M, T, route, X0,
-                     e_min, e_max, L, tol, k_range)
+    U, info = _chain(Hk_of, M, T, route, X0, e_min, e_max, L, tol, k_range)
     info.update(e_min=e_min, e_max=e_max)
     return (U, info) if return_info else U
 

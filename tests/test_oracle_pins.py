@@ -411,3 +411,74 @@ def test_nearest_unitary_is_the_polar_factor():
     assert np.max(np.abs(orc.nearest_unitary(Q) - Q)) < 1e-14
     W = orc.nearest_unitary(Q @ P)
     assert orc.unitarity_error(W)[0] < 1e-14
+
+
+# --- The paper's sixth-order Magnus scheme (three Gauss-Legendre nodes) -----------------------
+
+
+def _nodes6_cos(T, M):
+    return drive_cos(orc.node_times6(T, M), 0.0, 1.0, 1.0)
+
+
+def test_node_times6_integrate_quintics_exactly():
+    """Weights 5/18, 8/18, 5/18 at the three nodes integrate t^5 over each step."""
+    T, M = 1.7, 3
+    h = T / M
+    t = orc.node_times6(T, M)
+    w = np.array([5.0, 8.0, 5.0]) / 18.0
+    for k in range(M):
+        exact = ((k + 1) ** 6 - k ** 6) * h ** 6 / 6.0
+        assert abs(h * np.dot(w, t[k] ** 5) - exact) < 1e-13 * max(1.0, exact)
+
+
+def test_magnus6_static_drive_is_the_plain_exponent():
+    """A constant drive: every alpha_j but the first vanishes, H_eff = H0 + f V."""
+    H0, V = _rm(5, 41)
+    H = orc.magnus6_heff(H0, V, (0.7, 0.7, 0.7), 0.3)
+    assert np.abs(H - (H0 + 0.7 * V)).max() < 1e-14
+
+
+def test_magnus6_commuting_operators_reduce_to_gauss_legendre():
+    """Diagonal H0 and V commute: Omega = -i (h H0 + V * integral of f over the
+    step), and the three-node rule integrates a quintic drive exactly. A wrong
+    alpha_1 or alpha_3 weight breaks this."""
+    rng = np.random.default_rng(5)
+    H0 = np.diag(rng.normal(size=4)).astype(np.complex128)
+    V = np.diag(rng.normal(size=4)).astype(np.complex128)
+    c = rng.normal(size=6)
+    f = np.polynomial.Polynomial(c)
+    t0, h = 0.4, 0.9
+    f3 = f(t0 + np.asarray(orc.GL3_C) * h)
+    F = f.integ()
+    avg = (F(t0 + h) - F(t0)) / h
+    H = orc.magnus6_heff(H0, V, f3, h)
+    assert np.abs(H - (H0 + avg * V)).max() < 1e-12
+
+
+def test_magnus6_sixth_order_convergence():
+    """e(M) / e(2M) -> 64 against an independent integrator; dropping C_2 or the
+    commutator bracket leaves order four (ratio 16), which this rejects."""
+    H0, V, Ht = _gue_drive(6, 3)
+    T = TWO_PI
+    ref = _brute_force(Ht, 6, T)
+    errs = []
+    for M in (16, 32, 64):
+        U = orc.build_ut(H0, V, _nodes6_cos(T, M), T, M, route="exact", scheme="magnus6")
+        errs.append(orc.column_error(U, ref))
+    r = [errs[i] / errs[i + 1] for i in range(2)]
+    assert all(55.0 < x < 70.0 for x in r), r
+
+
+def test_magnus6_chebyshev_route_matches_exact_route():
+    H0, V, _ = _gue_drive(7, 8)
+    T, M = TWO_PI, 12
+    f = _nodes6_cos(T, M)
+    Ue = orc.build_ut(H0, V, f, T, M, route="exact", scheme="magnus6")
+    Uc, info = orc.build_ut(H0, V, f, T, M, route="cheb", scheme="magnus6", tol=1e-14,
+                            return_info=True)
+    assert orc.column_error(Uc, Ue) < 1e-12
+    # the exact cover is attained: some step's spectrum touches each end
+    lo, hi = info["e_min"], info["e_max"]
+    h = T / M
+    evs = [np.linalg.eigvalsh(orc.magnus6_heff(H0, V, f[k], h)) for k in range(M)]
+    assert min(e[0] for e in evs) == lo and max(e[-1] for e in evs) == hi
