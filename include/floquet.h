@@ -17,6 +17,20 @@
  *   - rescaling into [-1, 1] (Sec. 2, Eq. (11)):
  *         Ht = (H_eff,k - beta) / dE,  beta = (e_max + e_min) / 2,
  *         dE = (e_max - e_min) / 2,    R = h dE;
+ *     or, with fq_params.scheme = FQ_MAGNUS6, the paper's own sixth-order
+ *     scheme (Sec. 3, Eq. (14)) from the drive at the three Gauss-Legendre
+ *     nodes t_{k-1} + (1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10) h (values
+ *     f1, f2, f3), for the generator A(t) = -i H(t):
+ *         alpha_1 = h A(f2), alpha_2 = (sqrt(15) h / 3)(A(f3) - A(f1)),
+ *         alpha_3 = (10 h / 3)(A(f3) - 2 A(f2) + A(f1)),
+ *         C_1 = [alpha_1, alpha_2], C_2 = -[alpha_1, 2 alpha_3 + C_1] / 60,
+ *         Omega = alpha_1 + alpha_3 / 12
+ *                 + [-20 alpha_1 - alpha_3 + C_1, alpha_2 + C_2] / 240,
+ *         H_eff,k = i Omega / h
+ *     (the alpha_j as quadrature combinations rather than scaled midpoint
+ *     derivatives: with them the scheme has order six). H_eff,k is a real
+ *     combination of H0, Hmod and nine nested commutators of H0 and Hmod,
+ *     formed once per context (dense layout only);
  *   - Chebyshev expansion with Bessel weights (Sec. 2, Eqs. (10)-(12)), in the
  *     equivalent real-multiplier form
  *         P_0 = X, P_1 = Ht X, P_{l+1} = 2 Ht P_l - P_{l-1},
@@ -86,6 +100,11 @@ typedef struct fq_system {
   const double* hmod_diag;
 } fq_system;
 
+/* Effective Hamiltonian of one step. FQ_MAGNUS4: two Gauss-Legendre nodes,
+ * one commutator (fourth order). FQ_MAGNUS6: the paper's Eq. (14) from three
+ * Gauss-Legendre nodes (sixth order); dense layout, no gradient tape. */
+typedef enum fq_scheme { FQ_MAGNUS4 = 0, FQ_MAGNUS6 = 1 } fq_scheme;
+
 /* Storage of the state blocks that cross the boundary: U_T, X0, X_out, the
  * snapshots and U_bar. Operators stay complex128 / float64. */
 typedef enum fq_dtype {
@@ -100,9 +119,10 @@ typedef struct fq_params {
   int32_t M;                 /* steps per period >= 1; h = T / M */
   int32_t L;                 /* Chebyshev order; 0 = smallest L with
                                 2 sum_{l>L} |J_l(R)| <= tol */
-  const double* f_nodes;     /* host, 2*M float64: f at the two Gauss-Legendre
-                                nodes of each step, earlier node first
-                                (fq_node_times gives the times) */
+  const double* f_nodes;     /* host, float64: f at the Gauss-Legendre nodes
+                                of each step in time order, 2*M values for
+                                FQ_MAGNUS4 (fq_node_times gives the times) or
+                                3*M for FQ_MAGNUS6 (fq_node_times_magnus6) */
   double e_min, e_max;       /* spectral interval containing the spectrum of
                                 every H_eff,k; both NaN = the library computes
                                 it (tridiagonal: exact per-step extremes by
@@ -112,12 +132,16 @@ typedef struct fq_params {
                                 FQ_ERR_SPECTRUM when it misses a point known to
                                 lie in some step's spectral hull (tridiagonal:
                                 the exact extremes; dense: Ritz values of H_eff
-                                at the steps with the smallest and largest a_k) */
+                                at the steps with the smallest and largest
+                                weight of Hmod). FQ_MAGNUS6 widens the dense
+                                cover by sum_j |w_j| times a bound on the norm
+                                of each nested commutator (||[A, B]|| <=
+                                2 ||A|| ||B||) */
   double tol;                /* truncation tolerance used when L == 0 (> 0) */
   int32_t precision;         /* fq_precision (FQ_TRIDIAG supports FQ_FP64 only) */
   int32_t checkpoint_every;  /* > 0: floquet_build_UT keeps X_0, X_s, X_2s, ...
                                 (s = checkpoint_every) for floquet_grad;
-                                0 = no tape */
+                                0 = no tape. FQ_MAGNUS4 only. */
   int32_t profile;           /* 1: time every kernel launch of a build with HIP
                                 events on the library's stream and report the
                                 per-kind sums in fq_report; 0: off */
@@ -130,7 +154,9 @@ typedef struct fq_params {
                                 (a correction of the result, not part of the
                                 paper's method). 0: off */
   int32_t dtype;             /* fq_dtype of the state blocks */
-  int32_t reserved2;         /* must be 0 */
+  int32_t scheme;            /* fq_scheme; FQ_MAGNUS6 needs FQ_DENSE and
+                                checkpoint_every == 0 (else
+                                FQ_ERR_UNSUPPORTED) */
 } fq_params;
 
 /* Kernel kinds timed in profile mode (indices of fq_report.ms_kernel). */
@@ -166,6 +192,11 @@ typedef struct fq_ctx fq_ctx;  /* opaque; host memory owned by the library */
  * t_out: host, 2*M float64. */
 fq_status fq_node_times(double T, int32_t M, double* t_out);
 
+/* Three-point Gauss-Legendre sampling times for FQ_MAGNUS6: t_out[3k + j] =
+ * (k + c_j) h with c = 1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10.
+ * t_out: host, 3*M float64. */
+fq_status fq_node_times_magnus6(double T, int32_t M, double* t_out);
+
 /* Expansion weights a_0 = J_0(R), a_l = 2 J_l(R), l = 1..L (Sec. 2, Eq. (12)),
  * by Miller's backward recurrence normalised with J_0 + 2 sum_k J_2k = 1.
  * R >= 0, L >= 0; out: host, L+1 float64. */
@@ -184,9 +215,10 @@ fq_status fq_tridiag_extremes(int64_t n, const double* d, const double* e_abs,
  * pointer expected). Checks the arguments like fq_create. */
 fq_status fq_workspace_bytes(const fq_system* sys, const fq_params* par, size_t* bytes);
 
-/* Create a context: validates, computes K, the spectral interval, R, L, the
- * Bessel weights and the node scalars (host FP64 except K, which is formed on
- * the device). The operator arrays of sys must stay valid and unchanged for
+/* Create a context: validates, computes K (FQ_MAGNUS6: the nine nested
+ * commutators), the spectral interval, R, L, the Bessel weights and the node
+ * scalars (host FP64 except the commutators, which are formed on the device
+ * with FP64 matrix products). The operator arrays of sys must stay valid and unchanged for
  * the life of the context. workspace: device, ws_bytes >= fq_workspace_bytes.
  * stream: a hipStream_t (NULL = default stream). */
 fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par,
@@ -217,7 +249,7 @@ fq_status floquet_build_UT(fq_ctx* ctx, void* U_out, fq_report* rep);
 fq_status floquet_propagate(fq_ctx* ctx, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
                             void* X_out, void* snapshots, int32_t snap_every);
 
-/* Gradient of a real loss of U_T with respect to the 2*M drive samples, by
+/* Gradient of a real loss of U_T with respect to the 2*M drive samples (FQ_MAGNUS4), by
  * the reverse sweep through the Chebyshev recurrence of every step (beta, dE
  * and L held fixed), recomputing each segment from the tape of the last
  * floquet_build_UT. U_bar: device, n*n complex (fq_params.dtype) row-major with

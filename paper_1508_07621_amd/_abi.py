@@ -17,13 +17,15 @@ STATUS_NAMES = {0: "FQ_OK", 1: "FQ_ERR_ARG", 2: "FQ_ERR_NONFINITE", 3: "FQ_ERR_S
                 4: "FQ_ERR_HIP", 5: "FQ_ERR_UNSUPPORTED", 6: "FQ_ERR_STATE"}
 FQ_DENSE, FQ_TRIDIAG = 0, 1
 FQ_C128, FQ_C64 = 0, 1
+FQ_MAGNUS4, FQ_MAGNUS6 = 0, 1
+SCHEMES = {"magnus4": FQ_MAGNUS4, "magnus6": FQ_MAGNUS6}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 #: kernel kinds timed in profile mode (fq_report.ms_kernel indices)
 K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 8
 
 #: every entry point include/floquet.h declares
 EXPORTS = (
-    "fq_node_times", "fq_bessel_weights", "fq_choose_order", "fq_tridiag_extremes",
+    "fq_node_times", "fq_node_times_magnus6", "fq_bessel_weights", "fq_choose_order", "fq_tridiag_extremes",
     "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_get_report",
     "floquet_build_UT", "floquet_propagate", "floquet_grad", "fq_last_error",
 )
@@ -41,7 +43,7 @@ class FqParams(ctypes.Structure):
                 ("e_min", c_double), ("e_max", c_double), ("tol", c_double),
                 ("precision", c_int32), ("checkpoint_every", c_int32),
                 ("profile", c_int32), ("reorthonormalize", c_int32),
-                ("dtype", c_int32), ("reserved2", c_int32)]
+                ("dtype", c_int32), ("scheme", c_int32)]
 
 
 class FqReport(ctypes.Structure):
@@ -81,6 +83,7 @@ def lib() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     st = c_int32
     L.fq_node_times.argtypes = [c_double, c_int32, POINTER(c_double)]
+    L.fq_node_times_magnus6.argtypes = [c_double, c_int32, POINTER(c_double)]
     L.fq_bessel_weights.argtypes = [c_double, c_int32, POINTER(c_double)]
     L.fq_choose_order.argtypes = [c_double, c_double, POINTER(c_int32)]
     L.fq_tridiag_extremes.argtypes = [c_int64, POINTER(c_double), POINTER(c_double),

@@ -59,11 +59,17 @@ long pad_to(long x, long t) { return (x + t - 1) / t * t; }
 
 bool is_finite(double x) { return std::isfinite(x); }
 
+int nodes_per_step(int scheme) { return scheme == FQ_MAGNUS6 ? 3 : 2; }
+
+// Number of nested commutators in the sixth-order effective Hamiltonian.
+constexpr int kComm6 = 9;
+
 struct Layout {
   size_t total = 0;
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
          off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
-         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0;
+         off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0,
+         off_comm6 = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -96,6 +102,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.off_pa = take(pbytes);
     lay.off_pb = take(pbytes);
     if (par->precision != FQ_FP64) lay.off_htx = take(pbytes);
+    if (par->scheme == FQ_MAGNUS6) lay.off_comm6 = take(kComm6 * plane2);
     if (par->checkpoint_every > 0) {
       lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
       lay.off_tape = take(plane2 * (size_t)lay.n_tape);
@@ -149,7 +156,9 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (!is_finite(par->T) || par->T <= 0) return fail(FQ_ERR_ARG, "T must be finite and > 0");
   if (par->M < 1) return fail(FQ_ERR_ARG, "M must be >= 1");
   if (!par->f_nodes) return fail(FQ_ERR_ARG, "f_nodes is null");
-  for (int i = 0; i < 2 * par->M; ++i)
+  if (par->scheme != FQ_MAGNUS4 && par->scheme != FQ_MAGNUS6)
+    return fail(FQ_ERR_ARG, "scheme must be FQ_MAGNUS4 or FQ_MAGNUS6");
+  for (int i = 0; i < nodes_per_step(par->scheme) * par->M; ++i)
     if (!is_finite(par->f_nodes[i])) return fail(FQ_ERR_NONFINITE, "f_nodes[%d] is not finite", i);
   if (par->L < 0 || par->L > kMaxOrder) return fail(FQ_ERR_ARG, "L out of range [0, %d]", kMaxOrder);
   if (par->L == 0 && (!is_finite(par->tol) || par->tol <= 0))
@@ -169,7 +178,13 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
     return fail(FQ_ERR_ARG, "reorthonormalize must be 0 or 1");
   if (par->dtype != FQ_C128 && par->dtype != FQ_C64)
     return fail(FQ_ERR_ARG, "dtype must be FQ_C128 or FQ_C64");
-  if (par->reserved2 != 0) return fail(FQ_ERR_ARG, "reserved2 must be 0");
+  if (par->scheme == FQ_MAGNUS6) {
+    if (sys->layout != FQ_DENSE)
+      return fail(FQ_ERR_UNSUPPORTED, "FQ_MAGNUS6 needs the dense layout (its nested "
+                                      "commutators of a tridiagonal H0 are not tridiagonal)");
+    if (par->checkpoint_every > 0)
+      return fail(FQ_ERR_UNSUPPORTED, "the gradient tape is implemented for FQ_MAGNUS4 only");
+  }
   if (sys->layout == FQ_TRIDIAG) {
     if (par->precision != FQ_FP64)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal layout runs in FP64 only");
@@ -181,6 +196,89 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal gradient needs n <= %ld",
                   fq::tridiag_adjoint_max_n());
   }
+  return FQ_OK;
+}
+
+// ---- the sixth-order scheme -------------------------------------------------------------------
+//
+// For H(t) = H0 + f(t) V and A = -i H, the three-point Gauss-Legendre alphas of
+// Eq. (14) are alpha_1 = -i (h H0 + a V), alpha_2 = -i g2 V, alpha_3 = -i g3 V with
+//   a = h f2,  g2 = (sqrt(15) h / 3)(f3 - f1),  g3 = (10 h / 3)(f3 - 2 f2 + f1).
+// Writing K1 = [H0, V] (anti-Hermitian) and expanding C_1, C_2 and the bracket,
+// every term is a real multiple of one of the Hermitian matrices
+//   B1 = i K1,          B2 = [H0, K1],        B3 = [V, K1],
+//   B4 = i [H0, B2],    B5 = i [H0, B3],      B6 = i [V, B2],    B7 = i [V, B3],
+//   B8 = [K1, B2],      B9 = [K1, B3],
+// and H_eff = i Omega / h = H0 + (f2 + g3 / (12 h)) V + sum_j w_j B_j with
+//   w1 = g2 / 12,                 w2 = -g3 h / 360,
+//   w3 = (g2^2 - (20 a + g3) g3 / 30) / 240,
+//   w4 = h^2 g2 / 720,            w5 = h a g2 / 720,
+//   w6 = (20 a + g3) h g2 / 14400, w7 = (20 a + g3) a g2 / 14400,
+//   w8 = -h^2 g2^2 / 14400,       w9 = -h a g2^2 / 14400.
+// (A constant drive gives g2 = g3 = 0 and H_eff = H0 + f V.)
+void magnus6_weights(double h, double f1, double f2, double f3, double* wv, double* w) {
+  const double a = h * f2;
+  const double g2 = std::sqrt(15.0) * h / 3.0 * (f3 - f1);
+  const double g3 = 10.0 * h / 3.0 * (f3 - 2.0 * f2 + f1);
+  const double q = 20.0 * a + g3;
+  *wv = f2 + g3 / (12.0 * h);
+  w[0] = g2 / 12.0;
+  w[1] = -g3 * h / 360.0;
+  w[2] = (g2 * g2 - q * g3 / 30.0) / 240.0;
+  w[3] = h * h * g2 / 720.0;
+  w[4] = h * a * g2 / 720.0;
+  w[5] = q * h * g2 / 14400.0;
+  w[6] = q * a * g2 / 14400.0;
+  w[7] = -h * h * g2 * g2 / 14400.0;
+  w[8] = -h * a * g2 * g2 / 14400.0;
+}
+
+// B = s i [P, Q] for Hermitian P, Q on FP64 matrix cores: (P Q)(i, j) =
+// sum_k P(i, k) conj(Q(j, k)), and likewise Q P.
+fq_status hermitian_commutator(fq_ctx* c, const double* pr, const double* pi, const double* qr,
+                               const double* qi, double s, double* br, double* bi) {
+  const int np = (int)c->np;
+  FQ_HIP(c, fq::launch_zgemm_nt_f64(pr, pi, false, qr, qi, true, br, bi, np, np, np, np, 0.0, s,
+                                    0.0, 0.0, c->stream));
+  FQ_HIP(c, fq::launch_zgemm_nt_f64(qr, qi, false, pr, pi, true, br, bi, np, np, np, np, 0.0, -s,
+                                    1.0, 0.0, c->stream));
+  return FQ_OK;
+}
+
+// The nine B_j of the sixth-order scheme from the planar H0 and V.
+fq_status magnus6_commutators(fq_ctx* c) {
+  const size_t plane = (size_t)c->np * (size_t)c->np;
+  auto re = [&](int j) { return c->comm6 + 2 * plane * j; };
+  auto im = [&](int j) { return c->comm6 + 2 * plane * j + plane; };
+  // K1 = -i B1, so [X, K1] = -i [X, B1] and [K1, Y] = -i [B1, Y]
+  FQ_TRY(hermitian_commutator(c, c->h0r, c->h0i, c->vr, c->vi, 1.0, re(0), im(0)));   // B1
+  FQ_TRY(hermitian_commutator(c, c->h0r, c->h0i, re(0), im(0), -1.0, re(1), im(1)));  // B2
+  FQ_TRY(hermitian_commutator(c, c->vr, c->vi, re(0), im(0), -1.0, re(2), im(2)));    // B3
+  FQ_TRY(hermitian_commutator(c, c->h0r, c->h0i, re(1), im(1), 1.0, re(3), im(3)));   // B4
+  FQ_TRY(hermitian_commutator(c, c->h0r, c->h0i, re(2), im(2), 1.0, re(4), im(4)));   // B5
+  FQ_TRY(hermitian_commutator(c, c->vr, c->vi, re(1), im(1), 1.0, re(5), im(5)));     // B6
+  FQ_TRY(hermitian_commutator(c, c->vr, c->vi, re(2), im(2), 1.0, re(6), im(6)));     // B7
+  FQ_TRY(hermitian_commutator(c, re(0), im(0), re(1), im(1), -1.0, re(7), im(7)));    // B8
+  FQ_TRY(hermitian_commutator(c, re(0), im(0), re(2), im(2), -1.0, re(8), im(8)));    // B9
+  return FQ_OK;
+}
+
+// Into (outr, outi): sum_j w6[k][j] B_j, plus H0 + a_k V when with_base.
+fq_status magnus6_sum(fq_ctx* c, int k, bool with_base, double* outr, double* outi) {
+  const size_t plane = (size_t)c->np * (size_t)c->np;
+  fq::WeightedSum ws{};
+  int t = 0;
+  if (with_base) {
+    ws.re[t] = c->h0r; ws.im[t] = c->h0i; ws.w[t++] = 1.0;
+    ws.re[t] = c->vr;  ws.im[t] = c->vi;  ws.w[t++] = c->a[k];
+  }
+  for (int j = 0; j < kComm6; ++j) {
+    ws.re[t] = c->comm6 + 2 * plane * j;
+    ws.im[t] = c->comm6 + 2 * plane * j + plane;
+    ws.w[t++] = c->w6[(size_t)kComm6 * k + j];
+  }
+  ws.count = t;
+  FQ_HIP(c, fq::launch_weighted_sum(ws, (long)plane, outr, outi, c->stream));
   return FQ_OK;
 }
 
@@ -198,6 +296,20 @@ fq_status device_matvec(fq_ctx* ctx, const void* A, const std::vector<cd>& x, st
   y.resize(n);
   FQ_HIP(ctx, hipMemcpyAsync(dx, x.data(), n * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
   FQ_HIP(ctx, fq::launch_zgemv(A, n, dx, dy, ctx->stream));
+  FQ_HIP(ctx, hipMemcpyAsync(y.data(), dy, n * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+  FQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return FQ_OK;
+}
+
+// y = A x for a planar (re, im) device matrix with row stride np.
+fq_status device_matvec_planar(fq_ctx* ctx, const double* ar, const double* ai,
+                               const std::vector<cd>& x, std::vector<cd>& y) {
+  const long n = ctx->n;
+  void* dx = ctx->yr;
+  void* dy = ctx->yr + 2 * n;
+  y.resize(n);
+  FQ_HIP(ctx, hipMemcpyAsync(dx, x.data(), n * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+  FQ_HIP(ctx, fq::launch_zgemv_planar(ar, ai, n, ctx->np, dx, dy, ctx->stream));
   FQ_HIP(ctx, hipMemcpyAsync(y.data(), dy, n * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
   FQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return FQ_OK;
@@ -269,6 +381,30 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
   hv += margin * wv;
   const double kap = 2.0 * std::max(std::fabs(l0), std::fabs(h0)) * std::max(std::fabs(lv), std::fabs(hv));
   double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+  if (ctx->scheme == FQ_MAGNUS6) {
+    // ||B_j|| from ||[X, Y]|| <= 2 ||X|| ||Y|| along the nesting of the B_j
+    const double n0 = std::max(std::fabs(l0), std::fabs(h0)), nv = std::max(std::fabs(lv), std::fabs(hv));
+    double nb[kComm6];
+    nb[0] = kap;
+    nb[1] = 2.0 * n0 * nb[0];
+    nb[2] = 2.0 * nv * nb[0];
+    nb[3] = 2.0 * n0 * nb[1];
+    nb[4] = 2.0 * n0 * nb[2];
+    nb[5] = 2.0 * nv * nb[1];
+    nb[6] = 2.0 * nv * nb[2];
+    nb[7] = 2.0 * nb[0] * nb[1];
+    nb[8] = 2.0 * nb[0] * nb[2];
+    for (int k = 0; k < ctx->M; ++k) {
+      const double a = ctx->a[k];
+      double r = 0.0;
+      for (int j = 0; j < kComm6; ++j) r += std::fabs(ctx->w6[(size_t)kComm6 * k + j]) * nb[j];
+      lo = std::min(lo, l0 + std::min(a * lv, a * hv) - r);
+      hi = std::max(hi, h0 + std::max(a * lv, a * hv) + r);
+    }
+    *lo_out = lo;
+    *hi_out = hi;
+    return FQ_OK;
+  }
   for (int k = 0; k < ctx->M; ++k) {
     const double a = ctx->a[k], b = std::fabs(ctx->b[k]);
     lo = std::min(lo, l0 + std::min(a * lv, a * hv) - b * kap);
@@ -292,6 +428,18 @@ fq_status dense_inner_bounds(fq_ctx* ctx, double* lo_out, double* hi_out) {
   double lo = std::numeric_limits<double>::infinity(), hi = -lo;
   for (int k : {kmin, kmax}) {
     const double a = ctx->a[k], b = ctx->b[k];
+    if (ctx->scheme == FQ_MAGNUS6) {  // H_eff,k formed on the device (Ht planes are free)
+      FQ_TRY(magnus6_sum(ctx, k, true, ctx->htr, ctx->hti));
+      Matvec mz = [&](const std::vector<cd>& x, std::vector<cd>& y) {
+        return device_matvec_planar(ctx, ctx->htr, ctx->hti, x, y);
+      };
+      double l, h;
+      FQ_TRY(lanczos_ritz(ctx, mz, &l, &h));
+      lo = std::min(lo, l);
+      hi = std::max(hi, h);
+      if (kmin == kmax) break;
+      continue;
+    }
     Matvec mv = [&](const std::vector<cd>& x, std::vector<cd>& y) {
       // H0 x + a Hmod x + b K x with K x = -i (H0 (Hmod x) - Hmod (H0 x))
       std::vector<cd> u1, u2, u3, u4;
@@ -399,6 +547,7 @@ fq_status collect_profile(fq_ctx* c) {
 
 fq_status dense_heff(fq_ctx* c, int k) {
   FQ_MARK(c, FQ_K_HEFF);
+  if (c->scheme == FQ_MAGNUS6) FQ_TRY(magnus6_sum(c, k, false, c->kr, c->ki));  // K slot
   if (c->precision == FQ_FP64) {
     FQ_HIP(c, fq::launch_heff_f64(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
                                   c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->stream));
@@ -850,6 +999,14 @@ fq_status fq_node_times(double T, int32_t M, double* t_out) {
   return FQ_OK;
 }
 
+fq_status fq_node_times_magnus6(double T, int32_t M, double* t_out) {
+  if (!is_finite(T) || T <= 0) return fail(FQ_ERR_ARG, "T must be finite and > 0");
+  if (M < 1) return fail(FQ_ERR_ARG, "M must be >= 1");
+  if (!t_out) return fail(FQ_ERR_ARG, "t_out is null");
+  fq::gl3_node_times(T, M, t_out);
+  return FQ_OK;
+}
+
 fq_status fq_bessel_weights(double R, int32_t L, double* out) {
   if (!is_finite(R) || R < 0) return fail(FQ_ERR_ARG, "R must be finite and >= 0");
   if (L < 0 || L > kMaxOrder) return fail(FQ_ERR_ARG, "L out of range");
@@ -916,13 +1073,23 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->profile = par->profile != 0;
   c->reortho = par->reorthonormalize != 0;
   c->c64 = par->dtype == FQ_C64;
-  c->f_nodes.assign(par->f_nodes, par->f_nodes + 2 * par->M);
+  c->scheme = par->scheme;
+  c->f_nodes.assign(par->f_nodes, par->f_nodes + nodes_per_step(par->scheme) * par->M);
   c->a.resize(c->M);
   c->b.resize(c->M);
-  for (int k = 0; k < c->M; ++k) {
-    const double f1 = c->f_nodes[2 * k], f2 = c->f_nodes[2 * k + 1];
-    c->a[k] = 0.5 * (f1 + f2);
-    c->b[k] = std::sqrt(3.0) * c->h * (f1 - f2) / 12.0;
+  if (c->scheme == FQ_MAGNUS6) {
+    c->w6.resize((size_t)kComm6 * c->M);
+    for (int k = 0; k < c->M; ++k) {
+      const double* f = &c->f_nodes[3 * k];
+      magnus6_weights(c->h, f[0], f[1], f[2], &c->a[k], &c->w6[(size_t)kComm6 * k]);
+      c->b[k] = 1.0;  // the K slot holds the step's commutator sum
+    }
+  } else {
+    for (int k = 0; k < c->M; ++k) {
+      const double f1 = c->f_nodes[2 * k], f2 = c->f_nodes[2 * k + 1];
+      c->a[k] = 0.5 * (f1 + f2);
+      c->b[k] = std::sqrt(3.0) * c->h * (f1 - f2) / 12.0;
+    }
   }
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->ws = reinterpret_cast<char*>(workspace);
@@ -959,6 +1126,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     c->par = P(lay.off_pa); c->pai = c->par + plane;
     c->pbr = P(lay.off_pb); c->pbi = c->pbr + plane;
     if (par->precision != FQ_FP64) c->htx = P(lay.off_htx);
+    if (par->scheme == FQ_MAGNUS6) c->comm6 = P(lay.off_comm6);
     if (lay.n_tape > 0) {
       c->tape = P(lay.off_tape);
       c->n_tape = lay.n_tape;
@@ -989,6 +1157,10 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
         fq::launch_zgemm_nt_f64(c->vr, c->vi, false, c->h0r, c->h0i, true, c->kr, c->ki, np, np,
                                 np, np, 0.0, 1.0, 1.0, 0.0, c->stream) != hipSuccess)
       return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(hipGetLastError())));
+    if (c->scheme == FQ_MAGNUS6) {
+      st = magnus6_commutators(c);
+      if (st != FQ_OK) return bail(st);
+    }
   }
 
   // spectral interval

@@ -22,6 +22,18 @@ void gl2_node_times(double T, int M, double* t_out) {
   }
 }
 
+void gl3_node_times(double T, int M, double* t_out) {
+  // Nodes 1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10 of the three-point
+  // Gauss-Legendre rule on each step, for the sixth-order scheme (Sec. 3, Eq. (14)).
+  const double h = T / M;
+  const double d = std::sqrt(15.0) / 10.0;
+  for (int k = 0; k < M; ++k) {
+    t_out[3 * k] = (k + 0.5 - d) * h;
+    t_out[3 * k + 1] = (k + 0.5) * h;
+    t_out[3 * k + 2] = (k + 0.5 + d) * h;
+  }
+}
+
 // J_0(x) .. J_lmax(x) by Miller's backward recurrence
 //   J_{l-1}(x) = (2 l / x) J_l(x) - J_{l+1}(x),
 // started far above max(lmax, x) from (0, tiny) and normalised with the

@@ -14,6 +14,8 @@ namespace fq {
 
 // ---- host numerics (host_numerics.cpp) ---------------------------------------------------
 void gl2_node_times(double T, int M, double* t_out);
+// Three-point Gauss-Legendre nodes t_{k-1} + (1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10) h.
+void gl3_node_times(double T, int M, double* t_out);
 void bessel_j_table(double x, int lmax, std::vector<double>& out);
 int choose_order(double R, double tol);
 void tridiag_extremes(long n, const double* d, const double* e_abs, double* lo, double* hi);
@@ -145,6 +147,20 @@ hipError_t launch_scale_planar(const double* sr, const double* si, double dr, do
                                double* tr, double* ti, long count, hipStream_t s);
 // y = A x for a dense complex128 row-major matrix (n x n) and vectors x, y (complex128).
 hipError_t launch_zgemv(const void* A, long n, const void* x, void* y, hipStream_t s);
+// y = A x for a planar (re, im) matrix with row stride ld; x, y interleaved complex, n rows.
+hipError_t launch_zgemv_planar(const double* ar, const double* ai, long n, long ld, const void* x,
+                               void* y, hipStream_t s);
+
+// out = sum_j w_j M_j over planar matrices of `total` elements each (real weights).
+constexpr int kMaxSumTerms = 11;
+struct WeightedSum {
+  const double* re[kMaxSumTerms];
+  const double* im[kMaxSumTerms];
+  double w[kMaxSumTerms];
+  int count;
+};
+hipError_t launch_weighted_sum(const WeightedSum& ws, long total, double* outr, double* outi,
+                               hipStream_t s);
 
 // ---- tridiagonal kernels (kernels_tridiag.hip) --------------------------------------------
 struct TridiagJob {
@@ -238,6 +254,13 @@ struct fq_ctx {
   double T = 0, h = 0, tol = 0;
   int M = 0, L = 0, precision = 0, ckpt = 0;
   std::vector<double> f_nodes, a, b;  // host
+  // scheme: 0 = Magnus-4 (H0 + a V + b K); 1 = the sixth-order scheme, whose
+  // H_eff,k = H0 + a_k V + sum_j w6[k][j] B_j over nine fixed Hermitian nested
+  // commutators B_j (device planes comm6, 2 planes each); a_k as above, b_k = 1
+  // for the K slot, which then holds each step's sum over the B_j.
+  int scheme = 0;
+  std::vector<double> w6;             // M x 9
+  double* comm6 = nullptr;
   double e_min = 0, e_max = 0, beta = 0, dE = 0, R = 0;
   std::vector<double> weights;        // a_l = (2 - delta_l0) J_l(R), l = 0..L
   std::vector<double> coef;           // c_l = (2 - delta_l0) (-i)^l J_l(R), interleaved

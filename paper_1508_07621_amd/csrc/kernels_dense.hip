@@ -541,6 +541,48 @@ __global__ void zgemv_kernel(const double2* __restrict__ A, long n, const double
   if (threadIdx.x == 0) y[i] = make_double2(sr[0], si[0]);
 }
 
+// y = A x, A planar (re, im) with row stride ld; one workgroup per row.
+__global__ void zgemv_planar_kernel(const double* __restrict__ ar, const double* __restrict__ ai,
+                                    long n, long ld, const double2* __restrict__ x,
+                                    double2* __restrict__ y) {
+  __shared__ double sr[256], si[256];
+  const long i = blockIdx.x;
+  double accr = 0.0, acci = 0.0;
+  for (long k = threadIdx.x; k < n; k += blockDim.x) {
+    const double a = ar[i * ld + k], b = ai[i * ld + k];
+    const double2 v = x[k];
+    accr += a * v.x - b * v.y;
+    acci += a * v.y + b * v.x;
+  }
+  sr[threadIdx.x] = accr;
+  si[threadIdx.x] = acci;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      si[threadIdx.x] += si[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[i] = make_double2(sr[0], si[0]);
+}
+
+// out = sum_j w_j M_j elementwise over planar matrices (the per-step part of
+// the sixth-order effective Hamiltonian).
+__global__ void weighted_sum_kernel(WeightedSum ws, long total, double* __restrict__ outr,
+                                    double* __restrict__ outi) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < ws.count; ++j) {
+      sr = fma(ws.w[j], ws.re[j][e], sr);
+      si = fma(ws.w[j], ws.im[j][e], si);
+    }
+    outr[e] = sr;
+    outi[e] = si;
+  }
+}
+
 inline unsigned grid_for(long total, int block) {
   long g = (total + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -678,6 +720,24 @@ hipError_t launch_zgemv(const void* A, long n, const void* x, void* y, hipStream
   hipLaunchKernelGGL(zgemv_kernel, dim3((unsigned)n), dim3(256), 0, s,
                      reinterpret_cast<const double2*>(A), n, reinterpret_cast<const double2*>(x),
                      reinterpret_cast<double2*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemv_planar(const double* ar, const double* ai, long n, long ld, const void* x,
+                               void* y, hipStream_t s) {
+  if (n < 1 || ld < n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zgemv_planar_kernel, dim3((unsigned)n), dim3(256), 0, s, ar, ai, n, ld,
+                     reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum(const WeightedSum& ws, long total, double* outr, double* outi,
+                               hipStream_t s) {
+  if (ws.count < 1 || ws.count > kMaxSumTerms || total < 1) return hipErrorInvalidValue;
+  for (int j = 0; j < ws.count; ++j)
+    if (!ws.re[j] || !ws.im[j]) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(weighted_sum_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, ws, total,
+                     outr, outi);
   return hipGetLastError();
 }
 

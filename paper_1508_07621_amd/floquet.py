@@ -24,8 +24,15 @@ def _torch():
 
 # ---- host numerics exported by the library ---------------------------------------------------
 
-def node_times(T: float, M: int) -> np.ndarray:
-    """(M, 2) Gauss-Legendre sampling times of the drive (earlier node first)."""
+def node_times(T: float, M: int, scheme: str = "magnus4") -> np.ndarray:
+    """Gauss-Legendre sampling times of the drive in time order: (M, 2) for
+    "magnus4", (M, 3) for "magnus6"."""
+    if scheme == "magnus6":
+        out = np.empty(3 * M, dtype=np.float64)
+        check(lib().fq_node_times_magnus6(float(T), int(M), dptr(out)))
+        return out.reshape(M, 3)
+    if scheme != "magnus4":
+        raise ValueError("scheme must be magnus4 or magnus6")
     out = np.empty(2 * M, dtype=np.float64)
     check(lib().fq_node_times(float(T), int(M), dptr(out)))
     return out.reshape(M, 2)
@@ -72,7 +79,9 @@ class FloquetContext:
 
     Dense operators: h0, hmod (n x n complex). Tridiagonal: h0_diag (n real),
     h0_off (n-1 complex, H0[i][i+1]), hmod_diag (n real).
-    f_nodes: (M, 2) drive samples at node_times(T, M).
+    f_nodes: drive samples at node_times(T, M, scheme): (M, 2) for "magnus4",
+    (M, 3) for "magnus6" (the paper's sixth-order scheme; dense operators, no
+    gradient).
     precision: "fp64", "fp32" or "bf16x3" (arithmetic of the Chebyshev products).
     reorthonormalize: replace U_T by its polar factor after each build (FP64
     Newton-Schulz); the report keeps the unitarity before and after.
@@ -84,7 +93,8 @@ class FloquetContext:
                  h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
                  e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
                  precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
-                 reorthonormalize: bool = False, dtype: str = "complex128", device=None):
+                 reorthonormalize: bool = False, dtype: str = "complex128",
+                 scheme: str = "magnus4", device=None):
         torch = _torch()
         L_ = lib()
         self.device = torch.device(device if device is not None else "cuda")
@@ -114,9 +124,13 @@ class FloquetContext:
         self.layout = sysd.layout
         self.M = int(M)
         self.T = float(T)
+        if scheme not in _abi.SCHEMES:
+            raise ValueError("scheme must be magnus4 or magnus6")
+        self.scheme = scheme
+        per_step = 3 if scheme == "magnus6" else 2
         self._f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))
-        if self._f.size != 2 * self.M:
-            raise ValueError("f_nodes must hold 2*M values")
+        if self._f.size != per_step * self.M:
+            raise ValueError(f"f_nodes must hold {per_step}*M values for {scheme}")
         par = FqParams()
         par.T, par.M, par.L = self.T, self.M, int(L)
         par.f_nodes = dptr(self._f)
@@ -130,6 +144,7 @@ class FloquetContext:
         if dtype not in ("complex128", "complex64"):
             raise ValueError("dtype must be complex128 or complex64")
         par.dtype = _abi.FQ_C64 if dtype == "complex64" else _abi.FQ_C128
+        par.scheme = _abi.SCHEMES[scheme]
         self.state_dtype = torch.complex64 if dtype == "complex64" else torch.complex128
         self.precision = precision
         import ctypes

@@ -192,7 +192,8 @@ def test_workspace_bytes_ok_and_grows_with_n():
     (lambda s, p: setattr(p, "profile", 2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "reorthonormalize", 2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "dtype", 2), _abi.FQ_ERR_ARG),
-    (lambda s, p: setattr(p, "reserved2", 1), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "scheme", 2), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "scheme", -1), _abi.FQ_ERR_ARG),
 ])
 def test_invalid_arguments_rejected(mutate, status):
     s, p = _dense(), _params()
@@ -225,6 +226,35 @@ def test_tridiag_restrictions():
     assert st == _abi.FQ_OK and b >= 2 * 8 * 8 * 5000 * 5000
     st, _ = _ws(_tridiag(40001), _params())
     assert st == _abi.FQ_ERR_UNSUPPORTED
+
+
+def test_magnus6_restrictions_and_workspace():
+    """The sixth-order scheme reads 3*M drive samples, needs the dense layout and
+    no gradient tape, and holds nine more n x n complex matrices."""
+    f3 = np.zeros(12)
+    st, b4 = _ws(_dense(100), _params(M=4, f=np.zeros(8)))
+    st6, b6 = _ws(_dense(100), _params(M=4, f=f3, scheme=_abi.FQ_MAGNUS6))
+    assert st == st6 == _abi.FQ_OK
+    np_ = 128  # 100 padded to the 64-row tile
+    assert b6 - b4 >= 9 * 16 * np_ * np_
+    st, _ = _ws(_tridiag(100), _params(M=4, f=f3, scheme=_abi.FQ_MAGNUS6))
+    assert st == _abi.FQ_ERR_UNSUPPORTED
+    st, _ = _ws(_dense(100), _params(M=4, f=f3, scheme=_abi.FQ_MAGNUS6, checkpoint_every=2))
+    assert st == _abi.FQ_ERR_UNSUPPORTED
+    # the 3*M samples are all read: a NaN in the last one is caught
+    f3[11] = math.nan
+    st, _ = _ws(_dense(100), _params(M=4, f=f3, scheme=_abi.FQ_MAGNUS6))
+    assert st == _abi.FQ_ERR_NONFINITE
+    assert "f_nodes[11]" in _abi.lib().fq_last_error().decode()
+
+
+def test_magnus6_node_times_match_the_oracle():
+    import oracle as orc
+    t = fl.node_times(2.5, 7, scheme="magnus6")
+    assert t.shape == (7, 3)
+    assert np.abs(t - orc.node_times6(2.5, 7)).max() < 1e-14
+    with pytest.raises(_abi.FloquetError):
+        fl.node_times(2.5, 0, scheme="magnus6")
 
 
 def test_create_rejects_before_device_work():

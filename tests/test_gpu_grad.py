@@ -67,7 +67,7 @@ def test_smooth_drive_gradient_matches_oracle_differences(fl):
     H0, V = gue(n, rng), gue(n, rng)
     W = haar_unitary(n, rng)
     T = 2 * math.pi
-    f = drive_cos(fl.node_times(T, M), 0.2, 1.1, 1.0)
+    f = drive_cos(orc.node_times(T, M), 0.2, 1.1, 1.0)
     lo, hi = -5.0, 5.0
     L = 30
     ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
@@ -203,7 +203,7 @@ def test_tridiag_smooth_drive_gradient_matches_oracle_differences(fl):
     d, e, v = dimer_tridiag(nb, 1.0, 0.3)
     W = haar_unitary(nb + 1, np.random.default_rng(78))
     T = 2 * math.pi
-    f = drive_cos(fl.node_times(T, M), 0.5, 1.5, 1.0)
+    f = drive_cos(orc.node_times(T, M), 0.5, 1.5, 1.0)
     a, b = orc.magnus4_weights(f, T / M)
     lo, hi = orc.tridiag_cover(d, e, v, a, b)
     lo, hi = lo - 1.0, hi + 1.0   # room for the perturbed drives

@@ -30,7 +30,7 @@ def _say(*a):
 
 
 def _cos_nodes(fl, T, M, eps0=0.0, eps1=1.0):
-    return drive_cos(fl.node_times(T, M), eps0, eps1, 1.0)
+    return drive_cos(orc.node_times(T, M), eps0, eps1, 1.0)
 
 
 def _dense_case(n, seed):
@@ -420,7 +420,7 @@ def test_tridiag_dimer1000_full_config(fl):
     d, e, v = wl.arrays["h0_diag"], wl.arrays["h0_off"], wl.arrays["v_diag"]
     M, T = wl.M, wl.T
     _say("tridiag dimer1000", wl.n, M)
-    f = drive_cos(fl.node_times(T, M), 0.5, 1.5, 1.0)
+    f = drive_cos(orc.node_times(T, M), 0.5, 1.5, 1.0)
     a, b = orc.magnus4_weights(f, T / M)
     lo, hi = orc.tridiag_cover(d, e, v, a, b)
     _, _, R = orc.rescale(lo, hi, T / M)
@@ -466,7 +466,7 @@ def test_tridiag_dimer10000_sampled_columns(fl):
     wl = workload("dimer10000")
     d, e, v = wl.arrays["h0_diag"], wl.arrays["h0_off"], wl.arrays["v_diag"]
     M, T, n = wl.M, wl.T, wl.n
-    f = drive_cos(fl.node_times(T, M), 0.5, 1.5, 1.0)
+    f = drive_cos(orc.node_times(T, M), 0.5, 1.5, 1.0)
     a, b = orc.magnus4_weights(f, T / M)
     lo, hi = orc.tridiag_cover(d, e, v, a, b)
     _, _, R = orc.rescale(lo, hi, T / M)
