@@ -8,7 +8,7 @@ M steps, and the FP64 unitarity check of the result. Inputs (operators, drive
 samples) are resident in HBM before the timed region; setup (commutator,
 spectral interval, coefficients) is done once before it.
 
-    python bench.py [--steps K] [--warmup W] [--workload gue4096|dimer1000|gue64]
+    python bench.py [--steps K] [--warmup W] [--workload gue4096|dimer1000|gue64|gue4096m6|...]
 """
 from __future__ import annotations
 
@@ -50,6 +50,8 @@ WORKLOAD_TEXT = {
                    "step = forward build + gradient",
     "dimer10000": "Bose-Hubbard dimer, 9999 bosons (N=10^4, tridiagonal), params as dimer1000, M=500",
     "gue10000": "random-matrix model N=10^4 (GUE H0, V), f=cos t, T=2pi, M=200",
+    "gue4096m6": "random-matrix model N=4096 as gue4096 with the paper's sixth-order Magnus "
+                 "scheme (Eq. (14), three Gauss-Legendre nodes), M=50 steps",
 }
 
 
@@ -60,7 +62,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gue4096", choices=sorted(WORKLOAD_TEXT),
                     help="gue4096 (default), dimer1000, gue64, adjoint1024 (build + gradient), "
-                         "dimer10000, gue10000 (minutes per build)")
+                         "dimer10000, gue10000 (minutes per build), gue4096m6 (sixth-order scheme)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the dense Chebyshev products (the tridiagonal path is FP64)")
     ap.add_argument("--no-fp64-ref", action="store_true",
@@ -318,7 +320,7 @@ def main():
     elif wl.layout == "tridiag":
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.5, 1.5, 1.0)
     else:
-        f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.0, 1.0, 1.0)
+        f_nodes = drive_cos(fl.node_times(wl.T, wl.M, scheme=wl.scheme), 0.0, 1.0, 1.0)
     if wl.layout == "dense":
         kw = dict(h0=wl.arrays["h0"], hmod=wl.arrays["v"])
     else:
@@ -328,7 +330,8 @@ def main():
     t_setup = time.perf_counter()
     ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision=precision,
                             profile=True, device=dev, checkpoint_every=16 if grad_mode else 0,
-                            dtype="complex64" if grad_mode else "complex128", **kw)
+                            dtype="complex64" if grad_mode else "complex128",
+                            scheme=wl.scheme, **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     info = ctx.report
@@ -358,7 +361,7 @@ def main():
             # The FP64 build of the same workload: reference result and timing.
             ref = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision="fp64",
                                     e_min=info["e_min"], e_max=info["e_max"], L=info["L"],
-                                    profile=True, device=dev, **kw)
+                                    profile=True, device=dev, scheme=wl.scheme, **kw)
             Uref = torch.empty_like(U)
             s_ref, rep_ref = time_builds(ref, Uref, 0, 1, "fp64")
             D = U - Uref
@@ -415,14 +418,15 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "n": n,
                    "M": wl.M, "L": info["L"], "R": round(info["R"], 6),
                    "interval": [info["e_min"], info["e_max"]], "precision": precision,
-                   "parallelism": "1 GPU"},
+                   "scheme": wl.scheme, "parallelism": "1 GPU"},
         "build_tflops_algorithmic": round(build_tflops, 3),
         "errors": errors,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
     }
     out.update(extra)
-    if not args.no_cpu_baseline and not grad_mode and wl.n <= 4096:
+    if (not args.no_cpu_baseline and not grad_mode and wl.n <= 4096
+            and wl.scheme == "magnus4"):
         _log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(wl, f_nodes, args.cpu_seconds)
     print(json.dumps(out), flush=True)

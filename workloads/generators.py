@@ -105,6 +105,7 @@ class Workload:
     amplitudes: Optional[np.ndarray] = None   # piecewise-constant f_j per step
     arrays: Dict[str, np.ndarray] = field(default_factory=dict)
     extra: Dict[str, object] = field(default_factory=dict)
+    scheme: str = "magnus4"          # step operator: "magnus4" or "magnus6" (the paper's)
 
 
 def _seed(index: int) -> int:
@@ -130,6 +131,14 @@ def workload(name: str, n: Optional[int] = None, M: Optional[int] = None) -> Wor
         h0, v, _ = random_matrix_model(n, _seed(2))
         return Workload(name, n, "dense", two_pi, M or 200,
                         lambda t: drive_cos(t, 0.0, 1.0, 1.0), arrays={"h0": h0, "v": v})
+    if name == "gue4096m6":
+        # the 4096-state model of gue4096 with the paper's sixth-order scheme
+        # and four times longer steps
+        n = n or 4096
+        h0, v, _ = random_matrix_model(n, _seed(2))
+        return Workload(name, n, "dense", two_pi, M or 50,
+                        lambda t: drive_cos(t, 0.0, 1.0, 1.0), arrays={"h0": h0, "v": v},
+                        scheme="magnus6")
     if name == "adjoint1024":
         n = n or 1024
         m = M or 256
@@ -152,4 +161,5 @@ def workload(name: str, n: Optional[int] = None, M: Optional[int] = None) -> Wor
     raise KeyError(name)
 
 
-WORKLOADS = ("gue64", "dimer1000", "gue4096", "adjoint1024", "dimer10000", "gue10000")
+WORKLOADS = ("gue64", "dimer1000", "gue4096", "adjoint1024", "dimer10000", "gue10000",
+             "gue4096m6")
