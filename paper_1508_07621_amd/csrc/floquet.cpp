@@ -786,6 +786,14 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
   }
   // Longer columns: k-term passes with ghost rows, state ping-ponged through HBM.
   const int K = 128, G = 1;  // 768 owned rows per workgroup
+  if (x0 && x0 == x_out && k1 - k0 == 1 && c->L + 1 <= K) {
+    // One pass both reads X0 (with ghost rows) and writes X_out (owned rows):
+    // in place, a workgroup could overwrite rows its neighbour still reads.
+    // The state planes are unused by a single pass; stage X0 there.
+    const size_t bytes = (size_t)c->n * (size_t)ncols * (c->c64 ? 8 : 16);
+    FQ_HIP(c, hipMemcpyAsync(c->d_stream, x0, bytes, hipMemcpyDeviceToDevice, c->stream));
+    job.x0 = c->d_stream;
+  }
   fq::TridiagStream st{};
   st.G = G;
   st.n16 = (c->n + 15) / 16 * 16;
@@ -1300,6 +1308,13 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
   c->snap_k0 = k0;
   c->snap_ncols = ncols;
   c->n_events = 0;
+  if (k0 == k1) {  // no steps: X_out = X0 (and no snapshot falls in the empty range)
+    const size_t bytes = (size_t)c->n * (size_t)ncols * (c->c64 ? 8 : 16);
+    if (X_out != X0)
+      FQ_HIP(c, hipMemcpyAsync(X_out, X0, bytes, hipMemcpyDeviceToDevice, c->stream));
+    FQ_HIP(c, hipStreamSynchronize(c->stream));
+    return collect_profile(c);
+  }
   if (c->layout == FQ_DENSE) {
     const long mrows = pad_to(ncols, dense_tile(c->n));
     FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->c64,

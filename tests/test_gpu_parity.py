@@ -498,6 +498,62 @@ def test_tridiag_propagate(fl):
     assert orc.column_error(X, Xref) < FP64_TOL
 
 
+def _random_tridiag(n, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(n), rng.standard_normal(n - 1) + 1j * rng.standard_normal(n - 1),
+            rng.standard_normal(n))
+
+
+@pytest.mark.parametrize("layout,n", [("dense", 70), ("tridiag", 150), ("tridiag", 4500)])
+def test_propagate_empty_range_returns_x0(fl, layout, n):
+    """k0 == k1 applies no step: X_out = X0, also at k0 = M (no step's gauge
+    factors exist there) and in place."""
+    _say("empty range", layout, n)
+    T, M = TWO_PI, 6
+    f = _cos_nodes(fl, T, M, 0.2, 0.9)
+    if layout == "dense":
+        H0, V = _dense_case(n, 31)
+        ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f)
+    else:
+        d, e, v = _random_tridiag(n, 32)
+        ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f)
+    rng = np.random.default_rng(33)
+    X0 = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    for k in (0, 3, M):
+        X = ctx.propagate(X0, k, k).cpu().numpy()
+        assert np.array_equal(X, X0)
+    import torch
+    Xd = torch.from_numpy(X0).cuda()
+    ctx.propagate(Xd, M, M, out=Xd)
+    assert np.array_equal(Xd.cpu().numpy(), X0)
+
+
+def test_tridiag_streamed_in_place(fl):
+    """Columns longer than one workgroup holds (4500 rows) propagated in place:
+    one step whose terms fit one 128-term pass (that pass reads X0 with ghost
+    rows and writes X_out), and three steps."""
+    import torch
+    n, M, T = 4500, 10, TWO_PI
+    d, e, v = _random_tridiag(n, 34)
+    f = _cos_nodes(fl, T, M, 0.2, 0.9)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-12)
+    _say("streamed in place", n, M, "L", L)
+    assert L + 1 <= 128
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f, e_min=lo,
+                            e_max=hi, L=L)
+    X0 = haar_unitary(n, np.random.default_rng(35))[:, :4]
+    for k0, k1 in ((3, 4), (3, 6)):
+        Xd = torch.from_numpy(X0).cuda()
+        ctx.propagate(Xd, k0, k1, out=Xd)
+        Xref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L,
+                                    X0=X0, k_range=(k0, k1))
+        err = orc.column_error(Xd.cpu().numpy(), Xref)
+        _say("steps", k0, k1, "e_col", err)
+        assert err < FP64_TOL
+
+
 def test_tridiag_complex_offdiagonal(fl):
     """A general Hermitian tridiagonal H0 (complex couplings) with a diagonal Hmod."""
     rng = np.random.default_rng(12)
