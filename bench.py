@@ -69,6 +69,9 @@ def parse():
                     help="skip the FP64 reference build of a mixed-precision run")
     ap.add_argument("--no-eig", action="store_true", help="skip the host eigenphase comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--second-round", action="store_true",
+                    help="after the timed builds, diagonalise U_T on the host and time the second "
+                         "propagation round (period-averaged energies of all Floquet states)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one device-to-device copy of BYTES bytes (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -264,6 +267,38 @@ def dense_roofline(reports, n: int, precision: str, workload: str):
             "algorithmic_tflops": round(flops / (ms_launch * 1e-3) / 1e12, 3)}
 
 
+def second_round(ctx, U, wl, kw):
+    """The paper's post-processing of a build: host eigenvectors of U_T, then one
+    more period of propagation of all N Floquet states on the device with their
+    period-averaged energies (timed), sorted by mean energy. Full-size check:
+    the mean energies of a complete orthonormal set sum to the grid mean of
+    Tr H(t_k) = Tr H0 + f(t_k) Tr Hmod."""
+    import numpy as np
+    import torch
+    eps0, eps1 = (0.5, 1.5) if wl.layout == "tridiag" else (0.0, 1.0)
+    fg = eps0 + eps1 * np.cos(np.arange(wl.M) * wl.T / wl.M)
+    _log("second round: host eigendecomposition and device period averages")
+    t0 = time.perf_counter()
+    lam, phi = np.linalg.eig(U.cpu().numpy())
+    eig_s = time.perf_counter() - t0
+    phi = phi / np.linalg.norm(phi, axis=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_mean = ctx.period_average(phi, fg)
+    torch.cuda.synchronize()
+    round_s = time.perf_counter() - t0
+    if wl.layout == "dense":
+        tr0, trv = np.trace(kw["h0"]).real, np.trace(kw["hmod"]).real
+    else:
+        tr0, trv = float(np.sum(kw["h0_diag"])), float(np.sum(kw["hmod_diag"]))
+    expect = tr0 + float(np.mean(fg)) * trv
+    return {"s_period_average": round(round_s, 4), "host_eig_vectors_s": round(eig_s, 1),
+            "states": int(phi.shape[1]), "mean_energy_range": [float(e_mean.min()),
+                                                                float(e_mean.max())],
+            "trace_check": {"sum_mean_energies": float(e_mean.sum()), "expected": expect,
+                            "abs_diff": abs(float(e_mean.sum()) - expect)}}
+
+
 def eigen_errors(U, Uref, T: float):
     """Host FP64 eigenphases (LAPACK zgeev through NumPy) of both results and
     the largest quasienergy difference (symmetric circular matching)."""
@@ -401,6 +436,9 @@ def main():
                 "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops * per_build / s_per_build / 1e12
+
+    if args.second_round and not grad_mode:
+        extra["second_round"] = second_round(ctx, U, wl, kw)
 
     out = {
         "metric": "s per U_T build + TFLOP/s (% MFMA/HBM peak), mixed vs FP64 at stated error",

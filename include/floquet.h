@@ -249,6 +249,20 @@ fq_status floquet_build_UT(fq_ctx* ctx, void* U_out, fq_report* rep);
 fq_status floquet_propagate(fq_ctx* ctx, const void* X0, int64_t ncols, int32_t k0, int32_t k1,
                             void* X_out, void* snapshots, int32_t snap_every);
 
+/* Period average of the energy of ncols states (the second propagation round
+ * of Sec. 3: Eq. (average) with A(t) = H(t), e.g. for the Floquet states
+ * phi_mu(0), the eigenvectors of U_T, whose order by mean energy the paper
+ * uses): with x_0 = column c of X0, x_k = E_k ... E_1 x_0 and t_k = k h,
+ *     avg_out[c] = (1/M) sum_{k=0..M-1} <x_k| H0 + f_grid[k] Hmod |x_k> / <x_k|x_k>,
+ * the rectangle rule on the step grid (for a Floquet state the integrand is
+ * smooth and T-periodic, where it converges faster than any power of h).
+ * X0: device, n*ncols complex (fq_params.dtype) row-major, 1 <= ncols <= n;
+ * f_grid: host, M float64, the drive at t_k = k h (not at the quadrature
+ * nodes); avg_out: host, ncols float64. Steps use the context's scheme and
+ * precision; the expectations are FP64. */
+fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, const double* f_grid,
+                                 double* avg_out);
+
 /* Gradient of a real loss of U_T with respect to the 2*M drive samples (FQ_MAGNUS4), by
  * the reverse sweep through the Chebyshev recurrence of every step (beta, dE
  * and L held fixed), recomputing each segment from the tape of the last

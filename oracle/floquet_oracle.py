@@ -19,6 +19,8 @@ systems", arXiv:1508.07621):
   by the paper's Chebyshev recurrence (Sec. 2, Eqs. (10)-(12), "route C"), on
   the spectrum rescaled into [-1, 1] (Eq. (11));
 * quasienergies from the eigenvalues of U_T (Sec. 2, Eq. (4));
+* the period average of the energy of propagated states (the second round of
+  Sec. 3, Eq. (average) with A(t) = H(t)) by the rectangle rule on the step grid;
 * the gradient of a trace-fidelity loss with respect to piecewise-constant drive
   amplitudes (not in the paper; exact Daleckii-Krein derivative of the chain).
 
@@ -58,6 +60,7 @@ __all__ = [
     "quasienergy_distance",
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
     "GL3_C", "node_times6", "magnus6_omega", "magnus6_heff", "exact_cover",
+    "period_average", "period_average_tridiag",
 ]
 
 # ---------------------------------------------------------------------------
@@ -390,6 +393,64 @@ def build_ut_tridiag(h0_diag, h0_off, v_diag, f_nodes, T: float, M: int, route: 
                      e_min, e_max, L, tol, k_range)
     info.update(e_min=e_min, e_max=e_max)
     return (U, info) if return_info else U
+
+
+# ---------------------------------------------------------------------------
+# Second propagation round: period averages (Sec. 3, Eq. (average))
+# ---------------------------------------------------------------------------
+
+def _period_average(Hk_of, Hgrid_of, M, T, X0, route, e_min, e_max, L, tol):
+    """(1/M) sum_{k<M} <x_k|H(t_k)|x_k> / <x_k|x_k> per column, x_k the column
+    after k steps: Eq. (average) with A(t) = H(t) by the rectangle rule on the
+    step grid t_k = k h."""
+    X = np.asarray(X0, np.complex128)
+    acc = np.zeros(X.shape[1])
+    for k in range(M):
+        HX = Hgrid_of(k) @ X
+        acc += np.real(np.sum(X.conj() * HX, axis=0)) / np.sum(np.abs(X) ** 2, axis=0)
+        X, _ = _chain(Hk_of, M, T, route, X, e_min, e_max, L, tol, (k, k + 1))
+    return acc / M
+
+
+def period_average(H0, V, f_nodes, f_grid, T: float, M: int, X0, scheme: str = "magnus4",
+                   route: str = "cheb", e_min=None, e_max=None, L=None, tol: float = 1e-12):
+    """Period-averaged energy of the columns of X0 for the dense model (Eq. (average)
+    with A(t) = H0 + f(t) V); f_grid[k] = f(k h). The steps are those of build_ut
+    with the same arguments (f_nodes at the scheme's nodes)."""
+    H0 = np.asarray(H0, np.complex128)
+    V = np.asarray(V, np.complex128)
+    h = T / M
+    if scheme == "magnus6":
+        f3 = np.asarray(f_nodes, np.float64).reshape(M, 3)
+        Hs = [magnus6_heff(H0, V, f3[k], h) for k in range(M)]
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = exact_cover(Hs)
+        Hk_of = Hs.__getitem__
+    else:
+        K = commutator(H0, V)
+        a, b = magnus4_weights(f_nodes, h)
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = weyl_cover(H0, V, K, a, b)
+
+        def Hk_of(k):
+            return magnus4_heff(H0, V, K, a[k], b[k])
+    fg = np.asarray(f_grid, np.float64)
+    return _period_average(Hk_of, lambda k: H0 + fg[k] * V, M, T, X0, route, e_min, e_max, L, tol)
+
+
+def period_average_tridiag(h0_diag, h0_off, v_diag, f_nodes, f_grid, T: float, M: int, X0,
+                           route: str = "cheb", e_min=None, e_max=None, L=None,
+                           tol: float = 1e-12):
+    """period_average for a Hermitian tridiagonal H0 and a diagonal V (sparse)."""
+    h = T / M
+    H0, V, K = tridiag_matrices(h0_diag, h0_off, v_diag)
+    a, b = magnus4_weights(f_nodes, h)
+    if route == "cheb" and (e_min is None or e_max is None):
+        e_min, e_max = tridiag_cover(h0_diag, h0_off, v_diag, a, b)
+    fg = np.asarray(f_grid, np.float64)
+    return _period_average(lambda k: (H0 + a[k] * V + b[k] * K).tocsr(),
+                           lambda k: (H0 + fg[k] * V).tocsr(), M, T, X0, route, e_min, e_max,
+                           L, tol)
 
 
 # ---------------------------------------------------------------------------

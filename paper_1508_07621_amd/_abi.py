@@ -27,7 +27,8 @@ K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4
 EXPORTS = (
     "fq_node_times", "fq_node_times_magnus6", "fq_bessel_weights", "fq_choose_order", "fq_tridiag_extremes",
     "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_get_report",
-    "floquet_build_UT", "floquet_propagate", "floquet_grad", "fq_last_error",
+    "floquet_build_UT", "floquet_propagate", "floquet_period_average", "floquet_grad",
+    "fq_last_error",
 )
 
 
@@ -96,6 +97,8 @@ def lib() -> ctypes.CDLL:
     L.floquet_build_UT.argtypes = [c_void_p, c_void_p, POINTER(FqReport)]
     L.floquet_propagate.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
                                     c_void_p, c_int32]
+    L.floquet_period_average.argtypes = [c_void_p, c_void_p, c_int64, POINTER(c_double),
+                                         POINTER(c_double)]
     L.floquet_grad.argtypes = [c_void_p, c_void_p, POINTER(c_double)]
     for name in EXPORTS:
         if name != "fq_last_error":

@@ -24,3 +24,41 @@ def eigenphases(U) -> np.ndarray:
     th = -np.angle(lam)
     th[th <= -math.pi] += 2.0 * math.pi
     return np.sort(th)
+
+
+def floquet_states(ctx, U, f_grid):
+    """The Floquet states of a built U_T ordered by mean energy (the paper's
+    post-processing, Sec. 3 and Sec. 7): host eigendecomposition of U_T
+    (LAPACK zgeev through NumPy), then the second propagation round on the
+    device for the period-averaged energies (ctx.period_average). Returns
+    (quasienergies theta/T, states as columns, mean energies), sorted by mean
+    energy ascending. f_grid: the drive at t_k = k h, k = 0..M-1."""
+    try:
+        import torch
+        if isinstance(U, torch.Tensor):
+            U = U.detach().cpu().numpy()
+    except ImportError:
+        pass
+    lam, phi = np.linalg.eig(np.asarray(U, dtype=np.complex128))
+    th = -np.angle(lam)
+    th[th <= -math.pi] += 2.0 * math.pi
+    phi = phi / np.linalg.norm(phi, axis=0)
+    e_mean = ctx.period_average(phi, f_grid)
+    order = np.argsort(e_mean, kind="stable")
+    return th[order] / ctx.T, phi[:, order], e_mean[order]
+
+
+def state_errors(phi, eps, phi_ref, eps_ref, T):
+    """State-specific accuracy of Floquet states against a reference set (e.g.
+    from half the time step, as the paper's overlap phase error does): for each
+    state mu, its best-overlapping reference state nu, the overlap deficiency
+    1 - |<phi_mu|phi_ref_nu>| and the circular quasienergy difference
+    |eps_mu - eps_ref_nu| (modulo 2 pi / T). The printed measure keeps the
+    eigenphase inside the overlap, where it is not small; these two parts are
+    the reading taken here."""
+    ov = np.abs(np.asarray(phi_ref).conj().T @ np.asarray(phi))   # [nu, mu]
+    nu = np.argmax(ov, axis=0)
+    defic = 1.0 - ov[nu, np.arange(ov.shape[1])]
+    period = 2.0 * math.pi / T
+    d = np.abs(np.asarray(eps) - np.asarray(eps_ref)[nu]) % period
+    return defic, np.minimum(d, period - d)

@@ -69,7 +69,7 @@ struct Layout {
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
          off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
          off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0,
-         off_comm6 = 0;
+         off_comm6 = 0, off_vec = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -134,6 +134,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     }
   }
   lay.off_small = take(64 * sizeof(double));
+  lay.off_vec = take(3 * sizeof(double) * (size_t)n);
   lay.off_ab = take(2 * sizeof(double) * (size_t)par->M);
   lay.off_coef = take(2 * sizeof(double) * (size_t)(kMaxOrder + 1));
   lay.total = cur;
@@ -1106,6 +1107,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   auto P = [&](size_t off) { return reinterpret_cast<double*>(c->ws + off); };
   const size_t plane = (size_t)lay.np * (size_t)lay.np;
   c->small = P(lay.off_small);
+  c->d_vec = P(lay.off_vec);
   c->d_ab = P(lay.off_ab);
   c->d_coef = P(lay.off_coef);
   c->xr = P(lay.off_x);
@@ -1329,6 +1331,61 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
   }
+  FQ_HIP(c, hipStreamSynchronize(c->stream));
+  return collect_profile(c);
+}
+
+// Period average of the energy (Sec. 3, Eq. (average) with A(t) = H(t)) by the
+// rectangle rule on the step grid: avg_c = (1/M) sum_{k<M} <x_k|H(t_k)|x_k> / <x_k|x_k>,
+// x_k = E_k ... E_1 x_0, t_k = k h. For a Floquet state the integrand is smooth
+// and T-periodic, where this rule converges faster than any power of h.
+fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const double* f_grid,
+                                 double* avg_out) {
+  if (!c || !X0 || !f_grid || !avg_out) return fail(FQ_ERR_ARG, "null argument");
+  if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
+  for (int k = 0; k < c->M; ++k)
+    if (!is_finite(f_grid[k])) return fail(FQ_ERR_NONFINITE, "f_grid[%d] is not finite", k);
+  c->n_events = 0;
+  c->snap = nullptr;
+  const double w = 1.0 / c->M;
+  double* avg = c->d_vec;
+  double* num = c->d_vec + c->n;
+  double* den = c->d_vec + 2 * c->n;
+  FQ_HIP(c, fq::launch_fill_zero(c->d_vec, 3 * c->n, c->stream));
+  if (c->layout == FQ_DENSE) {
+    const int np = (int)c->np;
+    const long mrows = pad_to(ncols, dense_tile(c->n));
+    FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->c64,
+                                       c->stream));
+    for (int k = 0; k < c->M; ++k) {
+      // H(t_k) into the Ht planes (free between steps), H(t_k) x into the P planes
+      fq::WeightedSum ws{};
+      ws.re[0] = c->h0r; ws.im[0] = c->h0i; ws.w[0] = 1.0;
+      ws.re[1] = c->vr;  ws.im[1] = c->vi;  ws.w[1] = f_grid[k];
+      ws.count = 2;
+      FQ_HIP(c, fq::launch_weighted_sum(ws, c->np * c->np, c->htr, c->hti, c->stream));
+      FQ_HIP(c, fq::launch_zgemm_nt_f64(c->xr, c->xi, false, c->htr, c->hti, false, c->par,
+                                        c->pai, (int)mrows, np, np, np, 1.0, 0.0, 0.0, 0.0,
+                                        c->stream));
+      FQ_HIP(c, fq::launch_energy_rows(c->xr, c->xi, c->par, c->pai, ncols, c->n, c->np, w, avg,
+                                       c->stream));
+      FQ_TRY(dense_steps(c, k, k + 1, (int)mrows, false));
+    }
+  } else {
+    // the states in the user layout, propagated in place one step at a time
+    void* x = c->xr;
+    const size_t bytes = (size_t)c->n * (size_t)ncols * (c->c64 ? 8 : 16);
+    FQ_HIP(c, hipMemcpyAsync(x, X0, bytes, hipMemcpyDeviceToDevice, c->stream));
+    for (int k = 0; k < c->M; ++k) {
+      FQ_HIP(c, fq::launch_tridiag_energy(x, c->c64, c->n, ncols, c->sys.h0_diag, c->sys.h0_off,
+                                          c->sys.hmod_diag, f_grid[k], num, den, c->stream));
+      FQ_HIP(c, fq::launch_energy_finish(num, den, ncols, w, avg, c->stream));
+      FQ_TRY(tridiag_run(c, x, ncols, k, k + 1, x));
+    }
+  }
+  FQ_MARK(c, -1);
+  FQ_HIP(c, hipMemcpyAsync(avg_out, avg, ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   FQ_HIP(c, hipStreamSynchronize(c->stream));
   return collect_profile(c);
 }

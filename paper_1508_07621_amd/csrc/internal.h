@@ -162,6 +162,20 @@ struct WeightedSum {
 hipError_t launch_weighted_sum(const WeightedSum& ws, long total, double* outr, double* outi,
                                hipStream_t s);
 
+// Energy expectations for the period average. Dense (state-major planes, row m
+// = state m < rows, y = H x in the same layout): avg[m] += w Re<x_m, y_m> / |x_m|^2.
+hipError_t launch_energy_rows(const double* xr, const double* xi, const double* yr,
+                              const double* yi, long rows, long n, long ld, double w, double* avg,
+                              hipStream_t s);
+hipError_t launch_fill_zero(double* p, long count, hipStream_t s);
+// Tridiagonal (user layout, complex128 or complex64 when c64), H = H0 + f Hmod:
+// num[c] += Re<x_c, H x_c>, den[c] += |x_c|^2; finish: avg[c] += w num / den, num = den = 0.
+hipError_t launch_tridiag_energy(const void* x, bool c64, long n, long ncols, const double* d,
+                                 const void* off, const double* v, double f, double* num,
+                                 double* den, hipStream_t s);
+hipError_t launch_energy_finish(double* num, double* den, long ncols, double w, double* avg,
+                                hipStream_t s);
+
 // ---- tridiagonal kernels (kernels_tridiag.hip) --------------------------------------------
 struct TridiagJob {
   long n;                // dimension
@@ -290,6 +304,7 @@ struct fq_ctx {
   double* d_coef = nullptr;           // 2*(L+1)
   double* d_gauge = nullptr;          // tridiagonal: M x n complex gauge factors
   double* d_stream = nullptr;         // tridiagonal n > resident size: two 8-plane states
+  double* d_vec = nullptr;            // 3 n doubles: period-average accumulators
   // state
   bool tape_valid = false;
   bool broken = false;

@@ -583,6 +583,40 @@ __global__ void weighted_sum_kernel(WeightedSum ws, long total, double* __restri
   }
 }
 
+// Energy expectation of state rows (state-major planes, row m = state m):
+// avg[m] += w * sum_i Re(conj(x_mi) y_mi) / sum_i |x_mi|^2 with y = H x in
+// the same layout; one workgroup per state, i < n.
+__global__ void energy_rows_kernel(const double* __restrict__ xr, const double* __restrict__ xi,
+                                   const double* __restrict__ yr, const double* __restrict__ yi,
+                                   long n, long ld, double w, double* __restrict__ avg) {
+  __shared__ double sn[256], sd[256];
+  const long m = blockIdx.x;
+  double num = 0.0, den = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) {
+    const long e = m * ld + i;
+    const double a = xr[e], b = xi[e];
+    num += a * yr[e] + b * yi[e];
+    den += a * a + b * b;
+  }
+  sn[threadIdx.x] = num;
+  sd[threadIdx.x] = den;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sn[threadIdx.x] += sn[threadIdx.x + o];
+      sd[threadIdx.x] += sd[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) avg[m] += w * sn[0] / sd[0];
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ p, long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x)
+    p[e] = 0.0;
+}
+
 inline unsigned grid_for(long total, int block) {
   long g = (total + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -728,6 +762,21 @@ hipError_t launch_zgemv_planar(const double* ar, const double* ai, long n, long 
   if (n < 1 || ld < n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(zgemv_planar_kernel, dim3((unsigned)n), dim3(256), 0, s, ar, ai, n, ld,
                      reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_rows(const double* xr, const double* xi, const double* yr,
+                              const double* yi, long rows, long n, long ld, double w, double* avg,
+                              hipStream_t s) {
+  if (rows < 1 || n < 1 || ld < n || rows > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(energy_rows_kernel, dim3((unsigned)rows), dim3(256), 0, s, xr, xi, yr, yi, n,
+                     ld, w, avg);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, long count, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
 

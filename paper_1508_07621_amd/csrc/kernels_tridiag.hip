@@ -885,6 +885,87 @@ hipError_t launch_tridiag_resident(const TridiagJob& job, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// ---- energy expectations of tridiagonal states -------------------------------------------------
+//
+// For states x (user layout, row i of column c at i * ncols + c) and
+// H = H0 + f Hmod: num[c] += sum_i Re(conj(x_i) (H x)_i), den[c] += sum_i |x_i|^2
+// over a chunk of rows per workgroup row (blockIdx.y), one thread per column;
+// then energy_finish adds w num / den to avg and clears num, den.
+namespace {
+constexpr int kEnergyRows = 64;
+
+__global__ __launch_bounds__(256) void tridiag_energy_kernel(const void* x, int c64, long n,
+                                                            long ncols, const double* __restrict__ d,
+                                                            const double2* __restrict__ off,
+                                                            const double* __restrict__ v, double f,
+                                                            double* __restrict__ num,
+                                                            double* __restrict__ den) {
+  const long c = (long)blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncols) return;
+  const long i0 = (long)blockIdx.y * kEnergyRows;
+  const long i1 = (i0 + kEnergyRows < n) ? i0 + kEnergyRows : n;
+  double sn = 0.0, sd = 0.0;
+  double pr = 0.0, pi = 0.0, xr, xi, nr = 0.0, ni = 0.0;
+  if (i0 > 0) load_state(x, (i0 - 1) * ncols + c, c64, pr, pi);
+  load_state(x, i0 * ncols + c, c64, xr, xi);
+  for (long i = i0; i < i1; ++i) {
+    nr = ni = 0.0;
+    if (i + 1 < n) load_state(x, (i + 1) * ncols + c, c64, nr, ni);
+    // (H x)_i = (d_i + f v_i) x_i + H[i][i+1] x_{i+1} + conj(H[i-1][i]) x_{i-1}
+    const double dd = d[i] + f * v[i];
+    double hr = dd * xr, hi = dd * xi;
+    if (i + 1 < n) {
+      const double2 e = off[i];
+      hr += e.x * nr - e.y * ni;
+      hi += e.x * ni + e.y * nr;
+    }
+    if (i > 0) {
+      const double2 e = off[i - 1];
+      hr += e.x * pr + e.y * pi;
+      hi += e.x * pi - e.y * pr;
+    }
+    sn += xr * hr + xi * hi;
+    sd += xr * xr + xi * xi;
+    pr = xr;
+    pi = xi;
+    xr = nr;
+    xi = ni;
+  }
+  atomicAdd(num + c, sn);
+  atomicAdd(den + c, sd);
+}
+
+__global__ void energy_finish_kernel(double* __restrict__ num, double* __restrict__ den, long ncols,
+                                     double w, double* __restrict__ avg) {
+  const long c = (long)blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncols) return;
+  avg[c] += w * num[c] / den[c];
+  num[c] = 0.0;
+  den[c] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_tridiag_energy(const void* x, bool c64, long n, long ncols, const double* d,
+                                 const void* off, const double* v, double f, double* num,
+                                 double* den, hipStream_t s) {
+  if (n < 1 || ncols < 1 || (n > 1 && !off)) return hipErrorInvalidValue;
+  const long gx = (ncols + 255) / 256, gy = (n + kEnergyRows - 1) / kEnergyRows;
+  if (gx > 0x7fffffffL || gy > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_energy_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, x,
+                     c64 ? 1 : 0, n, ncols, d, reinterpret_cast<const double2*>(off), v, f, num,
+                     den);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_finish(double* num, double* den, long ncols, double w, double* avg,
+                                hipStream_t s) {
+  if (ncols < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(energy_finish_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s,
+                     num, den, ncols, w, avg);
+  return hipGetLastError();
+}
+
 long tridiag_stream_rows(int G) { return (long)G * 64 * 16; }
 
 hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s) {

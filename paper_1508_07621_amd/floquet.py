@@ -203,6 +203,22 @@ class FloquetContext:
                                           int(snap_every)))
         return (out, snaps) if snaps is not None else out
 
+    def period_average(self, X0, f_grid) -> np.ndarray:
+        """(1/M) sum_k <x_k|H(t_k)|x_k> / <x_k|x_k> for each column of X0 (n x ncols),
+        x_k the column propagated over k steps, t_k = k h, f_grid[k] = f(t_k)."""
+        X0 = _device_tensor(X0, self.state_dtype, self.device)
+        if X0.dim() != 2 or X0.shape[0] != self.n:
+            raise ValueError("X0 must be n x ncols")
+        fg = np.ascontiguousarray(np.asarray(f_grid, dtype=np.float64).reshape(-1))
+        if fg.size != self.M:
+            raise ValueError("f_grid must hold M values")
+        out = np.empty(int(X0.shape[1]), dtype=np.float64)
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            check(lib().floquet_period_average(self._ctx, X0.data_ptr(), int(X0.shape[1]),
+                                               dptr(fg), dptr(out)))
+        return out
+
     def grad(self, U_bar) -> np.ndarray:
         """d loss / d f_nodes, shape (M, 2), for U_bar = dL/dRe U + i dL/dIm U."""
         torch = _torch()

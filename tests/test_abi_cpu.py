@@ -274,6 +274,7 @@ def test_null_context_calls_rejected():
     assert L.floquet_build_UT(None, FAKE, None) == _abi.FQ_ERR_ARG
     assert L.floquet_propagate(None, FAKE, 1, 0, 1, FAKE, None, 0) == _abi.FQ_ERR_ARG
     assert L.floquet_grad(None, FAKE, _abi.dptr(g)) == _abi.FQ_ERR_ARG
+    assert L.floquet_period_average(None, FAKE, 1, _abi.dptr(g), _abi.dptr(g)) == _abi.FQ_ERR_ARG
     assert L.fq_node_times(1.0, 0, _abi.dptr(g)) == _abi.FQ_ERR_ARG
     assert L.fq_bessel_weights(-1.0, 3, _abi.dptr(g)) == _abi.FQ_ERR_ARG
     with pytest.raises(_abi.FloquetError):

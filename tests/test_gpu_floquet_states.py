@@ -1,0 +1,132 @@
+"""The second propagation round on the GPU (period-averaged energies of given
+states, Sec. 3, Eq. (average) with A(t) = H(t)) against the FP64 oracle, and the
+Floquet-state post-processing built on it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from workloads import dimer_tridiag, drive_cos, gue, haar_unitary
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2.0 * math.pi
+
+
+@pytest.fixture(scope="module")
+def fl(require_gpu):
+    from paper_1508_07621_amd import floquet
+    floquet.node_times(1.0, 1)          # loads the library or raises
+    return floquet
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _grid(T, M, eps0, eps1):
+    return eps0 + eps1 * np.cos(np.arange(M) * T / M)
+
+
+def _floquet_states_oracle(H0, V, f, T, M, lo, hi, L, scheme="magnus4"):
+    U = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L, scheme=scheme)
+    _, phi = np.linalg.eig(U)
+    return phi / np.linalg.norm(phi, axis=0)
+
+
+@pytest.mark.parametrize("n,M,precision,scheme,tol", [
+    (64, 20, "fp64", "magnus4", 1e-10), (200, 8, "fp64", "magnus4", 1e-10),
+    (130, 6, "fp64", "magnus6", 1e-10), (200, 8, "bf16x3", "magnus4", 1e-6),
+    (130, 6, "fp32", "magnus6", 1e-6)])
+def test_dense_period_average_matches_oracle(fl, n, M, precision, scheme, tol):
+    _say("dense period average", n, M, precision, scheme)
+    rng = np.random.default_rng(60 + n)
+    H0, V = gue(n, rng), gue(n, rng)
+    T = TWO_PI
+    t = orc.node_times6(T, M) if scheme == "magnus6" else orc.node_times(T, M)
+    f = drive_cos(t, 0.2, 0.9, 1.0)
+    fg = _grid(T, M, 0.2, 0.9)
+    h = T / M
+    if scheme == "magnus6":
+        lo, hi = orc.exact_cover([orc.magnus6_heff(H0, V, f[k], h) for k in range(M)])
+    else:
+        a, b = orc.magnus4_weights(f, h)
+        lo, hi = orc.weyl_cover(H0, V, orc.commutator(H0, V), a, b)
+    L = orc.choose_L(orc.rescale(lo, hi, h)[2], 1e-12)
+    phi = _floquet_states_oracle(H0, V, f, T, M, lo, hi, L, scheme)
+    cols = phi[:, :: max(1, n // 24)]
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=L,
+                            precision=precision, scheme=scheme)
+    got = ctx.period_average(cols, fg)
+    ref = orc.period_average(H0, V, f, fg, T, M, cols, scheme=scheme, route="cheb", e_min=lo,
+                             e_max=hi, L=L)
+    err = np.abs(got - ref).max()
+    _say("max |avg - oracle|", err)
+    assert err < tol
+
+
+@pytest.mark.parametrize("nb,M,c64", [(150, 12, False), (150, 12, True)])
+def test_tridiag_period_average_matches_oracle(fl, nb, M, c64):
+    _say("tridiag period average", nb, M, c64)
+    d, e, v = dimer_tridiag(nb, 1.0, 0.05)
+    T = TWO_PI
+    f = drive_cos(orc.node_times(T, M), 0.5, 1.5, 1.0)
+    fg = _grid(T, M, 0.5, 1.5)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-12)
+    X0 = haar_unitary(nb + 1, np.random.default_rng(61))[:, :7]
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f, e_min=lo,
+                            e_max=hi, L=L, dtype="complex64" if c64 else "complex128")
+    got = ctx.period_average(X0, fg)
+    ref = orc.period_average_tridiag(d, e, v, f, fg, T, M, X0, route="cheb", e_min=lo, e_max=hi,
+                                     L=L)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("relative error", err)
+    assert err < (1e-6 if c64 else 1e-12)
+
+
+def test_tridiag_streamed_period_average_matches_oracle(fl):
+    """Columns longer than one workgroup holds (4500 rows): streamed passes."""
+    rng = np.random.default_rng(62)
+    n, M, T = 4500, 6, TWO_PI
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(n - 1) + 1j * rng.standard_normal(n - 1)
+    v = rng.standard_normal(n)
+    f = drive_cos(orc.node_times(T, M), 0.2, 0.9, 1.0)
+    fg = _grid(T, M, 0.2, 0.9)
+    a, b = orc.magnus4_weights(f, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-12)
+    _say("streamed period average", n, M, "L", L)
+    X0 = haar_unitary(n, rng)[:, :3]
+    ctx = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f, e_min=lo,
+                            e_max=hi, L=L)
+    got = ctx.period_average(X0, fg)
+    ref = orc.period_average_tridiag(d, e, v, f, fg, T, M, X0, route="cheb", e_min=lo, e_max=hi,
+                                     L=L)
+    err = np.abs(got - ref).max()
+    _say("max |avg - oracle|", err)
+    assert err < 1e-10
+
+
+def test_floquet_states_sorted_and_trace(fl):
+    """analysis.floquet_states on a full build: mean energies ascending, each
+    returned state an eigenvector of U_T with its quasienergy, and the sum of
+    all mean energies equal to the grid mean of Tr H(t_k)."""
+    from paper_1508_07621_amd.analysis import floquet_states
+    n, M, T = 96, 24, TWO_PI
+    rng = np.random.default_rng(63)
+    H0, V = gue(n, rng), gue(n, rng)
+    f = drive_cos(orc.node_times(T, M), 0.1, 1.0, 1.0)
+    fg = _grid(T, M, 0.1, 1.0)
+    ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f)
+    U = ctx.build_ut().cpu().numpy()
+    eps, phi, e_mean = floquet_states(ctx, U, fg)
+    assert np.all(np.diff(e_mean) >= 0)
+    lam = np.exp(-1j * eps * T)
+    assert np.abs(U @ phi - phi * lam[None, :]).max() < 1e-9
+    expect = np.trace(H0).real + np.mean(fg) * np.trace(V).real
+    _say("sum of mean energies", e_mean.sum(), "expected", expect)
+    assert abs(e_mean.sum() - expect) < 1e-8

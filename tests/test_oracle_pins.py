@@ -482,3 +482,80 @@ def test_magnus6_chebyshev_route_matches_exact_route():
     h = T / M
     evs = [np.linalg.eigvalsh(orc.magnus6_heff(H0, V, f[k], h)) for k in range(M)]
     assert min(e[0] for e in evs) == lo and max(e[-1] for e in evs) == hi
+
+
+# --- Period averages (second propagation round) ----------------------------------------------
+
+
+def test_period_average_of_stationary_states_is_their_energy():
+    """A constant drive: eigenvectors of H0 + f V only gain phases, so their
+    period-averaged energy is their eigenvalue."""
+    H0, V = _rm(8, 51)
+    T, M, fc = 2.0, 7, 0.4
+    lam, Q = np.linalg.eigh(H0 + fc * V)
+    f = np.full((M, 2), fc)
+    avg = orc.period_average(H0, V, f, np.full(M, fc), T, M, Q, route="exact")
+    assert np.abs(avg - lam).max() < 1e-12
+
+
+def test_period_average_commuting_cosine_drive():
+    """Diagonal H0, V and f = cos t over a full period: basis states keep their
+    populations and the grid mean of cos vanishes, so <H>_T = H0_jj."""
+    rng = np.random.default_rng(52)
+    n, T, M = 5, TWO_PI, 9
+    H0 = np.diag(rng.normal(size=n)).astype(np.complex128)
+    V = np.diag(rng.normal(size=n)).astype(np.complex128)
+    fg = np.cos(np.arange(M) * T / M)
+    avg = orc.period_average(H0, V, _nodes_cos(T, M), fg, T, M, np.eye(n), route="exact")
+    assert np.abs(avg - np.diag(H0).real).max() < 1e-12
+
+
+def test_period_average_trace_over_a_unitary_basis():
+    """For any orthonormal basis of states the averages sum to the grid mean of
+    Tr H(t_k) = Tr H0 + f(t_k) Tr V (the chain is unitary)."""
+    H0, V = _rm(9, 53)
+    T, M = TWO_PI, 12
+    fg = 0.3 + 0.8 * np.cos(np.arange(M) * T / M)
+    W = haar_unitary(9, np.random.default_rng(54))
+    avg = orc.period_average(H0, V, _nodes_cos(T, M, 0.3, 0.8), fg, T, M, W, route="exact")
+    expect = np.trace(H0).real + np.mean(fg) * np.trace(V).real
+    assert abs(avg.sum() - expect) < 1e-11
+
+
+def test_period_average_matches_the_time_integral_for_a_floquet_state():
+    """Floquet states from an independent integrator; their energy averaged over
+    the period by integrating d/dt E = <phi|H|phi> along the same ODE, against
+    the rectangle rule on a fine grid (spectral for a smooth periodic integrand)."""
+    H0, V, Ht = _gue_drive(4, 55)
+    T = TWO_PI
+    U = _brute_force(Ht, 4, T)
+    _, phi = np.linalg.eig(U)
+    phi = phi / np.linalg.norm(phi, axis=0)
+
+    def rhs(t, y):
+        x = y[:4] + 1j * y[4:8]
+        hx = Ht(t) @ x
+        dx = -1j * hx
+        return np.concatenate([dx.real, dx.imag, [np.real(np.vdot(x, hx))]])
+
+    ref = []
+    for j in range(4):
+        y0 = np.concatenate([phi[:, j].real, phi[:, j].imag, [0.0]])
+        sol = scipy.integrate.solve_ivp(rhs, (0.0, T), y0, method="DOP853", rtol=1e-12, atol=1e-12)
+        ref.append(sol.y[-1, -1] / T)
+    M = 400
+    fg = np.cos(np.arange(M) * T / M)
+    avg = orc.period_average(H0, V, _nodes_cos(T, M), fg, T, M, phi, route="exact")
+    assert np.abs(avg - np.array(ref)).max() < 1e-7
+
+
+def test_period_average_tridiag_matches_dense():
+    d, e, v = dimer_tridiag(11, 1.0, 0.3)
+    n, T, M = 12, TWO_PI, 10
+    f = _nodes_cos(T, M, 0.5, 1.5)
+    fg = 0.5 + 1.5 * np.cos(np.arange(M) * T / M)
+    X0 = haar_unitary(n, np.random.default_rng(56))[:, :3]
+    H0, V, _ = orc.tridiag_matrices(d, e, v)
+    a = orc.period_average_tridiag(d, e, v, f, fg, T, M, X0, route="exact")
+    b = orc.period_average(H0.toarray(), V.toarray(), f, fg, T, M, X0, route="exact")
+    assert np.abs(a - b).max() < 1e-12
