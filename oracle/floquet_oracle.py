@@ -60,7 +60,7 @@ __all__ = [
     "quasienergy_distance",
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
     "GL3_C", "node_times6", "magnus6_omega", "magnus6_heff", "exact_cover",
-    "period_average", "period_average_tridiag",
+    "period_average", "period_average_tridiag", "CF4_A1", "CF4_A2", "cf4_exponents",
 ]
 
 # ---------------------------------------------------------------------------
@@ -169,6 +169,33 @@ def exact_cover(Heffs) -> Tuple[float, float]:
         lo = min(lo, float(ev[0]))
         hi = max(hi, float(ev[-1]))
     return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# Commutator-free fourth-order scheme (the variant Sec. 2 and Sec. 8 name)
+# ---------------------------------------------------------------------------
+
+#: Weights of the two-exponential commutator-free scheme on the two
+#: Gauss-Legendre nodes: E = exp(-i h (A2 H1 + A1 H2)) exp(-i h (A1 H1 + A2 H2)).
+CF4_A1 = 0.25 + math.sqrt(3.0) / 6.0
+CF4_A2 = 0.25 - math.sqrt(3.0) / 6.0
+
+
+def cf4_exponents(H0, V, f_nodes):
+    """The step's two exponents as a list of Hermitian operators, each to be
+    exponentiated over half a step, in the order they act (earlier first):
+    exp(-i h (a H1 + b H2)) = exp(-i (h/2) 2 (a H1 + b H2)) with a + b = 1/2 and
+    H_j = H0 + f_j V at the step's two Gauss-Legendre nodes (f1 earlier).
+    BCH of the product reproduces the Magnus-4 exponent (h/2)(A1 + A2) +
+    (sqrt(3) h^2 / 12)[A2, A1] of A = -i H up to O(h^5)."""
+    f = np.asarray(f_nodes, dtype=np.float64).reshape(-1, 2)
+    ops = []
+    for f1, f2 in f:
+        H1 = H0 + f1 * V
+        H2 = H0 + f2 * V
+        ops.append(2.0 * (CF4_A1 * H1 + CF4_A2 * H2))   # acts first
+        ops.append(2.0 * (CF4_A2 * H1 + CF4_A1 * H2))
+    return ops
 
 
 # ---------------------------------------------------------------------------
@@ -342,7 +369,10 @@ def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: in
 
     scheme "magnus4": f_nodes has shape (M, 2), the drive at the two
     Gauss-Legendre nodes of each step (node_times); scheme "magnus6" (the
-    paper's Eq. (14)): shape (M, 3) at the three nodes of node_times6.
+    paper's Eq. (14)): shape (M, 3) at the three nodes of node_times6; scheme
+    "cf4": the commutator-free product of two half-step exponentials
+    (cf4_exponents) on the nodes of node_times, run as 2M steps of h/2 (the
+    Chebyshev route's R is that of h/2).
     route "exact" exponentiates each H_eff exactly; route "cheb" uses the
     Chebyshev recurrence with the interval [e_min, e_max] (default: the Weyl
     cover for magnus4, the exact cover for magnus6) and order L (default:
@@ -368,6 +398,16 @@ def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: in
 
         def Hk_of(k):
             return magnus4_heff(H0, V, K, a[k], b[k])
+    elif scheme == "cf4":
+        # 2M half-steps, each the exponential of one of cf4_exponents
+        ops = cf4_exponents(H0, V, f_nodes)
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = exact_cover(ops)
+        X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
+        kr = None if k_range is None else (2 * k_range[0], 2 * k_range[1])
+        U, info = _chain(ops.__getitem__, 2 * M, T, route, X0, e_min, e_max, L, tol, kr)
+        info.update(e_min=e_min, e_max=e_max)
+        return (U, info) if return_info else U
     else:
         raise ValueError(scheme)
     X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
@@ -379,12 +419,29 @@ def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: in
 def build_ut_tridiag(h0_diag, h0_off, v_diag, f_nodes, T: float, M: int, route: str = "cheb",
                      e_min: Optional[float] = None, e_max: Optional[float] = None,
                      L: Optional[int] = None, tol: float = 1e-12, X0: Optional[np.ndarray] = None,
-                     return_info: bool = False, k_range: Optional[Tuple[int, int]] = None):
+                     return_info: bool = False, k_range: Optional[Tuple[int, int]] = None,
+                     scheme: str = "magnus4"):
     """Same as build_ut for a Hermitian tridiagonal H0 and a diagonal V, with
-    sparse products (default interval: tridiag_cover)."""
+    sparse products (default interval: tridiag_cover); schemes "magnus4" and
+    "cf4"."""
     n = len(h0_diag)
     h = T / M
     H0, V, K = tridiag_matrices(h0_diag, h0_off, v_diag)
+    if scheme == "cf4":
+        ops = [op.tocsr() for op in cf4_exponents(H0, V, f_nodes)]
+        if route == "cheb" and (e_min is None or e_max is None):
+            # each half-step operator is H0 + a V with a = 2 (a1 f1 + a2 f2) or swapped
+            f = np.asarray(f_nodes, np.float64).reshape(-1, 2)
+            asub = np.stack([2 * (CF4_A1 * f[:, 0] + CF4_A2 * f[:, 1]),
+                             2 * (CF4_A2 * f[:, 0] + CF4_A1 * f[:, 1])], 1).ravel()
+            e_min, e_max = tridiag_cover(h0_diag, h0_off, v_diag, asub, np.zeros_like(asub))
+        X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
+        kr = None if k_range is None else (2 * k_range[0], 2 * k_range[1])
+        U, info = _chain(ops.__getitem__, 2 * M, T, route, X0, e_min, e_max, L, tol, kr)
+        info.update(e_min=e_min, e_max=e_max)
+        return (U, info) if return_info else U
+    if scheme != "magnus4":
+        raise ValueError(scheme)
     a, b = magnus4_weights(f_nodes, h)
     if route == "cheb" and (e_min is None or e_max is None):
         e_min, e_max = tridiag_cover(h0_diag, h0_off, v_diag, a, b)
@@ -399,16 +456,17 @@ def build_ut_tridiag(h0_diag, h0_off, v_diag, f_nodes, T: float, M: int, route: 
 # Second propagation round: period averages (Sec. 3, Eq. (average))
 # ---------------------------------------------------------------------------
 
-def _period_average(Hk_of, Hgrid_of, M, T, X0, route, e_min, e_max, L, tol):
+def _period_average(Hk_of, Hgrid_of, M, T, X0, route, e_min, e_max, L, tol, spp=1):
     """(1/M) sum_{k<M} <x_k|H(t_k)|x_k> / <x_k|x_k> per column, x_k the column
     after k steps: Eq. (average) with A(t) = H(t) by the rectangle rule on the
-    step grid t_k = k h."""
+    step grid t_k = k h. A step is spp exponentials of Hk_of (h / spp each)."""
     X = np.asarray(X0, np.complex128)
     acc = np.zeros(X.shape[1])
     for k in range(M):
         HX = Hgrid_of(k) @ X
         acc += np.real(np.sum(X.conj() * HX, axis=0)) / np.sum(np.abs(X) ** 2, axis=0)
-        X, _ = _chain(Hk_of, M, T, route, X, e_min, e_max, L, tol, (k, k + 1))
+        X, _ = _chain(Hk_of, spp * M, T, route, X, e_min, e_max, L, tol,
+                      (spp * k, spp * (k + 1)))
     return acc / M
 
 
@@ -420,12 +478,19 @@ def period_average(H0, V, f_nodes, f_grid, T: float, M: int, X0, scheme: str = "
     H0 = np.asarray(H0, np.complex128)
     V = np.asarray(V, np.complex128)
     h = T / M
+    spp = 1
     if scheme == "magnus6":
         f3 = np.asarray(f_nodes, np.float64).reshape(M, 3)
         Hs = [magnus6_heff(H0, V, f3[k], h) for k in range(M)]
         if route == "cheb" and (e_min is None or e_max is None):
             e_min, e_max = exact_cover(Hs)
         Hk_of = Hs.__getitem__
+    elif scheme == "cf4":
+        ops = cf4_exponents(H0, V, f_nodes)
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = exact_cover(ops)
+        Hk_of = ops.__getitem__
+        spp = 2
     else:
         K = commutator(H0, V)
         a, b = magnus4_weights(f_nodes, h)
@@ -435,7 +500,8 @@ def period_average(H0, V, f_nodes, f_grid, T: float, M: int, X0, scheme: str = "
         def Hk_of(k):
             return magnus4_heff(H0, V, K, a[k], b[k])
     fg = np.asarray(f_grid, np.float64)
-    return _period_average(Hk_of, lambda k: H0 + fg[k] * V, M, T, X0, route, e_min, e_max, L, tol)
+    return _period_average(Hk_of, lambda k: H0 + fg[k] * V, M, T, X0, route, e_min, e_max, L, tol,
+                           spp)
 
 
 def period_average_tridiag(h0_diag, h0_off, v_diag, f_nodes, f_grid, T: float, M: int, X0,

@@ -559,3 +559,55 @@ def test_period_average_tridiag_matches_dense():
     a = orc.period_average_tridiag(d, e, v, f, fg, T, M, X0, route="exact")
     b = orc.period_average(H0.toarray(), V.toarray(), f, fg, T, M, X0, route="exact")
     assert np.abs(a - b).max() < 1e-12
+
+
+# --- Commutator-free fourth-order scheme ------------------------------------------------------
+
+
+def test_cf4_fourth_order_and_factor_order():
+    """e(M) / e(2M) -> 16 against an independent integrator; applying the two
+    half-step exponentials in the other order flips the sign of the generated
+    commutator term and leaves order two (ratio 4)."""
+    H0, V, Ht = _gue_drive(6, 3)
+    T = TWO_PI
+    ref = _brute_force(Ht, 6, T)
+    errs, errs_sw = [], []
+    for M in (25, 50, 100):
+        f = _nodes_cos(T, M)
+        errs.append(orc.column_error(orc.build_ut(H0, V, f, T, M, route="exact", scheme="cf4"), ref))
+        U = np.eye(6, dtype=np.complex128)
+        h = T / M
+        ops = orc.cf4_exponents(H0, V, f)
+        for k in range(M):            # the two factors swapped
+            for op in (ops[2 * k + 1], ops[2 * k]):
+                U = orc.exact_step(op, h / 2, U)
+        errs_sw.append(orc.column_error(U, ref))
+    r = [errs[i] / errs[i + 1] for i in range(2)]
+    rs = [errs_sw[i] / errs_sw[i + 1] for i in range(2)]
+    assert all(14.0 < x < 18.0 for x in r), r
+    assert all(3.5 < x < 4.6 for x in rs), rs
+
+
+def test_cf4_commuting_operators_reduce_to_gauss_legendre():
+    """Commuting H0, V: the product is exp(-i h (H0 + V (f1 + f2) / 2)), the
+    two-node rule, exact for a cubic drive."""
+    rng = np.random.default_rng(57)
+    H0 = np.diag(rng.normal(size=4)).astype(np.complex128)
+    V = np.diag(rng.normal(size=4)).astype(np.complex128)
+    f = np.polynomial.Polynomial(rng.normal(size=4))
+    T, M = 1.3, 3
+    fn = f(orc.node_times(T, M))
+    U = orc.build_ut(H0, V, fn, T, M, route="exact", scheme="cf4")
+    F = f.integ()
+    expect = np.diag(np.exp(-1j * (np.diag(H0) * T + np.diag(V) * (F(T) - F(0.0)))))
+    assert np.abs(U - expect).max() < 1e-12
+
+
+def test_cf4_tridiag_matches_dense_and_chebyshev_matches_exact():
+    d, e, v = dimer_tridiag(11, 1.0, 0.3)
+    T, M = TWO_PI, 10
+    f = _nodes_cos(T, M, 0.5, 1.5)
+    H0, V, _ = orc.tridiag_matrices(d, e, v)
+    Ut = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", tol=1e-14, scheme="cf4")
+    Ud = orc.build_ut(H0.toarray(), V.toarray(), f, T, M, route="exact", scheme="cf4")
+    assert orc.column_error(Ut, Ud) < 1e-11
