@@ -100,10 +100,16 @@ typedef struct fq_system {
   const double* hmod_diag;
 } fq_system;
 
-/* Effective Hamiltonian of one step. FQ_MAGNUS4: two Gauss-Legendre nodes,
- * one commutator (fourth order). FQ_MAGNUS6: the paper's Eq. (14) from three
- * Gauss-Legendre nodes (sixth order); dense layout, no gradient tape. */
-typedef enum fq_scheme { FQ_MAGNUS4 = 0, FQ_MAGNUS6 = 1 } fq_scheme;
+/* Step operator. FQ_MAGNUS4: two Gauss-Legendre nodes, one commutator (fourth
+ * order). FQ_MAGNUS6: the paper's Eq. (14) from three Gauss-Legendre nodes
+ * (sixth order); dense layout, no gradient tape. FQ_CF4: commutator-free
+ * (the variant the paper names as an improvement, Sec. 2 and Sec. 8): two
+ * exponentials of linear combinations of H at the two Gauss-Legendre nodes,
+ *     E_k = exp(-i h (a2 H(f1) + a1 H(f2))) exp(-i h (a1 H(f1) + a2 H(f2))),
+ *     a1 = 1/4 + sqrt(3)/6, a2 = 1/4 - sqrt(3)/6 (fourth order),
+ * each run as one Chebyshev propagation over h/2 of H0 + a Hmod; no commutator
+ * is formed, so it serves both layouts and the gradient. */
+typedef enum fq_scheme { FQ_MAGNUS4 = 0, FQ_MAGNUS6 = 1, FQ_CF4 = 2 } fq_scheme;
 
 /* Storage of the state blocks that cross the boundary: U_T, X0, X_out, the
  * snapshots and U_bar. Operators stay complex128 / float64. */
@@ -118,11 +124,13 @@ typedef struct fq_params {
   double T;                  /* period > 0 */
   int32_t M;                 /* steps per period >= 1; h = T / M */
   int32_t L;                 /* Chebyshev order; 0 = smallest L with
-                                2 sum_{l>L} |J_l(R)| <= tol */
+                                2 sum_{l>L} |J_l(R)| <= tol (FQ_CF4: R of the
+                                half step, h dE / 2) */
   const double* f_nodes;     /* host, float64: f at the Gauss-Legendre nodes
                                 of each step in time order, 2*M values for
-                                FQ_MAGNUS4 (fq_node_times gives the times) or
-                                3*M for FQ_MAGNUS6 (fq_node_times_magnus6) */
+                                FQ_MAGNUS4 and FQ_CF4 (fq_node_times gives the
+                                times) or 3*M for FQ_MAGNUS6
+                                (fq_node_times_magnus6) */
   double e_min, e_max;       /* spectral interval containing the spectrum of
                                 every H_eff,k; both NaN = the library computes
                                 it (tridiagonal: exact per-step extremes by
@@ -133,7 +141,8 @@ typedef struct fq_params {
                                 lie in some step's spectral hull (tridiagonal:
                                 the exact extremes; dense: Ritz values of H_eff
                                 at the steps with the smallest and largest
-                                weight of Hmod). FQ_MAGNUS6 widens the dense
+                                weight of Hmod; FQ_CF4: of each half-step's
+                                operator). FQ_MAGNUS6 widens the dense
                                 cover by sum_j |w_j| times a bound on the norm
                                 of each nested commutator (||[A, B]|| <=
                                 2 ||A|| ||B||) */

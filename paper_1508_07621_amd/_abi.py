@@ -17,8 +17,8 @@ STATUS_NAMES = {0: "FQ_OK", 1: "FQ_ERR_ARG", 2: "FQ_ERR_NONFINITE", 3: "FQ_ERR_S
                 4: "FQ_ERR_HIP", 5: "FQ_ERR_UNSUPPORTED", 6: "FQ_ERR_STATE"}
 FQ_DENSE, FQ_TRIDIAG = 0, 1
 FQ_C128, FQ_C64 = 0, 1
-FQ_MAGNUS4, FQ_MAGNUS6 = 0, 1
-SCHEMES = {"magnus4": FQ_MAGNUS4, "magnus6": FQ_MAGNUS6}
+FQ_MAGNUS4, FQ_MAGNUS6, FQ_CF4 = 0, 1, 2
+SCHEMES = {"magnus4": FQ_MAGNUS4, "magnus6": FQ_MAGNUS6, "cf4": FQ_CF4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 #: kernel kinds timed in profile mode (fq_report.ms_kernel indices)
 K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 8

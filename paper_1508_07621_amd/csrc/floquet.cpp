@@ -61,6 +61,16 @@ bool is_finite(double x) { return std::isfinite(x); }
 
 int nodes_per_step(int scheme) { return scheme == FQ_MAGNUS6 ? 3 : 2; }
 
+// Exponentials per step: FQ_CF4 runs each step as two half-steps. Inside the
+// library M, h, the checkpoint spacing and every table count these substeps;
+// the entry points map step indices of the caller to them.
+int substeps_per_step(int scheme) { return scheme == FQ_CF4 ? 2 : 1; }
+
+// FQ_CF4: weights of f1, f2 in the Hmod coefficient of the first and the second
+// half-step, 2 (a1, a2) and 2 (a2, a1) with a1,2 = 1/4 +/- sqrt(3)/6.
+constexpr double kCf4P = 0.5 + 0.57735026918962576451;  // 1/2 + sqrt(3)/3
+constexpr double kCf4Q = 0.5 - 0.57735026918962576451;  // 1/2 - sqrt(3)/3
+
 // Number of nested commutators in the sixth-order effective Hamiltonian.
 constexpr int kComm6 = 9;
 
@@ -83,6 +93,9 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     return o;
   };
   const long n = sys->n;
+  // substeps and checkpoint spacing as the library runs them
+  const int spp = substeps_per_step(par->scheme);
+  const long Ms = (long)par->M * spp, cks = (long)par->checkpoint_every * spp;
   if (sys->layout == FQ_DENSE) {
     lay.np = pad_to(n, dense_tile(n));
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
@@ -104,12 +117,12 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     if (par->precision != FQ_FP64) lay.off_htx = take(pbytes);
     if (par->scheme == FQ_MAGNUS6) lay.off_comm6 = take(kComm6 * plane2);
     if (par->checkpoint_every > 0) {
-      lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
+      lay.n_tape = (Ms + cks - 1) / cks + 1;
       lay.off_tape = take(plane2 * (size_t)lay.n_tape);
-      lay.off_seg = take(3 * plane2 * (size_t)par->checkpoint_every);
+      lay.off_seg = take(3 * plane2 * (size_t)cks);
       lay.off_stack = take(4 * plane2);
       lay.off_lam = take(plane2);
-      lay.off_grad = take(2 * sizeof(double) * (size_t)par->M);
+      lay.off_grad = take(2 * sizeof(double) * (size_t)Ms);
     }
   } else {
     lay.np = pad_to(n, dense_tile(n));
@@ -120,22 +133,22 @@ Layout plan(const fq_system* sys, const fq_params* par) {
       lay.off_pb = take(plane2);
       lay.off_y = take(plane2);
     }
-    lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)par->M);
+    lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)Ms);
     if (n > fq::tridiag_resident_max_n()) {  // two 8-plane states of n16 x n, per-step rows
       const size_t n16 = (size_t)(n + 15) / 16 * 16;
       lay.off_stream = take(sizeof(double) * (2 * 8 * n16 * (size_t)n + 6 * n16));
     }
     if (par->checkpoint_every > 0) {  // X_{j ckpt} per column; per-column segment buffers
       const size_t vec = 2 * sizeof(double) * (size_t)n;
-      lay.n_tape = (par->M + par->checkpoint_every - 1) / par->checkpoint_every + 1;
+      lay.n_tape = (Ms + cks - 1) / cks + 1;
       lay.off_tape = take(vec * (size_t)n * (size_t)lay.n_tape);
-      lay.off_seg = take(vec * (size_t)n * 3 * (size_t)par->checkpoint_every);
-      lay.off_grad = take(2 * sizeof(double) * (size_t)par->M);
+      lay.off_seg = take(vec * (size_t)n * 3 * (size_t)cks);
+      lay.off_grad = take(2 * sizeof(double) * (size_t)Ms);
     }
   }
   lay.off_small = take(64 * sizeof(double));
   lay.off_vec = take(3 * sizeof(double) * (size_t)n);
-  lay.off_ab = take(2 * sizeof(double) * (size_t)par->M);
+  lay.off_ab = take(2 * sizeof(double) * (size_t)Ms);
   lay.off_coef = take(2 * sizeof(double) * (size_t)(kMaxOrder + 1));
   lay.total = cur;
   return lay;
@@ -157,8 +170,9 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (!is_finite(par->T) || par->T <= 0) return fail(FQ_ERR_ARG, "T must be finite and > 0");
   if (par->M < 1) return fail(FQ_ERR_ARG, "M must be >= 1");
   if (!par->f_nodes) return fail(FQ_ERR_ARG, "f_nodes is null");
-  if (par->scheme != FQ_MAGNUS4 && par->scheme != FQ_MAGNUS6)
-    return fail(FQ_ERR_ARG, "scheme must be FQ_MAGNUS4 or FQ_MAGNUS6");
+  if (par->scheme != FQ_MAGNUS4 && par->scheme != FQ_MAGNUS6 && par->scheme != FQ_CF4)
+    return fail(FQ_ERR_ARG, "scheme must be FQ_MAGNUS4, FQ_MAGNUS6 or FQ_CF4");
+  if (par->M > 0x3fffffff / substeps_per_step(par->scheme)) return fail(FQ_ERR_ARG, "M too large");
   for (int i = 0; i < nodes_per_step(par->scheme) * par->M; ++i)
     if (!is_finite(par->f_nodes[i])) return fail(FQ_ERR_NONFINITE, "f_nodes[%d] is not finite", i);
   if (par->L < 0 || par->L > kMaxOrder) return fail(FQ_ERR_ARG, "L out of range [0, %d]", kMaxOrder);
@@ -741,7 +755,7 @@ fq_status finish_reortho(fq_ctx* c, void* U_out) {
 
 void fill_report(fq_ctx* c) {
   c->last.L = c->L;
-  c->last.M = c->M;
+  c->last.M = c->M_user;
   c->last.R = c->R;
   c->last.dE = c->dE;
   c->last.beta = c->beta;
@@ -910,6 +924,25 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
   return FQ_OK;
 }
 
+// Chain rule from dL/da, dL/db per (sub)step (g, contractions with the
+// unscaled Hmod and K, hence the 1/dE) to the drive samples.
+void grad_to_nodes(const fq_ctx* c, const std::vector<double>& g, double* grad_f_nodes) {
+  if (c->scheme == FQ_CF4) {  // a of the half-steps: (P f1 + Q f2, Q f1 + P f2)
+    for (int k = 0; k < c->M_user; ++k) {
+      const double g1 = g[4 * k] / c->dE, g2 = g[4 * k + 2] / c->dE;
+      grad_f_nodes[2 * k] = kCf4P * g1 + kCf4Q * g2;
+      grad_f_nodes[2 * k + 1] = kCf4Q * g1 + kCf4P * g2;
+    }
+    return;
+  }
+  const double w = std::sqrt(3.0) * c->h / 12.0;  // b = sqrt(3) h (f1 - f2) / 12
+  for (int k = 0; k < c->M; ++k) {
+    const double ga = g[2 * k] / c->dE, gb = g[2 * k + 1] / c->dE;
+    grad_f_nodes[2 * k] = 0.5 * ga + w * gb;
+    grad_f_nodes[2 * k + 1] = 0.5 * ga - w * gb;
+  }
+}
+
 fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const int M = c->M, s = c->ckpt;
   const long plane = c->np * c->np;
@@ -943,12 +976,7 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   FQ_HIP(c, hipStreamSynchronize(c->stream));
-  const double w = std::sqrt(3.0) * c->h / 12.0;
-  for (int k = 0; k < M; ++k) {
-    const double ga = g[2 * k] / c->dE, gb = g[2 * k + 1] / c->dE;
-    grad_f_nodes[2 * k] = 0.5 * ga + w * gb;
-    grad_f_nodes[2 * k + 1] = 0.5 * ga - w * gb;
-  }
+  grad_to_nodes(c, g, grad_f_nodes);
   return FQ_OK;
 }
 
@@ -985,12 +1013,7 @@ fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   FQ_HIP(c, hipStreamSynchronize(c->stream));
-  const double w = std::sqrt(3.0) * c->h / 12.0;
-  for (int k = 0; k < M; ++k) {
-    const double ga = g[2 * k] / c->dE, gb = g[2 * k + 1] / c->dE;
-    grad_f_nodes[2 * k] = 0.5 * ga + w * gb;
-    grad_f_nodes[2 * k + 1] = 0.5 * ga - w * gb;
-  }
+  grad_to_nodes(c, g, grad_f_nodes);
   return FQ_OK;
 }
 
@@ -1074,16 +1097,19 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->layout = sys->layout;
   c->sys = *sys;
   c->T = par->T;
-  c->M = par->M;
-  c->h = par->T / par->M;
+  c->spp = substeps_per_step(par->scheme);
+  c->M_user = par->M;
+  c->M = par->M * c->spp;
+  c->h = par->T / c->M;
   c->tol = par->tol;
   c->precision = par->precision;
-  c->ckpt = par->checkpoint_every;
+  c->ckpt = par->checkpoint_every * c->spp;
   c->profile = par->profile != 0;
   c->reortho = par->reorthonormalize != 0;
   c->c64 = par->dtype == FQ_C64;
   c->scheme = par->scheme;
   c->f_nodes.assign(par->f_nodes, par->f_nodes + nodes_per_step(par->scheme) * par->M);
+  // per (sub)step: H_eff = H0 + a Hmod + b K
   c->a.resize(c->M);
   c->b.resize(c->M);
   if (c->scheme == FQ_MAGNUS6) {
@@ -1092,6 +1118,13 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
       const double* f = &c->f_nodes[3 * k];
       magnus6_weights(c->h, f[0], f[1], f[2], &c->a[k], &c->w6[(size_t)kComm6 * k]);
       c->b[k] = 1.0;  // the K slot holds the step's commutator sum
+    }
+  } else if (c->scheme == FQ_CF4) {
+    for (int k = 0; k < c->M_user; ++k) {
+      const double f1 = c->f_nodes[2 * k], f2 = c->f_nodes[2 * k + 1];
+      c->a[2 * k] = kCf4P * f1 + kCf4Q * f2;      // first half-step
+      c->a[2 * k + 1] = kCf4Q * f1 + kCf4P * f2;  // second half-step
+      c->b[2 * k] = c->b[2 * k + 1] = 0.0;
     }
   } else {
     for (int k = 0; k < c->M; ++k) {
@@ -1298,15 +1331,18 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
   if (!c || !X0 || !X_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
-  if (k0 < 0 || k1 < k0 || k1 > c->M) return fail(FQ_ERR_ARG, "need 0 <= k0 <= k1 <= M");
+  if (k0 < 0 || k1 < k0 || k1 > c->M_user) return fail(FQ_ERR_ARG, "need 0 <= k0 <= k1 <= M");
   if (snapshots && snap_every < 1) return fail(FQ_ERR_ARG, "snap_every must be >= 1 with snapshots");
   if (!snapshots && snap_every != 0) return fail(FQ_ERR_ARG, "snap_every without a snapshot buffer");
   struct SnapReset {
     fq_ctx* c;
     ~SnapReset() { c->snap = nullptr; }
   } snap_reset{c};
+  // the library's substeps (FQ_CF4: two per step)
+  k0 *= c->spp;
+  k1 *= c->spp;
   c->snap = snapshots;
-  c->snap_every = snap_every;
+  c->snap_every = snap_every * c->spp;
   c->snap_k0 = k0;
   c->snap_ncols = ncols;
   c->n_events = 0;
@@ -1344,11 +1380,12 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
   if (!c || !X0 || !f_grid || !avg_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
-  for (int k = 0; k < c->M; ++k)
+  for (int k = 0; k < c->M_user; ++k)
     if (!is_finite(f_grid[k])) return fail(FQ_ERR_NONFINITE, "f_grid[%d] is not finite", k);
   c->n_events = 0;
   c->snap = nullptr;
-  const double w = 1.0 / c->M;
+  const int spp = c->spp;
+  const double w = 1.0 / c->M_user;
   double* avg = c->d_vec;
   double* num = c->d_vec + c->n;
   double* den = c->d_vec + 2 * c->n;
@@ -1358,7 +1395,7 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
     const long mrows = pad_to(ncols, dense_tile(c->n));
     FQ_HIP(c, fq::launch_pack_planar_t(X0, c->n, ncols, ncols, c->xr, c->xi, c->np, mrows, c->c64,
                                        c->stream));
-    for (int k = 0; k < c->M; ++k) {
+    for (int k = 0; k < c->M_user; ++k) {
       // H(t_k) into the Ht planes (free between steps), H(t_k) x into the P planes
       fq::WeightedSum ws{};
       ws.re[0] = c->h0r; ws.im[0] = c->h0i; ws.w[0] = 1.0;
@@ -1370,18 +1407,18 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
                                         c->stream));
       FQ_HIP(c, fq::launch_energy_rows(c->xr, c->xi, c->par, c->pai, ncols, c->n, c->np, w, avg,
                                        c->stream));
-      FQ_TRY(dense_steps(c, k, k + 1, (int)mrows, false));
+      FQ_TRY(dense_steps(c, k * spp, (k + 1) * spp, (int)mrows, false));
     }
   } else {
     // the states in the user layout, propagated in place one step at a time
     void* x = c->xr;
     const size_t bytes = (size_t)c->n * (size_t)ncols * (c->c64 ? 8 : 16);
     FQ_HIP(c, hipMemcpyAsync(x, X0, bytes, hipMemcpyDeviceToDevice, c->stream));
-    for (int k = 0; k < c->M; ++k) {
+    for (int k = 0; k < c->M_user; ++k) {
       FQ_HIP(c, fq::launch_tridiag_energy(x, c->c64, c->n, ncols, c->sys.h0_diag, c->sys.h0_off,
                                           c->sys.hmod_diag, f_grid[k], num, den, c->stream));
       FQ_HIP(c, fq::launch_energy_finish(num, den, ncols, w, avg, c->stream));
-      FQ_TRY(tridiag_run(c, x, ncols, k, k + 1, x));
+      FQ_TRY(tridiag_run(c, x, ncols, k * spp, (k + 1) * spp, x));
     }
   }
   FQ_MARK(c, -1);

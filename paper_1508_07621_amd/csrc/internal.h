@@ -273,6 +273,9 @@ struct fq_ctx {
   // commutators B_j (device planes comm6, 2 planes each); a_k as above, b_k = 1
   // for the K slot, which then holds each step's sum over the B_j.
   int scheme = 0;
+  // FQ_CF4 runs every step as spp = 2 half-steps: M, h and ckpt above count
+  // those; M_user is the caller's step count (API indices are scaled by spp).
+  int spp = 1, M_user = 0;
   std::vector<double> w6;             // M x 9
   double* comm6 = nullptr;
   double e_min = 0, e_max = 0, beta = 0, dE = 0, R = 0;

@@ -26,13 +26,13 @@ def _torch():
 
 def node_times(T: float, M: int, scheme: str = "magnus4") -> np.ndarray:
     """Gauss-Legendre sampling times of the drive in time order: (M, 2) for
-    "magnus4", (M, 3) for "magnus6"."""
+    "magnus4" and "cf4", (M, 3) for "magnus6"."""
     if scheme == "magnus6":
         out = np.empty(3 * M, dtype=np.float64)
         check(lib().fq_node_times_magnus6(float(T), int(M), dptr(out)))
         return out.reshape(M, 3)
-    if scheme != "magnus4":
-        raise ValueError("scheme must be magnus4 or magnus6")
+    if scheme not in ("magnus4", "cf4"):
+        raise ValueError("scheme must be magnus4, magnus6 or cf4")
     out = np.empty(2 * M, dtype=np.float64)
     check(lib().fq_node_times(float(T), int(M), dptr(out)))
     return out.reshape(M, 2)
@@ -79,9 +79,9 @@ class FloquetContext:
 
     Dense operators: h0, hmod (n x n complex). Tridiagonal: h0_diag (n real),
     h0_off (n-1 complex, H0[i][i+1]), hmod_diag (n real).
-    f_nodes: drive samples at node_times(T, M, scheme): (M, 2) for "magnus4",
-    (M, 3) for "magnus6" (the paper's sixth-order scheme; dense operators, no
-    gradient).
+    f_nodes: drive samples at node_times(T, M, scheme): (M, 2) for "magnus4"
+    and "cf4" (commutator-free, two exponentials per step), (M, 3) for
+    "magnus6" (the paper's sixth-order scheme; dense operators, no gradient).
     precision: "fp64", "fp32" or "bf16x3" (arithmetic of the Chebyshev products).
     reorthonormalize: replace U_T by its polar factor after each build (FP64
     Newton-Schulz); the report keeps the unitarity before and after.
@@ -125,7 +125,7 @@ class FloquetContext:
         self.M = int(M)
         self.T = float(T)
         if scheme not in _abi.SCHEMES:
-            raise ValueError("scheme must be magnus4 or magnus6")
+            raise ValueError("scheme must be magnus4, magnus6 or cf4")
         self.scheme = scheme
         per_step = 3 if scheme == "magnus6" else 2
         self._f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))

@@ -192,7 +192,7 @@ def test_workspace_bytes_ok_and_grows_with_n():
     (lambda s, p: setattr(p, "profile", 2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "reorthonormalize", 2), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "dtype", 2), _abi.FQ_ERR_ARG),
-    (lambda s, p: setattr(p, "scheme", 2), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(p, "scheme", 3), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "scheme", -1), _abi.FQ_ERR_ARG),
 ])
 def test_invalid_arguments_rejected(mutate, status):
@@ -246,6 +246,16 @@ def test_magnus6_restrictions_and_workspace():
     st, _ = _ws(_dense(100), _params(M=4, f=f3, scheme=_abi.FQ_MAGNUS6))
     assert st == _abi.FQ_ERR_NONFINITE
     assert "f_nodes[11]" in _abi.lib().fq_last_error().decode()
+
+
+def test_cf4_runs_two_half_steps_per_step():
+    """The commutator-free scheme takes the 2*M two-node samples, works for both
+    layouts and the gradient, and sizes its step tables for 2*M half-steps."""
+    st, b4 = _ws(_tridiag(100), _params(M=4, checkpoint_every=2))
+    stc, bc = _ws(_tridiag(100), _params(M=4, checkpoint_every=2, scheme=_abi.FQ_CF4))
+    assert st == stc == _abi.FQ_OK and bc > b4
+    st, _ = _ws(_dense(100), _params(M=4, scheme=_abi.FQ_CF4, checkpoint_every=2))
+    assert st == _abi.FQ_OK
 
 
 def test_magnus6_node_times_match_the_oracle():
