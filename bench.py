@@ -69,6 +69,12 @@ def parse():
                     help="skip the FP64 reference build of a mixed-precision run")
     ap.add_argument("--no-eig", action="store_true", help="skip the host eigenphase comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scheme", choices=["magnus4", "magnus6", "cf4"], default=None,
+                    help="step operator (default: the workload's)")
+    ap.add_argument("--M", type=int, default=0, help="steps per period (default: the workload's)")
+    ap.add_argument("--time-error-ref", default="", metavar="SCHEME:M",
+                    help="also build an FP64 reference with this scheme and step count and report "
+                         "the time-discretisation error e_col of the timed result against it")
     ap.add_argument("--second-round", action="store_true",
                     help="after the timed builds, diagonalise U_T on the host and time the second "
                          "propagation round (period-averaged energies of all Floquet states)")
@@ -267,6 +273,24 @@ def dense_roofline(reports, n: int, precision: str, workload: str):
             "algorithmic_tflops": round(flops / (ms_launch * 1e-3) / 1e12, 3)}
 
 
+def time_error(U, wl, kw, spec: str):
+    """e_col of U against an FP64 build of the same problem with another scheme
+    and step count (a converged reference isolates the time discretisation)."""
+    import torch
+    from paper_1508_07621_amd import floquet as fl
+    from workloads import drive_cos
+    scheme, m = spec.split(":")
+    m = int(m)
+    eps0, eps1 = (0.5, 1.5) if wl.layout == "tridiag" else (0.0, 1.0)
+    f = drive_cos(fl.node_times(wl.T, m, scheme=scheme), eps0, eps1, 1.0)
+    _log(f"time-discretisation reference: {scheme}, M = {m}, FP64")
+    ref = fl.FloquetContext(T=wl.T, M=m, f_nodes=f, tol=1e-12, precision="fp64", scheme=scheme,
+                            device=U.device, **kw)
+    R = ref.build_ut()
+    return {"reference": f"FP64 {scheme} build with M = {m}",
+            "e_col": torch.linalg.vector_norm(U - R, dim=0).max().item()}
+
+
 def second_round(ctx, U, wl, kw):
     """The paper's post-processing of a build: host eigenvectors of U_T, then one
     more period of propagation of all N Floquet states on the device with their
@@ -345,7 +369,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}), flush=True)
         return
-    wl = workload(args.workload)
+    wl = workload(args.workload, M=args.M or None)
+    if args.scheme:
+        wl.scheme = args.scheme
     precision = args.precision if wl.layout == "dense" else "fp64"
     grad_mode = args.workload == "adjoint1024"
     if grad_mode:
@@ -353,7 +379,7 @@ def main():
         if args.precision == "bf16x3" and "--precision" not in sys.argv:
             precision = "fp32"  # the configuration's complex64 forward
     elif wl.layout == "tridiag":
-        f_nodes = drive_cos(fl.node_times(wl.T, wl.M), 0.5, 1.5, 1.0)
+        f_nodes = drive_cos(fl.node_times(wl.T, wl.M, scheme=wl.scheme), 0.5, 1.5, 1.0)
     else:
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M, scheme=wl.scheme), 0.0, 1.0, 1.0)
     if wl.layout == "dense":
@@ -439,6 +465,8 @@ def main():
 
     if args.second_round and not grad_mode:
         extra["second_round"] = second_round(ctx, U, wl, kw)
+    if args.time_error_ref and not grad_mode:
+        extra["time_discretisation"] = time_error(U, wl, kw, args.time_error_ref)
 
     out = {
         "metric": "s per U_T build + TFLOP/s (% MFMA/HBM peak), mixed vs FP64 at stated error",
