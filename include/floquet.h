@@ -73,7 +73,11 @@ typedef enum {
   FQ_ERR_STATE = 6         /* call out of order (e.g. floquet_grad without a tape) */
 } fq_status;
 
-typedef enum { FQ_DENSE = 0, FQ_TRIDIAG = 1 } fq_layout;
+/* FQ_DENSE_EIGEN: the dense model written in the eigenbasis of H0 (Sec. 3,
+ * Eq. (Ham2)): H0 = diag(E_i), given as h0_diag, and Hmod dense in that basis.
+ * Every commutator with H0 is then elementwise, [H0, X]_ij = (E_i - E_j) X_ij,
+ * and the extremes of H0 are exact; the Chebyshev products are the dense ones. */
+typedef enum { FQ_DENSE = 0, FQ_TRIDIAG = 1, FQ_DENSE_EIGEN = 2 } fq_layout;
 
 /* Arithmetic of the Chebyshev products. FQ_FP64: everything in float64.
  * FQ_FP32: products on FP32 matrix cores with FP32 accumulation; P_l stored
@@ -88,7 +92,9 @@ typedef struct fq_system {
   int64_t n;                 /* dimension N >= 1 */
   int32_t layout;            /* fq_layout */
   int32_t reserved0;         /* must be 0 */
-  /* FQ_DENSE: device, n*n complex128, row-major, Hermitian (not checked). */
+  /* FQ_DENSE: device, n*n complex128, row-major, Hermitian (not checked).
+   * FQ_DENSE_EIGEN: hmod as for FQ_DENSE (in H0's eigenbasis), h0 unused, and
+   * h0_diag (below) holds the n eigenvalues E_i of H0. */
   const void* h0;
   const void* hmod;
   /* FQ_TRIDIAG: H0 Hermitian tridiagonal, Hmod real diagonal (the dimer of

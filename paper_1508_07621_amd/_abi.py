@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfloquet.so")
 FQ_OK, FQ_ERR_ARG, FQ_ERR_NONFINITE, FQ_ERR_SPECTRUM, FQ_ERR_HIP, FQ_ERR_UNSUPPORTED, FQ_ERR_STATE = range(7)
 STATUS_NAMES = {0: "FQ_OK", 1: "FQ_ERR_ARG", 2: "FQ_ERR_NONFINITE", 3: "FQ_ERR_SPECTRUM",
                 4: "FQ_ERR_HIP", 5: "FQ_ERR_UNSUPPORTED", 6: "FQ_ERR_STATE"}
-FQ_DENSE, FQ_TRIDIAG = 0, 1
+FQ_DENSE, FQ_TRIDIAG, FQ_DENSE_EIGEN = 0, 1, 2
 FQ_C128, FQ_C64 = 0, 1
 FQ_MAGNUS4, FQ_MAGNUS6, FQ_CF4 = 0, 1, 2
 SCHEMES = {"magnus4": FQ_MAGNUS4, "magnus6": FQ_MAGNUS6, "cf4": FQ_CF4}

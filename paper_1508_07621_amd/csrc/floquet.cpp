@@ -61,6 +61,9 @@ bool is_finite(double x) { return std::isfinite(x); }
 
 int nodes_per_step(int scheme) { return scheme == FQ_MAGNUS6 ? 3 : 2; }
 
+// Layouts served by the dense path (H0 given densely or by its eigenvalues).
+bool dense_like(int layout) { return layout == FQ_DENSE || layout == FQ_DENSE_EIGEN; }
+
 // Exponentials per step: FQ_CF4 runs each step as two half-steps. Inside the
 // library M, h, the checkpoint spacing and every table count these substeps;
 // the entry points map step indices of the caller to them.
@@ -96,7 +99,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
   // substeps and checkpoint spacing as the library runs them
   const int spp = substeps_per_step(par->scheme);
   const long Ms = (long)par->M * spp, cks = (long)par->checkpoint_every * spp;
-  if (sys->layout == FQ_DENSE) {
+  if (dense_like(sys->layout)) {
     lay.np = pad_to(n, dense_tile(n));
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
     lay.off_h0 = take(plane2);
@@ -161,6 +164,10 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (sys->layout == FQ_DENSE) {
     if (!sys->h0 || !sys->hmod) return fail(FQ_ERR_ARG, "dense layout needs h0 and hmod");
     if (sys->n > 46336) return fail(FQ_ERR_ARG, "n too large for 32-bit tile indexing");
+  } else if (sys->layout == FQ_DENSE_EIGEN) {
+    if (!sys->h0_diag || !sys->hmod)
+      return fail(FQ_ERR_ARG, "eigenbasis layout needs h0_diag (eigenvalues of H0) and hmod");
+    if (sys->n > 46336) return fail(FQ_ERR_ARG, "n too large for 32-bit tile indexing");
   } else if (sys->layout == FQ_TRIDIAG) {
     if (!sys->h0_diag || !sys->hmod_diag || (sys->n > 1 && !sys->h0_off))
       return fail(FQ_ERR_ARG, "tridiagonal layout needs h0_diag, h0_off and hmod_diag");
@@ -194,8 +201,8 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (par->dtype != FQ_C128 && par->dtype != FQ_C64)
     return fail(FQ_ERR_ARG, "dtype must be FQ_C128 or FQ_C64");
   if (par->scheme == FQ_MAGNUS6) {
-    if (sys->layout != FQ_DENSE)
-      return fail(FQ_ERR_UNSUPPORTED, "FQ_MAGNUS6 needs the dense layout (its nested "
+    if (!dense_like(sys->layout))
+      return fail(FQ_ERR_UNSUPPORTED, "FQ_MAGNUS6 needs a dense layout (its nested "
                                       "commutators of a tridiagonal H0 are not tridiagonal)");
     if (par->checkpoint_every > 0)
       return fail(FQ_ERR_UNSUPPORTED, "the gradient tape is implemented for FQ_MAGNUS4 only");
@@ -253,6 +260,10 @@ void magnus6_weights(double h, double f1, double f2, double f3, double* wv, doub
 fq_status hermitian_commutator(fq_ctx* c, const double* pr, const double* pi, const double* qr,
                                const double* qi, double s, double* br, double* bi) {
   const int np = (int)c->np;
+  if (c->h0_eigen && pr == c->h0r) {  // [diag(E), Q] elementwise
+    FQ_HIP(c, fq::launch_diag_commutator(c->sys.h0_diag, c->n, np, qr, qi, s, br, bi, c->stream));
+    return FQ_OK;
+  }
   FQ_HIP(c, fq::launch_zgemm_nt_f64(pr, pi, false, qr, qi, true, br, bi, np, np, np, np, 0.0, s,
                                     0.0, 0.0, c->stream));
   FQ_HIP(c, fq::launch_zgemm_nt_f64(qr, qi, false, pr, pi, true, br, bi, np, np, np, np, 0.0, -s,
@@ -385,8 +396,16 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
   double l0, h0, lv, hv;
   Matvec mh0 = [&](const std::vector<cd>& x, std::vector<cd>& y) { return device_matvec(ctx, ctx->sys.h0, x, y); };
   Matvec mv = [&](const std::vector<cd>& x, std::vector<cd>& y) { return device_matvec(ctx, ctx->sys.hmod, x, y); };
-  fq_status st = lanczos_ritz(ctx, mh0, &l0, &h0);
-  if (st != FQ_OK) return st;
+  fq_status st = FQ_OK;
+  if (ctx->h0_eigen) {  // the extremes of diag(E) are exact
+    std::vector<double> e(ctx->n);
+    FQ_HIP(ctx, hipMemcpy(e.data(), ctx->sys.h0_diag, ctx->n * sizeof(double), hipMemcpyDeviceToHost));
+    l0 = *std::min_element(e.begin(), e.end());
+    h0 = *std::max_element(e.begin(), e.end());
+  } else {
+    st = lanczos_ritz(ctx, mh0, &l0, &h0);
+    if (st != FQ_OK) return st;
+  }
   st = lanczos_ritz(ctx, mv, &lv, &hv);
   if (st != FQ_OK) return st;
   const double w0 = h0 - l0, wv = hv - lv;
@@ -458,9 +477,12 @@ fq_status dense_inner_bounds(fq_ctx* ctx, double* lo_out, double* hi_out) {
     Matvec mv = [&](const std::vector<cd>& x, std::vector<cd>& y) {
       // H0 x + a Hmod x + b K x with K x = -i (H0 (Hmod x) - Hmod (H0 x))
       std::vector<cd> u1, u2, u3, u4;
-      fq_status st = device_matvec(ctx, ctx->sys.h0, x, u1);
+      fq_status st = ctx->h0_eigen ? device_matvec_planar(ctx, ctx->h0r, ctx->h0i, x, u1)
+                                   : device_matvec(ctx, ctx->sys.h0, x, u1);
       if (st == FQ_OK) st = device_matvec(ctx, ctx->sys.hmod, x, u2);
-      if (st == FQ_OK && b != 0.0) st = device_matvec(ctx, ctx->sys.h0, u2, u3);
+      if (st == FQ_OK && b != 0.0)
+        st = ctx->h0_eigen ? device_matvec_planar(ctx, ctx->h0r, ctx->h0i, u2, u3)
+                           : device_matvec(ctx, ctx->sys.h0, u2, u3);
       if (st == FQ_OK && b != 0.0) st = device_matvec(ctx, ctx->sys.hmod, u1, u4);
       if (st != FQ_OK) return st;
       y.resize(x.size());
@@ -1094,7 +1116,8 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   fq_ctx* c = new (std::nothrow) fq_ctx();
   if (!c) return fail(FQ_ERR_ARG, "out of host memory");
   c->n = sys->n;
-  c->layout = sys->layout;
+  c->layout = dense_like(sys->layout) ? FQ_DENSE : sys->layout;
+  c->h0_eigen = sys->layout == FQ_DENSE_EIGEN;
   c->sys = *sys;
   c->T = par->T;
   c->spp = substeps_per_step(par->scheme);
@@ -1160,7 +1183,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     }
   }
   c->xi = c->xr + plane;
-  if (sys->layout == FQ_DENSE) {
+  if (dense_like(sys->layout)) {
     c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;
     c->vr = P(lay.off_v);   c->kr = c->vr + plane;   // re(Hmod), re(K),
     c->vi = c->vr + 2 * plane; c->ki = c->vr + 3 * plane;  // im(Hmod), im(K)
@@ -1189,7 +1212,19 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     return bail(fail(FQ_ERR_HIP, "hipMemsetAsync of the workspace failed"));
 
   const long n = c->n;
-  if (sys->layout == FQ_DENSE) {
+  if (c->h0_eigen) {
+    // H0 = diag(E) and K = -i [H0, Hmod] elementwise, K_ij = -i (E_i - E_j) Hmod_ij
+    const int np = (int)c->np;
+    if (fq::launch_diag_planar(sys->h0_diag, n, np, c->h0r, c->stream) != hipSuccess ||
+        fq::launch_pack_planar(sys->hmod, n, n, n, c->vr, c->vi, np, c->stream) != hipSuccess ||
+        fq::launch_diag_commutator(sys->h0_diag, n, np, c->vr, c->vi, -1.0, c->kr, c->ki,
+                                   c->stream) != hipSuccess)
+      return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(hipGetLastError())));
+    if (c->scheme == FQ_MAGNUS6) {
+      st = magnus6_commutators(c);
+      if (st != FQ_OK) return bail(st);
+    }
+  } else if (sys->layout == FQ_DENSE) {
     // planar copies of H0 and Hmod, and K = -i (H0 Hmod - Hmod H0) on FP64 matrix cores:
     // (H0 Hmod)(i,j) = sum_k H0(i,k) conj(Hmod(j,k)) for Hermitian Hmod, and likewise.
     const int np = (int)c->np;
@@ -1209,7 +1244,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   // spectral interval
   double lo, hi;
   const bool given = !std::isnan(par->e_min);
-  if (sys->layout == FQ_DENSE) {
+  if (dense_like(sys->layout)) {
     st = given ? dense_inner_bounds(c, &lo, &hi) : dense_cover(c, &lo, &hi, kDenseMargin);
   } else {
     st = tridiag_cover(c, &lo, &hi);

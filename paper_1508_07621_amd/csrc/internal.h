@@ -168,6 +168,11 @@ hipError_t launch_energy_rows(const double* xr, const double* xi, const double* 
                               const double* yi, long rows, long n, long ld, double w, double* avg,
                               hipStream_t s);
 hipError_t launch_fill_zero(double* p, long count, hipStream_t s);
+// H0 in its eigenbasis: diag(e) into zeroed planes; B = sgn i [diag(e), Q] elementwise.
+hipError_t launch_diag_planar(const double* e, long n, long ld, double* re, hipStream_t s);
+hipError_t launch_diag_commutator(const double* e, long n, long ld, const double* qr,
+                                  const double* qi, double sgn, double* br, double* bi,
+                                  hipStream_t s);
 // Tridiagonal (user layout, complex128 or complex64 when c64), H = H0 + f Hmod:
 // num[c] += Re<x_c, H x_c>, den[c] += |x_c|^2; finish: avg[c] += w num / den, num = den = 0.
 hipError_t launch_tridiag_energy(const void* x, bool c64, long n, long ncols, const double* d,
@@ -276,6 +281,9 @@ struct fq_ctx {
   // FQ_CF4 runs every step as spp = 2 half-steps: M, h and ckpt above count
   // those; M_user is the caller's step count (API indices are scaled by spp).
   int spp = 1, M_user = 0;
+  // dense model given in H0's eigenbasis (sys.h0_diag = E_i): H0 planes hold
+  // diag(E), and commutators with H0 are taken elementwise
+  bool h0_eigen = false;
   std::vector<double> w6;             // M x 9
   double* comm6 = nullptr;
   double e_min = 0, e_max = 0, beta = 0, dE = 0, R = 0;

@@ -567,6 +567,29 @@ __global__ void zgemv_planar_kernel(const double* __restrict__ ar, const double*
   if (threadIdx.x == 0) y[i] = make_double2(sr[0], si[0]);
 }
 
+// H0 = diag(e) into zeroed planes of row stride ld.
+__global__ void diag_planar_kernel(const double* __restrict__ e, long n, long ld,
+                                   double* __restrict__ re) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) re[i * ld + i] = e[i];
+}
+
+// B = s i [diag(e), Q] elementwise: B_ij = s i (e_i - e_j) Q_ij for i, j < n.
+__global__ void diag_commutator_kernel(const double* __restrict__ e, long n, long ld,
+                                       const double* __restrict__ qr,
+                                       const double* __restrict__ qi, double s,
+                                       double* __restrict__ br, double* __restrict__ bi) {
+  const long total = n * n;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    const long i = t / n, j = t % n, idx = i * ld + j;
+    const double d = s * (e[i] - e[j]);
+    const double xr = qr[idx], xi = qi[idx];
+    br[idx] = -d * xi;
+    bi[idx] = d * xr;
+  }
+}
+
 // out = sum_j w_j M_j elementwise over planar matrices (the per-step part of
 // the sixth-order effective Hamiltonian).
 __global__ void weighted_sum_kernel(WeightedSum ws, long total, double* __restrict__ outr,
@@ -771,6 +794,22 @@ hipError_t launch_energy_rows(const double* xr, const double* xi, const double* 
   if (rows < 1 || n < 1 || ld < n || rows > 0x7fffffffL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(energy_rows_kernel, dim3((unsigned)rows), dim3(256), 0, s, xr, xi, yr, yi, n,
                      ld, w, avg);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_planar(const double* e, long n, long ld, double* re, hipStream_t s) {
+  if (n < 1 || ld < n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(diag_planar_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, e, n,
+                     ld, re);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_commutator(const double* e, long n, long ld, const double* qr,
+                                  const double* qi, double sgn, double* br, double* bi,
+                                  hipStream_t s) {
+  if (n < 1 || ld < n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(diag_commutator_kernel, dim3(grid_for(n * n, 256)), dim3(256), 0, s, e, n,
+                     ld, qr, qi, sgn, br, bi);
   return hipGetLastError();
 }
 

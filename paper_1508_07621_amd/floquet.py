@@ -77,8 +77,10 @@ def _device_tensor(x, dtype, device):
 class FloquetContext:
     """One problem H(t) = H0 + f(t) Hmod on one GPU, set up once, built many times.
 
-    Dense operators: h0, hmod (n x n complex). Tridiagonal: h0_diag (n real),
-    h0_off (n-1 complex, H0[i][i+1]), hmod_diag (n real).
+    Dense operators: h0, hmod (n x n complex). In the eigenbasis of H0 (the
+    paper's working basis): h0_eigenvalues (n real) and hmod (n x n complex in
+    that basis). Tridiagonal: h0_diag (n real), h0_off (n-1 complex,
+    H0[i][i+1]), hmod_diag (n real).
     f_nodes: drive samples at node_times(T, M, scheme): (M, 2) for "magnus4"
     and "cf4" (commutator-free, two exponentials per step), (M, 3) for
     "magnus6" (the paper's sixth-order scheme; dense operators, no gradient).
@@ -89,7 +91,8 @@ class FloquetContext:
     operators stay complex128 / float64).
     """
 
-    def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_diag=None,
+    def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenvalues=None,
+                 h0_diag=None,
                  h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
                  e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
                  precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
@@ -100,7 +103,16 @@ class FloquetContext:
         self.device = torch.device(device if device is not None else "cuda")
         self._keep = []
         sysd = FqSystem()
-        if h0 is not None:
+        if h0_eigenvalues is not None:
+            e = _device_tensor(h0_eigenvalues, torch.float64, self.device)
+            vt = _device_tensor(hmod, torch.complex128, self.device)
+            self.n = int(e.shape[0])
+            if vt.shape != (self.n, self.n):
+                raise ValueError("hmod must be n x n for n eigenvalues of H0")
+            sysd.n, sysd.layout = self.n, _abi.FQ_DENSE_EIGEN
+            sysd.h0_diag, sysd.hmod = e.data_ptr(), vt.data_ptr()
+            self._keep += [e, vt]
+        elif h0 is not None:
             h0t = _device_tensor(h0, torch.complex128, self.device)
             vt = _device_tensor(hmod, torch.complex128, self.device)
             self.n = int(h0t.shape[0])

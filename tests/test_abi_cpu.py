@@ -258,6 +258,23 @@ def test_cf4_runs_two_half_steps_per_step():
     assert st == _abi.FQ_OK
 
 
+def test_eigenbasis_layout_arguments():
+    """FQ_DENSE_EIGEN takes H0 by its eigenvalues (h0_diag) and a dense hmod,
+    and needs the dense workspace."""
+    d = _dense(100)
+    e = _dense(100)
+    e.layout, e.h0, e.h0_diag = _abi.FQ_DENSE_EIGEN, None, FAKE
+    st_d, b_d = _ws(d, _params())
+    st_e, b_e = _ws(e, _params())
+    assert st_d == st_e == _abi.FQ_OK and b_e == b_d
+    e.h0_diag = None
+    st, _ = _ws(e, _params())
+    assert st == _abi.FQ_ERR_ARG
+    e.h0_diag = FAKE
+    st, _ = _ws(e, _params(M=4, f=np.zeros(12), scheme=_abi.FQ_MAGNUS6))
+    assert st == _abi.FQ_OK
+
+
 def test_magnus6_node_times_match_the_oracle():
     import oracle as orc
     t = fl.node_times(2.5, 7, scheme="magnus6")
