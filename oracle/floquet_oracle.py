@@ -61,6 +61,7 @@ __all__ = [
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
     "GL3_C", "node_times6", "magnus6_omega", "magnus6_heff", "exact_cover",
     "period_average", "period_average_tridiag", "CF4_A1", "CF4_A2", "cf4_exponents",
+    "magnus4_heff_drives",
 ]
 
 # ---------------------------------------------------------------------------
@@ -110,6 +111,27 @@ def magnus4_weights(f_nodes: np.ndarray, h: float) -> Tuple[np.ndarray, np.ndarr
 def magnus4_heff(H0, V, K, a: float, b: float):
     """H_eff = H0 + a V + b K (dense or scipy.sparse operands)."""
     return H0 + a * V + b * K
+
+
+def _drive(H0, Vs, fs):
+    """H0 + sum_s f_s V_s (one or several drive terms)."""
+    H = H0
+    for f, V in zip(fs, Vs):
+        H = H + f * V
+    return H
+
+
+def magnus4_heff_drives(H0, Vs, f1s, f2s, h: float) -> np.ndarray:
+    """H_eff of one step for H(t) = H0 + sum_s f_s(t) V_s (the several-term form
+    Sec. 3 mentions), from the same truncation as magnus4_weights written out with
+    matrices: Omega = (h/2)(A_1 + A_2) + (sqrt(3) h^2 / 12)[A_2, A_1],
+    A_j = -i H(node j), H_eff = i Omega / h. f1s, f2s: the drive terms at the
+    earlier and the later node."""
+    A1 = -1j * _drive(H0, Vs, f1s)
+    A2 = -1j * _drive(H0, Vs, f2s)
+    om = 0.5 * h * (A1 + A2) + (math.sqrt(3.0) * h * h / 12.0) * (A2 @ A1 - A1 @ A2)
+    H = 1j * om / h
+    return 0.5 * (H + H.conj().T)
 
 
 # ---------------------------------------------------------------------------
@@ -182,6 +204,21 @@ CF4_A2 = 0.25 - math.sqrt(3.0) / 6.0
 
 
 def cf4_exponents(H0, V, f_nodes):
+    """See _cf4_exponents; V may be a list of drive matrices, with f_nodes of shape
+    (M, 2, S)."""
+    if isinstance(V, (list, tuple)):
+        f = np.asarray(f_nodes, dtype=np.float64).reshape(-1, 2, len(V))
+        ops = []
+        for k in range(f.shape[0]):
+            H1 = _drive(H0, V, f[k, 0])
+            H2 = _drive(H0, V, f[k, 1])
+            ops.append(2.0 * (CF4_A1 * H1 + CF4_A2 * H2))   # acts first
+            ops.append(2.0 * (CF4_A2 * H1 + CF4_A1 * H2))
+        return ops
+    return _cf4_exponents(H0, V, f_nodes)
+
+
+def _cf4_exponents(H0, V, f_nodes):
     """The step's two exponents as a list of Hermitian operators, each to be
     exponentiated over half a step, in the order they act (earlier first):
     exp(-i h (a H1 + b H2)) = exp(-i (h/2) 2 (a H1 + b H2)) with a + b = 1/2 and
@@ -381,9 +418,26 @@ def build_ut(H0: np.ndarray, V: np.ndarray, f_nodes: np.ndarray, T: float, M: in
     (Sec. 2).
     """
     H0 = np.asarray(H0, np.complex128)
-    V = np.asarray(V, np.complex128)
     n = H0.shape[0]
     h = T / M
+    if isinstance(V, (list, tuple)):  # several drive terms, f_nodes (M, 2, S)
+        Vs = [np.asarray(v, np.complex128) for v in V]
+        X0 = np.eye(n, dtype=np.complex128) if X0 is None else np.asarray(X0, np.complex128)
+        f = np.asarray(f_nodes, np.float64).reshape(M, 2, len(Vs))
+        if scheme == "cf4":
+            ops = cf4_exponents(H0, Vs, f)
+            Mc, kr = 2 * M, None if k_range is None else (2 * k_range[0], 2 * k_range[1])
+        elif scheme == "magnus4":
+            ops = [magnus4_heff_drives(H0, Vs, f[k, 0], f[k, 1], h) for k in range(M)]
+            Mc, kr = M, k_range
+        else:
+            raise ValueError(scheme)
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = exact_cover(ops)
+        U, info = _chain(ops.__getitem__, Mc, T, route, X0, e_min, e_max, L, tol, kr)
+        info.update(e_min=e_min, e_max=e_max)
+        return (U, info) if return_info else U
+    V = np.asarray(V, np.complex128)
     if scheme == "magnus6":
         f3 = np.asarray(f_nodes, np.float64).reshape(M, 3)
         Hs = [magnus6_heff(H0, V, f3[k], h) for k in range(M)]
@@ -476,8 +530,22 @@ def period_average(H0, V, f_nodes, f_grid, T: float, M: int, X0, scheme: str = "
     with A(t) = H0 + f(t) V); f_grid[k] = f(k h). The steps are those of build_ut
     with the same arguments (f_nodes at the scheme's nodes)."""
     H0 = np.asarray(H0, np.complex128)
-    V = np.asarray(V, np.complex128)
     h = T / M
+    if isinstance(V, (list, tuple)):  # several drive terms: f_nodes (M, 2, S), f_grid (M, S)
+        Vs = [np.asarray(v, np.complex128) for v in V]
+        f = np.asarray(f_nodes, np.float64).reshape(M, 2, len(Vs))
+        if scheme == "cf4":
+            ops, spp = cf4_exponents(H0, Vs, f), 2
+        elif scheme == "magnus4":
+            ops, spp = [magnus4_heff_drives(H0, Vs, f[k, 0], f[k, 1], h) for k in range(M)], 1
+        else:
+            raise ValueError(scheme)
+        if route == "cheb" and (e_min is None or e_max is None):
+            e_min, e_max = exact_cover(ops)
+        fg = np.asarray(f_grid, np.float64).reshape(M, len(Vs))
+        return _period_average(ops.__getitem__, lambda k: _drive(H0, Vs, fg[k]), M, T, X0, route,
+                               e_min, e_max, L, tol, spp)
+    V = np.asarray(V, np.complex128)
     spp = 1
     if scheme == "magnus6":
         f3 = np.asarray(f_nodes, np.float64).reshape(M, 3)

@@ -611,3 +611,45 @@ def test_cf4_tridiag_matches_dense_and_chebyshev_matches_exact():
     Ut = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", tol=1e-14, scheme="cf4")
     Ud = orc.build_ut(H0.toarray(), V.toarray(), f, T, M, route="exact", scheme="cf4")
     assert orc.column_error(Ut, Ud) < 1e-11
+
+
+# --- Several drive terms ----------------------------------------------------------------------
+
+
+def _two_drives(seed):
+    H0, V1 = _rm(6, seed)
+    V2 = _rm(6, seed + 1)[0]
+    return H0, V1, V2
+
+
+@pytest.mark.parametrize("scheme", ["magnus4", "cf4"])
+def test_two_drive_terms_fourth_order(scheme):
+    """H0 + cos t V1 + sin 2t V2: ratio 16 per halving of h against DOP853. A
+    wrong sign or weight of the [V1, V2] term leaves order two."""
+    H0, V1, V2 = _two_drives(70)
+    T = TWO_PI
+    ref = _brute_force(lambda t: H0 + math.cos(t) * V1 + math.sin(2 * t) * V2, 6, T)
+    errs = []
+    for M in (25, 50, 100):
+        t = orc.node_times(T, M)
+        f = np.stack([np.cos(t), np.sin(2 * t)], -1)
+        errs.append(orc.column_error(orc.build_ut(H0, [V1, V2], f, T, M, route="exact",
+                                                  scheme=scheme), ref))
+    r = [errs[i] / errs[i + 1] for i in range(2)]
+    assert all(14.0 < x < 18.0 for x in r), r
+
+
+@pytest.mark.parametrize("scheme", ["magnus4", "cf4"])
+def test_two_drive_terms_reduce_to_one(scheme):
+    """V2 = V1 with f1 + f2 = f is the one-term model with f; V2 = 0 ignores f2."""
+    H0, V1, _ = _two_drives(71)
+    T, M = TWO_PI, 9
+    t = orc.node_times(T, M)
+    fa, fb = np.cos(t), 0.3 * np.sin(t)
+    U1 = orc.build_ut(H0, V1, fa + fb, T, M, route="exact", scheme=scheme)
+    U2 = orc.build_ut(H0, [V1, V1], np.stack([fa, fb], -1), T, M, route="exact", scheme=scheme)
+    assert orc.column_error(U2, U1) < 1e-12
+    Ua = orc.build_ut(H0, V1, fa, T, M, route="exact", scheme=scheme)
+    U3 = orc.build_ut(H0, [V1, np.zeros_like(V1)], np.stack([fa, fb], -1), T, M, route="exact",
+                      scheme=scheme)
+    assert orc.column_error(U3, Ua) < 1e-12
