@@ -87,11 +87,18 @@ typedef enum { FQ_DENSE = 0, FQ_TRIDIAG = 1, FQ_DENSE_EIGEN = 2 } fq_layout;
  * Chebyshev sum float64. Setup, coefficients and checks are always float64. */
 typedef enum { FQ_FP64 = 0, FQ_FP32 = 1, FQ_BF16X3 = 2 } fq_precision;
 
-/* The time-independent operators of H(t) = H0 + f(t) Hmod (Sec. 3, Eq. (13)). */
+/* The time-independent operators of H(t) = H0 + f(t) Hmod (Sec. 3, Eq. (13)),
+ * or of H(t) = H0 + sum_s f_s(t) Hmod_s with several drive terms (Sec. 3 notes
+ * the generalisation): n_drive = S >= 2 drive matrices given by hmods. */
 typedef struct fq_system {
   int64_t n;                 /* dimension N >= 1 */
   int32_t layout;            /* fq_layout */
-  int32_t reserved0;         /* must be 0 */
+  int32_t n_drive;           /* 0 or 1: one drive term (hmod / hmod_diag);
+                                2..4: that many dense drive matrices in hmods
+                                (dense layouts; FQ_MAGNUS4 or FQ_CF4). With S
+                                terms every per-node array (f_nodes, the
+                                gradient, f_grid) holds S values per entry, term
+                                index fastest. */
   /* FQ_DENSE: device, n*n complex128, row-major, Hermitian (not checked).
    * FQ_DENSE_EIGEN: hmod as for FQ_DENSE (in H0's eigenbasis), h0 unused, and
    * h0_diag (below) holds the n eigenvalues E_i of H0. */
@@ -104,6 +111,10 @@ typedef struct fq_system {
   const double* h0_diag;
   const void* h0_off;
   const double* hmod_diag;
+  /* n_drive >= 2: host array of n_drive device pointers, each an n*n
+   * complex128 row-major Hermitian matrix (in H0's eigenbasis for
+   * FQ_DENSE_EIGEN); hmod is then unused. */
+  const void* const* hmods;
 } fq_system;
 
 /* Step operator. FQ_MAGNUS4: two Gauss-Legendre nodes, one commutator (fourth
@@ -272,8 +283,8 @@ fq_status floquet_propagate(fq_ctx* ctx, const void* X0, int64_t ncols, int32_t 
  * the rectangle rule on the step grid (for a Floquet state the integrand is
  * smooth and T-periodic, where it converges faster than any power of h).
  * X0: device, n*ncols complex (fq_params.dtype) row-major, 1 <= ncols <= n;
- * f_grid: host, M float64, the drive at t_k = k h (not at the quadrature
- * nodes); avg_out: host, ncols float64. Steps use the context's scheme and
+ * f_grid: host, M float64 (M x S with several drive terms), the drive at
+ * t_k = k h (not at the quadrature nodes); avg_out: host, ncols float64. Steps use the context's scheme and
  * precision; the expectations are FP64. */
 fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, const double* f_grid,
                                  double* avg_out);
@@ -283,7 +294,8 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * and L held fixed), recomputing each segment from the tape of the last
  * floquet_build_UT. U_bar: device, n*n complex (fq_params.dtype) row-major with
  * U_bar[i][j] = dLoss/dRe U[i][j] + i dLoss/dIm U[i][j]. grad_f_nodes: host,
- * 2*M float64, same order as f_nodes. Needs checkpoint_every > 0. */
+ * 2*M float64 (2*M*S with several drive terms), same order as f_nodes. Needs
+ * checkpoint_every > 0. */
 fq_status floquet_grad(fq_ctx* ctx, const void* U_bar, double* grad_f_nodes);
 
 /* Thread-local description of the last non-OK status ("" if none). */

@@ -33,9 +33,10 @@ EXPORTS = (
 
 
 class FqSystem(ctypes.Structure):
-    _fields_ = [("n", c_int64), ("layout", c_int32), ("reserved0", c_int32),
+    _fields_ = [("n", c_int64), ("layout", c_int32), ("n_drive", c_int32),
                 ("h0", c_void_p), ("hmod", c_void_p),
-                ("h0_diag", c_void_p), ("h0_off", c_void_p), ("hmod_diag", c_void_p)]
+                ("h0_diag", c_void_p), ("h0_off", c_void_p), ("hmod_diag", c_void_p),
+                ("hmods", POINTER(c_void_p))]
 
 
 class FqParams(ctypes.Structure):

@@ -64,6 +64,13 @@ int nodes_per_step(int scheme) { return scheme == FQ_MAGNUS6 ? 3 : 2; }
 // Layouts served by the dense path (H0 given densely or by its eigenvalues).
 bool dense_like(int layout) { return layout == FQ_DENSE || layout == FQ_DENSE_EIGEN; }
 
+// Drive terms S and the matrices J of the drive block (see fq_ctx).
+int drive_terms(const fq_system* sys) { return sys->n_drive >= 2 ? sys->n_drive : 1; }
+int drive_block(int S, int scheme) {
+  if (S == 1) return 2;
+  return scheme == FQ_CF4 ? S : 2 * S + S * (S - 1) / 2;
+}
+
 // Exponentials per step: FQ_CF4 runs each step as two half-steps. Inside the
 // library M, h, the checkpoint spacing and every table count these substeps;
 // the entry points map step indices of the caller to them.
@@ -99,13 +106,15 @@ Layout plan(const fq_system* sys, const fq_params* par) {
   // substeps and checkpoint spacing as the library runs them
   const int spp = substeps_per_step(par->scheme);
   const long Ms = (long)par->M * spp, cks = (long)par->checkpoint_every * spp;
+  const int J = drive_block(drive_terms(sys), par->scheme);
   if (dense_like(sys->layout)) {
     lay.np = pad_to(n, dense_tile(n));
     const size_t plane2 = 2 * sizeof(double) * (size_t)lay.np * (size_t)lay.np;
     lay.off_h0 = take(plane2);
-    // Hmod and K share one block laid out re(Hmod), re(K), im(Hmod), im(K), so
-    // that [Hmod; K] is one 2np-row operand for the gradient contraction.
-    lay.off_v = take(2 * plane2);
+    // The drive block (Hmod and K, or the drive matrices and their commutators)
+    // is laid out re(B_0), re(B_1), ..., im(B_0), im(B_1), ..., so that
+    // [B_0; B_1; ...] is one J np-row operand for the gradient contraction.
+    lay.off_v = take((size_t)J * plane2);
     lay.off_k = lay.off_v;
     lay.off_ht = take(plane2);
     lay.off_x = take(plane2);
@@ -125,7 +134,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
       lay.off_seg = take(3 * plane2 * (size_t)cks);
       lay.off_stack = take(4 * plane2);
       lay.off_lam = take(plane2);
-      lay.off_grad = take(2 * sizeof(double) * (size_t)Ms);
+      lay.off_grad = take((size_t)J * sizeof(double) * (size_t)Ms);
     }
   } else {
     lay.np = pad_to(n, dense_tile(n));
@@ -160,12 +169,21 @@ Layout plan(const fq_system* sys, const fq_params* par) {
 fq_status validate(const fq_system* sys, const fq_params* par) {
   if (!sys || !par) return fail(FQ_ERR_ARG, "null system or params");
   if (sys->n < 1) return fail(FQ_ERR_ARG, "n must be >= 1 (got %lld)", (long long)sys->n);
-  if (sys->reserved0 != 0) return fail(FQ_ERR_ARG, "reserved0 must be 0");
+  if (sys->n_drive < 0 || sys->n_drive > 4)
+    return fail(FQ_ERR_ARG, "n_drive must be in [0, 4] (got %d)", sys->n_drive);
+  if (sys->n_drive >= 2) {
+    if (!dense_like(sys->layout))
+      return fail(FQ_ERR_UNSUPPORTED, "several drive terms need a dense layout");
+    if (!sys->hmods) return fail(FQ_ERR_ARG, "n_drive >= 2 needs hmods");
+    for (int d = 0; d < sys->n_drive; ++d)
+      if (!sys->hmods[d]) return fail(FQ_ERR_ARG, "hmods[%d] is null", d);
+  }
   if (sys->layout == FQ_DENSE) {
-    if (!sys->h0 || !sys->hmod) return fail(FQ_ERR_ARG, "dense layout needs h0 and hmod");
+    if (!sys->h0 || (!sys->hmod && sys->n_drive < 2))
+      return fail(FQ_ERR_ARG, "dense layout needs h0 and hmod");
     if (sys->n > 46336) return fail(FQ_ERR_ARG, "n too large for 32-bit tile indexing");
   } else if (sys->layout == FQ_DENSE_EIGEN) {
-    if (!sys->h0_diag || !sys->hmod)
+    if (!sys->h0_diag || (!sys->hmod && sys->n_drive < 2))
       return fail(FQ_ERR_ARG, "eigenbasis layout needs h0_diag (eigenvalues of H0) and hmod");
     if (sys->n > 46336) return fail(FQ_ERR_ARG, "n too large for 32-bit tile indexing");
   } else if (sys->layout == FQ_TRIDIAG) {
@@ -180,7 +198,9 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   if (par->scheme != FQ_MAGNUS4 && par->scheme != FQ_MAGNUS6 && par->scheme != FQ_CF4)
     return fail(FQ_ERR_ARG, "scheme must be FQ_MAGNUS4, FQ_MAGNUS6 or FQ_CF4");
   if (par->M > 0x3fffffff / substeps_per_step(par->scheme)) return fail(FQ_ERR_ARG, "M too large");
-  for (int i = 0; i < nodes_per_step(par->scheme) * par->M; ++i)
+  if (drive_terms(sys) > 1 && par->scheme == FQ_MAGNUS6)
+    return fail(FQ_ERR_UNSUPPORTED, "FQ_MAGNUS6 takes one drive term");
+  for (int i = 0; i < nodes_per_step(par->scheme) * par->M * drive_terms(sys); ++i)
     if (!is_finite(par->f_nodes[i])) return fail(FQ_ERR_NONFINITE, "f_nodes[%d] is not finite", i);
   if (par->L < 0 || par->L > kMaxOrder) return fail(FQ_ERR_ARG, "L out of range [0, %d]", kMaxOrder);
   if (par->L == 0 && (!is_finite(par->tol) || par->tol <= 0))
@@ -308,6 +328,25 @@ fq_status magnus6_sum(fq_ctx* c, int k, bool with_base, double* outr, double* ou
   return FQ_OK;
 }
 
+// Several drive terms: into (outr, outi) sum_j wS[k][j] B_j over the drive
+// block, plus H0 when with_base (the (sub)step's H_eff).
+fq_status drive_sum(fq_ctx* c, int k, bool with_base, double* outr, double* outi) {
+  const size_t plane = (size_t)c->np * (size_t)c->np;
+  fq::WeightedSum ws{};
+  int t = 0;
+  if (with_base) {
+    ws.re[t] = c->h0r; ws.im[t] = c->h0i; ws.w[t++] = 1.0;
+  }
+  for (int j = 0; j < c->J; ++j) {
+    ws.re[t] = c->vr + (size_t)j * plane;
+    ws.im[t] = c->vi + (size_t)j * plane;
+    ws.w[t++] = c->wS[(size_t)c->J * k + j];
+  }
+  ws.count = t;
+  FQ_HIP(c, fq::launch_weighted_sum(ws, (long)plane, outr, outi, c->stream));
+  return FQ_OK;
+}
+
 // ---- spectral interval ------------------------------------------------------------------------
 
 using cd = std::complex<double>;
@@ -406,6 +445,51 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
     st = lanczos_ritz(ctx, mh0, &l0, &h0);
     if (st != FQ_OK) return st;
   }
+  if (ctx->S > 1) {
+    // Weyl over the drive terms with their Lanczos extremes; ||K_s|| <= 2 ||H0|| ||Hmod_s||,
+    // ||K_st|| <= 2 ||Hmod_s|| ||Hmod_t||
+    const int S = ctx->S, J = ctx->J;
+    const double w0 = h0 - l0;
+    l0 -= margin * w0;
+    h0 += margin * w0;
+    const double n0 = std::max(std::fabs(l0), std::fabs(h0));
+    std::vector<double> ls(S), hs(S), nb(J, 0.0);
+    for (int d = 0; d < S; ++d) {
+      Matvec md = [&](const std::vector<cd>& x, std::vector<cd>& y) {
+        return device_matvec(ctx, ctx->sys.hmods[d], x, y);
+      };
+      FQ_TRY(lanczos_ritz(ctx, md, &ls[d], &hs[d]));
+      const double wd = hs[d] - ls[d];
+      ls[d] -= margin * wd;
+      hs[d] += margin * wd;
+      nb[d] = std::max(std::fabs(ls[d]), std::fabs(hs[d]));
+    }
+    if (ctx->scheme == FQ_MAGNUS4) {
+      int q = 2 * S;
+      for (int d = 0; d < S; ++d) {
+        nb[S + d] = 2.0 * n0 * nb[d];
+        for (int e = d + 1; e < S; ++e, ++q) nb[q] = 2.0 * nb[d] * nb[e];
+      }
+    }
+    double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+    for (int k = 0; k < ctx->M; ++k) {
+      const double* w = &ctx->wS[(size_t)J * k];
+      double l = l0, u = h0;
+      for (int d = 0; d < S; ++d) {
+        l += std::min(w[d] * ls[d], w[d] * hs[d]);
+        u += std::max(w[d] * ls[d], w[d] * hs[d]);
+      }
+      for (int j = S; j < J; ++j) {
+        l -= std::fabs(w[j]) * nb[j];
+        u += std::fabs(w[j]) * nb[j];
+      }
+      lo = std::min(lo, l);
+      hi = std::max(hi, u);
+    }
+    *lo_out = lo;
+    *hi_out = hi;
+    return FQ_OK;
+  }
   st = lanczos_ritz(ctx, mv, &lv, &hv);
   if (st != FQ_OK) return st;
   const double w0 = h0 - l0, wv = hv - lv;
@@ -456,14 +540,21 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
 fq_status dense_inner_bounds(fq_ctx* ctx, double* lo_out, double* hi_out) {
   int kmin = 0, kmax = 0;
   for (int k = 1; k < ctx->M; ++k) {
-    if (ctx->a[k] < ctx->a[kmin]) kmin = k;
-    if (ctx->a[k] > ctx->a[kmax]) kmax = k;
+    // one drive term: a_k; several: the weight of the first drive matrix
+    const double ak = ctx->S > 1 ? ctx->wS[(size_t)ctx->J * k] : ctx->a[k];
+    const double amin = ctx->S > 1 ? ctx->wS[(size_t)ctx->J * kmin] : ctx->a[kmin];
+    const double amax = ctx->S > 1 ? ctx->wS[(size_t)ctx->J * kmax] : ctx->a[kmax];
+    if (ak < amin) kmin = k;
+    if (ak > amax) kmax = k;
   }
   double lo = std::numeric_limits<double>::infinity(), hi = -lo;
   for (int k : {kmin, kmax}) {
     const double a = ctx->a[k], b = ctx->b[k];
-    if (ctx->scheme == FQ_MAGNUS6) {  // H_eff,k formed on the device (Ht planes are free)
-      FQ_TRY(magnus6_sum(ctx, k, true, ctx->htr, ctx->hti));
+    if (ctx->scheme == FQ_MAGNUS6 || ctx->S > 1) {  // H_eff,k formed on the device
+      if (ctx->S > 1)
+        FQ_TRY(drive_sum(ctx, k, true, ctx->htr, ctx->hti));  // (Ht planes are free)
+      else
+        FQ_TRY(magnus6_sum(ctx, k, true, ctx->htr, ctx->hti));
       Matvec mz = [&](const std::vector<cd>& x, std::vector<cd>& y) {
         return device_matvec_planar(ctx, ctx->htr, ctx->hti, x, y);
       };
@@ -585,11 +676,19 @@ fq_status collect_profile(fq_ctx* c) {
 fq_status dense_heff(fq_ctx* c, int k) {
   FQ_MARK(c, FQ_K_HEFF);
   if (c->scheme == FQ_MAGNUS6) FQ_TRY(magnus6_sum(c, k, false, c->kr, c->ki));  // K slot
+  // H0 + a V + b K, or with several drive terms the whole sum, formed first in
+  // the P planes (free at a step start) and passed as H0 with a = b = 0
+  const double *h0r = c->h0r, *h0i = c->h0i;
+  if (c->S > 1) {
+    FQ_TRY(drive_sum(c, k, true, c->par, c->pai));
+    h0r = c->par;
+    h0i = c->pai;
+  }
   if (c->precision == FQ_FP64) {
-    FQ_HIP(c, fq::launch_heff_f64(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
+    FQ_HIP(c, fq::launch_heff_f64(h0r, h0i, c->vr, c->vi, c->kr, c->ki, c->a[k], c->b[k],
                                   c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->stream));
   } else {
-    FQ_HIP(c, fq::launch_heff_mixed(c->h0r, c->h0i, c->vr, c->vi, c->kr, c->ki, c->a[k],
+    FQ_HIP(c, fq::launch_heff_mixed(h0r, h0i, c->vr, c->vi, c->kr, c->ki, c->a[k],
                                     c->b[k], c->beta, c->dE, c->n, c->np, c->htr, c->hti, c->htx,
                                     c->precision, c->stream));
   }
@@ -897,8 +996,10 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
   auto bot_im = [&](int i) { return c->stack[i] + 3 * plane; };
   double* lr = c->lam;
   double* li = c->lam + plane;
-  double* gk = c->d_grad + 2 * (size_t)k;
-  const int dot_cols = any_b ? 2 * np : np;
+  double* gk = c->d_grad + (size_t)c->J * k;
+  // contractions with the drive block: [Hmod; K] (K only when some b_k != 0),
+  // or all J matrices for several drive terms
+  const int dot_cols = c->S > 1 ? c->J * np : (any_b ? 2 * np : np);
   auto copy2 = [&](double* dre, double* dim, const double* src) -> fq_status {
     FQ_HIP(c, hipMemcpyAsync(dre, src, pbytes, hipMemcpyDeviceToDevice, s));
     FQ_HIP(c, hipMemcpyAsync(dim, src + plane, pbytes, hipMemcpyDeviceToDevice, s));
@@ -949,6 +1050,40 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
 // Chain rule from dL/da, dL/db per (sub)step (g, contractions with the
 // unscaled Hmod and K, hence the 1/dE) to the drive samples.
 void grad_to_nodes(const fq_ctx* c, const std::vector<double>& g, double* grad_f_nodes) {
+  if (c->S > 1) {  // g holds J values per (sub)step; output [step][node][term]
+    const int S = c->S, J = c->J;
+    const double w = std::sqrt(3.0) * c->h / 12.0;
+    for (int k = 0; k < c->M_user; ++k) {
+      double* o1 = grad_f_nodes + (size_t)(2 * k) * S;
+      double* o2 = grad_f_nodes + (size_t)(2 * k + 1) * S;
+      if (c->scheme == FQ_CF4) {
+        const double* g1 = &g[(size_t)J * (2 * k)];
+        const double* g2 = &g[(size_t)J * (2 * k + 1)];
+        for (int d = 0; d < S; ++d) {
+          o1[d] = (kCf4P * g1[d] + kCf4Q * g2[d]) / c->dE;
+          o2[d] = (kCf4Q * g1[d] + kCf4P * g2[d]) / c->dE;
+        }
+        continue;
+      }
+      const double* gk = &g[(size_t)J * k];
+      const double* f1 = &c->f_nodes[(size_t)(2 * k) * S];
+      const double* f2 = &c->f_nodes[(size_t)(2 * k + 1) * S];
+      for (int d = 0; d < S; ++d) {
+        o1[d] = (0.5 * gk[d] + w * gk[S + d]) / c->dE;
+        o2[d] = (0.5 * gk[d] - w * gk[S + d]) / c->dE;
+      }
+      int q = 2 * S;  // weight w (f_d2 f_e1 - f_e2 f_d1) of K_de
+      for (int d = 0; d < S; ++d)
+        for (int e = d + 1; e < S; ++e, ++q) {
+          const double gq = w * gk[q] / c->dE;
+          o1[d] -= gq * f2[e];
+          o2[d] += gq * f1[e];
+          o1[e] += gq * f2[d];
+          o2[e] -= gq * f1[d];
+        }
+    }
+    return;
+  }
   if (c->scheme == FQ_CF4) {  // a of the half-steps: (P f1 + Q f2, Q f1 + P f2)
     for (int k = 0; k < c->M_user; ++k) {
       const double g1 = g[4 * k] / c->dE, g2 = g[4 * k + 2] / c->dE;
@@ -971,7 +1106,7 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const size_t p2bytes = 2 * sizeof(double) * (size_t)plane;
   FQ_HIP(c, fq::launch_pack_planar_t(U_bar, c->n, c->n, c->n, c->lam, c->lam + plane, c->np,
                                      c->np, c->c64, c->stream));
-  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
+  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, (size_t)c->J * sizeof(double) * (size_t)M, c->stream));
   bool any_b = false;
   for (int k = 0; k < M; ++k) any_b = any_b || (c->b[k] != 0.0);
   const int nseg = (M + s - 1) / s;
@@ -994,7 +1129,7 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
       FQ_TRY(adjoint_step(c, k, k - k0, any_b));
     }
   }
-  std::vector<double> g(2 * (size_t)M);
+  std::vector<double> g((size_t)c->J * M);
   FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   FQ_HIP(c, hipStreamSynchronize(c->stream));
@@ -1131,11 +1266,40 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->reortho = par->reorthonormalize != 0;
   c->c64 = par->dtype == FQ_C64;
   c->scheme = par->scheme;
-  c->f_nodes.assign(par->f_nodes, par->f_nodes + nodes_per_step(par->scheme) * par->M);
+  c->S = drive_terms(sys);
+  c->J = drive_block(c->S, par->scheme);
+  c->f_nodes.assign(par->f_nodes, par->f_nodes + nodes_per_step(par->scheme) * par->M * c->S);
   // per (sub)step: H_eff = H0 + a Hmod + b K
   c->a.resize(c->M);
   c->b.resize(c->M);
-  if (c->scheme == FQ_MAGNUS6) {
+  if (c->S > 1) {  // weights of the drive block per (sub)step; a, b unused
+    const int S = c->S, J = c->J;
+    c->wS.assign((size_t)J * c->M, 0.0);
+    const double w = std::sqrt(3.0) * c->h / 12.0;
+    for (int k = 0; k < c->M_user; ++k) {
+      const double* f1 = &c->f_nodes[(size_t)(2 * k) * S];
+      const double* f2 = &c->f_nodes[(size_t)(2 * k + 1) * S];
+      if (c->scheme == FQ_CF4) {
+        double* w1 = &c->wS[(size_t)J * (2 * k)];
+        double* w2 = &c->wS[(size_t)J * (2 * k + 1)];
+        for (int d = 0; d < S; ++d) {
+          w1[d] = kCf4P * f1[d] + kCf4Q * f2[d];
+          w2[d] = kCf4Q * f1[d] + kCf4P * f2[d];
+        }
+      } else {
+        // Magnus-4: a_s, b_s = sqrt(3) h (f_s1 - f_s2) / 12 for K_s, and from
+        // [A2, A1] the weight of K_st: sqrt(3) h (f_s2 f_t1 - f_t2 f_s1) / 12
+        double* wk = &c->wS[(size_t)J * k];
+        int q = 2 * S;
+        for (int d = 0; d < S; ++d) {
+          wk[d] = 0.5 * (f1[d] + f2[d]);
+          wk[S + d] = w * (f1[d] - f2[d]);
+          for (int e = d + 1; e < S; ++e, ++q) wk[q] = w * (f2[d] * f1[e] - f2[e] * f1[d]);
+        }
+      }
+    }
+    for (int k = 0; k < c->M; ++k) c->a[k] = c->b[k] = 0.0;
+  } else if (c->scheme == FQ_MAGNUS6) {
     c->w6.resize((size_t)kComm6 * c->M);
     for (int k = 0; k < c->M; ++k) {
       const double* f = &c->f_nodes[3 * k];
@@ -1185,8 +1349,9 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->xi = c->xr + plane;
   if (dense_like(sys->layout)) {
     c->h0r = P(lay.off_h0); c->h0i = c->h0r + plane;
-    c->vr = P(lay.off_v);   c->kr = c->vr + plane;   // re(Hmod), re(K),
-    c->vi = c->vr + 2 * plane; c->ki = c->vr + 3 * plane;  // im(Hmod), im(K)
+    // drive block: re(B_0..B_{J-1}), then im; one term: B_0 = Hmod, B_1 = K
+    c->vr = P(lay.off_v);   c->kr = c->vr + plane;
+    c->vi = c->vr + (size_t)c->J * plane; c->ki = c->vi + plane;
     c->htr = P(lay.off_ht); c->hti = c->htr + plane;
     c->yr = P(lay.off_y);   c->yi = c->yr + plane;
     c->par = P(lay.off_pa); c->pai = c->par + plane;
@@ -1212,33 +1377,37 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     return bail(fail(FQ_ERR_HIP, "hipMemsetAsync of the workspace failed"));
 
   const long n = c->n;
-  if (c->h0_eigen) {
-    // H0 = diag(E) and K = -i [H0, Hmod] elementwise, K_ij = -i (E_i - E_j) Hmod_ij
+  if (c->layout == FQ_DENSE) {
+    // planar H0 (diag(E) in the eigenbasis layout), the drive matrices, and their
+    // commutators: K = -i [H0, Hmod] for one term; for S terms K_s = -i [H0, Hmod_s]
+    // and K_st = -i [Hmod_s, Hmod_t] (FQ_MAGNUS4). Products on FP64 matrix cores,
+    // (X Y)(i, j) = sum_k X(i, k) conj(Y(j, k)) for Hermitian Y; commutators with
+    // diag(E) elementwise.
     const int np = (int)c->np;
-    if (fq::launch_diag_planar(sys->h0_diag, n, np, c->h0r, c->stream) != hipSuccess ||
-        fq::launch_pack_planar(sys->hmod, n, n, n, c->vr, c->vi, np, c->stream) != hipSuccess ||
-        fq::launch_diag_commutator(sys->h0_diag, n, np, c->vr, c->vi, -1.0, c->kr, c->ki,
-                                   c->stream) != hipSuccess)
-      return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(hipGetLastError())));
-    if (c->scheme == FQ_MAGNUS6) {
-      st = magnus6_commutators(c);
-      if (st != FQ_OK) return bail(st);
+    const size_t plane = (size_t)c->np * (size_t)c->np;
+    auto bre = [&](int j) { return c->vr + (size_t)j * plane; };
+    auto bim = [&](int j) { return c->vi + (size_t)j * plane; };
+    hipError_t he = c->h0_eigen ? fq::launch_diag_planar(sys->h0_diag, n, np, c->h0r, c->stream)
+                                : fq::launch_pack_planar(sys->h0, n, n, n, c->h0r, c->h0i, np,
+                                                         c->stream);
+    for (int d = 0; d < c->S && he == hipSuccess; ++d)
+      he = fq::launch_pack_planar(c->S == 1 ? sys->hmod : sys->hmods[d], n, n, n, bre(d), bim(d),
+                                  np, c->stream);
+    if (he != hipSuccess)
+      return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(he)));
+    if (c->S == 1) {
+      st = hermitian_commutator(c, c->h0r, c->h0i, c->vr, c->vi, -1.0, c->kr, c->ki);
+    } else if (c->scheme == FQ_MAGNUS4) {
+      for (int d = 0; d < c->S && st == FQ_OK; ++d)
+        st = hermitian_commutator(c, c->h0r, c->h0i, bre(d), bim(d), -1.0, bre(c->S + d),
+                                  bim(c->S + d));
+      int q = 2 * c->S;
+      for (int d = 0; d < c->S; ++d)
+        for (int e = d + 1; e < c->S && st == FQ_OK; ++e, ++q)
+          st = hermitian_commutator(c, bre(d), bim(d), bre(e), bim(e), -1.0, bre(q), bim(q));
     }
-  } else if (sys->layout == FQ_DENSE) {
-    // planar copies of H0 and Hmod, and K = -i (H0 Hmod - Hmod H0) on FP64 matrix cores:
-    // (H0 Hmod)(i,j) = sum_k H0(i,k) conj(Hmod(j,k)) for Hermitian Hmod, and likewise.
-    const int np = (int)c->np;
-    if (fq::launch_pack_planar(sys->h0, n, n, n, c->h0r, c->h0i, np, c->stream) != hipSuccess ||
-        fq::launch_pack_planar(sys->hmod, n, n, n, c->vr, c->vi, np, c->stream) != hipSuccess ||
-        fq::launch_zgemm_nt_f64(c->h0r, c->h0i, false, c->vr, c->vi, true, c->kr, c->ki, np, np,
-                                np, np, 0.0, -1.0, 0.0, 0.0, c->stream) != hipSuccess ||
-        fq::launch_zgemm_nt_f64(c->vr, c->vi, false, c->h0r, c->h0i, true, c->kr, c->ki, np, np,
-                                np, np, 0.0, 1.0, 1.0, 0.0, c->stream) != hipSuccess)
-      return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(hipGetLastError())));
-    if (c->scheme == FQ_MAGNUS6) {
-      st = magnus6_commutators(c);
-      if (st != FQ_OK) return bail(st);
-    }
+    if (st == FQ_OK && c->scheme == FQ_MAGNUS6) st = magnus6_commutators(c);
+    if (st != FQ_OK) return bail(st);
   }
 
   // spectral interval
@@ -1415,7 +1584,7 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
   if (!c || !X0 || !f_grid || !avg_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
-  for (int k = 0; k < c->M_user; ++k)
+  for (int k = 0; k < c->M_user * c->S; ++k)
     if (!is_finite(f_grid[k])) return fail(FQ_ERR_NONFINITE, "f_grid[%d] is not finite", k);
   c->n_events = 0;
   c->snap = nullptr;
@@ -1434,8 +1603,12 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
       // H(t_k) into the Ht planes (free between steps), H(t_k) x into the P planes
       fq::WeightedSum ws{};
       ws.re[0] = c->h0r; ws.im[0] = c->h0i; ws.w[0] = 1.0;
-      ws.re[1] = c->vr;  ws.im[1] = c->vi;  ws.w[1] = f_grid[k];
-      ws.count = 2;
+      for (int d = 0; d < c->S; ++d) {  // drive matrices are the first S of the block
+        ws.re[1 + d] = c->vr + (size_t)d * c->np * c->np;
+        ws.im[1 + d] = c->vi + (size_t)d * c->np * c->np;
+        ws.w[1 + d] = f_grid[(size_t)k * c->S + d];
+      }
+      ws.count = 1 + c->S;
       FQ_HIP(c, fq::launch_weighted_sum(ws, c->np * c->np, c->htr, c->hti, c->stream));
       FQ_HIP(c, fq::launch_zgemm_nt_f64(c->xr, c->xi, false, c->htr, c->hti, false, c->par,
                                         c->pai, (int)mrows, np, np, np, 1.0, 0.0, 0.0, 0.0,

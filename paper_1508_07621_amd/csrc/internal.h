@@ -152,7 +152,7 @@ hipError_t launch_zgemv_planar(const double* ar, const double* ai, long n, long 
                                void* y, hipStream_t s);
 
 // out = sum_j w_j M_j over planar matrices of `total` elements each (real weights).
-constexpr int kMaxSumTerms = 11;
+constexpr int kMaxSumTerms = 16;
 struct WeightedSum {
   const double* re[kMaxSumTerms];
   const double* im[kMaxSumTerms];
@@ -284,6 +284,12 @@ struct fq_ctx {
   // dense model given in H0's eigenbasis (sys.h0_diag = E_i): H0 planes hold
   // diag(E), and commutators with H0 are taken elementwise
   bool h0_eigen = false;
+  // drive terms: S matrices Hmod_s; the drive block holds J planar matrices B_j
+  // (re planes of all J, then im planes): one term -> [Hmod, K]; S >= 2 ->
+  // [Hmod_s..., and for FQ_MAGNUS4 K_s = -i [H0, Hmod_s]..., K_st = -i [Hmod_s, Hmod_t]
+  // (s < t)]; wS (M x J) are the per-(sub)step weights of the B_j when S >= 2.
+  int S = 1, J = 2;
+  std::vector<double> wS;
   std::vector<double> w6;             // M x 9
   double* comm6 = nullptr;
   double e_min = 0, e_max = 0, beta = 0, dE = 0, R = 0;

@@ -346,35 +346,28 @@ struct EpiAdjStep {
   __device__ __forceinline__ void finish() const {}
 };
 
-// Gradient contraction of one term: acc(j, i) = (D P_l)(i', j) with D = Hmod
-// for i < np and D = K for i >= np (i' = i mod np); accumulates
-// w Re <Pbar_{l+1}, D P_l> into out[0] (Hmod) and out[1] (K).
+// Gradient contraction of one term against the stacked drive block
+// [B_0; B_1; ...] (each np rows): acc(j, i) = (B_q P_l)(i', j) for
+// q = i / np, i' = i mod np; accumulates w Re <Pbar_{l+1}, B_q P_l> into out[q].
+// np is a multiple of the tile width, so the columns of one wave's tile lie in
+// one block and a wave adds a single partial sum.
 struct EpiAdjDot {
   const double* pbr;  // Pbar_{l+1} (np x np)
   const double* pbi;
   double* out;
   long ld;
   double w;
-  double sa = 0.0, sb = 0.0;
+  double acc = 0.0;
+  long q = 0;
   __device__ __forceinline__ void operator()(int m, int n, double ar, double ai) {
-    const bool k_part = n >= ld;
-    const long idx = (long)m * ld + (k_part ? n - ld : n);
-    const double v = pbr[idx] * ar + pbi[idx] * ai;  // Re(conj(pbar) * acc)
-    if (k_part)
-      sb += v;
-    else
-      sa += v;
+    q = n / ld;
+    const long idx = (long)m * ld + (n - q * ld);
+    acc += pbr[idx] * ar + pbi[idx] * ai;  // Re(conj(pbar) * acc)
   }
   __device__ void finish() {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      sa += __shfl_xor(sa, o);
-      sb += __shfl_xor(sb, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      atomicAdd(out, w * sa);
-      atomicAdd(out + 1, w * sb);
-    }
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out + q, w * acc);
   }
 };
 

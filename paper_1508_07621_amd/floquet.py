@@ -77,7 +77,8 @@ def _device_tensor(x, dtype, device):
 class FloquetContext:
     """One problem H(t) = H0 + f(t) Hmod on one GPU, set up once, built many times.
 
-    Dense operators: h0, hmod (n x n complex). In the eigenbasis of H0 (the
+    Dense operators: h0, hmod (n x n complex; a list of 2..4 such matrices for
+    H0 + sum_s f_s(t) Hmod_s, with f_nodes of shape (M, nodes, S)). In the eigenbasis of H0 (the
     paper's working basis): h0_eigenvalues (n real) and hmod (n x n complex in
     that basis). Tridiagonal: h0_diag (n real), h0_off (n-1 complex,
     H0[i][i+1]), hmod_diag (n real).
@@ -103,24 +104,42 @@ class FloquetContext:
         self.device = torch.device(device if device is not None else "cuda")
         self._keep = []
         sysd = FqSystem()
+        drives = list(hmod) if isinstance(hmod, (list, tuple)) else None
+        self.S = len(drives) if drives else 1
+
+        def set_drives(n):
+            if drives is None:
+                vt = _device_tensor(hmod, torch.complex128, self.device)
+                if vt.shape != (n, n):
+                    raise ValueError("hmod must be n x n")
+                sysd.hmod = vt.data_ptr()
+                self._keep.append(vt)
+                return
+            vts = [_device_tensor(v, torch.complex128, self.device) for v in drives]
+            if any(v.shape != (n, n) for v in vts):
+                raise ValueError("every drive matrix must be n x n")
+            arr = (ctypes.c_void_p * len(vts))(*[v.data_ptr() for v in vts])
+            sysd.n_drive = len(vts)
+            sysd.hmods = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            self._keep += vts + [arr]
+
+        import ctypes
         if h0_eigenvalues is not None:
             e = _device_tensor(h0_eigenvalues, torch.float64, self.device)
-            vt = _device_tensor(hmod, torch.complex128, self.device)
             self.n = int(e.shape[0])
-            if vt.shape != (self.n, self.n):
-                raise ValueError("hmod must be n x n for n eigenvalues of H0")
             sysd.n, sysd.layout = self.n, _abi.FQ_DENSE_EIGEN
-            sysd.h0_diag, sysd.hmod = e.data_ptr(), vt.data_ptr()
-            self._keep += [e, vt]
+            sysd.h0_diag = e.data_ptr()
+            self._keep.append(e)
+            set_drives(self.n)
         elif h0 is not None:
             h0t = _device_tensor(h0, torch.complex128, self.device)
-            vt = _device_tensor(hmod, torch.complex128, self.device)
             self.n = int(h0t.shape[0])
-            if h0t.shape != (self.n, self.n) or vt.shape != (self.n, self.n):
-                raise ValueError("h0 and hmod must be square and of equal size")
+            if h0t.shape != (self.n, self.n):
+                raise ValueError("h0 must be square")
             sysd.n, sysd.layout = self.n, _abi.FQ_DENSE
-            sysd.h0, sysd.hmod = h0t.data_ptr(), vt.data_ptr()
-            self._keep += [h0t, vt]
+            sysd.h0 = h0t.data_ptr()
+            self._keep.append(h0t)
+            set_drives(self.n)
         else:
             d = _device_tensor(h0_diag, torch.float64, self.device)
             v = _device_tensor(hmod_diag, torch.float64, self.device)
@@ -139,7 +158,7 @@ class FloquetContext:
         if scheme not in _abi.SCHEMES:
             raise ValueError("scheme must be magnus4, magnus6 or cf4")
         self.scheme = scheme
-        per_step = 3 if scheme == "magnus6" else 2
+        per_step = (3 if scheme == "magnus6" else 2) * self.S
         self._f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))
         if self._f.size != per_step * self.M:
             raise ValueError(f"f_nodes must hold {per_step}*M values for {scheme}")
@@ -222,8 +241,8 @@ class FloquetContext:
         if X0.dim() != 2 or X0.shape[0] != self.n:
             raise ValueError("X0 must be n x ncols")
         fg = np.ascontiguousarray(np.asarray(f_grid, dtype=np.float64).reshape(-1))
-        if fg.size != self.M:
-            raise ValueError("f_grid must hold M values")
+        if fg.size != self.M * self.S:
+            raise ValueError("f_grid must hold M values per drive term")
         out = np.empty(int(X0.shape[1]), dtype=np.float64)
         torch = _torch()
         with torch.cuda.device(self.device):
@@ -235,10 +254,10 @@ class FloquetContext:
         """d loss / d f_nodes, shape (M, 2), for U_bar = dL/dRe U + i dL/dIm U."""
         torch = _torch()
         ub = _device_tensor(U_bar, self.state_dtype, self.device)
-        g = np.empty(2 * self.M, dtype=np.float64)
+        g = np.empty(2 * self.M * self.S, dtype=np.float64)
         with torch.cuda.device(self.device):
             check(lib().floquet_grad(self._ctx, ub.data_ptr(), dptr(g)))
-        return g.reshape(self.M, 2)
+        return g.reshape(self.M, 2) if self.S == 1 else g.reshape(self.M, 2, self.S)
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 5 * 8
+    assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 6 * 8
     assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 6 * 4
     assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 8 * 8 + 4 * 8
 
@@ -176,7 +176,8 @@ def test_workspace_bytes_ok_and_grows_with_n():
 @pytest.mark.parametrize("mutate,status", [
     (lambda s, p: setattr(s, "n", 0), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(s, "layout", 7), _abi.FQ_ERR_ARG),
-    (lambda s, p: setattr(s, "reserved0", 1), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(s, "n_drive", 5), _abi.FQ_ERR_ARG),
+    (lambda s, p: setattr(s, "n_drive", 2), _abi.FQ_ERR_ARG),   # no hmods
     (lambda s, p: setattr(s, "h0", None), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "T", -1.0), _abi.FQ_ERR_ARG),
     (lambda s, p: setattr(p, "T", math.inf), _abi.FQ_ERR_ARG),
@@ -273,6 +274,35 @@ def test_eigenbasis_layout_arguments():
     e.h0_diag = FAKE
     st, _ = _ws(e, _params(M=4, f=np.zeros(12), scheme=_abi.FQ_MAGNUS6))
     assert st == _abi.FQ_OK
+
+
+def test_several_drive_terms_arguments():
+    """n_drive >= 2 takes hmods (dense layouts, FQ_MAGNUS4 or FQ_CF4), S values per
+    node, and a drive block of 2S + S(S-1)/2 (Magnus-4) or S (CF4) matrices."""
+    arr = (ctypes.c_void_p * 3)(FAKE, FAKE, FAKE)
+
+    def sys3(layout=_abi.FQ_DENSE):
+        s = _dense(128)
+        s.layout, s.n_drive = layout, 3
+        s.hmods = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        s.hmod = None
+        return s
+    f = np.zeros(4 * 2 * 3)
+    st1, b1 = _ws(_dense(128), _params())
+    st4, b4 = _ws(sys3(), _params(M=4, f=f))
+    stc, bc = _ws(sys3(), _params(M=4, f=f, scheme=_abi.FQ_CF4))
+    assert st1 == st4 == stc == _abi.FQ_OK
+    plane2 = 16 * 128 * 128
+    assert b4 - b1 == (9 - 2) * plane2 and bc - b1 == (3 - 2) * plane2
+    st, _ = _ws(sys3(), _params(M=4, f=np.zeros(36), scheme=_abi.FQ_MAGNUS6))
+    assert st == _abi.FQ_ERR_UNSUPPORTED
+    t = _tridiag(128)
+    t.n_drive, t.hmods = 3, ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    st, _ = _ws(t, _params(M=4, f=f))
+    assert st == _abi.FQ_ERR_UNSUPPORTED
+    f[-1] = math.nan   # all 2 M S samples are read
+    st, _ = _ws(sys3(), _params(M=4, f=f))
+    assert st == _abi.FQ_ERR_NONFINITE
 
 
 def test_magnus6_node_times_match_the_oracle():
