@@ -56,9 +56,8 @@ __device__ __forceinline__ void split3(float x, u16& h, u16& m, u16& l) {
   l = bf16_bits((__bf16)r2);
 }
 
-// BF16X3 matrices have nine planes of 16-bit words: the hi, mid and lo pieces
-// of the real part, of the imaginary part, and of their sum (for three-product
-// complex multiplication). They are stored k-blocked: each plane of an np x np
+// BF16X3 matrices have six planes of 16-bit words: the hi, mid and lo pieces
+// of the real part and of the imaginary part. They are stored k-blocked: each plane of an np x np
 // matrix holds
 // np/16 slices, one per block of 16 columns k; slice kb holds the np rows in
 // order, 32 bytes per row (columns 16 kb .. 16 kb + 15), so the rows a
@@ -108,10 +107,6 @@ __device__ __forceinline__ void store_c(void* base, int fmt, long plane, long m,
   } else {
     u16* p = static_cast<u16*>(base) + bf3_offset(m, n, ld);
     u16 h, md, l;
-    split3((float)(re + im), h, md, l);
-    p[6 * plane] = h;
-    p[7 * plane] = md;
-    p[8 * plane] = l;
     split3((float)re, h, md, l);
     p[0] = h;
     p[plane] = md;

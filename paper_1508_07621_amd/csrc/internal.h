@@ -74,11 +74,13 @@ hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s);
 
 // ---- mixed-precision products (kernels_mixed.hip) ------------------------------------------
 // Storage formats of a complex plane pair. F64 and F32: two planes (re, im).
-// BF16X3: nine k-blocked planes of 16-bit words (formats.h), the hi, mid and lo
-// pieces of re, of im and of re + im; hi + mid + lo carries about 24
-// significant bits.
+// BF16X3: six k-blocked planes of 16-bit words (formats.h), the hi, mid and lo
+// pieces of re and of im; hi + mid + lo carries about 24 significant bits. The
+// product kernel forms the pieces of re + im (for three-product complex
+// multiplication) while it stages a k-block into LDS, which holds nine planes.
 enum Fmt : int { FMT_F64 = 0, FMT_F32 = 1, FMT_BF16X3 = 2 };
-constexpr int BF3_PLANES = 9;
+constexpr int BF3_PLANES = 6;
+constexpr int BF3_LDS_PLANES = 9;
 
 struct ChebTermX {
   int kind;

@@ -241,9 +241,12 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
 // Im = T3 - T1 - T2, each over the 6 kept piece pairs (hh, hm, mh, hl, mm, lh):
 // 18 products of 32x32x16 per tile and k-block instead of 24.
 //
-// One k-block (16 columns) of a BM-row tile is 9 contiguous runs of BM x 32
-// bytes, copied to LDS unchanged (16 bytes per thread and load, coalesced), so
-// LDS holds the same row-swizzled layout and the fragment reads
+// One k-block (16 columns) of a BM-row tile is 6 contiguous runs of BM x 32
+// bytes in the stored planes. Each thread owns one 16-byte chunk (8 columns of
+// one row) of A or of B: it loads that chunk from the six planes (coalesced
+// across the threads), forms the pieces of re + im from the values the pieces
+// hold (split3 of hi + mid + lo of re plus that of im, in FP32), and writes all
+// nine planes to LDS in the stored row-swizzled layout, so the fragment reads
 // (lane l: row l % 32, columns 8 (l / 32) .. + 7) are conflict-free. Two LDS
 // stages: while the waves multiply out of one, the next k-block is written to
 // the other from registers loaded one stage earlier; one barrier per k-block.
@@ -280,14 +283,14 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 32, FN = WTN / 32;
-  constexpr int NP = BF3_PLANES;
+  constexpr int NP = BF3_LDS_PLANES;         // planes in LDS (re, im, re + im pieces)
+  constexpr int NS = BF3_PLANES;             // stored planes (re, im pieces)
   constexpr int SA = BM * 32, SB = BN * 32;  // bytes per plane and k-block
   constexpr int STAGE = NP * (SA + SB);
-  constexpr int NCHA = 2 * NP * BM;          // 16-byte chunks of A per k-block
-  constexpr int NCH = 2 * NP * (BM + BN) / NT;  // per thread
+  constexpr int NCA = 2 * BM;                // 16-byte chunks of A per plane and k-block
   constexpr int EPI = 2 * BM * BN * 4;       // FP32 Re, Im in k-blocked order
   constexpr int SMEM = (2 * STAGE > EPI) ? 2 * STAGE : EPI;
-  static_assert(2 * NP * (BM + BN) % NT == 0, "chunk split");
+  static_assert(2 * (BM + BN) == NT, "one 16-byte chunk column of A or B per thread");
   static_assert(FM >= 1 && FN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile");
   static_assert(KIND == CHEB_MID || KIND == CHEB_LAST, "kind");
 
@@ -303,32 +306,43 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   const int nk = g.np / 16;
   const long kstride = np * 16;  // words between consecutive k-blocks of a plane
 
-  // This thread's chunks: global source (k-block 0) and LDS destination.
-  const u16* src[NCH];
-  int ldst[NCH];
-#pragma unroll
-  for (int j = 0; j < NCH; ++j) {
-    const int q = tid + j * NT;
-    if (q < NCHA) {
-      const int p = q / (2 * BM), c = q % (2 * BM);
-      src[j] = g.a + p * plane + (long)m0 * 16 + c * 8;
-      ldst[j] = p * SA + c * 16;
-    } else {
-      const int qb = q - NCHA;
-      const int p = qb / (2 * BN), c = qb % (2 * BN);
-      src[j] = g.b + p * plane + (long)n0 * 16 + c * 8;
-      ldst[j] = NP * SA + p * SB + c * 16;
-    }
-  }
-  u32x4 st[NCH];
+  // This thread's chunk column: A (threads < NCA, whole waves) or B.
+  const bool is_a = tid < NCA;
+  const int cq = is_a ? tid : tid - NCA;
+  const u16* src = is_a ? g.a + (long)m0 * 16 + cq * 8 : g.b + (long)n0 * 16 + cq * 8;
+  const int ldst = is_a ? cq * 16 : NP * SA + cq * 16;
+  const int pstep = is_a ? SA : SB;
+  u32x4 st[NS];
   auto gload = [&](int kb) {
 #pragma unroll
-    for (int j = 0; j < NCH; ++j) st[j] = *reinterpret_cast<const u32x4*>(src[j] + kb * kstride);
+    for (int p = 0; p < NS; ++p)
+      st[p] = *reinterpret_cast<const u32x4*>(src + p * plane + kb * kstride);
   };
   auto lstore = [&](int buf) {
+    unsigned char* d = smem + buf * STAGE + ldst;
 #pragma unroll
-    for (int j = 0; j < NCH; ++j)
-      *reinterpret_cast<u32x4*>(smem + buf * STAGE + ldst[j]) = st[j];
+    for (int p = 0; p < NS; ++p) *reinterpret_cast<u32x4*>(d + p * pstep) = st[p];
+    u32x4 sum[3];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t o[3] = {0u, 0u, 0u};
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const int sh = 16 * hf;
+        auto piece = [&](int p) { return bf16_val((u16)(st[p][w] >> sh)); };
+        const float re = (piece(0) + piece(1)) + piece(2);
+        const float im = (piece(3) + piece(4)) + piece(5);
+        u16 h, md, l;
+        split3(re + im, h, md, l);
+        o[0] |= (uint32_t)h << sh;
+        o[1] |= (uint32_t)md << sh;
+        o[2] |= (uint32_t)l << sh;
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sum[q][w] = o[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) *reinterpret_cast<u32x4*>(d + (NS + q) * pstep) = sum[q];
   };
 
   // Fragment offsets (bytes within a plane of a stage).
@@ -358,12 +372,10 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
 
   gload(0);
   lstore(0);
-  if (nk > 1) gload(1);
+  gload(nk > 1 ? 1 : 0);
   __syncthreads();
   for (int kb = 0; kb < nk; ++kb) {
     const int cur = kb & 1;
-    if (kb + 1 < nk) lstore(cur ^ 1);  // that buffer was last read before the previous barrier
-    if (kb + 2 < nk) gload(kb + 2);
     const unsigned char* sb = smem + cur * STAGE;
     bf8 fb[NP][FN];
 #pragma unroll
@@ -389,6 +401,13 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
       FQ_PAIR(2, 0)
 #undef FQ_PAIR
     }
+    // After this k-block's products: the next k-block (in registers since the
+    // previous iteration) into the other buffer, last read before the previous
+    // barrier, and the one after that into registers. Both unconditional, in
+    // the block of the products, so that the staging arithmetic can run beside
+    // them; the last iteration fills a buffer nobody reads.
+    lstore(cur ^ 1);
+    gload(kb + 2 < nk ? kb + 2 : nk - 1);
     __syncthreads();
   }
 
@@ -456,16 +475,15 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
     double* yr = g.y_re + m * np + n;
     double* yi = g.y_im + m * np + n;
     if constexpr (KIND == CHEB_MID) {
-      u32x4 w[NP];
+      u32x4 w[NS];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const double orr = 2.0 * (double)ar[e] - pr[e], oii = 2.0 * (double)ai[e] - pi[e];
-        u16 hs[NP];
+        u16 hs[NS];
         split3((float)orr, hs[0], hs[1], hs[2]);
         split3((float)oii, hs[3], hs[4], hs[5]);
-        split3((float)(orr + oii), hs[6], hs[7], hs[8]);
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
+        for (int k = 0; k < NS; ++k) {
           if (e & 1)
             w[k][e >> 1] |= (uint32_t)hs[k] << 16;
           else
@@ -477,7 +495,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
       }
       u16* o = static_cast<u16*>(g.o) + chunk;
 #pragma unroll
-      for (int k = 0; k < NP; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
+      for (int k = 0; k < NS; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
         d2 vr = *reinterpret_cast<const d2*>(yr + e);
@@ -656,7 +674,6 @@ __global__ void heff_bf3_kernel(const double* __restrict__ h0r, const double* __
         u16 hs[BF3_PLANES];
         split3((float)re, hs[0], hs[1], hs[2]);
         split3((float)im, hs[3], hs[4], hs[5]);
-        split3((float)(re + im), hs[6], hs[7], hs[8]);
 #pragma unroll
         for (int p = 0; p < BF3_PLANES; ++p) wd[p] |= (uint32_t)hs[p] << (16 * e);
       }
@@ -690,7 +707,6 @@ __global__ void to_product_kernel(const double* __restrict__ re, const double* _
         u16 hs[BF3_PLANES];
         split3((float)r2[e], hs[0], hs[1], hs[2]);
         split3((float)i2[e], hs[3], hs[4], hs[5]);
-        split3((float)(r2[e] + i2[e]), hs[6], hs[7], hs[8]);
 #pragma unroll
         for (int p = 0; p < BF3_PLANES; ++p) wd[p] |= (uint32_t)hs[p] << (16 * e);
       }
