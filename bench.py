@@ -78,6 +78,10 @@ def parse():
     ap.add_argument("--second-round", action="store_true",
                     help="after the timed builds, diagonalise U_T on the host and time the second "
                          "propagation round (period-averaged energies of all Floquet states)")
+    ap.add_argument("--shard", type=int, default=0, metavar="P",
+                    help="also time one GPU's share of a P-GPU column split: the first N/P "
+                         "columns of the identity propagated over the period (Sec. 5), against "
+                         "1/P of the full build")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one device-to-device copy of BYTES bytes (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -162,8 +166,9 @@ MFMA_FLOPS_PER_FLOP = {"fp64": 0.75, "fp32": 1.0, "bf16x3": 4.5}
 BIG_TILE_ELEMS = 256 * 128 * 128
 
 
-def mfma_flops_per_flop(precision: str, n: int) -> float:
-    if precision == "fp64" and n * n < BIG_TILE_ELEMS:
+def mfma_flops_per_flop(precision: str, n: int, rows: int = 0) -> float:
+    """MFMA flops per algorithmic flop of a product with (rows or n) x n outputs."""
+    if precision == "fp64" and (rows or n) * n < BIG_TILE_ELEMS:
         return 1.0
     return MFMA_FLOPS_PER_FLOP[precision]
 PEAKS = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
@@ -323,6 +328,45 @@ def second_round(ctx, U, wl, kw):
                             "abs_diff": abs(float(e_mean.sum()) - expect)}}
 
 
+def shard_share(ctx, U, wl, P: int, warmup: int, steps: int, s_full: float, precision: str):
+    """One GPU's share of the column split over P GPUs (Sec. 5, Fig. 2): the
+    first N/P identity columns propagated over the whole period with the same
+    context, timed like the builds. Each GPU of the split would run exactly
+    this (its own columns, no communication inside the period); the result must
+    equal those columns of the full build."""
+    import torch
+    from paper_1508_07621_amd._abi import K_MID, K_TRIDIAG
+    n = U.shape[0]
+    if P < 2 or n % P:
+        raise SystemExit(f"--shard {P}: P must be >= 2 and divide N = {n}")
+    cols = n // P
+    X0 = torch.eye(n, dtype=U.dtype, device=U.device)[:, :cols].contiguous()
+    out = torch.empty_like(X0)
+    for _ in range(warmup):
+        ctx.propagate(X0, 0, wl.M, out=out)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ctx.propagate(X0, 0, wl.M, out=out)
+        reps.append(ctx.report)
+        _log(f"shard 1/{P} timed propagation {i + 1}/{steps}")
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    kind = K_MID if wl.layout == "dense" else K_TRIDIAG
+    n_launch = sum(r["n_kernel"][kind] for r in reps)
+    ms_launch = sum(r["ms_kernel"][kind] for r in reps) / max(n_launch, 1)
+    res = {"P": P, "columns": cols, "s_per_share": round(t, 6),
+           "ideal_s": round(s_full / P, 6), "efficiency_vs_full_build": round(s_full / P / t, 4),
+           "max_abs_vs_full_build": (out - U[:, :cols]).abs().max().item(),
+           "dominant_kernel_avg_ms": round(ms_launch, 4)}
+    if wl.layout == "dense":
+        flops = 8.0 * n * n * cols
+        mf = flops * mfma_flops_per_flop(precision, n, cols)
+        res["dominant_kernel_mfma_frac"] = round(mf / (ms_launch * 1e-3) / 1e12 / PEAKS[precision], 4)
+    return res
+
+
 def eigen_errors(U, Uref, T: float):
     """Host FP64 eigenphases (LAPACK zgeev through NumPy) of both results and
     the largest quasienergy difference (symmetric circular matching)."""
@@ -463,6 +507,9 @@ def main():
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops * per_build / s_per_build / 1e12
 
+    if args.shard and not grad_mode:
+        extra["shard"] = shard_share(ctx, U, wl, args.shard, args.warmup, args.steps,
+                                     s_per_build, precision)
     if args.second_round and not grad_mode:
         extra["second_round"] = second_round(ctx, U, wl, kw)
     if args.time_error_ref and not grad_mode:
