@@ -39,6 +39,12 @@ TRIDIAG_FLOPS_PER_ELEMENT_TERM = 26
 #: as streamed passes with ghost rows
 TRIDIAG_RESIDENT_MAX_N = 4096
 
+#: algorithmic real flops per element and term of the streamed reverse pass:
+#: Pbar_l = w Ht Pbar_{l+1} - Pbar_{l+2} + d_l Lambda (couplings 12, diagonal 2,
+#: adds 4, scale and subtract 4, complex source 8), P_{l-1} = 2 Ht P_l - P_{l+1}
+#: (22) and the contraction w v_i Re(conj(Pbar) P) (6)
+TRIDIAG_ADJ_REV_FLOPS_PER_ELEMENT_TERM = 58
+
 WORKLOAD_TEXT = {
     "gue4096": "random-matrix model N=4096 (GUE H0, V), f=cos t, T=2pi, M=200 Magnus-4 steps, "
                "Chebyshev order for 1e-12 per step",
@@ -52,6 +58,10 @@ WORKLOAD_TEXT = {
     "gue10000": "random-matrix model N=10^4 (GUE H0, V), f=cos t, T=2pi, M=200",
     "gue4096m6": "random-matrix model N=4096 as gue4096 with the paper's sixth-order Magnus "
                  "scheme (Eq. (14), three Gauss-Legendre nodes), M=50 steps",
+    "adjointdimer10000": "adjoint: Bose-Hubbard dimer, 9999 bosons (N=10^4, tridiagonal, J=1, "
+                         "U=0.01), piecewise-constant f_j ~ U(-1,1) on V = n1 - n2, T=2pi, M=256, "
+                         "loss 1-|Tr(W^dagger U)|^2/N^2 with W = U_T of the drive f_j + 0.02 u_j, "
+                         "checkpoint every 16 steps; step = forward build + gradient",
 }
 
 
@@ -78,6 +88,9 @@ def parse():
     ap.add_argument("--second-round", action="store_true",
                     help="after the timed builds, diagonalise U_T on the host and time the second "
                          "propagation round (period-averaged energies of all Floquet states)")
+    ap.add_argument("--fd-check", type=float, default=0.0, metavar="EPS",
+                    help="gradient workloads: also compare the gradient along a seeded direction "
+                         "with a central difference of step EPS (two more builds)")
     ap.add_argument("--shard", type=int, default=0, metavar="P",
                     help="also time one GPU's share of a P-GPU column split: the first N/P "
                          "columns of the identity propagated over the period (Sec. 5), against "
@@ -245,20 +258,48 @@ def time_build_grad(ctx, U, W, warmup: int, steps: int):
         tau = torch.sum(torch.conj(W) * U)
         ubar = (-2.0 / n ** 2) * tau * W
         t0 = time.perf_counter()
-        ctx.grad(ubar)
-        return time.perf_counter() - t0
+        g = ctx.grad(ubar)
+        return time.perf_counter() - t0, g, tau.item()
 
     for _ in range(warmup):
         one()
     torch.cuda.synchronize()
-    reports, gsum = [], 0.0
+    reports, grad_reports, gsum = [], [], 0.0
     t0 = time.perf_counter()
     for i in range(steps):
-        gsum += one()
+        dt, g, tau = one()
+        gsum += dt
         reports.append(ctx.last_report)
-        _log(f"build+grad {i + 1}/{steps}: build {reports[-1]['ms_build']:.1f} ms")
+        grad_reports.append(ctx.report)
+        _log(f"build+grad {i + 1}/{steps}: build {reports[-1]['ms_build']:.1f} ms, "
+             f"gradient {1e3 * dt:.1f} ms")
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, reports, 1e3 * gsum / steps
+    return ((time.perf_counter() - t0) / steps, reports, 1e3 * gsum / steps, grad_reports, g,
+            1.0 - abs(tau) ** 2 / n ** 2)
+
+
+def fd_direction(wl, kw, f, g, W, eps: float):
+    """Directional check of the gradient: (L(f + eps d) - L(f - eps d)) / (2 eps)
+    against g . d for a seeded unit direction d over the amplitudes, with two
+    more builds of the library."""
+    import numpy as np
+    import torch
+    from paper_1508_07621_amd import floquet as fl
+    n = W.shape[0]
+    d = np.random.default_rng(1508 + 77).standard_normal(f.size)
+    d /= np.linalg.norm(d)
+    vals = []
+    for sgn in (+1, -1):
+        ff = f + sgn * eps * d
+        c = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=np.stack([ff, ff], 1), device=W.device, **kw)
+        Uf = c.build_ut()
+        tau = torch.sum(torch.conj(W) * Uf).item()
+        vals.append(1.0 - abs(tau) ** 2 / n ** 2)
+        del c, Uf
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    ad = float(np.dot(g, d))
+    return {"direction": "seeded unit vector over the amplitudes", "eps": eps, "adjoint": ad,
+            "finite_difference": fd, "rel_diff": abs(ad - fd) / max(abs(fd), 1e-300)}
 
 
 def dense_roofline(reports, n: int, precision: str, workload: str):
@@ -417,10 +458,11 @@ def main():
     if args.scheme:
         wl.scheme = args.scheme
     precision = args.precision if wl.layout == "dense" else "fp64"
-    grad_mode = args.workload == "adjoint1024"
+    grad_mode = wl.amplitudes is not None
     if grad_mode:
         f_nodes = np.stack([wl.amplitudes, wl.amplitudes], 1)
-        if args.precision == "bf16x3" and "--precision" not in sys.argv:
+        if (wl.layout == "dense" and args.precision == "bf16x3"
+                and "--precision" not in sys.argv):
             precision = "fp32"  # the configuration's complex64 forward
     elif wl.layout == "tridiag":
         f_nodes = drive_cos(fl.node_times(wl.T, wl.M, scheme=wl.scheme), 0.5, 1.5, 1.0)
@@ -433,10 +475,20 @@ def main():
                   hmod_diag=wl.arrays["v_diag"])
 
     t_setup = time.perf_counter()
+    c64_grad = grad_mode and wl.layout == "dense"   # the dense adjoint configuration's complex64
+    interval = {}
+    if grad_mode and args.fd_check > 0:
+        # room around the library's interval for the perturbed drives of the
+        # check, which then use the same interval and order (the gradient holds
+        # beta, dE and L fixed)
+        probe = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, device=dev,
+                                  scheme=wl.scheme, **kw).report
+        margin = 1.0 + 1e-3 * (probe["e_max"] - probe["e_min"])
+        interval = dict(e_min=probe["e_min"] - margin, e_max=probe["e_max"] + margin)
     ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision=precision,
                             profile=True, device=dev, checkpoint_every=16 if grad_mode else 0,
-                            dtype="complex64" if grad_mode else "complex128",
-                            scheme=wl.scheme, **kw)
+                            dtype="complex64" if c64_grad else "complex128",
+                            scheme=wl.scheme, **interval, **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     info = ctx.report
@@ -445,8 +497,17 @@ def main():
     n = wl.n
     U = torch.empty((n, n), dtype=ctx.state_dtype, device=dev)
     if grad_mode:
-        W = torch.from_numpy(wl.arrays["w"]).to(device=dev, dtype=ctx.state_dtype)
-        s_per_build, reports, grad_ms = time_build_grad(ctx, U, W, args.warmup, args.steps)
+        if "w" in wl.arrays:
+            W = torch.from_numpy(wl.arrays["w"]).to(device=dev, dtype=ctx.state_dtype)
+        else:  # the target gate: U_T of the nearby drive (untimed)
+            ft = wl.arrays["f_target"]
+            _log("target U_T of the nearby drive")
+            tctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=np.stack([ft, ft], 1), tol=1e-12,
+                                     device=dev, **kw)
+            W = tctx.build_ut()
+            del tctx
+        s_per_build, reports, grad_ms, grad_reports, g_last, loss = time_build_grad(
+            ctx, U, W, args.warmup, args.steps)
     else:
         s_per_build, reports = time_builds(ctx, U, args.warmup, args.steps, precision)
     last = reports[-1]
@@ -456,9 +517,19 @@ def main():
     if grad_mode:
         extra["gradient"] = {"ms_per_grad": round(grad_ms, 3),
                              "ms_per_build": round(1e3 * s_per_build - grad_ms, 3),
-                             "note": "value = forward build (FP32 products, tape every 16 steps) "
-                                     "+ FP64 reverse sweep for the 256 amplitudes; U_T and "
-                                     "U_bar stored in complex64"}
+                             "loss": loss, "max_abs_grad": float(np.max(np.abs(g_last))),
+                             "note": ("value = forward build (FP32 products, tape every 16 steps) "
+                                      "+ FP64 reverse sweep for the 256 amplitudes; U_T and "
+                                      "U_bar stored in complex64") if wl.layout == "dense" else
+                                     ("value = forward build (streamed passes, checkpoints every "
+                                      "16 steps) + streamed FP64 reverse sweep for the 256 "
+                                      "amplitudes")}
+        if args.fd_check > 0:
+            _log("directional finite-difference check of the gradient")
+            fkw = {k: v for k, v in kw.items()}
+            fkw.update(e_min=info["e_min"], e_max=info["e_max"], L=info["L"])
+            extra["gradient"]["fd_direction"] = fd_direction(wl, fkw, wl.amplitudes,
+                                                             g_last.sum(axis=1), W, args.fd_check)
     if wl.layout == "dense":
         roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
@@ -506,6 +577,29 @@ def main():
                 "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
                 "algorithmic_flops_per_launch": flops}
         build_tflops = flops * per_build / s_per_build / 1e12
+        if grad_mode:
+            # build + gradient: the streamed reverse pass dominates
+            from paper_1508_07621_amd._abi import K_ADJ_FWD, K_ADJ_REV
+            n_rev = sum(r["n_kernel"][K_ADJ_REV] for r in grad_reports)
+            ms_rev = sum(r["ms_kernel"][K_ADJ_REV] for r in grad_reports) / max(n_rev, 1)
+            n_fwd = sum(r["n_kernel"][K_ADJ_FWD] for r in grad_reports)
+            ms_fwd = sum(r["ms_kernel"][K_ADJ_FWD] for r in grad_reports) / max(n_fwd, 1)
+            if n_rev:
+                per_grad = n_rev / len(grad_reports)
+                flops_rev = (float(TRIDIAG_ADJ_REV_FLOPS_PER_ELEMENT_TERM) * n * n * wl.M
+                             * info["L"] / per_grad)
+                ach = flops_rev / (ms_rev * 1e-3) / 1e12
+                extra["build_roofline"] = roof
+                roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VECTOR_TFLOPS, 4),
+                        "traffic": None, "traffic_detail": None,
+                        "kernel": "tridiag_adj_reverse_kernel<4,8> (reverse passes of up to 128 "
+                                  "terms; 1792 owned + 2 x 128 ghost rows per workgroup, complex form)",
+                        "avg_launch_ms": round(ms_rev, 4), "launches_timed": n_rev,
+                        "algorithmic_flops_per_launch": flops_rev}
+                extra["gradient"]["segment_recompute_pass"] = {
+                    "kernel": "tridiag_adj_forward_kernel<4,8>", "avg_launch_ms": round(ms_fwd, 4),
+                    "launches_timed": n_fwd}
 
     if args.shard and not grad_mode:
         extra["shard"] = shard_share(ctx, U, wl, args.shard, args.warmup, args.steps,

@@ -193,6 +193,8 @@ enum {
   FQ_K_LAST = 3,        /* last product of a step, with the phase and hand-off */
   FQ_K_HEFF = 4,        /* per-step rescaled Hamiltonian */
   FQ_K_TRIDIAG = 5,     /* tridiagonal whole-chain kernel */
+  FQ_K_ADJ_FWD = 6,     /* gradient, streamed tridiagonal: segment recompute pass */
+  FQ_K_ADJ_REV = 7,     /* gradient, streamed tridiagonal: reverse pass */
   FQ_K_SLOTS = 8
 };
 
@@ -295,7 +297,17 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * floquet_build_UT. U_bar: device, n*n complex (fq_params.dtype) row-major with
  * U_bar[i][j] = dLoss/dRe U[i][j] + i dLoss/dIm U[i][j]. grad_f_nodes: host,
  * 2*M float64 (2*M*S with several drive terms), same order as f_nodes. Needs
- * checkpoint_every > 0. */
+ * checkpoint_every > 0.
+ * FQ_TRIDIAG: up to n = 2048 one workgroup reverses each state column;
+ * longer columns run the same recurrences in streamed passes of at most 128
+ * terms over windows of rows with ghost rows (setting the environment variable
+ * FQ_TRIDIAG_STREAMED_ADJOINT=1 before fq_workspace_bytes / fq_create selects
+ * the streamed form for any n; both give the same derivative). For n > 4096
+ * the build records its checkpoints in the state type, so the gradient needs
+ * complex128 state blocks there. In profile mode the report then holds the
+ * streamed passes' times (FQ_K_ADJ_FWD, FQ_K_ADJ_REV); with FQ_PROGRESS=1 in
+ * the environment the streamed sweep prints a line on stderr per checkpoint
+ * segment. */
 fq_status floquet_grad(fq_ctx* ctx, const void* U_bar, double* grad_f_nodes);
 
 /* Thread-local description of the last non-OK status ("" if none). */

@@ -22,6 +22,7 @@ SCHEMES = {"magnus4": FQ_MAGNUS4, "magnus6": FQ_MAGNUS6, "cf4": FQ_CF4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 #: kernel kinds timed in profile mode (fq_report.ms_kernel indices)
 K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 8
+K_ADJ_FWD, K_ADJ_REV = 6, 7
 
 #: every entry point include/floquet.h declares
 EXPORTS = (

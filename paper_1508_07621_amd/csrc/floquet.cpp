@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <limits>
@@ -89,10 +90,22 @@ struct Layout {
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
          off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
          off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0,
+         off_adj = 0,
          off_comm6 = 0, off_vec = 0;
   long np = 0;
   int n_tape = 0;
 };
+
+// The tridiagonal gradient of columns longer than one workgroup holds runs as
+// streamed passes (tridiag_adjoint_streamed). FQ_TRIDIAG_STREAMED_ADJOINT=1 in
+// the environment selects that form for every n (it gives the same derivative
+// as the per-column sweep; tests compare the two).
+bool streamed_adjoint(const fq_system* sys, const fq_params* par) {
+  if (sys->layout != FQ_TRIDIAG || par->checkpoint_every <= 0) return false;
+  if (sys->n > fq::tridiag_adjoint_max_n()) return true;
+  const char* e = std::getenv("FQ_TRIDIAG_STREAMED_ADJOINT");
+  return e && e[0] == '1' && e[1] == 0;
+}
 
 Layout plan(const fq_system* sys, const fq_params* par) {
   Layout lay;
@@ -156,6 +169,9 @@ Layout plan(const fq_system* sys, const fq_params* par) {
       lay.off_tape = take(vec * (size_t)n * (size_t)lay.n_tape);
       lay.off_seg = take(vec * (size_t)n * 3 * (size_t)cks);
       lay.off_grad = take(2 * sizeof(double) * (size_t)Ms);
+      // streamed reverse sweep: the carried state of two pass sets (4 + 4
+      // vectors) and two Lambda vectors
+      if (streamed_adjoint(sys, par)) lay.off_adj = take(10 * vec * (size_t)n);
     }
   }
   lay.off_small = take(64 * sizeof(double));
@@ -234,9 +250,11 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
     // 8-plane n x n FP64 states in the workspace (128 n^2 bytes)
     if (sys->n > 40000)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal n > 40000 not supported");
-    if (par->checkpoint_every > 0 && sys->n > fq::tridiag_adjoint_max_n())
-      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal gradient needs n <= %ld",
-                  fq::tridiag_adjoint_max_n());
+    // the streamed forward build records its checkpoints in the state blocks' type
+    if (par->checkpoint_every > 0 && sys->n > fq::tridiag_resident_max_n() &&
+        par->dtype == FQ_C64)
+      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal gradient with n > %ld needs complex128 state "
+                  "blocks", fq::tridiag_resident_max_n());
   }
   return FQ_OK;
 }
@@ -1140,7 +1158,135 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
 // Gradient of the tridiagonal chain: one reverse-sweep launch over all columns
 // (each workgroup recomputes its column's segments from the tape), then the
 // chain rule to the node samples as in the dense case.
+// The reverse sweep in streamed passes (columns longer than one workgroup
+// holds, or on request): per checkpoint segment, last first, the steps are
+// recomputed forward from the segment's checkpoint, keeping X_k, P_{L-1} and
+// P_L of every step (col-major vectors in the segment buffer); then each step
+// is reversed in passes of at most K terms, Lambda passing from step to step.
+fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
+  const int M = c->M, L = c->L, ckpt = c->ckpt;
+  const long n = c->n;
+  const size_t vec = 2 * (size_t)n * (size_t)n;  // doubles per complex n x n vector
+  const int K = 128;
+  const long win = fq::tridiag_adj_window_rows();
+  fq::TridiagAdjPass p{};
+  p.n = n;
+  p.ncols = n;
+  p.K = K;
+  p.B = (int)(win - 2L * K);
+  p.nblk = (int)((n + p.B - 1) / p.B);
+  p.L = L;
+  p.h0_diag = c->sys.h0_diag;
+  p.h0_off = reinterpret_cast<const double*>(c->sys.h0_off);
+  p.v_diag = c->sys.hmod_diag;
+  p.beta = c->beta;
+  p.inv_dE = 1.0 / c->dE;
+  p.phr = c->phr;
+  p.phi = c->phi;
+  p.coef = c->d_coef;
+  p.any_b = 0;
+  for (int k = 0; k < M; ++k) p.any_b |= (c->b[k] != 0.0);
+  double* set[2][4];
+  for (int q = 0; q < 2; ++q)
+    for (int j = 0; j < 4; ++j) set[q][j] = c->d_adj + (size_t)(4 * q + j) * vec;
+  double* lam[2] = {c->d_adj + 8 * vec, c->d_adj + 9 * vec};
+  auto seg_x = [&](int s) { return c->seg + (size_t)(3 * s) * vec; };
+  auto seg_plm1 = [&](int s) { return c->seg + (size_t)(3 * s + 1) * vec; };
+  auto seg_pl = [&](int s) { return c->seg + (size_t)(3 * s + 2) * vec; };
+  // tape entry j: X_{j ckpt}, col-major FP64 from the per-column build, row-major
+  // in the state type from the streamed build (entry 0 then not stored: identity)
+  const bool tape_rows = n > fq::tridiag_resident_max_n();
+  auto set_io = [&](int cur) {
+    for (int j = 0; j < 4; ++j) {
+      p.in[j] = set[cur][j];
+      p.out[j] = set[cur ^ 1][j];
+    }
+  };
+  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
+  c->n_events = 0;  // profile mode: the passes' times go to the report
+  const void* lam_src = U_bar;  // Lambda_M: U_bar, row-major in the state type
+  int lam_rows = 1, lam_c64 = c->c64 ? 1 : 0, lam_next = 0;
+  const int nseg = (M + ckpt - 1) / ckpt;
+  // FQ_PROGRESS=1: a line on stderr after each segment (long sweeps)
+  const char* prog = std::getenv("FQ_PROGRESS");
+  const bool progress = prog && prog[0] == '1';
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int k0 = sg * ckpt, k1 = std::min(k0 + ckpt, M);
+    int cur = 0;
+    for (int k = k0; k < k1; ++k) {  // forward recompute of the segment
+      p.a = c->a[k];
+      p.b = c->b[k];
+      for (int lo = 0; lo < L; lo += K) {
+        p.lo = lo;
+        p.hi = std::min(lo + K, L);
+        set_io(cur);
+        p.x = nullptr;
+        p.x_store = nullptr;
+        p.x_rowmajor = p.x_c64 = 0;
+        if (lo == 0) {
+          if (k == k0) {
+            if (!tape_rows) {
+              p.x = c->tape + (size_t)sg * vec;
+            } else if (sg > 0) {
+              p.x = c->tape + (size_t)sg * vec;
+              p.x_rowmajor = 1;
+              p.x_c64 = c->c64 ? 1 : 0;
+            }
+            p.x_store = seg_x(0);
+          } else {
+            p.x = seg_x(k - k0);
+          }
+        }
+        p.plm1 = seg_plm1(k - k0);
+        p.pl = seg_pl(k - k0);
+        p.xnext = (k + 1 < k1) ? seg_x(k + 1 - k0) : nullptr;
+        FQ_MARK(c, FQ_K_ADJ_FWD);
+        FQ_HIP(c, fq::launch_tridiag_adj_forward(p, c->stream));
+        cur ^= 1;
+      }
+    }
+    for (int k = k1 - 1; k >= k0; --k) {  // reverse
+      p.a = c->a[k];
+      p.b = c->b[k];
+      p.lam = lam_src;
+      p.lam_rowmajor = lam_rows;
+      p.lam_c64 = lam_c64;
+      p.p0 = seg_x(k - k0);
+      p.seg_plm1 = seg_plm1(k - k0);
+      p.seg_pl = seg_pl(k - k0);
+      p.lam_out = lam[lam_next];
+      p.grad = c->d_grad + 2 * (size_t)k;
+      for (int hi = L - 1; hi >= 0; hi -= K) {
+        p.hi = hi;
+        p.lo = std::max(hi - K + 1, 0);
+        set_io(cur);
+        FQ_MARK(c, FQ_K_ADJ_REV);
+        FQ_HIP(c, fq::launch_tridiag_adj_reverse(p, c->stream));
+        cur ^= 1;
+      }
+      lam_src = lam[lam_next];
+      lam_rows = 0;
+      lam_c64 = 0;
+      lam_next ^= 1;
+    }
+    if (progress) {
+      FQ_HIP(c, hipStreamSynchronize(c->stream));
+      std::fprintf(stderr, "floquet_grad: segment %d of %d reversed (steps %d..%d)\n",
+                   nseg - sg, nseg, k0, k1 - 1);
+      std::fflush(stderr);
+    }
+  }
+  FQ_MARK(c, -1);
+  std::vector<double> g(2 * (size_t)M);
+  FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  FQ_HIP(c, hipStreamSynchronize(c->stream));
+  grad_to_nodes(c, g, grad_f_nodes);
+  return collect_profile(c);
+}
+
 fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
+  if (c->d_adj) return tridiag_adjoint_streamed(c, U_bar, grad_f_nodes);
   const int M = c->M;
   fq::TridiagAdjJob job{};
   job.n = c->n;
@@ -1344,6 +1490,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
       c->n_tape = lay.n_tape;
       c->seg = P(lay.off_seg);
       c->d_grad = P(lay.off_grad);
+      if (lay.off_adj) c->d_adj = P(lay.off_adj);
     }
   }
   c->xi = c->xr + plane;
@@ -1506,7 +1653,17 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
   } else {
     FQ_HIP(c, hipEventRecord(e0, c->stream));
+    // Streamed columns record the checkpoints X_{j ckpt}, j >= 1, through the
+    // snapshot store (row-major, tape entries 1, 2, ...); entry 0 is the identity.
+    const bool snap_tape = c->ckpt > 0 && c->n > fq::tridiag_resident_max_n();
+    if (snap_tape) {
+      c->snap = c->tape + 2 * (size_t)c->n * (size_t)c->n;
+      c->snap_every = c->ckpt;
+      c->snap_k0 = 0;
+      c->snap_ncols = c->n;
+    }
     st = tridiag_run(c, nullptr, c->n, 0, c->M, U_out);
+    c->snap = nullptr;
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
     FQ_HIP(c, hipEventRecord(e1, c->stream));

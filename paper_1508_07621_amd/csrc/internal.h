@@ -257,6 +257,44 @@ struct TridiagAdjJob {
 };
 long tridiag_adjoint_max_n();
 hipError_t launch_tridiag_adjoint(const TridiagAdjJob& job, hipStream_t s);
+
+// One launch of the streamed reverse sweep for columns longer than one
+// workgroup holds: a window of tridiag_adj_window_rows() consecutive rows per
+// workgroup, K ghost rows on each side of the B rows it owns, at most K terms
+// of one step. Vectors are complex, column-major (column c at c * n) unless a
+// flag says row-major (i * ncols + c).
+struct TridiagAdjPass {
+  long n, ncols;
+  int nblk, B, K;            // blocks per column, owned rows per block, ghost rows per side
+  int L, lo, hi;             // forward: P_{lo+1} .. P_hi; reverse: terms l = hi .. lo
+  const double* h0_diag;
+  const double* h0_off;      // complex interleaved (n-1)
+  const double* v_diag;
+  double a, b, beta, inv_dE, phr, phi;  // step scalars
+  const double* coef;        // c_l complex interleaved
+  int any_b;                 // reverse: accumulate the K contraction
+  // forward pass
+  const void* x;             // lo == 0: P_0 = X_k; null = identity columns
+  int x_rowmajor, x_c64;
+  double* x_store;           // lo == 0: owned rows of P_0, or null
+  double* plm1;              // hi == L: P_{L-1}
+  double* pl;                // hi == L: P_L
+  double* xnext;             // hi == L: X_{k+1} = phase Y, or null
+  // reverse pass
+  const void* lam;           // Lambda of the step
+  int lam_rowmajor, lam_c64;
+  const double* p0;          // X_k, read at l == 1
+  const double* seg_plm1;    // hi == L - 1: P_{L-1}
+  const double* seg_pl;      // hi == L - 1: P_L
+  double* lam_out;           // lo == 0: Pbar_0
+  double* grad;              // the step's accumulators: Re sum w_l <Pbar_{l+1}, D P_l>, D = Hmod, K
+  // state carried between passes: forward (P_{l-1}, P_l, Y), reverse (P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2})
+  const double* in[4];
+  double* out[4];
+};
+long tridiag_adj_window_rows();
+hipError_t launch_tridiag_adj_forward(const TridiagAdjPass& p, hipStream_t s);
+hipError_t launch_tridiag_adj_reverse(const TridiagAdjPass& p, hipStream_t s);
 hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s);
 
 // Unit gauge factors of step s (host FP64): w_0 = 1, w_{i+1} = w_i conj(u_i) with
@@ -323,6 +361,7 @@ struct fq_ctx {
   double* d_coef = nullptr;           // 2*(L+1)
   double* d_gauge = nullptr;          // tridiagonal: M x n complex gauge factors
   double* d_stream = nullptr;         // tridiagonal n > resident size: two 8-plane states
+  double* d_adj = nullptr;            // streamed reverse sweep: 10 complex n x n vectors
   double* d_vec = nullptr;            // 3 n doubles: period-average accumulators
   // state
   bool tape_valid = false;

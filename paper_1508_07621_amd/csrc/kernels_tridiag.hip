@@ -869,6 +869,358 @@ hipError_t launch_adj_r(const TridiagAdjJob& job, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- streamed reverse sweep ------------------------------------------------------------------
+//
+// For columns longer than one workgroup holds, the recurrences of
+// tridiag_adjoint_kernel run one step at a time and at most K terms per
+// launch. A workgroup holds a window of W*64*R consecutive rows of one column:
+// the B rows it owns and K ghost rows on each side. Every term reads one
+// neighbour row on each side, so after at most K terms the owned rows are still
+// exact; they are written back and the next launch continues from them. Rows
+// outside [0, n) are zero, as are their couplings, which is exact at the ends of
+// the chain. Two kinds of pass:
+//   forward (segment recompute): P_{lo+1} .. P_hi and the running sum Y of one
+//     step, from P_0 = X_k when lo == 0; at hi == L it stores P_{L-1}, P_L and
+//     X_{k+1} = phase Y for the reverse passes;
+//   reverse: terms l = hi .. lo of the adjoint recurrence with P regenerated
+//     downwards, the contractions over the owned rows added to the step's two
+//     accumulators; at lo == 0 it stores Pbar_0, the Lambda of the step before.
+
+// Per-window operator rows of one step and the neighbour exchange of the window.
+template <int R, int W>
+struct AdjWindow {
+  double dd[R], er[R], ei[R], kr[R], ki[R], vv[R];
+  double emr, emi, kmr, kmi;  // couplings from row base - 1
+  double (*halo)[4][2][W];
+  int parity, lane, wid;
+
+  __device__ __forceinline__ void set(const TridiagAdjPass& p, long base) {
+    const double2* h0o = reinterpret_cast<const double2*>(p.h0_off);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      dd[r] = er[r] = ei[r] = kr[r] = ki[r] = vv[r] = 0.0;
+      if (i >= 0 && i < p.n) {
+        vv[r] = p.v_diag[i];
+        dd[r] = (p.h0_diag[i] + p.a * vv[r] - p.beta) * p.inv_dE;
+        if (i + 1 < p.n) {
+          const double2 h = h0o[i];
+          const double dv = p.v_diag[i + 1] - vv[r], q = p.b * dv;
+          er[r] = (h.x + h.y * q) * p.inv_dE;  // h (1 - i q) / dE
+          ei[r] = (h.y - h.x * q) * p.inv_dE;
+          kr[r] = h.y * dv;                    // K = -i h dv
+          ki[r] = -h.x * dv;
+        }
+      }
+    }
+    emr = emi = kmr = kmi = 0.0;
+    if (base >= 1 && base < p.n) {
+      const double2 h = h0o[base - 1];
+      const double dv = p.v_diag[base] - p.v_diag[base - 1], q = p.b * dv;
+      emr = (h.x + h.y * q) * p.inv_dE;
+      emi = (h.y - h.x * q) * p.inv_dE;
+      kmr = h.y * dv;
+      kmi = -h.x * dv;
+    }
+  }
+
+  // Neighbour rows of two complex vectors: base - 1 (nb[0..3]) and base + R
+  // (nb[4..7]); zero beyond the window.
+  __device__ __forceinline__ void exchange(const double* xr, const double* xi, const double* yr,
+                                           const double* yi,
+                           double nb[8]) {
+    nb[0] = from_prev_lane(xr[R - 1]);
+    nb[1] = from_prev_lane(xi[R - 1]);
+    nb[2] = from_prev_lane(yr[R - 1]);
+    nb[3] = from_prev_lane(yi[R - 1]);
+    nb[4] = from_next_lane(xr[0]);
+    nb[5] = from_next_lane(xi[0]);
+    nb[6] = from_next_lane(yr[0]);
+    nb[7] = from_next_lane(yi[0]);
+    if (lane == 0) {
+      halo[parity][0][0][wid] = xr[0];
+      halo[parity][1][0][wid] = xi[0];
+      halo[parity][2][0][wid] = yr[0];
+      halo[parity][3][0][wid] = yi[0];
+    }
+    if (lane == 63) {
+      halo[parity][0][1][wid] = xr[R - 1];
+      halo[parity][1][1][wid] = xi[R - 1];
+      halo[parity][2][1][wid] = yr[R - 1];
+      halo[parity][3][1][wid] = yi[R - 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double hu = (wid > 0) ? halo[parity][q][1][wid - 1] : 0.0;
+      const double hd = (wid + 1 < W) ? halo[parity][q][0][wid + 1] : 0.0;
+      nb[q] = (lane == 0) ? hu : nb[q];
+      nb[4 + q] = (lane == 63) ? hd : nb[4 + q];
+    }
+    parity ^= 1;
+  }
+
+  // out = f Ht x - out (+ (cr + i ci) lam with SRC)
+  template <bool SRC>
+  __device__ __forceinline__ void apply(const double* xr, const double* xi, double ur, double ui,
+                                        double dr_,
+                        double di_, double f, double* or_, double* oi, double cr, double ci,
+                        const double* lr, const double* li) const {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double lor = (r == 0) ? ur : xr[r - 1], loi = (r == 0) ? ui : xi[r - 1];
+      const double hir = (r == R - 1) ? dr_ : xr[r + 1], hii = (r == R - 1) ? di_ : xi[r + 1];
+      const double cer = (r == 0) ? emr : er[r - 1], cei = (r == 0) ? emi : ei[r - 1];
+      // conj(e_{i-1}) x_{i-1} + e_i x_{i+1} + d_i x_i
+      const double hr = dd[r] * xr[r] + cer * lor + cei * loi + er[r] * hir - ei[r] * hii;
+      const double hi = dd[r] * xi[r] + cer * loi - cei * lor + er[r] * hii + ei[r] * hir;
+      if constexpr (SRC) {
+        or_[r] = f * hr - or_[r] + (cr * lr[r] - ci * li[r]);
+        oi[r] = f * hi - oi[r] + (cr * li[r] + ci * lr[r]);
+      } else {
+        or_[r] = f * hr - or_[r];
+        oi[r] = f * hi - oi[r];
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ void load_vec(const double* v, long idx, double& re, double& im) {
+  const double2 x = reinterpret_cast<const double2*>(v)[idx];
+  re = x.x;
+  im = x.y;
+}
+__device__ __forceinline__ void store_vec(double* v, long idx, double re, double im) {
+  reinterpret_cast<double2*>(v)[idx] = make_double2(re, im);
+}
+
+template <int R, int W>
+__global__ __launch_bounds__(W * 64) void tridiag_adj_forward_kernel(TridiagAdjPass p) {
+  __shared__ double halo[2][4][2][W];
+  AdjWindow<R, W> win;
+  win.halo = halo;
+  win.parity = 0;
+  win.lane = threadIdx.x & 63;
+  win.wid = threadIdx.x >> 6;
+  const long col = blockIdx.x / p.nblk, r0 = (long)(blockIdx.x % p.nblk) * p.B;
+  const long n = p.n;
+  const long base = r0 - p.K + ((long)win.wid * 64 + win.lane) * R;
+  const long own_end = (r0 + p.B < n) ? r0 + p.B : n;
+  const double2* coef = reinterpret_cast<const double2*>(p.coef);
+  win.set(p, base);
+
+  double ar[R], ai[R], br[R], bi[R], yr[R], yi[R];  // P in a and b, the running sum Y
+  int l;
+  if (p.lo == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      ar[r] = ai[r] = 0.0;
+      if (i >= 0 && i < n) {
+        if (p.x == nullptr)
+          ar[r] = (i == col) ? 1.0 : 0.0;
+        else
+          load_state(p.x, p.x_rowmajor ? i * p.ncols + col : col * n + i, p.x_c64, ar[r], ai[r]);
+        if (p.x_store && i >= r0 && i < own_end) store_vec(p.x_store, col * n + i, ar[r], ai[r]);
+      }
+      br[r] = bi[r] = 0.0;
+    }
+    double nb[8];
+    win.exchange(ar, ai, ar, ai, nb);
+    win.template apply<false>(ar, ai, nb[0], nb[1], nb[4], nb[5], 1.0, br, bi, 0.0, 0.0, ar, ai);
+    const double2 c0 = coef[0], c1 = coef[1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      yr[r] = c0.x * ar[r] - c0.y * ai[r] + c1.x * br[r] - c1.y * bi[r];
+      yi[r] = c0.x * ai[r] + c0.y * ar[r] + c1.x * bi[r] + c1.y * br[r];
+    }
+    l = 1;
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      ar[r] = ai[r] = br[r] = bi[r] = yr[r] = yi[r] = 0.0;
+      if (i >= 0 && i < n) {
+        load_vec(p.in[0], col * n + i, ar[r], ai[r]);
+        load_vec(p.in[1], col * n + i, br[r], bi[r]);
+        load_vec(p.in[2], col * n + i, yr[r], yi[r]);
+      }
+    }
+    l = p.lo;
+  }
+  // P_l in b and P_{l-1} in a while `latest_b`, else the other way round
+  bool latest_b = true;
+  for (; l < p.hi; ++l) {
+    double nb[8];
+    const double2 c = coef[l + 1];
+    if (latest_b) {
+      win.exchange(br, bi, br, bi, nb);
+      win.template apply<false>(br, bi, nb[0], nb[1], nb[4], nb[5], 2.0, ar, ai, 0.0, 0.0, br, bi);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        yr[r] += c.x * ar[r] - c.y * ai[r];
+        yi[r] += c.x * ai[r] + c.y * ar[r];
+      }
+    } else {
+      win.exchange(ar, ai, ar, ai, nb);
+      win.template apply<false>(ar, ai, nb[0], nb[1], nb[4], nb[5], 2.0, br, bi, 0.0, 0.0, ar, ai);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        yr[r] += c.x * br[r] - c.y * bi[r];
+        yi[r] += c.x * bi[r] + c.y * br[r];
+      }
+    }
+    latest_b = !latest_b;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const long i = base + r;
+    if (i < r0 || i >= own_end) continue;
+    const long at = col * n + i;
+    const double pr = latest_b ? br[r] : ar[r], pi = latest_b ? bi[r] : ai[r];     // P_hi
+    const double qr = latest_b ? ar[r] : br[r], qi = latest_b ? ai[r] : bi[r];     // P_{hi-1}
+    if (p.hi == p.L) {
+      store_vec(p.plm1, at, qr, qi);
+      store_vec(p.pl, at, pr, pi);
+      if (p.xnext)
+        store_vec(p.xnext, at, p.phr * yr[r] - p.phi * yi[r], p.phr * yi[r] + p.phi * yr[r]);
+    } else {
+      store_vec(p.out[0], at, qr, qi);
+      store_vec(p.out[1], at, pr, pi);
+      store_vec(p.out[2], at, yr[r], yi[r]);
+    }
+  }
+}
+
+template <int R, int W>
+__global__ __launch_bounds__(W * 64) void tridiag_adj_reverse_kernel(TridiagAdjPass p) {
+  __shared__ double halo[2][4][2][W];
+  AdjWindow<R, W> win;
+  win.halo = halo;
+  win.parity = 0;
+  win.lane = threadIdx.x & 63;
+  win.wid = threadIdx.x >> 6;
+  const long col = blockIdx.x / p.nblk, r0 = (long)(blockIdx.x % p.nblk) * p.B;
+  const long n = p.n;
+  const long base = r0 - p.K + ((long)win.wid * 64 + win.lane) * R;
+  const long own_end = (r0 + p.B < n) ? r0 + p.B : n;
+  const double2* coef = reinterpret_cast<const double2*>(p.coef);
+  win.set(p, base);
+
+  double lr[R], li[R];                // Lambda
+  double ar[R], ai[R], br[R], bi[R];  // two P terms
+  double qr[R], qi[R], sr[R], si[R];  // two Pbar terms
+  double own[R];                      // 1 on the rows this workgroup owns
+  const bool first = (p.hi == p.L - 1);
+  const double2 cL = coef[p.L];
+  const double dLr = p.phr * cL.x - p.phi * cL.y, dLi = -(p.phr * cL.y + p.phi * cL.x);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const long i = base + r;
+    own[r] = (i >= r0 && i < own_end) ? 1.0 : 0.0;
+    lr[r] = li[r] = ar[r] = ai[r] = br[r] = bi[r] = qr[r] = qi[r] = sr[r] = si[r] = 0.0;
+    if (i >= 0 && i < n) {
+      load_state(p.lam, p.lam_rowmajor ? i * p.ncols + col : col * n + i, p.lam_c64, lr[r], li[r]);
+      if (first) {  // P_{L-1}, P_L; Pbar_L = d_L Lambda, Pbar_{L+1} = 0
+        load_vec(p.seg_plm1, col * n + i, ar[r], ai[r]);
+        load_vec(p.seg_pl, col * n + i, br[r], bi[r]);
+        qr[r] = dLr * lr[r] - dLi * li[r];
+        qi[r] = dLr * li[r] + dLi * lr[r];
+      } else {
+        load_vec(p.in[0], col * n + i, ar[r], ai[r]);
+        load_vec(p.in[1], col * n + i, br[r], bi[r]);
+        load_vec(p.in[2], col * n + i, qr[r], qi[r]);
+        load_vec(p.in[3], col * n + i, sr[r], si[r]);
+      }
+    }
+  }
+
+  double gv = 0.0, gk = 0.0;
+  // One downward term l with P_l in x, P_{l+1} in z (-> P_{l-1}), Pbar_{l+1} in
+  // pb and Pbar_{l+2} in o (-> Pbar_l). AB: x = a, z = b, pb = q, o = s; else
+  // the pairs swapped. Written out per assignment (no array pointers), so that
+  // every array stays in registers.
+#define FQ_DOWN(XR, XI, ZR, ZI, PR, PI, OR, OI, l_)                                           \
+  {                                                                                          \
+    const int lt = (l_);                                                                      \
+    double nb[8];                                                                            \
+    win.exchange(XR, XI, PR, PI, nb);                                                        \
+    const double w = (lt >= 1) ? 2.0 : 1.0;                                                   \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) {                                          \
+      gv += own[r] * w * win.vv[r] * (PR[r] * XR[r] + PI[r] * XI[r]);                        \
+      if (p.any_b) {                                                                         \
+        const double lor = (r == 0) ? nb[0] : XR[r - 1], loi = (r == 0) ? nb[1] : XI[r - 1]; \
+        const double hir = (r == R - 1) ? nb[4] : XR[r + 1],                                 \
+                     hii = (r == R - 1) ? nb[5] : XI[r + 1];                                 \
+        const double ckr = (r == 0) ? win.kmr : win.kr[r - 1],                               \
+                     cki = (r == 0) ? win.kmi : win.ki[r - 1];                               \
+        const double tr = ckr * lor + cki * loi + win.kr[r] * hir - win.ki[r] * hii;         \
+        const double ti = ckr * loi - cki * lor + win.kr[r] * hii + win.ki[r] * hir;         \
+        gk += own[r] * w * (PR[r] * tr + PI[r] * ti);                                        \
+      }                                                                                      \
+    }                                                                                        \
+    const double2 cl = coef[lt];                                                              \
+    const double dr = p.phr * cl.x - p.phi * cl.y, di = -(p.phr * cl.y + p.phi * cl.x);      \
+    win.template apply<true>(PR, PI, nb[2], nb[3], nb[6], nb[7], w, OR, OI, dr, di, lr, li); \
+    if (lt == 1) {                                                                            \
+      _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
+        const long i = base + r;                                                             \
+        ZR[r] = ZI[r] = 0.0;                                                                 \
+        if (i >= 0 && i < n) load_vec(p.p0, col * n + i, ZR[r], ZI[r]);                      \
+      }                                                                                      \
+    } else if (lt >= 2) {                                                                     \
+      win.template apply<false>(XR, XI, nb[0], nb[1], nb[4], nb[5], 2.0, ZR, ZI, 0.0, 0.0,   \
+                                lr, li);                                                     \
+    }                                                                                        \
+  }
+  // Pbar_l = w Ht Pbar_{l+1} - Pbar_{l+2} + conj(phase c_l) Lambda, w = 2 (l >= 1) or 1;
+  // P_{l-1} = 2 Ht P_l - P_{l+1}, P_0 read back; the contractions with Hmod
+  // (diagonal) and K (K_{i,i+1} = k_i, (K x)_i = conj(k_{i-1}) x_{i-1} + k_i x_{i+1})
+  int l = p.hi;
+  for (; l - 1 >= p.lo; l -= 2) {
+    FQ_DOWN(ar, ai, br, bi, qr, qi, sr, si, l)      // P_l in a, P_{l-1} -> b; Pbar_l -> s
+    FQ_DOWN(br, bi, ar, ai, sr, si, qr, qi, l - 1)  // P_{l-1} in b; Pbar_{l-1} -> q
+  }
+  const bool odd = (l == p.lo);
+  if (odd) FQ_DOWN(ar, ai, br, bi, qr, qi, sr, si, l)
+#undef FQ_DOWN
+  // even: P_{lo-1} a, P_lo b, Pbar_lo q, Pbar_{lo+1} s; odd: the pairs swapped.
+  // (Separate branches rather than selects between arrays, which would take
+  // their addresses and move them out of registers.)
+#define FQ_STORE(P1R, P1I, P2R, P2I, Q1R, Q1I, Q2R, Q2I)                        \
+  _Pragma("unroll") for (int r = 0; r < R; ++r) {                               \
+    const long i = base + r;                                                    \
+    if (i < r0 || i >= own_end) continue;                                       \
+    const long at = col * n + i;                                                \
+    if (p.lo == 0) {                                                            \
+      store_vec(p.lam_out, at, Q1R[r], Q1I[r]);                                 \
+    } else {                                                                    \
+      store_vec(p.out[0], at, P1R[r], P1I[r]);                                  \
+      store_vec(p.out[1], at, P2R[r], P2I[r]);                                  \
+      store_vec(p.out[2], at, Q1R[r], Q1I[r]);                                  \
+      store_vec(p.out[3], at, Q2R[r], Q2I[r]);                                  \
+    }                                                                           \
+  }
+  if (odd) {
+    FQ_STORE(br, bi, ar, ai, sr, si, qr, qi)
+  } else {
+    FQ_STORE(ar, ai, br, bi, qr, qi, sr, si)
+  }
+#undef FQ_STORE
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    gv += __shfl_xor(gv, o);
+    gk += __shfl_xor(gk, o);
+  }
+  if (win.lane == 0) {
+    atomicAdd(p.grad, gv);
+    if (p.any_b) atomicAdd(p.grad + 1, gk);
+  }
+}
+
+// 8 waves x 64 lanes x 4 rows: 2048-row windows.
+constexpr int kAdjR = 4, kAdjW = 8;
+
 }  // namespace
 
 // 16 rows per lane and up to 4 waves per part (512 threads, <= 256 VGPRs).
@@ -998,6 +1350,33 @@ hipError_t launch_tridiag_adjoint(const TridiagAdjJob& job, hipStream_t s) {
   if (job.n <= 1024) return launch_adj_r<4, 4>(job, s);
   if (job.n <= tridiag_adjoint_max_n()) return launch_adj_r<4, 8>(job, s);
   return hipErrorInvalidValue;
+}
+
+long tridiag_adj_window_rows() { return (long)kAdjW * 64 * kAdjR; }
+
+static hipError_t check_adj_pass(const TridiagAdjPass& p) {
+  const long win = tridiag_adj_window_rows();
+  if (p.n < 1 || p.ncols < 1 || p.K < 1 || p.B < 1 || p.B + 2L * p.K != win) return hipErrorInvalidValue;
+  if ((long)p.nblk * p.B < p.n || (long)(p.nblk - 1) * p.B >= p.n) return hipErrorInvalidValue;
+  const long grid = p.ncols * p.nblk;
+  if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+hipError_t launch_tridiag_adj_forward(const TridiagAdjPass& p, hipStream_t s) {
+  if (hipError_t e = check_adj_pass(p); e != hipSuccess) return e;
+  if (p.lo < 0 || p.hi <= p.lo || p.hi > p.L || p.hi - p.lo > p.K) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((tridiag_adj_forward_kernel<kAdjR, kAdjW>), dim3((unsigned)(p.ncols * p.nblk)),
+                     dim3(kAdjW * 64), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag_adj_reverse(const TridiagAdjPass& p, hipStream_t s) {
+  if (hipError_t e = check_adj_pass(p); e != hipSuccess) return e;
+  if (p.lo < 0 || p.hi < p.lo || p.hi > p.L - 1 || p.hi - p.lo + 1 > p.K) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((tridiag_adj_reverse_kernel<kAdjR, kAdjW>), dim3((unsigned)(p.ncols * p.nblk)),
+                     dim3(kAdjW * 64), 0, s, p);
+  return hipGetLastError();
 }
 
 }  // namespace fq

@@ -215,13 +215,20 @@ def test_nonfinite_drive_rejected():
 def test_tridiag_restrictions():
     st, _ = _ws(_tridiag(), _params(precision=1))
     assert st == _abi.FQ_ERR_UNSUPPORTED
-    # gradient tape: per-column reverse sweep up to 2048 rows
+    # gradient tape: per-column reverse sweep up to 2048 rows, streamed passes
+    # beyond (ten more n x n complex vectors for their carried state)
     st, b0 = _ws(_tridiag(2048), _params())
     st1, b1 = _ws(_tridiag(2048), _params(checkpoint_every=4))
     assert st == st1 == _abi.FQ_OK and b1 > b0
-    st, _ = _ws(_tridiag(2049), _params(checkpoint_every=4))
+    st2, b2 = _ws(_tridiag(2049), _params(checkpoint_every=4))
+    assert st2 == _abi.FQ_OK and b2 >= b1 + 10 * 16 * 2049 * 2049
+    # beyond one workgroup's column the forward build keeps its checkpoints in
+    # the state blocks' type: complex128 only
+    st, _ = _ws(_tridiag(5000), _params(checkpoint_every=4, dtype=_abi.FQ_C64))
     assert st == _abi.FQ_ERR_UNSUPPORTED
-    assert "2048" in _abi.lib().fq_last_error().decode()
+    assert "complex128" in _abi.lib().fq_last_error().decode()
+    st, _ = _ws(_tridiag(4096), _params(checkpoint_every=4, dtype=_abi.FQ_C64))
+    assert st == _abi.FQ_OK
     # columns longer than one workgroup: two streamed states of n x n doubles
     st, b = _ws(_tridiag(5000), _params())
     assert st == _abi.FQ_OK and b >= 2 * 8 * 8 * 5000 * 5000

@@ -285,3 +285,94 @@ def test_tridiag_gradient_complex64_ubar(fl):
     err = np.max(np.abs(g1 - g2)) / np.max(np.abs(g1))
     _say("c64 ubar rel", err)
     assert err < 1e-5
+
+
+# ---- streamed reverse sweep (columns longer than one workgroup holds) --------------------------
+
+def _dimer_kw(d, e, v, nodes, T, M, margin):
+    a, b = orc.magnus4_weights(nodes, T / M)
+    lo, hi = orc.tridiag_cover(d, e, v, a, b)
+    lo, hi = lo - margin, hi + margin
+    L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-13)
+    return dict(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, e_min=lo, e_max=hi, L=L)
+
+
+@pytest.mark.parametrize("nb,M,ckpt,smooth", [(299, 10, 3, False), (299, 8, 3, True),
+                                              (1999, 6, 4, False)])
+def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M, ckpt, smooth):
+    """The streamed reverse sweep (selected for n <= 2048 by the environment
+    switch) against the per-column sweep on the same problem: one block per
+    column (n = 300) and two (n = 2000, blocks of 1792 owned rows), with and
+    without the K contraction (b_k != 0 for a smooth drive)."""
+    _say("streamed vs per-column sweep", nb + 1, M, ckpt, smooth)
+    rng = np.random.default_rng(400 + nb)
+    if smooth:
+        d, e, v = dimer_tridiag(nb, 1.0, 0.3)
+        T = 2.0
+        nodes = drive_cos(orc.node_times(T, M), 0.5, 1.5, 1.0)
+    else:
+        d, e, v = dimer_tridiag(nb, 1.0, 0.01)
+        T = 2.0
+        f = rng.uniform(-1, 1, M)
+        nodes = np.stack([f, f], 1)
+    kw = _dimer_kw(d, e, v, nodes, T, M, 0.0)
+    W = haar_unitary(nb + 1, rng)
+    per_col = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, **kw)
+    monkeypatch.setenv("FQ_TRIDIAG_STREAMED_ADJOINT", "1")
+    streamed = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, **kw)
+    monkeypatch.delenv("FQ_TRIDIAG_STREAMED_ADJOINT")
+    U = per_col.build_ut().cpu().numpy()
+    streamed.build_ut()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g1 = per_col.grad(Ubar)
+    g2 = streamed.grad(Ubar)
+    err = np.max(np.abs(g1 - g2)) / np.max(np.abs(g1))
+    _say("L", kw["L"], "max|g|", np.max(np.abs(g1)), "rel diff", err)
+    assert err < 1e-10
+    if smooth:
+        assert np.max(np.abs(g2[:, 0] - g2[:, 1])) > 1e-6 * np.max(np.abs(g2))
+
+
+@pytest.mark.parametrize("nb,M,ckpt", [(2499, 6, 2), (4499, 6, 2)])
+def test_tridiag_long_column_gradient_against_fd(fl, nb, M, ckpt):
+    """Columns beyond the per-column sweep (n > 2048; for n > 4096 the forward
+    build streams too and records its checkpoints through the snapshot store):
+    the streamed reverse sweep against central differences (h = 1e-5) of the
+    library's own builds on three amplitudes. Loss 1 - |Tr(W^dagger U)|^2/N^2
+    with the target W = U_T of a slightly perturbed drive, so that the loss is
+    well below one. A unit of drive turns the phases by up to h_t |V| ~ 20 rad
+    here (|V| ~ N), which sets the difference step."""
+    import torch
+    T = 0.05
+    d, e, v = dimer_tridiag(nb, 1.0, 0.01)
+    n = nb + 1
+    rng = np.random.default_rng(500 + nb)
+    f = rng.uniform(-1, 1, M)
+    fw = f + 0.02 * rng.uniform(-1, 1, M)
+    kw = _dimer_kw(d, e, v, np.stack([f, f], 1), T, M, 10.0)
+    _say("long-column gradient", n, "M", M, "L", kw["L"])
+    sys_kw = {k: kw[k] for k in ("h0_diag", "h0_off", "hmod_diag", "T", "M")}
+    W = fl.FloquetContext(f_nodes=np.stack([fw, fw], 1), **sys_kw).build_ut()
+    ctx = fl.FloquetContext(f_nodes=np.stack([f, f], 1), checkpoint_every=ckpt, **kw)
+    U = ctx.build_ut()
+
+    def loss_of(Ut):
+        tau = torch.sum(torch.conj(W) * Ut).item()
+        return 1.0 - abs(tau) ** 2 / n ** 2, tau
+
+    loss, tau = loss_of(U)
+    ubar = (-2.0 / n ** 2) * tau * W
+    g = ctx.grad(ubar).sum(axis=1)
+    _say("loss", loss, "max|g|", np.max(np.abs(g)))
+    eps = 1e-5
+    for k in (0, M // 2, M - 1):
+        vals = []
+        for sgn in (+1, -1):
+            ff = f.copy()
+            ff[k] += sgn * eps
+            c = fl.FloquetContext(f_nodes=np.stack([ff, ff], 1), **kw)
+            vals.append(loss_of(c.build_ut())[0])
+            del c
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        _say("k", k, "adjoint", g[k], "fd", fd)
+        assert abs(g[k] - fd) <= 1e-5 * abs(fd) + 1e-9

@@ -153,6 +153,18 @@ def workload(name: str, n: Optional[int] = None, M: Optional[int] = None) -> Wor
         return Workload(name, nb + 1, "tridiag", two_pi, M or 500,
                         lambda t: drive_cos(t, 0.5, 1.5, 1.0),
                         arrays={"h0_diag": d, "h0_off": e, "v_diag": vd})
+    if name == "adjointdimer10000":
+        # the 9999-boson dimer of dimer10000 under a piecewise-constant drive of
+        # m amplitudes f_j ~ U(-1, 1); the loss targets U_T of the nearby drive
+        # f_j + 0.02 u_j (u_j ~ U(-1, 1)), a reachable target gate
+        nb = (n - 1) if n else 9999
+        m = M or 256
+        d, e, vd = dimer_tridiag(nb, 1.0, 0.01)
+        rng = np.random.default_rng(_seed(5))
+        f = piecewise_amplitudes(m, rng)
+        f_target = f + 0.02 * rng.uniform(-1.0, 1.0, m)
+        return Workload(name, nb + 1, "tridiag", two_pi, m, None, amplitudes=f,
+                        arrays={"h0_diag": d, "h0_off": e, "v_diag": vd, "f_target": f_target})
     if name == "gue10000":
         n = n or 10000
         h0, v, _ = random_matrix_model(n, _seed(4))
@@ -162,4 +174,4 @@ def workload(name: str, n: Optional[int] = None, M: Optional[int] = None) -> Wor
 
 
 WORKLOADS = ("gue64", "dimer1000", "gue4096", "adjoint1024", "dimer10000", "gue10000",
-             "gue4096m6")
+             "gue4096m6", "adjointdimer10000")
