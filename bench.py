@@ -39,11 +39,11 @@ TRIDIAG_FLOPS_PER_ELEMENT_TERM = 26
 #: as streamed passes with ghost rows
 TRIDIAG_RESIDENT_MAX_N = 4096
 
-#: algorithmic real flops per element and term of the streamed reverse pass:
-#: Pbar_l = w Ht Pbar_{l+1} - Pbar_{l+2} + d_l Lambda (couplings 12, diagonal 2,
-#: adds 4, scale and subtract 4, complex source 8), P_{l-1} = 2 Ht P_l - P_{l+1}
-#: (22) and the contraction w v_i Re(conj(Pbar) P) (6)
-TRIDIAG_ADJ_REV_FLOPS_PER_ELEMENT_TERM = 58
+#: algorithmic real flops per element and term of the streamed reverse pass in
+#: the gauge frame (real couplings): Pbar_l = w G Pbar_{l+1} - Pbar_{l+2} + d_l Lambda
+#: (G on a complex value 12, scale and subtract 4, complex source 8),
+#: P_{l-1} = 2 G P_l - P_{l+1} (16) and the contraction w v_i Re(conj(Pbar) P) (6)
+TRIDIAG_ADJ_REV_FLOPS_PER_ELEMENT_TERM = 46
 
 WORKLOAD_TEXT = {
     "gue4096": "random-matrix model N=4096 (GUE H0, V), f=cos t, T=2pi, M=200 Magnus-4 steps, "
@@ -594,7 +594,7 @@ def main():
                         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VECTOR_TFLOPS, 4),
                         "traffic": None, "traffic_detail": None,
                         "kernel": "tridiag_adj_reverse_kernel<4,8> (reverse passes of up to 128 "
-                                  "terms; 1792 owned + 2 x 128 ghost rows per workgroup, complex form)",
+                                  "terms; 1792 owned + 2 x 128 ghost rows per workgroup, real gauge frame)",
                         "avg_launch_ms": round(ms_rev, 4), "launches_timed": n_rev,
                         "algorithmic_flops_per_launch": flops_rev}
                 extra["gradient"]["segment_recompute_pass"] = {

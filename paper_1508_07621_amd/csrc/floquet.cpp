@@ -1160,9 +1160,10 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
 // chain rule to the node samples as in the dense case.
 // The reverse sweep in streamed passes (columns longer than one workgroup
 // holds, or on request): per checkpoint segment, last first, the steps are
-// recomputed forward from the segment's checkpoint, keeping X_k, P_{L-1} and
-// P_L of every step (col-major vectors in the segment buffer); then each step
-// is reversed in passes of at most K terms, Lambda passing from step to step.
+// recomputed forward from the segment's checkpoint, keeping X_k and the
+// gauge-frame P_{L-1}, P_L of every step (col-major vectors in the segment
+// buffer); then each step is reversed in passes of at most K terms, Lambda
+// passing from step to step in the plain frame.
 fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const int M = c->M, L = c->L, ckpt = c->ckpt;
   const long n = c->n;
@@ -1216,6 +1217,7 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
     for (int k = k0; k < k1; ++k) {  // forward recompute of the segment
       p.a = c->a[k];
       p.b = c->b[k];
+      p.gauge = c->d_gauge + 2 * (size_t)k * (size_t)n;
       for (int lo = 0; lo < L; lo += K) {
         p.lo = lo;
         p.hi = std::min(lo + K, L);
@@ -1248,6 +1250,7 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
     for (int k = k1 - 1; k >= k0; --k) {  // reverse
       p.a = c->a[k];
       p.b = c->b[k];
+      p.gauge = c->d_gauge + 2 * (size_t)k * (size_t)n;
       p.lam = lam_src;
       p.lam_rowmajor = lam_rows;
       p.lam_c64 = lam_c64;

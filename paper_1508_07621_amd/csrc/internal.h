@@ -271,6 +271,7 @@ struct TridiagAdjPass {
   const double* h0_off;      // complex interleaved (n-1)
   const double* v_diag;
   double a, b, beta, inv_dE, phr, phi;  // step scalars
+  const double* gauge;       // unit gauge factors w_i of the step (n complex): Ht = D G D^+
   const double* coef;        // c_l complex interleaved
   int any_b;                 // reverse: accumulate the K contraction
   // forward pass
@@ -288,7 +289,8 @@ struct TridiagAdjPass {
   const double* seg_pl;      // hi == L - 1: P_L
   double* lam_out;           // lo == 0: Pbar_0
   double* grad;              // the step's accumulators: Re sum w_l <Pbar_{l+1}, D P_l>, D = Hmod, K
-  // state carried between passes: forward (P_{l-1}, P_l, Y), reverse (P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2})
+  // state carried between passes, in the gauge frame of the step (terms of G):
+  // forward (P_{l-1}, P_l, Y), reverse (P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2})
   const double* in[4];
   double* out[4];
 };

@@ -885,43 +885,51 @@ hipError_t launch_adj_r(const TridiagAdjJob& job, hipStream_t s) {
 //   reverse: terms l = hi .. lo of the adjoint recurrence with P regenerated
 //     downwards, the contractions over the owned rows added to the step's two
 //     accumulators; at lo == 0 it stores Pbar_0, the Lambda of the step before.
+// Both work in the gauge frame of the step, Ht = D G D^+ with D = diag(w) and
+// G real symmetric tridiagonal (diagonal d_i, couplings g_i = |Ht[i][i+1]|), so
+// every term applies real couplings: the terms are those of G on D^+ X, the
+// step's output is phase D Y, Lambda enters as D^+ Lambda and leaves as
+// D Pbar_0. Hmod is diagonal and unchanged by D; K becomes D^+ K D, whose
+// couplings conj(w_i) k_i w_{i+1} stay complex.
 
 // Per-window operator rows of one step and the neighbour exchange of the window.
 template <int R, int W>
 struct AdjWindow {
-  double dd[R], er[R], ei[R], kr[R], ki[R], vv[R];
-  double emr, emi, kmr, kmi;  // couplings from row base - 1
+  double dd[R], gg[R], kr[R], ki[R], vv[R];  // G rows, D^+ K D couplings, Hmod
+  double gm, kmr, kmi;                       // couplings from row base - 1
   double (*halo)[4][2][W];
   int parity, lane, wid;
 
   __device__ __forceinline__ void set(const TridiagAdjPass& p, long base) {
     const double2* h0o = reinterpret_cast<const double2*>(p.h0_off);
+    const double2* w = reinterpret_cast<const double2*>(p.gauge);
+    // coupling g_i = |h_i| sqrt(1 + q^2) / dE and, with b != 0, conj(w_i) k_i w_{i+1}
+    // with k_i = -i h_i (v_{i+1} - v_i)
+    auto coupling = [&](long i, double& g, double& tr, double& ti) {
+      const double2 h = h0o[i];
+      const double dv = p.v_diag[i + 1] - p.v_diag[i], q = p.b * dv;
+      g = sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * p.inv_dE;
+      tr = ti = 0.0;
+      if (p.any_b) {
+        const double k_r = h.y * dv, k_i = -h.x * dv;
+        const double2 w0 = w[i], w1 = w[i + 1];
+        const double ur = k_r * w1.x - k_i * w1.y, ui = k_r * w1.y + k_i * w1.x;  // k w_{i+1}
+        tr = w0.x * ur + w0.y * ui;                                               // conj(w_i) (.)
+        ti = w0.x * ui - w0.y * ur;
+      }
+    };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const long i = base + r;
-      dd[r] = er[r] = ei[r] = kr[r] = ki[r] = vv[r] = 0.0;
+      dd[r] = gg[r] = kr[r] = ki[r] = vv[r] = 0.0;
       if (i >= 0 && i < p.n) {
         vv[r] = p.v_diag[i];
         dd[r] = (p.h0_diag[i] + p.a * vv[r] - p.beta) * p.inv_dE;
-        if (i + 1 < p.n) {
-          const double2 h = h0o[i];
-          const double dv = p.v_diag[i + 1] - vv[r], q = p.b * dv;
-          er[r] = (h.x + h.y * q) * p.inv_dE;  // h (1 - i q) / dE
-          ei[r] = (h.y - h.x * q) * p.inv_dE;
-          kr[r] = h.y * dv;                    // K = -i h dv
-          ki[r] = -h.x * dv;
-        }
+        if (i + 1 < p.n) coupling(i, gg[r], kr[r], ki[r]);
       }
     }
-    emr = emi = kmr = kmi = 0.0;
-    if (base >= 1 && base < p.n) {
-      const double2 h = h0o[base - 1];
-      const double dv = p.v_diag[base] - p.v_diag[base - 1], q = p.b * dv;
-      emr = (h.x + h.y * q) * p.inv_dE;
-      emi = (h.y - h.x * q) * p.inv_dE;
-      kmr = h.y * dv;
-      kmi = -h.x * dv;
-    }
+    gm = kmr = kmi = 0.0;
+    if (base >= 1 && base < p.n) coupling(base - 1, gm, kmr, kmi);
   }
 
   // Neighbour rows of two complex vectors: base - 1 (nb[0..3]) and base + R
@@ -960,20 +968,20 @@ struct AdjWindow {
     parity ^= 1;
   }
 
-  // out = f Ht x - out (+ (cr + i ci) lam with SRC)
+  // out = f G x - out (+ (cr + i ci) lam with SRC)
   template <bool SRC>
   __device__ __forceinline__ void apply(const double* xr, const double* xi, double ur, double ui,
-                                        double dr_,
-                        double di_, double f, double* or_, double* oi, double cr, double ci,
-                        const double* lr, const double* li) const {
+                                        double dr_, double di_, double f, double* or_, double* oi,
+                                        double cr, double ci, const double* lr,
+                                        const double* li) const {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double lor = (r == 0) ? ur : xr[r - 1], loi = (r == 0) ? ui : xi[r - 1];
       const double hir = (r == R - 1) ? dr_ : xr[r + 1], hii = (r == R - 1) ? di_ : xi[r + 1];
-      const double cer = (r == 0) ? emr : er[r - 1], cei = (r == 0) ? emi : ei[r - 1];
-      // conj(e_{i-1}) x_{i-1} + e_i x_{i+1} + d_i x_i
-      const double hr = dd[r] * xr[r] + cer * lor + cei * loi + er[r] * hir - ei[r] * hii;
-      const double hi = dd[r] * xi[r] + cer * loi - cei * lor + er[r] * hii + ei[r] * hir;
+      const double gl = (r == 0) ? gm : gg[r - 1];
+      // g_{i-1} x_{i-1} + d_i x_i + g_i x_{i+1}
+      const double hr = fma(dd[r], xr[r], fma(gl, lor, gg[r] * hir));
+      const double hi = fma(dd[r], xi[r], fma(gl, loi, gg[r] * hii));
       if constexpr (SRC) {
         or_[r] = f * hr - or_[r] + (cr * lr[r] - ci * li[r]);
         oi[r] = f * hi - oi[r] + (cr * li[r] + ci * lr[r]);
@@ -984,6 +992,18 @@ struct AdjWindow {
     }
   }
 };
+
+// v times conj(w) (to the gauge frame) or w (back to the plain frame).
+__device__ __forceinline__ void gauge_in(const double2 w, double& re, double& im) {
+  const double r = w.x * re + w.y * im, i = w.x * im - w.y * re;
+  re = r;
+  im = i;
+}
+__device__ __forceinline__ void gauge_out(const double2 w, double& re, double& im) {
+  const double r = w.x * re - w.y * im, i = w.x * im + w.y * re;
+  re = r;
+  im = i;
+}
 
 __device__ __forceinline__ void load_vec(const double* v, long idx, double& re, double& im) {
   const double2 x = reinterpret_cast<const double2*>(v)[idx];
@@ -1007,6 +1027,7 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_forward_kernel(TridiagAdjP
   const long base = r0 - p.K + ((long)win.wid * 64 + win.lane) * R;
   const long own_end = (r0 + p.B < n) ? r0 + p.B : n;
   const double2* coef = reinterpret_cast<const double2*>(p.coef);
+  const double2* gw = reinterpret_cast<const double2*>(p.gauge);
   win.set(p, base);
 
   double ar[R], ai[R], br[R], bi[R], yr[R], yi[R];  // P in a and b, the running sum Y
@@ -1022,6 +1043,7 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_forward_kernel(TridiagAdjP
         else
           load_state(p.x, p.x_rowmajor ? i * p.ncols + col : col * n + i, p.x_c64, ar[r], ai[r]);
         if (p.x_store && i >= r0 && i < own_end) store_vec(p.x_store, col * n + i, ar[r], ai[r]);
+        gauge_in(gw[i], ar[r], ai[r]);  // P_0 = D^+ X
       }
       br[r] = bi[r] = 0.0;
     }
@@ -1082,8 +1104,11 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_forward_kernel(TridiagAdjP
     if (p.hi == p.L) {
       store_vec(p.plm1, at, qr, qi);
       store_vec(p.pl, at, pr, pi);
-      if (p.xnext)
-        store_vec(p.xnext, at, p.phr * yr[r] - p.phi * yi[r], p.phr * yi[r] + p.phi * yr[r]);
+      if (p.xnext) {  // X_{k+1} = phase D Y
+        double xr = p.phr * yr[r] - p.phi * yi[r], xi = p.phr * yi[r] + p.phi * yr[r];
+        gauge_out(gw[i], xr, xi);
+        store_vec(p.xnext, at, xr, xi);
+      }
     } else {
       store_vec(p.out[0], at, qr, qi);
       store_vec(p.out[1], at, pr, pi);
@@ -1105,6 +1130,7 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_reverse_kernel(TridiagAdjP
   const long base = r0 - p.K + ((long)win.wid * 64 + win.lane) * R;
   const long own_end = (r0 + p.B < n) ? r0 + p.B : n;
   const double2* coef = reinterpret_cast<const double2*>(p.coef);
+  const double2* gw = reinterpret_cast<const double2*>(p.gauge);
   win.set(p, base);
 
   double lr[R], li[R];                // Lambda
@@ -1121,6 +1147,7 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_reverse_kernel(TridiagAdjP
     lr[r] = li[r] = ar[r] = ai[r] = br[r] = bi[r] = qr[r] = qi[r] = sr[r] = si[r] = 0.0;
     if (i >= 0 && i < n) {
       load_state(p.lam, p.lam_rowmajor ? i * p.ncols + col : col * n + i, p.lam_c64, lr[r], li[r]);
+      gauge_in(gw[i], lr[r], li[r]);  // D^+ Lambda
       if (first) {  // P_{L-1}, P_L; Pbar_L = d_L Lambda, Pbar_{L+1} = 0
         load_vec(p.seg_plm1, col * n + i, ar[r], ai[r]);
         load_vec(p.seg_pl, col * n + i, br[r], bi[r]);
@@ -1166,7 +1193,10 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_reverse_kernel(TridiagAdjP
       _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
         const long i = base + r;                                                             \
         ZR[r] = ZI[r] = 0.0;                                                                 \
-        if (i >= 0 && i < n) load_vec(p.p0, col * n + i, ZR[r], ZI[r]);                      \
+        if (i >= 0 && i < n) {                                                               \
+          load_vec(p.p0, col * n + i, ZR[r], ZI[r]);                                         \
+          gauge_in(gw[i], ZR[r], ZI[r]);                                                     \
+        }                                                                                    \
       }                                                                                      \
     } else if (lt >= 2) {                                                                     \
       win.template apply<false>(XR, XI, nb[0], nb[1], nb[4], nb[5], 2.0, ZR, ZI, 0.0, 0.0,   \
@@ -1193,7 +1223,9 @@ __global__ __launch_bounds__(W * 64) void tridiag_adj_reverse_kernel(TridiagAdjP
     if (i < r0 || i >= own_end) continue;                                       \
     const long at = col * n + i;                                                \
     if (p.lo == 0) {                                                            \
-      store_vec(p.lam_out, at, Q1R[r], Q1I[r]);                                 \
+      double xr = Q1R[r], xi = Q1I[r];                                          \
+      gauge_out(gw[i], xr, xi);                                                 \
+      store_vec(p.lam_out, at, xr, xi);                                         \
     } else {                                                                    \
       store_vec(p.out[0], at, P1R[r], P1I[r]);                                  \
       store_vec(p.out[1], at, P2R[r], P2I[r]);                                  \
