@@ -229,6 +229,21 @@ def test_tridiag_restrictions():
     assert "complex128" in _abi.lib().fq_last_error().decode()
     st, _ = _ws(_tridiag(4096), _params(checkpoint_every=4, dtype=_abi.FQ_C64))
     assert st == _abi.FQ_OK
+
+
+def test_streamed_adjoint_switch_sizes_the_workspace(monkeypatch):
+    """FQ_TRIDIAG_STREAMED_ADJOINT=1 selects the streamed reverse sweep for
+    short columns too: the workspace then holds its ten carried vectors."""
+    st0, b0 = _ws(_tridiag(300), _params(checkpoint_every=4))
+    monkeypatch.setenv("FQ_TRIDIAG_STREAMED_ADJOINT", "1")
+    st1, b1 = _ws(_tridiag(300), _params(checkpoint_every=4))
+    st2, b2 = _ws(_tridiag(300), _params())            # no tape: no gradient buffers
+    monkeypatch.setenv("FQ_TRIDIAG_STREAMED_ADJOINT", "0")
+    st3, b3 = _ws(_tridiag(300), _params(checkpoint_every=4))
+    assert st0 == st1 == st2 == st3 == _abi.FQ_OK
+    assert b1 >= b0 + 10 * 16 * 300 * 300
+    assert b3 == b0
+    assert b2 < b0
     # columns longer than one workgroup: two streamed states of n x n doubles
     st, b = _ws(_tridiag(5000), _params())
     assert st == _abi.FQ_OK and b >= 2 * 8 * 8 * 5000 * 5000
