@@ -297,14 +297,18 @@ def _dimer_kw(d, e, v, nodes, T, M, margin):
     return dict(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, e_min=lo, e_max=hi, L=L)
 
 
-@pytest.mark.parametrize("nb,M,ckpt,smooth", [(299, 10, 3, False), (299, 8, 3, True),
-                                              (1999, 6, 4, False)])
-def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M, ckpt, smooth):
+@pytest.mark.parametrize("nb,M,ckpt,smooth,dtype", [(299, 10, 3, False, "complex128"),
+                                                    (299, 8, 3, True, "complex128"),
+                                                    (1999, 6, 4, False, "complex128"),
+                                                    (299, 7, 2, False, "complex64")])
+def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M, ckpt, smooth,
+                                                         dtype):
     """The streamed reverse sweep (selected for n <= 2048 by the environment
     switch) against the per-column sweep on the same problem: one block per
     column (n = 300) and two (n = 2000, blocks of 1792 owned rows), with and
-    without the K contraction (b_k != 0 for a smooth drive)."""
-    _say("streamed vs per-column sweep", nb + 1, M, ckpt, smooth)
+    without the K contraction (b_k != 0 for a smooth drive), and with
+    complex64 state blocks (U_bar read as complex64)."""
+    _say("streamed vs per-column sweep", nb + 1, M, ckpt, smooth, dtype)
     rng = np.random.default_rng(400 + nb)
     if smooth:
         d, e, v = dimer_tridiag(nb, 1.0, 0.3)
@@ -317,13 +321,14 @@ def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M,
         nodes = np.stack([f, f], 1)
     kw = _dimer_kw(d, e, v, nodes, T, M, 0.0)
     W = haar_unitary(nb + 1, rng)
-    per_col = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, **kw)
+    per_col = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, dtype=dtype, **kw)
     monkeypatch.setenv("FQ_TRIDIAG_STREAMED_ADJOINT", "1")
-    streamed = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, **kw)
+    streamed = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, dtype=dtype, **kw)
     monkeypatch.delenv("FQ_TRIDIAG_STREAMED_ADJOINT")
     U = per_col.build_ut().cpu().numpy()
     streamed.build_ut()
-    _, Ubar = _trace_loss_and_bar(U, W)
+    _, Ubar = _trace_loss_and_bar(U.astype(np.complex128), W)
+    Ubar = Ubar.astype(U.dtype)
     g1 = per_col.grad(Ubar)
     g2 = streamed.grad(Ubar)
     err = np.max(np.abs(g1 - g2)) / np.max(np.abs(g1))
