@@ -192,6 +192,16 @@ KERNEL_NAMES = {"fp64": "zgemm_nt_f64_kernel<128,128,8,2,4,Gauss,EpiCheb<MID>> (
                 "bf16x3": "cheb_bf3_kernel<128,128,2,4,MID> (BF16 MFMA 32x32x16, 3 real products "
                           "x 6 piece pairs)"}
 
+def kernel_name(precision: str, n: int) -> str:
+    """The middle product's kernel: 128 x 128 tiles, or 64 x 64 below BIG_TILE_ELEMS outputs."""
+    if n * n >= BIG_TILE_ELEMS:
+        return KERNEL_NAMES[precision]
+    return {"fp64": "zgemm_nt_f64_kernel<64,64,16,2,2,EpiCheb<MID>> (FP64 MFMA 16x16x4)",
+            "fp32": "cheb_f32_kernel<64,64,32,2,2,EpiMix<MID>> (FP32 MFMA 16x16x4)",
+            "bf16x3": "cheb_bf3_kernel<64,64,2,2,MID> (BF16 MFMA 32x32x16, 3 real products "
+                      "x 6 piece pairs)"}[precision]
+
+
 #: Kernel sources behind each roofline entry; HBM traffic recorded under
 #: profiles/ is reported only while these files are unchanged.
 TRAFFIC_SOURCES = {
@@ -313,10 +323,32 @@ def dense_roofline(reports, n: int, precision: str, workload: str):
     tr = recorded_traffic(precision, workload)
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
-            "traffic_detail": tr, "kernel": KERNEL_NAMES[precision],
+            "traffic_detail": tr, "kernel": kernel_name(precision, n),
             "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
             "mfma_flops_per_launch": mfma_flops, "algorithmic_flops_per_launch": flops,
             "algorithmic_tflops": round(flops / (ms_launch * 1e-3) / 1e12, 3)}
+
+
+def dense_reverse_roofline(grad_reports, n: int, L: int, M: int):
+    """The dense gradient's reverse-sweep products (FP64): per step, L launches
+    of Ht times the stacked [P_l; Pbar_{l+1}] (2n rows) for l >= 2 and of Ht
+    times Pbar (n rows) for l = 1, 0."""
+    from paper_1508_07621_amd._abi import K_ADJ_REV
+    n_rev = sum(r["n_kernel"][K_ADJ_REV] for r in grad_reports)
+    if not n_rev:
+        return None
+    ms = sum(r["ms_kernel"][K_ADJ_REV] for r in grad_reports) / n_rev
+    rows = (2 * max(L - 2, 0) + (1 if L >= 2 else 0) + 1) * n   # rows per step, all launches
+    flops = 8.0 * rows * n * n * M * len(grad_reports) / n_rev  # per launch, averaged
+    mf = flops * mfma_flops_per_flop("fp64", n, 2 * n)
+    ach = mf / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None,
+            "traffic_detail": None,
+            "kernel": "zgemm_nt_f64_kernel + EpiAdjStep (reverse sweep: Ht times [P_l; Pbar_{l+1}])",
+            "avg_launch_ms": round(ms, 4), "launches_timed": n_rev,
+            "algorithmic_flops_per_launch": flops,
+            "algorithmic_tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
 
 
 def time_error(U, wl, kw, spec: str):
@@ -533,6 +565,11 @@ def main():
     if wl.layout == "dense":
         roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
+        if grad_mode:
+            rev = dense_reverse_roofline(grad_reports, n, info["L"], wl.M)
+            if rev:  # build + gradient: the FP64 reverse-sweep products dominate
+                extra["build_roofline"] = roof
+                roof = rev
         if precision != "fp64" and not args.no_fp64_ref and not grad_mode:
             # The FP64 build of the same workload: reference result and timing.
             ref = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision="fp64",

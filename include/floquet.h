@@ -194,7 +194,10 @@ enum {
   FQ_K_HEFF = 4,        /* per-step rescaled Hamiltonian */
   FQ_K_TRIDIAG = 5,     /* tridiagonal whole-chain kernel */
   FQ_K_ADJ_FWD = 6,     /* gradient, streamed tridiagonal: segment recompute pass */
-  FQ_K_ADJ_REV = 7,     /* gradient, streamed tridiagonal: reverse pass */
+  FQ_K_ADJ_REV = 7,     /* gradient: reverse-sweep products (dense) or reverse passes
+                           (streamed tridiagonal); after floquet_grad the dense
+                           segment recompute's products appear under FIRST / MID /
+                           LAST / HEFF */
   FQ_K_SLOTS = 8
 };
 

@@ -1041,11 +1041,15 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
     FQ_TRY(dot(cur, 2.0));  // <Pbar_{l+1}, D P_l>
     d = D(l);
     if (l >= 2) {
+      FQ_MARK(c, FQ_K_ADJ_REV);
       FQ_HIP(c, fq::launch_adj_step(top_re(cur), top_im(cur), 2 * np, c->htr, c->hti, top_re(o),
                                     top_im(o), lr, li, d.real(), d.imag(), 2.0, 0, np, s));
+      FQ_MARK(c, -1);
     } else {  // l = 1: Pbar_1 only; P_0 = X_{k-1} from the segment store
+      FQ_MARK(c, FQ_K_ADJ_REV);
       FQ_HIP(c, fq::launch_adj_step(bot_re(cur), bot_im(cur), np, c->htr, c->hti, top_re(o),
                                     top_im(o), lr, li, d.real(), d.imag(), 2.0, np, np, s));
+      FQ_MARK(c, -1);
       FQ_TRY(copy2(top_re(o), top_im(o), seg_x));
     }
     cur = o;
@@ -1058,8 +1062,10 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
   const int o = 1 - cur;
   FQ_TRY(dot(cur, 1.0));
   d = D(0);
+  FQ_MARK(c, FQ_K_ADJ_REV);
   FQ_HIP(c, fq::launch_adj_step(bot_re(cur), bot_im(cur), np, c->htr, c->hti, top_re(o), top_im(o),
                                 lr, li, d.real(), d.imag(), 1.0, np, np, s));
+  FQ_MARK(c, -1);
   FQ_HIP(c, hipMemcpyAsync(lr, bot_re(o), pbytes, hipMemcpyDeviceToDevice, s));
   FQ_HIP(c, hipMemcpyAsync(li, bot_im(o), pbytes, hipMemcpyDeviceToDevice, s));
   return FQ_OK;
@@ -1128,9 +1134,11 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   bool any_b = false;
   for (int k = 0; k < M; ++k) any_b = any_b || (c->b[k] != 0.0);
   const int nseg = (M + s - 1) / s;
+  c->n_events = 0;  // profile mode: the recompute and reverse products go to the report
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int k0 = sg * s, k1 = std::min(M, k0 + s);
     // regenerate the segment forward in FP64 from its checkpoint
+    FQ_MARK(c, -1);
     FQ_HIP(c, hipMemcpyAsync(c->xr, c->tape + (size_t)sg * 2 * plane, p2bytes,
                              hipMemcpyDeviceToDevice, c->stream));
     for (int k = k0; k < k1; ++k) {
@@ -1147,17 +1155,15 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
       FQ_TRY(adjoint_step(c, k, k - k0, any_b));
     }
   }
+  FQ_MARK(c, -1);
   std::vector<double> g((size_t)c->J * M);
   FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   FQ_HIP(c, hipStreamSynchronize(c->stream));
   grad_to_nodes(c, g, grad_f_nodes);
-  return FQ_OK;
+  return collect_profile(c);
 }
 
-// Gradient of the tridiagonal chain: one reverse-sweep launch over all columns
-// (each workgroup recomputes its column's segments from the tape), then the
-// chain rule to the node samples as in the dense case.
 // The reverse sweep in streamed passes (columns longer than one workgroup
 // holds, or on request): per checkpoint segment, last first, the steps are
 // recomputed forward from the segment's checkpoint, keeping X_k and the
@@ -1288,6 +1294,10 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
   return collect_profile(c);
 }
 
+// Gradient of the tridiagonal chain: one reverse-sweep launch over all columns
+// (each workgroup recomputes its column's segments from the tape), then the
+// chain rule to the node samples as in the dense case; streamed passes when
+// the context holds their buffers.
 fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   if (c->d_adj) return tridiag_adjoint_streamed(c, U_bar, grad_f_nodes);
   const int M = c->M;
@@ -1814,7 +1824,6 @@ fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
     }
   } restore{c, c->precision, c->profile};
   c->precision = FQ_FP64;
-  c->profile = false;
   fq_status st = adjoint(c, U_bar, grad_f_nodes);
   return st;
 }
