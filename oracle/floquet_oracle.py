@@ -56,7 +56,7 @@ __all__ = [
     "GL2_C1", "GL2_C2", "node_times", "commutator", "magnus4_weights", "magnus4_heff",
     "bessel_coefficients", "choose_L", "rescale", "weyl_cover", "tridiag_cover",
     "exact_step", "chebyshev_step", "build_ut", "build_ut_tridiag", "tridiag_matrices",
-    "column_error", "fro_error", "unitarity_error", "nearest_unitary", "eigenphases",
+    "column_error", "unitarity_error", "nearest_unitary", "eigenphases",
     "quasienergy_distance",
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
     "GL3_C", "node_times6", "magnus6_omega", "magnus6_heff", "exact_cover",
@@ -594,11 +594,6 @@ def period_average_tridiag(h0_diag, h0_off, v_diag, f_nodes, f_grid, T: float, M
 def column_error(U: np.ndarray, Uref: np.ndarray) -> float:
     """max_j || (U - Uref) e_j ||_2: the worst propagated basis state."""
     return float(np.max(np.linalg.norm(U - Uref, axis=0)))
-
-
-def fro_error(U: np.ndarray, Uref: np.ndarray) -> float:
-    """|| U - Uref ||_F / sqrt(N)."""
-    return float(np.linalg.norm(U - Uref) / math.sqrt(U.shape[0]))
 
 
 def unitarity_error(U: np.ndarray) -> Tuple[float, float]:

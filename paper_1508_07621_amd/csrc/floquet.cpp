@@ -48,6 +48,23 @@ fq_status fail(fq_status st, const char* fmt, ...) {
     if (s_ != FQ_OK) return s_;      \
   } while (0)
 
+// Zero `bytes` (a multiple of 8) of device memory with a fill kernel on the
+// context's stream (a kernel rather than hipMemsetAsync, so that the same
+// sequence can be recorded into a graph by a caller).
+hipError_t zero_async(hipStream_t s, void* p, size_t bytes) {
+  if (bytes == 0) return hipSuccess;
+  return fq::launch_fill_zero(static_cast<double*>(p), (long)(bytes / sizeof(double)), s);
+}
+
+// Device-to-host or host-to-device copy ordered on the context's stream and
+// complete on return (the caller's stream may be a non-blocking stream, which
+// the legacy null stream of a plain hipMemcpy does not wait for).
+hipError_t copy_sync(hipStream_t s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
 constexpr size_t kAlign = 256;
 constexpr int kMaxOrder = 65535;       // capacity of the device coefficient table
 constexpr int kLanczosSteps = 160;
@@ -132,7 +149,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
     lay.off_ht = take(plane2);
     lay.off_x = take(plane2);
     lay.off_y = take(plane2);
-    // P buffers hold FP64 planes, or the product format (BF16X3: nine 16-bit planes)
+    // P buffers hold FP64 planes, or the product format (BF16X3: six 16-bit planes)
     const size_t pbytes = par->precision == FQ_BF16X3
                               ? std::max(plane2, sizeof(uint16_t) * fq::BF3_PLANES *
                                                      (size_t)lay.np * (size_t)lay.np)
@@ -456,7 +473,8 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
   fq_status st = FQ_OK;
   if (ctx->h0_eigen) {  // the extremes of diag(E) are exact
     std::vector<double> e(ctx->n);
-    FQ_HIP(ctx, hipMemcpy(e.data(), ctx->sys.h0_diag, ctx->n * sizeof(double), hipMemcpyDeviceToHost));
+    FQ_HIP(ctx, copy_sync(ctx->stream, e.data(), ctx->sys.h0_diag, ctx->n * sizeof(double),
+                          hipMemcpyDeviceToHost));
     l0 = *std::min_element(e.begin(), e.end());
     h0 = *std::max_element(e.begin(), e.end());
   } else {
@@ -616,10 +634,12 @@ fq_status dense_inner_bounds(fq_ctx* ctx, double* lo_out, double* hi_out) {
 fq_status tridiag_cover(fq_ctx* ctx, double* lo_out, double* hi_out) {
   const long n = ctx->n;
   std::vector<double> d0(n), v(n), off(2 * std::max<long>(n - 1, 0));
-  FQ_HIP(ctx, hipMemcpy(d0.data(), ctx->sys.h0_diag, n * sizeof(double), hipMemcpyDeviceToHost));
-  FQ_HIP(ctx, hipMemcpy(v.data(), ctx->sys.hmod_diag, n * sizeof(double), hipMemcpyDeviceToHost));
+  FQ_HIP(ctx, copy_sync(ctx->stream, d0.data(), ctx->sys.h0_diag, n * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  FQ_HIP(ctx, copy_sync(ctx->stream, v.data(), ctx->sys.hmod_diag, n * sizeof(double),
+                        hipMemcpyDeviceToHost));
   if (n > 1)
-    FQ_HIP(ctx, hipMemcpy(off.data(), ctx->sys.h0_off, 2 * (n - 1) * sizeof(double),
+    FQ_HIP(ctx, copy_sync(ctx->stream, off.data(), ctx->sys.h0_off, 2 * (n - 1) * sizeof(double),
                           hipMemcpyDeviceToHost));
   std::vector<double> d(n), e(std::max<long>(n - 1, 1));
   double lo = std::numeric_limits<double>::infinity(), hi = -lo;
@@ -642,7 +662,7 @@ fq_status tridiag_cover(fq_ctx* ctx, double* lo_out, double* hi_out) {
   std::vector<double> wtab(2 * (size_t)n * ctx->M);
   for (int k = 0; k < ctx->M; ++k)
     fq::tridiag_gauge(n, off.data(), v.data(), ctx->b[k], wtab.data() + 2 * (size_t)n * k);
-  FQ_HIP(ctx, hipMemcpy(ctx->d_gauge, wtab.data(), wtab.size() * sizeof(double),
+  FQ_HIP(ctx, copy_sync(ctx->stream, ctx->d_gauge, wtab.data(), wtab.size() * sizeof(double),
                         hipMemcpyHostToDevice));
   return FQ_OK;
 }
@@ -846,7 +866,7 @@ fq_status dense_steps(fq_ctx* c, int k0, int k1, int mrows, bool record_tape) {
 }
 
 fq_status unitarity(fq_ctx* c, const double* xr, const double* xi) {
-  FQ_HIP(c, hipMemsetAsync(c->small, 0, 2 * sizeof(double), c->stream));
+  FQ_HIP(c, zero_async(c->stream, c->small, 2 * sizeof(double)));
   FQ_HIP(c, fq::launch_unitarity_f64(xr, xi, (int)c->n, (int)c->np, c->small, c->stream));
   double h[2];
   FQ_HIP(c, hipMemcpyAsync(h, c->small, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -1033,8 +1053,8 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
   FQ_TRY(copy2(top_re(0), top_im(0), seg_lm1));
   FQ_HIP(c, fq::launch_scale_planar(lr, li, d.real(), d.imag(), bot_re(0), bot_im(0), plane, s));
   FQ_TRY(copy2(top_re(1), top_im(1), seg_l));
-  FQ_HIP(c, hipMemsetAsync(bot_re(1), 0, pbytes, s));
-  FQ_HIP(c, hipMemsetAsync(bot_im(1), 0, pbytes, s));
+  FQ_HIP(c, zero_async(s, bot_re(1), pbytes));
+  FQ_HIP(c, zero_async(s, bot_im(1), pbytes));
   int cur = 0;
   for (int l = L - 1; l >= 1; --l) {
     const int o = 1 - cur;
@@ -1130,7 +1150,7 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const size_t p2bytes = 2 * sizeof(double) * (size_t)plane;
   FQ_HIP(c, fq::launch_pack_planar_t(U_bar, c->n, c->n, c->n, c->lam, c->lam + plane, c->np,
                                      c->np, c->c64, c->stream));
-  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, (size_t)c->J * sizeof(double) * (size_t)M, c->stream));
+  FQ_HIP(c, zero_async(c->stream, c->d_grad, (size_t)c->J * sizeof(double) * (size_t)M));
   bool any_b = false;
   for (int k = 0; k < M; ++k) any_b = any_b || (c->b[k] != 0.0);
   const int nseg = (M + s - 1) / s;
@@ -1209,7 +1229,7 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
       p.out[j] = set[cur ^ 1][j];
     }
   };
-  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
+  FQ_HIP(c, zero_async(c->stream, c->d_grad, 2 * sizeof(double) * (size_t)M));
   c->n_events = 0;  // profile mode: the passes' times go to the report
   const void* lam_src = U_bar;  // Lambda_M: U_bar, row-major in the state type
   int lam_rows = 1, lam_c64 = c->c64 ? 1 : 0, lam_next = 0;
@@ -1323,7 +1343,7 @@ fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   job.c64 = c->c64 ? 1 : 0;
   job.seg = c->seg;
   job.grad = c->d_grad;
-  FQ_HIP(c, hipMemsetAsync(c->d_grad, 0, 2 * sizeof(double) * (size_t)M, c->stream));
+  FQ_HIP(c, zero_async(c->stream, c->d_grad, 2 * sizeof(double) * (size_t)M));
   FQ_HIP(c, fq::launch_tridiag_adjoint(job, c->stream));
   std::vector<double> g(2 * (size_t)M);
   FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -1533,8 +1553,8 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     delete c;
     return s;
   };
-  if (hipMemsetAsync(c->ws, 0, lay.total, c->stream) != hipSuccess)
-    return bail(fail(FQ_ERR_HIP, "hipMemsetAsync of the workspace failed"));
+  if (zero_async(c->stream, c->ws, lay.total) != hipSuccess)
+    return bail(fail(FQ_ERR_HIP, "zeroing the workspace failed"));
 
   const long n = c->n;
   if (c->layout == FQ_DENSE) {
@@ -1647,25 +1667,29 @@ fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep) {
 fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
   if (!c || !U_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
-  hipEvent_t e0, e1;
-  FQ_HIP(c, hipEventCreate(&e0));
-  FQ_HIP(c, hipEventCreate(&e1));
+  // The build's two timing events live with the context (created once, freed
+  // by fq_destroy), so that no return path leaks them.
+  if (c->timed && !c->build_ev[0]) {
+    FQ_HIP(c, hipEventCreate(&c->build_ev[0]));
+    FQ_HIP(c, hipEventCreate(&c->build_ev[1]));
+  }
+  hipEvent_t e0 = c->build_ev[0], e1 = c->build_ev[1];
   fq_status st = FQ_OK;
   c->n_events = 0;
   if (c->layout == FQ_DENSE) {
     FQ_HIP(c, fq::launch_identity_rows(c->xr, c->xi, c->n, c->np, c->np, c->stream));
-    FQ_HIP(c, hipEventRecord(e0, c->stream));
+    if (e0) FQ_HIP(c, hipEventRecord(e0, c->stream));
     st = dense_steps(c, 0, c->M, (int)c->np, c->ckpt > 0);
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
-    FQ_HIP(c, hipEventRecord(e1, c->stream));
+    if (e1) FQ_HIP(c, hipEventRecord(e1, c->stream));
     FQ_HIP(c, fq::launch_unpack_planar_t(c->xr, c->xi, c->np, c->n, c->n, U_out, c->n, c->c64,
                                        c->stream));
     c->tape_valid = c->ckpt > 0;
     st = unitarity(c, c->xr, c->xi);
     if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
   } else {
-    FQ_HIP(c, hipEventRecord(e0, c->stream));
+    if (e0) FQ_HIP(c, hipEventRecord(e0, c->stream));
     // Streamed columns record the checkpoints X_{j ckpt}, j >= 1, through the
     // snapshot store (row-major, tape entries 1, 2, ...); entry 0 is the identity.
     const bool snap_tape = c->ckpt > 0 && c->n > fq::tridiag_resident_max_n();
@@ -1679,7 +1703,7 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     c->snap = nullptr;
     if (st != FQ_OK) return st;
     FQ_MARK(c, -1);
-    FQ_HIP(c, hipEventRecord(e1, c->stream));
+    if (e1) FQ_HIP(c, hipEventRecord(e1, c->stream));
     c->tape_valid = c->ckpt > 0;
     FQ_HIP(c, fq::launch_pack_planar_t(U_out, c->n, c->n, c->n, c->xr, c->xi, c->np, c->np, c->c64,
                                        c->stream));
@@ -1687,11 +1711,11 @@ fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
     if (st == FQ_OK && c->reortho) st = finish_reortho(c, U_out);
   }
   if (st != FQ_OK) return st;
-  FQ_HIP(c, hipEventSynchronize(e1));
   float ms = 0.f;
-  FQ_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e1) {
+    FQ_HIP(c, hipEventSynchronize(e1));
+    FQ_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+  }
   c->last.ms_build = ms;
   st = collect_profile(c);
   if (st != FQ_OK) return st;

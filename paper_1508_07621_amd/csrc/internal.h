@@ -380,7 +380,13 @@ struct fq_ctx {
   std::vector<hipEvent_t> events;
   std::vector<int> event_kind;
   size_t n_events = 0;
+  // device time of a whole build (ms_build); off for the allocation-free
+  // one-shot build, which creates no events
+  bool timed = true;
+  hipEvent_t build_ev[2] = {nullptr, nullptr};
   ~fq_ctx() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : build_ev)
+      if (e) (void)hipEventDestroy(e);
   }
 };

@@ -235,8 +235,9 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
 // Split-BF16 products P_{l+1} = 2 Ht P_l - P_{l-1} on 32x32x16 BF16 matrix cores.
 //
 // A = P_l and B = Ht are BF16X3 matrices in the k-blocked layout (bf3_offset)
-// with nine planes: the three pieces of the real part, of the imaginary part
-// and of their sum. A complex product takes three real ones (Gauss):
+// with six stored planes: the three pieces of the real part and of the
+// imaginary part; the three pieces of their sum are formed while staging, so
+// that LDS holds nine planes. A complex product takes three real ones (Gauss):
 // T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2,
 // Im = T3 - T1 - T2, each over the 6 kept piece pairs (hh, hm, mh, hl, mm, lh):
 // 18 products of 32x32x16 per tile and k-block instead of 24.

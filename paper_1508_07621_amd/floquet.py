@@ -316,6 +316,7 @@ class FloquetUT:
             def backward(ctx_, gU):
                 g = ctx_.fq.grad(gU)
                 ctx_.fq.close()
-                return torch.from_numpy(g).to(f_nodes.dtype).reshape(f_nodes.shape)
+                return torch.from_numpy(g).to(device=f_nodes.device,
+                                              dtype=f_nodes.dtype).reshape(f_nodes.shape)
 
         return _Fn.apply(f_nodes)

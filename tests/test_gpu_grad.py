@@ -94,19 +94,22 @@ def test_smooth_drive_gradient_matches_oracle_differences(fl):
     assert np.max(np.abs(g[:, 0] - g[:, 1])) > 1e-6 * np.max(np.abs(g))  # nodes differ
 
 
-def test_autograd_function(fl):
+@pytest.mark.parametrize("where", ["cpu", "cuda"])
+def test_autograd_function(fl, where):
+    """The gradient comes back on the device (and in the dtype) of f_nodes."""
     import torch
     n, M = 40, 10
     H0, V, f, W = _problem(n, M, 5)
     T = 1.5
     lo, hi = -5.0, 5.0
-    fn = torch.tensor(np.stack([f, f], 1), dtype=torch.float64, requires_grad=True)
+    fn = torch.tensor(np.stack([f, f], 1), dtype=torch.float64, device=where, requires_grad=True)
     U = fl.FloquetUT.apply(fn, h0=H0, hmod=V, T=T, M=M, e_min=lo, e_max=hi, tol=1e-13,
                            checkpoint_every=4)
     Wt = torch.from_numpy(W).to(U.device)
     loss = 1.0 - torch.abs(torch.sum(torch.conj(Wt) * U)) ** 2 / n ** 2
     loss.backward()
-    g = fn.grad.numpy().sum(axis=1)
+    assert fn.grad.device == fn.device and fn.grad.dtype == fn.dtype
+    g = fn.grad.cpu().numpy().sum(axis=1)
     ref = orc.grad_piecewise(H0, V, f, T, W, route="cheb", e_min=lo, e_max=hi, tol=1e-13)
     assert np.max(np.abs(g - ref)) / np.max(np.abs(ref)) < 1e-8
 

@@ -571,3 +571,38 @@ def test_tridiag_complex_offdiagonal(fl):
                           e_min=lo, e_max=hi, L=L).build_ut().cpu().numpy()
     Uref = orc.build_ut_tridiag(d, e, v, f, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
     assert orc.column_error(U, Uref) < FP64_TOL
+
+
+# ---- streams -----------------------------------------------------------------------------------------
+
+def test_context_on_side_stream_matches_default_stream(fl):
+    """Every setup copy and fill of fq_create runs on the context's stream: a
+    context created and built on a non-blocking side stream, with its operators
+    uploaded on that stream just before, gives bit for bit the result of the
+    default stream (tridiagonal: host copies of the diagonals and the gauge
+    table; dense eigenbasis layout: the eigenvalue copy and the Lanczos cover)."""
+    import torch
+    T, M = TWO_PI, 30
+    d, e, v = dimer_tridiag(200, 1.0, 0.01)
+    f = _cos_nodes(fl, T, M, 0.5, 1.5)
+    rng = np.random.default_rng(44)
+    E = np.sort(rng.standard_normal(150))
+    V = gue(150, rng)
+    fd = _cos_nodes(fl, T, M)
+
+    def builds():
+        tri = fl.FloquetContext(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, f_nodes=f)
+        den = fl.FloquetContext(h0_eigenvalues=E, hmod=V, T=T, M=M, f_nodes=fd)
+        return tri.build_ut(), den.build_ut(), tri.report, den.report
+
+    _say("side stream: default-stream builds")
+    ref = builds()
+    side = torch.cuda.Stream()
+    _say("side stream: builds on a non-blocking stream")
+    with torch.cuda.stream(side):
+        got = builds()
+    side.synchronize()
+    for r, g in zip(ref[:2], got[:2]):
+        assert torch.equal(r, g)
+    for r, g in zip(ref[2:], got[2:]):
+        assert (r["e_min"], r["e_max"], r["L"]) == (g["e_min"], g["e_max"], g["L"])
