@@ -313,6 +313,27 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * segment. */
 fq_status floquet_grad(fq_ctx* ctx, const void* U_bar, double* grad_f_nodes);
 
+/* One-shot build of U_T that allocates nothing, for callers that cannot
+ * allocate device memory (serving loops with a fixed memory budget, code that
+ * must not call hipMalloc or a caching allocator). It does what fq_create,
+ * floquet_build_UT and fq_destroy do in sequence, with the workspace taken
+ * from a static device array of the library (256 MiB per GPU, held from the
+ * first use on a device until the process ends) instead of caller memory;
+ * it calls no hipMalloc or hipFree and creates no events. sys and par as for
+ * fq_create, with checkpoint_every == 0 and profile == 0 (else
+ * FQ_ERR_UNSUPPORTED); a problem whose fq_workspace_bytes exceeds 256 MiB is
+ * rejected with FQ_ERR_ARG before any device work (dense Magnus-4 or
+ * commutator-free: n up to 1408 in FP64 and 1280 in FP32 or split-BF16; the
+ * tridiagonal chain: about 16 n^2 + 16 n M bytes, n up to about 3900).
+ * stream: hipStream_t of the current device (NULL = default stream); U_out:
+ * device, n*n complex (par->dtype) row-major, [i][j] = <i|U_T|j>; rep (host,
+ * nullable) as for floquet_build_UT, with ms_build = 0. Returns after the
+ * stream has drained. Every call on one GPU uses that GPU's single array
+ * (each call clears what it needs): calls that overlap on one GPU, from
+ * several host threads or on several streams, race and give wrong results. */
+fq_status floquet_build_UT_static(const fq_system* sys, const fq_params* par, void* stream,
+                                  void* U_out, fq_report* rep);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* fq_last_error(void);
 

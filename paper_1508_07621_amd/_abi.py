@@ -29,7 +29,7 @@ EXPORTS = (
     "fq_node_times", "fq_node_times_magnus6", "fq_bessel_weights", "fq_choose_order", "fq_tridiag_extremes",
     "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_get_report",
     "floquet_build_UT", "floquet_propagate", "floquet_period_average", "floquet_grad",
-    "fq_last_error",
+    "floquet_build_UT_static", "fq_last_error",
 )
 
 
@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
     L.floquet_period_average.argtypes = [c_void_p, c_void_p, c_int64, POINTER(c_double),
                                          POINTER(c_double)]
     L.floquet_grad.argtypes = [c_void_p, c_void_p, POINTER(c_double)]
+    L.floquet_build_UT_static.argtypes = [POINTER(FqSystem), POINTER(FqParams), c_void_p, c_void_p,
+                                          POINTER(FqReport)]
     for name in EXPORTS:
         if name != "fq_last_error":
             getattr(L, name).restype = st

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1355,6 +1356,47 @@ fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
 
 }  // namespace
 
+// ---- static scratch of the allocation-free one-shot build ------------------------------------
+//
+// floquet_build_UT_static places the whole workspace of its temporary context
+// in this array instead of caller memory. Each GPU the library runs on holds
+// its own copy (allocated when the code object loads on that device, kept
+// until the process ends). In host code `scratch` names a host-side stand-in,
+// not the device array: the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// handed to kernels and copies.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;  // 256 MiB
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array.
+fq_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(FQ_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(FQ_ERR_UNSUPPORTED, "device index %d beyond the %d devices with static scratch",
+                dev, kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FQ_ERR_HIP, "hipGetSymbolAddress of the static scratch failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return FQ_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* fq_last_error(void) { return g_err.c_str(); }
@@ -1849,6 +1891,33 @@ fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   } restore{c, c->precision, c->profile};
   c->precision = FQ_FP64;
   fq_status st = adjoint(c, U_bar, grad_f_nodes);
+  return st;
+}
+
+fq_status floquet_build_UT_static(const fq_system* sys, const fq_params* par, void* stream,
+                                  void* U_out, fq_report* rep) {
+  if (!U_out) return fail(FQ_ERR_ARG, "U_out is null");
+  fq_status st = validate(sys, par);
+  if (st != FQ_OK) return st;
+  if (par->checkpoint_every != 0)
+    return fail(FQ_ERR_UNSUPPORTED, "the one-shot build keeps no gradient tape "
+                                    "(checkpoint_every must be 0)");
+  if (par->profile != 0)
+    return fail(FQ_ERR_UNSUPPORTED, "the one-shot build does not time kernels (profile must be 0)");
+  const size_t need = plan(sys, par).total;
+  if (need > kStaticScratchBytes)
+    return fail(FQ_ERR_ARG, "this build needs %zu bytes of workspace, more than the %zu bytes of "
+                "static scratch; create a context with a caller workspace instead",
+                need, kStaticScratchBytes);
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != FQ_OK) return st;
+  fq_ctx* c = nullptr;
+  st = fq_create(&c, sys, par, ws, kStaticScratchBytes, stream);
+  if (st != FQ_OK) return st;
+  c->timed = false;  // no events: ms_build is reported as 0
+  st = floquet_build_UT(c, U_out, rep);
+  delete c;
   return st;
 }
 

@@ -14,7 +14,8 @@ from . import _abi
 from ._abi import FqParams, FqReport, FqSystem, check, dptr, lib
 
 __all__ = ["node_times", "bessel_weights", "choose_order", "tridiag_extremes",
-           "FloquetContext", "floquet_build_UT", "floquet_propagate", "floquet_grad", "FloquetUT"]
+           "FloquetContext", "floquet_build_UT", "floquet_build_UT_static", "floquet_propagate",
+           "floquet_grad", "FloquetUT"]
 
 
 def _torch():
@@ -74,6 +75,95 @@ def _device_tensor(x, dtype, device):
     return x.to(device=device, dtype=dtype).contiguous()
 
 
+def _marshal(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenvalues=None,
+             h0_diag=None, h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
+             e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
+             precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
+             reorthonormalize: bool = False, dtype: str = "complex128", scheme: str = "magnus4",
+             device=None):
+    """Device copies of the operators and the fq_system / fq_params structures
+    of one problem (arguments as for FloquetContext), set on `self`."""
+    import ctypes
+    torch = _torch()
+    self.device = torch.device(device if device is not None else "cuda")
+    self._keep = []
+    sysd = FqSystem()
+    drives = list(hmod) if isinstance(hmod, (list, tuple)) else None
+    self.S = len(drives) if drives else 1
+
+    def set_drives(n):
+        if drives is None:
+            vt = _device_tensor(hmod, torch.complex128, self.device)
+            if vt.shape != (n, n):
+                raise ValueError("hmod must be n x n")
+            sysd.hmod = vt.data_ptr()
+            self._keep.append(vt)
+            return
+        vts = [_device_tensor(v, torch.complex128, self.device) for v in drives]
+        if any(v.shape != (n, n) for v in vts):
+            raise ValueError("every drive matrix must be n x n")
+        arr = (ctypes.c_void_p * len(vts))(*[v.data_ptr() for v in vts])
+        sysd.n_drive = len(vts)
+        sysd.hmods = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        self._keep += vts + [arr]
+
+    if h0_eigenvalues is not None:
+        e = _device_tensor(h0_eigenvalues, torch.float64, self.device)
+        self.n = int(e.shape[0])
+        sysd.n, sysd.layout = self.n, _abi.FQ_DENSE_EIGEN
+        sysd.h0_diag = e.data_ptr()
+        self._keep.append(e)
+        set_drives(self.n)
+    elif h0 is not None:
+        h0t = _device_tensor(h0, torch.complex128, self.device)
+        self.n = int(h0t.shape[0])
+        if h0t.shape != (self.n, self.n):
+            raise ValueError("h0 must be square")
+        sysd.n, sysd.layout = self.n, _abi.FQ_DENSE
+        sysd.h0 = h0t.data_ptr()
+        self._keep.append(h0t)
+        set_drives(self.n)
+    else:
+        d = _device_tensor(h0_diag, torch.float64, self.device)
+        v = _device_tensor(hmod_diag, torch.float64, self.device)
+        self.n = int(d.shape[0])
+        off = _device_tensor(h0_off if h0_off is not None else np.zeros(max(self.n - 1, 0)),
+                             torch.complex128, self.device)
+        if v.shape[0] != self.n or off.shape[0] != max(self.n - 1, 0):
+            raise ValueError("tridiagonal arrays have inconsistent sizes")
+        sysd.n, sysd.layout = self.n, _abi.FQ_TRIDIAG
+        sysd.h0_diag, sysd.hmod_diag = d.data_ptr(), v.data_ptr()
+        sysd.h0_off = off.data_ptr() if self.n > 1 else None
+        self._keep += [d, v, off]
+    self.layout = sysd.layout
+    self.M = int(M)
+    self.T = float(T)
+    if scheme not in _abi.SCHEMES:
+        raise ValueError("scheme must be magnus4, magnus6 or cf4")
+    self.scheme = scheme
+    per_step = (3 if scheme == "magnus6" else 2) * self.S
+    self._f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))
+    if self._f.size != per_step * self.M:
+        raise ValueError(f"f_nodes must hold {per_step}*M values for {scheme}")
+    par = FqParams()
+    par.T, par.M, par.L = self.T, self.M, int(L)
+    par.f_nodes = dptr(self._f)
+    par.e_min = math.nan if e_min is None else float(e_min)
+    par.e_max = math.nan if e_max is None else float(e_max)
+    par.tol = float(tol)
+    par.precision = _abi.PRECISIONS[precision]
+    par.checkpoint_every = int(checkpoint_every)
+    par.profile = 1 if profile else 0
+    par.reorthonormalize = 1 if reorthonormalize else 0
+    if dtype not in ("complex128", "complex64"):
+        raise ValueError("dtype must be complex128 or complex64")
+    par.dtype = _abi.FQ_C64 if dtype == "complex64" else _abi.FQ_C128
+    par.scheme = _abi.SCHEMES[scheme]
+    self.state_dtype = torch.complex64 if dtype == "complex64" else torch.complex128
+    self.precision = precision
+    self._sys, self._par = sysd, par
+
+
 class FloquetContext:
     """One problem H(t) = H0 + f(t) Hmod on one GPU, set up once, built many times.
 
@@ -92,92 +182,11 @@ class FloquetContext:
     operators stay complex128 / float64).
     """
 
-    def __init__(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenvalues=None,
-                 h0_diag=None,
-                 h0_off=None, hmod_diag=None, e_min: Optional[float] = None,
-                 e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
-                 precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
-                 reorthonormalize: bool = False, dtype: str = "complex128",
-                 scheme: str = "magnus4", device=None):
+    def __init__(self, **kw):
         torch = _torch()
+        _marshal(self, **kw)
         L_ = lib()
-        self.device = torch.device(device if device is not None else "cuda")
-        self._keep = []
-        sysd = FqSystem()
-        drives = list(hmod) if isinstance(hmod, (list, tuple)) else None
-        self.S = len(drives) if drives else 1
-
-        def set_drives(n):
-            if drives is None:
-                vt = _device_tensor(hmod, torch.complex128, self.device)
-                if vt.shape != (n, n):
-                    raise ValueError("hmod must be n x n")
-                sysd.hmod = vt.data_ptr()
-                self._keep.append(vt)
-                return
-            vts = [_device_tensor(v, torch.complex128, self.device) for v in drives]
-            if any(v.shape != (n, n) for v in vts):
-                raise ValueError("every drive matrix must be n x n")
-            arr = (ctypes.c_void_p * len(vts))(*[v.data_ptr() for v in vts])
-            sysd.n_drive = len(vts)
-            sysd.hmods = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
-            self._keep += vts + [arr]
-
-        import ctypes
-        if h0_eigenvalues is not None:
-            e = _device_tensor(h0_eigenvalues, torch.float64, self.device)
-            self.n = int(e.shape[0])
-            sysd.n, sysd.layout = self.n, _abi.FQ_DENSE_EIGEN
-            sysd.h0_diag = e.data_ptr()
-            self._keep.append(e)
-            set_drives(self.n)
-        elif h0 is not None:
-            h0t = _device_tensor(h0, torch.complex128, self.device)
-            self.n = int(h0t.shape[0])
-            if h0t.shape != (self.n, self.n):
-                raise ValueError("h0 must be square")
-            sysd.n, sysd.layout = self.n, _abi.FQ_DENSE
-            sysd.h0 = h0t.data_ptr()
-            self._keep.append(h0t)
-            set_drives(self.n)
-        else:
-            d = _device_tensor(h0_diag, torch.float64, self.device)
-            v = _device_tensor(hmod_diag, torch.float64, self.device)
-            self.n = int(d.shape[0])
-            off = _device_tensor(h0_off if h0_off is not None else np.zeros(max(self.n - 1, 0)),
-                                 torch.complex128, self.device)
-            if v.shape[0] != self.n or off.shape[0] != max(self.n - 1, 0):
-                raise ValueError("tridiagonal arrays have inconsistent sizes")
-            sysd.n, sysd.layout = self.n, _abi.FQ_TRIDIAG
-            sysd.h0_diag, sysd.hmod_diag = d.data_ptr(), v.data_ptr()
-            sysd.h0_off = off.data_ptr() if self.n > 1 else None
-            self._keep += [d, v, off]
-        self.layout = sysd.layout
-        self.M = int(M)
-        self.T = float(T)
-        if scheme not in _abi.SCHEMES:
-            raise ValueError("scheme must be magnus4, magnus6 or cf4")
-        self.scheme = scheme
-        per_step = (3 if scheme == "magnus6" else 2) * self.S
-        self._f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))
-        if self._f.size != per_step * self.M:
-            raise ValueError(f"f_nodes must hold {per_step}*M values for {scheme}")
-        par = FqParams()
-        par.T, par.M, par.L = self.T, self.M, int(L)
-        par.f_nodes = dptr(self._f)
-        par.e_min = math.nan if e_min is None else float(e_min)
-        par.e_max = math.nan if e_max is None else float(e_max)
-        par.tol = float(tol)
-        par.precision = _abi.PRECISIONS[precision]
-        par.checkpoint_every = int(checkpoint_every)
-        par.profile = 1 if profile else 0
-        par.reorthonormalize = 1 if reorthonormalize else 0
-        if dtype not in ("complex128", "complex64"):
-            raise ValueError("dtype must be complex128 or complex64")
-        par.dtype = _abi.FQ_C64 if dtype == "complex64" else _abi.FQ_C128
-        par.scheme = _abi.SCHEMES[scheme]
-        self.state_dtype = torch.complex64 if dtype == "complex64" else torch.complex128
-        self.precision = precision
+        sysd, par = self._sys, self._par
         import ctypes
         nbytes = ctypes.c_size_t(0)
         check(L_.fq_workspace_bytes(ctypes.byref(sysd), ctypes.byref(par), ctypes.byref(nbytes)))
@@ -188,7 +197,6 @@ class FloquetContext:
             check(L_.fq_create(ctypes.byref(handle), ctypes.byref(sysd), ctypes.byref(par),
                                self.workspace.data_ptr(), nbytes.value, self._stream.cuda_stream))
         self._ctx = handle
-        self._sys, self._par = sysd, par
 
     @property
     def report(self) -> dict:
@@ -295,6 +303,31 @@ def floquet_grad(U_bar, **kw):
     g = ctx.grad(U_bar)
     ctx.close()
     return g
+
+
+def floquet_build_UT_static(out=None, **kw):
+    """U_T through the allocation-free one-shot entry point: the library takes
+    its workspace from its static device array (no workspace tensor, no context
+    kept). Arguments as for FloquetContext (checkpoint_every and profile must
+    be off). Returns (U_T tensor, report dict); the report's ms_build is 0."""
+    import ctypes
+    torch = _torch()
+
+    class _Problem:
+        pass
+
+    prob = _Problem()
+    _marshal(prob, **kw)
+    if out is None:
+        out = torch.empty((prob.n, prob.n), dtype=prob.state_dtype, device=prob.device)
+    if out.dtype != prob.state_dtype or not out.is_contiguous() or out.shape != (prob.n, prob.n):
+        raise ValueError("out must be a contiguous n x n tensor of the problem's dtype")
+    r = FqReport()
+    stream = torch.cuda.current_stream(prob.device)
+    with torch.cuda.device(prob.device):
+        check(lib().floquet_build_UT_static(ctypes.byref(prob._sys), ctypes.byref(prob._par),
+                                            stream.cuda_stream, out.data_ptr(), ctypes.byref(r)))
+    return out, r.as_dict()
 
 
 class FloquetUT:

@@ -384,3 +384,26 @@ def test_bench_refuses_more_than_one_gpu():
         assert r.returncode == 2
         assert "one GPU only" in r.stderr
         assert r.stdout == ""
+
+
+def test_static_build_rejects_before_device_work():
+    """The allocation-free one-shot build checks its arguments and the size of
+    the static scratch before any HIP call."""
+    L = _abi.lib()
+    rep = _abi.FqReport()
+
+    def call(s, p):
+        return L.floquet_build_UT_static(ctypes.byref(s), ctypes.byref(p), None, FAKE,
+                                         ctypes.byref(rep))
+
+    assert L.floquet_build_UT_static(ctypes.byref(_dense()), ctypes.byref(_params()), None, None,
+                                     None) == _abi.FQ_ERR_ARG
+    assert call(_dense(0), _params()) == _abi.FQ_ERR_ARG
+    assert call(_dense(), _params(checkpoint_every=2)) == _abi.FQ_ERR_UNSUPPORTED
+    assert call(_dense(), _params(profile=1)) == _abi.FQ_ERR_UNSUPPORTED
+    # 1536 x 1536 FP64 planes do not fit the 256 MiB array; 1408 do
+    assert call(_dense(1409), _params()) == _abi.FQ_ERR_ARG
+    assert "static scratch" in L.fq_last_error().decode()
+    assert _ws(_dense(1408), _params())[1] <= 256 << 20 < _ws(_dense(1409), _params())[1]
+    assert call(_dense(1281), _params(precision=2)) == _abi.FQ_ERR_ARG
+    assert call(_tridiag(4096), _params()) == _abi.FQ_ERR_ARG
