@@ -100,6 +100,14 @@ def parse():
                          "kernel for scaling HBM traffic counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--oracle-cols", type=int, default=-1, metavar="C",
+                    help="columns on which the FP64 oracle follows all M steps as the reference "
+                         "of errors.vs_oracle (default 4 for N <= 4096, 0 = off above)")
+    ap.add_argument("--mixed-tol", type=float, default=0.0,
+                    help="split-BF16: error target from which each term's product format is "
+                         "chosen (0 = the library's default)")
+    ap.add_argument("--fp64-builds", type=int, default=3,
+                    help="timed FP64 reference builds (after one warm-up); their median is reported")
     return ap.parse_args()
 
 
@@ -150,6 +158,27 @@ def cpu_baseline(wl, f_nodes, target_s: float):
     return {"value": scaled, "unit": "s/build", "cores": cores, "kind": "oracle",
             "sample": sample, "sample_seconds": round(dt, 3),
             "wall_seconds": round(time.time() - t_cpu0, 1)}
+
+
+def oracle_columns(wl, kw, f_nodes, info, ncols: int):
+    """The FP64 oracle (Chebyshev route, the build's interval and order) on
+    `ncols` seeded columns of the identity over all M steps: the reference
+    for the error of each GPU result on those columns."""
+    import numpy as np
+
+    import oracle as orc
+    rng = np.random.default_rng(1508 + 99)
+    cols = np.sort(rng.choice(wl.n, ncols, replace=False))
+    X0 = np.eye(wl.n, dtype=np.complex128)[:, cols]
+    common = dict(route="cheb", e_min=info["e_min"], e_max=info["e_max"], L=info["L"], X0=X0,
+                  scheme=wl.scheme)
+    t0 = time.perf_counter()
+    if wl.layout == "dense":
+        Xref = orc.build_ut(kw["h0"], kw["hmod"], f_nodes, wl.T, wl.M, **common)
+    else:
+        Xref = orc.build_ut_tridiag(kw["h0_diag"], kw["h0_off"], kw["hmod_diag"], f_nodes, wl.T,
+                                    wl.M, **common)
+    return cols, Xref, time.perf_counter() - t0
 
 
 def _log(msg: str) -> None:
@@ -208,6 +237,9 @@ TRAFFIC_SOURCES = {
     "fp64": ["kernels_dense.hip", "formats.h", "internal.h"],
     "fp32": ["kernels_mixed.hip", "formats.h", "internal.h"],
     "bf16x3": ["kernels_mixed.hip", "formats.h", "internal.h"],
+    "bf16x3_f64acc": ["kernels_mixed.hip", "formats.h", "internal.h"],
+    "bf16x2": ["kernels_mixed.hip", "formats.h", "internal.h"],
+    "bf16x1": ["kernels_mixed.hip", "formats.h", "internal.h"],
     "tridiag": ["kernels_tridiag.hip", "internal.h"],
 }
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
@@ -240,8 +272,11 @@ def recorded_traffic(key: str, workload: str):
     return None
 
 
-def time_builds(ctx, U, warmup: int, steps: int, tag: str):
-    """W untimed builds, then K builds timed between device synchronisations."""
+def time_builds(ctx, U, warmup: int, steps: int, tag: str, walls=None):
+    """W untimed builds, then K builds timed between device synchronisations
+    (every build returns after its stream has drained: the unitarity check
+    reads its result on the host). `walls` (a list) receives each build's wall
+    time."""
     import torch
     for i in range(warmup):
         ctx.build_ut(out=U)
@@ -250,7 +285,10 @@ def time_builds(ctx, U, warmup: int, steps: int, tag: str):
     reports = []
     t0 = time.perf_counter()
     for i in range(steps):
+        t1 = time.perf_counter()
         ctx.build_ut(out=U)
+        if walls is not None:
+            walls.append(time.perf_counter() - t1)
         reports.append(ctx.last_report)
         _log(f"{tag} timed build {i + 1}/{steps}: {reports[-1]['ms_build']:.1f} ms")
     torch.cuda.synchronize()
@@ -312,21 +350,88 @@ def fd_direction(wl, kw, f, g, W, eps: float):
             "finite_difference": fd, "rel_diff": abs(ad - fd) / max(abs(fd), 1e-300)}
 
 
+ALGO_NOTE = ("algorithmic flops: 8 N^3 per complex N x N x N product (four real products); the "
+             "FP64 kernel on 128 x 128 tiles forms each complex product from Gauss's three real "
+             "products (6 N^3 MFMA flops), so its algorithmic rate can exceed the FP64 MFMA peak; "
+             "split-BF16 issues three real products per kept piece pair")
+
+
 def dense_roofline(reports, n: int, precision: str, workload: str):
+    """The middle Chebyshev product: achieved = algorithmic flops (8 N^3) per
+    launch over the launch time, against the MFMA peak of the precision the
+    product runs in; the MFMA flops actually issued are reported beside it."""
     from paper_1508_07621_amd._abi import K_MID
     n_launch = sum(r["n_kernel"][K_MID] for r in reports)
     ms_launch = sum(r["ms_kernel"][K_MID] for r in reports) / max(n_launch, 1)
     flops = 8.0 * n ** 3                                   # one complex N x N x N product
     mfma_flops = flops * mfma_flops_per_flop(precision, n)
-    achieved = mfma_flops / (ms_launch * 1e-3) / 1e12
+    achieved = flops / (ms_launch * 1e-3) / 1e12
+    issued = mfma_flops / (ms_launch * 1e-3) / 1e12
     peak = PEAKS[precision]
     tr = recorded_traffic(precision, workload)
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
             "traffic_detail": tr, "kernel": kernel_name(precision, n),
             "avg_launch_ms": round(ms_launch, 4), "launches_timed": n_launch,
-            "mfma_flops_per_launch": mfma_flops, "algorithmic_flops_per_launch": flops,
-            "algorithmic_tflops": round(flops / (ms_launch * 1e-3) / 1e12, 3)}
+            "algorithmic_flops_per_launch": flops, "note": ALGO_NOTE,
+            "issued_mfma": {"flops_per_launch": mfma_flops, "achieved": round(issued, 3),
+                            "frac": round(issued / peak, 4)}}
+
+
+#: split-BF16 builds: profile kinds of the products by term format
+TERM_KINDS = {8: "fp64", 9: "bf16x3_f64acc", 10: "bf16x3", 11: "bf16x2", 12: "bf16x1"}
+#: MFMA flops issued per algorithmic flop (8 N^3 per complex product) of each format:
+#: FP64 Gauss (3 of 4 real products); FP64-accumulating split-BF16: four real products
+#: x six piece pairs / 4; split-BF16 with FP32 sums: Gauss x 6, 3 or 1 piece pairs / 4
+TERM_MFMA = {"fp64": 0.75, "bf16x3_f64acc": 6.0, "bf16x3": 4.5, "bf16x2": 2.25, "bf16x1": 0.75}
+TERM_KERNEL = {
+    "fp64": "zgemm_nt_f64_kernel<128,128,8,2,4,Gauss,EpiCheb> (FP64 MFMA 16x16x4)",
+    "bf16x3_f64acc": "cheb_acc_kernel<128> (BF16 MFMA 32x32x16, 4 real products x 6 piece "
+                     "pairs, FP64 sums per 16-column block)",
+    "bf16x3": "cheb_bf3_kernel<128,128,2,4,KIND,P,3> (BF16 MFMA 32x32x16, 3 real products x 6 "
+              "piece pairs)",
+    "bf16x2": "cheb_bf3_kernel<128,128,2,4,KIND,P,2> (3 real products x 3 piece pairs)",
+    "bf16x1": "cheb_bf3_kernel<128,128,2,4,KIND,P,1> (3 real products x 1 piece pair)",
+}
+
+
+def term_schedule(reports, n: int, workload: str):
+    """Per term format of a split-BF16 build: launches per build, average
+    launch time, share of the build, algorithmic and issued MFMA rates; and
+    the roofline entry of the format that takes the most time."""
+    rows = {}
+    for k, name in TERM_KINDS.items():
+        cnt = sum(r["n_kernel"][k] for r in reports)
+        if not cnt:
+            continue
+        ms = sum(r["ms_kernel"][k] for r in reports)
+        avg = ms / cnt
+        flops = 8.0 * n ** 3
+        peak = PEAK_FP64_MFMA_TFLOPS if name == "fp64" else PEAK_BF16_MFMA_TFLOPS
+        mf = flops * (mfma_flops_per_flop("fp64", n) if name == "fp64" else TERM_MFMA[name])
+        rows[name] = {"launches_per_build": cnt / len(reports), "avg_launch_ms": round(avg, 4),
+                      "ms_per_build": round(ms / len(reports), 2),
+                      "algorithmic_tflops": round(flops / (avg * 1e-3) / 1e12, 2),
+                      "frac": round(flops / (avg * 1e-3) / 1e12 / peak, 4),
+                      "issued_mfma_frac": round(mf / (avg * 1e-3) / 1e12 / peak, 4)}
+    if not rows:
+        return None, None
+    dom = max(rows, key=lambda k: rows[k]["ms_per_build"])
+    r = rows[dom]
+    flops = 8.0 * n ** 3
+    peak = PEAK_FP64_MFMA_TFLOPS if dom == "fp64" else PEAK_BF16_MFMA_TFLOPS
+    mf = flops * (mfma_flops_per_flop("fp64", n) if dom == "fp64" else TERM_MFMA[dom])
+    avg = r["avg_launch_ms"]
+    tr = recorded_traffic(dom, workload)
+    roof = {"bound": "mfma", "achieved": r["algorithmic_tflops"], "peak": peak,
+            "unit": "TFLOP/s", "frac": r["frac"], "traffic": tr["bytes"] if tr else None,
+            "traffic_detail": tr, "kernel": TERM_KERNEL[dom],
+            "term_format": dom, "avg_launch_ms": avg,
+            "launches_timed": int(round(r["launches_per_build"] * len(reports))),
+            "algorithmic_flops_per_launch": flops, "note": ALGO_NOTE,
+            "issued_mfma": {"flops_per_launch": mf, "achieved": round(mf / (avg * 1e-3) / 1e12, 3),
+                            "frac": round(mf / (avg * 1e-3) / 1e12 / peak, 4)}}
+    return rows, roof
 
 
 def dense_reverse_roofline(grad_reports, n: int, L: int, M: int):
@@ -341,14 +446,16 @@ def dense_reverse_roofline(grad_reports, n: int, L: int, M: int):
     rows = (2 * max(L - 2, 0) + (1 if L >= 2 else 0) + 1) * n   # rows per step, all launches
     flops = 8.0 * rows * n * n * M * len(grad_reports) / n_rev  # per launch, averaged
     mf = flops * mfma_flops_per_flop("fp64", n, 2 * n)
-    ach = mf / (ms * 1e-3) / 1e12
+    ach = flops / (ms * 1e-3) / 1e12
+    issued = mf / (ms * 1e-3) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None,
             "traffic_detail": None,
             "kernel": "zgemm_nt_f64_kernel + EpiAdjStep (reverse sweep: Ht times [P_l; Pbar_{l+1}])",
             "avg_launch_ms": round(ms, 4), "launches_timed": n_rev,
-            "algorithmic_flops_per_launch": flops,
-            "algorithmic_tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
+            "algorithmic_flops_per_launch": flops, "note": ALGO_NOTE,
+            "issued_mfma": {"flops_per_launch": mf, "achieved": round(issued, 3),
+                            "frac": round(issued / PEAK_FP64_MFMA_TFLOPS, 4)}}
 
 
 def time_error(U, wl, kw, spec: str):
@@ -518,6 +625,7 @@ def main():
         margin = 1.0 + 1e-3 * (probe["e_max"] - probe["e_min"])
         interval = dict(e_min=probe["e_min"] - margin, e_max=probe["e_max"] + margin)
     ctx = fl.FloquetContext(T=wl.T, M=wl.M, f_nodes=f_nodes, tol=1e-12, precision=precision,
+                            mixed_tol=args.mixed_tol if precision != "fp64" else 0.0,
                             profile=True, device=dev, checkpoint_every=16 if grad_mode else 0,
                             dtype="complex64" if c64_grad else "complex128",
                             scheme=wl.scheme, **interval, **kw)
@@ -544,6 +652,7 @@ def main():
         s_per_build, reports = time_builds(ctx, U, args.warmup, args.steps, precision)
     last = reports[-1]
     errors = {"unitarity_max": last["unitarity_max"], "unitarity_fro": last["unitarity_fro"]}
+    Uref = None
 
     extra = {}
     if grad_mode:
@@ -563,7 +672,14 @@ def main():
             extra["gradient"]["fd_direction"] = fd_direction(wl, fkw, wl.amplitudes,
                                                              g_last.sum(axis=1), W, args.fd_check)
     if wl.layout == "dense":
-        roof = dense_roofline(reports, n, precision, args.workload)
+        if precision == "bf16x3":
+            rows, roof = term_schedule(reports, n, args.workload)
+            from paper_1508_07621_amd._abi import TERM_FORMAT_NAMES
+            extra["schedule"] = {
+                "term_formats": [TERM_FORMAT_NAMES[f] for f in last["term_format"] if f >= 0],
+                "mixed_err_est": last["mixed_err_est"], "per_format": rows}
+        else:
+            roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
         if grad_mode:
             rev = dense_reverse_roofline(grad_reports, n, info["L"], wl.M)
@@ -576,7 +692,9 @@ def main():
                                     e_min=info["e_min"], e_max=info["e_max"], L=info["L"],
                                     profile=True, device=dev, scheme=wl.scheme, **kw)
             Uref = torch.empty_like(U)
-            s_ref, rep_ref = time_builds(ref, Uref, 0, 1, "fp64")
+            walls = []
+            _, rep_ref = time_builds(ref, Uref, 1, max(args.fp64_builds, 1), "fp64", walls)
+            s_ref = float(np.median(walls))
             D = U - Uref
             errors.update({
                 "reference": "FP64 build of the same workload on the GPU (same interval and L)",
@@ -591,11 +709,14 @@ def main():
                 errors["max_quasienergy_error"] = dq
                 extra["eig_seconds_host"] = round(eig_s, 1)
             extra["fp64"] = {"s_per_build": round(s_ref, 4),
+                             "timing": f"median of {len(walls)} builds after one warm-up",
+                             "s_per_build_each": [round(w, 4) for w in walls],
                              "build_tflops_algorithmic": round(
                                  info["L"] * wl.M * 8.0 * n ** 3 / s_ref / 1e12, 3),
+                             "build_tflops_note": ALGO_NOTE,
                              "roofline": dense_roofline(rep_ref, n, "fp64", args.workload)}
             extra["speedup_vs_fp64"] = round(s_ref / s_per_build, 3)
-            del ref, Uref
+            del ref
     else:
         n_launch = sum(r["n_kernel"][K_TRIDIAG] for r in reports)
         ms_launch = sum(r["ms_kernel"][K_TRIDIAG] for r in reports) / max(n_launch, 1)
@@ -638,6 +759,21 @@ def main():
                     "kernel": "tridiag_adj_forward_kernel<4,8>", "avg_launch_ms": round(ms_fwd, 4),
                     "launches_timed": n_fwd}
 
+    ocols = args.oracle_cols if args.oracle_cols >= 0 else (4 if n <= 4096 else 0)
+    if ocols > 0 and not grad_mode:
+        _log(f"FP64 oracle on {ocols} columns over all {wl.M} steps")
+        cols, Xref, o_s = oracle_columns(wl, kw, f_nodes, info, ocols)
+
+        def ecol(Ud):
+            return float(np.max(np.linalg.norm(Ud[:, cols].cpu().numpy() - Xref, axis=0)))
+
+        vs = {"reference": "FP64 oracle, Chebyshev route with the build's interval and L, on "
+                           "seeded columns of the identity over all M steps",
+              "columns": cols.tolist(), "oracle_s": round(o_s, 1), "e_col": ecol(U)}
+        if Uref is not None:
+            vs["fp64_e_col"] = ecol(Uref)
+        errors["vs_oracle"] = vs
+    del Uref
     if args.shard and not grad_mode:
         extra["shard"] = shard_share(ctx, U, wl, args.shard, args.warmup, args.steps,
                                      s_per_build, precision)
@@ -664,6 +800,8 @@ def main():
                    "interval": [info["e_min"], info["e_max"]], "precision": precision,
                    "scheme": wl.scheme, "parallelism": "1 GPU"},
         "build_tflops_algorithmic": round(build_tflops, 3),
+        "build_tflops_note": ALGO_NOTE if wl.layout == "dense" else
+                             "algorithmic flops per element and term of the tridiagonal pass",
         "errors": errors,
         "setup_s": round(setup_s, 3),
         "roofline": roof,

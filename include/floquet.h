@@ -80,12 +80,32 @@ typedef enum {
 typedef enum { FQ_DENSE = 0, FQ_TRIDIAG = 1, FQ_DENSE_EIGEN = 2 } fq_layout;
 
 /* Arithmetic of the Chebyshev products. FQ_FP64: everything in float64.
- * FQ_FP32: products on FP32 matrix cores with FP32 accumulation; P_l stored
- * FP32; X, the Chebyshev sum and the step phase stay float64.
- * FQ_BF16X3: products on BF16 matrix cores, each operand split into three
- * BF16 pieces (six cross products kept), FP32 accumulation; X and the
- * Chebyshev sum float64. Setup, coefficients and checks are always float64. */
+ * FQ_FP32: products on FP32 matrix cores with FP32 accumulation (the first
+ * product of a step on FP64 matrix cores); P_l stored FP32; X, the Chebyshev
+ * sum and the step phase stay float64.
+ * FQ_BF16X3: products on BF16 matrix cores with operands split into BF16
+ * pieces, each term in its own fq_term_format chosen from its Bessel weight;
+ * P_l stored as three BF16 pieces (about 24 bits); X and the Chebyshev sum
+ * float64. Setup, coefficients and checks are always float64. */
 typedef enum { FQ_FP64 = 0, FQ_FP32 = 1, FQ_BF16X3 = 2 } fq_precision;
+
+/* Format of one Chebyshev product P_l = 2 Ht P_{l-1} - P_{l-2} (P_1 = Ht X) of
+ * an FQ_BF16X3 build. Its rounding error enters the step's sum weighted by
+ * |c_l| = 2 |J_l(R)| (Sec. 2, Eq. (12)), so the library picks for each term
+ * the cheapest format whose estimated contribution stays within the error
+ * target (fq_params.mixed_tol), unless the caller fixes them. */
+typedef enum fq_term_format {
+  FQ_TERM_FP64 = 0,          /* FP64 matrix cores on FP64 operands */
+  FQ_TERM_BF16X3_F64ACC = 1, /* three BF16 pieces per operand, partial sums of
+                                each 16-column block added in FP64: about 24
+                                significant bits, independent of N */
+  FQ_TERM_BF16X3 = 2,        /* three BF16 pieces, FP32 accumulation */
+  FQ_TERM_BF16X2 = 3,        /* two BF16 pieces (about 16 bits) */
+  FQ_TERM_BF16X1 = 4,        /* one BF16 piece (about 8 bits) */
+  FQ_TERM_FP32 = 5           /* FP32 matrix cores on FP32 operands: the
+                                products of FQ_FP32 builds after their leading
+                                FP64 run (not selectable in term_formats) */
+} fq_term_format;
 
 /* The time-independent operators of H(t) = H0 + f(t) Hmod (Sec. 3, Eq. (13)),
  * or of H(t) = H0 + sum_s f_s(t) Hmod_s with several drive terms (Sec. 3 notes
@@ -183,6 +203,17 @@ typedef struct fq_params {
   int32_t scheme;            /* fq_scheme; FQ_MAGNUS6 needs FQ_DENSE and
                                 checkpoint_every == 0 (else
                                 FQ_ERR_UNSUPPORTED) */
+  double mixed_tol;          /* FQ_BF16X3 and FQ_FP32: target for the
+                                rounding error the products add to U_T (worst
+                                column 2-norm), from which each term's format
+                                is chosen (FQ_FP32: FP64 or FP32, the first
+                                term always FP64); 0 = 5e-7 */
+  const int32_t* term_formats;  /* FQ_BF16X3, host, nullable: fq_term_format of
+                                terms 1 .. n_term_formats (the last entry
+                                repeats for later terms) instead of the
+                                library's choice; FQ_TERM_FP64 only on a
+                                leading run of terms */
+  int32_t n_term_formats;    /* entries of term_formats (0 when NULL) */
 } fq_params;
 
 /* Kernel kinds timed in profile mode (indices of fq_report.ms_kernel). */
@@ -198,8 +229,16 @@ enum {
                            (streamed tridiagonal); after floquet_grad the dense
                            segment recompute's products appear under FIRST / MID /
                            LAST / HEFF */
-  FQ_K_SLOTS = 8
+  /* FQ_BF16X3 builds time their products by format instead of position: */
+  FQ_K_TERM_FP64 = 8,       /* FQ_TERM_FP64 products */
+  FQ_K_TERM_F64ACC = 9,     /* FQ_TERM_BF16X3_F64ACC */
+  FQ_K_TERM_X3 = 10,        /* FQ_TERM_BF16X3 */
+  FQ_K_TERM_X2 = 11,        /* FQ_TERM_BF16X2 */
+  FQ_K_TERM_X1 = 12,        /* FQ_TERM_BF16X1 */
+  FQ_K_CONVERT = 13,        /* FP64 planes rounded into the BF16X3 format */
+  FQ_K_SLOTS = 16
 };
+#define FQ_TERM_SLOTS 16
 
 /* Setup values and per-build measurements. */
 typedef struct fq_report {
@@ -214,6 +253,12 @@ typedef struct fq_report {
   double ms_build;           /* device time of the last build, milliseconds */
   double ms_kernel[FQ_K_SLOTS];   /* profile mode: summed event time per kind */
   int32_t n_kernel[FQ_K_SLOTS];   /* profile mode: launches per kind */
+  int32_t term_format[FQ_TERM_SLOTS];  /* FQ_BF16X3 and FQ_FP32: fq_term_format
+                                          of terms 1 .. min(L, 16) (later terms
+                                          are not listed); FQ_FP64 builds and
+                                          unused entries: -1 */
+  double mixed_err_est;           /* FQ_BF16X3 and FQ_FP32: the error estimate
+                                     the schedule was chosen for (0 otherwise) */
 } fq_report;
 
 typedef struct fq_ctx fq_ctx;  /* opaque; host memory owned by the library */

@@ -21,8 +21,14 @@ FQ_MAGNUS4, FQ_MAGNUS6, FQ_CF4 = 0, 1, 2
 SCHEMES = {"magnus4": FQ_MAGNUS4, "magnus6": FQ_MAGNUS6, "cf4": FQ_CF4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 #: kernel kinds timed in profile mode (fq_report.ms_kernel indices)
-K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 8
+K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4, 5, 16
 K_ADJ_FWD, K_ADJ_REV = 6, 7
+#: split-BF16 builds time their products by term format (fq_term_format + K_TERM_FP64)
+K_TERM_FP64, K_TERM_F64ACC, K_TERM_X3, K_TERM_X2, K_TERM_X1, K_CONVERT = 8, 9, 10, 11, 12, 13
+TERM_SLOTS = 16
+#: fq_term_format values
+TERM_FORMATS = {"fp64": 0, "bf16x3_f64acc": 1, "bf16x3": 2, "bf16x2": 3, "bf16x1": 4, "fp32": 5}
+TERM_FORMAT_NAMES = {v: k for k, v in TERM_FORMATS.items()}
 
 #: every entry point include/floquet.h declares
 EXPORTS = (
@@ -46,7 +52,9 @@ class FqParams(ctypes.Structure):
                 ("e_min", c_double), ("e_max", c_double), ("tol", c_double),
                 ("precision", c_int32), ("checkpoint_every", c_int32),
                 ("profile", c_int32), ("reorthonormalize", c_int32),
-                ("dtype", c_int32), ("scheme", c_int32)]
+                ("dtype", c_int32), ("scheme", c_int32),
+                ("mixed_tol", c_double), ("term_formats", POINTER(c_int32)),
+                ("n_term_formats", c_int32)]
 
 
 class FqReport(ctypes.Structure):
@@ -55,13 +63,14 @@ class FqReport(ctypes.Structure):
                 ("unitarity_max", c_double), ("unitarity_fro", c_double),
                 ("unitarity_max_after", c_double), ("unitarity_fro_after", c_double),
                 ("ms_build", c_double), ("ms_kernel", c_double * K_SLOTS),
-                ("n_kernel", c_int32 * K_SLOTS)]
+                ("n_kernel", c_int32 * K_SLOTS), ("term_format", c_int32 * TERM_SLOTS),
+                ("mixed_err_est", c_double)]
 
     def as_dict(self):
         out = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            out[name] = list(v) if name in ("ms_kernel", "n_kernel") else v
+            out[name] = list(v) if name in ("ms_kernel", "n_kernel", "term_format") else v
         return out
 
 

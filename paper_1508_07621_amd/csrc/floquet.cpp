@@ -106,7 +106,7 @@ constexpr int kComm6 = 9;
 struct Layout {
   size_t total = 0;
   size_t off_h0 = 0, off_v = 0, off_k = 0, off_ht = 0, off_x = 0, off_y = 0, off_pa = 0,
-         off_pb = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
+         off_pb = 0, off_pc = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
          off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0,
          off_adj = 0,
          off_comm6 = 0, off_vec = 0;
@@ -157,6 +157,7 @@ Layout plan(const fq_system* sys, const fq_params* par) {
                               : plane2;
     lay.off_pa = take(pbytes);
     lay.off_pb = take(pbytes);
+    if (par->precision != FQ_FP64) lay.off_pc = take(pbytes);
     if (par->precision != FQ_FP64) lay.off_htx = take(pbytes);
     if (par->scheme == FQ_MAGNUS6) lay.off_comm6 = take(kComm6 * plane2);
     if (par->checkpoint_every > 0) {
@@ -248,6 +249,23 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
   }
   if (par->precision < FQ_FP64 || par->precision > FQ_BF16X3)
     return fail(FQ_ERR_ARG, "unknown precision %d", par->precision);
+  if (!is_finite(par->mixed_tol) || par->mixed_tol < 0)
+    return fail(FQ_ERR_ARG, "mixed_tol must be finite and >= 0");
+  if (par->n_term_formats < 0 || (par->n_term_formats > 0) != (par->term_formats != nullptr))
+    return fail(FQ_ERR_ARG, "term_formats and n_term_formats must be given together");
+  if (par->n_term_formats > 0) {
+    if (par->precision != FQ_BF16X3)
+      return fail(FQ_ERR_ARG, "term_formats apply to FQ_BF16X3 builds only");
+    bool f64_run = true;
+    for (int l = 0; l < par->n_term_formats; ++l) {
+      const int f = par->term_formats[l];
+      if (f < FQ_TERM_FP64 || f > FQ_TERM_BF16X1)
+        return fail(FQ_ERR_ARG, "term_formats[%d] = %d is not an fq_term_format", l, f);
+      if (f == FQ_TERM_FP64 && !f64_run)
+        return fail(FQ_ERR_ARG, "FQ_TERM_FP64 only on a leading run of terms (term_formats[%d])", l);
+      f64_run = f64_run && f == FQ_TERM_FP64;
+    }
+  }
   if (par->checkpoint_every < 0) return fail(FQ_ERR_ARG, "checkpoint_every must be >= 0");
   if (par->profile != 0 && par->profile != 1) return fail(FQ_ERR_ARG, "profile must be 0 or 1");
   if (par->reorthonormalize != 0 && par->reorthonormalize != 1)
@@ -734,104 +752,296 @@ fq_status dense_heff(fq_ctx* c, int k) {
   return FQ_OK;
 }
 
-// One Chebyshev product. a, p, o are the first planes of their buffers
-// (real part first; the imaginary planes follow); `*_f64` says whether that
-// buffer holds FP64 planes (X, Y) or the product format of the context.
-fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, bool a_f64, double* p, bool p_f64,
-                      double* o, bool o_f64, std::complex<double> c0, std::complex<double> cl) {
+// One FP64 Chebyshev product. a, p, o are the first planes of their buffers
+// (real part first; the imaginary planes follow).
+fq_status cheb_launch(fq_ctx* c, int kind, int mrows, double* a, double* p, double* o,
+                      std::complex<double> c0, std::complex<double> cl) {
   const int np = (int)c->np;
   const long plane = c->np * c->np;
   static const int slot[4] = {FQ_K_FIRST, FQ_K_FIRST_LAST, FQ_K_MID, FQ_K_LAST};
   FQ_MARK(c, slot[kind]);
-  auto f64_term = [&](double* out) {
-    ChebTerm t{};
-    t.kind = kind;
-    t.a_re = a; t.a_im = a + plane;
-    t.b_re = c->htr; t.b_im = c->hti;
-    t.p_re = p; t.p_im = p + plane;
-    t.y_re = c->yr; t.y_im = c->yi;
-    t.o_re = out; t.o_im = out + plane;
-    t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
-    t.phr = c->phr; t.phi = c->phi;
-    return t;
-  };
-  const bool first = kind == fq::CHEB_FIRST || kind == fq::CHEB_FIRST_LAST;
-  if (c->precision == FQ_FP64) {
-    ChebTerm t = f64_term(o);
-    if (c->save_pl && (kind == fq::CHEB_LAST || kind == fq::CHEB_FIRST_LAST)) {
-      t.save_re = c->save_pl;
-      t.save_im = c->save_pl + plane;
-    }
-    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
-  } else if (first) {
-    // P_1 = Ht X carries the largest Chebyshev weight (|c_1| ~ R) and feeds
-    // every later term, so it is formed on FP64 matrix cores from the FP64
-    // Ht; Y takes its FP64 value. For L > 1 the product goes to the P buffer
-    // that is free until P_2 (pb) and is rounded from there into o.
-    const bool to_fmt = kind == fq::CHEB_FIRST;
-    ChebTerm t = f64_term(to_fmt ? c->pbr : o);
-    FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
-    if (to_fmt) {
-      const int pf = c->precision == FQ_FP32 ? fq::FMT_F32 : fq::FMT_BF16X3;
-      FQ_HIP(c, fq::launch_to_product(c->pbr, c->pbr + plane, o, pf, mrows, np, c->stream));
-    }
-  } else {
-    const int pf = c->precision == FQ_FP32 ? fq::FMT_F32 : fq::FMT_BF16X3;
-    fq::ChebTermX t{};
-    t.kind = kind;
-    t.a_fmt = a_f64 ? fq::FMT_F64 : pf;
-    t.p_fmt = p_f64 ? fq::FMT_F64 : pf;
-    t.o_fmt = o_f64 ? fq::FMT_F64 : pf;
-    t.plane = plane;
-    t.a = a; t.b = c->htx; t.p = p; t.o = o;
-    t.y_re = c->yr; t.y_im = c->yi;
-    t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
-    t.phr = c->phr; t.phi = c->phi;
-    FQ_HIP(c, fq::launch_cheb_mixed(t, c->precision, mrows, np, c->stream));
+  ChebTerm t{};
+  t.kind = kind;
+  t.a_re = a; t.a_im = a + plane;
+  t.b_re = c->htr; t.b_im = c->hti;
+  t.p_re = p; t.p_im = p + plane;
+  t.y_re = c->yr; t.y_im = c->yi;
+  t.o_re = o; t.o_im = o + plane;
+  t.c0r = c0.real(); t.c0i = c0.imag(); t.cr = cl.real(); t.ci = cl.imag();
+  t.phr = c->phr; t.phi = c->phi;
+  if (c->save_pl && (kind == fq::CHEB_LAST || kind == fq::CHEB_FIRST_LAST)) {
+    t.save_re = c->save_pl;
+    t.save_im = c->save_pl + plane;
   }
+  FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
   return FQ_OK;
 }
 
+fq_status dense_cheb_step_mixed(fq_ctx* c, int mrows);
+
 // One step on the state-major block held in the X planes: X <- E_k X.
-// Buffers: X and Y FP64; Pa, Pb hold P_1 .. P_L in the product format.
+// FP64 builds: X, Y, Pa and Pb hold FP64 planes (mixed builds: see
+// dense_cheb_step_mixed).
+
 fq_status dense_cheb_step(fq_ctx* c, int mrows) {
+  if (c->precision != FQ_FP64) return dense_cheb_step_mixed(c, mrows);
   const int L = c->L;
   const size_t p2bytes = 2 * sizeof(double) * (size_t)c->np * (size_t)c->np;
   auto C = [&](int l) { return std::complex<double>(c->coef[2 * l], c->coef[2 * l + 1]); };
   if (c->save_plm1 && L == 1)  // P_{L-1} = P_0 = X
     FQ_HIP(c, hipMemcpyAsync(c->save_plm1, c->xr, p2bytes, hipMemcpyDeviceToDevice, c->stream));
   if (L == 1) {  // X_new = ph (c0 X + c1 Ht X), written to Y, then the roles swap
-    FQ_TRY(cheb_launch(c, fq::CHEB_FIRST_LAST, mrows, c->xr, true, c->xr, true, c->yr, true, C(0), C(1)));
+    FQ_TRY(cheb_launch(c, fq::CHEB_FIRST_LAST, mrows, c->xr, c->xr, c->yr, C(0), C(1)));
     std::swap(c->xr, c->yr);
     std::swap(c->xi, c->yi);
     return FQ_OK;
   }
   // l = 0: P1 -> Pa, Y = c0 X + c1 P1
-  FQ_TRY(cheb_launch(c, fq::CHEB_FIRST, mrows, c->xr, true, c->xr, true, c->par, false, C(0), C(1)));
+  FQ_TRY(cheb_launch(c, fq::CHEB_FIRST, mrows, c->xr, c->xr, c->par, C(0), C(1)));
   double* prv = c->xr;  // P_{l-1}
-  bool prv_f64 = true;
   double* cur = c->par;  // P_l
   for (int l = 1; l <= L - 1; ++l) {
     const bool last = (l == L - 1);
     double* out;
-    bool out_f64 = false;
     if (last) {
       out = c->xr;  // X is free once P_2 exists (or is P_0 itself, updated in place)
-      out_f64 = true;
     } else if (l == 1) {
       out = c->pbr;  // keep X intact until P_2 is formed
     } else {
       out = prv;  // in place over P_{l-1}
     }
-    if (last && c->save_plm1)  // FP64 only: the buffers hold planar FP64 P_{L-1}
+    if (last && c->save_plm1)
       FQ_HIP(c, hipMemcpyAsync(c->save_plm1, cur, p2bytes, hipMemcpyDeviceToDevice, c->stream));
-    FQ_TRY(cheb_launch(c, last ? fq::CHEB_LAST : fq::CHEB_MID, mrows, cur, false, prv, prv_f64, out,
-                       out_f64, C(0), C(l + 1)));
+    FQ_TRY(cheb_launch(c, last ? fq::CHEB_LAST : fq::CHEB_MID, mrows, cur, prv, out, C(0),
+                       C(l + 1)));
     if (!last) {
       prv = cur;
-      prv_f64 = false;
       cur = out;
     }
+  }
+  return FQ_OK;
+}
+
+// ---- mixed-precision builds: one format per Chebyshev term -----------------------------------
+//
+// The rounding error of term l enters a step's sum weighted by |c_l| =
+// 2 |J_l(R)| (Eq. (12)), which falls off fast once l exceeds R, so each term
+// gets the cheapest format whose contribution stays within the error target.
+// Relative error (RMS over a column, relative to its norm) of one product per
+// format, u = 2^-24, nk blocks of 16 in the contraction. Leading terms from
+// the rounding analysis, constants measured on MI355X (one product of dense
+// orthonormal columns, and whole random-matrix builds at N = 1024 and 4096):
+// FP64 ~ 0; three pieces with FP64 sums per block: the 24-bit operands plus a
+// term that still grows as sqrt(nk); three pieces with FP32 running sums: the
+// FP32 roundings of the running sums, growing as sqrt(nk); two and one pieces:
+// their 16 and 8 significant bits; FP32 products (16x16x4 matrix cores): one
+// rounding of the running sum per 4 columns.
+constexpr double kErrAcc0 = 0.5, kErrAccN = 0.2;
+constexpr double kErrX30 = 1.0, kErrX3N = 0.55;
+constexpr double kErrX2 = 0.15;
+constexpr double kErrX1 = 0.6;
+constexpr double kErrF320 = 1.0, kErrF32N = 0.25;
+constexpr double kMixedTolDefault = 5e-7;  // half the 1e-6 bar of the mixed path
+
+double term_error(int tf, long nk) {
+  const double u = std::ldexp(1.0, -24), r = std::sqrt((double)nk);
+  switch (tf) {
+    case fq::TF_F64: return 0.0;
+    case fq::TF_ACC: return (kErrAcc0 + kErrAccN * r) * u;
+    case fq::TF_X3: return (kErrX30 + kErrX3N * r) * u;
+    case fq::TF_X2: return kErrX2 * std::ldexp(1.0, -16);
+    case fq::TF_F32: return (kErrF320 + kErrF32N * 2.0 * r) * u;
+    default: return kErrX1 * std::ldexp(1.0, -8);
+  }
+}
+
+// Formats of terms 1..L of a mixed build: the caller's, or the cheapest
+// schedule found as follows. Random rounding errors of the terms add in
+// quadrature over terms and steps, so the estimate for U_T is
+// sqrt(sum_l (|c_l| eps_l)^2 M). Each term takes the cheapest format whose own
+// contribution |c_l| eps_l sqrt(M) is within a per-term allowance, starting at
+// the whole target and shrinking until the total meets it; FP64 terms are then
+// extended to a leading run (the step converts from FP64 planes to the low
+// format once).
+void choose_schedule(fq_ctx* c, const fq_params* par) {
+  const int L = c->L;
+  const bool f32 = c->precision == FQ_FP32;
+  c->term_fmt.assign(L + 1, f32 ? fq::TF_F32 : fq::TF_X3);
+  const long nk = c->np / 16;
+  const double tol = par->mixed_tol > 0 ? par->mixed_tol : kMixedTolDefault;
+  const double sm = std::sqrt((double)c->M);
+  auto contribution = [&](int l, int f) { return std::fabs(c->weights[l]) * sm * term_error(f, nk); };
+  auto total = [&]() {
+    double e2 = 0.0;
+    for (int l = 1; l <= L; ++l) {
+      const double e = contribution(l, c->term_fmt[l]);
+      e2 += e * e;
+    }
+    return std::sqrt(e2);
+  };
+  if (par->n_term_formats > 0) {
+    for (int l = 1; l <= L; ++l)
+      c->term_fmt[l] = par->term_formats[std::min(l, par->n_term_formats) - 1];
+  } else {
+    double allowance = tol;
+    for (int pass = 0; pass < 64; ++pass, allowance *= 0.7) {
+      // FQ_FP32: FP32 products after a leading FP64 run of at least one term
+      int last_f64 = f32 ? 1 : 0;
+      for (int l = 1; l <= L; ++l) {
+        int f = fq::TF_F64;
+        if (f32) {
+          if (contribution(l, fq::TF_F32) <= allowance) f = fq::TF_F32;
+        } else {
+          for (int cand : {fq::TF_X1, fq::TF_X2, fq::TF_X3, fq::TF_ACC})
+            if (contribution(l, cand) <= allowance) {
+              f = cand;
+              break;
+            }
+        }
+        c->term_fmt[l] = f;
+        if (f == fq::TF_F64) last_f64 = l;
+      }
+      for (int l = 1; l <= std::min(last_f64, L); ++l) c->term_fmt[l] = fq::TF_F64;
+      if (total() <= tol) break;
+    }
+  }
+  c->mixed_err_est = total();
+}
+
+// One mixed-precision step on the state-major block in the X planes:
+// X <- E_k X. FP64 terms (a leading run of h terms) rotate FP64 planes through
+// Pa and Pb; the output of the last one goes to Pc and is rounded into the low
+// format (BF16X3 or FP32) for the next product's A operand; low-format terms
+// then run in place over P_{l-2} whenever it is in the low format too. The
+// last term writes X.
+fq_status dense_cheb_step_mixed(fq_ctx* c, int mrows) {
+  const int L = c->L, np = (int)c->np;
+  const long plane = c->np * c->np;
+  auto C = [&](int l) { return std::complex<double>(c->coef[2 * l], c->coef[2 * l + 1]); };
+  int h = 0;
+  while (h < L && c->term_fmt[h + 1] == fq::TF_F64) ++h;
+  struct Buf {
+    double* p;
+    bool f64;
+  };
+  auto kind_of = [&](int l) {  // position of term l (1-based) in the step
+    if (l == 1) return L == 1 ? fq::CHEB_FIRST_LAST : fq::CHEB_FIRST;
+    return l == L ? fq::CHEB_LAST : fq::CHEB_MID;
+  };
+  // term l from A = a (P_{l-1}; X for l = 1), prev = p (P_{l-2}; X for l <= 2)
+  const bool f32 = c->precision == FQ_FP32;
+  const int low = f32 ? fq::FMT_F32 : fq::FMT_BF16X3;  // storage of the non-FP64 terms
+  auto term = [&](int l, Buf a, Buf p, Buf o) -> fq_status {
+    const int kind = kind_of(l), tf = c->term_fmt[l];
+    // split-BF16 builds time products by format, FP32 builds by position
+    static const int slot[4] = {FQ_K_FIRST, FQ_K_FIRST_LAST, FQ_K_MID, FQ_K_LAST};
+    FQ_MARK(c, f32 ? slot[kind] : FQ_K_TERM_FP64 + tf);
+    if (tf == fq::TF_F64) {
+      ChebTerm t{};
+      t.kind = kind;
+      t.a_re = a.p; t.a_im = a.p + plane;
+      t.b_re = c->htr; t.b_im = c->hti;
+      t.p_re = p.p; t.p_im = p.p + plane;
+      t.y_re = c->yr; t.y_im = c->yi;
+      t.o_re = o.p; t.o_im = o.p + plane;
+      t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(l).real(); t.ci = C(l).imag();
+      t.phr = c->phr; t.phi = c->phi;
+      FQ_HIP(c, fq::launch_cheb_f64(t, mrows, np, c->stream));
+      return FQ_OK;
+    }
+    fq::ChebTermX t{};
+    t.kind = kind;
+    t.a_fmt = low;
+    t.p_fmt = p.f64 ? fq::FMT_F64 : low;
+    t.o_fmt = o.f64 ? fq::FMT_F64 : low;
+    t.plane = plane;
+    t.a = a.p; t.b = c->htx; t.p = p.p; t.o = o.p;
+    t.y_re = c->yr; t.y_im = c->yi;
+    t.c0r = C(0).real(); t.c0i = C(0).imag(); t.cr = C(l).real(); t.ci = C(l).imag();
+    t.phr = c->phr; t.phi = c->phi;
+    if (f32)
+      FQ_HIP(c, fq::launch_cheb_mixed(t, FQ_FP32, mrows, np, c->stream));
+    else
+      FQ_HIP(c, fq::launch_cheb_bf16(t, tf, mrows, np, c->stream));
+    return FQ_OK;
+  };
+  auto convert = [&](double* src, double* dst) -> fq_status {
+    FQ_MARK(c, FQ_K_CONVERT);
+    FQ_HIP(c, fq::launch_to_product(src, src + plane, dst, low, mrows, np, c->stream));
+    return FQ_OK;
+  };
+  const Buf X{c->xr, true};
+  Buf A{c->par, true}, B{c->pbr, true}, S{c->pcr, true};
+  if (h == L) {  // every term in FP64: the FP64 rotation through A and B
+    if (L == 1) {  // X_new = ph (c0 X + c1 Ht X) to Y (A = X is read by every tile), then swap
+      FQ_TRY(term(1, X, X, Buf{c->yr, true}));
+      std::swap(c->xr, c->yr);
+      std::swap(c->xi, c->yi);
+      return FQ_OK;
+    }
+    FQ_TRY(term(1, X, X, A));
+    Buf prv = X, cur = A;
+    for (int l = 2; l <= L; ++l) {
+      const Buf out = l == L ? X : (l == 2 ? B : prv);
+      FQ_TRY(term(l, cur, prv, out));
+      prv = cur;
+      cur = out;
+    }
+    return FQ_OK;
+  }
+  Buf prv, cur;  // P_{l-2}, P_{l-1} before term l
+  int l0;        // first BF16 term
+  if (h == 0) {
+    // X's BF16 copy for the first product's A operand, in B (free until term 2)
+    FQ_TRY(convert(c->xr, B.p));
+    const Buf xb{B.p, false};
+    if (L == 1) return term(1, xb, X, X);
+    A.f64 = false;
+    FQ_TRY(term(1, xb, X, A));
+    prv = X;
+    cur = A;
+    B.f64 = false;
+    l0 = 2;
+  } else {
+    // FP64 terms 1..h; term h writes S, rounded into the buffer term h read as
+    // P_{h-2} (B for h = 1 and h = 2), which is free from then on
+    Buf p2 = X, p1 = X;  // P_{l-2}, P_{l-1}
+    for (int l = 1; l <= h; ++l) {
+      Buf out = l == h ? S : (l == 1 ? A : (l == 2 ? B : p2));
+      FQ_TRY(term(l, p1, p2, out));
+      p2 = p1;
+      p1 = out;
+    }
+    // p1 = S holds P_h (FP64); p2 holds P_{h-1} (FP64)
+    Buf dst = (h <= 2) ? B : (p2.p == A.p ? B : A);
+    FQ_TRY(convert(S.p, dst.p));
+    dst.f64 = false;
+    prv = p2;   // P_{h-1}, FP64 (X when h = 1)
+    cur = dst;  // P_h, BF16
+    S.f64 = false;
+    l0 = h + 1;
+    // the FP64 buffers that no longer hold a live term become BF16 scratch
+    if (dst.p == B.p) B = dst; else A = dst;
+  }
+  for (int l = l0; l <= L; ++l) {
+    Buf out;
+    if (l == L) {
+      out = X;
+    } else if (!prv.f64) {
+      out = prv;  // in place over P_{l-2}
+    } else {
+      // P_{l-2} is FP64 (X, or the last FP64 term): a BF16 buffer that is neither operand
+      Buf cands[3] = {Buf{A.p, false}, Buf{B.p, false}, Buf{S.p, false}};
+      out = cands[0];
+      for (const Buf& q : cands)
+        if (q.p != cur.p && q.p != prv.p) {
+          out = q;
+          break;
+        }
+    }
+    FQ_TRY(term(l, cur, prv, out));
+    prv = cur;
+    cur = out;
   }
   return FQ_OK;
 }
@@ -914,6 +1124,10 @@ fq_status finish_reortho(fq_ctx* c, void* U_out) {
 }
 
 void fill_report(fq_ctx* c) {
+  for (int l = 0; l < FQ_TERM_SLOTS; ++l)
+    c->last.term_format[l] =
+        l < c->L && !c->term_fmt.empty() ? c->term_fmt[l + 1] : -1;
+  c->last.mixed_err_est = c->mixed_err_est;
   c->last.L = c->L;
   c->last.M = c->M_user;
   c->last.R = c->R;
@@ -1579,6 +1793,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     c->par = P(lay.off_pa); c->pai = c->par + plane;
     c->pbr = P(lay.off_pb); c->pbi = c->pbr + plane;
     if (par->precision != FQ_FP64) c->htx = P(lay.off_htx);
+    if (par->precision != FQ_FP64) c->pcr = P(lay.off_pc);
     if (par->scheme == FQ_MAGNUS6) c->comm6 = P(lay.off_comm6);
     if (lay.n_tape > 0) {
       c->tape = P(lay.off_tape);
@@ -1679,6 +1894,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     c->coef[2 * l] = (q == 0) ? w : (q == 2 ? -w : 0.0);
     c->coef[2 * l + 1] = (q == 1) ? -w : (q == 3 ? w : 0.0);
   }
+  if (c->precision != FQ_FP64 && c->layout == FQ_DENSE) choose_schedule(c, par);
   c->phr = std::cos(c->beta * c->h);
   c->phi = -std::sin(c->beta * c->h);
   std::vector<double> ab(2 * c->M);

@@ -95,9 +95,24 @@ struct ChebTermX {
   double c0r, c0i, cr, ci, phr, phi;
 };
 
-// Products P_{l+1} = 2 Ht P_l - P_{l-1} (l >= 1) with A = P_l in the product
-// format; precision: FQ_FP32 or FQ_BF16X3 (FP32 or BF16 matrix cores).
+// FP32 products P_{l+1} = 2 Ht P_l - P_{l-1} (l >= 1) with A = P_l in FP32
+// (precision FQ_FP32; FP32 matrix cores).
 hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s);
+
+// Formats of the Chebyshev products of a mixed build, one per term,
+// chosen on the host from the term's Bessel weight (fq_ctx::term_fmt):
+// TF_F64: FP64 matrix cores on FP64 operands; TF_ACC: three BF16 pieces per
+// operand with FP64 accumulation per k-block (about 24 bits independently of
+// N); TF_X3 / TF_X2 / TF_X1: three / two / one BF16 pieces with FP32
+// accumulation (about 24 bits less the accumulation error, 16 bits, 8 bits).
+// FQ_FP32 builds use TF_F64 and TF_F32 (FP32 matrix cores, FP32 operands).
+enum TermFmt : int { TF_F64 = 0, TF_ACC = 1, TF_X3 = 2, TF_X2 = 3, TF_X1 = 4, TF_F32 = 5 };
+
+// Split-BF16 product of one term in term_fmt (TF_ACC .. TF_X1). A: BF16X3 (P_l,
+// or X's BF16X3 copy for CHEB_FIRST / CHEB_FIRST_LAST); P_{l-1}: BF16X3 or FP64
+// (X for the first product, for c_0 X); output BF16X3 (FIRST, MID) or FP64
+// X_k (LAST, FIRST_LAST). mrows and np multiples of 64.
+hipError_t launch_cheb_bf16(const ChebTermX& t, int term_fmt, int mrows, int np, hipStream_t s);
 // FP64 planes (rows [0, mrows) of an np x np pair, row stride np) rounded into
 // the product format `fmt` (FMT_F32 planar or FMT_BF16X3 k-blocked) at `out`.
 // The first product of a mixed-precision step runs on FP64 matrix cores and
@@ -349,6 +364,9 @@ struct fq_ctx {
   double *xr = nullptr, *xi = nullptr, *yr = nullptr, *yi = nullptr;
   double *par = nullptr, *pai = nullptr, *pbr = nullptr, *pbi = nullptr;
   void* htx = nullptr;                // mixed builds: rescaled H in the product format
+  double* pcr = nullptr;              // mixed builds: a third P buffer (format changes)
+  std::vector<int> term_fmt;          // mixed builds: TermFmt of terms 1..L (index 0 unused)
+  double mixed_err_est = 0.0;         // the schedule's estimate of the error it adds to U_T
   double* tape = nullptr;             // checkpoints, each 2 planes
   int n_tape = 0;
   // gradient: per segment step X_{k-1}, P_{L-1}, P_L; two stacks; Lambda; d/da, d/db per step

@@ -267,33 +267,56 @@ __device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c) {
 }
 
 struct Bf3Args {
-  const u16* a;        // A, k-blocked BF16X3 (row capacity np)
+  const u16* a;        // A, k-blocked BF16X3 (row capacity np): P_l, or X for the first product
   const u16* b;        // B = Ht, k-blocked BF16X3
-  const void* p;       // P_{l-1}: k-blocked BF16X3, or FP64 planes (P_0 = X)
+  const void* p;       // P_{l-1}: k-blocked BF16X3, or FP64 planes (P_0 = X; X itself for the
+                       // first product, whose sum starts with c_0 X)
   void* o;             // P_{l+1} (k-blocked BF16X3) or X_k (FP64 planes, last product)
   double* y_re;        // Chebyshev sum, FP64 planes
   double* y_im;
   long plane;          // np * np
   int np;
   int tiles_m, tiles_n;
-  double cr, ci, phr, phi;
+  double c0r, c0i, cr, ci, phr, phi;
 };
 
-template <int BM, int BN, int WGM, int WGN, int KIND, bool P_F64>
+// The leading `npc` pieces of x (fp32): hi, or hi and mid, or all three.
+template <int NPC>
+__device__ __forceinline__ void split_n(float x, u16* out) {
+  if constexpr (NPC == 3) {
+    split3(x, out[0], out[1], out[2]);
+  } else {
+    const __bf16 bh = (__bf16)x;
+    out[0] = bf16_bits(bh);
+    if constexpr (NPC == 2) out[1] = bf16_bits((__bf16)(x - (float)bh));
+  }
+}
+
+// Split-BF16 product on 32x32x16 matrix cores with NPC = 1, 2 or 3 pieces per
+// operand: the piece pairs of weight at least 2^-8 (NPC - 1) of the leading one
+// ((hh); (hh, hm, mh); (hh, hm, mh, hl, mm, lh)), so the product carries about
+// 8, 16 or 24 significant bits. The stored matrices always hold three pieces;
+// fewer pieces read fewer planes. KIND CHEB_FIRST / CHEB_FIRST_LAST take
+// A = X (a BF16X3 copy) and p = X in FP64 for the c_0 X of the sum.
+template <int BM, int BN, int WGM, int WGN, int KIND, bool P_F64, int NPC>
 __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 32, FN = WTN / 32;
-  constexpr int NP = BF3_LDS_PLANES;         // planes in LDS (re, im, re + im pieces)
-  constexpr int NS = BF3_PLANES;             // stored planes (re, im pieces)
+  constexpr int NL = 2 * NPC;                // stored planes read per operand (re, im pieces)
+  constexpr int NP = 3 * NPC;                // planes in LDS (re, im, re + im pieces)
+  constexpr int NS = BF3_PLANES;             // stored planes written by the epilogue
   constexpr int SA = BM * 32, SB = BN * 32;  // bytes per plane and k-block
   constexpr int STAGE = NP * (SA + SB);
   constexpr int NCA = 2 * BM;                // 16-byte chunks of A per plane and k-block
   constexpr int EPI = 2 * BM * BN * 4;       // FP32 Re, Im in k-blocked order
   constexpr int SMEM = (2 * STAGE > EPI) ? 2 * STAGE : EPI;
+  constexpr bool FIRST = KIND == CHEB_FIRST || KIND == CHEB_FIRST_LAST;
+  constexpr bool TO_X = KIND == CHEB_LAST || KIND == CHEB_FIRST_LAST;  // FP64 X_k out
   static_assert(2 * (BM + BN) == NT, "one 16-byte chunk column of A or B per thread");
   static_assert(FM >= 1 && FN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile");
-  static_assert(KIND == CHEB_MID || KIND == CHEB_LAST, "kind");
+  static_assert(NPC >= 1 && NPC <= 3, "pieces");
+  static_assert(!FIRST || P_F64, "the first product reads X in FP64");
 
   __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
 
@@ -313,37 +336,44 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
   const u16* src = is_a ? g.a + (long)m0 * 16 + cq * 8 : g.b + (long)n0 * 16 + cq * 8;
   const int ldst = is_a ? cq * 16 : NP * SA + cq * 16;
   const int pstep = is_a ? SA : SB;
-  u32x4 st[NS];
+  u32x4 st[NL];
   auto gload = [&](int kb) {
 #pragma unroll
-    for (int p = 0; p < NS; ++p)
+    for (int p = 0; p < NPC; ++p) {
       st[p] = *reinterpret_cast<const u32x4*>(src + p * plane + kb * kstride);
+      st[NPC + p] = *reinterpret_cast<const u32x4*>(src + (3 + p) * plane + kb * kstride);
+    }
   };
   auto lstore = [&](int buf) {
     unsigned char* d = smem + buf * STAGE + ldst;
 #pragma unroll
-    for (int p = 0; p < NS; ++p) *reinterpret_cast<u32x4*>(d + p * pstep) = st[p];
-    u32x4 sum[3];
+    for (int p = 0; p < NL; ++p) *reinterpret_cast<u32x4*>(d + p * pstep) = st[p];
+    u32x4 sum[NPC];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      uint32_t o[3] = {0u, 0u, 0u};
+      uint32_t o[NPC];
+#pragma unroll
+      for (int q = 0; q < NPC; ++q) o[q] = 0u;
 #pragma unroll
       for (int hf = 0; hf < 2; ++hf) {
         const int sh = 16 * hf;
         auto piece = [&](int p) { return bf16_val((u16)(st[p][w] >> sh)); };
-        const float re = (piece(0) + piece(1)) + piece(2);
-        const float im = (piece(3) + piece(4)) + piece(5);
-        u16 h, md, l;
-        split3(re + im, h, md, l);
-        o[0] |= (uint32_t)h << sh;
-        o[1] |= (uint32_t)md << sh;
-        o[2] |= (uint32_t)l << sh;
+        float re = piece(0), im = piece(NPC);
+#pragma unroll
+        for (int p = 1; p < NPC; ++p) {
+          re += piece(p);
+          im += piece(NPC + p);
+        }
+        u16 hs[NPC];
+        split_n<NPC>(re + im, hs);
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) o[q] |= (uint32_t)hs[q] << sh;
       }
 #pragma unroll
-      for (int q = 0; q < 3; ++q) sum[q][w] = o[q];
+      for (int q = 0; q < NPC; ++q) sum[q][w] = o[q];
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) *reinterpret_cast<u32x4*>(d + (NS + q) * pstep) = sum[q];
+    for (int q = 0; q < NPC; ++q) *reinterpret_cast<u32x4*>(d + (NL + q) * pstep) = sum[q];
   };
 
   // Fragment offsets (bytes within a plane of a stage).
@@ -388,18 +418,22 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
       bf8 fa[NP];
 #pragma unroll
       for (int p = 0; p < NP; ++p) fa[p] = *reinterpret_cast<const bf8*>(sb + p * SA + aoff[i]);
-#define FQ_PAIR(pa, pb)                                                     \
-  _Pragma("unroll") for (int j = 0; j < FN; ++j) {                          \
-    t1[i][j] = mfma32_bf16(fa[pa], fb[pb][j], t1[i][j]);                    \
-    t2[i][j] = mfma32_bf16(fa[3 + pa], fb[3 + pb][j], t2[i][j]);            \
-    t3[i][j] = mfma32_bf16(fa[6 + pa], fb[6 + pb][j], t3[i][j]);            \
+#define FQ_PAIR(pa, pb)                                                         \
+  _Pragma("unroll") for (int j = 0; j < FN; ++j) {                              \
+    t1[i][j] = mfma32_bf16(fa[pa], fb[pb][j], t1[i][j]);                        \
+    t2[i][j] = mfma32_bf16(fa[NPC + pa], fb[NPC + pb][j], t2[i][j]);            \
+    t3[i][j] = mfma32_bf16(fa[2 * NPC + pa], fb[2 * NPC + pb][j], t3[i][j]);    \
   }
       FQ_PAIR(0, 0)
-      FQ_PAIR(0, 1)
-      FQ_PAIR(1, 0)
-      FQ_PAIR(0, 2)
-      FQ_PAIR(1, 1)
-      FQ_PAIR(2, 0)
+      if constexpr (NPC >= 2) {
+        FQ_PAIR(0, 1)
+        FQ_PAIR(1, 0)
+      }
+      if constexpr (NPC >= 3) {
+        FQ_PAIR(0, 2)
+        FQ_PAIR(1, 1)
+        FQ_PAIR(2, 0)
+      }
 #undef FQ_PAIR
     }
     // After this k-block's products: the next k-block (in registers since the
@@ -445,7 +479,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
     *reinterpret_cast<f4*>(ar + 4) = *reinterpret_cast<const f4*>(cre + q * 8 + 4);
     *reinterpret_cast<f4*>(ai) = *reinterpret_cast<const f4*>(cim + q * 8);
     *reinterpret_cast<f4*>(ai + 4) = *reinterpret_cast<const f4*>(cim + q * 8 + 4);
-    // P_{l-1}
+    // P_{l-1} (X for the first product)
     double pr[8], pi[8];
     if constexpr (P_F64) {
       const double* p = static_cast<const double*>(g.p) + m * np + n;
@@ -475,11 +509,14 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
     }
     double* yr = g.y_re + m * np + n;
     double* yi = g.y_im + m * np + n;
-    if constexpr (KIND == CHEB_MID) {
+    if constexpr (!TO_X) {
+      // P_{l+1} = 2 acc - P_{l-1}, or P_1 = acc: stored as BF16X3, and its
+      // stored value weighted into Y (Y = c_0 X + c_1 P_1 for the first)
       u32x4 w[NS];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const double orr = 2.0 * (double)ar[e] - pr[e], oii = 2.0 * (double)ai[e] - pi[e];
+        const double orr = FIRST ? (double)ar[e] : 2.0 * (double)ar[e] - pr[e];
+        const double oii = FIRST ? (double)ai[e] : 2.0 * (double)ai[e] - pi[e];
         u16 hs[NS];
         split3((float)orr, hs[0], hs[1], hs[2]);
         split3((float)oii, hs[3], hs[4], hs[5]);
@@ -490,44 +527,224 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
           else
             w[k][e >> 1] = hs[k];
         }
-        // the value the pieces hold
-        pr[e] = (double)(bf16_val(hs[0]) + bf16_val(hs[1]) + bf16_val(hs[2]));
-        pi[e] = (double)(bf16_val(hs[3]) + bf16_val(hs[4]) + bf16_val(hs[5]));
+        // the value the pieces hold; for the first product P_0 = X stays in (pr, pi)
+        const double vr = (double)(bf16_val(hs[0]) + bf16_val(hs[1]) + bf16_val(hs[2]));
+        const double vi = (double)(bf16_val(hs[3]) + bf16_val(hs[4]) + bf16_val(hs[5]));
+        if constexpr (FIRST) {
+          const double xr = pr[e], xi = pi[e];
+          pr[e] = g.c0r * xr - g.c0i * xi + cr_ * vr - ci_ * vi;
+          pi[e] = g.c0r * xi + g.c0i * xr + cr_ * vi + ci_ * vr;
+        } else {
+          pr[e] = vr;
+          pi[e] = vi;
+        }
       }
       u16* o = static_cast<u16*>(g.o) + chunk;
 #pragma unroll
       for (int k = 0; k < NS; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
-        d2 vr = *reinterpret_cast<const d2*>(yr + e);
-        d2 vi = *reinterpret_cast<const d2*>(yi + e);
+        d2 vr, vi;
+        if constexpr (FIRST) {
+          vr = d2{pr[e], pr[e + 1]};
+          vi = d2{pi[e], pi[e + 1]};
+        } else {
+          vr = *reinterpret_cast<const d2*>(yr + e);
+          vi = *reinterpret_cast<const d2*>(yi + e);
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          vr[u] += cr_ * pr[e + u] - ci_ * pi[e + u];
-          vi[u] += cr_ * pi[e + u] + ci_ * pr[e + u];
+          for (int u = 0; u < 2; ++u) {
+            vr[u] += cr_ * pr[e + u] - ci_ * pi[e + u];
+            vi[u] += cr_ * pi[e + u] + ci_ * pr[e + u];
+          }
         }
         *reinterpret_cast<d2*>(yr + e) = vr;
         *reinterpret_cast<d2*>(yi + e) = vi;
       }
-    } else {  // CHEB_LAST: X_k = ph (Y + c_L (2 acc - P_{L-1}))
+    } else {  // X_k = ph (Y + c_L (2 acc - P_{L-1})), or ph (c_0 X + c_1 acc) when L = 1
       double* o = static_cast<double*>(g.o) + m * np + n;
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
-        const d2 vr = *reinterpret_cast<const d2*>(yr + e);
-        const d2 vi = *reinterpret_cast<const d2*>(yi + e);
         d2 xr, xi;
+        d2 vr = d2{0.0, 0.0}, vi = d2{0.0, 0.0};
+        if constexpr (!FIRST) {
+          vr = *reinterpret_cast<const d2*>(yr + e);
+          vi = *reinterpret_cast<const d2*>(yi + e);
+        }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const double qr = 2.0 * (double)ar[e + u] - pr[e + u];
-          const double qi = 2.0 * (double)ai[e + u] - pi[e + u];
-          const double sr = vr[u] + cr_ * qr - ci_ * qi;
-          const double si = vi[u] + cr_ * qi + ci_ * qr;
+          double qr, qi, sr, si;
+          if constexpr (FIRST) {
+            qr = (double)ar[e + u];
+            qi = (double)ai[e + u];
+            sr = g.c0r * pr[e + u] - g.c0i * pi[e + u];
+            si = g.c0r * pi[e + u] + g.c0i * pr[e + u];
+          } else {
+            qr = 2.0 * (double)ar[e + u] - pr[e + u];
+            qi = 2.0 * (double)ai[e + u] - pi[e + u];
+            sr = vr[u];
+            si = vi[u];
+          }
+          sr += cr_ * qr - ci_ * qi;
+          si += cr_ * qi + ci_ * qr;
           xr[u] = g.phr * sr - g.phi * si;
           xi[u] = g.phr * si + g.phi * sr;
         }
         *reinterpret_cast<d2*>(o + e) = xr;
         *reinterpret_cast<d2*>(o + plane + e) = xi;
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Split-BF16 product with FP64 accumulation, for the terms whose Bessel weight
+// is too large for FP32 accumulators (P_1 of every step, and any term with a
+// comparable weight). Each operand is split into three BF16 pieces; per k-block
+// of 16 columns the six kept piece pairs of the four real products
+// (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br) go into FP32 partial sums that
+// start from zero, smallest pairs first, and are then added into FP64 sums.
+// The error of a product is then a few FP32 roundings of one k-block's partial
+// sum instead of one per accumulation over the whole contraction, so the
+// product carries about 24 significant bits independently of N. Tile BM x 64
+// (BM = 128 or 64), waves of 32 x 32; two LDS stages of the six stored planes. The
+// epilogue works from the FP64 sums in registers: the Chebyshev sum Y takes
+// the unrounded FP64 term, the stored P_{l+1} its BF16X3 rounding.
+// ---------------------------------------------------------------------------------------------
+template <int BM, int KIND, bool P_F64>
+__global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
+  constexpr int BN = 64, WGN = 2, NT = BM * 4;
+  constexpr int NS = BF3_PLANES;             // 6 planes: re pieces, im pieces
+  constexpr int SA = BM * 32, SB = BN * 32;  // bytes per plane and k-block
+  constexpr int STAGE = NS * (SA + SB);
+  constexpr int NCA = 2 * BM, NCB = 2 * BN;  // 16-byte chunk columns of A, B
+  constexpr bool FIRST = KIND == CHEB_FIRST || KIND == CHEB_FIRST_LAST;
+  constexpr bool TO_X = KIND == CHEB_LAST || KIND == CHEB_FIRST_LAST;
+  static_assert(!FIRST || P_F64, "the first product reads X in FP64");
+
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * STAGE];
+
+  int tm, tn;
+  tile_coords(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
+  if (tm >= g.tiles_m) return;  // grid padding
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / WGN, wn = wid % WGN;
+  const long np = g.np, plane = g.plane;
+  const int nk = g.np / 16;
+  const long kstride = np * 16;
+
+  // Staging: threads [0, NCA) take a chunk column of A, [NCA, NCA + NCB) of B.
+  const bool stager = tid < NCA + NCB;
+  const bool is_a = tid < NCA;
+  const int cq = is_a ? tid : tid - NCA;
+  const u16* src = is_a ? g.a + (long)m0 * 16 + cq * 8 : g.b + (long)n0 * 16 + cq * 8;
+  const int ldst = is_a ? cq * 16 : NS * SA + cq * 16;
+  const int pstep = is_a ? SA : SB;
+  u32x4 st[NS];
+  auto gload = [&](int kb) {
+    if (!stager) return;
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+      st[p] = *reinterpret_cast<const u32x4*>(src + p * plane + kb * kstride);
+  };
+  auto lstore = [&](int buf) {
+    if (!stager) return;
+    unsigned char* d = smem + buf * STAGE + ldst;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) *reinterpret_cast<u32x4*>(d + p * pstep) = st[p];
+  };
+
+  const int arow = wm * 32 + (lane & 31), brow = wn * 32 + (lane & 31);
+  const int aoff = arow * 32 + 16 * ((lane >> 5) ^ ((arow >> 3) & 1));
+  const int boff = NS * SA + brow * 32 + 16 * ((lane >> 5) ^ ((brow >> 3) & 1));
+
+  double sre[16], sim[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sre[r] = sim[r] = 0.0;
+  f16v zero;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) zero[r] = 0.f;
+
+  gload(0);
+  lstore(0);
+  gload(nk > 1 ? 1 : 0);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const unsigned char* sb = smem + (kb & 1) * STAGE;
+    bf8 fa[NS], fb[NS], na[3];
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      fa[p] = *reinterpret_cast<const bf8*>(sb + p * SA + aoff);
+      fb[p] = *reinterpret_cast<const bf8*>(sb + p * SB + boff);
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {  // -Ai pieces: flip the sign bits
+      u32x4 w = __builtin_bit_cast(u32x4, fa[3 + p]);
+      w ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+      na[p] = __builtin_bit_cast(bf8, w);
+    }
+    // pairs (i, j) with i + j <= 2, the two hi x hi products last
+    f16v pre = mfma32_bf16(fa[2], fb[0], zero);
+    f16v pim = mfma32_bf16(fa[2], fb[3], zero);
+    pre = mfma32_bf16(na[2], fb[3], pre);
+    pim = mfma32_bf16(fa[5], fb[0], pim);
+#define FQ_ACC_PAIR(i, j)                          \
+  pre = mfma32_bf16(fa[i], fb[j], pre);            \
+  pre = mfma32_bf16(na[i], fb[3 + (j)], pre);      \
+  pim = mfma32_bf16(fa[i], fb[3 + (j)], pim);      \
+  pim = mfma32_bf16(fa[3 + (i)], fb[j], pim);
+    FQ_ACC_PAIR(1, 1)
+    FQ_ACC_PAIR(0, 2)
+    FQ_ACC_PAIR(1, 0)
+    FQ_ACC_PAIR(0, 1)
+    FQ_ACC_PAIR(0, 0)
+#undef FQ_ACC_PAIR
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      sre[r] += (double)pre[r];
+      sim[r] += (double)pim[r];
+    }
+    lstore((kb & 1) ^ 1);
+    gload(kb + 2 < nk ? kb + 2 : nk - 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue, from the FP64 sums (lane: column n, rows of the 32 x 32 tile) ----
+  const long n = n0 + wn * 32 + (lane & 31);
+  const double cr_ = g.cr, ci_ = g.ci;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    // four rows at a time: keeps the scheduler from hoisting every row's loads
+    // above the others' stores (that spills with the FP64 sums live)
+    if (r % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+    const long m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const long idx = m * np + n;
+    double pr, pi;
+    load_c(g.p, P_F64 ? FMT_F64 : FMT_BF16X3, plane, m, n, np, pr, pi);
+    double vr, vi;  // the term P_l (or the product for the first)
+    if constexpr (FIRST) {
+      vr = sre[r];
+      vi = sim[r];
+    } else {
+      vr = 2.0 * sre[r] - pr;
+      vi = 2.0 * sim[r] - pi;
+    }
+    double sr, si;
+    if constexpr (FIRST) {
+      sr = g.c0r * pr - g.c0i * pi + cr_ * vr - ci_ * vi;
+      si = g.c0r * pi + g.c0i * pr + cr_ * vi + ci_ * vr;
+    } else {
+      sr = g.y_re[idx] + cr_ * vr - ci_ * vi;
+      si = g.y_im[idx] + cr_ * vi + ci_ * vr;
+    }
+    if constexpr (TO_X) {
+      double* o = static_cast<double*>(g.o);
+      o[idx] = g.phr * sr - g.phi * si;
+      o[plane + idx] = g.phr * si + g.phi * sr;
+    } else {
+      store_c(g.o, FMT_BF16X3, plane, m, n, np, vr, vi);
+      g.y_re[idx] = sr;
+      g.y_im[idx] = si;
     }
   }
 }
@@ -552,19 +769,19 @@ hipError_t launch_f32(MixOperands op, int mrows, int np, Epi epi, hipStream_t s)
   return hipGetLastError();
 }
 
-template <int KIND, bool P_F64>
+template <int KIND, bool P_F64, int NPC>
 hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
   Bf3Args g = g0;
   const int np = g.np;
   if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= kBigTileElems) {
     g.tiles_m = mrows / 128;
     g.tiles_n = np / 128;
-    hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64>),
+    hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64, NPC>),
                        dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(512), 0, s, g);
   } else if (mrows % 64 == 0 && np % 64 == 0) {
     g.tiles_m = mrows / 64;
     g.tiles_n = np / 64;
-    hipLaunchKernelGGL((cheb_bf3_kernel<64, 64, 2, 2, KIND, P_F64>),
+    hipLaunchKernelGGL((cheb_bf3_kernel<64, 64, 2, 2, KIND, P_F64, NPC>),
                        dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(256), 0, s, g);
   } else {
     return hipErrorInvalidValue;
@@ -572,9 +789,41 @@ hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Split-BF16 product of kind CHEB_MID (P_{l+1} in BF16X3) or CHEB_LAST (X_k in
-// FP64); A = P_l in BF16X3, P_{l-1} in BF16X3 or FP64 (P_0 = X).
-hipError_t dispatch_bf3(const ChebTermX& t, int mrows, int np, hipStream_t s) {
+template <int KIND, bool P_F64>
+hipError_t launch_acc(const Bf3Args& g0, int mrows, hipStream_t s) {
+  Bf3Args g = g0;
+  if (mrows % 64 != 0 || g.np % 64 != 0) return hipErrorInvalidValue;
+  g.tiles_n = g.np / 64;
+  // 128-row tiles when they still give every CU a workgroup
+  if (mrows % 128 == 0 && (long)(mrows / 128) * g.tiles_n >= 256) {
+    g.tiles_m = mrows / 128;
+    hipLaunchKernelGGL((cheb_acc_kernel<128, KIND, P_F64>),
+                       dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(512), 0, s, g);
+  } else {
+    g.tiles_m = mrows / 64;
+    hipLaunchKernelGGL((cheb_acc_kernel<64, KIND, P_F64>),
+                       dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+// One kind and P_{l-1} format of a split-BF16 product, in the given term format.
+template <int KIND, bool P_F64>
+hipError_t launch_term(const Bf3Args& g, int tf, int mrows, hipStream_t s) {
+  switch (tf) {
+    case TF_ACC: return launch_acc<KIND, P_F64>(g, mrows, s);
+    case TF_X3: return launch_bf3<KIND, P_F64, 3>(g, mrows, s);
+    case TF_X2: return launch_bf3<KIND, P_F64, 2>(g, mrows, s);
+    case TF_X1: return launch_bf3<KIND, P_F64, 1>(g, mrows, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Split-BF16 product of one Chebyshev term in term format tf (TF_ACC .. TF_X1):
+// A = P_l (or the BF16X3 copy of X for the first product) in BF16X3; P_{l-1}
+// in BF16X3 or FP64 (X, read for c_0 X by the first product); output P_{l+1}
+// in BF16X3, or X_k in FP64 for the last product.
+hipError_t dispatch_bf3(const ChebTermX& t, int tf, int mrows, int np, hipStream_t s) {
   if (t.a_fmt != FMT_BF16X3 || (t.p_fmt != FMT_BF16X3 && t.p_fmt != FMT_F64))
     return hipErrorInvalidValue;
   Bf3Args g{};
@@ -586,18 +835,26 @@ hipError_t dispatch_bf3(const ChebTermX& t, int mrows, int np, hipStream_t s) {
   g.y_im = t.y_im;
   g.plane = t.plane;
   g.np = np;
+  g.c0r = t.c0r;
+  g.c0i = t.c0i;
   g.cr = t.cr;
   g.ci = t.ci;
   g.phr = t.phr;
   g.phi = t.phi;
   const bool pf = t.p_fmt == FMT_F64;
-  if (t.kind == CHEB_MID) {
-    if (t.o_fmt != FMT_BF16X3) return hipErrorInvalidValue;
-    return pf ? launch_bf3<CHEB_MID, true>(g, mrows, s) : launch_bf3<CHEB_MID, false>(g, mrows, s);
-  }
-  if (t.kind == CHEB_LAST) {
-    if (t.o_fmt != FMT_F64) return hipErrorInvalidValue;
-    return pf ? launch_bf3<CHEB_LAST, true>(g, mrows, s) : launch_bf3<CHEB_LAST, false>(g, mrows, s);
+  const bool to_x = t.kind == CHEB_LAST || t.kind == CHEB_FIRST_LAST;
+  if (t.o_fmt != (to_x ? FMT_F64 : FMT_BF16X3)) return hipErrorInvalidValue;
+  switch (t.kind) {
+    case CHEB_FIRST:
+      return pf ? launch_term<CHEB_FIRST, true>(g, tf, mrows, s) : hipErrorInvalidValue;
+    case CHEB_FIRST_LAST:
+      return pf ? launch_term<CHEB_FIRST_LAST, true>(g, tf, mrows, s) : hipErrorInvalidValue;
+    case CHEB_MID:
+      return pf ? launch_term<CHEB_MID, true>(g, tf, mrows, s)
+                : launch_term<CHEB_MID, false>(g, tf, mrows, s);
+    case CHEB_LAST:
+      return pf ? launch_term<CHEB_LAST, true>(g, tf, mrows, s)
+                : launch_term<CHEB_LAST, false>(g, tf, mrows, s);
   }
   return hipErrorInvalidValue;
 }
@@ -720,8 +977,12 @@ __global__ void to_product_kernel(const double* __restrict__ re, const double* _
 
 }  // namespace
 
+hipError_t launch_cheb_bf16(const ChebTermX& t, int term_fmt, int mrows, int np, hipStream_t s) {
+  return dispatch_bf3(t, term_fmt, mrows, np, s);
+}
+
 hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int np, hipStream_t s) {
-  if (precision == FQ_BF16X3) return dispatch_bf3(t, mrows, np, s);
+  if (precision != FQ_FP32) return hipErrorInvalidValue;
   switch (t.kind) {
     case CHEB_FIRST:
       return dispatch(t, precision, mrows, np, EpiMix<CHEB_FIRST>{t, np}, s);

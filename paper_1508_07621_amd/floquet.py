@@ -80,7 +80,7 @@ def _marshal(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenval
              e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
              precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
              reorthonormalize: bool = False, dtype: str = "complex128", scheme: str = "magnus4",
-             device=None):
+             mixed_tol: float = 0.0, term_formats=None, device=None):
     """Device copies of the operators and the fq_system / fq_params structures
     of one problem (arguments as for FloquetContext), set on `self`."""
     import ctypes
@@ -159,6 +159,12 @@ def _marshal(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenval
         raise ValueError("dtype must be complex128 or complex64")
     par.dtype = _abi.FQ_C64 if dtype == "complex64" else _abi.FQ_C128
     par.scheme = _abi.SCHEMES[scheme]
+    par.mixed_tol = float(mixed_tol)
+    if term_formats is not None:
+        tf = [_abi.TERM_FORMATS[f] if isinstance(f, str) else int(f) for f in term_formats]
+        self._tf = (ctypes.c_int32 * len(tf))(*tf)
+        par.term_formats = ctypes.cast(self._tf, ctypes.POINTER(ctypes.c_int32))
+        par.n_term_formats = len(tf)
     self.state_dtype = torch.complex64 if dtype == "complex64" else torch.complex128
     self.precision = precision
     self._sys, self._par = sysd, par
@@ -176,6 +182,10 @@ class FloquetContext:
     and "cf4" (commutator-free, two exponentials per step), (M, 3) for
     "magnus6" (the paper's sixth-order scheme; dense operators, no gradient).
     precision: "fp64", "fp32" or "bf16x3" (arithmetic of the Chebyshev products).
+    For "bf16x3" each term's product format is chosen from its Bessel weight so
+    that the estimated rounding error of U_T stays below mixed_tol (0 = the
+    library's default, 5e-7); term_formats (names of _abi.TERM_FORMATS or their
+    values, for terms 1, 2, ...; the last repeats) fixes them instead.
     reorthonormalize: replace U_T by its polar factor after each build (FP64
     Newton-Schulz); the report keeps the unitarity before and after.
     dtype: "complex128" or "complex64", storage of U_T, X and U_bar (the

@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 6 * 8
-    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 6 * 4
-    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 8 * 8 + 4 * 8
+    assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 6 * 4 + 8 + 8 + 8
+    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 16 * 8 + 16 * 4 + 16 * 4 + 8
 
 
 def test_struct_offsets_match_compiled_header(tmp_path):
@@ -407,3 +407,27 @@ def test_static_build_rejects_before_device_work():
     assert _ws(_dense(1408), _params())[1] <= 256 << 20 < _ws(_dense(1409), _params())[1]
     assert call(_dense(1281), _params(precision=2)) == _abi.FQ_ERR_ARG
     assert call(_tridiag(4096), _params()) == _abi.FQ_ERR_ARG
+
+
+def test_schedule_arguments_rejected():
+    """Per-term formats: values, the leading FP64 run, the precision they need,
+    and the error target are checked before any device work."""
+    def with_formats(fmts, precision=2, tol=0.0):
+        arr = (ctypes.c_int32 * max(len(fmts), 1))(*fmts)
+        p = _params(precision=precision, mixed_tol=tol)
+        if fmts:
+            p.term_formats = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+            p.n_term_formats = len(fmts)
+        p._arr = arr
+        return _ws(_dense(), p)[0]
+
+    assert with_formats([0, 0, 1, 2, 3, 4]) == _abi.FQ_OK
+    assert with_formats([2, 0]) == _abi.FQ_ERR_ARG          # FP64 after a BF16 term
+    assert with_formats([5]) == _abi.FQ_ERR_ARG
+    assert with_formats([-1]) == _abi.FQ_ERR_ARG
+    assert with_formats([2], precision=0) == _abi.FQ_ERR_ARG
+    assert with_formats([], tol=-1.0) == _abi.FQ_ERR_ARG
+    assert with_formats([], tol=math.nan) == _abi.FQ_ERR_ARG
+    p = _params(precision=2)
+    p.n_term_formats = 3                                    # count without the array
+    assert _ws(_dense(), p)[0] == _abi.FQ_ERR_ARG
