@@ -501,11 +501,36 @@ def second_round(ctx, U, wl, kw):
     else:
         tr0, trv = float(np.sum(kw["h0_diag"])), float(np.sum(kw["hmod_diag"]))
     expect = tr0 + float(np.mean(fg)) * trv
+    # the paper's per-state accuracy (Sec. 7, Eq. (error)): every Floquet state
+    # of U_T(h) against the best-matching one of a companion build at h/2
+    from paper_1508_07621_amd import analysis
+    from paper_1508_07621_amd import floquet as fl
+    from workloads import drive_cos
+    _log("second round: companion build at h/2 and per-state errors")
+    f2 = drive_cos(fl.node_times(wl.T, 2 * wl.M, scheme=wl.scheme), eps0, eps1, 1.0)
+    ctx2 = fl.FloquetContext(T=wl.T, M=2 * wl.M, f_nodes=f2, tol=1e-12,
+                             precision=ctx.precision, scheme=wl.scheme, device=U.device, **kw)
+    t0 = time.perf_counter()
+    U2 = ctx2.build_ut()
+    torch.cuda.synchronize()
+    half_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sigma, dq, _ = analysis.state_errors_of_builds(U, U2, wl.T)
+    err_s = time.perf_counter() - t0
+    del ctx2, U2
     return {"s_period_average": round(round_s, 4), "host_eig_vectors_s": round(eig_s, 1),
             "states": int(phi.shape[1]), "mean_energy_range": [float(e_mean.min()),
                                                                 float(e_mean.max())],
             "trace_check": {"sum_mean_energies": float(e_mean.sum()), "expected": expect,
-                            "abs_diff": abs(float(e_mean.sum()) - expect)}}
+                            "abs_diff": abs(float(e_mean.sum()) - expect)},
+            "state_errors": {"reference": "companion build at h/2 (M = %d), host eigenvectors of "
+                                          "both, best-matching state" % (2 * wl.M),
+                             "overlap_deficiency_max": float(sigma.max()),
+                             "overlap_deficiency_median": float(np.median(sigma)),
+                             "quasienergy_diff_max": float(dq.max()),
+                             "quasienergy_diff_median": float(np.median(dq)),
+                             "s_half_step_build": round(half_s, 3),
+                             "host_s": round(err_s, 1)}}
 
 
 def shard_share(ctx, U, wl, P: int, warmup: int, steps: int, s_full: float, precision: str):

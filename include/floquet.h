@@ -171,8 +171,8 @@ typedef struct fq_params {
   double e_min, e_max;       /* spectral interval containing the spectrum of
                                 every H_eff,k; both NaN = the library computes
                                 it (tridiagonal: exact per-step extremes by
-                                Sturm bisection; dense: Weyl cover from Lanczos
-                                extremes of H0 and Hmod plus a 1 % margin).
+                                Sturm bisection; dense: Weyl cover from the
+                                bounds fq_hermitian_cover gives for H0 and Hmod).
                                 A given interval is rejected with
                                 FQ_ERR_SPECTRUM when it misses a point known to
                                 lie in some step's spectral hull (tridiagonal:
@@ -259,6 +259,11 @@ typedef struct fq_report {
                                           unused entries: -1 */
   double mixed_err_est;           /* FQ_BF16X3 and FQ_FP32: the error estimate
                                      the schedule was chosen for (0 otherwise) */
+  int32_t diverged;               /* 1 when the last build's max |(U^dagger U -
+                                     1)_ij| exceeds 1e-3 (or is not finite): the
+                                     Chebyshev series diverged, e.g. because a
+                                     step's spectrum left the interval; 0
+                                     otherwise */
 } fq_report;
 
 typedef struct fq_ctx fq_ctx;  /* opaque; host memory owned by the library */
@@ -286,6 +291,18 @@ fq_status fq_choose_order(double R, double tol, int32_t* L_out);
  * bisection to full FP64 accuracy. Host pointers. */
 fq_status fq_tridiag_extremes(int64_t n, const double* d, const double* e_abs,
                               double* lam_min, double* lam_max);
+
+/* Outer estimate [lo, hi] of the spectrum of a dense Hermitian matrix, the
+ * way the library bounds H0 and each Hmod for its dense spectral cover (the
+ * paper's interval of Sec. 3, made to contain the spectrum): the extreme Ritz
+ * values of 200 Lanczos steps, from a start vector drawn from a hash of
+ * A (1, ..., 1), widened by 1 % of their spread on each side. For a start
+ * uniform on the sphere an extreme Ritz value lies more than 1 % of the spread
+ * inside the spectrum with probability below 1.648 sqrt(n) exp(-0.1 (2k - 1)),
+ * k = min(n, 200) (Kuczynski and Wozniakowski, 1992): below 1e-14 for
+ * n <= 10^6. a: host, n*n complex128 row-major (Hermitian, not checked);
+ * lo, hi: host. Runs on the host. */
+fq_status fq_hermitian_cover(int64_t n, const void* a, double* lo, double* hi);
 
 /* Bytes of device workspace a context for (sys, par) needs (256-byte aligned
  * pointer expected). Checks the arguments like fq_create. */

@@ -21,6 +21,9 @@ systems", arXiv:1508.07621):
 * quasienergies from the eigenvalues of U_T (Sec. 2, Eq. (4));
 * the period average of the energy of propagated states (the second round of
   Sec. 3, Eq. (average) with A(t) = H(t)) by the rectangle rule on the step grid;
+* the accuracy of individual Floquet states (Sec. 7, Eq. (error)): each state of
+  U_T(h) against the best-matching state of U_T(h/2), as an overlap deficiency
+  and a quasienergy difference (the printed overlap contains the eigenphase);
 * the gradient of a trace-fidelity loss with respect to piecewise-constant drive
   amplitudes (not in the paper; exact Daleckii-Krein derivative of the chain).
 
@@ -61,7 +64,7 @@ __all__ = [
     "trace_fidelity_loss", "grad_piecewise", "chebyshev_polynomial_values",
     "GL3_C", "node_times6", "magnus6_omega", "magnus6_heff", "exact_cover",
     "period_average", "period_average_tridiag", "CF4_A1", "CF4_A2", "cf4_exponents",
-    "magnus4_heff_drives",
+    "magnus4_heff_drives", "floquet_state_errors",
 ]
 
 # ---------------------------------------------------------------------------
@@ -617,6 +620,43 @@ def eigenphases(U: np.ndarray) -> np.ndarray:
     th = -np.angle(lam)
     th[th <= -math.pi] += 2.0 * math.pi
     return np.sort(th)
+
+
+def floquet_state_errors(U: np.ndarray, U_half: np.ndarray, T: float):
+    """Accuracy of each Floquet state of U = U_T(h) against U_half = U_T(h/2)
+    (Sec. 7, Eq. (error) with the paper's companion run at half the time step).
+
+    The Floquet states are the eigenvectors phi_mu of U (U phi_mu =
+    exp(-i theta_mu) phi_mu, Sec. 2, Eq. (4)); the states of U_half are the
+    references. The printed measure |1 - <phi_mu|U_T|phi~_mu>| keeps the
+    eigenphase exp(-i theta_mu) inside the overlap, where it is not small;
+    it is read here as its two parts. For every mu, taking the reference state
+    nu with the largest |<phi~_nu|phi_mu>|:
+        sigma[mu] = 1 - |<phi~_nu|phi_mu>|      (normalised states)
+        dq[mu]    = circular distance between theta_mu / T and theta~_nu / T
+                    (modulo 2 pi / T).
+    Returns (sigma, dq, theta / T), indexed like the eigenvalues of U as
+    LAPACK zgeev returns them."""
+    n = U.shape[0]
+    lam, phi = np.linalg.eig(np.asarray(U, np.complex128))
+    lam_r, phi_r = np.linalg.eig(np.asarray(U_half, np.complex128))
+    theta = -np.angle(lam)
+    theta_r = -np.angle(lam_r)
+    period = 2.0 * math.pi / T
+    sigma = np.empty(n)
+    dq = np.empty(n)
+    for mu in range(n):
+        v = phi[:, mu] / np.linalg.norm(phi[:, mu])
+        best, nu = -1.0, -1
+        for j in range(n):
+            w = phi_r[:, j] / np.linalg.norm(phi_r[:, j])
+            o = abs(np.vdot(w, v))
+            if o > best:
+                best, nu = o, j
+        sigma[mu] = 1.0 - best
+        d = abs(theta[mu] / T - theta_r[nu] / T) % period
+        dq[mu] = min(d, period - d)
+    return sigma, dq, theta / T
 
 
 def quasienergy_distance(theta1: np.ndarray, theta2: np.ndarray, T: float) -> float:

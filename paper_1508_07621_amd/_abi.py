@@ -33,7 +33,7 @@ TERM_FORMAT_NAMES = {v: k for k, v in TERM_FORMATS.items()}
 #: every entry point include/floquet.h declares
 EXPORTS = (
     "fq_node_times", "fq_node_times_magnus6", "fq_bessel_weights", "fq_choose_order", "fq_tridiag_extremes",
-    "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_get_report",
+    "fq_hermitian_cover", "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_get_report",
     "floquet_build_UT", "floquet_propagate", "floquet_period_average", "floquet_grad",
     "floquet_build_UT_static", "fq_last_error",
 )
@@ -64,7 +64,7 @@ class FqReport(ctypes.Structure):
                 ("unitarity_max_after", c_double), ("unitarity_fro_after", c_double),
                 ("ms_build", c_double), ("ms_kernel", c_double * K_SLOTS),
                 ("n_kernel", c_int32 * K_SLOTS), ("term_format", c_int32 * TERM_SLOTS),
-                ("mixed_err_est", c_double)]
+                ("mixed_err_est", c_double), ("diverged", c_int32)]
 
     def as_dict(self):
         out = {}
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
     L.fq_choose_order.argtypes = [c_double, c_double, POINTER(c_int32)]
     L.fq_tridiag_extremes.argtypes = [c_int64, POINTER(c_double), POINTER(c_double),
                                       POINTER(c_double), POINTER(c_double)]
+    L.fq_hermitian_cover.argtypes = [c_int64, c_void_p, POINTER(c_double), POINTER(c_double)]
     L.fq_workspace_bytes.argtypes = [POINTER(FqSystem), POINTER(FqParams), POINTER(c_size_t)]
     L.fq_create.argtypes = [POINTER(c_void_p), POINTER(FqSystem), POINTER(FqParams), c_void_p,
                             c_size_t, c_void_p]

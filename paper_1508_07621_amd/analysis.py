@@ -62,3 +62,29 @@ def state_errors(phi, eps, phi_ref, eps_ref, T):
     period = 2.0 * math.pi / T
     d = np.abs(np.asarray(eps) - np.asarray(eps_ref)[nu]) % period
     return defic, np.minimum(d, period - d)
+
+
+def state_errors_of_builds(U, U_half, T):
+    """The accuracy of each Floquet state of U = U_T(h), estimated as the paper
+    does (Sec. 7, Eq. (error)) from a companion build with half the time step,
+    U_half = U_T(h/2): host eigendecompositions of both (LAPACK zgeev through
+    NumPy), then state_errors of the first set against the second. Returns
+    (sigma, dq, eps) per eigenvector of U: overlap deficiency with the
+    best-matching state of U_half, quasienergy difference to it (modulo
+    2 pi / T), and the quasienergy theta / T."""
+    try:
+        import torch
+        if isinstance(U, torch.Tensor):
+            U = U.detach().cpu().numpy()
+        if isinstance(U_half, torch.Tensor):
+            U_half = U_half.detach().cpu().numpy()
+    except ImportError:
+        pass
+    out = []
+    for W in (U, U_half):
+        lam, phi = np.linalg.eig(np.asarray(W, dtype=np.complex128))
+        th = -np.angle(lam)
+        out.append((phi / np.linalg.norm(phi, axis=0), th / T))
+    (phi, eps), (phi_r, eps_r) = out
+    sigma, dq = state_errors(phi, eps, phi_r, eps_r, T)
+    return sigma, dq, eps

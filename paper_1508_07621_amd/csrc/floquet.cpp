@@ -68,8 +68,16 @@ hipError_t copy_sync(hipStream_t s, void* dst, const void* src, size_t bytes, hi
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxOrder = 65535;       // capacity of the device coefficient table
-constexpr int kLanczosSteps = 160;
-constexpr double kDenseMargin = 0.01;  // relative widening of the Lanczos-based cover
+// Lanczos steps for the dense covers and the relative widening of their Ritz
+// extremes (see lanczos_ritz): with a start vector uniform on the sphere, k
+// steps leave an extreme Ritz value more than a fraction eps of the spread
+// inside the spectrum with probability at most 1.648 sqrt(n) exp(-sqrt(eps) (2k - 1))
+// (Kuczynski and Wozniakowski, SIAM J. Matrix Anal. Appl. 13 (1992)); at
+// eps = 0.01, k = 200 this is below 1e-14 for n up to 10^6.
+constexpr int kLanczosSteps = 200;
+constexpr double kDenseMargin = 0.01;
+// A build whose max |(U^dagger U - 1)_ij| exceeds this is reported as diverged.
+constexpr double kDivergence = 1e-3;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -434,23 +442,41 @@ fq_status device_matvec_planar(fq_ctx* ctx, const double* ar, const double* ai,
   return FQ_OK;
 }
 
-// Extreme Ritz values of a Hermitian operator after k Lanczos steps from a
-// fixed pseudo-random start vector. Ritz values lie inside
-// [lambda_min, lambda_max] and converge to its ends fastest.
-fq_status lanczos_ritz(fq_ctx* ctx, const Matvec& mv, double* lo, double* hi) {
-  const long n = ctx->n;
+// Extreme Ritz values of a Hermitian operator after k Lanczos steps. The start
+// vector is drawn from a generator seeded with a hash of A x0 for a fixed x0,
+// so it is not fixed in advance of the operator (no operator can be chosen with
+// its extreme eigenvector orthogonal to a known start) and the same operator
+// always gets the same start (reproducible covers). Ritz values lie inside
+// [lambda_min, lambda_max] and converge to its ends fastest; the probability
+// bound above applies to starts uniform on the sphere, which complex Gaussian
+// components give after normalisation.
+fq_status lanczos_extremes(long n, const Matvec& mv, double* lo, double* hi) {
   std::vector<cd> q(n), qp(n, 0.0), w(n);
-  uint64_t s = 0x9E3779B97F4A7C15ull;
-  auto next = [&]() {
+  // hash of A x0, x0 = (1, 1, ..., 1) / sqrt(n)
+  for (long i = 0; i < n; ++i) q[i] = cd(1.0 / std::sqrt((double)n), 0.0);
+  fq_status st = mv(q, w);
+  if (st != FQ_OK) return st;
+  uint64_t s = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
+  for (long i = 0; i < n; ++i) {
+    uint64_t bits[2];
+    std::memcpy(bits, &w[i], sizeof bits);
+    for (uint64_t b : bits) {
+      s ^= b + 0x9E3779B97F4A7C15ull + (s << 6) + (s >> 2);
+      s *= 0xBF58476D1CE4E5B9ull;
+      s ^= s >> 31;
+    }
+  }
+  if (s == 0) s = 1;
+  auto next = [&]() {  // xorshift64, then uniform in (0, 1)
     s ^= s << 13;
     s ^= s >> 7;
     s ^= s << 17;
-    return (double)(s >> 11) / 9007199254740992.0 - 0.5;
+    return ((double)(s >> 11) + 0.5) / 9007199254740992.0;
   };
   double nrm = 0.0;
-  for (long i = 0; i < n; ++i) {
-    const double re = next();
-    q[i] = cd(re, next());
+  for (long i = 0; i < n; ++i) {  // complex Gaussian components (Box-Muller)
+    const double r = std::sqrt(-2.0 * std::log(next())), t = 6.283185307179586 * next();
+    q[i] = cd(r * std::cos(t), r * std::sin(t));
     nrm += std::norm(q[i]);
   }
   nrm = std::sqrt(nrm);
@@ -459,7 +485,7 @@ fq_status lanczos_ritz(fq_ctx* ctx, const Matvec& mv, double* lo, double* hi) {
   std::vector<double> alpha, beta;
   double bprev = 0.0;
   for (int j = 0; j < ksteps; ++j) {
-    fq_status st = mv(q, w);
+    st = mv(q, w);
     if (st != FQ_OK) return st;
     double a = 0.0;
     for (long i = 0; i < n; ++i) a += std::real(std::conj(q[i]) * w[i]);
@@ -480,6 +506,10 @@ fq_status lanczos_ritz(fq_ctx* ctx, const Matvec& mv, double* lo, double* hi) {
   }
   fq::tridiag_extremes((long)alpha.size(), alpha.data(), beta.data(), lo, hi);
   return FQ_OK;
+}
+
+fq_status lanczos_ritz(fq_ctx* ctx, const Matvec& mv, double* lo, double* hi) {
+  return lanczos_extremes(ctx->n, mv, lo, hi);
 }
 
 // Outer estimate of the union of spec(H_eff,k): Weyl's inequalities on the
@@ -1084,6 +1114,7 @@ fq_status unitarity(fq_ctx* c, const double* xr, const double* xi) {
   FQ_HIP(c, hipStreamSynchronize(c->stream));
   c->last.unitarity_max = h[0];
   c->last.unitarity_fro = std::sqrt(h[1]);
+  c->last.diverged = !(h[0] <= kDivergence);  // also NaN
   return FQ_OK;
 }
 
@@ -1659,6 +1690,30 @@ fq_status fq_tridiag_extremes(int64_t n, const double* d, const double* e_abs, d
     if (!is_finite(d[i]) || (i + 1 < n && !is_finite(e_abs[i])))
       return fail(FQ_ERR_NONFINITE, "non-finite entry");
   fq::tridiag_extremes((long)n, d, e_abs, lam_min, lam_max);
+  return FQ_OK;
+}
+
+fq_status fq_hermitian_cover(int64_t n, const void* a, double* lo, double* hi) {
+  if (n < 1 || !a || !lo || !hi) return fail(FQ_ERR_ARG, "need n >= 1 and non-null pointers");
+  const cd* A = static_cast<const cd*>(a);
+  for (int64_t i = 0; i < n * n; ++i)
+    if (!std::isfinite(A[i].real()) || !std::isfinite(A[i].imag()))
+      return fail(FQ_ERR_NONFINITE, "matrix entry %lld is not finite", (long long)i);
+  Matvec mv = [&](const std::vector<cd>& x, std::vector<cd>& y) {
+    y.assign(n, cd(0.0, 0.0));
+    for (int64_t i = 0; i < n; ++i) {
+      cd acc(0.0, 0.0);
+      for (int64_t j = 0; j < n; ++j) acc += A[i * n + j] * x[j];
+      y[i] = acc;
+    }
+    return FQ_OK;
+  };
+  double l, h;
+  fq_status st = lanczos_extremes(n, mv, &l, &h);
+  if (st != FQ_OK) return st;
+  const double w = h - l;
+  *lo = l - kDenseMargin * w;
+  *hi = h + kDenseMargin * w;
   return FQ_OK;
 }
 

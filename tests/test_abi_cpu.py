@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.FqSystem) == 8 + 4 + 4 + 6 * 8
     assert ctypes.sizeof(_abi.FqParams) == 8 + 4 + 4 + 8 + 3 * 8 + 6 * 4 + 8 + 8 + 8
-    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 16 * 8 + 16 * 4 + 16 * 4 + 8
+    assert ctypes.sizeof(_abi.FqReport) == 4 + 4 + 10 * 8 + 16 * 8 + 16 * 4 + 16 * 4 + 8 + 8
 
 
 def test_struct_offsets_match_compiled_header(tmp_path):
@@ -431,3 +431,103 @@ def test_schedule_arguments_rejected():
     p = _params(precision=2)
     p.n_term_formats = 3                                    # count without the array
     assert _ws(_dense(), p)[0] == _abi.FQ_ERR_ARG
+
+
+def _cover(A):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    st = _abi.lib().fq_hermitian_cover(A.shape[0], A.ctypes.data, ctypes.byref(lo),
+                                       ctypes.byref(hi))
+    assert st == _abi.FQ_OK, _abi.lib().fq_last_error()
+    return lo.value, hi.value
+
+
+def _fixed_start(n):
+    """A start vector fixed in advance of the operator (an xorshift sequence
+    from a constant seed), for building an operator that defeats it."""
+    s = 0x9E3779B97F4A7C15
+    mask = (1 << 64) - 1
+    out = np.empty(n, complex)
+    vals = []
+    for _ in range(2 * n):
+        s ^= (s << 13) & mask
+        s ^= s >> 7
+        s ^= (s << 17) & mask
+        vals.append((s >> 11) / 9007199254740992.0 - 0.5)
+    out.real, out.imag = vals[0::2], vals[1::2]
+    return out / np.linalg.norm(out)
+
+
+def _lanczos_extremes(A, q, k):
+    """Plain Lanczos from q (no reorthogonalisation), extreme Ritz values."""
+    n = A.shape[0]
+    alpha, beta = [], []
+    qp = np.zeros(n, complex)
+    b = 0.0
+    for j in range(min(k, n)):
+        w = A @ q - b * qp
+        a = np.vdot(q, w).real
+        w = w - a * q
+        alpha.append(a)
+        b = np.linalg.norm(w)
+        if b < 1e-12:
+            break
+        beta.append(b)
+        qp, q = q, w / b
+    T = np.diag(alpha) + np.diag(beta[:len(alpha) - 1], 1) + np.diag(beta[:len(alpha) - 1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return ev[0], ev[-1]
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (64, 3), (300, 4), (700, 5)])
+def test_hermitian_cover_contains_the_spectrum(n, seed):
+    """The dense cover's bound for one operator contains its spectrum (LAPACK
+    eigvalsh) and is not wider than the spectrum plus a few per cent."""
+    from workloads import gue
+    A = gue(n, np.random.default_rng(seed))
+    ev = np.linalg.eigvalsh(A)
+    lo, hi = _cover(A)
+    spread = max(ev[-1] - ev[0], 1e-300)
+    assert lo <= ev[0] + 1e-12 and hi >= ev[-1] - 1e-12
+    if n > 1:
+        assert (ev[0] - lo) < 0.05 * spread and (hi - ev[-1]) < 0.05 * spread
+
+
+@pytest.mark.parametrize("gap", [4.0, 0.1, 0.02])
+def test_hermitian_cover_finds_an_extreme_hidden_from_a_fixed_start(gap):
+    """Operators whose largest eigenvalue sits `gap` above a semicircle bulk
+    on [-2, 2], with its eigenvector orthogonal to a start vector fixed in
+    advance and to the all-ones vector (the library hashes A times it): the
+    cover still contains the whole spectrum. (In exact arithmetic Lanczos from
+    that fixed start would never see the outlier; in floating point it surfaces
+    from rounding noise only after enough steps, later the closer it is to the
+    bulk, which is what the margin and the operator-dependent start are for.)"""
+    from workloads import gue
+    n = 400
+    rng = np.random.default_rng(17)
+    B = gue(n, rng)
+    q0 = _fixed_start(n)
+    ones = np.ones(n, complex) / math.sqrt(n)
+    Qb, _ = np.linalg.qr(np.stack([q0, ones], 1))
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    v = v - Qb @ (Qb.conj().T @ v)
+    v /= np.linalg.norm(v)
+    P = np.eye(n) - np.outer(v, v.conj())
+    bulk_top = np.linalg.eigvalsh(P @ B @ P)[-1]
+    A = P @ B @ P + (bulk_top + gap) * np.outer(v, v.conj())
+    A = 0.5 * (A + A.conj().T)
+    ev = np.linalg.eigvalsh(A)
+    assert abs(abs(np.vdot(v, q0))) < 1e-12 and ev[-1] > bulk_top + 0.99 * gap
+    lo, hi = _cover(A)
+    assert hi >= ev[-1] and lo <= ev[0]
+
+
+def test_hermitian_cover_rejects_bad_arguments():
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    A = np.zeros((2, 2), complex)
+    A[0, 1] = np.nan
+    L = _abi.lib()
+    assert L.fq_hermitian_cover(0, A.ctypes.data, ctypes.byref(lo), ctypes.byref(hi)) == _abi.FQ_ERR_ARG
+    assert L.fq_hermitian_cover(2, None, ctypes.byref(lo), ctypes.byref(hi)) == _abi.FQ_ERR_ARG
+    assert L.fq_hermitian_cover(2, A.ctypes.data, ctypes.byref(lo), ctypes.byref(hi)) == \
+        _abi.FQ_ERR_NONFINITE

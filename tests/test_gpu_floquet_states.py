@@ -130,3 +130,45 @@ def test_floquet_states_sorted_and_trace(fl):
     expect = np.trace(H0).real + np.mean(fg) * np.trace(V).real
     _say("sum of mean energies", e_mean.sum(), "expected", expect)
     assert abs(e_mean.sum() - expect) < 1e-8
+
+
+@pytest.mark.parametrize("layout", ["dense", "tridiag"])
+def test_state_errors_from_half_step_builds_match_oracle(fl, layout):
+    """The paper's per-state accuracy (Sec. 7, Eq. (error)) from builds at h and
+    h/2 on the GPU, against the oracle's from its own builds with the same
+    intervals and orders: states are paired by quasienergy, and each state's
+    overlap deficiency and quasienergy difference must agree (both are small
+    differences of FP64 results, so the bar is absolute)."""
+    from paper_1508_07621_amd import analysis
+    T, M = TWO_PI, 16
+    if layout == "dense":
+        rng = np.random.default_rng(91)
+        H0, V = gue(48, rng), gue(48, rng)
+        kw = dict(h0=H0, hmod=V)
+        eps0 = 0.0
+    else:
+        d, e, v = dimer_tridiag(39, 1.0, 0.01)
+        kw = dict(h0_diag=d, h0_off=e, hmod_diag=v)
+        eps0 = 0.5
+    Us, refs = [], []
+    for m in (M, 2 * M):
+        f = drive_cos(orc.node_times(T, m), eps0, 1.0 if layout == "dense" else 1.5, 1.0)
+        ctx = fl.FloquetContext(T=T, M=m, f_nodes=f, **kw)
+        rep = ctx.report
+        Us.append(ctx.build_ut().cpu().numpy())
+        common = dict(route="cheb", e_min=rep["e_min"], e_max=rep["e_max"], L=rep["L"])
+        if layout == "dense":
+            refs.append(orc.build_ut(H0, V, f, T, m, **common))
+        else:
+            refs.append(orc.build_ut_tridiag(d, e, v, f, T, m, **common))
+    sigma, dq, q = analysis.state_errors_of_builds(Us[0], Us[1], T)
+    s_ref, d_ref, q_ref = orc.floquet_state_errors(refs[0], refs[1], T)
+    _say(layout, "sigma max", sigma.max(), "dq max", dq.max())
+    period = TWO_PI / T
+    for mu in range(len(q)):
+        dist = np.abs((q_ref - q[mu] + period / 2) % period - period / 2)
+        j = int(np.argmin(dist))
+        assert dist[j] < 1e-9
+        assert abs(sigma[mu] - s_ref[j]) < 1e-9
+        assert abs(dq[mu] - d_ref[j]) < 1e-9
+    assert dq.max() > 1e-12        # the comparison is not between zeros

@@ -639,3 +639,20 @@ def test_dense_n4096_full_period_sampled_columns(fl):
         err = orc.column_error(Uc, ref)
         _say("e_col", precision, err)
         assert err < tol
+
+
+def test_divergence_flag(fl):
+    """The report flags a build whose result is far from unitary: with a
+    Chebyshev order far below what the step needs (R ~ 8 with L = 2) the series
+    does not converge and ||U^dagger U - 1|| is of order one; the properly
+    ordered build of the same problem is not flagged."""
+    H0, V = _dense_case(64, 5)
+    T, M = TWO_PI, 3
+    f = _cos_nodes(fl, T, M)
+    lo, hi, L = _oracle_interval(H0, V, f, T, M)
+    for order, flag in ((L, 0), (2, 1)):
+        ctx = fl.FloquetContext(h0=H0, hmod=V, T=T, M=M, f_nodes=f, e_min=lo, e_max=hi, L=order)
+        ctx.build_ut()
+        rep = ctx.last_report
+        _say("L", order, "unitarity", rep["unitarity_max"], "diverged", rep["diverged"])
+        assert rep["diverged"] == flag

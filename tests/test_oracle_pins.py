@@ -653,3 +653,62 @@ def test_two_drive_terms_reduce_to_one(scheme):
     U3 = orc.build_ut(H0, [V1, np.zeros_like(V1)], np.stack([fa, fb], -1), T, M, route="exact",
                       scheme=scheme)
     assert orc.column_error(U3, Ua) < 1e-12
+
+
+# --- accuracy of individual Floquet states (Sec. 7, Eq. (error)) ----------------------------------
+
+def _fold(q, T):
+    """Quasienergies folded into (-pi/T, pi/T]."""
+    period = 2.0 * math.pi / T
+    return q - period * np.round(q / period + 1e-15)
+
+
+def test_state_errors_vanish_for_commuting_operators_with_the_closed_form_quasienergies():
+    """Diagonal H0, V and f = eps0 + eps1 cos t over a full period: every step
+    commutes and the Gauss-Legendre sums of cos vanish, so U_T(h) = U_T(h/2) =
+    diag(exp(-i (E_j + eps0 v_j) T)): the Floquet states are the basis states
+    (sigma = 0, dq = 0) and the quasienergies are E_j + eps0 v_j modulo 2 pi / T."""
+    rng = np.random.default_rng(71)
+    n, T, M, eps0 = 6, TWO_PI, 10, 0.3
+    E = np.sort(rng.uniform(-0.45, 0.45, n))
+    v = rng.uniform(-0.2, 0.2, n)
+    H0, V = np.diag(E).astype(complex), np.diag(v).astype(complex)
+    U = orc.build_ut(H0, V, _nodes_cos(T, M, eps0), T, M, route="exact")
+    U2 = orc.build_ut(H0, V, _nodes_cos(T, 2 * M, eps0), T, 2 * M, route="exact")
+    sigma, dq, q = orc.floquet_state_errors(U, U2, T)
+    assert sigma.max() < 1e-13 and dq.max() < 1e-13
+    expect = np.sort(_fold(E + eps0 * v, T))
+    assert np.abs(np.sort(_fold(q, T)) - expect).max() < 1e-13
+
+
+def test_state_errors_against_an_independent_integrator():
+    """Magnus-4 Floquet states of a random model: the error of each state of
+    U_T(h) against the exact states (a DOP853 propagator) is estimated by its
+    difference from U_T(h/2) as the paper does: with a fourth-order error C h^4,
+    phi(h) - phi(h/2) = (15/16) C h^4, so the quasienergy estimate is 15/16 of the
+    true error and the overlap deficiency, quadratic in the state error,
+    (15/16)^2 of it. A state that is not matched to its partner, a missing
+    normalisation or a wrong phase convention breaks both ratios."""
+    H0, V = _rm(5, 72)
+    T, M = TWO_PI, 24
+    f = _nodes_cos(T, M)
+    U = orc.build_ut(H0, V, f, T, M, route="exact")
+    U2 = orc.build_ut(H0, V, _nodes_cos(T, 2 * M), T, 2 * M, route="exact")
+    Uex = _brute_force(lambda t: H0 + math.cos(t) * V, 5, T)
+    s_est, d_est, _ = orc.floquet_state_errors(U, U2, T)
+    s_true, d_true, _ = orc.floquet_state_errors(U, Uex, T)
+    assert d_true.min() > 1e-9 and s_true.min() > 1e-17   # errors resolved above round-off
+    np.testing.assert_allclose(d_est / d_true, 15.0 / 16.0, rtol=0.03)
+    np.testing.assert_allclose(s_est / s_true, (15.0 / 16.0) ** 2, rtol=0.06)
+
+
+def test_state_errors_fall_with_the_fourth_power_of_the_step():
+    """Halving h again: quasienergy differences fall by 16 (order four), overlap
+    deficiencies by 256."""
+    H0, V = _rm(5, 73)
+    T = TWO_PI
+    Us = [orc.build_ut(H0, V, _nodes_cos(T, m), T, m, route="exact") for m in (20, 40, 80)]
+    s1, d1, _ = orc.floquet_state_errors(Us[0], Us[1], T)
+    s2, d2, _ = orc.floquet_state_errors(Us[1], Us[2], T)
+    assert 14.0 < np.median(d1 / d2) < 18.0
+    assert 180.0 < np.median(s1 / s2) < 330.0
