@@ -73,8 +73,11 @@ def parse():
     ap.add_argument("--workload", default="gue4096", choices=sorted(WORKLOAD_TEXT),
                     help="gue4096 (default), dimer1000, gue64, adjoint1024 (build + gradient), "
                          "dimer10000, gue10000 (minutes per build), gue4096m6 (sixth-order scheme)")
-    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
-                    help="arithmetic of the dense Chebyshev products (the tridiagonal path is FP64)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the dense Chebyshev products (default: bf16x3, fp64 for "
+                         "gue64; the tridiagonal path is FP64)")
+    ap.add_argument("--no-small-chain", action="store_true",
+                    help="N <= 64: time the launch-per-product form instead of the one-launch chain")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the FP64 reference build of a mixed-precision run")
     ap.add_argument("--no-eig", action="store_true", help="skip the host eigenphase comparison")
@@ -434,6 +437,29 @@ def term_schedule(reports, n: int, workload: str):
     return rows, roof
 
 
+def chain_roofline(reports, n: int, M: int, terms_per_step: int):
+    """The one-launch chain of N <= 64 FP64 builds: every step's products in
+    one kernel on N/16 workgroups (one per 16 states), so the launch's
+    algorithmic work is M x (terms per step) x 8 N^3 over the chain's time; it
+    uses N/16 of the 256 compute units, so its fraction of the FP64 peak is
+    bounded by (N/16)/256 by construction."""
+    from paper_1508_07621_amd._abi import K_CHAIN
+    cnt = sum(r["n_kernel"][K_CHAIN] for r in reports)
+    ms = sum(r["ms_kernel"][K_CHAIN] for r in reports) / cnt
+    flops = float(M) * terms_per_step * 8.0 * n ** 3
+    ach = flops / (ms * 1e-3) / 1e12
+    cus = max(n // 16, 1)
+    return {"bound": "mfma", "achieved": round(ach, 4), "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_MFMA_TFLOPS, 5), "traffic": None,
+            "traffic_detail": None,
+            "kernel": "small_chain_kernel (whole build in one launch, 16 states per workgroup, "
+                      "FP64 MFMA 16x16x4)",
+            "avg_launch_ms": round(ms, 4), "launches_timed": cnt,
+            "algorithmic_flops_per_launch": flops,
+            "compute_units_used": cus,
+            "frac_of_used_units": round(ach / (PEAK_FP64_MFMA_TFLOPS * cus / 256), 4)}
+
+
 def dense_reverse_roofline(grad_reports, n: int, L: int, M: int):
     """The dense gradient's reverse-sweep products (FP64): per step, L launches
     of Ht times the stacked [P_l; Pbar_{l+1}] (2n rows) for l >= 2 and of Ht
@@ -621,6 +647,10 @@ def main():
     wl = workload(args.workload, M=args.M or None)
     if args.scheme:
         wl.scheme = args.scheme
+    if args.precision is None:  # the 64-state configuration is the plain FP64 build
+        args.precision = "fp64" if args.workload == "gue64" else "bf16x3"
+    if args.no_small_chain:
+        os.environ["FQ_SMALL_CHAIN"] = "0"
     precision = args.precision if wl.layout == "dense" else "fp64"
     grad_mode = wl.amplitudes is not None
     if grad_mode:
@@ -697,7 +727,10 @@ def main():
             extra["gradient"]["fd_direction"] = fd_direction(wl, fkw, wl.amplitudes,
                                                              g_last.sum(axis=1), W, args.fd_check)
     if wl.layout == "dense":
-        if precision == "bf16x3":
+        from paper_1508_07621_amd._abi import K_CHAIN
+        if sum(r["n_kernel"][K_CHAIN] for r in reports):
+            roof = chain_roofline(reports, n, wl.M, info["L"] * (2 if wl.scheme == "cf4" else 1))
+        elif precision == "bf16x3":
             rows, roof = term_schedule(reports, n, args.workload)
             from paper_1508_07621_amd._abi import TERM_FORMAT_NAMES
             extra["schedule"] = {

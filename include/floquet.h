@@ -236,6 +236,8 @@ enum {
   FQ_K_TERM_X2 = 11,        /* FQ_TERM_BF16X2 */
   FQ_K_TERM_X1 = 12,        /* FQ_TERM_BF16X1 */
   FQ_K_CONVERT = 13,        /* FP64 planes rounded into the BF16X3 format */
+  FQ_K_CHAIN = 14,          /* dense N <= 64 in FP64: every step of the range in one
+                               launch (Ht, all terms and the hand-off per step) */
   FQ_K_SLOTS = 16
 };
 #define FQ_TERM_SLOTS 16

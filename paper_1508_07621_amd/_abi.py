@@ -25,6 +25,7 @@ K_FIRST, K_FIRST_LAST, K_MID, K_LAST, K_HEFF, K_TRIDIAG, K_SLOTS = 0, 1, 2, 3, 4
 K_ADJ_FWD, K_ADJ_REV = 6, 7
 #: split-BF16 builds time their products by term format (fq_term_format + K_TERM_FP64)
 K_TERM_FP64, K_TERM_F64ACC, K_TERM_X3, K_TERM_X2, K_TERM_X1, K_CONVERT = 8, 9, 10, 11, 12, 13
+K_CHAIN = 14
 TERM_SLOTS = 16
 #: fq_term_format values
 TERM_FORMATS = {"fp64": 0, "bf16x3_f64acc": 1, "bf16x3": 2, "bf16x2": 3, "bf16x1": 4, "fp32": 5}

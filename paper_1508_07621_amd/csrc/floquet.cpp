@@ -888,7 +888,7 @@ double term_error(int tf, long nk) {
 // Formats of terms 1..L of a mixed build: the caller's, or the cheapest
 // schedule found as follows. Random rounding errors of the terms add in
 // quadrature over terms and steps, so the estimate for U_T is
-// sqrt(sum_l (|c_l| eps_l)^2 M). Each term takes the cheapest format whose own
+// sqrt(sum_l (w_l eps_l)^2 M) with w_l the effective weight below. Each term takes the cheapest format whose own
 // contribution |c_l| eps_l sqrt(M) is within a per-term allowance, starting at
 // the whole target and shrinking until the total meets it; FP64 terms are then
 // extended to a leading run (the step converts from FP64 planes to the low
@@ -900,7 +900,15 @@ void choose_schedule(fq_ctx* c, const fq_params* par) {
   const long nk = c->np / 16;
   const double tol = par->mixed_tol > 0 ? par->mixed_tol : kMixedTolDefault;
   const double sm = std::sqrt((double)c->M);
-  auto contribution = [&](int l, int f) { return std::fabs(c->weights[l]) * sm * term_error(f, nk); };
+  // An error in P_l also enters every later term through the recurrence, as a
+  // Chebyshev polynomial of the second kind of degree l' - l (norm at most
+  // l' - l + 1 on the spectrum), so term l's effective weight is
+  // |c_l| + sum_{l' > l} (l' - l + 1) |c_l'| (its own weight when R is small,
+  // several times it when R is large).
+  std::vector<double> weff(L + 1, 0.0);
+  for (int l = 1; l <= L; ++l)
+    for (int q = l; q <= L; ++q) weff[l] += (q - l + 1) * std::fabs(c->weights[q]);
+  auto contribution = [&](int l, int f) { return weff[l] * sm * term_error(f, nk); };
   auto total = [&]() {
     double e2 = 0.0;
     for (int l = 1; l <= L; ++l) {
@@ -1076,8 +1084,39 @@ fq_status dense_cheb_step_mixed(fq_ctx* c, int mrows) {
   return FQ_OK;
 }
 
+// The one-launch chain of small_chain_kernel serves FP64 steps of one drive
+// term whose Ht is H0 + a_k V + b_k K (Magnus-4, commutator-free) at np = 64,
+// without tape, snapshots or saved terms. FQ_SMALL_CHAIN=0 in the environment
+// (read at fq_create) keeps the launch-per-product form instead.
+bool small_chain_ok(const fq_ctx* c, bool record_tape) {
+  return c->small_chain && c->precision == FQ_FP64 && c->np == fq::small_chain_max_n() &&
+         c->scheme != FQ_MAGNUS6 && c->S == 1 && !record_tape && !c->snap && !c->save_pl &&
+         !c->save_plm1;
+}
+
 fq_status dense_steps(fq_ctx* c, int k0, int k1, int mrows, bool record_tape) {
   const size_t plane2 = 2 * (size_t)c->np * (size_t)c->np;
+  if (small_chain_ok(c, record_tape)) {
+    fq::SmallChain sc{};
+    sc.h0r = c->h0r; sc.h0i = c->h0i;
+    sc.vr = c->vr; sc.vi = c->vi;
+    sc.kr = c->kr; sc.ki = c->ki;
+    sc.ab = c->d_ab;
+    sc.coef = c->d_coef;
+    sc.xr = c->xr; sc.xi = c->xi;
+    sc.ld = c->np;
+    sc.n = (int)c->n;
+    sc.L = c->L;
+    sc.k0 = k0;
+    sc.k1 = k1;
+    sc.beta = c->beta;
+    sc.inv_dE = 1.0 / c->dE;
+    sc.phr = c->phr;
+    sc.phi = c->phi;
+    FQ_MARK(c, FQ_K_CHAIN);
+    FQ_HIP(c, fq::launch_small_chain(sc, mrows, c->stream));
+    return FQ_OK;
+  }
   if (record_tape && k0 == 0)
     FQ_HIP(c, hipMemcpyAsync(c->tape, c->xr, plane2 / 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (record_tape && k0 == 0)
@@ -1755,6 +1794,10 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
   c->profile = par->profile != 0;
   c->reortho = par->reorthonormalize != 0;
   c->c64 = par->dtype == FQ_C64;
+  {
+    const char* e = std::getenv("FQ_SMALL_CHAIN");
+    c->small_chain = !(e && e[0] == '0' && e[1] == 0);
+  }
   c->scheme = par->scheme;
   c->S = drive_terms(sys);
   c->J = drive_block(c->S, par->scheme);

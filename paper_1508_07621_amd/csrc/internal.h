@@ -68,6 +68,23 @@ hipError_t launch_adj_dot(const double* pr, const double* pi, const double* dr, 
                           int ncols, const double* pbr, const double* pbi, double w, double* out,
                           int np, hipStream_t s);
 
+// Whole chain of steps k0+1 .. k1 for np = 64 in one launch (FP64; Magnus-4 or
+// commutator-free steps, one drive term): rows [0, mrows) of the state-major X
+// planes (mrows a multiple of 16) are propagated in place, 16 states per
+// workgroup, each forming every step's Ht in LDS from H0, V, K and a_k, b_k.
+struct SmallChain {
+  const double *h0r, *h0i, *vr, *vi, *kr, *ki;  // planar operators, row stride ld
+  const double* ab;                            // device: a_k, b_k
+  const double* coef;                          // device: c_l, complex interleaved
+  double* xr;                                  // state-major X planes, in place
+  double* xi;
+  long ld;                                     // np (must be 64)
+  int n, L, k0, k1;
+  double beta, inv_dE, phr, phi;
+};
+long small_chain_max_n();
+hipError_t launch_small_chain(const SmallChain& c, int mrows, hipStream_t s);
+
 // Launch one Chebyshev product over rows [0, mrows) of the state-major
 // operands (mrows, np multiples of the tile size chosen by the launcher).
 hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s);
@@ -391,6 +408,7 @@ struct fq_ctx {
   // last); launch i took the time between events i and i+1.
   bool profile = false;
   bool reortho = false;               // polar factor of U_T after the build
+  bool small_chain = true;            // np = 64 FP64 steps in one launch (small_chain_kernel)
   bool c64 = false;                   // user state blocks (U, X, W, snapshots) in complex64
   void* snap = nullptr;               // propagate: snapshot buffer, every snap_every steps
   int snap_every = 0, snap_k0 = 0;

@@ -633,6 +633,126 @@ __global__ void fill_zero_kernel(double* __restrict__ p, long count) {
     p[e] = 0.0;
 }
 
+// ---------------------------------------------------------------------------------------
+// Whole chain for N <= 64 in one launch. The columns of U_T are independent
+// propagations (Sec. 5: the identity is split into blocks of columns), so each
+// workgroup takes 16 states (rows of the state-major block) through every
+// step on its own: per step it forms Ht_k = (H0 + a_k V + b_k K - beta) / dE in
+// LDS, runs the L Chebyshev terms with its 16 x 64 block of P_{l-1}, P_l in
+// LDS, keeps its share of the sum Y in registers, and ends the step with
+// X_k = exp(-i beta h) Y in LDS. One barrier per term, none between
+// workgroups; the only HBM traffic is the operators (L2-resident, 192 KB) and
+// the block of X read once and written once.
+// Wave j computes output columns i = 16 j .. 16 j + 15 of each product
+// C(s, i) = sum_k P(s, k) Ht(i, k) with four real products per k-step on the
+// 16x16x4 FP64 matrix cores; lane l then owns states 4 r + l / 16 and column
+// 16 j + l % 16 of every term, so P_{l+1} overwrites P_{l-1} element by
+// element in place.
+// ---------------------------------------------------------------------------------------
+constexpr int kSmallN = 64, kSmallS = 16, kSmallLd = 65;  // padded LDS rows: no bank conflicts
+
+__global__ __launch_bounds__(256) void small_chain_kernel(SmallChain c) {
+  __shared__ double hs[2][kSmallN * kSmallLd];            // Ht re, im
+  __shared__ double ps[2][2][kSmallS * kSmallLd];         // two P buffers [buf][re, im]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s0 = blockIdx.x * kSmallS;                    // first state of this workgroup
+  const int n = c.n;
+  const long ld = c.ld;
+  // the block of X (rows s0 .. s0 + 15 of the state-major planes) into buffer 0
+  for (int e = tid; e < kSmallS * kSmallN; e += 256) {
+    const int s = e / kSmallN, k = e % kSmallN;
+    ps[0][0][s * kSmallLd + k] = c.xr[(long)(s0 + s) * ld + k];
+    ps[0][1][s * kSmallLd + k] = c.xi[(long)(s0 + s) * ld + k];
+  }
+  const int ci = 16 * wave + (lane & 15);  // output column i of this lane
+  const int kq = lane >> 4;                // k within a 4-step of the matrix cores
+  const int L = c.L;
+  int cur = 0;                             // buffer holding X_k (then P_l)
+  for (int k = c.k0; k < c.k1; ++k) {
+    const double a = c.ab[2 * k], b = c.ab[2 * k + 1];
+    __syncthreads();  // the previous step's last writes; Ht no longer read
+    for (int e = tid; e < kSmallN * kSmallN; e += 256) {
+      const int i = e / kSmallN, kk = e % kSmallN;
+      double re = 0.0, im = 0.0;
+      if (i < n && kk < n) {
+        const long g = (long)i * ld + kk;
+        re = c.h0r[g] + a * c.vr[g] + b * c.kr[g];
+        im = c.h0i[g] + a * c.vi[g] + b * c.ki[g];
+        if (i == kk) re -= c.beta;
+        re *= c.inv_dE;
+        im *= c.inv_dE;
+      }
+      hs[0][i * kSmallLd + kk] = re;
+      hs[1][i * kSmallLd + kk] = im;
+    }
+    __syncthreads();
+    double yr[4], yi[4];
+    const int prv = cur ^ 1;  // P_{l-1} buffer (P_0 = X stays in `cur` for the first term)
+    for (int l = 0; l < L; ++l) {
+      // acc = Ht P_l for this lane's four (state, column) pairs; P_l in buffer `src`
+      const int src = (l == 0) ? cur : ((l & 1) ? prv : cur);
+      const double* pr = ps[src][0];
+      const double* pi = ps[src][1];
+      d4 accR = d4{0, 0, 0, 0}, accI = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int k4 = 0; k4 < kSmallN; k4 += 4) {
+        const int kk = k4 + kq;
+        const double ar = pr[(lane & 15) * kSmallLd + kk], ai = pi[(lane & 15) * kSmallLd + kk];
+        const double br = hs[0][ci * kSmallLd + kk], bi = hs[1][ci * kSmallLd + kk];
+        accR = mfma_f64(ar, br, accR);
+        accR = mfma_f64(-ai, bi, accR);
+        accI = mfma_f64(ar, bi, accI);
+        accI = mfma_f64(ai, br, accI);
+      }
+      // term l + 1 from acc: P_1 = acc, P_{l+1} = 2 acc - P_{l-1}; the old
+      // P_{l-1} (or X) sits where P_{l+1} goes, read and written by this lane only
+      const int dst = (l == 0) ? prv : ((l & 1) ? cur : prv);
+      const double cr = c.coef[2 * (l + 1)], cim = c.coef[2 * (l + 1) + 1];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = 4 * r + kq;
+        const int idx = s * kSmallLd + ci;
+        double vr, vi;
+        if (l == 0) {
+          vr = accR[r];
+          vi = accI[r];
+          const double xr = ps[cur][0][idx], xi = ps[cur][1][idx];
+          yr[r] = c.coef[0] * xr - c.coef[1] * xi;
+          yi[r] = c.coef[0] * xi + c.coef[1] * xr;
+        } else {
+          vr = 2.0 * accR[r] - ps[dst][0][idx];
+          vi = 2.0 * accI[r] - ps[dst][1][idx];
+        }
+        yr[r] += cr * vr - cim * vi;
+        yi[r] += cr * vi + cim * vr;
+        if (l + 1 < L) {
+          ps[dst][0][idx] = vr;
+          ps[dst][1][idx] = vi;
+        }
+      }
+      if (l + 1 < L) __syncthreads();  // P_{l+1} complete before the next product reads it
+    }
+    // X_k = ph Y into the buffer the last product did not read: every wave must
+    // be done with that product first
+    const int last_src = (L == 1) ? cur : (((L - 1) & 1) ? prv : cur);
+    const int xb = last_src ^ 1;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int idx = (4 * r + kq) * kSmallLd + ci;
+      ps[xb][0][idx] = c.phr * yr[r] - c.phi * yi[r];
+      ps[xb][1][idx] = c.phr * yi[r] + c.phi * yr[r];
+    }
+    cur = xb;
+  }
+  __syncthreads();
+  for (int e = tid; e < kSmallS * kSmallN; e += 256) {
+    const int s = e / kSmallN, k = e % kSmallN;
+    c.xr[(long)(s0 + s) * ld + k] = ps[cur][0][s * kSmallLd + k];
+    c.xi[(long)(s0 + s) * ld + k] = ps[cur][1][s * kSmallLd + k];
+  }
+}
+
 inline unsigned grid_for(long total, int block) {
   long g = (total + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -803,6 +923,16 @@ hipError_t launch_diag_commutator(const double* e, long n, long ld, const double
   if (n < 1 || ld < n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(diag_commutator_kernel, dim3(grid_for(n * n, 256)), dim3(256), 0, s, e, n,
                      ld, qr, qi, sgn, br, bi);
+  return hipGetLastError();
+}
+
+long small_chain_max_n() { return kSmallN; }
+
+hipError_t launch_small_chain(const SmallChain& c, int mrows, hipStream_t s) {
+  if (c.ld != kSmallN || mrows < kSmallS || mrows % kSmallS || mrows > kSmallN || c.n > kSmallN ||
+      c.L < 1 || c.k0 < 0 || c.k1 < c.k0)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(small_chain_kernel, dim3(mrows / kSmallS), dim3(256), 0, s, c);
   return hipGetLastError();
 }
 

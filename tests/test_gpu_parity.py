@@ -656,3 +656,41 @@ def test_divergence_flag(fl):
         rep = ctx.last_report
         _say("L", order, "unitarity", rep["unitarity_max"], "diverged", rep["diverged"])
         assert rep["diverged"] == flag
+
+
+@pytest.mark.parametrize("case", ["magnus4", "cf4", "eigen", "propagate"])
+def test_small_chain_matches_launch_per_product_form(fl, case, monkeypatch):
+    """N <= 64 in FP64 runs every step of a build in one launch (16 states per
+    workgroup, Ht formed in LDS per step); the launch-per-product form
+    (FQ_SMALL_CHAIN=0) and the oracle must agree with it."""
+    import torch
+    n, M = 64 if case != "propagate" else 50, 100
+    T = TWO_PI
+    H0, V = _dense_case(n, 1508)
+    scheme = "cf4" if case == "cf4" else "magnus4"
+    f = _cos_nodes(fl, T, M)
+    kw = dict(T=T, M=M, f_nodes=f, scheme=scheme)
+    if case == "eigen":
+        E, Q = np.linalg.eigh(H0)
+        kw.update(h0_eigenvalues=E, hmod=Q.conj().T @ V @ Q)
+    else:
+        kw.update(h0=H0, hmod=V)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("FQ_SMALL_CHAIN", flag)
+        ctx = fl.FloquetContext(profile=True, **kw)
+        if case == "propagate":
+            X0 = haar_unitary(n, np.random.default_rng(3))[:, :7]
+            outs.append(ctx.propagate(X0, 13, 71).cpu().numpy())
+        else:
+            outs.append(ctx.build_ut().cpu().numpy())
+            from paper_1508_07621_amd._abi import K_CHAIN
+            launches = ctx.last_report["n_kernel"][K_CHAIN]
+            assert launches == (1 if flag == "1" else 0)
+        rep = ctx.report
+    _say(case, "chain vs per-product", np.abs(outs[0] - outs[1]).max())
+    assert np.abs(outs[0] - outs[1]).max() < 1e-13
+    if case == "magnus4":
+        Uref = orc.build_ut(H0, V, f, T, M, route="cheb", e_min=rep["e_min"], e_max=rep["e_max"],
+                            L=rep["L"])
+        assert orc.column_error(outs[0], Uref) < FP64_TOL
