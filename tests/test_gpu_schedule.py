@@ -112,3 +112,15 @@ def test_auto_schedule_orders_formats_by_weight(fl):
         reps[tol] = tf
     assert all(a <= b for a, b in zip(reps[1e-9], reps[1e-7]))
     assert all(a <= b for a, b in zip(reps[1e-7], reps[1e-5]))
+
+
+LARGE_SCHEDULES = [["bf16x1"], ["bf16x2"], ["bf16x3_f64acc", "bf16x2", "bf16x1"],
+                   ["fp64", "bf16x1"]]
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5])
+@pytest.mark.parametrize("sched", LARGE_SCHEDULES, ids=["-".join(s) for s in LARGE_SCHEDULES])
+def test_forced_schedule_large_tiles(fl, L, sched):
+    """n = 2049 (17 x 17 tiles of 128): the split-BF16 products take their
+    128 x 128 tiles, the FP64-sum product its 128-row tiles."""
+    test_forced_schedule_matches_oracle(fl, 2049, L, sched)
