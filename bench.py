@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the FP64 reference build of a mixed-precision run")
     ap.add_argument("--no-eig", action="store_true", help="skip the host eigenphase comparison")
+    ap.add_argument("--eig", action="store_true",
+                    help="also time the host eigenphases of U_T when there is no FP64 reference "
+                         "build to compare with (FP64 and tridiagonal runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["magnus4", "magnus6", "cf4"], default=None,
                     help="step operator (default: the workload's)")
@@ -598,14 +601,24 @@ def shard_share(ctx, U, wl, P: int, warmup: int, steps: int, s_full: float, prec
     return res
 
 
+def host_eigenphases(U):
+    """Host FP64 eigenphases: LAPACK zgeev through NumPy (the paper's routine)
+    up to N = 4096, the Hermitian Cayley route above (zgeev takes minutes at
+    N = 10^4). Returns (phases, method)."""
+    from paper_1508_07621_amd.analysis import eigenphases, eigenphases_unitary
+    if U.shape[0] <= 4096:
+        return eigenphases(U), "zgeev"
+    return eigenphases_unitary(U), "zheevd of the Cayley transform"
+
+
 def eigen_errors(U, Uref, T: float):
-    """Host FP64 eigenphases (LAPACK zgeev through NumPy) of both results and
-    the largest quasienergy difference (symmetric circular matching)."""
+    """Host FP64 eigenphases of both results and the largest quasienergy
+    difference (symmetric circular matching)."""
     import numpy as np
-    from paper_1508_07621_amd.analysis import eigenphases
     t0 = time.perf_counter()
-    th = eigenphases(U)
-    th_ref = eigenphases(Uref)
+    th, _ = host_eigenphases(U)
+    _log("host eigenphases of the first result done")
+    th_ref, _ = host_eigenphases(Uref)
 
     def one_way(x, y):
         ext = np.concatenate([y - 2 * math.pi, y, y + 2 * math.pi])
@@ -766,6 +779,8 @@ def main():
                 dq, eig_s = eigen_errors(U.cpu().numpy(), Uref.cpu().numpy(), wl.T)
                 errors["max_quasienergy_error"] = dq
                 extra["eig_seconds_host"] = round(eig_s, 1)
+                extra["eig_method"] = ("zgeev" if n <= 4096 else
+                                       "zheevd of the Cayley transform")
             extra["fp64"] = {"s_per_build": round(s_ref, 4),
                              "timing": f"median of {len(walls)} builds after one warm-up",
                              "s_per_build_each": [round(w, 4) for w in walls],
@@ -832,6 +847,15 @@ def main():
             vs["fp64_e_col"] = ecol(Uref)
         errors["vs_oracle"] = vs
     del Uref
+    if args.eig and not grad_mode and "eig_seconds_host" not in extra:
+        # the paper's routine diagonalisation of U_T (Sec. 3, Sec. 5), timed on the host
+        _log("host FP64 eigenphases of U_T")
+        t0 = time.perf_counter()
+        th, method = host_eigenphases(U.cpu().numpy())
+        extra["eigenphases"] = {"host_s": round(time.perf_counter() - t0, 1), "method": method,
+                                "quasienergy_range": [float(th.min() / wl.T),
+                                                      float(th.max() / wl.T)],
+                                "count": int(th.size)}
     if args.shard and not grad_mode:
         extra["shard"] = shard_share(ctx, U, wl, args.shard, args.warmup, args.steps,
                                      s_per_build, precision)
@@ -865,7 +889,7 @@ def main():
         "roofline": roof,
     }
     out.update(extra)
-    if (not args.no_cpu_baseline and not grad_mode and wl.n <= 4096
+    if (not args.no_cpu_baseline and not grad_mode and wl.n <= 10000
             and wl.scheme == "magnus4"):
         _log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(wl, f_nodes, args.cpu_seconds)

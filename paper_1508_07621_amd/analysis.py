@@ -26,6 +26,37 @@ def eigenphases(U) -> np.ndarray:
     return np.sort(th)
 
 
+def eigenphases_unitary(U) -> np.ndarray:
+    """Sorted theta_mu in (-pi, pi] of a (nearly) unitary U through a Hermitian
+    eigenproblem, for sizes where the general eigensolver (zgeev) is slow
+    (N = 10^4 in minutes): for U' = exp(i phi) U the Cayley transform
+    C = -i (1 - U')(1 + U')^(-1) has the eigenvalues tan(theta'_mu / 2),
+    theta' = theta - phi, and is Hermitian when U is unitary; its Hermitian
+    part is diagonalised (LAPACK zheevd, eigenvalues only) and
+    theta = 2 atan(lambda) + phi. The departure of U from unitarity enters the
+    phases at second order. phi is chosen so that no eigenvalue of U' is close
+    to -1 (|C| bounded), trying a few phases."""
+    try:
+        import torch
+        if isinstance(U, torch.Tensor):
+            U = U.detach().cpu().numpy()
+    except ImportError:
+        pass
+    U = np.asarray(U, dtype=np.complex128)
+    n = U.shape[0]
+    eye = np.eye(n, dtype=np.complex128)
+    for phi in (0.0, 1.0, 2.0, 3.0, 0.5, 2.5):
+        Up = np.exp(1j * phi) * U
+        C = -1j * np.linalg.solve(eye + Up, eye - Up)
+        if np.isfinite(C).all() and np.abs(C).max() < 1e8:
+            break
+    lam = np.linalg.eigvalsh(0.5 * (C + C.conj().T))
+    th = 2.0 * np.arctan(lam) + phi
+    th = np.mod(th + math.pi, 2.0 * math.pi) - math.pi
+    th[th <= -math.pi] += 2.0 * math.pi
+    return np.sort(th)
+
+
 def floquet_states(ctx, U, f_grid):
     """The Floquet states of a built U_T ordered by mean energy (the paper's
     post-processing, Sec. 3 and Sec. 7): host eigendecomposition of U_T

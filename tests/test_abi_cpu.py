@@ -531,3 +531,24 @@ def test_hermitian_cover_rejects_bad_arguments():
     assert L.fq_hermitian_cover(2, None, ctypes.byref(lo), ctypes.byref(hi)) == _abi.FQ_ERR_ARG
     assert L.fq_hermitian_cover(2, A.ctypes.data, ctypes.byref(lo), ctypes.byref(hi)) == \
         _abi.FQ_ERR_NONFINITE
+
+
+def test_unitary_eigenphases_match_the_general_eigensolver():
+    """The Hermitian (Cayley) route to the eigenphases of a unitary U agrees
+    with LAPACK's general eigensolver on Haar-random unitaries (eigenvalues
+    spread over the whole circle, some near -1) and on a slightly non-unitary
+    U as a mixed-precision build leaves it (second order in the departure)."""
+    from paper_1508_07621_amd import analysis
+    from workloads import haar_unitary
+    rng = np.random.default_rng(5)
+    for n in (1, 7, 200):
+        U = haar_unitary(n, rng)
+        th = analysis.eigenphases_unitary(U)
+        ref = orc.eigenphases(U)
+        assert len(th) == n and orc.quasienergy_distance(th, ref, 1.0) < 1e-11
+    U = haar_unitary(150, rng)
+    E = 1e-7 * (rng.standard_normal((150, 150)) + 1j * rng.standard_normal((150, 150))) / 150
+    Up = U + E
+    th = analysis.eigenphases_unitary(Up)
+    ref = np.sort(orc.eigenphases(Up))
+    assert orc.quasienergy_distance(th, ref, 1.0) < 1e-9
