@@ -463,10 +463,11 @@ def chain_roofline(reports, n: int, M: int, terms_per_step: int):
             "frac_of_used_units": round(ach / (PEAK_FP64_MFMA_TFLOPS * cus / 256), 4)}
 
 
-def dense_reverse_roofline(grad_reports, n: int, L: int, M: int):
-    """The dense gradient's reverse-sweep products (FP64): per step, L launches
-    of Ht times the stacked [P_l; Pbar_{l+1}] (2n rows) for l >= 2 and of Ht
-    times Pbar (n rows) for l = 1, 0."""
+def dense_reverse_roofline(grad_reports, n: int, L: int, M: int, precision: str = "fp64"):
+    """The dense gradient's reverse-sweep products (FP64, or FP32 matrix cores
+    for FP32 contexts): per step, L launches of Ht times the stacked
+    [P_l; Pbar_{l+1}] (2n rows) for l >= 2 and of Ht times Pbar (n rows) for
+    l = 1, 0."""
     from paper_1508_07621_amd._abi import K_ADJ_REV
     n_rev = sum(r["n_kernel"][K_ADJ_REV] for r in grad_reports)
     if not n_rev:
@@ -474,17 +475,21 @@ def dense_reverse_roofline(grad_reports, n: int, L: int, M: int):
     ms = sum(r["ms_kernel"][K_ADJ_REV] for r in grad_reports) / n_rev
     rows = (2 * max(L - 2, 0) + (1 if L >= 2 else 0) + 1) * n   # rows per step, all launches
     flops = 8.0 * rows * n * n * M * len(grad_reports) / n_rev  # per launch, averaged
-    mf = flops * mfma_flops_per_flop("fp64", n, 2 * n)
+    f32 = precision == "fp32"
+    mf = flops * (1.0 if f32 else mfma_flops_per_flop("fp64", n, 2 * n))
+    peak = PEAK_FP32_MFMA_TFLOPS if f32 else PEAK_FP64_MFMA_TFLOPS
     ach = flops / (ms * 1e-3) / 1e12
     issued = mf / (ms * 1e-3) / 1e12
-    return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None,
+    return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
             "traffic_detail": None,
-            "kernel": "zgemm_nt_f64_kernel + EpiAdjStep (reverse sweep: Ht times [P_l; Pbar_{l+1}])",
+            "kernel": ("cheb_f32_kernel<..., EpiAdjStep> (FP32 MFMA 16x16x4" if f32 else
+                       "zgemm_nt_f64_kernel + EpiAdjStep (FP64 MFMA 16x16x4") +
+                      "; reverse sweep: Ht times [P_l; Pbar_{l+1}])",
             "avg_launch_ms": round(ms, 4), "launches_timed": n_rev,
             "algorithmic_flops_per_launch": flops, "note": ALGO_NOTE,
             "issued_mfma": {"flops_per_launch": mf, "achieved": round(issued, 3),
-                            "frac": round(issued / PEAK_FP64_MFMA_TFLOPS, 4)}}
+                            "frac": round(issued / peak, 4)}}
 
 
 def time_error(U, wl, kw, spec: str):
@@ -728,8 +733,10 @@ def main():
                              "ms_per_build": round(1e3 * s_per_build - grad_ms, 3),
                              "loss": loss, "max_abs_grad": float(np.max(np.abs(g_last))),
                              "note": ("value = forward build (FP32 products, tape every 16 steps) "
-                                      "+ FP64 reverse sweep for the 256 amplitudes; U_T and "
-                                      "U_bar stored in complex64") if wl.layout == "dense" else
+                                      "+ reverse sweep for the 256 amplitudes (segments "
+                                      "recomputed in FP64, reverse products on FP32 matrix "
+                                      "cores); U_T and U_bar stored in complex64")
+                                     if wl.layout == "dense" else
                                      ("value = forward build (streamed passes, checkpoints every "
                                       "16 steps) + streamed FP64 reverse sweep for the 256 "
                                       "amplitudes")}
@@ -753,7 +760,7 @@ def main():
             roof = dense_roofline(reports, n, precision, args.workload)
         build_tflops = info["L"] * wl.M * 8.0 * n ** 3 / s_per_build / 1e12
         if grad_mode:
-            rev = dense_reverse_roofline(grad_reports, n, info["L"], wl.M)
+            rev = dense_reverse_roofline(grad_reports, n, info["L"], wl.M, precision)
             if rev:  # build + gradient: the FP64 reverse-sweep products dominate
                 extra["build_roofline"] = roof
                 roof = rev

@@ -364,7 +364,11 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * floquet_build_UT. U_bar: device, n*n complex (fq_params.dtype) row-major with
  * U_bar[i][j] = dLoss/dRe U[i][j] + i dLoss/dIm U[i][j]. grad_f_nodes: host,
  * 2*M float64 (2*M*S with several drive terms), same order as f_nodes. Needs
- * checkpoint_every > 0.
+ * checkpoint_every > 0. Dense layouts: every step of a checkpoint segment is
+ * recomputed in FP64; the reverse products run in FP64, or, for FQ_FP32
+ * contexts, on FP32 matrix cores (operands rounded to FP32 as they are
+ * staged, FP64 epilogues and FP64 sums of the contractions: about FP32
+ * accuracy in the derivative).
  * FQ_TRIDIAG: up to n = 2048 one workgroup reverses each state column;
  * longer columns run the same recurrences in streamed passes of at most 128
  * terms over windows of rows with ghost rows (setting the environment variable

@@ -117,7 +117,7 @@ struct Layout {
          off_pb = 0, off_pc = 0, off_htx = 0, off_tape = 0, off_small = 0, off_ab = 0, off_coef = 0,
          off_seg = 0, off_stack = 0, off_lam = 0, off_grad = 0, off_gauge = 0, off_stream = 0,
          off_adj = 0,
-         off_comm6 = 0, off_vec = 0;
+         off_comm6 = 0, off_vec = 0, off_drive32 = 0;
   long np = 0;
   int n_tape = 0;
 };
@@ -175,6 +175,8 @@ Layout plan(const fq_system* sys, const fq_params* par) {
       lay.off_stack = take(4 * plane2);
       lay.off_lam = take(plane2);
       lay.off_grad = take((size_t)J * sizeof(double) * (size_t)Ms);
+      if (par->precision == FQ_FP32)  // the drive block in FP32 planes for the reverse products
+        lay.off_drive32 = take((size_t)J * 2 * sizeof(float) * (size_t)lay.np * (size_t)lay.np);
     }
   } else {
     lay.np = pad_to(n, dense_tile(n));
@@ -1328,9 +1330,30 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
     FQ_HIP(c, hipMemcpyAsync(dim, src + plane, pbytes, hipMemcpyDeviceToDevice, s));
     return FQ_OK;
   };
+  // FQ_FP32 contexts run the reverse products on FP32 matrix cores (operands
+  // rounded while staged; FP64 epilogues and contraction sums)
+  const bool f32 = c->adj_f32;
+  const float* ht32 = static_cast<const float*>(c->htx);
   auto dot = [&](int i, double w) -> fq_status {
-    FQ_HIP(c, fq::launch_adj_dot(top_re(i), top_im(i), c->vr, c->vi, dot_cols, bot_re(i),
-                                 bot_im(i), w, gk, np, s));
+    if (f32)
+      FQ_HIP(c, fq::launch_adj_dot_f32(top_re(i), 2 * plane, c->drive32, (long)c->J * plane,
+                                       dot_cols, bot_re(i), bot_im(i), w, gk, np, s));
+    else
+      FQ_HIP(c, fq::launch_adj_dot(top_re(i), top_im(i), c->vr, c->vi, dot_cols, bot_re(i),
+                                   bot_im(i), w, gk, np, s));
+    return FQ_OK;
+  };
+  // A = [P_l; Pbar_{l+1}] rows from a_re (imaginary plane two planes on), Ht
+  auto rev = [&](double* a_re, double* a_im, int mrows, int o, std::complex<double> dl, double fac,
+                 int row_off) -> fq_status {
+    FQ_MARK(c, FQ_K_ADJ_REV);
+    if (f32)
+      FQ_HIP(c, fq::launch_adj_step_f32(a_re, mrows, 2 * plane, ht32, top_re(o), top_im(o), lr, li,
+                                        dl.real(), dl.imag(), fac, row_off, np, s));
+    else
+      FQ_HIP(c, fq::launch_adj_step(a_re, a_im, mrows, c->htr, c->hti, top_re(o), top_im(o), lr,
+                                    li, dl.real(), dl.imag(), fac, row_off, np, s));
+    FQ_MARK(c, -1);
     return FQ_OK;
   };
   // Pbar_L = d_L Lambda over P_{L-1} in stack 0; P_L over zero in stack 1
@@ -1346,15 +1369,9 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
     FQ_TRY(dot(cur, 2.0));  // <Pbar_{l+1}, D P_l>
     d = D(l);
     if (l >= 2) {
-      FQ_MARK(c, FQ_K_ADJ_REV);
-      FQ_HIP(c, fq::launch_adj_step(top_re(cur), top_im(cur), 2 * np, c->htr, c->hti, top_re(o),
-                                    top_im(o), lr, li, d.real(), d.imag(), 2.0, 0, np, s));
-      FQ_MARK(c, -1);
+      FQ_TRY(rev(top_re(cur), top_im(cur), 2 * np, o, d, 2.0, 0));
     } else {  // l = 1: Pbar_1 only; P_0 = X_{k-1} from the segment store
-      FQ_MARK(c, FQ_K_ADJ_REV);
-      FQ_HIP(c, fq::launch_adj_step(bot_re(cur), bot_im(cur), np, c->htr, c->hti, top_re(o),
-                                    top_im(o), lr, li, d.real(), d.imag(), 2.0, np, np, s));
-      FQ_MARK(c, -1);
+      FQ_TRY(rev(bot_re(cur), bot_im(cur), np, o, d, 2.0, np));
       FQ_TRY(copy2(top_re(o), top_im(o), seg_x));
     }
     cur = o;
@@ -1367,10 +1384,7 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
   const int o = 1 - cur;
   FQ_TRY(dot(cur, 1.0));
   d = D(0);
-  FQ_MARK(c, FQ_K_ADJ_REV);
-  FQ_HIP(c, fq::launch_adj_step(bot_re(cur), bot_im(cur), np, c->htr, c->hti, top_re(o), top_im(o),
-                                lr, li, d.real(), d.imag(), 1.0, np, np, s));
-  FQ_MARK(c, -1);
+  FQ_TRY(rev(bot_re(cur), bot_im(cur), np, o, d, 1.0, np));
   FQ_HIP(c, hipMemcpyAsync(lr, bot_re(o), pbytes, hipMemcpyDeviceToDevice, s));
   FQ_HIP(c, hipMemcpyAsync(li, bot_im(o), pbytes, hipMemcpyDeviceToDevice, s));
   return FQ_OK;
@@ -1456,7 +1470,14 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
       c->save_pl = c->save_plm1 = nullptr;
     }
     for (int k = k1 - 1; k >= k0; --k) {
-      FQ_TRY(dense_heff(c, k));
+      if (c->adj_f32) {  // Ht also in the FP32 product format for the reverse products
+        c->precision = FQ_FP32;
+        const fq_status hs = dense_heff(c, k);
+        c->precision = FQ_FP64;
+        FQ_TRY(hs);
+      } else {
+        FQ_TRY(dense_heff(c, k));
+      }
       FQ_TRY(adjoint_step(c, k, k - k0, any_b));
     }
   }
@@ -1901,6 +1922,10 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
       c->stack[1] = c->stack[0] + 4 * plane;
       c->lam = P(lay.off_lam);
       c->d_grad = P(lay.off_grad);
+      if (lay.off_drive32) {
+        c->drive32 = reinterpret_cast<float*>(c->ws + lay.off_drive32);
+        c->adj_f32 = true;
+      }
     }
   }
 
@@ -1943,6 +1968,11 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     }
     if (st == FQ_OK && c->scheme == FQ_MAGNUS6) st = magnus6_commutators(c);
     if (st != FQ_OK) return bail(st);
+    if (c->drive32) {  // both planes of all J drive matrices, in their order
+      he = fq::launch_f64_to_f32(c->vr, c->drive32, 2L * c->J * (long)plane, c->stream);
+      if (he != hipSuccess)
+        return bail(fail(FQ_ERR_HIP, "setup kernels failed: %s", hipGetErrorString(he)));
+    }
   }
 
   // spectral interval
@@ -2191,8 +2221,9 @@ fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   if (c->ckpt <= 0) return fail(FQ_ERR_STATE, "context was created without a gradient tape");
   if (!c->tape_valid) return fail(FQ_ERR_STATE, "no tape: call floquet_build_UT first");
   if (c->layout == FQ_TRIDIAG) return tridiag_adjoint(c, U_bar, grad_f_nodes);
-  // The reverse sweep and the segment recomputation run in FP64 whatever the
-  // build precision: they differentiate the FP64 Chebyshev map.
+  // The segment recomputation runs in FP64 whatever the build precision (the
+  // sweep differentiates the FP64 Chebyshev map); the reverse products run in
+  // FP64, or on FP32 matrix cores for FQ_FP32 contexts (adj_f32).
   struct Restore {
     fq_ctx* c;
     int prec;

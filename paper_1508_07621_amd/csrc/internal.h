@@ -85,6 +85,19 @@ struct SmallChain {
 long small_chain_max_n();
 hipError_t launch_small_chain(const SmallChain& c, int mrows, hipStream_t s);
 
+// The same two adjoint products on FP32 matrix cores (FQ_FP32 contexts): A in
+// FP64 planes (re plane, im plane at + plane_a elements) rounded to FP32 while
+// staged, B in FP32 planes (Ht in the FP32 product format; the drive block
+// re planes then im planes at + plane_b), FP64 epilogues and contraction sums.
+hipError_t launch_adj_step_f32(const double* ar, int mrows, long plane_a, const float* ht,
+                               double* sr, double* si, const double* lr, const double* li, double dr,
+                               double di, double fac, int row_off, int np, hipStream_t s);
+hipError_t launch_adj_dot_f32(const double* pr, long plane_a, const float* drive, long plane_b,
+                              int ncols, const double* pbr, const double* pbi, double w,
+                              double* out, int np, hipStream_t s);
+// dst[e] = (float)src[e], e < count.
+hipError_t launch_f64_to_f32(const double* src, float* dst, long count, hipStream_t s);
+
 // Launch one Chebyshev product over rows [0, mrows) of the state-major
 // operands (mrows, np multiples of the tile size chosen by the launcher).
 hipError_t launch_cheb_f64(const ChebTerm& t, int mrows, int np, hipStream_t s);
@@ -391,6 +404,8 @@ struct fq_ctx {
   double* stack[2] = {nullptr, nullptr};
   double* lam = nullptr;
   double* d_grad = nullptr;
+  float* drive32 = nullptr;           // FQ_FP32 gradient: the drive block in FP32 planes
+  bool adj_f32 = false;               // reverse-sweep products on FP32 matrix cores
   double* save_pl = nullptr;          // when set, a step also stores P_L and P_{L-1} here
   double* save_plm1 = nullptr;
   double* small = nullptr;            // 64 doubles of reduction scratch

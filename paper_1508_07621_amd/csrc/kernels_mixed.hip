@@ -19,6 +19,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "epilogues.h"
 #include "formats.h"
 #include "internal.h"
 
@@ -72,12 +73,14 @@ struct EpiMix {
       store_c(t.o, t.o_fmt, t.plane, m, n, ld, o_r, o_i);
     }
   }
+  __device__ __forceinline__ void finish() const {}
 };
 
 struct MixOperands {
-  const void* a;  // A planes (format per kernel instance)
+  const void* a;  // A planes (format per kernel instance): real plane, imaginary plane
   const void* b;  // B planes
-  long plane;
+  long plane_a;   // elements from A's real plane to its imaginary plane
+  long plane_b;   // same for B
   int ld;
   int kdim;
   int tiles_m, tiles_n;
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WGN, wn = wid % WGN;
-  const long ld = op.ld, plane = op.plane;
+  const long ld = op.ld, plane = op.plane_a, plane_b = op.plane_b;
 
   f4 accR[FM][FN], accI[FM][FN];
 #pragma unroll
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
       const int c = tid + r * NT, row = c / CPRB, col = 4 * (c % CPRB);
       const long off = (long)(n0 + row) * ld + k0 + col;
       gb[0][r] = *reinterpret_cast<const f4*>(b + off);
-      gb[1][r] = *reinterpret_cast<const f4*>(b + plane + off);
+      gb[1][r] = *reinterpret_cast<const f4*>(b + plane_b + off);
     }
   };
   auto lstore = [&](int st) {
@@ -229,6 +232,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_f32_kernel(MixOperands op,
         const int n = n0 + wn * WTN + j * 16 + (lane & 15);
         epi(m, n, accR[i][j][r], accI[i][j][r]);
       }
+  epi.finish();
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -877,7 +881,7 @@ hipError_t dispatch_bf3(const ChebTermX& t, int tf, int mrows, int np, hipStream
 
 template <class Epi>
 hipError_t dispatch(const ChebTermX& t, int precision, int mrows, int np, Epi epi, hipStream_t s) {
-  MixOperands op{t.a, t.b, t.plane, np, np, 0, 0};
+  MixOperands op{t.a, t.b, t.plane, t.plane, np, np, 0, 0};
   // The first product of a step (A = X in FP64) runs on FP64 matrix cores and
   // reaches the product format through launch_to_product; these kernels take
   // the P_l in the product format.
@@ -1010,6 +1014,37 @@ hipError_t launch_cheb_mixed(const ChebTermX& t, int precision, int mrows, int n
       return dispatch(t, precision, mrows, np, EpiMix<CHEB_LAST>{t, np}, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_step_f32(const double* ar, int mrows, long plane_a, const float* ht,
+                               double* sr, double* si, const double* lr, const double* li, double dr,
+                               double di, double fac, int row_off, int np, hipStream_t s) {
+  MixOperands op{ar, ht, plane_a, (long)np * np, np, np, 0, 0};
+  EpiAdjStep e{sr, si, lr, li, dr, di, fac, np, row_off};
+  return launch_f32<true>(op, mrows, np, e, s);
+}
+
+hipError_t launch_adj_dot_f32(const double* pr, long plane_a, const float* drive, long plane_b,
+                              int ncols, const double* pbr, const double* pbi, double w,
+                              double* out, int np, hipStream_t s) {
+  MixOperands op{pr, drive, plane_a, plane_b, np, np, 0, 0};
+  EpiAdjDot e{pbr, pbi, out, np, w};
+  return launch_f32<true>(op, np, ncols, e, s);
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                  long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+hipError_t launch_f64_to_f32(const double* src, float* dst, long count, hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  long g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)g), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_heff_mixed(const double* h0r, const double* h0i, const double* vr,
