@@ -298,141 +298,159 @@ __device__ __forceinline__ void split_n(float x, u16* out) {
 
 // Epilogue of a split-BF16 product tile from its Re and Im in LDS (FP32,
 // k-blocked order, see the writers): each thread takes 8 consecutive columns
-// of one row (one 16-byte chunk of every BF16 plane), reads P_{l-1} (or X for
-// the first product), forms the term in FP64 and stores it as BF16X3 pieces
-// with its stored value weighted into the sum Y, or, for the last product,
-// writes X_k = exp(-i beta h) (Y + c_L P_L) as FP64 planes.
+// of one row at a time (one 16-byte chunk of every BF16 plane), reads P_{l-1}
+// (or X for the first product), forms the term in FP64 and stores it as BF16X3
+// pieces with its stored value weighted into the sum Y, or, for the last
+// product, writes X_k = exp(-i beta h) (Y + c_L P_L) as FP64 planes. The
+// global loads of two chunks (P_{l-1} and Y) are issued before any of their
+// stores: the stores may alias later loads of the same buffers in the
+// compiler's view (P_{l+1} overwrites P_{l-1} in place), which would otherwise
+// serialise one memory round trip per chunk and per buffer.
 template <int BM, int BN, int NT, int KIND, bool P_F64>
 __device__ __forceinline__ void bf3_tile_epilogue(const Bf3Args& g, const float* cre,
                                                   const float* cim, int m0, int n0, int tid) {
   constexpr int NS = BF3_PLANES;
   constexpr bool FIRST = KIND == CHEB_FIRST || KIND == CHEB_FIRST_LAST;
   constexpr bool TO_X = KIND == CHEB_LAST || KIND == CHEB_FIRST_LAST;
+  constexpr int NQ = BM * BN / 8 / NT;   // chunks per thread
+  constexpr int B = NQ >= 2 ? 2 : 1;     // chunks whose loads are in flight together
+  static_assert(NQ * NT * 8 == BM * BN && NQ % B == 0, "chunk split");
   const long np = g.np, plane = g.plane;
   const double cr_ = g.cr, ci_ = g.ci;
-  for (int q = tid; q < BM * BN / 8; q += NT) {
-    const int kbl = q / (2 * BM), rem = q % (2 * BM);
-    const int row = rem >> 1, slot = rem & 1;
-    const long m = m0 + row;
-    const long n = n0 + kbl * 16 + 8 * (slot ^ ((row >> 3) & 1));  // first of 8 columns
-    const long chunk = ((long)(n0 / 16 + kbl) * np + m) * 16 + 8 * slot;  // in a BF16X3 plane
-    float ar[8], ai[8];
-    *reinterpret_cast<f4*>(ar) = *reinterpret_cast<const f4*>(cre + q * 8);
-    *reinterpret_cast<f4*>(ar + 4) = *reinterpret_cast<const f4*>(cre + q * 8 + 4);
-    *reinterpret_cast<f4*>(ai) = *reinterpret_cast<const f4*>(cim + q * 8);
-    *reinterpret_cast<f4*>(ai + 4) = *reinterpret_cast<const f4*>(cim + q * 8 + 4);
-    // P_{l-1} (X for the first product)
-    double pr[8], pi[8];
-    if constexpr (P_F64) {
-      const double* p = static_cast<const double*>(g.p) + m * np + n;
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        const d2 vr = *reinterpret_cast<const d2*>(p + e);
-        const d2 vi = *reinterpret_cast<const d2*>(p + plane + e);
-        pr[e] = vr[0]; pr[e + 1] = vr[1];
-        pi[e] = vi[0]; pi[e + 1] = vi[1];
-      }
-    } else {
-      const u16* p = static_cast<const u16*>(g.p) + chunk;
-      u32x4 w[6];
+  for (int i0 = 0; i0 < NQ; i0 += B) {
+    long mrow[B], ncol[B], chunk[B];
+    float ar[B][8], ai[B][8];
+    u32x4 pw[B][6];          // P_{l-1} as stored pieces (BF16X3)
+    d2 pd[B][8];             // or as FP64 pairs: [0..3] re, [4..7] im
+    d2 yv[B][8];             // Y pairs: [0..3] re, [4..7] im
+    // ---- loads of B chunks ----
 #pragma unroll
-      for (int k = 0; k < 6; ++k) w[k] = *reinterpret_cast<const u32x4*>(p + k * plane);
+    for (int b = 0; b < B; ++b) {
+      const int q = tid + (i0 + b) * NT;
+      const int kbl = q / (2 * BM), rem = q % (2 * BM);
+      const int row = rem >> 1, slot = rem & 1;
+      mrow[b] = m0 + row;
+      ncol[b] = n0 + kbl * 16 + 8 * (slot ^ ((row >> 3) & 1));  // first of 8 columns
+      chunk[b] = ((long)(n0 / 16 + kbl) * np + mrow[b]) * 16 + 8 * slot;  // in a BF16X3 plane
+      *reinterpret_cast<f4*>(ar[b]) = *reinterpret_cast<const f4*>(cre + q * 8);
+      *reinterpret_cast<f4*>(ar[b] + 4) = *reinterpret_cast<const f4*>(cre + q * 8 + 4);
+      *reinterpret_cast<f4*>(ai[b]) = *reinterpret_cast<const f4*>(cim + q * 8);
+      *reinterpret_cast<f4*>(ai[b] + 4) = *reinterpret_cast<const f4*>(cim + q * 8 + 4);
+      if constexpr (P_F64) {
+        const double* p = static_cast<const double*>(g.p) + mrow[b] * np + ncol[b];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        float s3[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const uint32_t word = w[k][e >> 1];
-          s3[k] = bf16_val((u16)((e & 1) ? (word >> 16) : (word & 0xffffu)));
+        for (int e = 0; e < 4; ++e) {
+          pd[b][e] = *reinterpret_cast<const d2*>(p + 2 * e);
+          pd[b][4 + e] = *reinterpret_cast<const d2*>(p + plane + 2 * e);
         }
-        pr[e] = (double)(s3[0] + s3[1] + s3[2]);
-        pi[e] = (double)(s3[3] + s3[4] + s3[5]);
+      } else {
+        const u16* p = static_cast<const u16*>(g.p) + chunk[b];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pw[b][k] = *reinterpret_cast<const u32x4*>(p + k * plane);
+      }
+      if constexpr (!FIRST) {
+        const double* yr = g.y_re + mrow[b] * np + ncol[b];
+        const double* yi = g.y_im + mrow[b] * np + ncol[b];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          yv[b][e] = *reinterpret_cast<const d2*>(yr + 2 * e);
+          yv[b][4 + e] = *reinterpret_cast<const d2*>(yi + 2 * e);
+        }
       }
     }
-    double* yr = g.y_re + m * np + n;
-    double* yi = g.y_im + m * np + n;
-    if constexpr (!TO_X) {
-      // P_{l+1} = 2 acc - P_{l-1}, or P_1 = acc: stored as BF16X3, and its
-      // stored value weighted into Y (Y = c_0 X + c_1 P_1 for the first)
-      u32x4 w[NS];
+    // ---- arithmetic and stores ----
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      double pr[8], pi[8];  // P_{l-1} (X for the first product)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const double orr = FIRST ? (double)ar[e] : 2.0 * (double)ar[e] - pr[e];
-        const double oii = FIRST ? (double)ai[e] : 2.0 * (double)ai[e] - pi[e];
-        u16 hs[NS];
-        split3((float)orr, hs[0], hs[1], hs[2]);
-        split3((float)oii, hs[3], hs[4], hs[5]);
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          if (e & 1)
-            w[k][e >> 1] |= (uint32_t)hs[k] << 16;
-          else
-            w[k][e >> 1] = hs[k];
-        }
-        // the value the pieces hold; for the first product P_0 = X stays in (pr, pi)
-        const double vr = (double)(bf16_val(hs[0]) + bf16_val(hs[1]) + bf16_val(hs[2]));
-        const double vi = (double)(bf16_val(hs[3]) + bf16_val(hs[4]) + bf16_val(hs[5]));
-        if constexpr (FIRST) {
-          const double xr = pr[e], xi = pi[e];
-          pr[e] = g.c0r * xr - g.c0i * xi + cr_ * vr - ci_ * vi;
-          pi[e] = g.c0r * xi + g.c0i * xr + cr_ * vi + ci_ * vr;
+        if constexpr (P_F64) {
+          pr[e] = pd[b][e >> 1][e & 1];
+          pi[e] = pd[b][4 + (e >> 1)][e & 1];
         } else {
-          pr[e] = vr;
-          pi[e] = vi;
+          float s3[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const uint32_t word = pw[b][k][e >> 1];
+            s3[k] = bf16_val((u16)((e & 1) ? (word >> 16) : (word & 0xffffu)));
+          }
+          pr[e] = (double)(s3[0] + s3[1] + s3[2]);
+          pi[e] = (double)(s3[3] + s3[4] + s3[5]);
         }
       }
-      u16* o = static_cast<u16*>(g.o) + chunk;
+      double* yr = g.y_re + mrow[b] * np + ncol[b];
+      double* yi = g.y_im + mrow[b] * np + ncol[b];
+      if constexpr (!TO_X) {
+        // P_{l+1} = 2 acc - P_{l-1}, or P_1 = acc: stored as BF16X3, and its
+        // stored value weighted into Y (Y = c_0 X + c_1 P_1 for the first)
+        u32x4 w[NS];
+        double vr8[8], vi8[8];
 #pragma unroll
-      for (int k = 0; k < NS; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
+        for (int e = 0; e < 8; ++e) {
+          const double orr = FIRST ? (double)ar[b][e] : 2.0 * (double)ar[b][e] - pr[e];
+          const double oii = FIRST ? (double)ai[b][e] : 2.0 * (double)ai[b][e] - pi[e];
+          u16 hs[NS];
+          split3((float)orr, hs[0], hs[1], hs[2]);
+          split3((float)oii, hs[3], hs[4], hs[5]);
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        d2 vr, vi;
-        if constexpr (FIRST) {
-          vr = d2{pr[e], pr[e + 1]};
-          vi = d2{pi[e], pi[e + 1]};
-        } else {
-          vr = *reinterpret_cast<const d2*>(yr + e);
-          vi = *reinterpret_cast<const d2*>(yi + e);
+          for (int k = 0; k < NS; ++k) {
+            if (e & 1)
+              w[k][e >> 1] |= (uint32_t)hs[k] << 16;
+            else
+              w[k][e >> 1] = hs[k];
+          }
+          vr8[e] = (double)(bf16_val(hs[0]) + bf16_val(hs[1]) + bf16_val(hs[2]));
+          vi8[e] = (double)(bf16_val(hs[3]) + bf16_val(hs[4]) + bf16_val(hs[5]));
+        }
+        u16* o = static_cast<u16*>(g.o) + chunk[b];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) *reinterpret_cast<u32x4*>(o + k * plane) = w[k];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          d2 vr, vi;
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            vr[u] += cr_ * pr[e + u] - ci_ * pi[e + u];
-            vi[u] += cr_ * pi[e + u] + ci_ * pr[e + u];
+            const double tr = cr_ * vr8[e + u] - ci_ * vi8[e + u];
+            const double ti = cr_ * vi8[e + u] + ci_ * vr8[e + u];
+            if constexpr (FIRST) {
+              vr[u] = g.c0r * pr[e + u] - g.c0i * pi[e + u] + tr;
+              vi[u] = g.c0r * pi[e + u] + g.c0i * pr[e + u] + ti;
+            } else {
+              vr[u] = yv[b][e >> 1][u] + tr;
+              vi[u] = yv[b][4 + (e >> 1)][u] + ti;
+            }
           }
+          *reinterpret_cast<d2*>(yr + e) = vr;
+          *reinterpret_cast<d2*>(yi + e) = vi;
         }
-        *reinterpret_cast<d2*>(yr + e) = vr;
-        *reinterpret_cast<d2*>(yi + e) = vi;
-      }
-    } else {  // X_k = ph (Y + c_L (2 acc - P_{L-1})), or ph (c_0 X + c_1 acc) when L = 1
-      double* o = static_cast<double*>(g.o) + m * np + n;
+      } else {  // X_k = ph (Y + c_L (2 acc - P_{L-1})), or ph (c_0 X + c_1 acc) when L = 1
+        double* o = static_cast<double*>(g.o) + mrow[b] * np + ncol[b];
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        d2 xr, xi;
-        d2 vr = d2{0.0, 0.0}, vi = d2{0.0, 0.0};
-        if constexpr (!FIRST) {
-          vr = *reinterpret_cast<const d2*>(yr + e);
-          vi = *reinterpret_cast<const d2*>(yi + e);
-        }
+        for (int e = 0; e < 8; e += 2) {
+          d2 xr, xi;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          double qr, qi, sr, si;
-          if constexpr (FIRST) {
-            qr = (double)ar[e + u];
-            qi = (double)ai[e + u];
-            sr = g.c0r * pr[e + u] - g.c0i * pi[e + u];
-            si = g.c0r * pi[e + u] + g.c0i * pr[e + u];
-          } else {
-            qr = 2.0 * (double)ar[e + u] - pr[e + u];
-            qi = 2.0 * (double)ai[e + u] - pi[e + u];
-            sr = vr[u];
-            si = vi[u];
+          for (int u = 0; u < 2; ++u) {
+            double qr, qi, sr, si;
+            if constexpr (FIRST) {
+              qr = (double)ar[b][e + u];
+              qi = (double)ai[b][e + u];
+              sr = g.c0r * pr[e + u] - g.c0i * pi[e + u];
+              si = g.c0r * pi[e + u] + g.c0i * pr[e + u];
+            } else {
+              qr = 2.0 * (double)ar[b][e + u] - pr[e + u];
+              qi = 2.0 * (double)ai[b][e + u] - pi[e + u];
+              sr = yv[b][e >> 1][u];
+              si = yv[b][4 + (e >> 1)][u];
+            }
+            sr += cr_ * qr - ci_ * qi;
+            si += cr_ * qi + ci_ * qr;
+            xr[u] = g.phr * sr - g.phi * si;
+            xi[u] = g.phr * si + g.phi * sr;
           }
-          sr += cr_ * qr - ci_ * qi;
-          si += cr_ * qi + ci_ * qr;
-          xr[u] = g.phr * sr - g.phi * si;
-          xi[u] = g.phr * si + g.phi * sr;
+          *reinterpret_cast<d2*>(o + e) = xr;
+          *reinterpret_cast<d2*>(o + plane + e) = xi;
         }
-        *reinterpret_cast<d2*>(o + e) = xr;
-        *reinterpret_cast<d2*>(o + plane + e) = xi;
       }
     }
   }
