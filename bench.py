@@ -701,6 +701,7 @@ def main():
                             mixed_tol=args.mixed_tol if precision != "fp64" else 0.0,
                             profile=True, device=dev, checkpoint_every=16 if grad_mode else 0,
                             dtype="complex64" if c64_grad else "complex128",
+                            grad_pair_sums=grad_mode,   # gradient w.r.t. step amplitudes
                             scheme=wl.scheme, **interval, **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
@@ -735,11 +736,13 @@ def main():
                              "note": ("value = forward build (FP32 products, tape every 16 steps) "
                                       "+ reverse sweep for the 256 amplitudes (segments "
                                       "recomputed in FP64, reverse products on FP32 matrix "
-                                      "cores); U_T and U_bar stored in complex64")
+                                      "cores); U_T and U_bar stored in complex64; "
+                                      "node-pair sums only (the commutator contraction, "
+                                      "which cancels in them, skipped)")
                                      if wl.layout == "dense" else
                                      ("value = forward build (streamed passes, checkpoints every "
                                       "16 steps) + streamed FP64 reverse sweep for the 256 "
-                                      "amplitudes")}
+                                      "amplitudes (node-pair sums only)")}
         if args.fd_check > 0:
             _log("directional finite-difference check of the gradient")
             fkw = {k: v for k, v in kw.items()}

@@ -214,6 +214,17 @@ typedef struct fq_params {
                                 library's choice; FQ_TERM_FP64 only on a
                                 leading run of terms */
   int32_t n_term_formats;    /* entries of term_formats (0 when NULL) */
+  int32_t grad_pair_sums;    /* floquet_grad with one drive term: 0 = the
+                                derivative with respect to every node sample;
+                                1 = only the sums over each step's two nodes,
+                                grad[2k] + grad[2k+1] = dLoss/dA_k for an
+                                amplitude A_k moving both nodes of step k
+                                together (the caller's drive need not be
+                                constant over the step), returned as two equal
+                                halves. The commutator K enters H_eff through
+                                b_k, proportional to the node difference, so
+                                its contraction cancels in these sums and is
+                                skipped. Ignored with several drive terms. */
 } fq_params;
 
 /* Kernel kinds timed in profile mode (indices of fq_report.ms_kernel). */
@@ -363,7 +374,8 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * and L held fixed), recomputing each segment from the tape of the last
  * floquet_build_UT. U_bar: device, n*n complex (fq_params.dtype) row-major with
  * U_bar[i][j] = dLoss/dRe U[i][j] + i dLoss/dIm U[i][j]. grad_f_nodes: host,
- * 2*M float64 (2*M*S with several drive terms), same order as f_nodes. Needs
+ * 2*M float64 (2*M*S with several drive terms), same order as f_nodes (with
+ * fq_params.grad_pair_sums only each step's node sum is meaningful). Needs
  * checkpoint_every > 0. Dense layouts: every step of a checkpoint segment is
  * recomputed in FP64; the reverse products run in FP64, or, for FQ_FP32
  * contexts, on FP32 matrix cores (operands rounded to FP32 as they are
@@ -371,14 +383,15 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * accuracy in the derivative).
  * FQ_TRIDIAG: up to n = 2048 one workgroup reverses each state column;
  * longer columns run the same recurrences in streamed passes of at most 128
- * terms over windows of rows with ghost rows (setting the environment variable
- * FQ_TRIDIAG_STREAMED_ADJOINT=1 before fq_workspace_bytes / fq_create selects
- * the streamed form for any n; both give the same derivative). For n > 4096
- * the build records its checkpoints in the state type, so the gradient needs
- * complex128 state blocks there. In profile mode the report then holds the
- * streamed passes' times (FQ_K_ADJ_FWD, FQ_K_ADJ_REV); with FQ_PROGRESS=1 in
- * the environment the streamed sweep prints a line on stderr per checkpoint
- * segment. */
+ * terms over windows of rows with ghost rows, one wave per real or imaginary
+ * part (setting the environment variable FQ_TRIDIAG_STREAMED_ADJOINT=1 before
+ * fq_workspace_bytes / fq_create selects the streamed form for any n; both
+ * give the same derivative up to rounding). For n > 4096 the build records its
+ * checkpoints in the state type (complex64 checkpoints round the recomputed
+ * segments' starting states). In profile mode the report then holds the
+ * streamed passes' times (FQ_K_ADJ_FWD: segment recompute, FQ_K_ADJ_REV:
+ * reverse); with FQ_PROGRESS=1 in the environment the streamed sweep prints a
+ * line on stderr per checkpoint segment. */
 fq_status floquet_grad(fq_ctx* ctx, const void* U_bar, double* grad_f_nodes);
 
 /* One-shot build of U_T that allocates nothing, for callers that cannot

@@ -55,7 +55,7 @@ class FqParams(ctypes.Structure):
                 ("profile", c_int32), ("reorthonormalize", c_int32),
                 ("dtype", c_int32), ("scheme", c_int32),
                 ("mixed_tol", c_double), ("term_formats", POINTER(c_int32)),
-                ("n_term_formats", c_int32)]
+                ("n_term_formats", c_int32), ("grad_pair_sums", c_int32)]
 
 
 class FqReport(ctypes.Structure):

@@ -188,19 +188,25 @@ Layout plan(const fq_system* sys, const fq_params* par) {
       lay.off_y = take(plane2);
     }
     lay.off_gauge = take(2 * sizeof(double) * (size_t)n * (size_t)Ms);
-    if (n > fq::tridiag_resident_max_n()) {  // two 8-plane states of n16 x n, per-step rows
-      const size_t n16 = (size_t)(n + 15) / 16 * 16;
-      lay.off_stream = take(sizeof(double) * (2 * 8 * n16 * (size_t)n + 6 * n16));
-    }
-    if (par->checkpoint_every > 0) {  // X_{j ckpt} per column; per-column segment buffers
+    const bool streamed_grad = streamed_adjoint(sys, par);
+    const size_t n16 = (size_t)(n + 15) / 16 * 16;
+    const size_t splane = sizeof(double) * n16 * (size_t)n;  // one state plane
+    if (n > fq::tridiag_resident_max_n() || streamed_grad)  // two 8-plane states, per-step rows
+      lay.off_stream = take(2 * 8 * splane + sizeof(double) * 6 * n16);
+    if (par->checkpoint_every > 0) {  // X_{j ckpt} per column; segment buffers
       const size_t vec = 2 * sizeof(double) * (size_t)n;
       lay.n_tape = (Ms + cks - 1) / cks + 1;
       lay.off_tape = take(vec * (size_t)n * (size_t)lay.n_tape);
-      lay.off_seg = take(vec * (size_t)n * 3 * (size_t)cks);
-      lay.off_grad = take(2 * sizeof(double) * (size_t)Ms);
-      // streamed reverse sweep: the carried state of two pass sets (4 + 4
-      // vectors) and two Lambda vectors
-      if (streamed_adjoint(sys, par)) lay.off_adj = take(10 * vec * (size_t)n);
+      if (streamed_grad) {
+        // per step of a segment P_{L-1}, P_L (4 planes); two 8-plane pass
+        // states, two 2-plane Lambdas and the per-step tables; slotted sums
+        lay.off_seg = take(4 * splane * (size_t)cks);
+        lay.off_adj = take(20 * splane + sizeof(double) * 7 * n16);
+        lay.off_grad = take(2 * sizeof(double) * fq::kAdjSlots * (size_t)Ms);
+      } else {  // per column: X_k, P_{L-1}, P_L of every step of a segment
+        lay.off_seg = take(vec * (size_t)n * 3 * (size_t)cks);
+        lay.off_grad = take(2 * sizeof(double) * (size_t)Ms);
+      }
     }
   }
   lay.off_small = take(64 * sizeof(double));
@@ -276,6 +282,8 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
       f64_run = f64_run && f == FQ_TERM_FP64;
     }
   }
+  if (par->grad_pair_sums != 0 && par->grad_pair_sums != 1)
+    return fail(FQ_ERR_ARG, "grad_pair_sums must be 0 or 1");
   if (par->checkpoint_every < 0) return fail(FQ_ERR_ARG, "checkpoint_every must be >= 0");
   if (par->profile != 0 && par->profile != 1) return fail(FQ_ERR_ARG, "profile must be 0 or 1");
   if (par->reorthonormalize != 0 && par->reorthonormalize != 1)
@@ -296,11 +304,6 @@ fq_status validate(const fq_system* sys, const fq_params* par) {
     // 8-plane n x n FP64 states in the workspace (128 n^2 bytes)
     if (sys->n > 40000)
       return fail(FQ_ERR_UNSUPPORTED, "tridiagonal n > 40000 not supported");
-    // the streamed forward build records its checkpoints in the state blocks' type
-    if (par->checkpoint_every > 0 && sys->n > fq::tridiag_resident_max_n() &&
-        par->dtype == FQ_C64)
-      return fail(FQ_ERR_UNSUPPORTED, "tridiagonal gradient with n > %ld needs complex128 state "
-                  "blocks", fq::tridiag_resident_max_n());
   }
   return FQ_OK;
 }
@@ -1301,7 +1304,7 @@ fq_status tridiag_run(fq_ctx* c, const void* x0, long ncols, int k0, int k1, voi
 // (stacked operand [P_l; Pbar_{l+1}]). X_{k-1}, P_{L-1}, P_L of each step come
 // from recomputing its segment forward from the tape.
 
-fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
+fq_status adjoint_step(fq_ctx* c, int k, int slot, bool with_k) {
   const int L = c->L;
   const int np = (int)c->np;
   const long plane = c->np * c->np;
@@ -1322,9 +1325,9 @@ fq_status adjoint_step(fq_ctx* c, int k, int slot, bool any_b) {
   double* lr = c->lam;
   double* li = c->lam + plane;
   double* gk = c->d_grad + (size_t)c->J * k;
-  // contractions with the drive block: [Hmod; K] (K only when some b_k != 0),
-  // or all J matrices for several drive terms
-  const int dot_cols = c->S > 1 ? c->J * np : (any_b ? 2 * np : np);
+  // contractions with the drive block: [Hmod; K] (K skipped when only the
+  // node-pair sums are asked for), or all J matrices for several drive terms
+  const int dot_cols = c->S > 1 ? c->J * np : (with_k ? 2 * np : np);
   auto copy2 = [&](double* dre, double* dim, const double* src) -> fq_status {
     FQ_HIP(c, hipMemcpyAsync(dre, src, pbytes, hipMemcpyDeviceToDevice, s));
     FQ_HIP(c, hipMemcpyAsync(dim, src + plane, pbytes, hipMemcpyDeviceToDevice, s));
@@ -1450,8 +1453,9 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   FQ_HIP(c, fq::launch_pack_planar_t(U_bar, c->n, c->n, c->n, c->lam, c->lam + plane, c->np,
                                      c->np, c->c64, c->stream));
   FQ_HIP(c, zero_async(c->stream, c->d_grad, (size_t)c->J * sizeof(double) * (size_t)M));
-  bool any_b = false;
-  for (int k = 0; k < M; ++k) any_b = any_b || (c->b[k] != 0.0);
+  // dL/db_k is needed for the node derivatives even where b_k = 0; it cancels
+  // in the node-pair sums
+  const bool with_k = !c->pair_sums;
   const int nseg = (M + s - 1) / s;
   c->n_events = 0;  // profile mode: the recompute and reverse products go to the report
   for (int sg = nseg - 1; sg >= 0; --sg) {
@@ -1478,7 +1482,7 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
       } else {
         FQ_TRY(dense_heff(c, k));
       }
-      FQ_TRY(adjoint_step(c, k, k - k0, any_b));
+      FQ_TRY(adjoint_step(c, k, k - k0, with_k));
     }
   }
   FQ_MARK(c, -1);
@@ -1492,117 +1496,133 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
 
 // The reverse sweep in streamed passes (columns longer than one workgroup
 // holds, or on request): per checkpoint segment, last first, the steps are
-// recomputed forward from the segment's checkpoint, keeping X_k and the
-// gauge-frame P_{L-1}, P_L of every step (col-major vectors in the segment
-// buffer); then each step is reversed in passes of at most K terms, Lambda
-// passing from step to step in the plain frame.
+// recomputed by the forward passes from the segment's checkpoint, which leave
+// the gauge-frame P_{L-1}, P_L of every step in the segment buffer; then each
+// step is reversed in passes of at most K terms (P_0 regenerated with the
+// other terms), Lambda passing from step to step as Pbar_0 in the gauge frame
+// of the step it came from.
 fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const int M = c->M, L = c->L, ckpt = c->ckpt;
   const long n = c->n;
-  const size_t vec = 2 * (size_t)n * (size_t)n;  // doubles per complex n x n vector
   const int K = 128;
-  const long win = fq::tridiag_adj_window_rows();
-  fq::TridiagAdjPass p{};
+  const long n16 = (n + 15) / 16 * 16;
+  const size_t plane = (size_t)n16 * (size_t)n;  // doubles per state plane
+  const bool with_k = !c->pair_sums;
+
+  // forward passes of the recompute: the build's job and pass geometry
+  fq::TridiagJob job{};
+  job.n = n;
+  job.ncols = n;
+  job.h0_diag = c->sys.h0_diag;
+  job.h0_off = reinterpret_cast<const double*>(c->sys.h0_off);
+  job.v_diag = c->sys.hmod_diag;
+  job.ab = c->d_ab;
+  job.coef = c->d_coef;
+  job.gauge = c->d_gauge;
+  job.L = L;
+  job.beta = c->beta;
+  job.inv_dE = 1.0 / c->dE;
+  job.phr = c->phr;
+  job.phi = c->phi;
+  job.ld_x0 = n;
+  job.c64 = c->c64 ? 1 : 0;
+  fq::TridiagStream st{};
+  st.G = 1;
+  st.n16 = n16;
+  st.plane = (long)plane;
+  st.K = K;
+  st.B = fq::tridiag_stream_rows(1) - 2L * K;
+  st.nblk = (n + st.B - 1) / st.B;
+  double* fbuf[2] = {c->d_stream, c->d_stream + 8 * plane};
+  double* stepc = c->d_stream + 16 * plane;
+  st.stepc = stepc;
+
+  fq::TridiagAdjStream p{};
   p.n = n;
   p.ncols = n;
+  p.n16 = n16;
+  p.plane = (long)plane;
   p.K = K;
-  p.B = (int)(win - 2L * K);
-  p.nblk = (int)((n + p.B - 1) / p.B);
+  p.B = st.B;
+  p.nblk = st.nblk;
   p.L = L;
+  p.coef = c->d_coef;
+  p.phr = c->phr;
+  p.phi = c->phi;
   p.h0_diag = c->sys.h0_diag;
   p.h0_off = reinterpret_cast<const double*>(c->sys.h0_off);
   p.v_diag = c->sys.hmod_diag;
+  p.gauge = c->d_gauge;
   p.beta = c->beta;
   p.inv_dE = 1.0 / c->dE;
-  p.phr = c->phr;
-  p.phi = c->phi;
-  p.coef = c->d_coef;
-  p.any_b = 0;
-  for (int k = 0; k < M; ++k) p.any_b |= (c->b[k] != 0.0);
-  double* set[2][4];
-  for (int q = 0; q < 2; ++q)
-    for (int j = 0; j < 4; ++j) set[q][j] = c->d_adj + (size_t)(4 * q + j) * vec;
-  double* lam[2] = {c->d_adj + 8 * vec, c->d_adj + 9 * vec};
-  auto seg_x = [&](int s) { return c->seg + (size_t)(3 * s) * vec; };
-  auto seg_plm1 = [&](int s) { return c->seg + (size_t)(3 * s + 1) * vec; };
-  auto seg_pl = [&](int s) { return c->seg + (size_t)(3 * s + 2) * vec; };
-  // tape entry j: X_{j ckpt}, col-major FP64 from the per-column build, row-major
-  // in the state type from the streamed build (entry 0 then not stored: identity)
+  double* rset[2] = {c->d_adj, c->d_adj + 8 * plane};
+  double* lam[2] = {c->d_adj + 16 * plane, c->d_adj + 18 * plane};
+  double* tab = c->d_adj + 20 * plane;
+  auto seg = [&](int j) { return c->seg + (size_t)j * 4 * plane; };
+  // tape entry j: X_{j ckpt}; column-major complex128 from the per-column
+  // build, or (n > tridiag_resident_max_n()) the snapshot store of the streamed
+  // build, row-major in the state type from entry 1 on (entry 0: identity)
   const bool tape_rows = n > fq::tridiag_resident_max_n();
-  auto set_io = [&](int cur) {
-    for (int j = 0; j < 4; ++j) {
-      p.in[j] = set[cur][j];
-      p.out[j] = set[cur ^ 1][j];
-    }
+  auto tape_entry = [&](int j) -> const void* {
+    if (!tape_rows) return c->tape + (size_t)j * 2 * (size_t)n * (size_t)n;
+    if (j == 0) return nullptr;
+    const size_t esz = c->c64 ? 8 : 16;
+    return reinterpret_cast<const char*>(c->tape) + 16 * (size_t)n * (size_t)n +
+           (size_t)(j - 1) * (size_t)n * (size_t)n * esz;
   };
-  FQ_HIP(c, zero_async(c->stream, c->d_grad, 2 * sizeof(double) * (size_t)M));
+
+  FQ_HIP(c, zero_async(c->stream, c->d_grad, 2 * sizeof(double) * fq::kAdjSlots * (size_t)M));
+  FQ_HIP(c, fq::launch_tridiag_lam_pack(U_bar, c->c64, n, n, n16, lam[0], c->stream));
   c->n_events = 0;  // profile mode: the passes' times go to the report
-  const void* lam_src = U_bar;  // Lambda_M: U_bar, row-major in the state type
-  int lam_rows = 1, lam_c64 = c->c64 ? 1 : 0, lam_next = 0;
+  int lam_cur = 0;
   const int nseg = (M + ckpt - 1) / ckpt;
   // FQ_PROGRESS=1: a line on stderr after each segment (long sweeps)
   const char* prog = std::getenv("FQ_PROGRESS");
   const bool progress = prog && prog[0] == '1';
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int k0 = sg * ckpt, k1 = std::min(k0 + ckpt, M);
+    job.x0 = tape_entry(sg);
+    job.x0_colmajor = tape_rows ? 0 : 1;
     int cur = 0;
-    for (int k = k0; k < k1; ++k) {  // forward recompute of the segment
-      p.a = c->a[k];
-      p.b = c->b[k];
-      p.gauge = c->d_gauge + 2 * (size_t)k * (size_t)n;
-      for (int lo = 0; lo < L; lo += K) {
-        p.lo = lo;
-        p.hi = std::min(lo + K, L);
-        set_io(cur);
-        p.x = nullptr;
-        p.x_store = nullptr;
-        p.x_rowmajor = p.x_c64 = 0;
-        if (lo == 0) {
-          if (k == k0) {
-            if (!tape_rows) {
-              p.x = c->tape + (size_t)sg * vec;
-            } else if (sg > 0) {
-              p.x = c->tape + (size_t)sg * vec;
-              p.x_rowmajor = 1;
-              p.x_c64 = c->c64 ? 1 : 0;
-            }
-            p.x_store = seg_x(0);
-          } else {
-            p.x = seg_x(k - k0);
-          }
-        }
-        p.plm1 = seg_plm1(k - k0);
-        p.pl = seg_pl(k - k0);
-        p.xnext = (k + 1 < k1) ? seg_x(k + 1 - k0) : nullptr;
+    for (int k = k0; k < k1; ++k) {  // forward recompute, keeping P_{L-1}, P_L
+      st.s = k;
+      st.last_step = (k + 1 == M);  // the step rows: no gauge of a step M
+      FQ_MARK(c, FQ_K_HEFF);
+      FQ_HIP(c, fq::launch_tridiag_stream_step(job, st, stepc, c->stream));
+      st.last_step = 0;  // X~_{k+1} stays in the pass state (unused after step M - 1)
+      for (int l0 = 0; l0 <= L; l0 += K) {
+        st.l0 = l0;
+        st.l1 = std::min(l0 + K, L + 1);
+        st.first_step = (k == k0 && l0 == 0);
+        st.in = fbuf[cur];
+        st.out = fbuf[cur ^ 1];
+        st.save = st.l1 > L ? seg(k - k0) : nullptr;
         FQ_MARK(c, FQ_K_ADJ_FWD);
-        FQ_HIP(c, fq::launch_tridiag_adj_forward(p, c->stream));
+        FQ_HIP(c, fq::launch_tridiag_stream(job, st, c->stream));
         cur ^= 1;
       }
     }
+    st.save = nullptr;
     for (int k = k1 - 1; k >= k0; --k) {  // reverse
       p.a = c->a[k];
       p.b = c->b[k];
-      p.gauge = c->d_gauge + 2 * (size_t)k * (size_t)n;
-      p.lam = lam_src;
-      p.lam_rowmajor = lam_rows;
-      p.lam_c64 = lam_c64;
-      p.p0 = seg_x(k - k0);
-      p.seg_plm1 = seg_plm1(k - k0);
-      p.seg_pl = seg_pl(k - k0);
-      p.lam_out = lam[lam_next];
-      p.grad = c->d_grad + 2 * (size_t)k;
+      FQ_MARK(c, FQ_K_HEFF);
+      FQ_HIP(c, fq::launch_tridiag_adj_table(p, k, k == M - 1, tab, c->stream));
+      p.lam = lam[lam_cur];
+      p.lam_out = lam[lam_cur ^ 1];
+      p.seg = seg(k - k0);
+      p.grad = c->d_grad + 2 * (size_t)fq::kAdjSlots * (size_t)k;
+      int rc = 0;
       for (int hi = L - 1; hi >= 0; hi -= K) {
         p.hi = hi;
         p.lo = std::max(hi - K + 1, 0);
-        set_io(cur);
+        p.in = rset[rc];
+        p.out = rset[rc ^ 1];
         FQ_MARK(c, FQ_K_ADJ_REV);
-        FQ_HIP(c, fq::launch_tridiag_adj_reverse(p, c->stream));
-        cur ^= 1;
+        FQ_HIP(c, fq::launch_tridiag_adj_stream(p, tab, with_k, c->stream));
+        rc ^= 1;
       }
-      lam_src = lam[lam_next];
-      lam_rows = 0;
-      lam_c64 = 0;
-      lam_next ^= 1;
+      lam_cur ^= 1;
     }
     if (progress) {
       FQ_HIP(c, hipStreamSynchronize(c->stream));
@@ -1612,10 +1632,16 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
     }
   }
   FQ_MARK(c, -1);
-  std::vector<double> g(2 * (size_t)M);
-  FQ_HIP(c, hipMemcpyAsync(g.data(), c->d_grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
-                           c->stream));
+  std::vector<double> slots(2 * (size_t)fq::kAdjSlots * (size_t)M);
+  FQ_HIP(c, hipMemcpyAsync(slots.data(), c->d_grad, slots.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
   FQ_HIP(c, hipStreamSynchronize(c->stream));
+  std::vector<double> g(2 * (size_t)M, 0.0);
+  for (int k = 0; k < M; ++k)
+    for (int j = 0; j < fq::kAdjSlots; ++j) {
+      g[2 * k] += slots[(size_t)(k * fq::kAdjSlots + j) * 2];
+      g[2 * k + 1] += slots[(size_t)(k * fq::kAdjSlots + j) * 2 + 1];
+    }
   grad_to_nodes(c, g, grad_f_nodes);
   return collect_profile(c);
 }
@@ -1638,8 +1664,7 @@ fq_status tridiag_adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   job.L = c->L;
   job.M = M;
   job.ckpt = c->ckpt;
-  job.any_b = 0;
-  for (int k = 0; k < M; ++k) job.any_b |= (c->b[k] != 0.0);
+  job.any_b = c->pair_sums ? 0 : 1;
   job.beta = c->beta;
   job.inv_dE = 1.0 / c->dE;
   job.phr = c->phr;
@@ -1820,6 +1845,7 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     c->small_chain = !(e && e[0] == '0' && e[1] == 0);
   }
   c->scheme = par->scheme;
+  c->pair_sums = par->grad_pair_sums == 1;
   c->S = drive_terms(sys);
   c->J = drive_block(c->S, par->scheme);
   c->f_nodes.assign(par->f_nodes, par->f_nodes + nodes_per_step(par->scheme) * par->M * c->S);

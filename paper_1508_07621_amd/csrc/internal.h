@@ -243,6 +243,7 @@ struct TridiagJob {
   double beta, inv_dE, phr, phi;
   const void* x0;        // device complex128 n x ncols row-major, or nullptr = identity
   long ld_x0;
+  int x0_colmajor;       // streamed passes: x0 is complex128 column-major (col at col * n)
   void* x_out;           // device complex128 n x ncols row-major
   long ld_out;
   double* tape;          // optional (resident kernel): X_{j ckpt} as complex, slot j at
@@ -274,6 +275,8 @@ struct TridiagStream {
   int l0, l1;       // terms of this launch, l1 - l0 <= K, l0 != 1
   int first_step;
   int last_step;
+  double* save;     // nullable: at the step's end, its last two terms P_{L-1}, P_L
+                    // (4 planes [l & 1][part] in the state-plane layout)
   int K;            // ghost rows per side
   int G;            // waves per part: 1024 G rows per workgroup (the launcher takes G = 1)
   long B;           // owned rows per block
@@ -304,44 +307,41 @@ long tridiag_adjoint_max_n();
 hipError_t launch_tridiag_adjoint(const TridiagAdjJob& job, hipStream_t s);
 
 // One launch of the streamed reverse sweep for columns longer than one
-// workgroup holds: a window of tridiag_adj_window_rows() consecutive rows per
-// workgroup, K ghost rows on each side of the B rows it owns, at most K terms
-// of one step. Vectors are complex, column-major (column c at c * n) unless a
-// flag says row-major (i * ncols + c).
-struct TridiagAdjPass {
-  long n, ncols;
-  int nblk, B, K;            // blocks per column, owned rows per block, ghost rows per side
-  int L, lo, hi;             // forward: P_{lo+1} .. P_hi; reverse: terms l = hi .. lo
+// workgroup holds: terms l = hi .. lo of one step on the windows of the forward
+// passes (B owned rows, K ghost rows per side, B + 2K = tridiag_stream_rows(1);
+// both multiples of 16), in the gauge frame of the step. Vectors are planes of
+// ncols x n16 doubles in the interleaved row layout of TridiagStream.
+constexpr int kAdjSlots = 64;  // accumulator slots per step (workgroup b adds to b mod 64)
+struct TridiagAdjStream {
+  long n, ncols, n16, plane;  // plane = n16 * ncols (doubles)
+  int K;
+  long B, nblk;
+  int L, lo, hi;              // hi - lo + 1 <= K, hi <= L - 1
+  const double* coef;         // c_l complex interleaved
+  double phr, phi;            // exp(-i beta h)
+  // table inputs (launch_tridiag_adj_table)
   const double* h0_diag;
-  const double* h0_off;      // complex interleaved (n-1)
+  const double* h0_off;       // complex interleaved (n-1)
   const double* v_diag;
-  double a, b, beta, inv_dE, phr, phi;  // step scalars
-  const double* gauge;       // unit gauge factors w_i of the step (n complex): Ht = D G D^+
-  const double* coef;        // c_l complex interleaved
-  int any_b;                 // reverse: accumulate the K contraction
-  // forward pass
-  const void* x;             // lo == 0: P_0 = X_k; null = identity columns
-  int x_rowmajor, x_c64;
-  double* x_store;           // lo == 0: owned rows of P_0, or null
-  double* plm1;              // hi == L: P_{L-1}
-  double* pl;                // hi == L: P_L
-  double* xnext;             // hi == L: X_{k+1} = phase Y, or null
-  // reverse pass
-  const void* lam;           // Lambda of the step
-  int lam_rowmajor, lam_c64;
-  const double* p0;          // X_k, read at l == 1
-  const double* seg_plm1;    // hi == L - 1: P_{L-1}
-  const double* seg_pl;      // hi == L - 1: P_L
-  double* lam_out;           // lo == 0: Pbar_0
-  double* grad;              // the step's accumulators: Re sum w_l <Pbar_{l+1}, D P_l>, D = Hmod, K
-  // state carried between passes, in the gauge frame of the step (terms of G):
-  // forward (P_{l-1}, P_l, Y), reverse (P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2})
-  const double* in[4];
-  double* out[4];
+  const double* gauge;        // M x n complex: w_k
+  double a, b, beta, inv_dE;  // step scalars
+  // pass state
+  const double* lam;          // 2 planes (re, im): Lambda before the table's factor
+  const double* seg;          // hi == L-1: P_{L-1}, P_L of the step (4 planes [l & 1][part])
+  const double* in;           // hi < L-1: 8 planes [role][part]: P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2}
+  double* out;                // lo > 0: the same for the next launch (terms from lo - 1)
+  double* lam_out;            // lo == 0: Pbar_0 in the step's gauge frame (2 planes)
+  double* grad;               // the step's 2 x kAdjSlots accumulators: (V, K) per slot
 };
-long tridiag_adj_window_rows();
-hipError_t launch_tridiag_adj_forward(const TridiagAdjPass& p, hipStream_t s);
-hipError_t launch_tridiag_adj_reverse(const TridiagAdjPass& p, hipStream_t s);
+// Per-step tables (7 n16 doubles): 2d, 2g, v, Lambda factor (re, im), K~ (re, im);
+// plain_lambda: the step reads U_bar (factor conj(w_k)), else Pbar_0 of step k+1.
+hipError_t launch_tridiag_adj_table(const TridiagAdjStream& p, int k, bool plain_lambda,
+                                    double* tab, hipStream_t s);
+// U_bar (n x ncols row-major, complex64 when c64) into two planes.
+hipError_t launch_tridiag_lam_pack(const void* ubar, bool c64, long n, long ncols, long n16,
+                                   double* out, hipStream_t s);
+hipError_t launch_tridiag_adj_stream(const TridiagAdjStream& p, const double* tab, bool with_k,
+                                     hipStream_t s);
 hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s);
 
 // Unit gauge factors of step s (host FP64): w_0 = 1, w_{i+1} = w_i conj(u_i) with
@@ -376,6 +376,7 @@ struct fq_ctx {
   // [Hmod_s..., and for FQ_MAGNUS4 K_s = -i [H0, Hmod_s]..., K_st = -i [Hmod_s, Hmod_t]
   // (s < t)]; wS (M x J) are the per-(sub)step weights of the B_j when S >= 2.
   int S = 1, J = 2;
+  bool pair_sums = false;             // floquet_grad: node-pair sums only (no K contraction)
   std::vector<double> wS;
   std::vector<double> w6;             // M x 9
   double* comm6 = nullptr;

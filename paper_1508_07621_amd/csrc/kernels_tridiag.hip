@@ -367,7 +367,10 @@ __global__ __launch_bounds__(512) void tridiag_stream_kernel(TridiagJob job, Tri
       if (st.l0 == 0 && st.first_step) {
         double xr, xi;
         if (job.x0) {
-          load_state(job.x0, i * job.ld_x0 + col, job.c64, xr, xi);
+          if (job.x0_colmajor)  // complex128, column col at col * n
+            load_state(job.x0, col * n + i, 0, xr, xi);
+          else
+            load_state(job.x0, i * job.ld_x0 + col, job.c64, xr, xi);
         } else {
           xr = (i == col) ? 1.0 : 0.0;
           xi = 0.0;
@@ -507,8 +510,19 @@ __global__ __launch_bounds__(512) void tridiag_stream_kernel(TridiagJob job, Tri
     return;
   }
 
-  // step end: both halves of Y meet; X~_{s+1} = phase w_s conj(w_{s+1}) Y, or
-  // X = phase w_s Y after the last step (to x_out, row-major).
+  // step end: the last two terms P_{L-1}, P_L on request (planes [l & 1][part]);
+  // both halves of Y meet; X~_{s+1} = phase w_s conj(w_{s+1}) Y, or X = phase
+  // w_s Y after the last step (to x_out, row-major).
+  if (st.save) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      if (i >= a0 && i < own_end) {
+        st.save[part * st.plane + cn + at(r)] = pe[r];
+        st.save[(2 + part) * st.plane + cn + at(r)] = po[r];
+      }
+    }
+  }
   const int np = G * 64;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -871,387 +885,358 @@ hipError_t launch_adj_r(const TridiagAdjJob& job, hipStream_t s) {
 
 // ---- streamed reverse sweep ------------------------------------------------------------------
 //
-// For columns longer than one workgroup holds, the recurrences of
-// tridiag_adjoint_kernel run one step at a time and at most K terms per
-// launch. A workgroup holds a window of W*64*R consecutive rows of one column:
-// the B rows it owns and K ghost rows on each side. Every term reads one
-// neighbour row on each side, so after at most K terms the owned rows are still
-// exact; they are written back and the next launch continues from them. Rows
-// outside [0, n) are zero, as are their couplings, which is exact at the ends of
-// the chain. Two kinds of pass:
-//   forward (segment recompute): P_{lo+1} .. P_hi and the running sum Y of one
-//     step, from P_0 = X_k when lo == 0; at hi == L it stores P_{L-1}, P_L and
-//     X_{k+1} = phase Y for the reverse passes;
-//   reverse: terms l = hi .. lo of the adjoint recurrence with P regenerated
-//     downwards, the contractions over the owned rows added to the step's two
-//     accumulators; at lo == 0 it stores Pbar_0, the Lambda of the step before.
-// Both work in the gauge frame of the step, Ht = D G D^+ with D = diag(w) and
-// G real symmetric tridiagonal (diagonal d_i, couplings g_i = |Ht[i][i+1]|), so
-// every term applies real couplings: the terms are those of G on D^+ X, the
-// step's output is phase D Y, Lambda enters as D^+ Lambda and leaves as
-// D Pbar_0. Hmod is diagonal and unchanged by D; K becomes D^+ K D, whose
-// couplings conj(w_i) k_i w_{i+1} stay complex.
+// For columns longer than one workgroup holds, the reverse recurrences run one
+// step at a time, at most K terms per launch, on the windows of the forward
+// passes: B owned rows and K ghost rows on each side, 16 rows per lane, one
+// wave for the real part and one for the imaginary part of every vector, the
+// state between launches in planes of the interleaved row layout. The segment
+// recompute is the forward pass itself (tridiag_stream_kernel), which leaves
+// the last two terms P_{L-1}, P_L of every step in the segment buffer.
+//
+// Everything runs in the gauge frame of the step, Ht = D G D^+ with real G: a
+// term applies G to the real and imaginary parts separately, so each wave only
+// needs neighbour rows of its own part (lane shifts; the window edges read
+// zero, which the ghost rows absorb). Per term l, going down from L - 1:
+//   Pbar_l  = (2 - delta_l0) G Pbar_{l+1} - Pbar_{l+2} + d_l Lambda~,
+//   P_{l-1} = 2 G P_l - P_{l+1}   (l >= 1; at l = 1 this regenerates P_0),
+//   S_V    += Re Pbar_{l+1} P_l per row and part (Hmod is diagonal),
+//   S_K    += Re conj(Pbar_{l+1}) (K~ P_l) per row and part,
+// with d_l = conj(phase c_l), Lambda~ = D^+ Lambda and K~ = D^+ K D (complex
+// couplings conj(w_i) k_i w_{i+1}). The source mixes the parts of Lambda~, so
+// each wave holds both; K~ mixes the parts of P_l, so with the K contraction
+// the two waves trade P_l through LDS once per term. The sums over the owned
+// rows, (2 - delta_l0)-weighted, go to the step's two accumulators. At l = 0
+// Pbar_0 leaves in the gauge frame of step k; the step before applies the
+// factor conj(w_{k-1}) w_k as it reads it (the first reversed step reads
+// U_bar with conj(w_{M-1})).
 
-// Per-window operator rows of one step and the neighbour exchange of the window.
-template <int R, int W>
-struct AdjWindow {
-  double dd[R], gg[R], kr[R], ki[R], vv[R];  // G rows, D^+ K D couplings, Hmod
-  double gm, kmr, kmi;                       // couplings from row base - 1
-  double (*halo)[4][2][W];
-  int parity, lane, wid;
-
-  __device__ __forceinline__ void set(const TridiagAdjPass& p, long base) {
-    const double2* h0o = reinterpret_cast<const double2*>(p.h0_off);
-    const double2* w = reinterpret_cast<const double2*>(p.gauge);
-    // coupling g_i = |h_i| sqrt(1 + q^2) / dE and, with b != 0, conj(w_i) k_i w_{i+1}
-    // with k_i = -i h_i (v_{i+1} - v_i)
-    auto coupling = [&](long i, double& g, double& tr, double& ti) {
-      const double2 h = h0o[i];
-      const double dv = p.v_diag[i + 1] - p.v_diag[i], q = p.b * dv;
-      g = sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * p.inv_dE;
-      tr = ti = 0.0;
-      if (p.any_b) {
-        const double k_r = h.y * dv, k_i = -h.x * dv;
-        const double2 w0 = w[i], w1 = w[i + 1];
-        const double ur = k_r * w1.x - k_i * w1.y, ui = k_r * w1.y + k_i * w1.x;  // k w_{i+1}
-        tr = w0.x * ur + w0.y * ui;                                               // conj(w_i) (.)
-        ti = w0.x * ui - w0.y * ur;
-      }
-    };
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const long i = base + r;
-      dd[r] = gg[r] = kr[r] = ki[r] = vv[r] = 0.0;
-      if (i >= 0 && i < p.n) {
-        vv[r] = p.v_diag[i];
-        dd[r] = (p.h0_diag[i] + p.a * vv[r] - p.beta) * p.inv_dE;
-        if (i + 1 < p.n) coupling(i, gg[r], kr[r], ki[r]);
-      }
+// Rows of the reverse pass tables of step k (interleaved layout, rows n .. n16-1
+// zero): 2 d_i, 2 g_i, v_i, the factor that takes the Lambda planes into the
+// gauge frame (conj(w_k) w_{k+1}, or conj(w_k) when Lambda is U_bar), and the
+// K~ couplings conj(w_i) k_i w_{i+1} with k_i = -i h_i (v_{i+1} - v_i).
+__global__ __launch_bounds__(256) void tridiag_adj_table_kernel(TridiagAdjStream p, int k,
+                                                                int plain_lambda, double* tab) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  const long n = p.n, n16 = p.n16;
+  if (i >= n16) return;
+  const long at = (i & 15) * (n16 >> 4) + (i >> 4);
+  double d2 = 0, g2 = 0, vi = 0, fr = 0, fi = 0, kr = 0, ki = 0;
+  if (i < n) {
+    const double2* w = reinterpret_cast<const double2*>(p.gauge) + (long)k * n;
+    vi = p.v_diag[i];
+    d2 = 2.0 * (p.h0_diag[i] + p.a * vi - p.beta) * p.inv_dE;
+    const double2 wk = w[i];
+    double ur = 1.0, ui = 0.0;  // w_{k+1}
+    if (!plain_lambda) {
+      const double2 wn = w[n + i];
+      ur = wn.x;
+      ui = wn.y;
     }
-    gm = kmr = kmi = 0.0;
-    if (base >= 1 && base < p.n) coupling(base - 1, gm, kmr, kmi);
-  }
-
-  // Neighbour rows of two complex vectors: base - 1 (nb[0..3]) and base + R
-  // (nb[4..7]); zero beyond the window.
-  __device__ __forceinline__ void exchange(const double* xr, const double* xi, const double* yr,
-                                           const double* yi,
-                           double nb[8]) {
-    nb[0] = from_prev_lane(xr[R - 1]);
-    nb[1] = from_prev_lane(xi[R - 1]);
-    nb[2] = from_prev_lane(yr[R - 1]);
-    nb[3] = from_prev_lane(yi[R - 1]);
-    nb[4] = from_next_lane(xr[0]);
-    nb[5] = from_next_lane(xi[0]);
-    nb[6] = from_next_lane(yr[0]);
-    nb[7] = from_next_lane(yi[0]);
-    if (lane == 0) {
-      halo[parity][0][0][wid] = xr[0];
-      halo[parity][1][0][wid] = xi[0];
-      halo[parity][2][0][wid] = yr[0];
-      halo[parity][3][0][wid] = yi[0];
-    }
-    if (lane == 63) {
-      halo[parity][0][1][wid] = xr[R - 1];
-      halo[parity][1][1][wid] = xi[R - 1];
-      halo[parity][2][1][wid] = yr[R - 1];
-      halo[parity][3][1][wid] = yi[R - 1];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double hu = (wid > 0) ? halo[parity][q][1][wid - 1] : 0.0;
-      const double hd = (wid + 1 < W) ? halo[parity][q][0][wid + 1] : 0.0;
-      nb[q] = (lane == 0) ? hu : nb[q];
-      nb[4 + q] = (lane == 63) ? hd : nb[4 + q];
-    }
-    parity ^= 1;
-  }
-
-  // out = f G x - out (+ (cr + i ci) lam with SRC)
-  template <bool SRC>
-  __device__ __forceinline__ void apply(const double* xr, const double* xi, double ur, double ui,
-                                        double dr_, double di_, double f, double* or_, double* oi,
-                                        double cr, double ci, const double* lr,
-                                        const double* li) const {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double lor = (r == 0) ? ur : xr[r - 1], loi = (r == 0) ? ui : xi[r - 1];
-      const double hir = (r == R - 1) ? dr_ : xr[r + 1], hii = (r == R - 1) ? di_ : xi[r + 1];
-      const double gl = (r == 0) ? gm : gg[r - 1];
-      // g_{i-1} x_{i-1} + d_i x_i + g_i x_{i+1}
-      const double hr = fma(dd[r], xr[r], fma(gl, lor, gg[r] * hir));
-      const double hi = fma(dd[r], xi[r], fma(gl, loi, gg[r] * hii));
-      if constexpr (SRC) {
-        or_[r] = f * hr - or_[r] + (cr * lr[r] - ci * li[r]);
-        oi[r] = f * hi - oi[r] + (cr * li[r] + ci * lr[r]);
-      } else {
-        or_[r] = f * hr - or_[r];
-        oi[r] = f * hi - oi[r];
-      }
+    const double tr = wk.x * ur + wk.y * ui, ti = wk.x * ui - wk.y * ur;  // conj(w_k) u
+    fr = p.phr * tr + p.phi * ti;  // conj(phase) conj(w_k) u
+    fi = p.phr * ti - p.phi * tr;
+    if (i + 1 < n) {
+      const double2 h = reinterpret_cast<const double2*>(p.h0_off)[i];
+      const double dv = p.v_diag[i + 1] - vi, q = p.b * dv;
+      g2 = 2.0 * sqrt((h.x * h.x + h.y * h.y) * (1.0 + q * q)) * p.inv_dE;
+      const double k_r = h.y * dv, k_i = -h.x * dv;  // -i h dv
+      const double2 w1 = w[i + 1];
+      const double tr = k_r * w1.x - k_i * w1.y, ti = k_r * w1.y + k_i * w1.x;
+      kr = wk.x * tr + wk.y * ti;
+      ki = wk.x * ti - wk.y * tr;
     }
   }
+  tab[at] = d2;
+  tab[n16 + at] = g2;
+  tab[2 * n16 + at] = vi;
+  tab[3 * n16 + at] = fr;
+  tab[4 * n16 + at] = fi;
+  tab[5 * n16 + at] = kr;
+  tab[6 * n16 + at] = ki;
+}
+
+// U_bar (n x ncols row-major, the state type) into two planes (re, im) of the
+// interleaved layout, rows n .. n16-1 zero.
+__global__ __launch_bounds__(256) void tridiag_lam_pack_kernel(const void* ubar, int c64, long n,
+                                                               long ncols, long n16,
+                                                               double* out) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n16 * ncols) return;
+  const long i = t / ncols, col = t % ncols;
+  double re = 0.0, im = 0.0;
+  if (i < n) load_state(ubar, i * ncols + col, c64, re, im);
+  const long at = col * n16 + (i & 15) * (n16 >> 4) + (i >> 4);
+  out[at] = re;
+  out[n16 * ncols + at] = im;
+}
+
+// Lane shifts for the reverse passes: the lane without a source reads +0.0
+// (bound_ctrl), with no separate zeroing of the destination.
+__device__ __forceinline__ double prev_lane_or_zero(double v) {  // lane l <- lane l-1
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double next_lane_or_zero(double v) {  // lane l <- lane l+1
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+template <int V>
+struct Parity {
+  static constexpr int value = V;
 };
 
-// v times conj(w) (to the gauge frame) or w (back to the plain frame).
-__device__ __forceinline__ void gauge_in(const double2 w, double& re, double& im) {
-  const double r = w.x * re + w.y * im, i = w.x * im - w.y * re;
-  re = r;
-  im = i;
-}
-__device__ __forceinline__ void gauge_out(const double2 w, double& re, double& im) {
-  const double r = w.x * re - w.y * im, i = w.x * im + w.y * re;
-  re = r;
-  im = i;
-}
+template <bool KC, bool HI_ODD>
+__global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStream p,
+                                                                 const double* __restrict__ tab,
+                                                                 const double2* __restrict__ coef) {
+  constexpr int R = 16, XR = KC ? R : 1, XL = KC ? 64 : 1;
+  // Lambda' = conj(phase) Lambda~ of the window (both waves read both parts),
+  // the pass's Chebyshev coefficients, the K~ couplings (re, im), P_l of both
+  // parts two terms deep, the waves' sums
+  __shared__ double lam_s[2][R][64];
+  __shared__ double2 c_s[128];
+  __shared__ double k_s[2][XR][XL];
+  __shared__ double xs[2][2][XR][XL];
+  __shared__ double red[2][2];
 
-__device__ __forceinline__ void load_vec(const double* v, long idx, double& re, double& im) {
-  const double2 x = reinterpret_cast<const double2*>(v)[idx];
-  re = x.x;
-  im = x.y;
-}
-__device__ __forceinline__ void store_vec(double* v, long idx, double re, double im) {
-  reinterpret_cast<double2*>(v)[idx] = make_double2(re, im);
-}
+  const int part = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long col = blockIdx.x / p.nblk, blk = blockIdx.x % p.nblk;
+  const long n = p.n, n16 = p.n16, nq = n16 >> 4, plane = p.plane;
+  const long a0 = blk * p.B;
+  const long q = (a0 - p.K) / 16 + lane;  // row group of this lane (may be < 0)
+  const long base = q * 16;
+  // row base + r of this column sits at r nq + q of a plane: lane pointers
+  // plus uniform offsets
+  const long off = col * n16 + q;
+  const double* tq = tab + q;
+  auto in_col = [&](int r) { return base + r >= 0 && base + r < n; };
+  // K and B are multiples of 16: a lane's 16 rows are all owned or all ghosts
+  const bool own_lane = base >= a0 && base < a0 + p.B;
 
-template <int R, int W>
-__global__ __launch_bounds__(W * 64) void tridiag_adj_forward_kernel(TridiagAdjPass p) {
-  __shared__ double halo[2][4][2][W];
-  AdjWindow<R, W> win;
-  win.halo = halo;
-  win.parity = 0;
-  win.lane = threadIdx.x & 63;
-  win.wid = threadIdx.x >> 6;
-  const long col = blockIdx.x / p.nblk, r0 = (long)(blockIdx.x % p.nblk) * p.B;
-  const long n = p.n;
-  const long base = r0 - p.K + ((long)win.wid * 64 + win.lane) * R;
-  const long own_end = (r0 + p.B < n) ? r0 + p.B : n;
-  const double2* coef = reinterpret_cast<const double2*>(p.coef);
-  const double2* gw = reinterpret_cast<const double2*>(p.gauge);
-  win.set(p, base);
+  double d2[R], g2[R];             // rows of 2 G
+  double x[R], z[R], pb[R], o[R];  // P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2}
+  double sv[R];                    // Re Pbar_{l+1} P_l summed over the terms
+  double gk = 0.0;                 // Re <Pbar_{l+1}, K~ P_l> over the lane's rows, summed
+  double gm2 = 0.0;                // coupling from row base - 1
 
-  double ar[R], ai[R], br[R], bi[R], yr[R], yi[R];  // P in a and b, the running sum Y
-  int l;
-  if (p.lo == 0) {
+  // Lambda' = f Lambda with f = conj(phase) conj(w_k) w_{k+1} from the table;
+  // this wave stores its own part
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = 0.0;
+    if (in_col(r)) {
+      const double ar = p.lam[off + r * nq], ai = p.lam[plane + off + r * nq];
+      const double fr = tq[3 * n16 + r * nq], fi = tq[4 * n16 + r * nq];
+      v = part == 0 ? fr * ar - fi * ai : fr * ai + fi * ar;
+    }
+    lam_s[part][r][lane] = v;
+    if constexpr (KC) k_s[part][r][lane] = in_col(r) ? tq[(5 + part) * n16 + r * nq] : 0.0;
+  }
+  for (int t = threadIdx.x; t <= p.hi - p.lo; t += 128) c_s[t] = coef[p.hi - t];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool ok = in_col(r);
+    d2[r] = ok ? tq[r * nq] : 0.0;
+    g2[r] = ok ? tq[n16 + r * nq] : 0.0;
+    sv[r] = 0.0;
+  }
+  if (base >= 1 && base < n) gm2 = tq[n16 + (long)(R - 1) * nq - 1];  // row base - 1
+  double kmr = 0.0, kmi = 0.0;  // K~ coupling from row base - 1
+  if constexpr (KC) {
+    if (base >= 1 && base < n) {
+      kmr = tq[5 * n16 + (long)(R - 1) * nq - 1];
+      kmi = tq[6 * n16 + (long)(R - 1) * nq - 1];
+    }
+  }
+  const double sgn = part == 0 ? 1.0 : -1.0;
+  __syncthreads();
+
+  // d_l Lambda~ = conj(c_l) Lambda'. c_l is real for even l and imaginary for
+  // odd l: a part takes its own part of Lambda' with Re c_l (even l), or the
+  // other part with +/- Im c_l (odd l)
+  const double(*lam_own)[64] = lam_s[part];
+  const double(*lam_oth)[64] = lam_s[1 - part];
+
+  const bool first = p.hi == p.L - 1;
+  if (first) {  // P_{L-1}, P_L from the recompute; Pbar_L = d_L Lambda~, Pbar_{L+1} = 0
+    const double2 cL = c_s[0];
+    const bool odd = p.L & 1;
+    const double cs = odd ? sgn * cL.y : cL.x;
+    const double(*lm)[64] = odd ? lam_oth : lam_own;
+    const double* sx = p.seg + ((((p.L - 1) & 1) * 2 + part) * plane) + off;
+    const double* sz = p.seg + (((p.L & 1) * 2 + part) * plane) + off;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const long i = base + r;
-      ar[r] = ai[r] = 0.0;
-      if (i >= 0 && i < n) {
-        if (p.x == nullptr)
-          ar[r] = (i == col) ? 1.0 : 0.0;
-        else
-          load_state(p.x, p.x_rowmajor ? i * p.ncols + col : col * n + i, p.x_c64, ar[r], ai[r]);
-        if (p.x_store && i >= r0 && i < own_end) store_vec(p.x_store, col * n + i, ar[r], ai[r]);
-        gauge_in(gw[i], ar[r], ai[r]);  // P_0 = D^+ X
-      }
-      br[r] = bi[r] = 0.0;
+      const bool ok = in_col(r);
+      x[r] = ok ? sx[r * nq] : 0.0;
+      z[r] = ok ? sz[r * nq] : 0.0;
+      pb[r] = cs * lm[r][lane];
+      o[r] = 0.0;
     }
-    double nb[8];
-    win.exchange(ar, ai, ar, ai, nb);
-    win.template apply<false>(ar, ai, nb[0], nb[1], nb[4], nb[5], 1.0, br, bi, 0.0, 0.0, ar, ai);
-    const double2 c0 = coef[0], c1 = coef[1];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      yr[r] = c0.x * ar[r] - c0.y * ai[r] + c1.x * br[r] - c1.y * bi[r];
-      yi[r] = c0.x * ai[r] + c0.y * ar[r] + c1.x * bi[r] + c1.y * br[r];
-    }
-    l = 1;
   } else {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const long i = base + r;
-      ar[r] = ai[r] = br[r] = bi[r] = yr[r] = yi[r] = 0.0;
-      if (i >= 0 && i < n) {
-        load_vec(p.in[0], col * n + i, ar[r], ai[r]);
-        load_vec(p.in[1], col * n + i, br[r], bi[r]);
-        load_vec(p.in[2], col * n + i, yr[r], yi[r]);
-      }
+      const bool ok = in_col(r);
+      const double* v = p.in + part * plane + off + r * nq;
+      x[r] = ok ? v[0] : 0.0;
+      z[r] = ok ? v[2 * plane] : 0.0;
+      pb[r] = ok ? v[4 * plane] : 0.0;
+      o[r] = ok ? v[6 * plane] : 0.0;
     }
-    l = p.lo;
   }
-  // P_l in b and P_{l-1} in a while `latest_b`, else the other way round
-  bool latest_b = true;
-  for (; l < p.hi; ++l) {
-    double nb[8];
-    const double2 c = coef[l + 1];
-    if (latest_b) {
-      win.exchange(br, bi, br, bi, nb);
-      win.template apply<false>(br, bi, nb[0], nb[1], nb[4], nb[5], 2.0, ar, ai, 0.0, 0.0, br, bi);
+
+  int parity = 0;
+  // One term l >= 1 of parity P::value: Pbar_l = 2 G PB - O + d_l Lambda~ into
+  // O, P_{l-1} = 2 G X - Z into Z, the sums. L0: the term l = 0 (G instead of
+  // 2 G, no new P, the sums weighted by one half; every sum is doubled at the
+  // end).
+  auto term = [&](auto par, const double* X, double* Z, const double* PB, double* O, int l,
+                  bool L0) {
+    constexpr bool ODD = decltype(par)::value;
+    // Lambda' and c_l are read from LDS in every term, not kept in registers
+    asm volatile("" ::: "memory");
+    const double2 cl = c_s[p.hi - l];
+    const double cs = ODD ? sgn * cl.y : cl.x;
+    const double(*lm)[64] = ODD ? lam_oth : lam_own;
+    const double xu = prev_lane_or_zero(X[R - 1]), xd = next_lane_or_zero(X[0]);
+    const double pu = prev_lane_or_zero(PB[R - 1]), pd = next_lane_or_zero(PB[0]);
+    const double hw = L0 ? 0.5 : 1.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) sv[r] = fma(hw * PB[r], X[r], sv[r]);
+    if constexpr (KC) {
+      // (K~ P)_r = conj(k_{r-1}) P_{r-1} + k_r P_{r+1}; this part of it takes
+      // this part's P with Re k and the other part's with -/+ Im k
+#pragma unroll
+      for (int r = 0; r < R; ++r) xs[parity][part][r][lane] = X[r];
+      __syncthreads();
+      const auto ox = xs[parity][1 - part];
+      double tk = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        yr[r] += c.x * ar[r] - c.y * ai[r];
-        yi[r] += c.x * ai[r] + c.y * ar[r];
+        const double om = r > 0 ? ox[r - 1][lane] : (lane > 0 ? ox[R - 1][lane - 1] : 0.0);
+        const double op = r < R - 1 ? ox[r + 1][lane] : (lane < 63 ? ox[0][lane + 1] : 0.0);
+        const double xm = r > 0 ? X[r - 1] : xu, xp = r < R - 1 ? X[r + 1] : xd;
+        const double cmr = r > 0 ? k_s[0][r - 1][lane] : kmr;
+        const double cmi = r > 0 ? k_s[1][r - 1][lane] : kmi;
+        const double khr = k_s[0][r][lane], khi = k_s[1][r][lane];
+        double t = cmr * xm;
+        t = fma(khr, xp, t);
+        t = fma(sgn * cmi, om, t);
+        t = fma(-sgn * khi, op, t);
+        tk = fma(PB[r], t, tk);
       }
-    } else {
-      win.exchange(ar, ai, ar, ai, nb);
-      win.template apply<false>(ar, ai, nb[0], nb[1], nb[4], nb[5], 2.0, br, bi, 0.0, 0.0, ar, ai);
+      gk = fma(hw, tk, gk);
+      parity ^= 1;
+    }
+    if (!L0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        yr[r] += c.x * br[r] - c.y * bi[r];
-        yi[r] += c.x * bi[r] + c.y * br[r];
+        const double lo = r > 0 ? X[r - 1] : xu, hi = r < R - 1 ? X[r + 1] : xd;
+        const double gl = r > 0 ? g2[r - 1] : gm2;
+        double t = fma(d2[r], X[r], -Z[r]);
+        t = fma(gl, lo, t);
+        Z[r] = fma(g2[r], hi, t);
       }
-    }
-    latest_b = !latest_b;
-  }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const long i = base + r;
-    if (i < r0 || i >= own_end) continue;
-    const long at = col * n + i;
-    const double pr = latest_b ? br[r] : ar[r], pi = latest_b ? bi[r] : ai[r];     // P_hi
-    const double qr = latest_b ? ar[r] : br[r], qi = latest_b ? ai[r] : bi[r];     // P_{hi-1}
-    if (p.hi == p.L) {
-      store_vec(p.plm1, at, qr, qi);
-      store_vec(p.pl, at, pr, pi);
-      if (p.xnext) {  // X_{k+1} = phase D Y
-        double xr = p.phr * yr[r] - p.phi * yi[r], xi = p.phr * yi[r] + p.phi * yr[r];
-        gauge_out(gw[i], xr, xi);
-        store_vec(p.xnext, at, xr, xi);
+      for (int r = 0; r < R; ++r) {
+        const double lo = r > 0 ? PB[r - 1] : pu, hi = r < R - 1 ? PB[r + 1] : pd;
+        const double gl = r > 0 ? g2[r - 1] : gm2;
+        double t = fma(d2[r], PB[r], -O[r]);
+        t = fma(gl, lo, t);
+        t = fma(g2[r], hi, t);
+        O[r] = fma(cs, lm[r][lane], t);
       }
     } else {
-      store_vec(p.out[0], at, qr, qi);
-      store_vec(p.out[1], at, pr, pi);
-      store_vec(p.out[2], at, yr[r], yi[r]);
-    }
-  }
-}
-
-template <int R, int W>
-__global__ __launch_bounds__(W * 64) void tridiag_adj_reverse_kernel(TridiagAdjPass p) {
-  __shared__ double halo[2][4][2][W];
-  AdjWindow<R, W> win;
-  win.halo = halo;
-  win.parity = 0;
-  win.lane = threadIdx.x & 63;
-  win.wid = threadIdx.x >> 6;
-  const long col = blockIdx.x / p.nblk, r0 = (long)(blockIdx.x % p.nblk) * p.B;
-  const long n = p.n;
-  const long base = r0 - p.K + ((long)win.wid * 64 + win.lane) * R;
-  const long own_end = (r0 + p.B < n) ? r0 + p.B : n;
-  const double2* coef = reinterpret_cast<const double2*>(p.coef);
-  const double2* gw = reinterpret_cast<const double2*>(p.gauge);
-  win.set(p, base);
-
-  double lr[R], li[R];                // Lambda
-  double ar[R], ai[R], br[R], bi[R];  // two P terms
-  double qr[R], qi[R], sr[R], si[R];  // two Pbar terms
-  double own[R];                      // 1 on the rows this workgroup owns
-  const bool first = (p.hi == p.L - 1);
-  const double2 cL = coef[p.L];
-  const double dLr = p.phr * cL.x - p.phi * cL.y, dLi = -(p.phr * cL.y + p.phi * cL.x);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const long i = base + r;
-    own[r] = (i >= r0 && i < own_end) ? 1.0 : 0.0;
-    lr[r] = li[r] = ar[r] = ai[r] = br[r] = bi[r] = qr[r] = qi[r] = sr[r] = si[r] = 0.0;
-    if (i >= 0 && i < n) {
-      load_state(p.lam, p.lam_rowmajor ? i * p.ncols + col : col * n + i, p.lam_c64, lr[r], li[r]);
-      gauge_in(gw[i], lr[r], li[r]);  // D^+ Lambda
-      if (first) {  // P_{L-1}, P_L; Pbar_L = d_L Lambda, Pbar_{L+1} = 0
-        load_vec(p.seg_plm1, col * n + i, ar[r], ai[r]);
-        load_vec(p.seg_pl, col * n + i, br[r], bi[r]);
-        qr[r] = dLr * lr[r] - dLi * li[r];
-        qi[r] = dLr * li[r] + dLi * lr[r];
-      } else {
-        load_vec(p.in[0], col * n + i, ar[r], ai[r]);
-        load_vec(p.in[1], col * n + i, br[r], bi[r]);
-        load_vec(p.in[2], col * n + i, qr[r], qi[r]);
-        load_vec(p.in[3], col * n + i, sr[r], si[r]);
+      for (int r = 0; r < R; ++r) {
+        const double lo = r > 0 ? PB[r - 1] : pu, hi = r < R - 1 ? PB[r + 1] : pd;
+        const double gl = r > 0 ? g2[r - 1] : gm2;
+        double h = d2[r] * PB[r];
+        h = fma(gl, lo, h);
+        h = fma(g2[r], hi, h);
+        const double t = fma(0.5, h, -O[r]);
+        O[r] = fma(cs, lm[r][lane], t);
       }
     }
-  }
-
-  double gv = 0.0, gk = 0.0;
-  // One downward term l with P_l in x, P_{l+1} in z (-> P_{l-1}), Pbar_{l+1} in
-  // pb and Pbar_{l+2} in o (-> Pbar_l). AB: x = a, z = b, pb = q, o = s; else
-  // the pairs swapped. Written out per assignment (no array pointers), so that
-  // every array stays in registers.
-#define FQ_DOWN(XR, XI, ZR, ZI, PR, PI, OR, OI, l_)                                           \
-  {                                                                                          \
-    const int lt = (l_);                                                                      \
-    double nb[8];                                                                            \
-    win.exchange(XR, XI, PR, PI, nb);                                                        \
-    const double w = (lt >= 1) ? 2.0 : 1.0;                                                   \
-    _Pragma("unroll") for (int r = 0; r < R; ++r) {                                          \
-      gv += own[r] * w * win.vv[r] * (PR[r] * XR[r] + PI[r] * XI[r]);                        \
-      if (p.any_b) {                                                                         \
-        const double lor = (r == 0) ? nb[0] : XR[r - 1], loi = (r == 0) ? nb[1] : XI[r - 1]; \
-        const double hir = (r == R - 1) ? nb[4] : XR[r + 1],                                 \
-                     hii = (r == R - 1) ? nb[5] : XI[r + 1];                                 \
-        const double ckr = (r == 0) ? win.kmr : win.kr[r - 1],                               \
-                     cki = (r == 0) ? win.kmi : win.ki[r - 1];                               \
-        const double tr = ckr * lor + cki * loi + win.kr[r] * hir - win.ki[r] * hii;         \
-        const double ti = ckr * loi - cki * lor + win.kr[r] * hii + win.ki[r] * hir;         \
-        gk += own[r] * w * (PR[r] * tr + PI[r] * ti);                                        \
-      }                                                                                      \
-    }                                                                                        \
-    const double2 cl = coef[lt];                                                              \
-    const double dr = p.phr * cl.x - p.phi * cl.y, di = -(p.phr * cl.y + p.phi * cl.x);      \
-    win.template apply<true>(PR, PI, nb[2], nb[3], nb[6], nb[7], w, OR, OI, dr, di, lr, li); \
-    if (lt == 1) {                                                                            \
-      _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
-        const long i = base + r;                                                             \
-        ZR[r] = ZI[r] = 0.0;                                                                 \
-        if (i >= 0 && i < n) {                                                               \
-          load_vec(p.p0, col * n + i, ZR[r], ZI[r]);                                         \
-          gauge_in(gw[i], ZR[r], ZI[r]);                                                     \
-        }                                                                                    \
-      }                                                                                      \
-    } else if (lt >= 2) {                                                                     \
-      win.template apply<false>(XR, XI, nb[0], nb[1], nb[4], nb[5], 2.0, ZR, ZI, 0.0, 0.0,   \
-                                lr, li);                                                     \
-    }                                                                                        \
-  }
-  // Pbar_l = w Ht Pbar_{l+1} - Pbar_{l+2} + conj(phase c_l) Lambda, w = 2 (l >= 1) or 1;
-  // P_{l-1} = 2 Ht P_l - P_{l+1}, P_0 read back; the contractions with Hmod
-  // (diagonal) and K (K_{i,i+1} = k_i, (K x)_i = conj(k_{i-1}) x_{i-1} + k_i x_{i+1})
-  int l = p.hi;
-  for (; l - 1 >= p.lo; l -= 2) {
-    FQ_DOWN(ar, ai, br, bi, qr, qi, sr, si, l)      // P_l in a, P_{l-1} -> b; Pbar_l -> s
-    FQ_DOWN(br, bi, ar, ai, sr, si, qr, qi, l - 1)  // P_{l-1} in b; Pbar_{l-1} -> q
-  }
-  const bool odd = (l == p.lo);
-  if (odd) FQ_DOWN(ar, ai, br, bi, qr, qi, sr, si, l)
-#undef FQ_DOWN
-  // even: P_{lo-1} a, P_lo b, Pbar_lo q, Pbar_{lo+1} s; odd: the pairs swapped.
-  // (Separate branches rather than selects between arrays, which would take
-  // their addresses and move them out of registers.)
-#define FQ_STORE(P1R, P1I, P2R, P2I, Q1R, Q1I, Q2R, Q2I)                        \
-  _Pragma("unroll") for (int r = 0; r < R; ++r) {                               \
-    const long i = base + r;                                                    \
-    if (i < r0 || i >= own_end) continue;                                       \
-    const long at = col * n + i;                                                \
-    if (p.lo == 0) {                                                            \
-      double xr = Q1R[r], xi = Q1I[r];                                          \
-      gauge_out(gw[i], xr, xi);                                                 \
-      store_vec(p.lam_out, at, xr, xi);                                         \
-    } else {                                                                    \
-      store_vec(p.out[0], at, P1R[r], P1I[r]);                                  \
-      store_vec(p.out[1], at, P2R[r], P2I[r]);                                  \
-      store_vec(p.out[2], at, Q1R[r], Q1I[r]);                                  \
-      store_vec(p.out[3], at, Q2R[r], Q2I[r]);                                  \
-    }                                                                           \
-  }
-  if (odd) {
-    FQ_STORE(br, bi, ar, ai, sr, si, qr, qi)
+  };
+  // After the terms down to lo (>= 1): P_{lo-1}, P_lo, Pbar_lo, Pbar_{lo+1} in
+  // (X, Z, PB, O); with lo = 0 the l = 0 term, then Pbar_0 out.
+  // (The lane offset is recomputed here rather than kept live through the terms.)
+  auto finish = [&](double* X, double* Z, double* PB, double* O) {
+    if (p.lo == 0) term(Parity<0>{}, X, Z, PB, O, 0, true);
+    long off2 = off;
+    asm volatile("" : "+v"(off2));
+    if (!own_lane) return;
+    if (p.lo == 0) {
+      double* v = p.lam_out + part * plane + off2;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (base + r < n) v[r * nq] = O[r];
+    } else {
+      double* v = p.out + part * plane + off2;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (base + r < n) {
+          v[r * nq] = X[r];
+          v[2 * plane + r * nq] = Z[r];
+          v[4 * plane + r * nq] = PB[r];
+          v[6 * plane + r * nq] = O[r];
+        }
+      }
+    }
+  };
+  // the terms l >= lmin from an even l down, in pairs (even, odd) so that the
+  // parity of every term is known where it is compiled
+  const int lmin = p.lo > 1 ? p.lo : 1;
+  auto run = [&](double* X, double* Z, double* PB, double* O, int l) {
+    for (; l - 1 >= lmin; l -= 2) {
+      term(Parity<0>{}, X, Z, PB, O, l, false);      // P_{l-1} -> Z, Pbar_l -> O
+      term(Parity<1>{}, Z, X, O, PB, l - 1, false);  // P_{l-2} -> X, Pbar_{l-1} -> PB
+    }
+    if (l >= lmin) {
+      term(Parity<0>{}, X, Z, PB, O, l, false);
+      finish(Z, X, O, PB);
+    } else {
+      finish(X, Z, PB, O);
+    }
+  };
+  // (hi >= 1 when it is odd)
+  if constexpr (HI_ODD) {
+    term(Parity<1>{}, x, z, pb, o, p.hi, false);
+    run(z, x, o, pb, p.hi - 1);
   } else {
-    FQ_STORE(ar, ai, br, bi, qr, qi, sr, si)
+    run(x, z, pb, o, p.hi);
   }
-#undef FQ_STORE
+
+  // the owned rows' sums (rows beyond n hold zeros)
+  double gv = 0.0;
+  if (own_lane) {
+    const double* vq = tab + 2 * n16 + q;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    gv += __shfl_xor(gv, o);
-    gk += __shfl_xor(gk, o);
+    for (int r = 0; r < R; ++r)
+      if (base + r < n) gv = fma(vq[r * nq], sv[r], gv);
+  } else {
+    gk = 0.0;
   }
-  if (win.lane == 0) {
-    atomicAdd(p.grad, gv);
-    if (p.any_b) atomicAdd(p.grad + 1, gk);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    gv += __shfl_xor(gv, m);
+    if constexpr (KC) gk += __shfl_xor(gk, m);
+  }
+  if (lane == 0) {
+    red[part][0] = gv;
+    red[part][1] = gk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one add per workgroup, spread over the step's slots
+    double* g = p.grad + 2 * (blockIdx.x % kAdjSlots);
+    atomicAdd(g, 2.0 * (red[0][0] + red[1][0]));
+    if constexpr (KC) atomicAdd(g + 1, 2.0 * (red[0][1] + red[1][1]));
   }
 }
-
-// 8 waves x 64 lanes x 4 rows: 2048-row windows.
-constexpr int kAdjR = 4, kAdjW = 8;
 
 }  // namespace
 
@@ -1384,30 +1369,44 @@ hipError_t launch_tridiag_adjoint(const TridiagAdjJob& job, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-long tridiag_adj_window_rows() { return (long)kAdjW * 64 * kAdjR; }
-
-static hipError_t check_adj_pass(const TridiagAdjPass& p) {
-  const long win = tridiag_adj_window_rows();
-  if (p.n < 1 || p.ncols < 1 || p.K < 1 || p.B < 1 || p.B + 2L * p.K != win) return hipErrorInvalidValue;
-  if ((long)p.nblk * p.B < p.n || (long)(p.nblk - 1) * p.B >= p.n) return hipErrorInvalidValue;
-  const long grid = p.ncols * p.nblk;
-  if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-  return hipSuccess;
-}
-
-hipError_t launch_tridiag_adj_forward(const TridiagAdjPass& p, hipStream_t s) {
-  if (hipError_t e = check_adj_pass(p); e != hipSuccess) return e;
-  if (p.lo < 0 || p.hi <= p.lo || p.hi > p.L || p.hi - p.lo > p.K) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((tridiag_adj_forward_kernel<kAdjR, kAdjW>), dim3((unsigned)(p.ncols * p.nblk)),
-                     dim3(kAdjW * 64), 0, s, p);
+hipError_t launch_tridiag_adj_table(const TridiagAdjStream& p, int k, bool plain_lambda,
+                                    double* tab, hipStream_t s) {
+  const long blocks = (p.n16 + 255) / 256;
+  hipLaunchKernelGGL(tridiag_adj_table_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, k,
+                     plain_lambda ? 1 : 0, tab);
   return hipGetLastError();
 }
 
-hipError_t launch_tridiag_adj_reverse(const TridiagAdjPass& p, hipStream_t s) {
-  if (hipError_t e = check_adj_pass(p); e != hipSuccess) return e;
-  if (p.lo < 0 || p.hi < p.lo || p.hi > p.L - 1 || p.hi - p.lo + 1 > p.K) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((tridiag_adj_reverse_kernel<kAdjR, kAdjW>), dim3((unsigned)(p.ncols * p.nblk)),
-                     dim3(kAdjW * 64), 0, s, p);
+hipError_t launch_tridiag_lam_pack(const void* ubar, bool c64, long n, long ncols, long n16,
+                                   double* out, hipStream_t s) {
+  const long blocks = (n16 * ncols + 255) / 256;
+  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_lam_pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ubar,
+                     c64 ? 1 : 0, n, ncols, n16, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag_adj_stream(const TridiagAdjStream& p, const double* tab, bool with_k,
+                                     hipStream_t s) {
+  const long grid = p.ncols * p.nblk;
+  if (p.n < 1 || p.ncols < 1 || p.K < 16 || p.K % 16 || p.B < 16 || p.B % 16 ||
+      p.B + 2L * p.K != tridiag_stream_rows(1) || p.nblk != (p.n + p.B - 1) / p.B ||
+      p.n16 != (p.n + 15) / 16 * 16 || p.plane < p.n16 * p.ncols || p.L < 1 || p.lo < 0 ||
+      p.hi < p.lo || p.hi > p.L - 1 || p.hi - p.lo + 1 > p.K || grid > 0x7fffffffL ||
+      !tab || !p.lam || !p.grad || (p.hi == p.L - 1 ? !p.seg : !p.in) ||
+      (p.lo == 0 ? !p.lam_out : !p.out))
+    return hipErrorInvalidValue;
+  const double2* coef = reinterpret_cast<const double2*>(p.coef);
+  const dim3 g((unsigned)grid), b(128);
+  const bool odd = p.hi & 1;
+  if (with_k && odd)
+    hipLaunchKernelGGL((tridiag_adj_stream_kernel<true, true>), g, b, 0, s, p, tab, coef);
+  else if (with_k)
+    hipLaunchKernelGGL((tridiag_adj_stream_kernel<true, false>), g, b, 0, s, p, tab, coef);
+  else if (odd)
+    hipLaunchKernelGGL((tridiag_adj_stream_kernel<false, true>), g, b, 0, s, p, tab, coef);
+  else
+    hipLaunchKernelGGL((tridiag_adj_stream_kernel<false, false>), g, b, 0, s, p, tab, coef);
   return hipGetLastError();
 }
 

@@ -80,7 +80,8 @@ def _marshal(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenval
              e_max: Optional[float] = None, L: int = 0, tol: float = 1e-12,
              precision: str = "fp64", checkpoint_every: int = 0, profile: bool = False,
              reorthonormalize: bool = False, dtype: str = "complex128", scheme: str = "magnus4",
-             mixed_tol: float = 0.0, term_formats=None, device=None):
+             mixed_tol: float = 0.0, term_formats=None, grad_pair_sums: bool = False,
+             device=None):
     """Device copies of the operators and the fq_system / fq_params structures
     of one problem (arguments as for FloquetContext), set on `self`."""
     import ctypes
@@ -160,6 +161,7 @@ def _marshal(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenval
     par.dtype = _abi.FQ_C64 if dtype == "complex64" else _abi.FQ_C128
     par.scheme = _abi.SCHEMES[scheme]
     par.mixed_tol = float(mixed_tol)
+    par.grad_pair_sums = 1 if grad_pair_sums else 0
     if term_formats is not None:
         tf = [_abi.TERM_FORMATS[f] if isinstance(f, str) else int(f) for f in term_formats]
         self._tf = (ctypes.c_int32 * len(tf))(*tf)
@@ -186,6 +188,9 @@ class FloquetContext:
     that the estimated rounding error of U_T stays below mixed_tol (0 = the
     library's default, 5e-7); term_formats (names of _abi.TERM_FORMATS or their
     values, for terms 1, 2, ...; the last repeats) fixes them instead.
+    grad_pair_sums: grad() then gives only each step's node sum correctly
+    (dL/dA_k for an amplitude moving both nodes of step k, returned as two
+    equal halves), skipping the commutator contraction that cancels in it.
     reorthonormalize: replace U_T by its polar factor after each build (FP64
     Newton-Schulz); the report keeps the unitarity before and after.
     dtype: "complex128" or "complex64", storage of U_T, X and U_bar (the

@@ -216,17 +216,17 @@ def test_tridiag_restrictions():
     st, _ = _ws(_tridiag(), _params(precision=1))
     assert st == _abi.FQ_ERR_UNSUPPORTED
     # gradient tape: per-column reverse sweep up to 2048 rows, streamed passes
-    # beyond (ten more n x n complex vectors for their carried state)
+    # beyond (20 more n x n16 FP64 planes for their carried state, and the
+    # forward passes' two 8-plane states for the segment recompute)
     st, b0 = _ws(_tridiag(2048), _params())
     st1, b1 = _ws(_tridiag(2048), _params(checkpoint_every=4))
     assert st == st1 == _abi.FQ_OK and b1 > b0
     st2, b2 = _ws(_tridiag(2049), _params(checkpoint_every=4))
-    assert st2 == _abi.FQ_OK and b2 >= b1 + 10 * 16 * 2049 * 2049
+    assert st2 == _abi.FQ_OK and b2 >= b1 + 20 * 8 * 2064 * 2049
     # beyond one workgroup's column the forward build keeps its checkpoints in
-    # the state blocks' type: complex128 only
+    # the state blocks' type, complex64 included
     st, _ = _ws(_tridiag(5000), _params(checkpoint_every=4, dtype=_abi.FQ_C64))
-    assert st == _abi.FQ_ERR_UNSUPPORTED
-    assert "complex128" in _abi.lib().fq_last_error().decode()
+    assert st == _abi.FQ_OK
     st, _ = _ws(_tridiag(4096), _params(checkpoint_every=4, dtype=_abi.FQ_C64))
     assert st == _abi.FQ_OK
 
@@ -431,6 +431,12 @@ def test_schedule_arguments_rejected():
     p = _params(precision=2)
     p.n_term_formats = 3                                    # count without the array
     assert _ws(_dense(), p)[0] == _abi.FQ_ERR_ARG
+
+
+def test_grad_pair_sums_flag_values():
+    for v, want in ((0, _abi.FQ_OK), (1, _abi.FQ_OK), (2, _abi.FQ_ERR_ARG), (-1, _abi.FQ_ERR_ARG)):
+        for sysd in (_dense(), _tridiag()):
+            assert _ws(sysd, _params(checkpoint_every=2, grad_pair_sums=v))[0] == want
 
 
 def _cover(A):

@@ -94,6 +94,64 @@ def test_smooth_drive_gradient_matches_oracle_differences(fl):
     assert np.max(np.abs(g[:, 0] - g[:, 1])) > 1e-6 * np.max(np.abs(g))  # nodes differ
 
 
+@pytest.mark.parametrize("layout", ["dense", "tridiag"])
+def test_constant_drive_node_derivatives(fl, layout):
+    """A drive constant over every step (b_k = 0 throughout): each node's own
+    derivative still has the commutator part (moving one node makes b_k
+    nonzero), against central differences of the oracle node by node; with
+    grad_pair_sums only the node sums are kept, as equal halves."""
+    M = 6
+    rng = np.random.default_rng(91)
+    T = 2.0
+    f = rng.uniform(-1, 1, M)
+    nodes = np.stack([f, f], 1)
+    if layout == "dense":
+        n = 20
+        H0, V = gue(n, rng), gue(n, rng)
+        sysk = dict(h0=H0, hmod=V)
+        lo, hi, L = -8.0, 8.0, 40
+
+        def build(ff):
+            return orc.build_ut(H0, V, ff, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+    else:
+        d, e, v = dimer_tridiag(19, 1.0, 0.3)
+        n = 20
+        sysk = dict(h0_diag=d, h0_off=e, hmod_diag=v)
+        a, b = orc.magnus4_weights(nodes, T / M)
+        lo, hi = orc.tridiag_cover(d, e, v, a, b)
+        lo, hi = lo - 1.0, hi + 1.0
+        L = orc.choose_L(orc.rescale(lo, hi, T / M)[2], 1e-14)
+
+        def build(ff):
+            return orc.build_ut_tridiag(d, e, v, ff, T, M, route="cheb", e_min=lo, e_max=hi, L=L)
+    W = haar_unitary(n, rng)
+    kw = dict(T=T, M=M, f_nodes=nodes, e_min=lo, e_max=hi, L=L, checkpoint_every=2, **sysk)
+    ctx = fl.FloquetContext(**kw)
+    U = ctx.build_ut().cpu().numpy()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g = ctx.grad(Ubar)
+    eps = 1e-5
+    fd = np.zeros_like(nodes)
+    for k in range(M):
+        for i in range(2):
+            fp, fm = nodes.copy(), nodes.copy()
+            fp[k, i] += eps
+            fm[k, i] -= eps
+            fd[k, i] = (_trace_loss_and_bar(build(fp), W)[0] -
+                        _trace_loss_and_bar(build(fm), W)[0]) / (2 * eps)
+    err = np.max(np.abs(g - fd)) / np.max(np.abs(fd))
+    _say(layout, "constant-drive node derivatives rel err", err)
+    assert err < 1e-6
+    assert np.max(np.abs(g[:, 0] - g[:, 1])) > 1e-4 * np.max(np.abs(g))  # the K part is there
+    cp = fl.FloquetContext(grad_pair_sums=True, **kw)
+    cp.build_ut()
+    gp = cp.grad(Ubar)
+    assert np.array_equal(gp[:, 0], gp[:, 1])
+    err = np.max(np.abs(gp.sum(axis=1) - g.sum(axis=1))) / np.max(np.abs(g.sum(axis=1)))
+    _say(layout, "pair sums rel diff", err)
+    assert err < 1e-10
+
+
 @pytest.mark.parametrize("where", ["cpu", "cuda"])
 def test_autograd_function(fl, where):
     """The gradient comes back on the device (and in the dtype) of f_nodes."""
@@ -196,7 +254,8 @@ def test_tridiag_piecewise_gradient_matches_oracle(fl, nb, M, ckpt):
     err = np.max(np.abs(g.sum(axis=1) - ref)) / np.max(np.abs(ref))
     _say("rel err", err, "L", L, "max|g|", np.max(np.abs(ref)))
     assert err < 1e-9
-    assert np.max(np.abs(g[:, 0] - g[:, 1])) < 1e-12 * np.max(np.abs(g))  # b_k = 0: nodes agree
+    # b_k = 0, but each node's own derivative keeps its commutator part
+    assert np.max(np.abs(g[:, 0] - g[:, 1])) > 1e-6 * np.max(np.abs(g))
 
 
 def test_tridiag_smooth_drive_gradient_matches_oracle_differences(fl):
@@ -300,18 +359,25 @@ def _dimer_kw(d, e, v, nodes, T, M, margin):
     return dict(h0_diag=d, h0_off=e, hmod_diag=v, T=T, M=M, e_min=lo, e_max=hi, L=L)
 
 
-@pytest.mark.parametrize("nb,M,ckpt,smooth,dtype", [(299, 10, 3, False, "complex128"),
-                                                    (299, 8, 3, True, "complex128"),
-                                                    (1999, 6, 4, False, "complex128"),
-                                                    (299, 7, 2, False, "complex64")])
+@pytest.mark.parametrize("nb,M,ckpt,smooth,dtype,pair", [(299, 10, 3, False, "complex128", False),
+                                                         (299, 10, 3, False, "complex128", True),
+                                                         (299, 8, 3, True, "complex128", False),
+                                                         (299, 8, 3, True, "complex128", True),
+                                                         (1999, 6, 4, False, "complex128", True),
+                                                         (1999, 6, 4, True, "complex128", False),
+                                                         (299, 7, 2, False, "complex64", False),
+                                                         (779, 5, 5, False, "complex128", True),
+                                                         (15, 4, 2, True, "complex128", False)])
 def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M, ckpt, smooth,
-                                                         dtype):
+                                                         dtype, pair):
     """The streamed reverse sweep (selected for n <= 2048 by the environment
     switch) against the per-column sweep on the same problem: one block per
-    column (n = 300) and two (n = 2000, blocks of 1792 owned rows), with and
-    without the K contraction (b_k != 0 for a smooth drive), and with
-    complex64 state blocks (U_bar read as complex64)."""
-    _say("streamed vs per-column sweep", nb + 1, M, ckpt, smooth, dtype)
+    column (n = 16, 300, 780 with a column end inside the last lane group)
+    and three (n = 2000, blocks of 768 owned rows), with the K contraction
+    (the default) and without it (node-pair sums), for piecewise-constant and
+    smooth drives, one checkpoint segment and several, and with complex64
+    state blocks (U_bar read as complex64)."""
+    _say("streamed vs per-column sweep", nb + 1, M, ckpt, smooth, dtype, "pair sums", pair)
     rng = np.random.default_rng(400 + nb)
     if smooth:
         d, e, v = dimer_tridiag(nb, 1.0, 0.3)
@@ -324,9 +390,11 @@ def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M,
         nodes = np.stack([f, f], 1)
     kw = _dimer_kw(d, e, v, nodes, T, M, 0.0)
     W = haar_unitary(nb + 1, rng)
-    per_col = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, dtype=dtype, **kw)
+    per_col = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, dtype=dtype,
+                                grad_pair_sums=pair, **kw)
     monkeypatch.setenv("FQ_TRIDIAG_STREAMED_ADJOINT", "1")
-    streamed = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, dtype=dtype, **kw)
+    streamed = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, dtype=dtype,
+                                 grad_pair_sums=pair, **kw)
     monkeypatch.delenv("FQ_TRIDIAG_STREAMED_ADJOINT")
     U = per_col.build_ut().cpu().numpy()
     streamed.build_ut()
@@ -337,12 +405,12 @@ def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M,
     err = np.max(np.abs(g1 - g2)) / np.max(np.abs(g1))
     _say("L", kw["L"], "max|g|", np.max(np.abs(g1)), "rel diff", err)
     assert err < 1e-10
-    if smooth:
+    if not pair:
         assert np.max(np.abs(g2[:, 0] - g2[:, 1])) > 1e-6 * np.max(np.abs(g2))
 
 
-@pytest.mark.parametrize("nb,M,ckpt", [(2499, 6, 2), (4499, 6, 2)])
-def test_tridiag_long_column_gradient_against_fd(fl, nb, M, ckpt):
+@pytest.mark.parametrize("nb,M,ckpt,pair", [(2499, 6, 2, True), (4499, 6, 2, False)])
+def test_tridiag_long_column_gradient_against_fd(fl, nb, M, ckpt, pair):
     """Columns beyond the per-column sweep (n > 2048; for n > 4096 the forward
     build streams too and records its checkpoints through the snapshot store):
     the streamed reverse sweep against central differences (h = 1e-5) of the
@@ -361,7 +429,8 @@ def test_tridiag_long_column_gradient_against_fd(fl, nb, M, ckpt):
     _say("long-column gradient", n, "M", M, "L", kw["L"])
     sys_kw = {k: kw[k] for k in ("h0_diag", "h0_off", "hmod_diag", "T", "M")}
     W = fl.FloquetContext(f_nodes=np.stack([fw, fw], 1), **sys_kw).build_ut()
-    ctx = fl.FloquetContext(f_nodes=np.stack([f, f], 1), checkpoint_every=ckpt, **kw)
+    ctx = fl.FloquetContext(f_nodes=np.stack([f, f], 1), checkpoint_every=ckpt,
+                            grad_pair_sums=pair, **kw)
     U = ctx.build_ut()
 
     def loss_of(Ut):
@@ -384,3 +453,30 @@ def test_tridiag_long_column_gradient_against_fd(fl, nb, M, ckpt):
         fd = (vals[0] - vals[1]) / (2 * eps)
         _say("k", k, "adjoint", g[k], "fd", fd)
         assert abs(g[k] - fd) <= 1e-5 * abs(fd) + 1e-9
+
+
+def test_tridiag_long_column_complex64_tape(fl):
+    """n > 4096 with complex64 state blocks: the streamed build records its
+    checkpoints in complex64 (entries of half the size), which the reverse
+    sweep reads back for every segment; against the complex128 gradient."""
+    import torch
+    nb, M, ckpt = 4199, 6, 2
+    d, e, v = dimer_tridiag(nb, 1.0, 0.01)
+    n = nb + 1
+    rng = np.random.default_rng(600)
+    f = rng.uniform(-1, 1, M)
+    kw = _dimer_kw(d, e, v, np.stack([f, f], 1), 0.05, M, 10.0)
+    W = torch.from_numpy(haar_unitary(n, rng)).to("cuda")
+    gs = []
+    for dtype in ("complex128", "complex64"):
+        _say("long-column tape", n, dtype)
+        ctx = fl.FloquetContext(f_nodes=np.stack([f, f], 1), checkpoint_every=ckpt, dtype=dtype,
+                                **kw)
+        U = ctx.build_ut()
+        Wd = W.to(U.dtype)
+        tau = torch.sum(torch.conj(Wd) * U)
+        gs.append(ctx.grad((-2.0 / n ** 2) * tau * Wd))
+        del ctx, U
+    err = np.max(np.abs(gs[0] - gs[1])) / np.max(np.abs(gs[0]))
+    _say("complex64 tape rel diff", err)
+    assert err < 1e-5
