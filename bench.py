@@ -834,12 +834,15 @@ def main():
                 roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VECTOR_TFLOPS, 4),
                         "traffic": None, "traffic_detail": None,
-                        "kernel": "tridiag_adj_reverse_kernel<4,8> (reverse passes of up to 128 "
-                                  "terms; 1792 owned + 2 x 128 ghost rows per workgroup, real gauge frame)",
+                        "kernel": ("tridiag_adj_stream_kernel<%s, ...> (reverse passes of up to "
+                                   "128 terms; 768 owned + 2 x 128 ghost rows per workgroup, one "
+                                   "wave per real or imaginary part, real gauge frame)"
+                                   % ("false" if ctx.grad_pair_sums else "true")),
                         "avg_launch_ms": round(ms_rev, 4), "launches_timed": n_rev,
                         "algorithmic_flops_per_launch": flops_rev}
                 extra["gradient"]["segment_recompute_pass"] = {
-                    "kernel": "tridiag_adj_forward_kernel<4,8>", "avg_launch_ms": round(ms_fwd, 4),
+                    "kernel": "tridiag_stream_kernel<16,1> (the forward pass, saving each step's "
+                              "last two terms)", "avg_launch_ms": round(ms_fwd, 4),
                     "launches_timed": n_fwd}
 
     ocols = args.oracle_cols if args.oracle_cols >= 0 else (4 if n <= 4096 else 0)

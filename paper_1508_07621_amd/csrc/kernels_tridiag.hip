@@ -993,13 +993,13 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
                                                                  const double* __restrict__ tab,
                                                                  const double2* __restrict__ coef) {
   constexpr int R = 16, XR = KC ? R : 1, XL = KC ? 64 : 1;
-  // Lambda' = conj(phase) Lambda~ of the window (both waves read both parts),
-  // the pass's Chebyshev coefficients, the K~ couplings (re, im), P_l of both
-  // parts two terms deep, the waves' sums
-  __shared__ double lam_s[2][R][64];
+  // the pass's Chebyshev coefficients, P_l of both parts two terms deep (K
+  // contraction), the waves' sums
   __shared__ double2 c_s[128];
-  __shared__ double k_s[2][XR][XL];
+  // Lambda' of the window for the K contraction (registers otherwise)
+  __shared__ double lam_s[2][XR][XL];
   __shared__ double xs[2][2][XR][XL];
+  __shared__ double d_s[XR][XL];  // K contraction: the diagonal of 2 G (registers otherwise)
   __shared__ double red[2][2];
 
   const int part = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1016,56 +1016,76 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
   // K and B are multiples of 16: a lane's 16 rows are all owned or all ghosts
   const bool own_lane = base >= a0 && base < a0 + p.B;
 
-  double d2[R], g2[R];             // rows of 2 G
+  double d2r[KC ? 1 : R], g2[R];   // rows of 2 G
   double x[R], z[R], pb[R], o[R];  // P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2}
   double sv[R];                    // Re Pbar_{l+1} P_l summed over the terms
   double gk = 0.0;                 // Re <Pbar_{l+1}, K~ P_l> over the lane's rows, summed
+  double kr[KC ? R : 1], ki[KC ? R : 1];  // K~ couplings k_i (re, im; im signed for this part)
   double gm2 = 0.0;                // coupling from row base - 1
 
-  // Lambda' = f Lambda with f = conj(phase) conj(w_k) w_{k+1} from the table;
-  // this wave stores its own part
+  // Lambda' = f Lambda with f = conj(phase) conj(w_k) w_{k+1} from the table:
+  // this part and the other (with the K contraction: in LDS, this wave
+  // storing its own part)
+  double lam_o[KC ? 1 : R], lam_x[KC ? 1 : R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    double v = 0.0;
+    double vr = 0.0, vi = 0.0;
     if (in_col(r)) {
       const double ar = p.lam[off + r * nq], ai = p.lam[plane + off + r * nq];
       const double fr = tq[3 * n16 + r * nq], fi = tq[4 * n16 + r * nq];
-      v = part == 0 ? fr * ar - fi * ai : fr * ai + fi * ar;
+      vr = fr * ar - fi * ai;
+      vi = fr * ai + fi * ar;
     }
-    lam_s[part][r][lane] = v;
-    if constexpr (KC) k_s[part][r][lane] = in_col(r) ? tq[(5 + part) * n16 + r * nq] : 0.0;
+    if constexpr (KC) {
+      lam_s[part][r][lane] = part == 0 ? vr : vi;
+    } else {
+      lam_o[r] = part == 0 ? vr : vi;
+      lam_x[r] = part == 0 ? vi : vr;
+    }
   }
+  auto lam = [&](bool other, int r) {
+    if constexpr (KC)
+      return lam_s[other ? 1 - part : part][r][lane];
+    else
+      return other ? lam_x[r] : lam_o[r];
+  };
   for (int t = threadIdx.x; t <= p.hi - p.lo; t += 128) c_s[t] = coef[p.hi - t];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const bool ok = in_col(r);
-    d2[r] = ok ? tq[r * nq] : 0.0;
+    if constexpr (KC) {
+      if (part == 0) d_s[r][lane] = ok ? tq[r * nq] : 0.0;
+    } else {
+      d2r[r] = ok ? tq[r * nq] : 0.0;
+    }
     g2[r] = ok ? tq[n16 + r * nq] : 0.0;
     sv[r] = 0.0;
   }
   if (base >= 1 && base < n) gm2 = tq[n16 + (long)(R - 1) * nq - 1];  // row base - 1
+  const double sgn = part == 0 ? 1.0 : -1.0;
   double kmr = 0.0, kmi = 0.0;  // K~ coupling from row base - 1
   if constexpr (KC) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      kr[r] = in_col(r) ? tq[5 * n16 + r * nq] : 0.0;
+      ki[r] = in_col(r) ? sgn * tq[6 * n16 + r * nq] : 0.0;
+    }
     if (base >= 1 && base < n) {
       kmr = tq[5 * n16 + (long)(R - 1) * nq - 1];
-      kmi = tq[6 * n16 + (long)(R - 1) * nq - 1];
+      kmi = sgn * tq[6 * n16 + (long)(R - 1) * nq - 1];
     }
   }
-  const double sgn = part == 0 ? 1.0 : -1.0;
   __syncthreads();
 
   // d_l Lambda~ = conj(c_l) Lambda'. c_l is real for even l and imaginary for
   // odd l: a part takes its own part of Lambda' with Re c_l (even l), or the
   // other part with +/- Im c_l (odd l)
-  const double(*lam_own)[64] = lam_s[part];
-  const double(*lam_oth)[64] = lam_s[1 - part];
 
   const bool first = p.hi == p.L - 1;
   if (first) {  // P_{L-1}, P_L from the recompute; Pbar_L = d_L Lambda~, Pbar_{L+1} = 0
     const double2 cL = c_s[0];
     const bool odd = p.L & 1;
     const double cs = odd ? sgn * cL.y : cL.x;
-    const double(*lm)[64] = odd ? lam_oth : lam_own;
     const double* sx = p.seg + ((((p.L - 1) & 1) * 2 + part) * plane) + off;
     const double* sz = p.seg + (((p.L & 1) * 2 + part) * plane) + off;
 #pragma unroll
@@ -1073,7 +1093,7 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
       const bool ok = in_col(r);
       x[r] = ok ? sx[r * nq] : 0.0;
       z[r] = ok ? sz[r * nq] : 0.0;
-      pb[r] = cs * lm[r][lane];
+      pb[r] = cs * lam(odd, r);
       o[r] = 0.0;
     }
   } else {
@@ -1096,11 +1116,16 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
   auto term = [&](auto par, const double* X, double* Z, const double* PB, double* O, int l,
                   bool L0) {
     constexpr bool ODD = decltype(par)::value;
-    // Lambda' and c_l are read from LDS in every term, not kept in registers
-    asm volatile("" ::: "memory");
+    // (LDS values are read in every term, not kept in registers)
+    if constexpr (KC) asm volatile("" ::: "memory");
     const double2 cl = c_s[p.hi - l];
     const double cs = ODD ? sgn * cl.y : cl.x;
-    const double(*lm)[64] = ODD ? lam_oth : lam_own;
+    auto d2 = [&](int r) {
+      if constexpr (KC)
+        return d_s[r][lane];
+      else
+        return d2r[r];
+    };
     const double xu = prev_lane_or_zero(X[R - 1]), xd = next_lane_or_zero(X[0]);
     const double pu = prev_lane_or_zero(PB[R - 1]), pd = next_lane_or_zero(PB[0]);
     const double hw = L0 ? 0.5 : 1.0;
@@ -1113,19 +1138,20 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
       for (int r = 0; r < R; ++r) xs[parity][part][r][lane] = X[r];
       __syncthreads();
       const auto ox = xs[parity][1 - part];
+      // the other part's rows base - 1 and base + 16 (zero beyond the window)
+      const double oe0 = ox[R - 1][(lane + 63) & 63], oe1 = ox[0][(lane + 1) & 63];
+      const double om0 = lane > 0 ? oe0 : 0.0, op15 = lane < 63 ? oe1 : 0.0;
       double tk = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double om = r > 0 ? ox[r - 1][lane] : (lane > 0 ? ox[R - 1][lane - 1] : 0.0);
-        const double op = r < R - 1 ? ox[r + 1][lane] : (lane < 63 ? ox[0][lane + 1] : 0.0);
+        const double om = r > 0 ? ox[r - 1][lane] : om0;
+        const double op = r < R - 1 ? ox[r + 1][lane] : op15;
         const double xm = r > 0 ? X[r - 1] : xu, xp = r < R - 1 ? X[r + 1] : xd;
-        const double cmr = r > 0 ? k_s[0][r - 1][lane] : kmr;
-        const double cmi = r > 0 ? k_s[1][r - 1][lane] : kmi;
-        const double khr = k_s[0][r][lane], khi = k_s[1][r][lane];
+        const double cmr = r > 0 ? kr[r - 1] : kmr, cmi = r > 0 ? ki[r - 1] : kmi;
         double t = cmr * xm;
-        t = fma(khr, xp, t);
-        t = fma(sgn * cmi, om, t);
-        t = fma(-sgn * khi, op, t);
+        t = fma(kr[r], xp, t);
+        t = fma(cmi, om, t);
+        t = fma(-ki[r], op, t);
         tk = fma(PB[r], t, tk);
       }
       gk = fma(hw, tk, gk);
@@ -1136,7 +1162,7 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
       for (int r = 0; r < R; ++r) {
         const double lo = r > 0 ? X[r - 1] : xu, hi = r < R - 1 ? X[r + 1] : xd;
         const double gl = r > 0 ? g2[r - 1] : gm2;
-        double t = fma(d2[r], X[r], -Z[r]);
+        double t = fma(d2(r), X[r], -Z[r]);
         t = fma(gl, lo, t);
         Z[r] = fma(g2[r], hi, t);
       }
@@ -1144,21 +1170,21 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
       for (int r = 0; r < R; ++r) {
         const double lo = r > 0 ? PB[r - 1] : pu, hi = r < R - 1 ? PB[r + 1] : pd;
         const double gl = r > 0 ? g2[r - 1] : gm2;
-        double t = fma(d2[r], PB[r], -O[r]);
+        double t = fma(d2(r), PB[r], -O[r]);
         t = fma(gl, lo, t);
         t = fma(g2[r], hi, t);
-        O[r] = fma(cs, lm[r][lane], t);
+        O[r] = fma(cs, lam(ODD, r), t);
       }
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double lo = r > 0 ? PB[r - 1] : pu, hi = r < R - 1 ? PB[r + 1] : pd;
         const double gl = r > 0 ? g2[r - 1] : gm2;
-        double h = d2[r] * PB[r];
+        double h = d2(r) * PB[r];
         h = fma(gl, lo, h);
         h = fma(g2[r], hi, h);
         const double t = fma(0.5, h, -O[r]);
-        O[r] = fma(cs, lm[r][lane], t);
+        O[r] = fma(cs, lam(ODD, r), t);
       }
     }
   };

@@ -162,6 +162,7 @@ def _marshal(self, *, T: float, M: int, f_nodes, h0=None, hmod=None, h0_eigenval
     par.scheme = _abi.SCHEMES[scheme]
     par.mixed_tol = float(mixed_tol)
     par.grad_pair_sums = 1 if grad_pair_sums else 0
+    self.grad_pair_sums = bool(grad_pair_sums)
     if term_formats is not None:
         tf = [_abi.TERM_FORMATS[f] if isinstance(f, str) else int(f) for f in term_formats]
         self._tf = (ctypes.c_int32 * len(tf))(*tf)
