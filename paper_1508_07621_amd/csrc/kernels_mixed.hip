@@ -306,14 +306,14 @@ __device__ __forceinline__ void split_n(float x, u16* out) {
 // stores: the stores may alias later loads of the same buffers in the
 // compiler's view (P_{l+1} overwrites P_{l-1} in place), which would otherwise
 // serialise one memory round trip per chunk and per buffer.
-template <int BM, int BN, int NT, int KIND, bool P_F64>
+template <int BM, int BN, int NT, int KIND, bool P_F64, int BATCH = 2>
 __device__ __forceinline__ void bf3_tile_epilogue(const Bf3Args& g, const float* cre,
                                                   const float* cim, int m0, int n0, int tid) {
   constexpr int NS = BF3_PLANES;
   constexpr bool FIRST = KIND == CHEB_FIRST || KIND == CHEB_FIRST_LAST;
   constexpr bool TO_X = KIND == CHEB_LAST || KIND == CHEB_FIRST_LAST;
-  constexpr int NQ = BM * BN / 8 / NT;   // chunks per thread
-  constexpr int B = NQ >= 2 ? 2 : 1;     // chunks whose loads are in flight together
+  constexpr int NQ = BM * BN / 8 / NT;     // chunks per thread
+  constexpr int B = NQ >= BATCH ? BATCH : 1;  // chunks whose loads are in flight together
   static_assert(NQ * NT * 8 == BM * BN && NQ % B == 0, "chunk split");
   const long np = g.np, plane = g.plane;
   const double cr_ = g.cr, ci_ = g.ci;
@@ -635,6 +635,174 @@ __global__ __launch_bounds__(WGM* WGN * 64) void cheb_bf3_kernel(Bf3Args g) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// One- and two-piece products on 128 x 128 tiles with four waves of 64 x 64
+// and the four real products of the complex one (Re = Ar Br - Ai Bi,
+// Im = Ar Bi + Ai Br, -Ai by flipping sign bits in registers) instead of
+// Gauss's three: per wave and k-block 4 NPC fragments of A and of B feed 16
+// matrix-core operations per piece pair, a quarter of the LDS reads per
+// operation of the 64 x 32 Gauss tiles, whose three operands also need the
+// pieces of re + im staged. LDS holds only the 2 NPC stored planes of A and B,
+// in two stages (32 or 64 KiB), so that two workgroups share a CU and cover
+// each other's waits. The epilogue runs in two halves of 64 columns through
+// 64 KiB of LDS.
+// ---------------------------------------------------------------------------------------------
+template <int KIND, bool P_F64, int NPC>
+__global__ __launch_bounds__(256, 2) void cheb_x4_kernel(Bf3Args g) {
+  constexpr int BM = 128, BN = 128, NT = 256, FM = 2, FN = 2;
+  constexpr int NL = 2 * NPC;                // stored planes read per operand
+  constexpr int SA = BM * 32, SB = BN * 32;  // bytes per plane and k-block
+  constexpr int STAGE = NL * (SA + SB);
+  constexpr int EPI = 2 * 128 * 64 * 4;      // FP32 Re, Im of one half, k-blocked order
+  constexpr int SMEM = (2 * STAGE > EPI) ? 2 * STAGE : EPI;
+  constexpr int NPAIR = NPC == 1 ? 1 : 3;
+  constexpr bool FIRST = KIND == CHEB_FIRST || KIND == CHEB_FIRST_LAST;
+  static_assert(NPC == 1 || NPC == 2, "pieces (three take the Gauss kernel)");
+  static_assert(!FIRST || P_F64, "the first product reads X in FP64");
+  static_assert(EPI == 2 * 2 * 4096 * 4, "two 128 x 32 groups of Re and of Im");
+  static_assert(2 * BM == NT && 2 * BN == NT, "one 16-byte chunk of A and of B per thread");
+
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+
+  int tm, tn;
+  tile_coords(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
+  if (tm >= g.tiles_m) return;  // grid padding
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const long np = g.np, plane = g.plane;
+  const int nk = g.np / 16;
+  const long kstride = np * 16;  // words between consecutive k-blocks of a plane
+
+  // Staging: thread t copies 16-byte chunk t of A and of B in every plane.
+  const u16* srca = g.a + (long)m0 * 16 + tid * 8;
+  const u16* srcb = g.b + (long)n0 * 16 + tid * 8;
+  u32x4 sta[NL], stb[NL];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const long po = (q < NPC ? q : 3 + q - NPC) * plane + kb * kstride;
+      sta[q] = *reinterpret_cast<const u32x4*>(srca + po);
+      stb[q] = *reinterpret_cast<const u32x4*>(srcb + po);
+    }
+  };
+  auto lstore = [&](int buf) {
+    unsigned char* d = smem + buf * STAGE + tid * 16;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      *reinterpret_cast<u32x4*>(d + q * SA) = sta[q];
+      *reinterpret_cast<u32x4*>(d + NL * SA + q * SB) = stb[q];
+    }
+  };
+
+  // Fragment offsets (bytes within a plane of a stage).
+  int aoff[FM], boff[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int row = wm * 64 + i * 32 + (lane & 31);
+    aoff[i] = row * 32 + 16 * ((lane >> 5) ^ ((row >> 3) & 1));
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int row = wn * 64 + j * 32 + (lane & 31);
+    boff[j] = NL * SA + row * 32 + 16 * ((lane >> 5) ^ ((row >> 3) & 1));
+  }
+  // fragments [plane q][i]: q < NPC the real pieces, q >= NPC the imaginary ones
+  bf8 fa[NL][FM], fb[NL][FN];
+  auto fload = [&](int buf, bf8 (&xa)[NL][FM], bf8 (&xb)[NL][FN]) {
+    const unsigned char* sb = smem + buf * STAGE;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i) xa[q][i] = *reinterpret_cast<const bf8*>(sb + q * SA + aoff[i]);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) xb[q][j] = *reinterpret_cast<const bf8*>(sb + q * SB + boff[j]);
+    }
+  };
+
+  f16v cre[FM][FN], cim[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cre[i][j][r] = cim[i][j][r] = 0.f;
+
+  gload(0);
+  lstore(0);
+  gload(nk > 1 ? 1 : 0);
+  lstore(1);
+  gload(nk > 2 ? 2 : nk - 1);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    fload(kb & 1, fa, fb);
+    bf8 ma[NPC][FM];  // -Ai pieces: flipped sign bits
+#pragma unroll
+    for (int q = 0; q < NPC; ++q)
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        u32x4 w = __builtin_bit_cast(u32x4, fa[NPC + q][i]);
+        w ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        ma[q][i] = __builtin_bit_cast(bf8, w);
+      }
+    // piece pairs (pa, pb), the leading pair last
+#pragma unroll
+    for (int t = NPAIR - 1; t >= 0; --t) {
+      constexpr int PA[3] = {0, 0, 1}, PB[3] = {0, 1, 0};
+      const int pa = PA[t], pb = PB[t];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          cre[i][j] = mfma32_bf16(fa[pa][i], fb[pb][j], cre[i][j]);
+          cim[i][j] = mfma32_bf16(fa[pa][i], fb[NPC + pb][j], cim[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          cre[i][j] = mfma32_bf16(ma[pa][i], fb[NPC + pb][j], cre[i][j]);
+          cim[i][j] = mfma32_bf16(fa[NPC + pa][i], fb[pb][j], cim[i][j]);
+        }
+    }
+    // k-block kb + 2 into the buffer kb came from, once every wave has read
+    // its fragments there; the one after into registers
+    __syncthreads();
+    lstore(kb & 1);
+    gload(kb + 3 < nk ? kb + 3 : nk - 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue in two halves: half h takes every wave's fragments j = h, the
+  // 128 x 32 column groups n0 + 64 s + 32 h (s = wave column), so that each
+  // wave keeps only the other half's accumulators while the first is written.
+  // Re and Im to LDS, k-blocked order per group: element (row, col) of group s
+  // at float index s * 4096 + ((col / 16) * 128 + row) * 16 + 8 * slot + col % 8
+  // with slot = ((col / 8) & 1) ^ ((row / 8) & 1); real parts, then imaginary.
+  float* ere = reinterpret_cast<float*>(smem);
+  float* eim = ere + 2 * 128 * 32;  // two groups of 128 x 32 each
+#pragma unroll
+  for (int h = 0; h < FN; ++h) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = lane & 31;
+        const int slot = ((col >> 3) & 1) ^ ((row >> 3) & 1);
+        const int f = wn * 4096 + ((col >> 4) * 128 + row) * 16 + 8 * slot + (col & 7);
+        ere[f] = cre[i][h][r];
+        eim[f] = cim[i][h][r];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int sgrp = 0; sgrp < 2; ++sgrp)
+      bf3_tile_epilogue<128, 32, NT, KIND, P_F64, 1>(
+          g, ere + sgrp * 4096, eim + sgrp * 4096, m0, n0 + 64 * sgrp + 32 * h, tid);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Split-BF16 product with FP64 accumulation, for the terms whose Bessel weight
 // is too large for FP32 accumulators (P_1 of every step, and any term with a
 // comparable weight). Each operand is split into three BF16 pieces; per k-block
@@ -814,8 +982,15 @@ hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
   if (mrows % 128 == 0 && np % 128 == 0 && (long)mrows * np >= kBigTileElems) {
     g.tiles_m = mrows / 128;
     g.tiles_n = np / 128;
-    hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64, NPC>),
-                       dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(512), 0, s, g);
+    // one or two pieces: 64 x 64 wave tiles, four real products, two
+    // workgroups per CU; three pieces: the Gauss form on 64 x 32 wave tiles
+    // (measured faster there: the four-product form needs 96 KiB of LDS)
+    if constexpr (NPC <= 2)
+      hipLaunchKernelGGL((cheb_x4_kernel<KIND, P_F64, NPC>),
+                         dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((cheb_bf3_kernel<128, 128, 2, 4, KIND, P_F64, NPC>),
+                         dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(512), 0, s, g);
   } else if (mrows % 64 == 0 && np % 64 == 0) {
     g.tiles_m = mrows / 64;
     g.tiles_n = np / 64;
