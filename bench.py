@@ -393,7 +393,7 @@ TERM_MFMA = {"fp64": 0.75, "bf16x3_f64acc": 6.0, "bf16x3": 4.5, "bf16x2": 2.25, 
 TERM_KERNEL = {
     "fp64": "zgemm_nt_f64_kernel<128,128,8,2,4,Gauss,EpiCheb> (FP64 MFMA 16x16x4)",
     "bf16x3_f64acc": "cheb_acc_kernel<128> (BF16 MFMA 32x32x16, 4 real products x 6 piece "
-                     "pairs, FP64 sums per 16-column block)",
+                     "pairs, FP64 sums per 64-column block)",
     "bf16x3": "cheb_bf3_kernel<128,128,2,4,KIND,P,3> (BF16 MFMA 32x32x16, 3 real products x 6 "
               "piece pairs)",
     "bf16x2": "cheb_bf3_kernel<128,128,2,4,KIND,P,2> (3 real products x 3 piece pairs)",

@@ -96,9 +96,9 @@ typedef enum { FQ_FP64 = 0, FQ_FP32 = 1, FQ_BF16X3 = 2 } fq_precision;
  * target (fq_params.mixed_tol), unless the caller fixes them. */
 typedef enum fq_term_format {
   FQ_TERM_FP64 = 0,          /* FP64 matrix cores on FP64 operands */
-  FQ_TERM_BF16X3_F64ACC = 1, /* three BF16 pieces per operand, partial sums of
-                                each 16-column block added in FP64: about 24
-                                significant bits, independent of N */
+  FQ_TERM_BF16X3_F64ACC = 1, /* three BF16 pieces per operand, FP32 partial
+                                sums of each 64-column block added in FP64:
+                                about 24 significant bits, independent of N */
   FQ_TERM_BF16X3 = 2,        /* three BF16 pieces, FP32 accumulation */
   FQ_TERM_BF16X2 = 3,        /* two BF16 pieces (about 16 bits) */
   FQ_TERM_BF16X1 = 4,        /* one BF16 piece (about 8 bits) */

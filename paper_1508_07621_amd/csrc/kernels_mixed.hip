@@ -805,18 +805,19 @@ __global__ __launch_bounds__(256, 2) void cheb_x4_kernel(Bf3Args g) {
 // ---------------------------------------------------------------------------------------------
 // Split-BF16 product with FP64 accumulation, for the terms whose Bessel weight
 // is too large for FP32 accumulators (P_1 of every step, and any term with a
-// comparable weight). Each operand is split into three BF16 pieces; per k-block
-// of 16 columns the six kept piece pairs of the four real products
+// comparable weight). Each operand is split into three BF16 pieces; per FLUSH
+// k-blocks of 16 columns the six kept piece pairs of the four real products
 // (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br) go into FP32 partial sums that
-// start from zero, smallest pairs first, and are then added into FP64 sums.
-// The error of a product is then a few FP32 roundings of one k-block's partial
-// sum instead of one per accumulation over the whole contraction, so the
-// product carries about 24 significant bits independently of N. Tile BM x 64
+// start from zero, smallest pairs first within a k-block, and are then added
+// into FP64 sums. The error of a product is then a few FP32 roundings of a
+// partial sum over 16 FLUSH columns instead of one per accumulation over the
+// whole contraction, so the product carries about 24 significant bits
+// independently of N. Tile BM x 64
 // (BM = 128 or 64), waves of 32 x 32; two LDS stages of the six stored planes. The
 // epilogue works from the FP64 sums in registers: the Chebyshev sum Y takes
 // the unrounded FP64 term, the stored P_{l+1} its BF16X3 rounding.
 // ---------------------------------------------------------------------------------------------
-template <int BM, int KIND, bool P_F64>
+template <int BM, int KIND, bool P_F64, int FLUSH>
 __global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
   constexpr int BN = 64, WGN = 2, NT = BM * 4;
   constexpr int NS = BF3_PLANES;             // 6 planes: re pieces, im pieces
@@ -875,7 +876,11 @@ __global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
   lstore(0);
   gload(nk > 1 ? 1 : 0);
   __syncthreads();
-  for (int kb = 0; kb < nk; ++kb) {
+  f16v pre = zero, pim = zero;
+  for (int kb0 = 0; kb0 < nk; kb0 += FLUSH) {
+#pragma unroll
+  for (int u = 0; u < FLUSH; ++u) {
+    const int kb = kb0 + u;
     const unsigned char* sb = smem + (kb & 1) * STAGE;
     bf8 fa[NS], fb[NS], na[3];
 #pragma unroll
@@ -889,9 +894,10 @@ __global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
       w ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
       na[p] = __builtin_bit_cast(bf8, w);
     }
-    // pairs (i, j) with i + j <= 2, the two hi x hi products last
-    f16v pre = mfma32_bf16(fa[2], fb[0], zero);
-    f16v pim = mfma32_bf16(fa[2], fb[3], zero);
+    // pairs (i, j) with i + j <= 2, the two hi x hi products last; the
+    // partial sums start from zero every FLUSH k-blocks
+    pre = mfma32_bf16(fa[2], fb[0], u == 0 ? zero : pre);
+    pim = mfma32_bf16(fa[2], fb[3], u == 0 ? zero : pim);
     pre = mfma32_bf16(na[2], fb[3], pre);
     pim = mfma32_bf16(fa[5], fb[0], pim);
 #define FQ_ACC_PAIR(i, j)                          \
@@ -905,14 +911,17 @@ __global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
     FQ_ACC_PAIR(0, 1)
     FQ_ACC_PAIR(0, 0)
 #undef FQ_ACC_PAIR
+    if (u == FLUSH - 1) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      sre[r] += (double)pre[r];
-      sim[r] += (double)pim[r];
+      for (int r = 0; r < 16; ++r) {
+        sre[r] += (double)pre[r];
+        sim[r] += (double)pim[r];
+      }
     }
     lstore((kb & 1) ^ 1);
     gload(kb + 2 < nk ? kb + 2 : nk - 1);
     __syncthreads();
+  }
   }
 
   // ---- epilogue, from the FP64 sums (lane: column n, rows of the 32 x 32 tile) ----
@@ -1002,6 +1011,14 @@ hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
   return hipGetLastError();
 }
 
+// k-blocks of 16 columns per FP32 partial sum of the FP64-sum product. Measured
+// on the 4096-state model (whole build against the FP64 build; the product
+// dominates the build's error): 1 -> e_col 3.7e-7, 3.59 ms per product;
+// 2 -> 2.8e-7, 3.07 ms; 4 -> 2.7e-7, 2.94 ms; 8 -> 3.3e-7, 2.86 ms;
+// 16 -> 4.5e-7, 2.85 ms. Fewer FP64 additions per MFMA, and no larger error up
+// to 4.
+constexpr int kAccFlush = 4;
+
 template <int KIND, bool P_F64>
 hipError_t launch_acc(const Bf3Args& g0, int mrows, hipStream_t s) {
   Bf3Args g = g0;
@@ -1010,11 +1027,11 @@ hipError_t launch_acc(const Bf3Args& g0, int mrows, hipStream_t s) {
   // 128-row tiles when they still give every CU a workgroup
   if (mrows % 128 == 0 && (long)(mrows / 128) * g.tiles_n >= 256) {
     g.tiles_m = mrows / 128;
-    hipLaunchKernelGGL((cheb_acc_kernel<128, KIND, P_F64>),
+    hipLaunchKernelGGL((cheb_acc_kernel<128, KIND, P_F64, kAccFlush>),
                        dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(512), 0, s, g);
   } else {
     g.tiles_m = mrows / 64;
-    hipLaunchKernelGGL((cheb_acc_kernel<64, KIND, P_F64>),
+    hipLaunchKernelGGL((cheb_acc_kernel<64, KIND, P_F64, kAccFlush>),
                        dim3(grid_rows(g.tiles_m) * g.tiles_n), dim3(256), 0, s, g);
   }
   return hipGetLastError();
