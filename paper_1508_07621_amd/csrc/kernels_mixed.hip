@@ -876,34 +876,30 @@ __global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
   lstore(0);
   gload(nk > 1 ? 1 : 0);
   __syncthreads();
-  f16v pre = zero, pim = zero;
+  f16v prr = zero, pii = zero, pim = zero;
   for (int kb0 = 0; kb0 < nk; kb0 += FLUSH) {
 #pragma unroll
   for (int u = 0; u < FLUSH; ++u) {
     const int kb = kb0 + u;
     const unsigned char* sb = smem + (kb & 1) * STAGE;
-    bf8 fa[NS], fb[NS], na[3];
+    bf8 fa[NS], fb[NS];
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
       fa[p] = *reinterpret_cast<const bf8*>(sb + p * SA + aoff);
       fb[p] = *reinterpret_cast<const bf8*>(sb + p * SB + boff);
     }
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {  // -Ai pieces: flip the sign bits
-      u32x4 w = __builtin_bit_cast(u32x4, fa[3 + p]);
-      w ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-      na[p] = __builtin_bit_cast(bf8, w);
-    }
-    // pairs (i, j) with i + j <= 2, the two hi x hi products last; the
-    // partial sums start from zero every FLUSH k-blocks
-    pre = mfma32_bf16(fa[2], fb[0], u == 0 ? zero : pre);
+    // pairs (i, j) with i + j <= 2, the two hi x hi products last; Ar Br and
+    // Ai Bi in separate partial sums (Re = their difference, taken in FP32 at
+    // the flush), so no operand needs its sign flipped; the partial sums
+    // start from zero every FLUSH k-blocks
+    prr = mfma32_bf16(fa[2], fb[0], u == 0 ? zero : prr);
     pim = mfma32_bf16(fa[2], fb[3], u == 0 ? zero : pim);
-    pre = mfma32_bf16(na[2], fb[3], pre);
+    pii = mfma32_bf16(fa[5], fb[3], u == 0 ? zero : pii);
     pim = mfma32_bf16(fa[5], fb[0], pim);
 #define FQ_ACC_PAIR(i, j)                          \
-  pre = mfma32_bf16(fa[i], fb[j], pre);            \
-  pre = mfma32_bf16(na[i], fb[3 + (j)], pre);      \
+  prr = mfma32_bf16(fa[i], fb[j], prr);            \
   pim = mfma32_bf16(fa[i], fb[3 + (j)], pim);      \
+  pii = mfma32_bf16(fa[3 + (i)], fb[3 + (j)], pii); \
   pim = mfma32_bf16(fa[3 + (i)], fb[j], pim);
     FQ_ACC_PAIR(1, 1)
     FQ_ACC_PAIR(0, 2)
@@ -914,7 +910,7 @@ __global__ __launch_bounds__(BM * 4) void cheb_acc_kernel(Bf3Args g) {
     if (u == FLUSH - 1) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        sre[r] += (double)pre[r];
+        sre[r] += (double)(prr[r] - pii[r]);
         sim[r] += (double)pim[r];
       }
     }
