@@ -1009,10 +1009,10 @@ hipError_t launch_bf3(const Bf3Args& g0, int mrows, hipStream_t s) {
 
 // k-blocks of 16 columns per FP32 partial sum of the FP64-sum product. Measured
 // on the 4096-state model (whole build against the FP64 build; the product
-// dominates the build's error): 1 -> e_col 3.7e-7, 3.59 ms per product;
-// 2 -> 2.8e-7, 3.07 ms; 4 -> 2.7e-7, 2.94 ms; 8 -> 3.3e-7, 2.86 ms;
-// 16 -> 4.5e-7, 2.85 ms. Fewer FP64 additions per MFMA, and no larger error up
-// to 4.
+// dominates the build's error), with Re in one partial sum: 1 -> e_col 3.7e-7,
+// 3.59 ms per product; 2 -> 2.8e-7, 3.07 ms; 4 -> 2.7e-7, 2.94 ms; 8 -> 3.3e-7,
+// 2.86 ms; 16 -> 4.5e-7, 2.85 ms. With Ar Br and Ai Bi in separate ones:
+// 2 -> 1.9e-7, 2.84 ms; 4 -> 1.9e-7, 2.67 ms; 8 -> 2.4e-7, 2.60 ms.
 constexpr int kAccFlush = 4;
 
 template <int KIND, bool P_F64>
