@@ -332,6 +332,19 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par,
 
 fq_status fq_destroy(fq_ctx* ctx);
 
+/* Replace the drive samples of a context (same layout as fq_params.f_nodes)
+ * and redo what depends on them: the per-step weights of H_eff (Sec. 3),
+ * the spectral interval (a caller's fixed interval is checked against the
+ * new drive, FQ_ERR_SPECTRUM if it no longer contains it; a library interval
+ * is recomputed, reusing the fixed operators' Lanczos extremes), beta, dE, R,
+ * the order L unless fixed, the Bessel coefficients, the mixed-precision
+ * schedule and the device step tables. The operators, commutators and the
+ * workspace are kept, so a sequence of drives (an optimisation loop) costs no
+ * setup beyond this. The gradient tape of the previous build is dropped
+ * (floquet_grad then needs a new build). On any error the context refuses
+ * builds, propagation and gradients (FQ_ERR_STATE) until a call succeeds. */
+fq_status fq_set_drive(fq_ctx* ctx, const double* f_nodes);
+
 /* Setup values (L, R, dE, beta, interval) and the last build's measurements. */
 fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep);
 

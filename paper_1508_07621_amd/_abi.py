@@ -34,7 +34,8 @@ TERM_FORMAT_NAMES = {v: k for k, v in TERM_FORMATS.items()}
 #: every entry point include/floquet.h declares
 EXPORTS = (
     "fq_node_times", "fq_node_times_magnus6", "fq_bessel_weights", "fq_choose_order", "fq_tridiag_extremes",
-    "fq_hermitian_cover", "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_get_report",
+    "fq_hermitian_cover", "fq_workspace_bytes", "fq_create", "fq_destroy", "fq_set_drive",
+    "fq_get_report",
     "floquet_build_UT", "floquet_propagate", "floquet_period_average", "floquet_grad",
     "floquet_build_UT_static", "fq_last_error",
 )
@@ -106,6 +107,7 @@ def lib() -> ctypes.CDLL:
     L.fq_create.argtypes = [POINTER(c_void_p), POINTER(FqSystem), POINTER(FqParams), c_void_p,
                             c_size_t, c_void_p]
     L.fq_destroy.argtypes = [c_void_p]
+    L.fq_set_drive.argtypes = [c_void_p, POINTER(c_double)]
     L.fq_get_report.argtypes = [c_void_p, POINTER(FqReport)]
     L.floquet_build_UT.argtypes = [c_void_p, c_void_p, POINTER(FqReport)]
     L.floquet_propagate.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,

@@ -517,6 +517,20 @@ fq_status lanczos_ritz(fq_ctx* ctx, const Matvec& mv, double* lo, double* hi) {
   return lanczos_extremes(ctx->n, mv, lo, hi);
 }
 
+// Ritz extremes of one of the context's fixed operators (key: its device
+// pointer), computed once per context: fq_set_drive reuses them.
+fq_status cached_ritz(fq_ctx* ctx, const void* key, const Matvec& mv, double* lo, double* hi) {
+  for (const auto& e : ctx->ritz_cache)
+    if (e.first == key) {
+      *lo = e.second.first;
+      *hi = e.second.second;
+      return FQ_OK;
+    }
+  FQ_TRY(lanczos_ritz(ctx, mv, lo, hi));
+  ctx->ritz_cache.push_back({key, {*lo, *hi}});
+  return FQ_OK;
+}
+
 // Outer estimate of the union of spec(H_eff,k): Weyl's inequalities on the
 // Lanczos extremes of H0 and Hmod (each widened by `margin` of its spread, as
 // Ritz values approach the ends from inside) and ||K||_2 <= 2 ||H0|| ||Hmod||.
@@ -532,7 +546,7 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
     l0 = *std::min_element(e.begin(), e.end());
     h0 = *std::max_element(e.begin(), e.end());
   } else {
-    st = lanczos_ritz(ctx, mh0, &l0, &h0);
+    st = cached_ritz(ctx, ctx->sys.h0, mh0, &l0, &h0);
     if (st != FQ_OK) return st;
   }
   if (ctx->S > 1) {
@@ -548,7 +562,7 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
       Matvec md = [&](const std::vector<cd>& x, std::vector<cd>& y) {
         return device_matvec(ctx, ctx->sys.hmods[d], x, y);
       };
-      FQ_TRY(lanczos_ritz(ctx, md, &ls[d], &hs[d]));
+      FQ_TRY(cached_ritz(ctx, ctx->sys.hmods[d], md, &ls[d], &hs[d]));
       const double wd = hs[d] - ls[d];
       ls[d] -= margin * wd;
       hs[d] += margin * wd;
@@ -580,7 +594,7 @@ fq_status dense_cover(fq_ctx* ctx, double* lo_out, double* hi_out, double margin
     *hi_out = hi;
     return FQ_OK;
   }
-  st = lanczos_ritz(ctx, mv, &lv, &hv);
+  st = cached_ritz(ctx, ctx->sys.hmod, mv, &lv, &hv);
   if (st != FQ_OK) return st;
   const double w0 = h0 - l0, wv = hv - lv;
   l0 -= margin * w0;
@@ -902,12 +916,12 @@ double term_error(int tf, long nk) {
 // the whole target and shrinking until the total meets it; FP64 terms are then
 // extended to a leading run (the step converts from FP64 planes to the low
 // format once).
-void choose_schedule(fq_ctx* c, const fq_params* par) {
+void choose_schedule(fq_ctx* c) {
   const int L = c->L;
   const bool f32 = c->precision == FQ_FP32;
   c->term_fmt.assign(L + 1, f32 ? fq::TF_F32 : fq::TF_X3);
   const long nk = c->np / 16;
-  const double tol = par->mixed_tol > 0 ? par->mixed_tol : kMixedTolDefault;
+  const double tol = c->mixed_tol > 0 ? c->mixed_tol : kMixedTolDefault;
   const double sm = std::sqrt((double)c->M);
   // An error in P_l also enters every later term through the recurrence, as a
   // Chebyshev polynomial of the second kind of degree l' - l (norm at most
@@ -926,9 +940,9 @@ void choose_schedule(fq_ctx* c, const fq_params* par) {
     }
     return std::sqrt(e2);
   };
-  if (par->n_term_formats > 0) {
-    for (int l = 1; l <= L; ++l)
-      c->term_fmt[l] = par->term_formats[std::min(l, par->n_term_formats) - 1];
+  const int nf = (int)c->term_formats.size();
+  if (nf > 0) {
+    for (int l = 1; l <= L; ++l) c->term_fmt[l] = c->term_formats[std::min(l, nf) - 1];
   } else {
     double allowance = tol;
     for (int pass = 0; pass < 64; ++pass, allowance *= 0.7) {
@@ -1814,45 +1828,13 @@ fq_status fq_workspace_bytes(const fq_system* sys, const fq_params* par, size_t*
   return FQ_OK;
 }
 
-fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, void* workspace,
-                    size_t ws_bytes, void* stream) {
-  if (!out) return fail(FQ_ERR_ARG, "out is null");
-  *out = nullptr;
-  fq_status st = validate(sys, par);
-  if (st != FQ_OK) return st;
-  const Layout lay = plan(sys, par);
-  if (!workspace) return fail(FQ_ERR_ARG, "workspace is null");
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-    return fail(FQ_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
-  if (ws_bytes < lay.total)
-    return fail(FQ_ERR_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
-
-  fq_ctx* c = new (std::nothrow) fq_ctx();
-  if (!c) return fail(FQ_ERR_ARG, "out of host memory");
-  c->n = sys->n;
-  c->layout = dense_like(sys->layout) ? FQ_DENSE : sys->layout;
-  c->h0_eigen = sys->layout == FQ_DENSE_EIGEN;
-  c->sys = *sys;
-  c->T = par->T;
-  c->spp = substeps_per_step(par->scheme);
-  c->M_user = par->M;
-  c->M = par->M * c->spp;
-  c->h = par->T / c->M;
-  c->tol = par->tol;
-  c->precision = par->precision;
-  c->ckpt = par->checkpoint_every * c->spp;
-  c->profile = par->profile != 0;
-  c->reortho = par->reorthonormalize != 0;
-  c->c64 = par->dtype == FQ_C64;
-  {
-    const char* e = std::getenv("FQ_SMALL_CHAIN");
-    c->small_chain = !(e && e[0] == '0' && e[1] == 0);
-  }
-  c->scheme = par->scheme;
-  c->pair_sums = par->grad_pair_sums == 1;
-  c->S = drive_terms(sys);
-  c->J = drive_block(c->S, par->scheme);
-  c->f_nodes.assign(par->f_nodes, par->f_nodes + nodes_per_step(par->scheme) * par->M * c->S);
+// Everything that follows from the drive samples: the per-(sub)step weights,
+// the spectral interval (the caller's, checked against the drive's bounds, or
+// the library's cover), beta, dE, R, the order L (unless fixed), the Bessel
+// coefficients, the mixed schedule, the step phase, and the device step
+// tables. Run by fq_create and again by fq_set_drive.
+fq_status apply_drive(fq_ctx* c, const double* f_nodes) {
+  c->f_nodes.assign(f_nodes, f_nodes + nodes_per_step(c->scheme) * c->M_user * c->S);
   // per (sub)step: H_eff = H0 + a Hmod + b K
   c->a.resize(c->M);
   c->b.resize(c->M);
@@ -1904,6 +1886,115 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
       c->b[k] = std::sqrt(3.0) * c->h * (f1 - f2) / 12.0;
     }
   }
+  // spectral interval
+  double lo, hi;
+  const bool given = c->interval_given;
+  fq_status st;
+  if (c->layout == FQ_DENSE)
+    st = given ? dense_inner_bounds(c, &lo, &hi) : dense_cover(c, &lo, &hi, kDenseMargin);
+  else
+    st = tridiag_cover(c, &lo, &hi);
+  if (st != FQ_OK) return st;
+  if (given) {
+    const double slack = 1e-9 * std::max({1.0, std::fabs(lo), std::fabs(hi)});
+    if (c->e_min_given > lo + slack || c->e_max_given < hi - slack)
+      return fail(FQ_ERR_SPECTRUM,
+                  "interval [%.17g, %.17g] does not contain the bounds [%.17g, %.17g]",
+                  c->e_min_given, c->e_max_given, lo, hi);
+    lo = c->e_min_given;
+    hi = c->e_max_given;
+  }
+  if (!(hi > lo)) {  // a constant H: any positive half-width gives the exact phase
+    const double s = std::max(1.0, std::fabs(lo)) * 1e-8;
+    lo -= s;
+    hi += s;
+  }
+  c->e_min = lo;
+  c->e_max = hi;
+  c->beta = 0.5 * (hi + lo);
+  c->dE = 0.5 * (hi - lo);
+  c->R = c->h * c->dE;
+  if (c->L_given > 0) {
+    c->L = c->L_given;
+  } else {
+    c->L = fq::choose_order(c->R, c->tol);
+    if (c->L < 1 || c->L > kMaxOrder)
+      return fail(FQ_ERR_UNSUPPORTED, "required Chebyshev order exceeds %d (R = %g)", kMaxOrder, c->R);
+  }
+  std::vector<double> j;
+  fq::bessel_j_table(c->R, c->L, j);
+  c->weights.resize(c->L + 1);
+  c->coef.resize(2 * (c->L + 1));
+  for (int l = 0; l <= c->L; ++l) {
+    const double w = (l == 0 ? 1.0 : 2.0) * j[l];
+    c->weights[l] = w;
+    // (-i)^l w
+    const int q = l & 3;
+    c->coef[2 * l] = (q == 0) ? w : (q == 2 ? -w : 0.0);
+    c->coef[2 * l + 1] = (q == 1) ? -w : (q == 3 ? w : 0.0);
+  }
+  if (c->precision != FQ_FP64 && c->layout == FQ_DENSE) choose_schedule(c);
+  c->phr = std::cos(c->beta * c->h);
+  c->phi = -std::sin(c->beta * c->h);
+  std::vector<double> ab(2 * c->M);
+  for (int k = 0; k < c->M; ++k) {
+    ab[2 * k] = c->a[k];
+    ab[2 * k + 1] = c->b[k];
+  }
+  if (hipMemcpyAsync(c->d_ab, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(FQ_ERR_HIP, "upload of the step tables failed");
+  c->tape_valid = false;
+  fill_report(c);
+  return FQ_OK;
+}
+
+fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  if (!out) return fail(FQ_ERR_ARG, "out is null");
+  *out = nullptr;
+  fq_status st = validate(sys, par);
+  if (st != FQ_OK) return st;
+  const Layout lay = plan(sys, par);
+  if (!workspace) return fail(FQ_ERR_ARG, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(FQ_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (ws_bytes < lay.total)
+    return fail(FQ_ERR_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
+
+  fq_ctx* c = new (std::nothrow) fq_ctx();
+  if (!c) return fail(FQ_ERR_ARG, "out of host memory");
+  c->n = sys->n;
+  c->layout = dense_like(sys->layout) ? FQ_DENSE : sys->layout;
+  c->h0_eigen = sys->layout == FQ_DENSE_EIGEN;
+  c->sys = *sys;
+  c->T = par->T;
+  c->spp = substeps_per_step(par->scheme);
+  c->M_user = par->M;
+  c->M = par->M * c->spp;
+  c->h = par->T / c->M;
+  c->tol = par->tol;
+  c->precision = par->precision;
+  c->ckpt = par->checkpoint_every * c->spp;
+  c->profile = par->profile != 0;
+  c->reortho = par->reorthonormalize != 0;
+  c->c64 = par->dtype == FQ_C64;
+  {
+    const char* e = std::getenv("FQ_SMALL_CHAIN");
+    c->small_chain = !(e && e[0] == '0' && e[1] == 0);
+  }
+  c->scheme = par->scheme;
+  c->pair_sums = par->grad_pair_sums == 1;
+  c->S = drive_terms(sys);
+  c->J = drive_block(c->S, par->scheme);
+  c->mixed_tol = par->mixed_tol;
+  if (par->n_term_formats > 0)
+    c->term_formats.assign(par->term_formats, par->term_formats + par->n_term_formats);
+  c->interval_given = !std::isnan(par->e_min);
+  c->e_min_given = par->e_min;
+  c->e_max_given = par->e_max;
+  c->L_given = par->L;
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->ws = reinterpret_cast<char*>(workspace);
   c->ws_bytes = ws_bytes;
@@ -2005,66 +2096,8 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
     }
   }
 
-  // spectral interval
-  double lo, hi;
-  const bool given = !std::isnan(par->e_min);
-  if (dense_like(sys->layout)) {
-    st = given ? dense_inner_bounds(c, &lo, &hi) : dense_cover(c, &lo, &hi, kDenseMargin);
-  } else {
-    st = tridiag_cover(c, &lo, &hi);
-  }
+  st = apply_drive(c, par->f_nodes);
   if (st != FQ_OK) return bail(st);
-  if (given) {
-    const double slack = 1e-9 * std::max({1.0, std::fabs(lo), std::fabs(hi)});
-    if (par->e_min > lo + slack || par->e_max < hi - slack)
-      return bail(fail(FQ_ERR_SPECTRUM,
-                       "interval [%.17g, %.17g] does not contain the bounds [%.17g, %.17g]",
-                       par->e_min, par->e_max, lo, hi));
-    lo = par->e_min;
-    hi = par->e_max;
-  }
-  if (!(hi > lo)) {  // a constant H: any positive half-width gives the exact phase
-    const double s = std::max(1.0, std::fabs(lo)) * 1e-8;
-    lo -= s;
-    hi += s;
-  }
-  c->e_min = lo;
-  c->e_max = hi;
-  c->beta = 0.5 * (hi + lo);
-  c->dE = 0.5 * (hi - lo);
-  c->R = c->h * c->dE;
-  if (par->L > 0) {
-    c->L = par->L;
-  } else {
-    c->L = fq::choose_order(c->R, par->tol);
-    if (c->L < 1 || c->L > kMaxOrder)
-      return bail(fail(FQ_ERR_UNSUPPORTED, "required Chebyshev order exceeds %d (R = %g)", kMaxOrder, c->R));
-  }
-  std::vector<double> j;
-  fq::bessel_j_table(c->R, c->L, j);
-  c->weights.resize(c->L + 1);
-  c->coef.resize(2 * (c->L + 1));
-  for (int l = 0; l <= c->L; ++l) {
-    const double w = (l == 0 ? 1.0 : 2.0) * j[l];
-    c->weights[l] = w;
-    // (-i)^l w
-    const int q = l & 3;
-    c->coef[2 * l] = (q == 0) ? w : (q == 2 ? -w : 0.0);
-    c->coef[2 * l + 1] = (q == 1) ? -w : (q == 3 ? w : 0.0);
-  }
-  if (c->precision != FQ_FP64 && c->layout == FQ_DENSE) choose_schedule(c, par);
-  c->phr = std::cos(c->beta * c->h);
-  c->phi = -std::sin(c->beta * c->h);
-  std::vector<double> ab(2 * c->M);
-  for (int k = 0; k < c->M; ++k) {
-    ab[2 * k] = c->a[k];
-    ab[2 * k + 1] = c->b[k];
-  }
-  if (hipMemcpyAsync(c->d_ab, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
-    return bail(fail(FQ_ERR_HIP, "upload of the step tables failed"));
-  fill_report(c);
   *out = c;
   return FQ_OK;
 }
@@ -2072,6 +2105,17 @@ fq_status fq_create(fq_ctx** out, const fq_system* sys, const fq_params* par, vo
 fq_status fq_destroy(fq_ctx* ctx) {
   delete ctx;
   return FQ_OK;
+}
+
+fq_status fq_set_drive(fq_ctx* c, const double* f_nodes) {
+  if (!c || !f_nodes) return fail(FQ_ERR_ARG, "null argument");
+  if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  const long cnt = (long)nodes_per_step(c->scheme) * c->M_user * c->S;
+  for (long i = 0; i < cnt; ++i)
+    if (!is_finite(f_nodes[i])) return fail(FQ_ERR_NONFINITE, "f_nodes[%ld] is not finite", i);
+  const fq_status st = apply_drive(c, f_nodes);
+  c->drive_ok = st == FQ_OK;
+  return st;
 }
 
 fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep) {
@@ -2083,6 +2127,7 @@ fq_status fq_get_report(const fq_ctx* ctx, fq_report* rep) {
 fq_status floquet_build_UT(fq_ctx* c, void* U_out, fq_report* rep) {
   if (!c || !U_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  if (!c->drive_ok) return fail(FQ_ERR_STATE, "the last fq_set_drive failed: set a valid drive first");
   // The build's two timing events live with the context (created once, freed
   // by fq_destroy), so that no return path leaks them.
   if (c->timed && !c->build_ev[0]) {
@@ -2144,6 +2189,7 @@ fq_status floquet_propagate(fq_ctx* c, const void* X0, int64_t ncols, int32_t k0
                             void* X_out, void* snapshots, int32_t snap_every) {
   if (!c || !X0 || !X_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  if (!c->drive_ok) return fail(FQ_ERR_STATE, "the last fq_set_drive failed: set a valid drive first");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
   if (k0 < 0 || k1 < k0 || k1 > c->M_user) return fail(FQ_ERR_ARG, "need 0 <= k0 <= k1 <= M");
   if (snapshots && snap_every < 1) return fail(FQ_ERR_ARG, "snap_every must be >= 1 with snapshots");
@@ -2193,6 +2239,7 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
                                  double* avg_out) {
   if (!c || !X0 || !f_grid || !avg_out) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  if (!c->drive_ok) return fail(FQ_ERR_STATE, "the last fq_set_drive failed: set a valid drive first");
   if (ncols < 1 || ncols > c->n) return fail(FQ_ERR_ARG, "ncols must be in [1, n]");
   for (int k = 0; k < c->M_user * c->S; ++k)
     if (!is_finite(f_grid[k])) return fail(FQ_ERR_NONFINITE, "f_grid[%d] is not finite", k);
@@ -2248,6 +2295,7 @@ fq_status floquet_period_average(fq_ctx* c, const void* X0, int64_t ncols, const
 fq_status floquet_grad(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   if (!c || !U_bar || !grad_f_nodes) return fail(FQ_ERR_ARG, "null argument");
   if (c->broken) return fail(FQ_ERR_HIP, "context unusable after an earlier HIP failure");
+  if (!c->drive_ok) return fail(FQ_ERR_STATE, "the last fq_set_drive failed: set a valid drive first");
   if (c->ckpt <= 0) return fail(FQ_ERR_STATE, "context was created without a gradient tape");
   if (!c->tape_valid) return fail(FQ_ERR_STATE, "no tape: call floquet_build_UT first");
   if (c->layout == FQ_TRIDIAG) return tridiag_adjoint(c, U_bar, grad_f_nodes);

@@ -377,6 +377,15 @@ struct fq_ctx {
   // (s < t)]; wS (M x J) are the per-(sub)step weights of the B_j when S >= 2.
   int S = 1, J = 2;
   bool pair_sums = false;             // floquet_grad: node-pair sums only (no K contraction)
+  // the parameters the drive-dependent setup needs again on fq_set_drive
+  double mixed_tol = 0.0;
+  std::vector<int> term_formats;      // caller's term formats (empty: the library's schedule)
+  bool interval_given = false;        // the caller fixed [e_min, e_max]
+  double e_min_given = 0.0, e_max_given = 0.0;
+  int L_given = 0;                    // the caller fixed L (> 0)
+  bool drive_ok = true;               // false after a failed fq_set_drive
+  // Ritz extremes of the fixed operators (H0, Hmod, ...), by operator pointer
+  std::vector<std::pair<const void*, std::pair<double, double>>> ritz_cache;
   std::vector<double> wS;
   std::vector<double> w6;             // M x 9
   double* comm6 = nullptr;

@@ -225,6 +225,7 @@ class FloquetContext:
         """U_T as an n x n tensor of the context's dtype ([i, j] = <i|U_T|j>)."""
         import ctypes
         torch = _torch()
+        self.generation = getattr(self, "generation", 0) + 1  # the tape this build records
         if out is None:
             out = torch.empty((self.n, self.n), dtype=self.state_dtype, device=self.device)
         if out.dtype != self.state_dtype or not out.is_contiguous():
@@ -282,6 +283,19 @@ class FloquetContext:
         with torch.cuda.device(self.device):
             check(lib().floquet_grad(self._ctx, ub.data_ptr(), dptr(g)))
         return g.reshape(self.M, 2) if self.S == 1 else g.reshape(self.M, 2, self.S)
+
+    def set_drive(self, f_nodes):
+        """New drive samples (same shape as at creation) for this context:
+        fq_set_drive redoes the drive-dependent setup and keeps the operators,
+        their commutators and the workspace. Drops the gradient tape."""
+        f = np.ascontiguousarray(np.asarray(f_nodes, dtype=np.float64).reshape(-1))
+        if f.size != self._f.size:
+            raise ValueError(f"f_nodes must hold {self._f.size} values")
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            check(lib().fq_set_drive(self._ctx, dptr(f)))
+        self._f = f
+        self.generation = getattr(self, "generation", 0) + 1
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -348,23 +362,42 @@ def floquet_build_UT_static(out=None, **kw):
 
 class FloquetUT:
     """torch.autograd.Function wrapper: forward builds U_T with a tape,
-    backward returns d loss / d f_nodes through floquet_grad."""
+    backward returns d loss / d f_nodes through floquet_grad.
+
+    apply(f_nodes, context=ctx) reuses one FloquetContext (created with
+    checkpoint_every > 0) across calls: each forward sets the context's drive
+    (fq_set_drive) and builds, so the operator setup runs once. A backward must
+    then come before the context's next build (its tape is the last build's);
+    otherwise it raises. Without a context each forward creates its own from
+    the keyword arguments."""
 
     @staticmethod
-    def apply(f_nodes, **kw):
+    def apply(f_nodes, context=None, **kw):
         torch = _torch()
 
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(ctx_, f):
-                c = FloquetContext(f_nodes=f.detach().cpu().numpy(), **kw)
+                fn = f.detach().cpu().numpy()
+                if context is None:
+                    c = FloquetContext(f_nodes=fn, **kw)
+                else:
+                    c = context
+                    c.set_drive(fn)
                 ctx_.fq = c
-                return c.build_ut()
+                U = c.build_ut()
+                ctx_.generation = c.generation
+                return U
 
             @staticmethod
             def backward(ctx_, gU):
-                g = ctx_.fq.grad(gU)
-                ctx_.fq.close()
+                c = ctx_.fq
+                if c.generation != ctx_.generation:
+                    raise RuntimeError("the context was rebuilt after this forward: its "
+                                       "gradient tape belongs to a later build")
+                g = c.grad(gU)
+                if context is None:
+                    c.close()
                 return torch.from_numpy(g).to(device=f_nodes.device,
                                               dtype=f_nodes.dtype).reshape(f_nodes.shape)
 

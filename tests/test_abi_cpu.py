@@ -433,6 +433,11 @@ def test_schedule_arguments_rejected():
     assert _ws(_dense(), p)[0] == _abi.FQ_ERR_ARG
 
 
+def test_set_drive_rejects_null_arguments():
+    f = np.zeros(8)
+    assert _abi.lib().fq_set_drive(None, _abi.dptr(f)) == _abi.FQ_ERR_ARG
+
+
 def test_grad_pair_sums_flag_values():
     for v, want in ((0, _abi.FQ_OK), (1, _abi.FQ_OK), (2, _abi.FQ_ERR_ARG), (-1, _abi.FQ_ERR_ARG)):
         for sysd in (_dense(), _tridiag()):
