@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "context.h"
 
 using fq::ChebTerm;
 
