@@ -1628,6 +1628,9 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
       FQ_HIP(c, fq::launch_tridiag_adj_table(p, k, k == M - 1, tab, c->stream));
       p.lam = lam[lam_cur];
       p.lam_out = lam[lam_cur ^ 1];
+      // without the K contraction the passes read Lambda' = f Lambda (f of
+      // the step's table), formed once here in place
+      if (!with_k) FQ_HIP(c, fq::launch_tridiag_lam_gauge(p, tab, lam[lam_cur], c->stream));
       p.seg = seg(k - k0);
       p.grad = c->d_grad + 2 * (size_t)fq::kAdjSlots * (size_t)k;
       int rc = 0;
@@ -1637,7 +1640,8 @@ fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_
         p.in = rset[rc];
         p.out = rset[rc ^ 1];
         FQ_MARK(c, FQ_K_ADJ_REV);
-        FQ_HIP(c, fq::launch_tridiag_adj_stream(p, tab, with_k, c->stream));
+        FQ_HIP(c, with_k ? fq::launch_tridiag_adj_stream(p, tab, true, c->stream)
+                         : fq::launch_tridiag_adj_persist(p, tab, c->stream));
         rc ^= 1;
       }
       lam_cur ^= 1;

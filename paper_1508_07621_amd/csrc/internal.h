@@ -326,7 +326,7 @@ struct TridiagAdjStream {
   const double* gauge;        // M x n complex: w_k
   double a, b, beta, inv_dE;  // step scalars
   // pass state
-  const double* lam;          // 2 planes (re, im): Lambda before the table's factor
+  const double* lam;          // 2 planes (re, im): Lambda before the table's factor (after it: persistent pass)
   const double* seg;          // hi == L-1: P_{L-1}, P_L of the step (4 planes [l & 1][part])
   const double* in;           // hi < L-1: 8 planes [role][part]: P_l, P_{l+1}, Pbar_{l+1}, Pbar_{l+2}
   double* out;                // lo > 0: the same for the next launch (terms from lo - 1)
@@ -342,6 +342,13 @@ hipError_t launch_tridiag_lam_pack(const void* ubar, bool c64, long n, long ncol
                                    double* out, hipStream_t s);
 hipError_t launch_tridiag_adj_stream(const TridiagAdjStream& p, const double* tab, bool with_k,
                                      hipStream_t s);
+// Lambda' = f Lambda in place (both planes), f the table's Lambda factor.
+hipError_t launch_tridiag_lam_gauge(const TridiagAdjStream& p, const double* tab, double* lam,
+                                    hipStream_t s);
+// The reverse pass without the K contraction in its persistent form; p.lam
+// holds Lambda' (launch_tridiag_lam_gauge), not Lambda.
+hipError_t launch_tridiag_adj_persist(const TridiagAdjStream& p, const double* tab,
+                                      hipStream_t s);
 hipError_t launch_tridiag_stream(const TridiagJob& job, const TridiagStream& st, hipStream_t s);
 
 // Unit gauge factors of step s (host FP64): w_0 = 1, w_{i+1} = w_i conj(u_i) with

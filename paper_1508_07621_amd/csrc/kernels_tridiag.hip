@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
 
   const bool first = p.hi == p.L - 1;
   if (first) {  // P_{L-1}, P_L from the recompute; Pbar_L = d_L Lambda~, Pbar_{L+1} = 0
-    const double2 cL = c_s[0];
+    const double2 cL = coef[p.L];
     const bool odd = p.L & 1;
     const double cs = odd ? sgn * cL.y : cL.x;
     const double* sx = p.seg + ((((p.L - 1) & 1) * 2 + part) * plane) + off;
@@ -1264,6 +1264,249 @@ __global__ __launch_bounds__(128) void tridiag_adj_stream_kernel(TridiagAdjStrea
   }
 }
 
+// Lambda' = f Lambda in place over both planes (n16 x ncols each), with f the
+// Lambda factor of the step's table (zero on the padding rows n .. n16-1).
+__global__ __launch_bounds__(256) void tridiag_lam_gauge_kernel(long n16, long plane,
+                                                                const double* __restrict__ tab,
+                                                                double* lam) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= plane) return;
+  const long at = t % n16;
+  const double fr = tab[3 * n16 + at], fi = tab[4 * n16 + at];
+  const double ar = lam[t], ai = lam[plane + t];
+  lam[t] = fr * ar - fi * ai;
+  lam[plane + t] = fr * ai + fi * ar;
+}
+
+// The reverse pass without the K contraction (node-pair sums), persistent: a
+// workgroup (one wave per part, as in tridiag_adj_stream_kernel) walks the
+// items it, it + G, it + 2G, ... of the pass (item = window blk x column, blk =
+// it / ncols), so consecutive items mostly share their window and the rows of
+// 2 G stay in registers. While an item's terms run, the next item's state
+// planes of the wave's part travel from HBM into LDS by direct global-to-LDS
+// loads (no registers), one dword per lane and load; the coefficients come
+// through the scalar cache, so nothing else in the term loop touches LDS or
+// the vector memory pipeline. Lambda arrives already multiplied by its gauge
+// factor (tridiag_lam_gauge_kernel), and each wave adds its V sums into the
+// step's slot once, at the end.
+template <bool HI_ODD>
+__global__ __launch_bounds__(128) void tridiag_adj_persist_kernel(TridiagAdjStream p,
+                                                                  const double* __restrict__ tab,
+                                                                  const double2* __restrict__ coef) {
+  constexpr int R = 16;
+  // the next item's X, Z, PB, O of each part: [part][plane][row r][lane]
+  __shared__ __attribute__((aligned(16))) double pf[2][4][R][64];
+
+  const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const long n = p.n, n16 = p.n16, nq = n16 >> 4, plane = p.plane;
+  const long items = p.ncols * p.nblk;
+  const bool first = p.hi == p.L - 1;
+  const int npf = first ? 2 : 4;  // planes that come from memory: X, Z (and PB, O)
+  const double sgn = part == 0 ? 1.0 : -1.0;
+  const int lmin = p.lo > 1 ? p.lo : 1;
+  // plane a (0..3: X, Z, PB, O) of this part
+  auto src_plane = [&](int a) -> const double* {
+    if (first) return p.seg + ((((a == 0 ? p.L - 1 : p.L) & 1) * 2 + part) * plane);
+    return p.in + (part + 2 * a) * plane;
+  };
+  // the direct loads of item it2 into pf: lane l takes dword l & 1 of the
+  // lane-(32 h + l / 2) element of every row and plane (row groups outside the
+  // column skipped; they are masked where pf is read)
+  auto prefetch = [&](long it2) {
+    const long blk2 = it2 / p.ncols, col2 = it2 % p.ncols;
+    const long q2 = (blk2 * p.B - p.K) / 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const long qe = q2 + 32 * h + (lane >> 1);
+      if (qe >= 0 && qe < nq) {
+        const long e = col2 * n16 + qe;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a >= npf) break;
+          const unsigned* s = reinterpret_cast<const unsigned*>(src_plane(a) + e) + (lane & 1);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            __builtin_amdgcn_global_load_lds(s + 2 * r * nq, &pf[part][a][r][32 * h], 4, 0, 0);
+        }
+      }
+    }
+  };
+
+  double d2r[R], g2[R], gm2 = 0.0;
+  long tblk = -1;
+  double gsum = 0.0;  // this lane's share of the V sums over its items
+
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const long blk = it / p.ncols, col = it % p.ncols;
+    const long a0 = blk * p.B;
+    const long q = (a0 - p.K) / 16 + lane;  // row group of this lane (may be < 0)
+    const long base = q * 16;
+    const long off = col * n16 + q;
+    auto in_col = [&](int r) { return base + r >= 0 && base + r < n; };
+    const bool own_lane = base >= a0 && base < a0 + p.B;
+    if (blk != tblk) {  // rows of 2 G for this window
+      const double* tq = tab + q;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool ok = in_col(r);
+        d2r[r] = ok ? tq[r * nq] : 0.0;
+        g2[r] = ok ? tq[n16 + r * nq] : 0.0;
+      }
+      gm2 = (base >= 1 && base < n) ? tq[n16 + (long)(R - 1) * nq - 1] : 0.0;
+      tblk = blk;
+    }
+    // Lambda' of this part and of the other
+    double lam_o[R], lam_x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ok = in_col(r);
+      lam_o[r] = ok ? p.lam[part * plane + off + r * nq] : 0.0;
+      lam_x[r] = ok ? p.lam[(1 - part) * plane + off + r * nq] : 0.0;
+    }
+    double x[R], z[R], pb[R], o[R], sv[R];
+    if (it != (long)blockIdx.x) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the direct loads have landed
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool ok = in_col(r);
+        x[r] = ok ? pf[part][0][r][lane] : 0.0;
+        z[r] = ok ? pf[part][1][r][lane] : 0.0;
+        if (!first) {
+          pb[r] = ok ? pf[part][2][r][lane] : 0.0;
+          o[r] = ok ? pf[part][3][r][lane] : 0.0;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool ok = in_col(r);
+        const double* v = src_plane(0) + off + r * nq;
+        x[r] = ok ? v[0] : 0.0;
+        z[r] = ok ? src_plane(1)[off + r * nq] : 0.0;
+        if (!first) {
+          pb[r] = ok ? src_plane(2)[off + r * nq] : 0.0;
+          o[r] = ok ? src_plane(3)[off + r * nq] : 0.0;
+        }
+      }
+    }
+    if (first) {  // Pbar_L = d_L Lambda~, Pbar_{L+1} = 0
+      const double2 cL = coef[p.L];
+      const bool odd = p.L & 1;
+      const double cs = odd ? sgn * cL.y : cL.x;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        pb[r] = cs * (odd ? lam_x[r] : lam_o[r]);
+        o[r] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) sv[r] = 0.0;
+    // the pf reads are complete before the next item's loads overwrite pf
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    if (it + (long)gridDim.x < items) prefetch(it + gridDim.x);
+
+    // One term l >= 1 of parity P::value: Pbar_l = 2 G PB - O + d_l Lambda~
+    // into O, P_{l-1} = 2 G X - Z into Z, the V sums; L0: the term l = 0.
+    // cl = c_l (uniform; its real part for even l, imaginary for odd l)
+    auto term = [&](auto par, const double* X, double* Z, const double* PB, double* O,
+                    double2 cl, bool L0) {
+      constexpr bool ODD = decltype(par)::value;
+      const double cs = ODD ? sgn * cl.y : cl.x;
+      const double xu = prev_lane_or_zero(X[R - 1]), xd = next_lane_or_zero(X[0]);
+      const double pu = prev_lane_or_zero(PB[R - 1]), pd = next_lane_or_zero(PB[0]);
+      const double hw = L0 ? 0.5 : 1.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) sv[r] = fma(hw * PB[r], X[r], sv[r]);
+      if (!L0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double lo = r > 0 ? X[r - 1] : xu, hi = r < R - 1 ? X[r + 1] : xd;
+          const double gl = r > 0 ? g2[r - 1] : gm2;
+          double t = fma(d2r[r], X[r], -Z[r]);
+          t = fma(gl, lo, t);
+          Z[r] = fma(g2[r], hi, t);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double lo = r > 0 ? PB[r - 1] : pu, hi = r < R - 1 ? PB[r + 1] : pd;
+          const double gl = r > 0 ? g2[r - 1] : gm2;
+          double t = fma(d2r[r], PB[r], -O[r]);
+          t = fma(gl, lo, t);
+          t = fma(g2[r], hi, t);
+          O[r] = fma(cs, ODD ? lam_x[r] : lam_o[r], t);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double lo = r > 0 ? PB[r - 1] : pu, hi = r < R - 1 ? PB[r + 1] : pd;
+          const double gl = r > 0 ? g2[r - 1] : gm2;
+          double hh = d2r[r] * PB[r];
+          hh = fma(gl, lo, hh);
+          hh = fma(g2[r], hi, hh);
+          const double t = fma(0.5, hh, -O[r]);
+          O[r] = fma(cs, ODD ? lam_x[r] : lam_o[r], t);
+        }
+      }
+    };
+    auto finish = [&](double* X, double* Z, double* PB, double* O) {
+      if (p.lo == 0) term(Parity<0>{}, X, Z, PB, O, coef[0], true);
+      long off2 = off;
+      asm volatile("" : "+v"(off2));
+      if (!own_lane) return;
+      if (p.lo == 0) {
+        double* v = p.lam_out + part * plane + off2;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (base + r < n) v[r * nq] = O[r];
+      } else {
+        double* v = p.out + part * plane + off2;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (base + r < n) {
+            v[r * nq] = X[r];
+            v[2 * plane + r * nq] = Z[r];
+            v[4 * plane + r * nq] = PB[r];
+            v[6 * plane + r * nq] = O[r];
+          }
+        }
+      }
+    };
+    // the coefficients of the next pair are loaded one pair ahead, so the
+    // scalar loads' latency hides behind a pair of terms
+    auto run = [&](double* X, double* Z, double* PB, double* O, int l) {
+      double2 ca = coef[l], cb = coef[l >= 1 ? l - 1 : 0];
+      for (; l - 1 >= lmin; l -= 2) {
+        const double2 na = coef[l >= 2 ? l - 2 : 0], nb = coef[l >= 3 ? l - 3 : 0];
+        term(Parity<0>{}, X, Z, PB, O, ca, false);
+        term(Parity<1>{}, Z, X, O, PB, cb, false);
+        ca = na;
+        cb = nb;
+      }
+      if (l >= lmin) {
+        term(Parity<0>{}, X, Z, PB, O, ca, false);
+        finish(Z, X, O, PB);
+      } else {
+        finish(X, Z, PB, O);
+      }
+    };
+    if constexpr (HI_ODD) {
+      term(Parity<1>{}, x, z, pb, o, coef[p.hi], false);
+      run(z, x, o, pb, p.hi - 1);
+    } else {
+      run(x, z, pb, o, p.hi);
+    }
+    if (own_lane) {
+      const double* vq = tab + 2 * n16 + q;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (base + r < n) gsum = fma(vq[r * nq], sv[r], gsum);
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) gsum += __shfl_xor(gsum, m);
+  if (lane == 0) atomicAdd(p.grad + 2 * (blockIdx.x % kAdjSlots), 2.0 * gsum);
+}
+
 }  // namespace
 
 // 16 rows per lane and up to 4 waves per part (512 threads, <= 256 VGPRs).
@@ -1433,6 +1676,50 @@ hipError_t launch_tridiag_adj_stream(const TridiagAdjStream& p, const double* ta
     hipLaunchKernelGGL((tridiag_adj_stream_kernel<false, true>), g, b, 0, s, p, tab, coef);
   else
     hipLaunchKernelGGL((tridiag_adj_stream_kernel<false, false>), g, b, 0, s, p, tab, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag_lam_gauge(const TridiagAdjStream& p, const double* tab, double* lam,
+                                    hipStream_t s) {
+  const long blocks = (p.plane + 255) / 256;
+  if (p.n16 < 16 || p.plane < p.n16 || p.plane % p.n16 || !tab || !lam || blocks > 0x7fffffffL)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_lam_gauge_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p.n16,
+                     p.plane, tab, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag_adj_persist(const TridiagAdjStream& p, const double* tab,
+                                      hipStream_t s) {
+  const long items = p.ncols * p.nblk;
+  if (p.n < 1 || p.ncols < 1 || p.K < 16 || p.K % 16 || p.B < 16 || p.B % 16 ||
+      p.B + 2L * p.K != tridiag_stream_rows(1) || p.nblk != (p.n + p.B - 1) / p.B ||
+      p.n16 != (p.n + 15) / 16 * 16 || p.plane < p.n16 * p.ncols || p.L < 1 || p.lo < 0 ||
+      p.hi < p.lo || p.hi > p.L - 1 || p.hi - p.lo + 1 > p.K || items > 0x7fffffffL ||
+      !tab || !p.lam || !p.grad || (p.hi == p.L - 1 ? !p.seg : !p.in) ||
+      (p.lo == 0 ? !p.lam_out : !p.out))
+    return hipErrorInvalidValue;
+  // two workgroups per CU (one wave per SIMD: the kernel holds more than 256
+  // registers per lane; 64 KiB of LDS each)
+  static int cus[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (cus[dev] == 0) {
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    cus[dev] = v > 0 ? v : 1;
+  }
+  const long grid = std::min(items, 2L * cus[dev]);
+  const double2* coef = reinterpret_cast<const double2*>(p.coef);
+  if (p.hi & 1)
+    hipLaunchKernelGGL((tridiag_adj_persist_kernel<true>), dim3((unsigned)grid), dim3(128), 0, s, p,
+                       tab, coef);
+  else
+    hipLaunchKernelGGL((tridiag_adj_persist_kernel<false>), dim3((unsigned)grid), dim3(128), 0, s,
+                       p, tab, coef);
   return hipGetLastError();
 }
 
