@@ -834,10 +834,14 @@ def main():
                 roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VECTOR_TFLOPS, 4),
                         "traffic": None, "traffic_detail": None,
-                        "kernel": ("tridiag_adj_stream_kernel<%s, ...> (reverse passes of up to "
-                                   "128 terms; 768 owned + 2 x 128 ghost rows per workgroup, one "
-                                   "wave per real or imaginary part, real gauge frame)"
-                                   % ("false" if ctx.grad_pair_sums else "true")),
+                        "kernel": (("tridiag_adj_persist_kernel<HI_ODD> (persistent reverse "
+                                    "passes of up to 128 terms, two workgroups per CU walking "
+                                    "the (window, column) items, the next item's state loaded "
+                                    "into LDS during the terms; " if ctx.grad_pair_sums else
+                                    "tridiag_adj_stream_kernel<true, HI_ODD> (reverse passes of "
+                                    "up to 128 terms with the K contraction; ")
+                                   + "768 owned + 2 x 128 ghost rows per item, one wave per real "
+                                   "or imaginary part, real gauge frame)"),
                         "avg_launch_ms": round(ms_rev, 4), "launches_timed": n_rev,
                         "algorithmic_flops_per_launch": flops_rev}
                 extra["gradient"]["segment_recompute_pass"] = {
