@@ -389,7 +389,41 @@ TERM_KINDS = {8: "fp64", 9: "bf16x3_f64acc", 10: "bf16x3", 11: "bf16x2", 12: "bf
 #: MFMA flops issued per algorithmic flop (8 N^3 per complex product) of each format:
 #: FP64 Gauss (3 of 4 real products); FP64-accumulating split-BF16: four real products
 #: x six piece pairs / 4; split-BF16 with FP32 sums: Gauss x 6, 3 or 1 piece pairs / 4
+#: (64 x 64 output tiles; on 128 x 128 tiles the one- and two-piece products run the
+#: four real products, TERM_MFMA_X4)
 TERM_MFMA = {"fp64": 0.75, "bf16x3_f64acc": 6.0, "bf16x3": 4.5, "bf16x2": 2.25, "bf16x1": 0.75}
+TERM_MFMA_X4 = {"bf16x2": 3.0, "bf16x1": 1.0}
+TERM_KERNEL_X4 = {
+    "bf16x2": "cheb_x4_kernel<KIND,P,2> (BF16 MFMA 32x32x16 on 64 x 64 wave tiles, 4 real "
+              "products x 3 piece pairs)",
+    "bf16x1": "cheb_x4_kernel<KIND,P,1> (BF16 MFMA 32x32x16 on 64 x 64 wave tiles, 4 real "
+              "products x 1 piece pair)",
+}
+
+
+def x4_tiles(n: int) -> bool:
+    """Whether the split-BF16 products of an n-state build run on 128 x 128 output
+    tiles (states padded to 128 from n = 1024 on, to 64 below), where the one- and
+    two-piece products use cheb_x4_kernel."""
+    t = 128 if n >= 1024 else 64
+    npad = (n + t - 1) // t * t
+    return npad % 128 == 0 and npad * npad >= BIG_TILE_ELEMS
+
+
+def term_mfma(name: str, n: int) -> float:
+    if name == "fp64":
+        return mfma_flops_per_flop("fp64", n)
+    if name in TERM_MFMA_X4 and x4_tiles(n):
+        return TERM_MFMA_X4[name]
+    return TERM_MFMA[name]
+
+
+def term_kernel(name: str, n: int) -> str:
+    if name in TERM_KERNEL_X4 and x4_tiles(n):
+        return TERM_KERNEL_X4[name]
+    return TERM_KERNEL[name]
+
+
 TERM_KERNEL = {
     "fp64": "zgemm_nt_f64_kernel<128,128,8,2,4,Gauss,EpiCheb> (FP64 MFMA 16x16x4)",
     "bf16x3_f64acc": "cheb_acc_kernel<128> (BF16 MFMA 32x32x16, 4 real products x 6 piece "
@@ -414,7 +448,7 @@ def term_schedule(reports, n: int, workload: str):
         avg = ms / cnt
         flops = 8.0 * n ** 3
         peak = PEAK_FP64_MFMA_TFLOPS if name == "fp64" else PEAK_BF16_MFMA_TFLOPS
-        mf = flops * (mfma_flops_per_flop("fp64", n) if name == "fp64" else TERM_MFMA[name])
+        mf = flops * term_mfma(name, n)
         rows[name] = {"launches_per_build": cnt / len(reports), "avg_launch_ms": round(avg, 4),
                       "ms_per_build": round(ms / len(reports), 2),
                       "algorithmic_tflops": round(flops / (avg * 1e-3) / 1e12, 2),
@@ -426,12 +460,12 @@ def term_schedule(reports, n: int, workload: str):
     r = rows[dom]
     flops = 8.0 * n ** 3
     peak = PEAK_FP64_MFMA_TFLOPS if dom == "fp64" else PEAK_BF16_MFMA_TFLOPS
-    mf = flops * (mfma_flops_per_flop("fp64", n) if dom == "fp64" else TERM_MFMA[dom])
+    mf = flops * term_mfma(dom, n)
     avg = r["avg_launch_ms"]
     tr = recorded_traffic(dom, workload)
     roof = {"bound": "mfma", "achieved": r["algorithmic_tflops"], "peak": peak,
             "unit": "TFLOP/s", "frac": r["frac"], "traffic": tr["bytes"] if tr else None,
-            "traffic_detail": tr, "kernel": TERM_KERNEL[dom],
+            "traffic_detail": tr, "kernel": term_kernel(dom, n),
             "term_format": dom, "avg_launch_ms": avg,
             "launches_timed": int(round(r["launches_per_build"] * len(reports))),
             "algorithmic_flops_per_launch": flops, "note": ALGO_NOTE,
