@@ -409,6 +409,40 @@ def test_tridiag_streamed_sweep_matches_per_column_sweep(fl, monkeypatch, nb, M,
         assert np.max(np.abs(g2[:, 0] - g2[:, 1])) > 1e-6 * np.max(np.abs(g2))
 
 
+@pytest.mark.parametrize("pair", [True, False])
+def test_tridiag_streamed_sweep_short_expansion(fl, monkeypatch, pair):
+    """A deliberately short expansion (L from a 1e-4 truncation tolerance, so the
+    last weight |c_L| is near 1e-5 instead of 1e-13): the reverse sweep starts
+    from Pbar_L = conj(c_L) Lambda, in the streamed passes as in the per-column
+    sweep, so the two agree to rounding; a first pass that dropped or misread
+    c_L would differ at about |c_L| relative."""
+    nb, M, ckpt = 299, 4, 2
+    _say("streamed vs per-column sweep, short expansion, pair sums", pair)
+    rng = np.random.default_rng(4242)
+    d, e, v = dimer_tridiag(nb, 1.0, 0.01)
+    T = 2.0
+    f = rng.uniform(-1, 1, M)
+    nodes = np.stack([f, f], 1)
+    kw = _dimer_kw(d, e, v, nodes, T, M, 0.0)
+    R = orc.rescale(kw["e_min"], kw["e_max"], T / M)[2]
+    kw["L"] = orc.choose_L(R, 1e-4)
+    cL = abs(orc.bessel_coefficients(R, kw["L"])[-1])
+    assert cL > 1e-8
+    W = haar_unitary(nb + 1, rng)
+    per_col = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, grad_pair_sums=pair, **kw)
+    monkeypatch.setenv("FQ_TRIDIAG_STREAMED_ADJOINT", "1")
+    streamed = fl.FloquetContext(f_nodes=nodes, checkpoint_every=ckpt, grad_pair_sums=pair, **kw)
+    monkeypatch.delenv("FQ_TRIDIAG_STREAMED_ADJOINT")
+    U = per_col.build_ut().cpu().numpy()
+    streamed.build_ut()
+    _, Ubar = _trace_loss_and_bar(U, W)
+    g1 = per_col.grad(Ubar)
+    g2 = streamed.grad(Ubar)
+    err = np.max(np.abs(g1 - g2)) / np.max(np.abs(g1))
+    _say("L", kw["L"], "R", R, "|c_L|", cL, "rel diff", err)
+    assert err < 1e-10
+
+
 @pytest.mark.parametrize("nb,M,ckpt,pair", [(2499, 6, 2, True), (4499, 6, 2, False)])
 def test_tridiag_long_column_gradient_against_fd(fl, nb, M, ckpt, pair):
     """Columns beyond the per-column sweep (n > 2048; for n > 4096 the forward
