@@ -22,15 +22,17 @@ namespace {
 
 constexpr int kMaxWaves = 8;  // waves per part
 
-// Whole-wave DPP shifts by one lane; the lane without a source gets +0.0.
+// Whole-wave DPP shifts by one lane; the lane without a source gets +0.0
+// (bound_ctrl: the shift itself writes the zero, with no separate zeroing of
+// the destination).
 __device__ __forceinline__ double from_prev_lane(double v) {  // lane l <- lane l-1
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_next_lane(double v) {  // lane l <- lane l+1
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -416,10 +418,8 @@ __global__ __launch_bounds__(512) void tridiag_stream_kernel(TridiagJob job, Tri
       const double hd = (w + 1 < G) ? halo[parity][part][0][w + 1] : 0.0;
       up = (lane == 0) ? hu : up;
       dn = (lane == 63) ? hd : dn;
-    } else {
-      up = (lane == 0) ? 0.0 : up;
-      dn = (lane == 63) ? 0.0 : dn;
     }
+    // (one wave per part: the shifts already read zero beyond the window)
     parity ^= 1;
   };
   auto advance = [&](const double* v, double* nw) {  // nw = 2 Ht v - nw
