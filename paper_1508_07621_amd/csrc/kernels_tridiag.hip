@@ -479,15 +479,22 @@ __global__ __launch_bounds__(512) void tridiag_stream_kernel(TridiagJob job, Tri
     for (int r = 0; r < R; ++r) yo[r] = fma(c, po[r], yo[r]);
     ++l;
   }
-  for (; l + 1 < st.l1; l += 2) {  // even l into pe, odd l + 1 into po
-    advance(po, pe);
-    const double ce = coef[l].x;
+  // even l into pe, odd l + 1 into po; each pair's coefficients are loaded one
+  // pair ahead, so the scalar loads' latency hides behind a pair of terms
+  {
+    const int lc = job.L;  // coef holds c_0 .. c_L
+    double ce_n = coef[l < lc ? l : lc].x, co_n = coef[l + 1 < lc ? l + 1 : lc].y;
+    for (; l + 1 < st.l1; l += 2) {
+      const double ce = ce_n, co = sgn * co_n;
+      ce_n = coef[l + 2 < lc ? l + 2 : lc].x;
+      co_n = coef[l + 3 < lc ? l + 3 : lc].y;
+      advance(po, pe);
 #pragma unroll
-    for (int r = 0; r < R; ++r) ys[r] = fma(ce, pe[r], ys[r]);
-    advance(pe, po);
-    const double co = sgn * coef[l + 1].y;
+      for (int r = 0; r < R; ++r) ys[r] = fma(ce, pe[r], ys[r]);
+      advance(pe, po);
 #pragma unroll
-    for (int r = 0; r < R; ++r) yo[r] = fma(co, po[r], yo[r]);
+      for (int r = 0; r < R; ++r) yo[r] = fma(co, po[r], yo[r]);
+    }
   }
   if (l < st.l1) {
     advance(po, pe);
