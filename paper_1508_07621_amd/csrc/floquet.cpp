@@ -84,6 +84,32 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 long dense_tile(long n) { return n >= 1024 ? 128 : 64; }
 long pad_to(long x, long t) { return (x + t - 1) / t * t; }
 
+// Terms per pass of the streamed tridiagonal gradient (a multiple of 16;
+// windows of tridiag_stream_rows(1) rows hold 2K ghost and B = rows - 2K owned
+// rows): the K that minimises passes x windows x (overhead + terms per pass)
+// for `terms` terms per step over columns of n rows. The overhead is a pass
+// window's cost beyond its terms, in terms, measured on the 10^4-row dimer
+// (24-step gradients with K = 112, 128, 144): 60 for the reverse pass. A short
+// last window costs a full one, which is why K = 128 (14 windows, the last
+// with 16 owned rows) lost 3 % against K = 144 there. kmax: the reverse pass
+// with the K contraction stages at most 128 of its coefficients in LDS.
+int stream_pass_terms(long n, int terms, double overhead, int kmax) {
+  const long rows = fq::tridiag_stream_rows(1);
+  int best = 64;
+  double best_cost = 0.0;
+  for (int K = 64; K <= kmax && rows - 2L * K >= 256; K += 16) {
+    const long B = rows - 2L * K;
+    const long passes = (terms + K - 1) / K, windows = (n + B - 1) / B;
+    const double cost = (double)passes * (double)windows * (overhead + (double)terms / passes);
+    if (best_cost == 0.0 || cost < best_cost) {
+      best_cost = cost;
+      best = K;
+    }
+  }
+  return best;
+}
+constexpr double kStreamOverheadRev = 60.0;
+
 bool is_finite(double x) { return std::isfinite(x); }
 
 int nodes_per_step(int scheme) { return scheme == FQ_MAGNUS6 ? 3 : 2; }
@@ -1522,10 +1548,12 @@ fq_status adjoint(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
 fq_status tridiag_adjoint_streamed(fq_ctx* c, const void* U_bar, double* grad_f_nodes) {
   const int M = c->M, L = c->L, ckpt = c->ckpt;
   const long n = c->n;
-  const int K = 128;
+  const bool with_k = !c->pair_sums;
+  // one pass length for the recompute and the reverse passes, chosen for the
+  // reverse passes (two thirds of the sweep)
+  const int K = stream_pass_terms(n, L, kStreamOverheadRev, with_k ? 128 : 256);
   const long n16 = (n + 15) / 16 * 16;
   const size_t plane = (size_t)n16 * (size_t)n;  // doubles per state plane
-  const bool with_k = !c->pair_sums;
 
   // forward passes of the recompute: the build's job and pass geometry
   fq::TridiagJob job{};
