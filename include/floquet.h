@@ -395,8 +395,9 @@ fq_status floquet_period_average(fq_ctx* ctx, const void* X0, int64_t ncols, con
  * staged, FP64 epilogues and FP64 sums of the contractions: about FP32
  * accuracy in the derivative).
  * FQ_TRIDIAG: up to n = 2048 one workgroup reverses each state column;
- * longer columns run the same recurrences in streamed passes of at most 128
- * terms over windows of rows with ghost rows, one wave per real or imaginary
+ * longer columns run the same recurrences in streamed passes of K terms over
+ * windows of rows with K ghost rows per side (K chosen per problem: at most
+ * 256, at most 128 with the K contraction), one wave per real or imaginary
  * part (setting the environment variable FQ_TRIDIAG_STREAMED_ADJOINT=1 before
  * fq_workspace_bytes / fq_create selects the streamed form for any n; both
  * give the same derivative up to rounding). For n > 4096 the build records its
